@@ -1,0 +1,138 @@
+"""The neutrino amplitude of eq. (P-final), by quadrature over the stored history (FP64).
+
+For each k-bin, with s the superconformal time (Sec. 3.2) and I_{s',s} = I(k (s - s') T_nu0 / m):
+
+  P_nu^{1/2}(k, tau) = I_{s_i,s} P_nu^{1/2}(k, tau_i) {1 - (s - s_i) a_i [theta/delta]_i(k)}
+                     + (3/2) Omega_M H0^2 int_{tau_i}^{tau} I_{s',s} P_M^{1/2}(k, tau') (s - s') dtau'
+
+(the initial-condition term is eq. (deltaI-nu) under the phase assumptions of Sec. 4.2).
+
+Discretisation (the paper integrates "interpolating over our tables of stored power
+spectra", Sec. 4.3 (iii), and gives no rule):
+  * the stored nodes a_0 < ... < a_{n-1} and the current a_n split [a_0, a_n]; every
+    interval is cut into Q equal steps in ln a;
+  * dtau' = d ln a' / (a' H(a')); the integral is the trapezoid rule in ln a over the
+    sub-nodes;
+  * P_M^{1/2} at a sub-node is linear in ln a between the two bracketing nodes;
+  * the current node is not known yet (the equation is implicit, Sec. 4.3 (iii)): the first
+    iteration uses P_M^{1/2}(a_n) = (1 - f_nu) P_cdm^{1/2}(a_n) + f_nu P_nu^{1/2}(a_{n-1}),
+    i.e. P_nu(tau) ~ P_nu(tau - dtau); iteration i+1 uses the P_nu^{1/2} of iteration i
+    (Appendix B).
+"""
+import numpy as np
+
+from .background import H0, T_NU0, f_nu as f_nu_of, hubble_rate, superconformal_interval
+from .kernel import I_fit
+
+_DS_CACHE = {}
+
+
+def _ds_piece(a1, a2, omega_m):
+    key = (float(a1), float(a2), float(omega_m))
+    v = _DS_CACHE.get(key)
+    if v is None:
+        v = superconformal_interval(a1, a2, omega_m)
+        _DS_CACHE[key] = v
+    return v
+
+
+def sub_grid(a_nodes, substeps, omega_m):
+    """Sub-nodes of the quadrature over nodes a_0..a_n (a_n = current step).
+
+    Returns a dict of per-sub-node arrays: a, trapezoid weight in ln a, bracketing node j,
+    interpolation fraction t (amplitude = (1-t) A_j + t A_{j+1}), and s_n - s_q.
+    """
+    lna = np.log(np.asarray(a_nodes, dtype=np.float64))
+    n = len(lna) - 1
+    q_lna, q_j, q_t, q_w = [], [], [], []
+    for j in range(n):
+        h = (lna[j + 1] - lna[j]) / substeps
+        for r in range(substeps):
+            q_lna.append(lna[j] + r * h)
+            q_j.append(j)
+            q_t.append(r / substeps)
+            q_w.append(h if r > 0 else 0.5 * h)
+        if j > 0:
+            q_w[j * substeps] += 0.5 * (lna[j] - lna[j - 1]) / substeps
+    # final sub-node: the current step itself
+    q_lna.append(lna[n])
+    q_j.append(n - 1 if n > 0 else 0)
+    q_t.append(1.0 if n > 0 else 0.0)
+    q_w.append(0.5 * (lna[n] - lna[n - 1]) / substeps if n > 0 else 0.0)
+    a_sub = np.exp(np.array(q_lna))
+    a_sub[-1] = a_nodes[-1]
+    for j in range(n):                      # sub-nodes that coincide with nodes are exact
+        a_sub[j * substeps] = a_nodes[j]
+    # s_n - s_q, summed backwards over the sub-intervals (each an accurate quadrature)
+    ds = np.zeros(len(a_sub))
+    for q in range(len(a_sub) - 2, -1, -1):
+        ds[q] = ds[q + 1] + _ds_piece(a_sub[q], a_sub[q + 1], omega_m)
+    return dict(a=a_sub, w=np.array(q_w), j=np.array(q_j), t=np.array(q_t), ds=ds)
+
+
+def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
+                 pnu_half_init, theta_over_delta_init, a_now, m_nu_total, omega_m,
+                 hubble, substeps, iterations=1, n_species=3, f_nu=None):
+    """P_nu^{1/2}(k_b, a_now) for every bin, eq. (P-final).
+
+    hist_a (n,), hist_pm_half (n, B): stored nodes strictly before a_now (hist_a[0] = a_i).
+    pnu_half_prev (B,): P_nu^{1/2} at the last stored node (the first-iteration guess).
+    Returns dict: pnu_half, ratio = P_nu^{1/2}/P_cdm^{1/2}, pm_half_now (the node to store),
+    f_nu. Empty bins (counts == 0) give 0 everywhere.
+    """
+    k = np.asarray(k_mean, dtype=np.float64)
+    ok = np.asarray(counts) > 0
+    pcdm_half = np.asarray(pcdm_half, dtype=np.float64)
+    fn = f_nu_of(m_nu_total, omega_m, hubble) if f_nu is None else f_nu
+    m1 = m_nu_total / n_species
+    nodes = np.append(np.asarray(hist_a, dtype=np.float64), a_now)
+    g = sub_grid(nodes, substeps, omega_m)
+    pref = 1.5 * omega_m * H0 * H0
+    measure = g["w"] / (g["a"] * hubble_rate(g["a"], omega_m))     # d ln a / (a H)
+    hist = np.asarray(hist_pm_half, dtype=np.float64)
+
+    # initial-condition term: I(x_i) P_nu^{1/2}(a_i) {1 - (s - s_i) a_i [theta/delta]_i}
+    x_i = k * g["ds"][0] * T_NU0 / m1
+    ic = I_fit(x_i) * np.asarray(pnu_half_init) * (
+        1.0 - g["ds"][0] * nodes[0] * np.asarray(theta_over_delta_init))
+
+    kernel = I_fit(np.outer(g["ds"] * T_NU0 / m1, k)) * g["ds"][:, None]   # (q, B)
+
+    pnu_guess = np.asarray(pnu_half_prev, dtype=np.float64)
+    for _ in range(max(1, iterations)):
+        a_cur = (1.0 - fn) * pcdm_half + fn * pnu_guess
+        table = np.vstack([hist, a_cur[None, :]])                     # (n+1, B)
+        amp = ((1.0 - g["t"])[:, None] * table[g["j"]]
+               + g["t"][:, None] * table[np.minimum(g["j"] + 1, len(table) - 1)])
+        integral = pref * np.sum(measure[:, None] * kernel * amp, axis=0)
+        pnu = ic + integral
+        pnu_guess = pnu
+    pnu = np.where(ok, pnu, 0.0)
+    ratio = np.where(ok, pnu / np.where(ok, pcdm_half, 1.0), 0.0)
+    pm_now = np.where(ok, (1.0 - fn) * pcdm_half + fn * pnu, 0.0)
+    return dict(pnu_half=pnu, ratio=ratio, pm_half_now=pm_now, f_nu=fn)
+
+
+def replay_history(k_mean, counts, cdm_half, a_nodes, pnu_half_init,
+                   theta_over_delta_init, m_nu_total, omega_m, hubble, substeps,
+                   n_species=3, f_nu=None):
+    """A self-consistent stored history: the neutrino amplitude at every node computed by
+    eq. (P-final) from the earlier nodes, as the step-by-step loop of Sec. 4.3 would.
+
+    cdm_half (n_nodes, B): CDM amplitudes at every node a_nodes[j].
+    Returns pm_half (n_nodes, B) and pnu_half (n_nodes, B).
+    """
+    fn = f_nu_of(m_nu_total, omega_m, hubble) if f_nu is None else f_nu
+    n = len(a_nodes)
+    B = len(k_mean)
+    pm = np.zeros((n, B))
+    pnu = np.zeros((n, B))
+    pnu[0] = pnu_half_init
+    pm[0] = (1.0 - fn) * cdm_half[0] + fn * pnu[0]
+    for j in range(1, n):
+        r = nu_amplitude(k_mean, counts, cdm_half[j], a_nodes[:j], pm[:j], pnu[j - 1],
+                         pnu_half_init, theta_over_delta_init, a_nodes[j], m_nu_total,
+                         omega_m, hubble, substeps, n_species=n_species, f_nu=fn)
+        pnu[j] = r["pnu_half"]
+        pm[j] = r["pm_half_now"]
+    return pm, pnu

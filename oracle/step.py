@@ -1,0 +1,61 @@
+"""One PM + linear-response-neutrino step in the order of Sec. 4.3 (ii)-(iv), FP64.
+
+  (ii)  CDM density by cloud-in-cell, its Fourier transform and binned power spectrum
+  (iii) P_nu^{1/2} from eq. (P-final) over the stored history (one iteration by default)
+  (iv)  delta_nu = (P_nu/P_cdm)^{1/2} delta_cdm (eq. (phases)), delta_M = (1-f_nu) delta_cdm
+        + f_nu delta_nu, then Poisson's equation and the force back at the particles;
+        the new total-matter amplitude is what gets stored for later steps.
+"""
+import numpy as np
+
+from . import pm, response
+
+
+def spectrum(pos, n_mesh, box, n_bins):
+    """Stage (ii): density, modes and binned CDM power of one box."""
+    pos = np.asarray(pos, dtype=np.float64)
+    rho = pm.cic_deposit(pos, n_mesh, box)
+    delta = pm.overdensity(rho, pos.shape[0])
+    delta_k = pm.forward_modes(delta)
+    edges, counts, k_mean = pm.bin_geometry(n_mesh, box, n_bins)
+    p_cdm = pm.binned_power(delta_k, n_mesh, box, n_bins)
+    return dict(rho=rho, delta_k=delta_k, edges=edges, counts=counts, k_mean=k_mean,
+                p_cdm=p_cdm)
+
+
+def forces(pos, delta_k, n_mesh, box, k_mean, counts, ratio, f_nu, a_now, omega_m,
+           deconvolve=True, return_grids=False):
+    """Stage (iv): total-matter modes, potential, gradient, inverse FFT, interpolation."""
+    pos = np.asarray(pos, dtype=np.float64)
+    rm = pm.ratio_on_modes(n_mesh, box, k_mean, counts, ratio)
+    dm = pm.total_matter_modes(delta_k, f_nu, rm)
+    phi = pm.potential_modes(dm, n_mesh, box, a_now, omega_m, deconvolve)
+    grids = np.stack([pm.inverse_real(g, n_mesh) for g in pm.gradient_modes(phi, n_mesh, box)])
+    acc = pm.cic_interpolate(pos, grids, box)
+    if return_grids:
+        return acc, grids
+    return acc
+
+
+def full_step(pos, n_mesh, box, n_bins, history, a_now, m_nu_total, omega_m=0.3,
+              hubble=0.7, substeps=8, iterations=1, deconvolve=True, n_species=3,
+              return_grids=False):
+    """Whole step for one box. ``history`` is a dict with keys a, pm_half, pnu_half,
+    pnu_half_init, theta_over_delta_init (as produced by synth.synthetic_history)."""
+    sp = spectrum(pos, n_mesh, box, n_bins)
+    pcdm_half = np.sqrt(sp["p_cdm"])
+    r = response.nu_amplitude(sp["k_mean"], sp["counts"], pcdm_half, history["a"],
+                              history["pm_half"], history["pnu_half"][-1],
+                              history["pnu_half_init"], history["theta_over_delta_init"],
+                              a_now, m_nu_total, omega_m, hubble, substeps,
+                              iterations=iterations, n_species=n_species)
+    out = forces(pos, sp["delta_k"], n_mesh, box, sp["k_mean"], sp["counts"], r["ratio"],
+                 r["f_nu"], a_now, omega_m, deconvolve, return_grids)
+    if return_grids:
+        acc, grids = out
+        sp["grids"] = grids
+    else:
+        acc = out
+    sp.update(r)
+    sp["acc"] = acc
+    return sp

@@ -1,0 +1,99 @@
+"""Zel'dovich-displaced particle lattices with a power-law spectrum (seeded, FP64 -> FP32).
+
+The paper's runs start from Boltzmann-code transfer functions and a 2LPT generator, which
+are not available here. A power-law Gaussian field displaced with the Zel'dovich
+approximation stands in for them: it has the same structure (a lattice perturbed by a
+smooth, curl-free displacement) and a controlled amplitude.
+
+Recipe (all in FP64 with ``numpy.random.default_rng(seed)``):
+  1. white noise on the n^3 lattice;
+  2. forward real FFT, multiplied by sqrt(P(k)) with P(k) ~ k^spectral_index, k != 0;
+  3. the DC mode and every mode with a Nyquist index on any axis are zeroed;
+  4. displacement psi_k = i k delta_k / k^2 (so that delta = -div psi), back to real space;
+  5. psi is rescaled so that its 3-D RMS equals ``sigma_cells`` mesh cells;
+  6. positions q = (i + 1/2) * spacing + psi, wrapped into [0, L), rounded to FP32.
+
+The lattice sits at cell centres: a lattice on the mesh nodes makes the cloud-in-cell
+density of the unperturbed lattice non-smooth at first order in psi.
+
+Particles are returned in C order of their lattice index (i, j, l) -> (i*n + j)*n + l and
+position component 0 belongs to lattice axis i.
+"""
+import numpy as np
+
+# The workloads, by name. Sizes follow the measurement plan of the method's PM step.
+CONFIGS = {
+    # 32^3 particles on a 32^3 mesh in a 128 Mpc/h box; small enough for the oracle.
+    "tiny32": dict(n_side=32, n_mesh=32, box=128.0, sigma_cells=0.2, m_nu=(0.3,),
+                   n_kbins=32, n_hist=16, a_lo=0.01, a_now=0.5, substeps=8,
+                   seeds=(0, 1, 2, 3, 4), n_boxes=1),
+    # 256^3 particles on a 256^3 mesh, 512 Mpc/h: the headline single-box workload.
+    "pm256": dict(n_side=256, n_mesh=256, box=512.0, sigma_cells=0.3,
+                  m_nu=(0.15, 0.3, 0.6), n_kbins=64, n_hist=200, a_lo=0.01,
+                  a_now=1.0, substeps=8, seeds=(256, 257, 258), n_boxes=1),
+    # 512^3 particles on a 512^3 mesh, 1000 Mpc/h (cell 1.953125 Mpc/h, exact in binary).
+    "pm512": dict(n_side=512, n_mesh=512, box=1000.0, sigma_cells=0.3, m_nu=(0.3,),
+                  n_kbins=128, n_hist=400, a_lo=0.01, a_now=1.0, substeps=8,
+                  seeds=(512,), n_boxes=1),
+    # 64 independent boxes of 64^3 particles on 64^3 meshes, 256 Mpc/h each.
+    "batch64x64": dict(n_side=64, n_mesh=64, box=256.0, sigma_cells=0.3, m_nu=None,
+                       m_nu_range=(0.05, 0.6), m_nu_seed=999, n_kbins=48, n_hist=100,
+                       a_lo=0.01, a_now=1.0, substeps=8, seeds=None, seed0=1000,
+                       n_boxes=64),
+}
+
+
+def zeldovich_lattice(n_side, box, sigma_cells, seed, spectral_index=-2.0):
+    """Return FP32 positions, shape (n_side**3, 3), in [0, box)."""
+    n = int(n_side)
+    if n < 2 or n & (n - 1):
+        raise ValueError("n_side must be a power of two >= 2")
+    spacing = box / n
+    rng = np.random.default_rng(seed)
+    noise = rng.standard_normal((n, n, n))
+    dk = np.fft.rfftn(noise)
+    del noise
+    ix = np.fft.fftfreq(n, d=1.0 / n)            # integer mode index, [-n/2, n/2)
+    iz = np.arange(n // 2 + 1, dtype=np.float64)
+    nx = ix[:, None, None]
+    ny = ix[None, :, None]
+    nz = iz[None, None, :]
+    n2 = nx * nx + ny * ny + nz * nz
+    amp = np.zeros_like(n2)
+    nz0 = n2 > 0
+    amp[nz0] = n2[nz0] ** (0.25 * spectral_index)   # sqrt(P) with P ~ |n|^index
+    nyq = (np.abs(nx) == n // 2) | (np.abs(ny) == n // 2) | (nz == n // 2)
+    amp = np.where(nyq, 0.0, amp)
+    dk *= amp
+    del amp
+    inv_n2 = np.zeros_like(n2)
+    inv_n2[nz0] = 1.0 / n2[nz0]
+    psi = np.empty((n, n, n, 3), dtype=np.float64)
+    for axis, na in enumerate((nx, ny, nz)):
+        comp = 1j * na * inv_n2 * dk                  # unit-free: rescaled below
+        psi[..., axis] = np.fft.irfftn(comp, s=(n, n, n), axes=(0, 1, 2))
+    del dk
+    rms = np.sqrt(np.mean(np.sum(psi * psi, axis=-1)))
+    psi *= (sigma_cells * spacing) / rms
+    grid = (np.arange(n, dtype=np.float64) + 0.5) * spacing
+    psi[..., 0] += grid[:, None, None]
+    psi[..., 1] += grid[None, :, None]
+    psi[..., 2] += grid[None, None, :]
+    pos = np.mod(psi.reshape(-1, 3), box).astype(np.float32)
+    pos[pos >= np.float32(box)] = np.float32(0.0)  # an FP32 round-up to L wraps to 0
+    pos[pos < 0] = np.float32(0.0)
+    return np.ascontiguousarray(pos)
+
+
+def batched_lattices(cfg):
+    """Positions (n_boxes, n_side**3, 3) FP32 and per-box total neutrino masses [eV]."""
+    nb = cfg["n_boxes"]
+    if cfg.get("m_nu") is not None:
+        masses = np.resize(np.asarray(cfg["m_nu"], dtype=np.float64), nb)
+    else:
+        lo, hi = cfg["m_nu_range"]
+        masses = np.random.default_rng(cfg["m_nu_seed"]).uniform(lo, hi, size=nb)
+    seeds = cfg.get("seeds") or tuple(cfg["seed0"] + b for b in range(nb))
+    pos = np.stack([zeldovich_lattice(cfg["n_side"], cfg["box"], cfg["sigma_cells"],
+                                      seeds[b % len(seeds)]) for b in range(nb)])
+    return pos, masses

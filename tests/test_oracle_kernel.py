@@ -1,0 +1,101 @@
+"""Pins of the oracle's free-streaming kernel and constants (CPU).
+
+Each check ties the oracle to something other than its own formula: the definition of
+I as a momentum integral (eq. (I.def)), the paper's printed accuracy of the fit and its
+asymptotes (Appendix C), and the numbers printed in Sec. 2.
+"""
+import numpy as np
+import pytest
+from scipy import integrate, optimize
+
+from oracle import background as bg
+from oracle import kernel
+
+
+def _I_definition(x):
+    """eq. (I.def) by direct quadrature: int q^2 j0(qx) f0(q) dq / int q^2 f0(q) dq,
+    with f0 the relativistic Fermi-Dirac occupation and q in units of T_nu0."""
+    norm = integrate.quad(lambda q: q * q / (np.exp(q) + 1.0), 0.0, 80.0,
+                          epsabs=0.0, epsrel=1e-13, limit=400)[0]
+    if x == 0.0:
+        return 1.0
+    # q^2 j0(qx) = q sin(qx)/x
+    val = integrate.quad(lambda q: q / (np.exp(q) + 1.0) / x, 0.0, 80.0, weight="sin",
+                         wvar=x, epsabs=1e-15, epsrel=1e-12, limit=800)[0]
+    return val / norm
+
+
+@pytest.mark.parametrize("x", [0.05, 0.3, 1.0, 2.0, 3.7, 8.0, 20.0])
+def test_series_equals_definition(x):
+    assert kernel.I_series(x)[0] == pytest.approx(_I_definition(x), rel=1e-8, abs=1e-12)
+
+
+def test_fit_value_at_zero():
+    assert kernel.I_fit(0.0) == 1.0
+
+
+def test_fit_accuracy_as_printed():
+    # Appendix C: |dI/I| < ~1% for x <= 2, < ~3% everywhere, |dI| < ~0.07%.
+    # Recomputed here: 1.18% (x <= 2), 3.14% (near x = 2.84), 0.070% absolute; the
+    # tolerances below take the paper's figures to their next significant digit.
+    x = np.concatenate([np.linspace(0.0, 2.0, 801), np.geomspace(2.0, 300.0, 1500)])
+    exact = kernel.I_series(x, n_terms=20000)
+    fit = kernel.I_fit(x)
+    rel = np.abs(fit - exact) / exact
+    assert rel[x <= 2.0].max() < 0.012
+    assert rel.max() < 0.032
+    assert np.abs(fit - exact).max() < 7.1e-4
+
+
+def test_exact_asymptotes():
+    # small x: 1 - 5 zeta(5)/(2 zeta(3)) x^2 = 1 - 2.1566 x^2
+    xs = 1e-3
+    slope = (1.0 - kernel.I_series(xs)[0]) / xs ** 2
+    assert slope == pytest.approx(5.0 * bg.ZETA5 / (2.0 * bg.ZETA3), rel=1e-5)
+    assert slope == pytest.approx(2.1566, abs=1e-4)
+    # large x: 1/(3 zeta(3) x^4) = 0.2773 / x^4
+    xl = 400.0
+    assert kernel.I_series(xl, n_terms=40000)[0] * xl ** 4 == pytest.approx(
+        1.0 / (3.0 * bg.ZETA3), rel=1e-4)
+    assert 1.0 / (3.0 * bg.ZETA3) == pytest.approx(0.2773, abs=1e-4)
+
+
+def test_fit_asymptotes_match_exact_ones():
+    xs = 1e-4
+    assert (1.0 - kernel.I_fit(xs)) / xs ** 2 == pytest.approx(2.1566, abs=2e-4)
+    xl = 1e4
+    assert kernel.I_fit(xl) * xl ** 4 == pytest.approx(0.2773, rel=2e-3)
+
+
+def test_first_moment_gives_small_scale_limit():
+    # Sec. 3.3.2: delta_hdm(k >> k_fs) = -(m a)^2 phi int X I(X) dX reproduces
+    # -<v^-2> phi, i.e. int_0^inf x I(x) dx = 2 ln 2 / (3 zeta(3)) in units of T_nu0.
+    f = lambda t: t * kernel.I_series(t, n_terms=6000)[0]
+    head = integrate.quad(f, 0.0, 60.0, limit=400, epsrel=1e-10)[0]
+    tail = integrate.quad(lambda t: 1.0 / (3.0 * bg.ZETA3 * t ** 3), 60.0, np.inf)[0]
+    assert head + tail == pytest.approx(2.0 * np.log(2.0) / (3.0 * bg.ZETA3), rel=1e-6)
+
+
+def test_fermi_dirac_quantiles_as_printed():
+    # Sec. 2.2: 50% of neutrinos have p < 2.84 T, 90% have p < 5.47 T; Sec. 2.4: ~6% p < T.
+    dens = lambda q: q * q / (np.exp(q) + 1.0)
+    tot = integrate.quad(dens, 0, 80)[0]
+    cdf = lambda p: integrate.quad(dens, 0, p)[0] / tot
+    assert optimize.brentq(lambda p: cdf(p) - 0.5, 0.1, 20) == pytest.approx(2.84, abs=0.005)
+    assert optimize.brentq(lambda p: cdf(p) - 0.9, 0.1, 20) == pytest.approx(5.47, abs=0.005)
+    assert cdf(1.0) == pytest.approx(0.06, abs=0.005)
+
+
+def test_printed_constants():
+    # Sec. 2.1: f_nu ~ 0.022 (0.147 / Omega_M h^2)(sum m / 0.3 eV)
+    assert bg.f_nu(0.3, 1.0, np.sqrt(0.147)) == pytest.approx(0.022, abs=5e-4)
+    # T_nu0 = 1.95 K = 1.68e-4 eV
+    assert bg.T_NU0 == pytest.approx(1.68e-4, rel=2e-3)
+    # eq. (v2): <v^-2>^{-1/2} ~ 810 km/s (1+z)(0.1 eV/m); recomputed 812.5 km/s
+    v = bg.C_KMS / np.sqrt(bg.mean_inverse_v2(1.0, 0.1))
+    assert v == pytest.approx(810.0, rel=5e-3)
+    # eq. (kfs): k_fs ~ 0.08/sqrt(1+z) sqrt(Omega_M/0.3) (m/0.1 eV); recomputed 0.0826
+    # (the numeric form treats Omega_M(a) as 1, i.e. matter domination)
+    a = 0.1
+    kfs_md = (np.sqrt(1.5 * bg.mean_inverse_v2(a, 0.1)) * a * bg.H0 * np.sqrt(0.3 / a ** 3))
+    assert kfs_md * np.sqrt(1.0 / a) == pytest.approx(0.08, rel=0.04)

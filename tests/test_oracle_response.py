@@ -1,0 +1,133 @@
+"""Pins of the oracle's neutrino response, eq. (P-final) (CPU).
+
+* Appendix A: in a matter-dominated universe with delta_M ~ a and no initial neutrino
+  perturbation, P_nu^{1/2}/delta_M has a closed form F_fin(k); the quadrature must converge
+  to it at second order in the history spacing.
+* Sec. 3.3.1: for k -> 0 the neutrinos follow the pressureless fluid solution, so with a
+  growing-mode history and initial conditions P_nu^{1/2} -> P_M^{1/2}.
+* Sec. 3.3.2 / Appendix A: for k >> k_fs, delta_nu -> (k_fs/k)^2 delta_M, and at all k
+  F ~ 1/(1 + k/k_fs)^2 to within 12%.
+* Appendix B / Sec. 4.3 (iii): one iteration is converged to ~1e-4.
+"""
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import background as bg
+from oracle import kernel, response
+from synth import log_spaced_nodes, synthetic_history
+from synth.history import growth
+
+
+def _eds_response(k, m, a0, an, J, Q=8):
+    nodes = log_spaced_nodes(a0, an, J)
+    B = len(k)
+    r = response.nu_amplitude(k, np.ones(B), an * np.ones(B), nodes[:-1],
+                              nodes[:-1, None] * np.ones((1, B)), np.zeros(B), np.zeros(B),
+                              np.zeros(B), an, 3 * m, 1.0, 0.7, Q, f_nu=0.0)
+    return r["pnu_half"] / an
+
+
+def _eds_closed_form(k, m, a0, an):
+    """F_fin = (6/x_k^2) int_0^{x_max} x I(x) / (1 + x/x_k)^4 dx (Appendix A), with
+    x_k = 2 k T/(m a^2 H) and x_max = k (s - s_i) T / m, s = -2/(H0 sqrt(a)) in EdS."""
+    T = bg.T_NU0
+    h = bg.H0 * an ** -1.5
+    xk = 2 * k * T / (m * an ** 2 * h)
+    xmax = k * (2.0 / bg.H0) * (a0 ** -0.5 - an ** -0.5) * T / m
+    val = integrate.quad(lambda x: x * kernel.I_fit(x) / (1 + x / xk) ** 4, 0, xmax,
+                         limit=500, epsrel=1e-12)[0]
+    return 6.0 / xk ** 2 * val
+
+
+def test_eds_closed_form_second_order_convergence():
+    k = np.array([0.01, 0.1, 0.3, 1.0])
+    m, a0, an = 0.1, 0.01, 0.5
+    ref = np.array([_eds_closed_form(kk, m, a0, an) for kk in k])
+    errs = []
+    for J in (100, 200, 400):
+        errs.append(np.abs(_eds_response(k, m, a0, an, J) / ref - 1.0))
+    errs = np.array(errs)
+    assert np.all(errs[-1] < 2e-5)
+    ratio = errs[:-1] / errs[1:]
+    assert np.all((ratio > 3.6) & (ratio < 4.4))
+
+
+def test_eds_closed_form_other_mass():
+    k = np.array([0.05, 0.5])
+    m, a0, an = 0.05, 0.02, 1.0
+    ref = np.array([_eds_closed_form(kk, m, a0, an) for kk in k])
+    got = _eds_response(k, m, a0, an, 600)
+    assert np.allclose(got, ref, rtol=2e-5)
+
+
+def test_large_scale_fluid_limit():
+    """k -> 0 in LCDM: history ~ D(a), growing-mode initial conditions -> R -> 1, with an
+    error that falls at second order in the node spacing."""
+    om = 0.3
+    errs = []
+    for J in (32, 64, 128):
+        nodes = log_spaced_nodes(0.01, 1.0, J)
+        d, f = growth(nodes, om)
+        amp = d / d[-1]
+        k = np.array([1e-5])
+        theta = -f[0] * nodes[0] * bg.hubble_rate(nodes[0], om)
+        r = response.nu_amplitude(k, [1], [1.0], nodes[:-1], amp[:-1, None], [amp[-2]],
+                                  [amp[0]], [theta], 1.0, 0.3, om, 0.7, 1)
+        errs.append(abs(1.0 - r["ratio"][0]))
+    assert errs[-1] < 1e-4
+    assert 3.5 < errs[0] / errs[1] < 4.6 and 3.5 < errs[1] / errs[2] < 4.6
+
+
+def test_initial_condition_term_alone():
+    """With no source (P_M = 0) and k -> 0, P_nu^{1/2} = P_nu,i^{1/2}{1 - (s - s_i) a_i [theta/delta]_i}."""
+    om, a0, an = 0.3, 0.05, 0.4
+    nodes = log_spaced_nodes(a0, an, 20)
+    theta = -3.7e-4
+    r = response.nu_amplitude([1e-7], [1], [1e-300], nodes[:-1], np.zeros((19, 1)), [0.0],
+                              [2.0], [theta], an, 0.3, om, 0.7, 4, f_nu=0.0)
+    ds = integrate.quad(lambda a: 1.0 / (a ** 3 * bg.hubble_rate(a, om)), a0, an,
+                        epsrel=1e-13)[0]
+    assert r["pnu_half"][0] == pytest.approx(2.0 * (1.0 - ds * a0 * theta), rel=1e-10)
+
+
+def test_small_scale_limit_and_appendix_a_fit():
+    """EdS, history ~ a: R (k/k_fs)^2 -> 1 for k >> k_fs; R ~ 1/(1+k/k_fs)^2 within 12%."""
+    m, a0, an = 0.1, 1e-3, 1.0
+    kfs = np.sqrt(1.5 * bg.mean_inverse_v2(an, m)) * an * bg.hubble_rate(an, 1.0)
+    k = kfs * np.array([0.3, 1.0, 3.0, 10.0, 30.0, 100.0])
+    r = _eds_response(k, m, a0, an, 600)
+    approx = 1.0 / (1.0 + k / kfs) ** 2
+    assert np.all(np.abs(r / approx - 1.0) < 0.12)
+    lim = r * (k / kfs) ** 2
+    assert lim[-1] == pytest.approx(1.0, abs=0.05)
+    assert np.all(np.diff(lim[2:]) > 0)
+
+
+def test_trapezoid_weights_integrate_ln_a():
+    nodes = np.array([0.01, 0.02, 0.05, 0.07, 0.2])
+    g = response.sub_grid(nodes, 5, 0.3)
+    assert g["w"].sum() == pytest.approx(np.log(0.2 / 0.01), rel=1e-14)
+    assert g["ds"][-1] == 0.0 and np.all(np.diff(g["ds"]) < 0)
+    full = integrate.quad(lambda a: 1.0 / (a ** 3 * bg.hubble_rate(a, 0.3)), 0.01, 0.2,
+                          epsrel=1e-13)[0]
+    assert g["ds"][0] == pytest.approx(full, rel=1e-11)
+
+
+def test_single_iteration_is_converged():
+    """Sec. 4.3 (iii): iterating again changes P_nu^{1/2} by ~1e-4 (Appendix B: O(f_nu (H dt)^2))."""
+    om = 0.3
+    nodes = log_spaced_nodes(0.01, 1.0, 200)
+    k = np.geomspace(0.0123, 2.7, 24)
+    pcdm = 30.0 / k
+    h = synthetic_history(k, pcdm, nodes, 0.6, om)
+    kw = dict(k_mean=k, counts=np.ones(24), pcdm_half=pcdm, hist_a=h["a"],
+              hist_pm_half=h["pm_half"], pnu_half_prev=h["pnu_half"][-1],
+              pnu_half_init=h["pnu_half_init"], theta_over_delta_init=h["theta_over_delta_init"],
+              a_now=1.0, m_nu_total=0.6, omega_m=om, hubble=0.7, substeps=8)
+    one = response.nu_amplitude(iterations=1, **kw)["pnu_half"]
+    two = response.nu_amplitude(iterations=2, **kw)["pnu_half"]
+    three = response.nu_amplitude(iterations=3, **kw)["pnu_half"]
+    d12 = np.abs(two / one - 1.0)
+    assert d12.max() < 3e-4
+    assert np.abs(three / two - 1.0).max() < 1e-2 * d12.max() + 1e-15
