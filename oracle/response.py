@@ -78,13 +78,19 @@ def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
     hist_a (n,), hist_pm_half (n, B): stored nodes strictly before a_now (hist_a[0] = a_i).
     pnu_half_prev (B,): P_nu^{1/2} at the last stored node (the first-iteration guess).
     Returns dict: pnu_half, ratio = P_nu^{1/2}/P_cdm^{1/2}, pm_half_now (the node to store),
-    f_nu. Empty bins (counts == 0) give 0 everywhere.
+    f_nu. Empty bins (counts == 0) give 0 everywhere. Without massive neutrinos
+    (m_nu_total = 0, so f_nu = 0) the neutrino term of Sec. 4.3 (iv) drops out: P_nu^{1/2}
+    and R are reported as 0 and the stored node is P_cdm^{1/2}.
     """
     k = np.asarray(k_mean, dtype=np.float64)
     ok = np.asarray(counts) > 0
     pcdm_half = np.asarray(pcdm_half, dtype=np.float64)
     fn = f_nu_of(m_nu_total, omega_m, hubble) if f_nu is None else f_nu
     m1 = m_nu_total / n_species
+    if m1 <= 0.0:
+        zero = np.zeros_like(k)
+        return dict(pnu_half=zero, ratio=zero.copy(),
+                    pm_half_now=np.where(ok, pcdm_half, 0.0), f_nu=0.0)
     nodes = np.append(np.asarray(hist_a, dtype=np.float64), a_now)
     g = sub_grid(nodes, substeps, omega_m)
     pref = 1.5 * omega_m * H0 * H0

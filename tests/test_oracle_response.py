@@ -131,3 +131,13 @@ def test_single_iteration_is_converged():
     d12 = np.abs(two / one - 1.0)
     assert d12.max() < 3e-4
     assert np.abs(three / two - 1.0).max() < 1e-2 * d12.max() + 1e-15
+
+
+def test_massless_neutrinos_drop_out():
+    """M_nu = 0: f_nu = 0, no neutrino term (Sec. 4.3 (iv)); the stored node is P_cdm^{1/2}."""
+    nodes = log_spaced_nodes(0.01, 0.5, 8)
+    k = np.array([0.05, 0.5])
+    r = response.nu_amplitude(k, [1, 1], [2.0, 3.0], nodes[:-1], np.ones((7, 2)), [1, 1],
+                              [1, 1], [0, 0], 0.5, 0.0, 0.3, 0.7, 4)
+    assert r["f_nu"] == 0.0 and np.all(r["pnu_half"] == 0) and np.all(r["ratio"] == 0)
+    assert np.array_equal(r["pm_half_now"], [2.0, 3.0])
