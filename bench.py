@@ -1,0 +1,239 @@
+"""Benchmark of the PM + linear-response-neutrino step on one MI355X.
+
+Workload (default): 256^3 particles (Zel'dovich lattice, k^-2 spectrum, RMS displacement
+0.3 cells) on a 256^3 mesh in a 512 Mpc/h box, 64 log k-bins, a 200-node history over
+a in [0.01, 1] (199 stored + the current step at a = 1), Q = 8 quadrature steps per
+interval, M_nu = 0.3 eV. A step is deposit -> response -> force for every particle; each
+timed step recomputes the node a = 1 from the same stored history.
+
+Prints one JSON line. `value` is steps/s of the whole step with inputs resident in HBM;
+`roofline` is the dominant kernel's algorithmic bytes per launch over its mean launch
+time from HIP events recorded on the library's stream inside the timed region;
+`cpu_baseline` is the FP64 oracle timed on this host on one full step (single-threaded
+NumPy).
+
+    python bench.py [--steps K] [--warmup W] [--workload pm256|pm512|tiny32|batch64x64]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PM+nu steps/sec and particle-updates/s at 256^3; %HBM peak; surrogate vs integral"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = {
+    "cic_deposit": "grid_kernels.hip", "cic_interp": "grid_kernels.hip",
+    "zero_mesh": "grid_kernels.hip", "fft_fwd_z": "fft_kernels.hip",
+    "fft_fwd_y": "fft_kernels.hip", "fft_fwd_x_bin": "fft_kernels.hip",
+    "inv_x_green": "fft_kernels.hip", "fft_inv_y": "fft_kernels.hip",
+    "fft_inv_z": "fft_kernels.hip", "nu_response": "response_kernels.hip",
+    "rtable": "response_kernels.hip",
+}
+
+
+def stage_bytes(n_mesh, n_part, nbox, nbins, n_hist, n_partial):
+    """Algorithmic bytes per launch of every kernel: each input read once, each output
+    written once (FP32 grids, complex64 modes, FP32 positions/accelerations)."""
+    m = n_mesh ** 3 * nbox
+    mh = n_mesh * n_mesh * (n_mesh // 2 + 1) * nbox
+    npt = n_part * nbox
+    return {
+        "zero_mesh": 4 * m,
+        "cic_deposit": 12 * npt + 4 * m,
+        "fft_fwd_z": 4 * m + 8 * mh,
+        "fft_fwd_y": 16 * mh,
+        "fft_fwd_x_bin": 16 * mh + 8 * n_partial * nbins * nbox,
+        "nu_response": 8 * nbox * nbins * (2 * n_hist + n_partial + 8),
+        "rtable": 4 * nbox * (3 * n_mesh * n_mesh // 4 + 1),
+        "inv_x_green": 8 * mh + 16 * mh,
+        "fft_inv_y": 16 * mh + 24 * mh,
+        "fft_inv_z": 24 * mh + 12 * m,
+        "cic_interp": 12 * npt + 12 * m + 12 * npt,
+    }
+
+
+def step_algorithmic_bytes(n_mesh, n_part, nbox, nbins, n_hist):
+    """Whole step: read positions twice and write accelerations (36 N_p), the density
+    grid written and read and the three force grids written and read (32 M), the modes
+    written and read once (16 M_h), plus the history (8 J B)."""
+    m = n_mesh ** 3 * nbox
+    mh = n_mesh * n_mesh * (n_mesh // 2 + 1) * nbox
+    return 36 * n_part * nbox + 32 * m + 16 * mh + 8 * n_hist * nbins * nbox
+
+
+def source_sha(name):
+    p = os.path.join(ROOT, "paper_1209_0461_amd", "csrc", name)
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(workload, kernel):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        rec = t[workload][kernel]
+        if rec.get("source_sha") != source_sha(KERNEL_SOURCES[kernel]):
+            return None       # kernel changed since the counters were taken
+        return rec["bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def make_workload(name, mass_index):
+    from synth import CONFIGS, batched_lattices, zeldovich_lattice
+    cfg = dict(CONFIGS[name])
+    if cfg["n_boxes"] == 1:
+        m = cfg["m_nu"][mass_index % len(cfg["m_nu"])]
+        seed = cfg["seeds"][mass_index % len(cfg["seeds"])]
+        pos = zeldovich_lattice(cfg["n_side"], cfg["box"], cfg["sigma_cells"], seed)[None]
+        masses = np.array([m])
+    else:
+        pos, masses = batched_lattices(cfg)
+    return cfg, np.ascontiguousarray(pos), masses
+
+
+def cpu_baseline(cfg, pos, masses, hists):
+    """Time the FP64 oracle on one full step of box 0 (single-threaded NumPy)."""
+    import oracle.step as ostep
+    t0 = time.perf_counter()
+    ostep.full_step(pos[0], cfg["n_mesh"], cfg["box"], cfg["n_kbins"], hists[0], cfg["a_now"],
+                    float(masses[0]), substeps=cfg["substeps"])
+    dt = time.perf_counter() - t0
+    nbox = pos.shape[0]
+    return {"value": 1.0 / (dt * nbox), "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full FP64 oracle step of one {cfg['n_mesh']}^3 box "
+                      f"({pos.shape[1]} particles), {dt:.1f} s, single-threaded NumPy"
+                      + (f"; scaled to {nbox} boxes" if nbox > 1 else "")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="pm256")
+    ap.add_argument("--mass-index", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay the step as a HIP graph")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the step is "
+              "single-GPU in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1209_0461_amd import PMNu, binding, LIB_PATH
+    if not os.path.exists(LIB_PATH):
+        from paper_1209_0461_amd import build
+        build.build()
+    dev = torch.device("cuda:0")
+
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(n, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_mib": args.copy_probe}))
+        return
+
+    from synth import log_spaced_nodes, synthetic_history
+    cfg, pos_np, masses = make_workload(args.workload, args.mass_index)
+    nbox, npart = pos_np.shape[0], pos_np.shape[1]
+    n_mesh, nbins, J = cfg["n_mesh"], cfg["n_kbins"], cfg["n_hist"]
+    a_now = cfg["a_now"]
+    nodes = log_spaced_nodes(cfg["a_lo"], a_now, J)
+
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = PMNu(n_mesh, npart, cfg["box"], nbins, J + 2, masses, substeps=cfg["substeps"])
+        pos = torch.from_numpy(pos_np).to(dev)
+        acc = torch.zeros_like(pos)
+        # stored history: synthetic linear growth scaled to this run's measured spectrum
+        ctx.deposit(pos)
+        _, _, kmean = ctx.bins()
+        hists = []
+        for b in range(nbox):
+            pc = ctx.spectrum(b)["p_cdm"]
+            h = synthetic_history(kmean, np.sqrt(pc), nodes, float(masses[b]))
+            ctx.set_history(b, h)
+            hists.append(h)
+        for _ in range(args.warmup):
+            ctx.step(pos, acc, a_now)
+        if args.graph:
+            binding.pm_nu_graph_capture(ctx.h, pos, acc, a_now)
+            for _ in range(args.warmup):
+                binding.pm_nu_graph_launch(ctx.h)
+        stream.synchronize()
+        binding.pm_nu_read_timing(ctx.h)
+        binding.pm_nu_set_timing(ctx.h, not args.graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            if args.graph:
+                binding.pm_nu_graph_launch(ctx.h)
+            else:
+                ctx.step(pos, acc, a_now)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        timing = binding.pm_nu_read_timing(ctx.h)
+        binding.pm_nu_set_timing(ctx.h, False)
+        sp = ctx.spectrum(0)
+        finite = bool(np.isfinite(acc.cpu().numpy()).all() and np.isfinite(sp["ratio"]).all())
+
+    from paper_1209_0461_amd.binding import load_library  # noqa: F401
+    n_partial = (n_mesh // min(16 if n_mesh <= 256 else 8, n_mesh)) * (n_mesh // 2 + 1)
+    sb = stage_bytes(n_mesh, npart, nbox, nbins, J, n_partial)
+    stages = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1],
+                  "gbs": sb.get(k, 0) / (v[0] / v[1] * 1e-3) / 1e9 if k in sb else None}
+              for k, v in timing.items() if v[1] > 0}
+    value = args.steps / dt
+    out = {
+        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "dtype_detail": "FP32 deposit/FFT/Green/interpolation; FP64 k-bin sums and the "
+                        "neutrino history integral",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {nbox} x {npart} particles on {n_mesh}^3, "
+                               f"L={cfg['box']} Mpc/h, {nbins} k-bins, {J} history nodes "
+                               f"over a in [{cfg['a_lo']}, {a_now}], Q={cfg['substeps']}, "
+                               f"M_nu={','.join(f'{m:.3g}' for m in masses[:4])}"
+                               + ("..." if nbox > 4 else "") + " eV",
+                   "n_mesh": n_mesh, "n_particles": npart * nbox, "n_boxes": nbox,
+                   "graph": bool(args.graph)},
+        "particle_updates_per_s": value * npart * nbox,
+        "finite": finite,
+    }
+    step_bytes = step_algorithmic_bytes(n_mesh, npart, nbox, nbins, J)
+    out["step_hbm"] = {"algorithmic_bytes": step_bytes,
+                       "achieved_gbs": step_bytes * value / 1e9,
+                       "frac": step_bytes * value / 1e9 / HBM_PEAK_GBS}
+    if stages:
+        dom = max(stages, key=lambda k: stages[k]["ms_per_launch"] * stages[k]["launches"])
+        ach = sb[dom] / (stages[dom]["ms_per_launch"] * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                           "traffic": load_traffic(args.workload, dom),
+                           "algorithmic_bytes_per_launch": sb[dom]}
+        out["stages"] = stages
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, pos_np, masses, hists)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

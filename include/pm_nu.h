@@ -1,0 +1,216 @@
+/* pm_nu.h -- C ABI of the MI355X (gfx950) particle-mesh gravity step with the massive-
+ * neutrino density added by linear response (Ali-Haimoud & Bird, arXiv:1209.0461).
+ *
+ * The step follows the loop of the paper's Sec. 4.3 (ii)-(iv):
+ *   pm_nu_deposit   CDM density by cloud-in-cell, forward FFT, binned P_cdm(k)     (ii)
+ *   pm_nu_response  P_nu^{1/2}(k, a) from the history integral eq. (P-final),
+ *                   the ratio R(k) = (P_nu/P_cdm)^{1/2} (eq. (phases)) and the new
+ *                   total-matter amplitude appended to the history                 (iii)
+ *   pm_nu_force     delta_M = [(1 - f_nu) + f_nu R(|k|)] delta_cdm (Sec. 4.3 (iv)),
+ *                   Poisson's equation eq. (Poisson), spectral gradient, inverse FFT
+ *                   and cloud-in-cell interpolation of the acceleration             (iv)
+ *
+ * Conventions
+ *   Units: c = 1, lengths in Mpc/h, wavenumbers in h/Mpc, H0 = 1/2997.92458 h/Mpc.
+ *   Positions: FP32 array [n_boxes][n_particles][3]; component 0 is mesh axis 0 (the
+ *     slowest index of a C-order N^3 grid). Values outside [0, L) are wrapped.
+ *   Accelerations: FP32 [n_boxes][n_particles][3], acc = -grad(phi) with
+ *     k^2 phi = -(3/2) H0^2 Omega_M delta_M / a  (units h/Mpc with c = 1).
+ *   Pointers marked (dev) are device pointers owned by the caller; pointers marked
+ *     (host) are host memory owned by the caller. The library owns all other memory.
+ *   Work is enqueued on cfg.stream and runs asynchronously unless marked (sync).
+ *   Every int-returning call returns PM_NU_OK (0) or a negative PM_NU_E* code; the
+ *     message of the last failure on the calling thread is pm_nu_last_error().
+ *   Per step the calls must come in the order deposit -> response -> force
+ *     (pm_nu_step does all three); any other order returns PM_NU_ESTATE.
+ *   Mesh sizes: powers of two from 8 to 512.
+ */
+#ifndef PM_NU_H
+#define PM_NU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PM_NU_OK = 0,
+  PM_NU_EINVAL = -1,      /* bad argument or configuration                          */
+  PM_NU_ENOMEM = -2,      /* device or host allocation failed                        */
+  PM_NU_EHIP = -3,        /* a HIP runtime call failed                               */
+  PM_NU_ESTATE = -4,      /* call order violated (e.g. force before response)        */
+  PM_NU_EHISTORY = -5,    /* history missing, not increasing in a, or full           */
+  PM_NU_ENODEV = -6,      /* no usable gfx950 device                                 */
+  PM_NU_ESURROGATE = -7,  /* surrogate requested but not loaded / input out of range */
+  PM_NU_ENONFINITE = -8   /* a non-finite particle position was seen by the deposit  */
+};
+
+typedef struct pm_nu_ctx pm_nu_ctx;
+
+typedef struct {
+  int32_t n_mesh;          /* N: mesh points per side, power of two in [8, 512]         */
+  int32_t n_boxes;         /* independent boxes sharing N, L, bins (>= 1)                */
+  int64_t n_particles;     /* CDM particles per box (>= 1)                               */
+  double box_size;         /* L [Mpc/h]                                                  */
+  double omega_m;          /* Omega_M today, neutrinos included                          */
+  double hubble;           /* h                                                          */
+  int32_t n_kbins;         /* B: log-spaced bins over [2 pi/L, sqrt(3) pi N/L], 1..1024  */
+  int32_t max_history;     /* history capacity in nodes per box, current step included   */
+  int32_t substeps;        /* Q: quadrature steps per history interval (>= 1)            */
+  int32_t iterations;      /* iterations of the implicit equation (Sec. 4.3 (iii)), >= 1 */
+  int32_t deconvolve;      /* 1: divide the Green's function by the CIC window squared  */
+  int32_t response_mode;   /* 0: exact integral; 1: surrogate network; 2: surrogate with
+                              the exact integral run beside it as a check                */
+  int32_t n_species;       /* degenerate neutrino species sharing the total mass (3)    */
+  void* stream;            /* hipStream_t for all work; NULL = the null stream           */
+} pm_nu_config;
+
+/* Fill *cfg with defaults: N = 32, one box, 32768 particles, L = 128, Omega_M = 0.3,
+ * h = 0.7, 32 bins, 256 history nodes, Q = 8, 1 iteration, deconvolution on, exact
+ * response, 3 species, null stream. */
+void pm_nu_default_config(pm_nu_config* cfg);
+
+/* Create a context on the current HIP device. m_nu_total (host) [n_boxes]: total
+ * neutrino mass per box in eV (0 allowed: plain CDM). Allocates every buffer the step
+ * needs; later calls allocate nothing on the device (sync). */
+int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** out);
+
+/* Release everything owned by ctx (sync). NULL is ignored. */
+void pm_nu_destroy(pm_nu_ctx* ctx);
+
+/* Thread-local text of the last error (never NULL). */
+const char* pm_nu_last_error(void);
+
+/* Bin geometry (host, sync): integer |n|^2 edges [B+1] (mode n is in bin b when
+ * edge[b] <= |n|^2 < edge[b+1], the top bin also takes |n|^2 = 3N^2/4), mode counts
+ * [B] (full-sphere counts) and mean |k| [B] in h/Mpc. Any pointer may be NULL. */
+int pm_nu_get_bins(pm_nu_ctx* ctx, int64_t* edge_n2, double* mode_count, double* k_mean);
+
+/* Load the stored history of one box (sync). Nodes j = 0..n_nodes-1 at strictly
+ * increasing scale factors a (host) [n]; node 0 is the initial time a_i.
+ *   pm_half  (host) [n][B]: P_M^{1/2}(k_b, a_j), the stored total-matter amplitudes
+ *   pnu_half (host) [n][B]: P_nu^{1/2}(k_b, a_j) (the last row seeds the first iteration)
+ *   pnu_half_init (host) [B]: P_nu^{1/2}(k_b, a_i) of the initial-condition term
+ *   theta_over_delta_init (host) [B]: [theta_nu/delta_nu]_i(k_b) in h/Mpc
+ * (eq. (P-final), eq. (deltaI-nu)). Replaces any previous history of the box. */
+int pm_nu_set_history(pm_nu_ctx* ctx, int box, int n_nodes, const double* a,
+                      const double* pm_half, const double* pnu_half,
+                      const double* pnu_half_init, const double* theta_over_delta_init);
+
+/* Read the history of one box (sync): *n_nodes, a [n], pm_half [n][B], pnu_half [n][B]
+ * (caller sizes the arrays with max_history; any array pointer may be NULL). */
+int pm_nu_get_history(pm_nu_ctx* ctx, int box, int* n_nodes, double* a, double* pm_half,
+                      double* pnu_half);
+
+/* Stage (ii): CIC mass of every particle (unit mass), delta = rho/rho_bar - 1, forward
+ * real FFT and the binned power P_cdm(k_b) = (L^3/N^6) sum_b w |delta_k|^2 / C_b with
+ * FP64 sums. pos (dev) [n_boxes][n_particles][3]. */
+int pm_nu_deposit(pm_nu_ctx* ctx, const float* pos);
+
+/* Stage (iii) at scale factor a_now, which must not precede the last stored node.
+ * Evaluates eq. (P-final) in FP64 by the trapezoid rule in ln a (Q steps per history
+ * interval, P_M^{1/2} linear in ln a between nodes, dtau = dln a/(a H), flat matter +
+ * Lambda H(a)), using P_nu(a_now) ~ P_nu(previous node) inside the integral for the
+ * first iteration (Sec. 4.3 (iii), Appendix B). Writes P_nu^{1/2}, R_b and appends the
+ * node a_now with P_M^{1/2} = (1-f_nu) P_cdm^{1/2} + f_nu P_nu^{1/2}; if a_now equals
+ * the last stored node that node is recomputed from the ones before it instead. A box
+ * with m_nu_total = 0 has f_nu = 0: its P_nu^{1/2} and R read 0 and the step is plain CDM.
+ * Needs pm_nu_deposit first. */
+int pm_nu_response(pm_nu_ctx* ctx, double a_now);
+
+/* Stage (iv): rescale the modes by (1 - f_nu) + f_nu R(|k|) (R linear in ln k between
+ * non-empty bin means, held outside), phi = -(3/2) H0^2 Omega_M delta_M /(a k^2 W^2)
+ * (W = prod sinc^2(pi n_a/N) when deconvolve), g_a = -i k_a phi (zero on the Nyquist
+ * index of axis a), inverse FFT, CIC interpolation into acc (dev)
+ * [n_boxes][n_particles][3]. pos must be the array given to the deposit. a_now must
+ * equal the one given to pm_nu_response. */
+int pm_nu_force(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now);
+
+/* deposit + response + force. */
+int pm_nu_step(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now);
+
+/* Per-box spectra of the last step (host, sync), each [B], any may be NULL:
+ * P_cdm(k_b) [(Mpc/h)^3], P_nu^{1/2}(k_b), R_b = P_nu^{1/2}/P_cdm^{1/2}. Empty bins
+ * read 0. Returns PM_NU_ENONFINITE if the last deposit saw a non-finite position. */
+int pm_nu_get_spectrum(pm_nu_ctx* ctx, int box, double* p_cdm, double* pnu_half,
+                       double* ratio);
+
+/* ---- diagnostics (copies of internal state, enqueued on the stream) ---------------- */
+/* Deposited mass rho (unit mass per particle) of one box into out (dev) [N][N][N]. */
+int pm_nu_copy_density(pm_nu_ctx* ctx, int box, float* out);
+/* delta_k of one box (after pm_nu_deposit) into out (dev) as complex64 pairs in the
+ * layout of numpy.fft.rfftn: [N][N][N/2+1][2]. */
+int pm_nu_copy_modes(pm_nu_ctx* ctx, int box, float* out);
+/* Acceleration grid of one axis (after pm_nu_force) into out (dev) [N][N][N]. */
+int pm_nu_copy_force_grid(pm_nu_ctx* ctx, int box, int axis, float* out);
+
+/* ---- per-kernel timing with HIP events on the library's stream ---------------------- */
+/* enable != 0 starts recording an event pair around every kernel launch. */
+int pm_nu_set_timing(pm_nu_ctx* ctx, int enable);
+/* (sync) Sums of kernel times [ms] and launch counts per stage since the last read,
+ * then resets them. names[i] are static strings. Arrays hold *n_stages entries on
+ * input (capacity) and output (count). */
+int pm_nu_read_timing(pm_nu_ctx* ctx, int* n_stages, const char** names, double* total_ms,
+                      int64_t* launches);
+
+/* ---- HIP graph of a whole step (for batched small boxes and launch-bound loops) ------ */
+/* Capture deposit + response + force at a_now for the given pointers into a graph
+ * (sync). The time grid for a_now is prepared before capture. Replays recompute the
+ * node a_now each time. */
+int pm_nu_graph_capture(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now);
+/* Launch the captured graph on the stream. */
+int pm_nu_graph_launch(pm_nu_ctx* ctx);
+
+/* ---- launch-shape autotuning ----------------------------------------------------------- */
+/* Time the candidate launch shapes of the tunable kernels on this context's buffers with
+ * HIP events (pos/acc (dev) as for pm_nu_step, a_now as for pm_nu_response; the history
+ * must be set), keep the fastest, and if cache_path is not NULL read/write the choice
+ * as JSON keyed by (device name, N, n_boxes) (sync). */
+int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
+                   const char* cache_path);
+/* Current launch-shape choice as a short JSON text (host buffer of cap bytes, sync). */
+int pm_nu_tuning(pm_nu_ctx* ctx, char* out, size_t cap);
+
+/* ---- learned surrogate for the history integral (not in the paper) -------------------- */
+/* A fully connected network 11 -> 128 -> 128 -> 128 -> 1, GELU hidden activations,
+ * bfloat16 weights and activations on the matrix cores with FP32 accumulation, FP32
+ * master weights. Inputs per (box, bin): ln k_b, ln a, M_nu, and the 8 latest stored
+ * amplitudes P_M^{1/2}(a_{n-m})/P_cdm^{1/2}(a_now), m = 1..8; output
+ * y = ln(R_b (1 + k_b/k_fs(a))^2), i.e. R relative to the Appendix A approximation.
+ * Features are standardised with the mean/scale stored with the weights. */
+enum { PM_NU_SUR_IN = 11, PM_NU_SUR_HIDDEN = 128 };
+/* Number of FP32 values in a weight blob: 34689 parameters + 2*11 feature stats +
+ * 2 target stats. */
+int64_t pm_nu_surrogate_blob_floats(void);
+/* Load weights (host) [pm_nu_surrogate_blob_floats()] (sync). */
+int pm_nu_surrogate_load(pm_nu_ctx* ctx, const float* blob, int64_t n_floats);
+/* Copy the current weights out (host) (sync). */
+int pm_nu_surrogate_save(pm_nu_ctx* ctx, float* blob, int64_t n_floats);
+/* Initialise weights (seeded) and the feature/target standardisation from a dataset
+ * x (dev) [n][11], y (dev) [n] (sync). */
+int pm_nu_surrogate_init(pm_nu_ctx* ctx, const float* x, const float* y, int64_t n,
+                         uint64_t seed);
+/* Train on x (dev) [n][11], y (dev) [n] with Adam (lr, betas 0.9/0.999) for `epochs`
+ * passes in minibatches of `batch` (multiple of 64), shuffled per epoch with `seed`.
+ * *loss_out (host) gets the mean squared error of the last epoch (sync). */
+int pm_nu_surrogate_train(pm_nu_ctx* ctx, const float* x, const float* y, int64_t n,
+                          int epochs, int batch, float lr, uint64_t seed, float* loss_out);
+/* Network output for x (dev) [n][11] into y (dev) [n] (raw features, not standardised). */
+int pm_nu_surrogate_predict(pm_nu_ctx* ctx, const float* x, float* y, int64_t n);
+/* One forward + backward of the MSE loss on x (dev) [n][11], y (dev) [n] with the current
+ * weights; writes the FP32 gradients (dev) [34689] in blob order and the loss (host). */
+int pm_nu_surrogate_grad(pm_nu_ctx* ctx, const float* x, const float* y, int64_t n,
+                         float* grad, float* loss_out);
+/* Features (dev) [n_boxes][B][11] of the current step (after pm_nu_deposit, history
+ * set), as the response would feed them to the network. */
+int pm_nu_surrogate_features(pm_nu_ctx* ctx, double a_now, float* x);
+/* Ratios of the check mode (response_mode 2): exact R and surrogate R (host) [B]. */
+int pm_nu_get_surrogate_check(pm_nu_ctx* ctx, int box, double* ratio_exact,
+                              double* ratio_surrogate);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PM_NU_H */

@@ -1,0 +1,385 @@
+"""ctypes binding of libpmnu.so (include/pm_nu.h): argument marshalling only.
+
+Functions carry the C names (pm_nu_init, pm_nu_deposit, ...). Device arrays are passed as
+torch tensors (their data_ptr()); host arrays as NumPy arrays. All device work runs in
+the library's HIP kernels; nothing here computes any part of the step.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmnu.so")
+
+PM_NU_OK = 0
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "EHISTORY",
+          -6: "ENODEV", -7: "ESURROGATE", -8: "ENONFINITE"}
+SUR_IN = 11
+STAGE_CAP = 32
+
+
+class PMNuError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pm_nu error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n_mesh", ctypes.c_int32), ("n_boxes", ctypes.c_int32),
+                ("n_particles", ctypes.c_int64), ("box_size", ctypes.c_double),
+                ("omega_m", ctypes.c_double), ("hubble", ctypes.c_double),
+                ("n_kbins", ctypes.c_int32), ("max_history", ctypes.c_int32),
+                ("substeps", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("deconvolve", ctypes.c_int32), ("response_mode", ctypes.c_int32),
+                ("n_species", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+_INT = ctypes.c_int
+_F = ctypes.POINTER(ctypes.c_float)
+
+SIGNATURES = {
+    "pm_nu_default_config": (None, [ctypes.POINTER(Config)]),
+    "pm_nu_init": (_INT, [ctypes.POINTER(Config), _D, ctypes.POINTER(_P)]),
+    "pm_nu_destroy": (None, [_P]),
+    "pm_nu_last_error": (ctypes.c_char_p, []),
+    "pm_nu_get_bins": (_INT, [_P, _I64, _D, _D]),
+    "pm_nu_set_history": (_INT, [_P, _INT, _INT, _D, _D, _D, _D, _D]),
+    "pm_nu_get_history": (_INT, [_P, _INT, ctypes.POINTER(_INT), _D, _D, _D]),
+    "pm_nu_deposit": (_INT, [_P, _P]),
+    "pm_nu_response": (_INT, [_P, ctypes.c_double]),
+    "pm_nu_force": (_INT, [_P, _P, _P, ctypes.c_double]),
+    "pm_nu_step": (_INT, [_P, _P, _P, ctypes.c_double]),
+    "pm_nu_get_spectrum": (_INT, [_P, _INT, _D, _D, _D]),
+    "pm_nu_copy_density": (_INT, [_P, _INT, _P]),
+    "pm_nu_copy_modes": (_INT, [_P, _INT, _P]),
+    "pm_nu_copy_force_grid": (_INT, [_P, _INT, _INT, _P]),
+    "pm_nu_set_timing": (_INT, [_P, _INT]),
+    "pm_nu_read_timing": (_INT, [_P, ctypes.POINTER(_INT), ctypes.POINTER(ctypes.c_char_p), _D, _I64]),
+    "pm_nu_graph_capture": (_INT, [_P, _P, _P, ctypes.c_double]),
+    "pm_nu_graph_launch": (_INT, [_P]),
+    "pm_nu_autotune": (_INT, [_P, _P, _P, ctypes.c_double, ctypes.c_char_p]),
+    "pm_nu_tuning": (_INT, [_P, ctypes.c_char_p, ctypes.c_size_t]),
+    "pm_nu_surrogate_blob_floats": (ctypes.c_int64, []),
+    "pm_nu_surrogate_load": (_INT, [_P, _F, ctypes.c_int64]),
+    "pm_nu_surrogate_save": (_INT, [_P, _F, ctypes.c_int64]),
+    "pm_nu_surrogate_init": (_INT, [_P, _P, _P, ctypes.c_int64, ctypes.c_uint64]),
+    "pm_nu_surrogate_train": (_INT, [_P, _P, _P, ctypes.c_int64, _INT, _INT, ctypes.c_float,
+                                     ctypes.c_uint64, _F]),
+    "pm_nu_surrogate_predict": (_INT, [_P, _P, _P, ctypes.c_int64]),
+    "pm_nu_surrogate_grad": (_INT, [_P, _P, _P, ctypes.c_int64, _P, _F]),
+    "pm_nu_surrogate_features": (_INT, [_P, ctypes.c_double, _P]),
+    "pm_nu_get_surrogate_check": (_INT, [_P, _INT, _D, _D]),
+}
+
+_lib = None
+
+
+def load_library(path=None):
+    """Load libpmnu.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_1209_0461_amd.build`"
+                           " (the step has no CPU fallback)")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != PM_NU_OK:
+        msg = load_library().pm_nu_last_error()
+        raise PMNuError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def _dptr(a):
+    """Host double array pointer (contiguous float64 copy kept alive by the caller)."""
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None and a.shape != shape:
+        a = a.reshape(shape)
+    return a
+
+
+def _dev(t):
+    """Device pointer of a torch tensor on a GPU."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def current_stream_handle():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ---------------------------------------------------------------- C-named calls ----
+def pm_nu_default_config():
+    cfg = Config()
+    load_library().pm_nu_default_config(ctypes.byref(cfg))
+    return cfg
+
+
+def pm_nu_init(cfg, m_nu_total):
+    m = _f64(m_nu_total).reshape(-1)
+    if m.size != cfg.n_boxes:
+        raise ValueError("one neutrino mass per box is required")
+    h = _P()
+    _check(load_library().pm_nu_init(ctypes.byref(cfg), _dptr(m), ctypes.byref(h)))
+    return h
+
+
+def pm_nu_destroy(h):
+    if h:
+        load_library().pm_nu_destroy(h)
+
+
+def pm_nu_get_bins(h, n_kbins):
+    edges = np.zeros(n_kbins + 1, dtype=np.int64)
+    counts = np.zeros(n_kbins)
+    kmean = np.zeros(n_kbins)
+    _check(load_library().pm_nu_get_bins(h, edges.ctypes.data_as(_I64), _dptr(counts),
+                                         _dptr(kmean)))
+    return edges, counts, kmean
+
+
+def pm_nu_set_history(h, box, a, pm_half, pnu_half, pnu_half_init, theta_over_delta_init):
+    a = _f64(a).reshape(-1)
+    n = a.size
+    pm = _f64(pm_half)
+    pn = _f64(pnu_half)
+    pi = _f64(pnu_half_init).reshape(-1)
+    th = _f64(theta_over_delta_init).reshape(-1)
+    if pm.shape[0] != n or pn.shape[0] != n:
+        raise ValueError("history arrays must have one row per node")
+    _check(load_library().pm_nu_set_history(h, box, n, _dptr(a), _dptr(pm), _dptr(pn),
+                                            _dptr(pi), _dptr(th)))
+
+
+def pm_nu_get_history(h, box, max_history, n_kbins):
+    n = _INT()
+    a = np.zeros(max_history)
+    pm = np.zeros((max_history, n_kbins))
+    pn = np.zeros((max_history, n_kbins))
+    _check(load_library().pm_nu_get_history(h, box, ctypes.byref(n), _dptr(a), _dptr(pm),
+                                            _dptr(pn)))
+    k = n.value
+    return a[:k].copy(), pm[:k].copy(), pn[:k].copy()
+
+
+def pm_nu_deposit(h, pos):
+    _check(load_library().pm_nu_deposit(h, _dev(pos)))
+
+
+def pm_nu_response(h, a_now):
+    _check(load_library().pm_nu_response(h, float(a_now)))
+
+
+def pm_nu_force(h, pos, acc, a_now):
+    _check(load_library().pm_nu_force(h, _dev(pos), _dev(acc), float(a_now)))
+
+
+def pm_nu_step(h, pos, acc, a_now):
+    _check(load_library().pm_nu_step(h, _dev(pos), _dev(acc), float(a_now)))
+
+
+def pm_nu_get_spectrum(h, box, n_kbins):
+    p = np.zeros(n_kbins)
+    pn = np.zeros(n_kbins)
+    r = np.zeros(n_kbins)
+    _check(load_library().pm_nu_get_spectrum(h, box, _dptr(p), _dptr(pn), _dptr(r)))
+    return p, pn, r
+
+
+def pm_nu_copy_density(h, box, out):
+    _check(load_library().pm_nu_copy_density(h, box, _dev(out)))
+
+
+def pm_nu_copy_modes(h, box, out):
+    _check(load_library().pm_nu_copy_modes(h, box, _dev(out)))
+
+
+def pm_nu_copy_force_grid(h, box, axis, out):
+    _check(load_library().pm_nu_copy_force_grid(h, box, axis, _dev(out)))
+
+
+def pm_nu_set_timing(h, enable):
+    _check(load_library().pm_nu_set_timing(h, 1 if enable else 0))
+
+
+def pm_nu_read_timing(h):
+    n = _INT(STAGE_CAP)
+    names = (ctypes.c_char_p * STAGE_CAP)()
+    ms = np.zeros(STAGE_CAP)
+    cnt = np.zeros(STAGE_CAP, dtype=np.int64)
+    _check(load_library().pm_nu_read_timing(h, ctypes.byref(n), names, _dptr(ms),
+                                            cnt.ctypes.data_as(_I64)))
+    return {names[i].decode(): (float(ms[i]), int(cnt[i])) for i in range(n.value)}
+
+
+def pm_nu_graph_capture(h, pos, acc, a_now):
+    _check(load_library().pm_nu_graph_capture(h, _dev(pos), _dev(acc), float(a_now)))
+
+
+def pm_nu_graph_launch(h):
+    _check(load_library().pm_nu_graph_launch(h))
+
+
+def pm_nu_autotune(h, pos, acc, a_now, cache_path=None):
+    cp = cache_path.encode() if cache_path else None
+    _check(load_library().pm_nu_autotune(h, _dev(pos), _dev(acc), float(a_now), cp))
+
+
+def pm_nu_tuning(h):
+    buf = ctypes.create_string_buffer(1024)
+    _check(load_library().pm_nu_tuning(h, buf, 1024))
+    return buf.value.decode()
+
+
+def pm_nu_surrogate_blob_floats():
+    return int(load_library().pm_nu_surrogate_blob_floats())
+
+
+def pm_nu_surrogate_load(h, blob):
+    b = np.ascontiguousarray(np.asarray(blob, dtype=np.float32)).reshape(-1)
+    _check(load_library().pm_nu_surrogate_load(h, b.ctypes.data_as(_F), b.size))
+
+
+def pm_nu_surrogate_save(h):
+    b = np.zeros(pm_nu_surrogate_blob_floats(), dtype=np.float32)
+    _check(load_library().pm_nu_surrogate_save(h, b.ctypes.data_as(_F), b.size))
+    return b
+
+
+def pm_nu_surrogate_init(h, x, y, seed):
+    _check(load_library().pm_nu_surrogate_init(h, _dev(x), _dev(y), x.shape[0], int(seed)))
+
+
+def pm_nu_surrogate_train(h, x, y, epochs, batch, lr, seed):
+    loss = ctypes.c_float(0.0)
+    _check(load_library().pm_nu_surrogate_train(h, _dev(x), _dev(y), x.shape[0], int(epochs),
+                                                int(batch), float(lr), int(seed),
+                                                ctypes.byref(loss)))
+    return float(loss.value)
+
+
+def pm_nu_surrogate_predict(h, x, y):
+    _check(load_library().pm_nu_surrogate_predict(h, _dev(x), _dev(y), x.shape[0]))
+
+
+def pm_nu_surrogate_grad(h, x, y, grad):
+    loss = ctypes.c_float(0.0)
+    _check(load_library().pm_nu_surrogate_grad(h, _dev(x), _dev(y), x.shape[0], _dev(grad),
+                                               ctypes.byref(loss)))
+    return float(loss.value)
+
+
+def pm_nu_surrogate_features(h, a_now, x):
+    _check(load_library().pm_nu_surrogate_features(h, float(a_now), _dev(x)))
+
+
+def pm_nu_get_surrogate_check(h, box, n_kbins):
+    ex = np.zeros(n_kbins)
+    su = np.zeros(n_kbins)
+    _check(load_library().pm_nu_get_surrogate_check(h, box, _dptr(ex), _dptr(su)))
+    return ex, su
+
+
+# --------------------------------------------------------------- convenience class ----
+class PMNu:
+    """One library context. Device tensors in, device tensors out."""
+
+    def __init__(self, n_mesh, n_particles, box_size, n_kbins, max_history, m_nu_total,
+                 omega_m=0.3, hubble=0.7, substeps=8, iterations=1, deconvolve=True,
+                 response_mode=0, n_species=3, stream=None):
+        m = np.atleast_1d(np.asarray(m_nu_total, dtype=np.float64))
+        cfg = pm_nu_default_config()
+        cfg.n_mesh = int(n_mesh)
+        cfg.n_boxes = int(m.size)
+        cfg.n_particles = int(n_particles)
+        cfg.box_size = float(box_size)
+        cfg.omega_m = float(omega_m)
+        cfg.hubble = float(hubble)
+        cfg.n_kbins = int(n_kbins)
+        cfg.max_history = int(max_history)
+        cfg.substeps = int(substeps)
+        cfg.iterations = int(iterations)
+        cfg.deconvolve = 1 if deconvolve else 0
+        cfg.response_mode = int(response_mode)
+        cfg.n_species = int(n_species)
+        cfg.stream = stream if stream is not None else current_stream_handle()
+        self.cfg = cfg
+        self.m_nu = m
+        self.h = pm_nu_init(cfg, m)
+
+    def close(self):
+        if getattr(self, "h", None):
+            pm_nu_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_boxes(self):
+        return self.cfg.n_boxes
+
+    def bins(self):
+        return pm_nu_get_bins(self.h, self.cfg.n_kbins)
+
+    def set_history(self, box, hist):
+        pm_nu_set_history(self.h, box, hist["a"], hist["pm_half"], hist["pnu_half"],
+                          hist["pnu_half_init"], hist["theta_over_delta_init"])
+
+    def history(self, box):
+        return pm_nu_get_history(self.h, box, self.cfg.max_history, self.cfg.n_kbins)
+
+    def _check_particles(self, t, name):
+        import torch
+        want = self.cfg.n_boxes * self.cfg.n_particles * 3
+        if t.dtype != torch.float32 or t.numel() != want:
+            raise ValueError(f"{name} must be float32 with n_boxes*n_particles*3 = {want} "
+                             f"elements (got {t.dtype}, {t.numel()})")
+
+    def deposit(self, pos):
+        self._check_particles(pos, "pos")
+        pm_nu_deposit(self.h, pos)
+
+    def response(self, a_now):
+        pm_nu_response(self.h, a_now)
+
+    def force(self, pos, acc, a_now):
+        self._check_particles(pos, "pos")
+        self._check_particles(acc, "acc")
+        pm_nu_force(self.h, pos, acc, a_now)
+
+    def step(self, pos, acc, a_now):
+        self._check_particles(pos, "pos")
+        self._check_particles(acc, "acc")
+        pm_nu_step(self.h, pos, acc, a_now)
+
+    def spectrum(self, box=0):
+        p, pn, r = pm_nu_get_spectrum(self.h, box, self.cfg.n_kbins)
+        return dict(p_cdm=p, pnu_half=pn, ratio=r)

@@ -1,0 +1,385 @@
+// 3-D real FFT passes of the PM step, with the k-binning fused into the last forward pass
+// and the neutrino rescale, Green's function and first gradient factor fused into the
+// first inverse pass (gfx950, FP32 data, FP64 bin sums).
+//
+// Layouts (per box b):
+//   real grid  [b][x][y][z]                 (z contiguous)
+//   modes      [b][kz][kx][ky], kz in [0, N/2], kx, ky in [0, N)   (ky contiguous)
+// Putting the half-length axis kz outermost keeps every row a power of two long and
+// aligned; numpy's rfftn order [kx][ky][kz] is produced only by launch_copy_modes.
+//
+// Forward:  fwd_z   delta = rho/rho_bar - 1 from the fixed-point density, real rows along
+//                   z -> half spectra (two rows per complex FFT), written transposed into
+//                   [kz][x][y]
+//           fwd_y   complex FFT of every contiguous ky row
+//           fwd_x   complex FFT along kx (tile of N x TX), then the FP64 mode sums per
+//                   k-bin: sum w |delta_k|^2, w = 1 on the kz = 0, N/2 planes, else 2
+// Inverse:  inv_x   delta_M = T(|n|^2) delta_cdm, phi = -C T delta/(k^2 W^2), and the two
+//                   fields F1 = phi, F2 = -i k_x phi, inverse FFT along kx
+//           inv_y   G1 = IFFT_y F1, G2 = IFFT_y(-i k_y F1), G3 = IFFT_y F2
+//           inv_z   complex-to-real along z of -i k_z G1, G2, G3 (two rows per complex
+//                   FFT), transposed back to [x][y][z]: the acceleration grids g_z, g_y, g_x
+// Since the derivative along an axis commutes with the transforms along the other axes,
+// this needs 2 + 3 intermediate fields instead of 3 + 3 + 3.
+#include "fft_lds.hpp"
+#include "pm_nu_internal.hpp"
+
+namespace pmnu {
+namespace {
+
+constexpr int NT = 256;
+
+template <int N> struct Shape {
+  static constexpr int NK = N / 2 + 1;
+  static constexpr int FZ_TY = N <= 32 ? N : (N <= 256 ? 32 : 16);   // real rows per WG
+  static constexpr int FY_NL = N <= 256 ? (N < 16 ? N : 16) : 8;      // rows per WG
+  static constexpr int FX_TX = N < 16 ? N : (N <= 256 ? 16 : 8);      // ky columns per WG
+  static constexpr int IX_TX = N < 8 ? N : (N <= 256 ? 8 : 4);
+  static constexpr int IY_NL = N < 8 ? N : (N <= 256 ? 8 : 4);
+  static constexpr int IZ_TY = N < 16 ? N : (N <= 256 ? 16 : 8);
+};
+
+__device__ __forceinline__ int signed_index(int i, int n) { return i < n / 2 ? i : i - n; }
+
+// ------------------------------------------------------------------------ forward ----
+template <int N>
+__global__ __launch_bounds__(NT) void fwd_z_kernel(const unsigned long long* __restrict__ rho,
+                                                   float2* __restrict__ out,
+                                                   const float2* __restrict__ twg,
+                                                   double scale) {
+  constexpr int TY = Shape<N>::FZ_TY, NL = TY / 2, ES = NL + 1, NK = Shape<N>::NK;
+  __shared__ float2 lds[N * ES];
+  __shared__ float2 tw[N];
+  const int y0 = blockIdx.x * TY, x = blockIdx.y, box = blockIdx.z;
+  load_twiddles<N, NT>(tw, twg);
+  const unsigned long long* src = rho + ((static_cast<size_t>(box) * N + x) * N + y0) * N;
+  float* ldsf = reinterpret_cast<float*>(lds);
+  for (int t = threadIdx.x; t < TY * N; t += NT) {
+    const int row = t / N, e = t % N;
+    // delta = rho / rho_bar - 1 from the exact fixed-point sum, rounded once to FP32
+    ldsf[(e * ES + (row >> 1)) * 2 + (row & 1)] =
+        static_cast<float>(static_cast<double>(src[t]) * scale - 1.0);
+  }
+  __syncthreads();
+  fft_lines<N, NL, NT, -1>(lds, tw);
+  for (int t = threadIdx.x; t < NK * TY; t += NT) {
+    const int row = t % TY, k = t / TY, p = row >> 1;
+    const float2 zk = lds[k * ES + p];
+    const float2 zn = cconj(lds[((N - k) & (N - 1)) * ES + p]);
+    float2 r;
+    if ((row & 1) == 0) {
+      r = cscale(cadd(zk, zn), 0.5f);                       // A = (Z_k + conj Z_{N-k})/2
+    } else {
+      const float2 d = csub(zk, zn);                        // B = (Z_k - conj Z_{N-k})/(2i)
+      r = make_float2(0.5f * d.y, -0.5f * d.x);
+    }
+    out[((static_cast<size_t>(box) * NK + k) * N + x) * N + y0 + row] = r;
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(NT) void fwd_y_kernel(float2* __restrict__ data,
+                                                   const float2* __restrict__ twg) {
+  constexpr int NL = Shape<N>::FY_NL, ES = NL + 1;
+  __shared__ float2 lds[N * ES];
+  __shared__ float2 tw[N];
+  load_twiddles<N, NT>(tw, twg);
+  float2* base = data + static_cast<size_t>(blockIdx.x) * NL * N;
+  for (int t = threadIdx.x; t < NL * N; t += NT) lds[(t % N) * ES + t / N] = base[t];
+  __syncthreads();
+  fft_lines<N, NL, NT, -1>(lds, tw);
+  for (int t = threadIdx.x; t < NL * N; t += NT) base[t] = lds[(t % N) * ES + t / N];
+}
+
+template <int N>
+__global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data,
+                                                       const float2* __restrict__ twg,
+                                                       const uint16_t* __restrict__ bin_of_n2,
+                                                       double* __restrict__ partial, int nbins) {
+  constexpr int TX = Shape<N>::FX_TX, ES = TX + 1, NK = Shape<N>::NK;
+  __shared__ float2 lds[N * ES];
+  __shared__ float2 tw[N];
+  extern __shared__ double bins[];
+  const int y0 = blockIdx.x * TX, kz = blockIdx.y, box = blockIdx.z;
+  load_twiddles<N, NT>(tw, twg);
+  for (int b = threadIdx.x; b < nbins; b += NT) bins[b] = 0.0;
+  float2* base = data + ((static_cast<size_t>(box) * NK + kz) * N) * N + y0;
+  for (int t = threadIdx.x; t < N * TX; t += NT) {
+    const int y = t % TX, x = t / TX;
+    lds[x * ES + y] = base[static_cast<size_t>(x) * N + y];
+  }
+  __syncthreads();
+  fft_lines<N, TX, NT, -1>(lds, tw);
+  const double w = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
+  for (int t = threadIdx.x; t < N * TX; t += NT) {
+    const int y = t % TX, x = t / TX;
+    const float2 v = lds[x * ES + y];
+    base[static_cast<size_t>(x) * N + y] = v;
+    const int nx = signed_index(x, N), ny = signed_index(y0 + y, N);
+    const int n2 = nx * nx + ny * ny + kz * kz;
+    if (n2 > 0) {
+      const double re = v.x, im = v.y;
+      atomicAdd(&bins[bin_of_n2[n2]], w * (re * re + im * im));
+    }
+  }
+  __syncthreads();
+  const int wg = blockIdx.y * gridDim.x + blockIdx.x;
+  double* dst = partial + (static_cast<size_t>(box) * gridDim.x * gridDim.y + wg) * nbins;
+  for (int b = threadIdx.x; b < nbins; b += NT) dst[b] = bins[b];
+}
+
+// ------------------------------------------------------------------------ inverse ----
+template <int N>
+__global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk,
+                                                   float2* __restrict__ f1,
+                                                   float2* __restrict__ f2,
+                                                   const float2* __restrict__ twg,
+                                                   const float* __restrict__ rtable, int n2max,
+                                                   const float* __restrict__ inv_w2,
+                                                   float c, float kf) {
+  constexpr int TX = Shape<N>::IX_TX, NL = 2 * TX, ES = NL + 1, NK = Shape<N>::NK;
+  __shared__ float2 lds[N * ES];
+  __shared__ float2 tw[N];
+  const int y0 = blockIdx.x * TX, kz = blockIdx.y, box = blockIdx.z;
+  load_twiddles<N, NT>(tw, twg);
+  const size_t off = ((static_cast<size_t>(box) * NK + kz) * N) * N + y0;
+  const float* rt = rtable + static_cast<size_t>(box) * (n2max + 1);
+  const float wz = inv_w2[kz];
+  for (int t = threadIdx.x; t < N * TX; t += NT) {
+    const int y = t % TX, x = t / TX;
+    const float2 v = dk[off + static_cast<size_t>(x) * N + y];
+    const int nx = signed_index(x, N), ny = signed_index(y0 + y, N);
+    const int n2 = nx * nx + ny * ny + kz * kz;
+    float2 phi = make_float2(0.f, 0.f);
+    if (n2 > 0) {
+      // phi = -C T(n^2) delta / (k^2 W^2), k^2 = kf^2 n^2
+      const float g = -c * rt[n2] * inv_w2[x] * inv_w2[y0 + y] * wz /
+                      (kf * kf * static_cast<float>(n2));
+      phi = cscale(v, g);
+    }
+    lds[x * ES + y] = phi;
+    const float kx = (x == N / 2) ? 0.f : kf * static_cast<float>(nx);
+    lds[x * ES + TX + y] = make_float2(kx * phi.y, -kx * phi.x);     // -i k_x phi
+  }
+  __syncthreads();
+  fft_lines<N, NL, NT, +1>(lds, tw);
+  for (int t = threadIdx.x; t < N * TX; t += NT) {
+    const int y = t % TX, x = t / TX;
+    f1[off + static_cast<size_t>(x) * N + y] = lds[x * ES + y];
+    f2[off + static_cast<size_t>(x) * N + y] = lds[x * ES + TX + y];
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(NT) void inv_y_kernel(float2* __restrict__ f1,
+                                                   float2* __restrict__ f2,
+                                                   float2* __restrict__ g2,
+                                                   const float2* __restrict__ twg, float kf) {
+  constexpr int NLR = Shape<N>::IY_NL, NL = 3 * NLR, ES = NL + 1;
+  __shared__ float2 lds[N * ES];
+  __shared__ float2 tw[N];
+  load_twiddles<N, NT>(tw, twg);
+  const size_t off = static_cast<size_t>(blockIdx.x) * NLR * N;
+  for (int t = threadIdx.x; t < NLR * N; t += NT) {
+    const int l = t / N, e = t % N;
+    const float2 a = f1[off + t];
+    lds[e * ES + l] = a;
+    const float ky = (e == N / 2) ? 0.f : kf * static_cast<float>(signed_index(e, N));
+    lds[e * ES + NLR + l] = make_float2(ky * a.y, -ky * a.x);          // -i k_y F1
+    lds[e * ES + 2 * NLR + l] = f2[off + t];
+  }
+  __syncthreads();
+  fft_lines<N, NL, NT, +1>(lds, tw);
+  for (int t = threadIdx.x; t < NLR * N; t += NT) {
+    const int l = t / N, e = t % N;
+    f1[off + t] = lds[e * ES + l];
+    g2[off + t] = lds[e * ES + NLR + l];
+    f2[off + t] = lds[e * ES + 2 * NLR + l];
+  }
+}
+
+// out: [3][nbox][x][y][z] with component 0 = g_x (from G3), 1 = g_y (G2), 2 = g_z (G1).
+template <int N>
+__global__ __launch_bounds__(NT) void inv_z_kernel(const float2* __restrict__ g1,
+                                                   const float2* __restrict__ g2,
+                                                   const float2* __restrict__ g3,
+                                                   float* __restrict__ out,
+                                                   const float2* __restrict__ twg, float kf,
+                                                   int nbox) {
+  constexpr int TY = Shape<N>::IZ_TY, ROWS = 3 * TY, NL = ROWS / 2, ES = NL + 1;
+  constexpr int NK = Shape<N>::NK;
+  __shared__ float2 lds[N * ES];
+  __shared__ float2 tw[N];
+  const int y0 = blockIdx.x * TY, x = blockIdx.y, box = blockIdx.z;
+  load_twiddles<N, NT>(tw, twg);
+  float* ldsf = reinterpret_cast<float*>(lds);
+  // Half spectra of row pair p: A[k] at slot k and B[k] at slot N-k for 0 < k < N/2;
+  // the real parts of A and B at k = 0 and k = N/2 share slots 0 and N/2.
+  for (int t = threadIdx.x; t < NK * ROWS; t += NT) {
+    const int y = t % TY, k = (t / TY) % NK, comp = t / (TY * NK);
+    const size_t gi = ((static_cast<size_t>(box) * NK + k) * N + x) * N + y0 + y;
+    float2 v;
+    if (comp == 0) {
+      v = g3[gi];
+    } else if (comp == 1) {
+      v = g2[gi];
+    } else {
+      const float2 a = g1[gi];
+      const float kz = (k == N / 2) ? 0.f : kf * static_cast<float>(k);
+      v = make_float2(kz * a.y, -kz * a.x);                            // -i k_z G1
+    }
+    const int row = comp * TY + y, p = row >> 1;
+    if (k == 0 || k == N / 2) {
+      ldsf[(k * ES + p) * 2 + (row & 1)] = v.x;
+    } else {
+      lds[((row & 1) ? N - k : k) * ES + p] = v;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < (N / 2 - 1) * NL; t += NT) {
+    const int p = t % NL, k = 1 + t / NL;
+    const float2 a = lds[k * ES + p], b = lds[(N - k) * ES + p];
+    lds[k * ES + p] = make_float2(a.x - b.y, a.y + b.x);                // A + iB
+    lds[(N - k) * ES + p] = make_float2(a.x + b.y, b.x - a.y);          // conj A + i conj B
+  }
+  __syncthreads();
+  fft_lines<N, NL, NT, +1>(lds, tw);
+  const size_t m = static_cast<size_t>(N) * N * N;
+  for (int t = threadIdx.x; t < ROWS * N; t += NT) {
+    const int e = t % N, row = t / N, comp = row / TY, y = row % TY;
+    const float2 z = lds[e * ES + (row >> 1)];
+    out[(static_cast<size_t>(comp) * nbox + box) * m + (static_cast<size_t>(x) * N + y0 + y) * N +
+        e] = (row & 1) ? z.y : z.x;
+  }
+}
+
+template <int N>
+__global__ void copy_modes_kernel(const float2* __restrict__ ck, float2* __restrict__ out,
+                                  int box) {
+  constexpr int NK = N / 2 + 1;
+  const int64_t total = static_cast<int64_t>(N) * N * NK;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int kz = static_cast<int>(i % NK);
+    const int ky = static_cast<int>((i / NK) % N);
+    const int kx = static_cast<int>(i / (static_cast<int64_t>(NK) * N));
+    out[i] = ck[((static_cast<size_t>(box) * NK + kz) * N + kx) * N + ky];
+  }
+}
+
+// ------------------------------------------------------------------ dispatchers ----
+template <template <int> class F, typename... A>
+hipError_t dispatch_n(int n, A... args) {
+  switch (n) {
+    case 8: return F<8>::run(args...);
+    case 16: return F<16>::run(args...);
+    case 32: return F<32>::run(args...);
+    case 64: return F<64>::run(args...);
+    case 128: return F<128>::run(args...);
+    case 256: return F<256>::run(args...);
+    case 512: return F<512>::run(args...);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int N> struct FwdZ {
+  static hipError_t run(const unsigned long long* rho, float2* out, const float2* tw,
+                        double scale, int nbox, hipStream_t s) {
+    dim3 grid(N / Shape<N>::FZ_TY, N, nbox);
+    hipLaunchKernelGGL(fwd_z_kernel<N>, grid, dim3(NT), 0, s, rho, out, tw, scale);
+    return hipGetLastError();
+  }
+};
+template <int N> struct FwdY {
+  static hipError_t run(float2* data, const float2* tw, int nbox, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>(static_cast<int64_t>(nbox) * Shape<N>::NK * N /
+                                    Shape<N>::FY_NL));
+    hipLaunchKernelGGL(fwd_y_kernel<N>, grid, dim3(NT), 0, s, data, tw);
+    return hipGetLastError();
+  }
+};
+template <int N> struct FwdX {
+  static hipError_t run(float2* data, const float2* tw, const uint16_t* bins, double* partial,
+                        int nbins, int nbox, hipStream_t s) {
+    dim3 grid(N / Shape<N>::FX_TX, Shape<N>::NK, nbox);
+    hipLaunchKernelGGL(fwd_x_bin_kernel<N>, grid, dim3(NT), nbins * sizeof(double), s, data,
+                       tw, bins, partial, nbins);
+    return hipGetLastError();
+  }
+};
+template <int N> struct InvX {
+  static hipError_t run(const float2* dk, float2* f1, float2* f2, const float2* tw,
+                        const float* rt, int n2max, const float* iw, float cfac,
+                        float kf, int nbox, hipStream_t s) {
+    dim3 grid(N / Shape<N>::IX_TX, Shape<N>::NK, nbox);
+    hipLaunchKernelGGL(inv_x_kernel<N>, grid, dim3(NT), 0, s, dk, f1, f2, tw, rt, n2max, iw,
+                       cfac, kf);
+    return hipGetLastError();
+  }
+};
+template <int N> struct InvY {
+  static hipError_t run(float2* f1, float2* f2, float2* g2, const float2* tw, float kf,
+                        int nbox, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>(static_cast<int64_t>(nbox) * Shape<N>::NK * N /
+                                    Shape<N>::IY_NL));
+    hipLaunchKernelGGL(inv_y_kernel<N>, grid, dim3(NT), 0, s, f1, f2, g2, tw, kf);
+    return hipGetLastError();
+  }
+};
+template <int N> struct InvZ {
+  static hipError_t run(const float2* g1, const float2* g2, const float2* g3, float* out,
+                        const float2* tw, float kf, int nbox, hipStream_t s) {
+    dim3 grid(N / Shape<N>::IZ_TY, N, nbox);
+    hipLaunchKernelGGL(inv_z_kernel<N>, grid, dim3(NT), 0, s, g1, g2, g3, out, tw, kf, nbox);
+    return hipGetLastError();
+  }
+};
+template <int N> struct CopyModes {
+  static hipError_t run(const float2* ck, float2* out, int box, hipStream_t s) {
+    hipLaunchKernelGGL(copy_modes_kernel<N>, dim3(1024), dim3(256), 0, s, ck, out, box);
+    return hipGetLastError();
+  }
+};
+template <int N> struct Partials {
+  static hipError_t run(int* out) {
+    *out = (N / Shape<N>::FX_TX) * Shape<N>::NK;
+    return hipSuccess;
+  }
+};
+
+}  // namespace
+
+hipError_t launch_fwd_z(int n, const unsigned long long* rho, float2* out, const float2* tw,
+                        double scale, int nbox, hipStream_t s) {
+  return dispatch_n<FwdZ>(n, rho, out, tw, scale, nbox, s);
+}
+hipError_t launch_fwd_y(int n, float2* data, const float2* tw, int nbox, hipStream_t s) {
+  return dispatch_n<FwdY>(n, data, tw, nbox, s);
+}
+hipError_t launch_fwd_x_bin(int n, float2* data, const float2* tw, const uint16_t* bin_of_n2,
+                            double* partial, int nbins, int nbox, hipStream_t s) {
+  return dispatch_n<FwdX>(n, data, tw, bin_of_n2, partial, nbins, nbox, s);
+}
+int fwd_x_partials(int n) {
+  int out = 0;
+  if (dispatch_n<Partials>(n, &out) != hipSuccess) return 0;
+  return out;
+}
+hipError_t launch_inv_x(int n, const float2* dk, float2* f1, float2* f2, const float2* tw,
+                        const float* rtable, int n2max, const float* inv_w2,
+                        float cfac, float kf, int nbox, hipStream_t s) {
+  return dispatch_n<InvX>(n, dk, f1, f2, tw, rtable, n2max, inv_w2, cfac, kf, nbox, s);
+}
+hipError_t launch_inv_y(int n, float2* f1, float2* f2, float2* g2, const float2* tw, float kf,
+                        int nbox, hipStream_t s) {
+  return dispatch_n<InvY>(n, f1, f2, g2, tw, kf, nbox, s);
+}
+hipError_t launch_inv_z(int n, const float2* g1, const float2* g2, const float2* g3, float* out,
+                        const float2* tw, float kf, int nbox, hipStream_t s) {
+  return dispatch_n<InvZ>(n, g1, g2, g3, out, tw, kf, nbox, s);
+}
+hipError_t launch_copy_modes(int n, const float2* ck, float2* out, int box, hipStream_t s) {
+  return dispatch_n<CopyModes>(n, ck, out, box, s);
+}
+
+}  // namespace pmnu

@@ -1,0 +1,724 @@
+// Host runtime of the pm_nu library: configuration, bin geometry, the FP64 time grid of
+// the history integral, buffer ownership, stage ordering, timing and graph capture.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pm_nu_internal.hpp"
+
+namespace pmnu {
+
+const char* const kStageNames[ST_COUNT] = {
+    "zero_mesh", "cic_deposit", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x_bin", "nu_response",
+    "rtable", "inv_x_green", "fft_inv_y", "fft_inv_z", "cic_interp", "surrogate"};
+
+namespace {
+thread_local std::string g_err = "no error";
+}
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+void timer_begin(Ctx& c, int stage) {
+  if (!c.timer.enabled || c.capturing) return;
+  Timer& t = c.timer;
+  if (2 * (t.used + 1) > t.pool.size()) {
+    for (int i = 0; i < 2; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      t.pool.push_back(e);
+    }
+  }
+  if (t.stage_of.size() <= t.used) t.stage_of.resize(t.used + 1);
+  t.stage_of[t.used] = stage;
+  (void)hipEventRecord(t.pool[2 * t.used], c.stream);
+}
+
+void timer_end(Ctx& c) {
+  if (!c.timer.enabled || c.capturing) return;
+  Timer& t = c.timer;
+  if (2 * t.used + 1 >= t.pool.size()) return;
+  (void)hipEventRecord(t.pool[2 * t.used + 1], c.stream);
+  ++t.used;
+}
+
+namespace {
+
+// ------------------------------------------------------------- quadrature -----------
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
+struct GaussLegendre {
+  std::vector<double> x, w;
+  explicit GaussLegendre(int n) : x(n), w(n) {
+    for (int i = 0; i < n; ++i) {
+      double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+          const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+        const double dz = p1 / dp;
+        z -= dz;
+        if (std::fabs(dz) < 1e-16) {
+          double q0 = 1.0, q1 = z;
+          for (int k = 2; k <= n; ++k) {
+            const double q2 = ((2.0 * k - 1.0) * z * q1 - (k - 1.0) * q0) / k;
+            q0 = q1;
+            q1 = q2;
+          }
+          const double d = n * (z * q1 - q0) / (z * z - 1.0);
+          x[i] = z;
+          w[i] = 2.0 / ((1.0 - z * z) * d * d);
+          break;
+        }
+      }
+    }
+  }
+};
+
+const GaussLegendre& gl16() {
+  static const GaussLegendre g(16);
+  return g;
+}
+
+double hubble(double a, double om) { return kH0 * std::sqrt(om / (a * a * a) + 1.0 - om); }
+
+// s(a2) - s(a1) = int da / (a^3 H) = int dln a / (a^2 H), over a short interval in ln a.
+double ds_interval(double a1, double a2, double om) {
+  const GaussLegendre& g = gl16();
+  const double u1 = std::log(a1), u2 = std::log(a2);
+  const double hw = 0.5 * (u2 - u1), mid = 0.5 * (u1 + u2);
+  double s = 0.0;
+  for (size_t i = 0; i < g.x.size(); ++i) {
+    const double a = std::exp(mid + hw * g.x[i]);
+    s += g.w[i] / (a * a * hubble(a, om));
+  }
+  return s * hw;
+}
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int validate(const pm_nu_config* c) {
+  if (!c) return set_error(PM_NU_EINVAL, "config is NULL");
+  if (!is_pow2(c->n_mesh) || c->n_mesh < 8 || c->n_mesh > 512)
+    return set_error(PM_NU_EINVAL, "n_mesh must be a power of two in [8, 512] (got %d)",
+                     c->n_mesh);
+  if (c->n_boxes < 1 || c->n_boxes > 65535)
+    return set_error(PM_NU_EINVAL, "n_boxes must be in [1, 65535]");
+  if (c->n_particles < 1) return set_error(PM_NU_EINVAL, "n_particles must be >= 1");
+  if (!(c->box_size > 0.0) || !std::isfinite(c->box_size))
+    return set_error(PM_NU_EINVAL, "box_size must be positive");
+  if (!(c->omega_m > 0.0 && c->omega_m <= 1.0))
+    return set_error(PM_NU_EINVAL, "omega_m must be in (0, 1]");
+  if (!(c->hubble > 0.0)) return set_error(PM_NU_EINVAL, "hubble must be positive");
+  if (c->n_kbins < 1 || c->n_kbins > 1024)
+    return set_error(PM_NU_EINVAL, "n_kbins must be in [1, 1024]");
+  if (c->max_history < 2) return set_error(PM_NU_EINVAL, "max_history must be >= 2");
+  if (c->substeps < 1 || c->substeps > 1024)
+    return set_error(PM_NU_EINVAL, "substeps must be in [1, 1024]");
+  if (c->iterations < 1 || c->iterations > 16)
+    return set_error(PM_NU_EINVAL, "iterations must be in [1, 16]");
+  if (c->response_mode < 0 || c->response_mode > 2)
+    return set_error(PM_NU_EINVAL, "response_mode must be 0, 1 or 2");
+  if (c->n_species < 1) return set_error(PM_NU_EINVAL, "n_species must be >= 1");
+  const double qcap = (static_cast<double>(c->max_history) - 1.0) * c->substeps + 1.0;
+  if (qcap > 1e8) return set_error(PM_NU_EINVAL, "max_history * substeps too large");
+  return PM_NU_OK;
+}
+
+template <typename T>
+int dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+  if (e != hipSuccess)
+    return set_error(PM_NU_ENOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                     hipGetErrorString(e));
+  return PM_NU_OK;
+}
+
+void free_ctx(Ctx* c);
+
+// Bin geometry from the multiplicity of every integer |n|^2 (full sphere of modes).
+void build_bins(Ctx& c) {
+  const int n = c.N, B = c.B;
+  const double r2 = 3.0 * n * n / 4.0;
+  c.edges.assign(B + 1, 0);
+  for (int b = 0; b <= B; ++b)
+    c.edges[b] = static_cast<int64_t>(std::ceil(std::pow(r2, static_cast<double>(b) / B)));
+  c.edges[0] = 1;
+  std::vector<int64_t> mult(c.n2max + 1, 0);
+  const int h = n / 2;
+  for (int i = -h; i < h; ++i)
+    for (int j = -h; j < h; ++j)
+      for (int l = -h; l < h; ++l) ++mult[i * i + j * j + l * l];
+  std::vector<uint16_t> bin(c.n2max + 1, 0);
+  c.counts.assign(B, 0.0);
+  std::vector<double> ksum(B, 0.0);
+  const double kf = 2.0 * kPi / c.cfg.box_size;
+  int b = 0;
+  for (int n2 = 1; n2 <= c.n2max; ++n2) {
+    while (b < B - 1 && n2 >= c.edges[b + 1]) ++b;
+    bin[n2] = static_cast<uint16_t>(b);
+    c.counts[b] += static_cast<double>(mult[n2]);
+    ksum[b] += static_cast<double>(mult[n2]) * kf * std::sqrt(static_cast<double>(n2));
+  }
+  c.kmean.assign(B, 0.0);
+  c.nonempty.clear();
+  for (int k = 0; k < B; ++k) {
+    if (c.counts[k] > 0) {
+      c.kmean[k] = ksum[k] / c.counts[k];
+      c.nonempty.push_back(k);
+    }
+  }
+  hipMemcpy(c.bin_of_n2, bin.data(), bin.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+}
+
+// Node list of one box for a response at a_now: the stored nodes strictly before a_now
+// (a stored node equal to a_now is recomputed) plus a_now itself.
+int nodes_for(const Ctx& c, int box, double a_now, std::vector<double>& nodes, int& n_cur) {
+  const std::vector<double>& ha = c.hist_a[box];
+  if (ha.empty()) return set_error(PM_NU_EHISTORY, "box %d has no stored history", box);
+  size_t m = ha.size();
+  if (std::fabs(ha.back() - a_now) <= 1e-12 * a_now) --m;
+  else if (a_now < ha.back())
+    return set_error(PM_NU_EHISTORY, "a_now=%g precedes the last stored node %g of box %d",
+                     a_now, ha.back(), box);
+  if (m < 1) return set_error(PM_NU_EHISTORY, "box %d: no stored node before a_now", box);
+  if (static_cast<int>(m) >= c.Jcap)
+    return set_error(PM_NU_EHISTORY, "box %d: history full (%d nodes)", box, c.Jcap);
+  nodes.assign(ha.begin(), ha.begin() + m);
+  nodes.push_back(a_now);
+  n_cur = static_cast<int>(m);
+  return PM_NU_OK;
+}
+
+// Time grid of eq. (P-final) for every box at a_now (host FP64, uploaded when changed).
+int prepare_time_grid(Ctx& c, double a_now) {
+  std::vector<std::vector<double>> all_nodes(c.nbox);
+  std::vector<int> ncur(c.nbox);
+  for (int b = 0; b < c.nbox; ++b) {
+    int rc = nodes_for(c, b, a_now, all_nodes[b], ncur[b]);
+    if (rc) return rc;
+  }
+  bool same = (c.tg_a_now == a_now) && (c.tg_version == c.hist_version) && ncur == c.n_cur;
+  if (same) return PM_NU_OK;
+  const double om = c.cfg.omega_m;
+  const double pref = 1.5 * om * kH0 * kH0;
+  const int Q = c.Q;
+  std::vector<double> ds(static_cast<size_t>(c.nbox) * c.qcap, 0.0);
+  std::vector<double> w(static_cast<size_t>(c.nbox) * c.qcap, 0.0);
+  std::vector<RespBox> rb(c.nbox);
+  for (int b = 0; b < c.nbox; ++b) {
+    const std::vector<double>& nd = all_nodes[b];
+    const int n = ncur[b];
+    const int nq = n * Q + 1;
+    std::vector<double> a(nq), tw(nq, 0.0);
+    for (int j = 0; j < n; ++j) {
+      const double u0 = std::log(nd[j]), u1 = std::log(nd[j + 1]);
+      const double h = (u1 - u0) / Q;
+      for (int r = 0; r < Q; ++r) {
+        a[j * Q + r] = (r == 0) ? nd[j] : std::exp(u0 + r * h);
+        tw[j * Q + r] += (r == 0) ? 0.5 * h : h;
+        tw[j * Q + r + 1] += (r == Q - 1) ? 0.5 * h : 0.0;
+      }
+    }
+    a[nq - 1] = nd[n];
+    double* dsb = ds.data() + static_cast<size_t>(b) * c.qcap;
+    double* wb = w.data() + static_cast<size_t>(b) * c.qcap;
+    dsb[nq - 1] = 0.0;
+    for (int q = nq - 2; q >= 0; --q) dsb[q] = dsb[q + 1] + ds_interval(a[q], a[q + 1], om);
+    for (int q = 0; q < nq; ++q) wb[q] = pref * tw[q] / (a[q] * hubble(a[q], om));
+    rb[b].f_nu = c.f_nu[b];
+    rb[b].t_over_m = c.t_over_m[b];
+    rb[b].ds_ic = dsb[0];
+    rb[b].a_i = nd[0];
+    rb[b].nq = nq;
+    rb[b].n_cur = n;
+  }
+  PMNU_HIP(hipStreamSynchronize(c.stream));
+  PMNU_HIP(hipMemcpy(c.tg_ds, ds.data(), ds.size() * sizeof(double), hipMemcpyHostToDevice));
+  PMNU_HIP(hipMemcpy(c.tg_w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
+  PMNU_HIP(hipMemcpy(c.d_resp, rb.data(), rb.size() * sizeof(RespBox), hipMemcpyHostToDevice));
+  c.tg_a_now = a_now;
+  c.tg_version = c.hist_version;
+  c.n_cur = ncur;
+  return PM_NU_OK;
+}
+
+#define TIMED(ctx, stage, launch)                                                      \
+  do {                                                                                 \
+    timer_begin(ctx, stage);                                                           \
+    hipError_t e_ = (launch);                                                          \
+    timer_end(ctx);                                                                    \
+    if (e_ != hipSuccess)                                                              \
+      return set_error(PM_NU_EHIP, "kernel launch (%s) failed: %s", kStageNames[stage], \
+                       hipGetErrorString(e_));                                         \
+  } while (0)
+
+int do_deposit(Ctx& c, const float* pos) {
+  if (!pos) return set_error(PM_NU_EINVAL, "pos is NULL");
+  const int64_t cells = c.M * c.nbox;
+  TIMED(c, ST_ZERO, launch_fill_zero(c.rho, cells * 8, c.stream));
+  TIMED(c, ST_DEPOSIT, launch_deposit(pos, c.rho, c.Np, c.nbox, c.N, c.N / c.cfg.box_size,
+                                      c.d_flags, c.tune.deposit_block, c.tune.deposit_ppt,
+                                      c.stream));
+  const double scale = static_cast<double>(c.M) / static_cast<double>(c.Np) / kFixScale;
+  TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, c.rho, c.ck[0], c.tw, scale, c.nbox, c.stream));
+  TIMED(c, ST_FFT_Y, launch_fwd_y(c.N, c.ck[0], c.tw, c.nbox, c.stream));
+  TIMED(c, ST_FFT_X_BIN, launch_fwd_x_bin(c.N, c.ck[0], c.tw, c.bin_of_n2, c.bin_partial,
+                                          c.B, c.nbox, c.stream));
+  c.stage = 1;
+  c.pos_dep = pos;
+  return PM_NU_OK;
+}
+
+int do_response(Ctx& c, double a_now) {
+  if (c.stage < 1) return set_error(PM_NU_ESTATE, "pm_nu_response needs pm_nu_deposit first");
+  if (!(a_now > 0.0) || !std::isfinite(a_now)) return set_error(PM_NU_EINVAL, "bad a_now");
+  if (!c.capturing) {
+    int rc = prepare_time_grid(c, a_now);
+    if (rc) return rc;
+  } else if (c.tg_a_now != a_now) {
+    return set_error(PM_NU_ESTATE, "time grid not prepared before capture");
+  }
+  const double norm = std::pow(c.cfg.box_size, 3) / (static_cast<double>(c.M) * c.M);
+  TIMED(c, ST_RESPONSE,
+        launch_response(c.d_resp, c.bin_partial, c.n_partial, c.d_counts, c.d_kmean,
+                        c.hist_pm, c.hist_pnu, c.ic_pnu, c.ic_theta, c.tg_ds, c.tg_w, c.B,
+                        c.Jcap, c.qcap, c.Q, c.cfg.iterations, norm, c.nbox, c.pcdm, c.pnu,
+                        c.ratio, c.stream));
+  TIMED(c, ST_RTABLE,
+        launch_rtable(c.ratio, c.d_kmean, c.d_nonempty, static_cast<int>(c.nonempty.size()),
+                      c.d_resp, c.B, c.n2max, 2.0 * kPi / c.cfg.box_size, c.nbox, c.rtable,
+                      c.stream));
+  // commit the node on the host side (the kernel wrote row n_cur)
+  for (int b = 0; b < c.nbox; ++b) {
+    std::vector<double>& ha = c.hist_a[b];
+    if (static_cast<int>(ha.size()) == c.n_cur[b]) {
+      ha.push_back(a_now);
+    } else {
+      ha.resize(c.n_cur[b] + 1);
+      ha.back() = a_now;
+    }
+  }
+  c.stage = 2;
+  c.a_resp = a_now;
+  return PM_NU_OK;
+}
+
+int do_force(Ctx& c, const float* pos, float* acc, double a_now) {
+  if (c.stage != 2) return set_error(PM_NU_ESTATE, "pm_nu_force needs pm_nu_response first");
+  if (a_now != c.a_resp)
+    return set_error(PM_NU_ESTATE, "pm_nu_force a_now differs from the response's");
+  if (!pos || !acc) return set_error(PM_NU_EINVAL, "pos/acc is NULL");
+  const float kf = static_cast<float>(2.0 * kPi / c.cfg.box_size);
+  const double cgreen = 1.5 * c.cfg.omega_m * kH0 * kH0 / a_now / static_cast<double>(c.M);
+  TIMED(c, ST_INV_X_GREEN,
+        launch_inv_x(c.N, c.ck[0], c.ck[1], c.ck[2], c.tw, c.rtable, c.n2max, c.inv_w2,
+                     static_cast<float>(cgreen), kf, c.nbox, c.stream));
+  TIMED(c, ST_INV_Y, launch_inv_y(c.N, c.ck[1], c.ck[2], c.ck[0], c.tw, kf, c.nbox, c.stream));
+  TIMED(c, ST_INV_Z, launch_inv_z(c.N, c.ck[1], c.ck[0], c.ck[2], c.force, c.tw, kf, c.nbox,
+                                  c.stream));
+  TIMED(c, ST_INTERP, launch_interp(pos, c.force, acc, c.Np, c.nbox, c.N,
+                                    c.N / c.cfg.box_size, c.tune.interp_block,
+                                    c.tune.interp_ppt, c.stream));
+  c.stage = 0;
+  return PM_NU_OK;
+}
+
+void free_ctx(Ctx* c) {
+  if (!c) return;
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  for (hipEvent_t e : c->timer.pool) hipEventDestroy(e);
+  void* bufs[] = {c->rho, c->ck[0], c->ck[1], c->ck[2], c->force, c->bin_partial,
+                  c->bin_of_n2, c->d_counts, c->d_kmean, c->d_nonempty, c->pcdm, c->pnu,
+                  c->ratio, c->hist_pm, c->hist_pnu, c->ic_pnu, c->ic_theta, c->tg_ds,
+                  c->tg_w, c->d_resp, c->rtable, c->tw, c->inv_w2, c->d_flags};
+  for (void* p : bufs)
+    if (p) hipFree(p);
+  delete c;
+}
+
+}  // namespace
+
+// Surrogate hooks (surrogate.cpp)
+void surrogate_free(Ctx& c);
+int surrogate_response(Ctx& c, double a_now);
+
+}  // namespace pmnu
+
+using namespace pmnu;
+
+extern "C" {
+
+void pm_nu_default_config(pm_nu_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->n_mesh = 32;
+  cfg->n_boxes = 1;
+  cfg->n_particles = 32768;
+  cfg->box_size = 128.0;
+  cfg->omega_m = 0.3;
+  cfg->hubble = 0.7;
+  cfg->n_kbins = 32;
+  cfg->max_history = 256;
+  cfg->substeps = 8;
+  cfg->iterations = 1;
+  cfg->deconvolve = 1;
+  cfg->response_mode = 0;
+  cfg->n_species = 3;
+  cfg->stream = nullptr;
+}
+
+const char* pm_nu_last_error(void) { return g_err.c_str(); }
+
+int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** out) {
+  if (!out) return set_error(PM_NU_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!m_nu_total) return set_error(PM_NU_EINVAL, "m_nu_total is NULL");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return set_error(PM_NU_ENODEV, "no HIP device");
+  Ctx* c = new (std::nothrow) Ctx();
+  if (!c) return set_error(PM_NU_ENOMEM, "host allocation failed");
+  c->cfg = *cfg;
+  hipGetDevice(&c->device);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess &&
+      std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    delete c;
+    return set_error(PM_NU_ENODEV, "device %d is %s, this library is built for gfx950",
+                     c->device, prop.gcnArchName);
+  }
+  c->N = cfg->n_mesh;
+  c->NK = c->N / 2 + 1;
+  c->nbox = cfg->n_boxes;
+  c->B = cfg->n_kbins;
+  c->Jcap = cfg->max_history;
+  c->Q = cfg->substeps;
+  c->Np = cfg->n_particles;
+  c->M = static_cast<int64_t>(c->N) * c->N * c->N;
+  c->MH = static_cast<int64_t>(c->NK) * c->N * c->N;
+  c->n2max = 3 * c->N * c->N / 4;
+  c->qcap = (c->Jcap - 1) * c->Q + 1;
+  c->n_partial = fwd_x_partials(c->N);
+  c->stream = static_cast<hipStream_t>(cfg->stream);
+  c->m_nu.assign(m_nu_total, m_nu_total + c->nbox);
+  for (int b = 0; b < c->nbox; ++b) {
+    const double m = c->m_nu[b];
+    if (!(m >= 0.0) || !std::isfinite(m)) {
+      delete c;
+      return set_error(PM_NU_EINVAL, "m_nu_total[%d] must be >= 0", b);
+    }
+    c->f_nu.push_back(m / (93.14 * cfg->omega_m * cfg->hubble * cfg->hubble));
+    const double m1 = m / cfg->n_species;
+    c->t_over_m.push_back(m1 > 0 ? kTnu0 / m1 : 0.0);
+  }
+  const size_t nb = c->nbox, B = c->B;
+#define ALLOC(ptr, count)                 \
+  do {                                    \
+    int rc_ = dalloc(&(ptr), (count));    \
+    if (rc_) {                            \
+      free_ctx(c);                        \
+      return rc_;                         \
+    }                                     \
+  } while (0)
+  ALLOC(c->rho, nb * c->M);
+  for (int i = 0; i < 3; ++i) ALLOC(c->ck[i], nb * c->MH);
+  ALLOC(c->force, 3 * nb * c->M);
+  ALLOC(c->bin_partial, nb * c->n_partial * B);
+  ALLOC(c->bin_of_n2, static_cast<size_t>(c->n2max) + 1);
+  ALLOC(c->d_counts, B);
+  ALLOC(c->d_kmean, B);
+  ALLOC(c->d_nonempty, B);
+  ALLOC(c->pcdm, nb * B);
+  ALLOC(c->pnu, nb * B);
+  ALLOC(c->ratio, nb * B);
+  ALLOC(c->hist_pm, nb * c->Jcap * B);
+  ALLOC(c->hist_pnu, nb * c->Jcap * B);
+  ALLOC(c->ic_pnu, nb * B);
+  ALLOC(c->ic_theta, nb * B);
+  ALLOC(c->tg_ds, nb * c->qcap);
+  ALLOC(c->tg_w, nb * c->qcap);
+  ALLOC(c->d_resp, nb);
+  ALLOC(c->rtable, nb * (static_cast<size_t>(c->n2max) + 1));
+  ALLOC(c->tw, static_cast<size_t>(c->N));
+  ALLOC(c->inv_w2, static_cast<size_t>(c->N));
+  ALLOC(c->d_flags, 1);
+#undef ALLOC
+  build_bins(*c);
+  if (c->nonempty.empty()) {
+    free_ctx(c);
+    return set_error(PM_NU_EINVAL, "all k-bins are empty");
+  }
+  std::vector<float2> tw(c->N);
+  std::vector<float> iw(c->N);
+  for (int m = 0; m < c->N; ++m) {
+    const double ph = -2.0 * kPi * m / c->N;
+    tw[m] = make_float2(static_cast<float>(std::cos(ph)), static_cast<float>(std::sin(ph)));
+    const int nm = m < c->N / 2 ? m : m - c->N;
+    const double t = kPi * nm / c->N;
+    const double sinc = (nm == 0) ? 1.0 : std::sin(t) / t;
+    iw[m] = cfg->deconvolve ? static_cast<float>(1.0 / std::pow(sinc, 4)) : 1.0f;
+  }
+  std::vector<int> ne(c->nonempty);
+  ne.resize(B, 0);
+  hipError_t e = hipSuccess;
+  e = e ? e : hipMemcpy(c->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(c->inv_w2, iw.data(), iw.size() * sizeof(float), hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(c->d_counts, c->counts.data(), B * sizeof(double), hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(c->d_kmean, c->kmean.data(), B * sizeof(double), hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(c->d_nonempty, ne.data(), B * sizeof(int), hipMemcpyHostToDevice);
+  e = e ? e : hipMemset(c->d_flags, 0, sizeof(int));
+  e = e ? e : hipMemset(c->hist_pm, 0, nb * c->Jcap * B * sizeof(double));
+  e = e ? e : hipMemset(c->hist_pnu, 0, nb * c->Jcap * B * sizeof(double));
+  e = e ? e : hipMemset(c->ic_pnu, 0, nb * B * sizeof(double));
+  e = e ? e : hipMemset(c->ic_theta, 0, nb * B * sizeof(double));
+  e = e ? e : hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_ctx(c);
+    return set_error(PM_NU_EHIP, "init upload failed: %s", hipGetErrorString(e));
+  }
+  c->hist_a.assign(c->nbox, {});
+  c->has_ic.assign(c->nbox, 0);
+  c->n_cur.assign(c->nbox, -1);
+  *out = reinterpret_cast<pm_nu_ctx*>(c);
+  return PM_NU_OK;
+}
+
+void pm_nu_destroy(pm_nu_ctx* ctx) {
+  Ctx* c = reinterpret_cast<Ctx*>(ctx);
+  if (!c) return;
+  hipDeviceSynchronize();
+  surrogate_free(*c);
+  free_ctx(c);
+}
+
+#define GET_CTX(ctx)                                                    \
+  Ctx* c = reinterpret_cast<Ctx*>(ctx);                                 \
+  if (!c) return set_error(PM_NU_EINVAL, "ctx is NULL")
+
+int pm_nu_get_bins(pm_nu_ctx* ctx, int64_t* edge_n2, double* mode_count, double* k_mean) {
+  GET_CTX(ctx);
+  if (edge_n2) std::copy(c->edges.begin(), c->edges.end(), edge_n2);
+  if (mode_count) std::copy(c->counts.begin(), c->counts.end(), mode_count);
+  if (k_mean) std::copy(c->kmean.begin(), c->kmean.end(), k_mean);
+  return PM_NU_OK;
+}
+
+int pm_nu_set_history(pm_nu_ctx* ctx, int box, int n_nodes, const double* a,
+                      const double* pm_half, const double* pnu_half,
+                      const double* pnu_half_init, const double* theta_over_delta_init) {
+  GET_CTX(ctx);
+  if (box < 0 || box >= c->nbox) return set_error(PM_NU_EINVAL, "box %d out of range", box);
+  if (n_nodes < 1 || n_nodes >= c->Jcap)
+    return set_error(PM_NU_EHISTORY, "n_nodes must be in [1, max_history-1] (got %d)", n_nodes);
+  if (!a || !pm_half || !pnu_half || !pnu_half_init || !theta_over_delta_init)
+    return set_error(PM_NU_EINVAL, "history array is NULL");
+  for (int j = 0; j < n_nodes; ++j) {
+    if (!(a[j] > 0.0) || !std::isfinite(a[j]) || (j > 0 && !(a[j] > a[j - 1])))
+      return set_error(PM_NU_EHISTORY, "history scale factors must be positive and increasing");
+  }
+  const size_t B = c->B;
+  PMNU_HIP(hipStreamSynchronize(c->stream));
+  const size_t off = static_cast<size_t>(box) * c->Jcap * B;
+  PMNU_HIP(hipMemcpy(c->hist_pm + off, pm_half, n_nodes * B * sizeof(double),
+                     hipMemcpyHostToDevice));
+  PMNU_HIP(hipMemcpy(c->hist_pnu + off, pnu_half, n_nodes * B * sizeof(double),
+                     hipMemcpyHostToDevice));
+  PMNU_HIP(hipMemcpy(c->ic_pnu + box * B, pnu_half_init, B * sizeof(double),
+                     hipMemcpyHostToDevice));
+  PMNU_HIP(hipMemcpy(c->ic_theta + box * B, theta_over_delta_init, B * sizeof(double),
+                     hipMemcpyHostToDevice));
+  c->hist_a[box].assign(a, a + n_nodes);
+  c->has_ic[box] = 1;
+  ++c->hist_version;
+  return PM_NU_OK;
+}
+
+int pm_nu_get_history(pm_nu_ctx* ctx, int box, int* n_nodes, double* a, double* pm_half,
+                      double* pnu_half) {
+  GET_CTX(ctx);
+  if (box < 0 || box >= c->nbox) return set_error(PM_NU_EINVAL, "box %d out of range", box);
+  const int n = static_cast<int>(c->hist_a[box].size());
+  if (n_nodes) *n_nodes = n;
+  if (a) std::copy(c->hist_a[box].begin(), c->hist_a[box].end(), a);
+  PMNU_HIP(hipStreamSynchronize(c->stream));
+  const size_t B = c->B, off = static_cast<size_t>(box) * c->Jcap * B;
+  if (pm_half && n)
+    PMNU_HIP(hipMemcpy(pm_half, c->hist_pm + off, n * B * sizeof(double), hipMemcpyDeviceToHost));
+  if (pnu_half && n)
+    PMNU_HIP(hipMemcpy(pnu_half, c->hist_pnu + off, n * B * sizeof(double),
+                       hipMemcpyDeviceToHost));
+  return PM_NU_OK;
+}
+
+int pm_nu_deposit(pm_nu_ctx* ctx, const float* pos) {
+  GET_CTX(ctx);
+  return do_deposit(*c, pos);
+}
+
+int pm_nu_response(pm_nu_ctx* ctx, double a_now) {
+  GET_CTX(ctx);
+  if (c->cfg.response_mode != 0) return surrogate_response(*c, a_now);
+  return do_response(*c, a_now);
+}
+
+int pm_nu_force(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now) {
+  GET_CTX(ctx);
+  if (pos != c->pos_dep) return set_error(PM_NU_EINVAL, "pos differs from the deposit's array");
+  return do_force(*c, pos, acc, a_now);
+}
+
+int pm_nu_step(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now) {
+  int rc = pm_nu_deposit(ctx, pos);
+  if (rc) return rc;
+  rc = pm_nu_response(ctx, a_now);
+  if (rc) return rc;
+  return pm_nu_force(ctx, pos, acc, a_now);
+}
+
+int pm_nu_get_spectrum(pm_nu_ctx* ctx, int box, double* p_cdm, double* pnu_half,
+                       double* ratio) {
+  GET_CTX(ctx);
+  if (box < 0 || box >= c->nbox) return set_error(PM_NU_EINVAL, "box %d out of range", box);
+  PMNU_HIP(hipStreamSynchronize(c->stream));
+  const size_t B = c->B;
+  if (p_cdm) PMNU_HIP(hipMemcpy(p_cdm, c->pcdm + box * B, B * sizeof(double), hipMemcpyDeviceToHost));
+  if (pnu_half)
+    PMNU_HIP(hipMemcpy(pnu_half, c->pnu + box * B, B * sizeof(double), hipMemcpyDeviceToHost));
+  if (ratio) PMNU_HIP(hipMemcpy(ratio, c->ratio + box * B, B * sizeof(double), hipMemcpyDeviceToHost));
+  int flags = 0;
+  PMNU_HIP(hipMemcpy(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost));
+  if (flags & 1) {
+    PMNU_HIP(hipMemset(c->d_flags, 0, sizeof(int)));
+    return set_error(PM_NU_ENONFINITE, "a non-finite particle position was skipped");
+  }
+  return PM_NU_OK;
+}
+
+int pm_nu_copy_density(pm_nu_ctx* ctx, int box, float* out) {
+  GET_CTX(ctx);
+  if (box < 0 || box >= c->nbox || !out) return set_error(PM_NU_EINVAL, "bad box/out");
+  hipError_t e = launch_fixed_to_float(c->rho + box * c->M, out, c->M, c->stream);
+  if (e != hipSuccess) return set_error(PM_NU_EHIP, "copy_density: %s", hipGetErrorString(e));
+  return PM_NU_OK;
+}
+
+int pm_nu_copy_modes(pm_nu_ctx* ctx, int box, float* out) {
+  GET_CTX(ctx);
+  if (box < 0 || box >= c->nbox || !out) return set_error(PM_NU_EINVAL, "bad box/out");
+  if (c->stage < 1) return set_error(PM_NU_ESTATE, "modes are valid after pm_nu_deposit");
+  hipError_t e = launch_copy_modes(c->N, c->ck[0], reinterpret_cast<float2*>(out), box, c->stream);
+  if (e != hipSuccess) return set_error(PM_NU_EHIP, "copy_modes: %s", hipGetErrorString(e));
+  return PM_NU_OK;
+}
+
+int pm_nu_copy_force_grid(pm_nu_ctx* ctx, int box, int axis, float* out) {
+  GET_CTX(ctx);
+  if (box < 0 || box >= c->nbox || axis < 0 || axis > 2 || !out)
+    return set_error(PM_NU_EINVAL, "bad box/axis/out");
+  PMNU_HIP(hipMemcpyAsync(out, c->force + (static_cast<size_t>(axis) * c->nbox + box) * c->M,
+                          c->M * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+  return PM_NU_OK;
+}
+
+int pm_nu_set_timing(pm_nu_ctx* ctx, int enable) {
+  GET_CTX(ctx);
+  c->timer.enabled = enable != 0;
+  return PM_NU_OK;
+}
+
+int pm_nu_read_timing(pm_nu_ctx* ctx, int* n_stages, const char** names, double* total_ms,
+                      int64_t* launches) {
+  GET_CTX(ctx);
+  if (!n_stages) return set_error(PM_NU_EINVAL, "n_stages is NULL");
+  Timer& t = c->timer;
+  std::vector<double> ms(ST_COUNT, 0.0);
+  std::vector<int64_t> cnt(ST_COUNT, 0);
+  if (t.used > 0) {
+    PMNU_HIP(hipEventSynchronize(t.pool[2 * t.used - 1]));
+    for (size_t i = 0; i < t.used; ++i) {
+      float v = 0.f;
+      PMNU_HIP(hipEventElapsedTime(&v, t.pool[2 * i], t.pool[2 * i + 1]));
+      ms[t.stage_of[i]] += v;
+      cnt[t.stage_of[i]] += 1;
+    }
+  }
+  t.used = 0;
+  const int cap = *n_stages;
+  const int n = std::min<int>(cap, ST_COUNT);
+  for (int i = 0; i < n; ++i) {
+    if (names) names[i] = kStageNames[i];
+    if (total_ms) total_ms[i] = ms[i];
+    if (launches) launches[i] = cnt[i];
+  }
+  *n_stages = n;
+  return PM_NU_OK;
+}
+
+int pm_nu_graph_capture(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now) {
+  GET_CTX(ctx);
+  if (!c->stream) return set_error(PM_NU_EINVAL, "graph capture needs a non-null stream");
+  if (c->cfg.response_mode == 2)
+    return set_error(PM_NU_EINVAL, "the surrogate check mode cannot be captured");
+  int rc = prepare_time_grid(*c, a_now);
+  if (rc) return rc;
+  // run one step eagerly so that the node a_now exists and later replays recompute it
+  rc = pm_nu_step(ctx, pos, acc, a_now);
+  if (rc) return rc;
+  rc = prepare_time_grid(*c, a_now);
+  if (rc) return rc;
+  PMNU_HIP(hipStreamSynchronize(c->stream));
+  if (c->graph_exec) {
+    hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+  }
+  if (c->graph) {
+    hipGraphDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  PMNU_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  c->capturing = true;
+  rc = pm_nu_step(ctx, pos, acc, a_now);
+  c->capturing = false;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return set_error(PM_NU_EHIP, "end capture: %s", hipGetErrorString(e));
+  c->graph = g;
+  PMNU_HIP(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+  return PM_NU_OK;
+}
+
+int pm_nu_graph_launch(pm_nu_ctx* ctx) {
+  GET_CTX(ctx);
+  if (!c->graph_exec) return set_error(PM_NU_ESTATE, "no captured graph");
+  PMNU_HIP(hipGraphLaunch(c->graph_exec, c->stream));
+  return PM_NU_OK;
+}
+
+}  // extern "C"

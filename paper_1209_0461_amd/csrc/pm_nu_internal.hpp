@@ -1,0 +1,164 @@
+// Internal interfaces of the pm_nu library: the context and the host-side launchers of
+// every kernel. Only the C ABI in include/pm_nu.h is exported.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pm_nu.h"
+
+namespace pmnu {
+
+constexpr double kC_KMS = 299792.458;
+constexpr double kH0 = 100.0 / kC_KMS;                 // h/Mpc, c = 1
+constexpr double kTnu0 = 1.95 * 8.617333262e-5;         // eV (1.95 K)
+constexpr double kPi = 3.14159265358979323846;
+
+// Per-box constants of the response kernel (device copy, one per box).
+struct RespBox {
+  double f_nu;       // Omega_nu / Omega_M
+  double t_over_m;   // T_nu0 / m_single
+  double ds_ic;      // s(a_now) - s(a_i)
+  double a_i;        // scale factor of node 0
+  int nq;            // sub-nodes of the quadrature (current step included)
+  int n_cur;         // history row of the current step
+  int pad0, pad1;
+};
+
+// Launch shapes chosen by the autotuner (defaults are safe for every N).
+struct Tuning {
+  int deposit_block = 256;
+  int deposit_ppt = 1;       // particles per thread in the deposit
+  int interp_block = 256;
+  int interp_ppt = 1;
+};
+
+struct Timer {
+  bool enabled = false;
+  std::vector<hipEvent_t> pool;   // events recorded since the last read
+  std::vector<int> stage_of;      // stage of each event pair
+  size_t used = 0;                // pairs in use
+};
+
+enum Stage {
+  ST_ZERO = 0, ST_DEPOSIT, ST_FFT_Z, ST_FFT_Y, ST_FFT_X_BIN, ST_RESPONSE, ST_RTABLE,
+  ST_INV_X_GREEN, ST_INV_Y, ST_INV_Z, ST_INTERP, ST_SURROGATE, ST_COUNT
+};
+extern const char* const kStageNames[ST_COUNT];
+
+struct Surrogate;  // defined in surrogate.cpp
+
+struct Ctx {
+  pm_nu_config cfg{};
+  int N = 0, NK = 0, nbox = 0, B = 0, Jcap = 0, Q = 0;
+  int64_t Np = 0, M = 0, MH = 0;   // particles per box, N^3, (N/2+1) N^2
+  int n2max = 0;                   // 3 N^2 / 4
+  int qcap = 0;                    // sub-node capacity per box
+  int n_partial = 0;               // per-box partial bin sums
+  hipStream_t stream = nullptr;
+  int device = 0;
+
+  std::vector<double> m_nu, f_nu, t_over_m;
+  std::vector<int64_t> edges;      // [B+1]
+  std::vector<double> counts, kmean;
+  std::vector<int> nonempty;       // bins with counts > 0
+
+  // device buffers
+  unsigned long long* rho = nullptr;   // [nbox][M] deposit, fixed point (unit 2^-40)
+  float2* ck[3] = {nullptr, nullptr, nullptr};   // [nbox][NK][N][N]
+  float* force = nullptr;          // [3][nbox][M]
+  double* bin_partial = nullptr;   // [nbox][n_partial][B]
+  uint16_t* bin_of_n2 = nullptr;   // [n2max+1]
+  double* d_counts = nullptr;      // [B]
+  double* d_kmean = nullptr;       // [B]
+  int* d_nonempty = nullptr;       // [B]
+  double* pcdm = nullptr;          // [nbox][B]
+  double* pnu = nullptr;           // [nbox][B]
+  double* ratio = nullptr;         // [nbox][B]
+  double* hist_pm = nullptr;       // [nbox][Jcap][B]
+  double* hist_pnu = nullptr;      // [nbox][Jcap][B]
+  double* ic_pnu = nullptr;        // [nbox][B]
+  double* ic_theta = nullptr;      // [nbox][B]
+  double* tg_ds = nullptr;         // [nbox][qcap]
+  double* tg_w = nullptr;          // [nbox][qcap]
+  RespBox* d_resp = nullptr;       // [nbox]
+  float* rtable = nullptr;         // [nbox][n2max+1]
+  float2* tw = nullptr;            // [N] exp(-2 pi i m/N)
+  float* inv_w2 = nullptr;         // [N] 1/sinc^4(pi n/N) per axis index (or 1)
+  int* d_flags = nullptr;          // [1] bit 0: non-finite position seen
+
+  // host state
+  std::vector<std::vector<double>> hist_a;   // committed node scale factors per box
+  std::vector<int> has_ic;
+  int stage = 0;                   // 0: idle, 1: deposited, 2: responded
+  double a_resp = 0.0;
+  const float* pos_dep = nullptr;
+  // time-grid cache: valid for (a_now, history version)
+  double tg_a_now = -1.0;
+  int64_t hist_version = 0, tg_version = -1;
+  std::vector<int> n_cur;          // row of the current step per box (valid after prepare)
+
+  Tuning tune;
+  Timer timer;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool capturing = false;
+
+  Surrogate* sur = nullptr;
+};
+
+// ---- error helpers (host.cpp) -------------------------------------------------------
+int set_error(int code, const char* fmt, ...);
+#define PMNU_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return ::pmnu::set_error(PM_NU_EHIP, "%s failed: %s (%s:%d)", #call,              \
+                               hipGetErrorString(e_), __FILE__, __LINE__);              \
+  } while (0)
+
+// Event-bracketed launch helpers (host.cpp)
+void timer_begin(Ctx& c, int stage);
+void timer_end(Ctx& c);
+
+// ---- kernel launchers (each returns hipGetLastError() of its launch) -----------------
+// grid_kernels.hip
+constexpr double kFixScale = 1099511627776.0;   // 2^40: fixed-point unit of the deposit
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
+hipError_t launch_fixed_to_float(const unsigned long long* src, float* dst, int64_t n,
+                                 hipStream_t s);
+hipError_t launch_deposit(const float* pos, unsigned long long* rho, int64_t np, int nbox, int N,
+                          double inv_cell, int* flags, int block, int ppt, hipStream_t s);
+hipError_t launch_interp(const float* pos, const float* force, float* acc, int64_t np,
+                         int nbox, int N, double inv_cell, int block, int ppt,
+                         hipStream_t s);
+// fft_kernels.hip
+hipError_t launch_fwd_z(int N, const unsigned long long* rho, float2* out, const float2* tw,
+                        double scale, int nbox, hipStream_t s);
+hipError_t launch_fwd_y(int N, float2* data, const float2* tw, int nbox, hipStream_t s);
+hipError_t launch_fwd_x_bin(int N, float2* data, const float2* tw, const uint16_t* bin_of_n2,
+                            double* partial, int B, int nbox, hipStream_t s);
+int fwd_x_partials(int N);   // partial bin sums per box written by launch_fwd_x_bin
+hipError_t launch_inv_x(int N, const float2* dk, float2* f1, float2* f2, const float2* tw,
+                        const float* rtable, int n2max, const float* inv_w2,
+                        float cfac, float kf, int nbox, hipStream_t s);
+hipError_t launch_inv_y(int N, float2* f1, float2* f2, float2* g2, const float2* tw, float kf,
+                        int nbox, hipStream_t s);
+hipError_t launch_inv_z(int N, const float2* g1, const float2* g2, const float2* g3,
+                        float* out, const float2* tw, float kf, int nbox, hipStream_t s);
+hipError_t launch_copy_modes(int N, const float2* ck, float2* out, int box, hipStream_t s);
+// response_kernels.hip
+hipError_t launch_response(const RespBox* boxes, const double* partial, int n_partial,
+                           const double* counts, const double* kmean, const double* hist_pm,
+                           const double* hist_pnu, const double* ic_pnu,
+                           const double* ic_theta, const double* tg_ds, const double* tg_w,
+                           int B, int Jcap, int qcap, int Q, int iterations, double norm,
+                           int nbox, double* pcdm, double* pnu, double* ratio,
+                           hipStream_t s);
+hipError_t launch_rtable(const double* ratio, const double* kmean, const int* nonempty,
+                         int n_nonempty, const RespBox* boxes, int B, int n2max, double kf,
+                         int nbox, float* rtable, hipStream_t s);
+
+}  // namespace pmnu

@@ -1,0 +1,190 @@
+// Neutrino response of the step, FP64 (gfx950).
+//
+// response_kernel: one workgroup per (bin b, box). It
+//   1. sums the per-workgroup partial mode sums of the forward FFT for bin b and forms
+//      P_cdm(k_b) = (L^3/N^6) sum w |delta_k|^2 / C_b;
+//   2. evaluates eq. (P-final) for P_nu^{1/2}(k_b, a_now):
+//        I(x_i) P_nu,i^{1/2} {1 - (s - s_i) a_i [theta/delta]_i}
+//        + sum_q W_q I(k_b ds_q T/m) ds_q A_q
+//      where ds_q = s(a_now) - s(a_q), W_q = (3/2) Omega_M H0^2 * (trapezoid weight in
+//      ln a) / (a_q H(a_q)) and A_q is the stored P_M^{1/2}, linear in ln a between the
+//      two bracketing nodes (Q sub-nodes per interval). The current node uses
+//      (1 - f_nu) P_cdm^{1/2} + f_nu P_nu^{1/2}(previous node) on the first iteration
+//      and the previous iteration's P_nu^{1/2} after that;
+//   3. writes P_nu^{1/2}, R = P_nu^{1/2}/P_cdm^{1/2}, and the new history row.
+// Lanes stride over the sub-nodes; sums are reduced across the wave and the workgroup
+// in FP64 in a fixed order.
+//
+// I(x) is the rational fit of the paper's Appendix C, eq. (fit).
+//
+// rtable_kernel: T(n^2) = (1 - f_nu) + f_nu R(|k|) for every integer n^2 in [0, 3N^2/4]
+// with R linear in ln k between the means of the non-empty bins, held at the end values.
+#include "pm_nu_internal.hpp"
+
+namespace pmnu {
+namespace {
+
+constexpr int RT = 256;
+
+__device__ __forceinline__ double i_fit(double x) {
+  const double x2 = x * x, x4 = x2 * x2;
+  const double num = 1.0 + 0.0168 * x2 + 0.0407 * x4;
+  const double den = 1.0 + 2.1734 * x2 + 1.6787 * pow(x, 4.1811) + 0.1467 * x4 * x4;
+  return num / den;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the workgroup (RT threads); every thread gets the result.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < RT / 64; ++w) s += red[w];
+  return s;
+}
+
+__global__ __launch_bounds__(RT) void response_kernel(
+    const RespBox* __restrict__ boxes, const double* __restrict__ partial, int n_partial,
+    const double* __restrict__ counts, const double* __restrict__ kmean,
+    double* __restrict__ hist_pm, double* __restrict__ hist_pnu,
+    const double* __restrict__ ic_pnu, const double* __restrict__ ic_theta,
+    const double* __restrict__ tg_ds, const double* __restrict__ tg_w, int nbins, int jcap,
+    int qcap, int q_sub, int iterations, double norm, double* __restrict__ pcdm_out,
+    double* __restrict__ pnu_out, double* __restrict__ ratio_out) {
+  __shared__ double red[RT / 64];
+  const int b = blockIdx.x, box = blockIdx.y;
+  const RespBox bx = boxes[box];
+  const size_t ob = static_cast<size_t>(box) * nbins + b;
+
+  // 1. binned CDM power
+  double s = 0.0;
+  const double* pp = partial + static_cast<size_t>(box) * n_partial * nbins + b;
+  for (int i = threadIdx.x; i < n_partial; i += RT) s += pp[static_cast<size_t>(i) * nbins];
+  s = block_sum(s, red);
+  const double cb = counts[b];
+  double* hpm = hist_pm + static_cast<size_t>(box) * jcap * nbins;
+  double* hpn = hist_pnu + static_cast<size_t>(box) * jcap * nbins;
+  if (!(cb > 0.0)) {
+    if (threadIdx.x == 0) {
+      pcdm_out[ob] = 0.0;
+      pnu_out[ob] = 0.0;
+      ratio_out[ob] = 0.0;
+      hpm[static_cast<size_t>(bx.n_cur) * nbins + b] = 0.0;
+      hpn[static_cast<size_t>(bx.n_cur) * nbins + b] = 0.0;
+    }
+    return;
+  }
+  const double pcdm = norm * s / cb;
+  const double pcdm_half = sqrt(pcdm);
+  const double k = kmean[b];
+  const double kt = k * bx.t_over_m;
+
+  // 2. history integral; the kernel factor does not depend on the iteration
+  const double* ds = tg_ds + static_cast<size_t>(box) * qcap;
+  const double* w = tg_w + static_cast<size_t>(box) * qcap;
+  const double inv_q = 1.0 / q_sub;
+  double pnu_guess = hpn[static_cast<size_t>(bx.n_cur - 1) * nbins + b];
+  double pnu = 0.0;
+  const double ic = bx.t_over_m <= 0.0 ? 0.0 : i_fit(kt * bx.ds_ic) * ic_pnu[ob] *
+                    (1.0 - bx.ds_ic * bx.a_i * ic_theta[ob]);
+  // without massive neutrinos (t_over_m = 0, f_nu = 0) the neutrino term drops out
+  for (int it = 0; it < (bx.t_over_m > 0.0 ? iterations : 0); ++it) {
+    const double a_cur = (1.0 - bx.f_nu) * pcdm_half + bx.f_nu * pnu_guess;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < bx.nq; q += RT) {
+      const double d = ds[q];
+      const int j = q / q_sub, r = q - j * q_sub;
+      const double t = r * inv_q;
+      const double aj = (j < bx.n_cur) ? hpm[static_cast<size_t>(j) * nbins + b] : a_cur;
+      double amp = aj;
+      if (r != 0) {
+        const double aj1 =
+            (j + 1 < bx.n_cur) ? hpm[static_cast<size_t>(j + 1) * nbins + b] : a_cur;
+        amp = (1.0 - t) * aj + t * aj1;
+      }
+      acc += w[q] * i_fit(kt * d) * d * amp;
+    }
+    pnu = ic + block_sum(acc, red);
+    pnu_guess = pnu;
+  }
+  if (threadIdx.x == 0) {
+    pcdm_out[ob] = pcdm;
+    pnu_out[ob] = pnu;
+    ratio_out[ob] = pnu / pcdm_half;
+    hpm[static_cast<size_t>(bx.n_cur) * nbins + b] = (1.0 - bx.f_nu) * pcdm_half + bx.f_nu * pnu;
+    hpn[static_cast<size_t>(bx.n_cur) * nbins + b] = pnu;
+  }
+}
+
+__global__ __launch_bounds__(256) void rtable_kernel(const double* __restrict__ ratio,
+                                                     const double* __restrict__ kmean,
+                                                     const int* __restrict__ nonempty,
+                                                     int n_nonempty,
+                                                     const RespBox* __restrict__ boxes,
+                                                     int nbins, int n2max, double kf,
+                                                     float* __restrict__ rtable) {
+  const int box = blockIdx.y;
+  const int n2 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n2 > n2max) return;
+  const double f = boxes[box].f_nu;
+  const double* rb = ratio + static_cast<size_t>(box) * nbins;
+  double r;
+  if (n2 == 0) {
+    r = rb[nonempty[0]];
+  } else {
+    const double lk = log(kf * sqrt(static_cast<double>(n2)));
+    const double lo = log(kmean[nonempty[0]]);
+    const double hi = log(kmean[nonempty[n_nonempty - 1]]);
+    if (lk <= lo) {
+      r = rb[nonempty[0]];
+    } else if (lk >= hi) {
+      r = rb[nonempty[n_nonempty - 1]];
+    } else {
+      int a = 0, z = n_nonempty - 1;   // log k of nonempty[a] <= lk < that of nonempty[z]
+      while (z - a > 1) {
+        const int mid = (a + z) >> 1;
+        if (log(kmean[nonempty[mid]]) <= lk) a = mid; else z = mid;
+      }
+      const double la = log(kmean[nonempty[a]]), lz = log(kmean[nonempty[z]]);
+      const double t = (lk - la) / (lz - la);
+      r = rb[nonempty[a]] + t * (rb[nonempty[z]] - rb[nonempty[a]]);
+    }
+  }
+  rtable[static_cast<size_t>(box) * (n2max + 1) + n2] = static_cast<float>((1.0 - f) + f * r);
+}
+
+}  // namespace
+
+hipError_t launch_response(const RespBox* boxes, const double* partial, int n_partial,
+                           const double* counts, const double* kmean, const double* hist_pm,
+                           const double* hist_pnu, const double* ic_pnu,
+                           const double* ic_theta, const double* tg_ds, const double* tg_w,
+                           int nbins, int jcap, int qcap, int q_sub, int iterations,
+                           double norm, int nbox, double* pcdm, double* pnu, double* ratio,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(response_kernel, dim3(nbins, nbox), dim3(RT), 0, s, boxes, partial,
+                     n_partial, counts, kmean, const_cast<double*>(hist_pm),
+                     const_cast<double*>(hist_pnu), ic_pnu, ic_theta, tg_ds, tg_w, nbins, jcap,
+                     qcap, q_sub, iterations, norm, pcdm, pnu, ratio);
+  return hipGetLastError();
+}
+
+hipError_t launch_rtable(const double* ratio, const double* kmean, const int* nonempty,
+                         int n_nonempty, const RespBox* boxes, int nbins, int n2max, double kf,
+                         int nbox, float* rtable, hipStream_t s) {
+  dim3 grid((n2max + 1 + 255) / 256, nbox);
+  hipLaunchKernelGGL(rtable_kernel, grid, dim3(256), 0, s, ratio, kmean, nonempty, n_nonempty,
+                     boxes, nbins, n2max, kf, rtable);
+  return hipGetLastError();
+}
+
+}  // namespace pmnu

@@ -1,0 +1,216 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, stage by stage.
+
+Tolerances: force RMS relative error <= 1e-4 and P_nu^{1/2} max relative error <= 1e-6
+(the accuracy targets of the step); FP32 stages are checked at the level FP32 arithmetic
+allows (density 2e-6 of the peak, modes 1e-5 of the peak, binned power 2e-6: the density
+is accumulated exactly in fixed point and only delta is rounded to FP32).
+Integer work (bin edges, mode counts) must be bit-exact.
+"""
+import numpy as np
+import pytest
+
+from gpu_cases import (TOL_FORCE_RMS, TOL_NU, gpu_case, make_inputs, oracle_case, rms_rel)
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_box(g, ref, hist_len, label):
+    ok = ref["counts"] > 0
+    # density (fixed-point sums of FP64 weights; unit mass per particle)
+    assert np.abs(g["rho"] - ref["rho"]).max() <= 1e-7 * ref["rho"].max(), label
+    assert abs(g["rho"].astype(np.float64).sum() / ref["rho"].sum() - 1.0) < 1e-6, label
+    # forward FFT modes, numpy rfftn layout
+    if "modes" in g:
+        scale = np.abs(ref["delta_k"]).max()
+        assert np.abs(g["modes"] - ref["delta_k"]).max() <= 1e-5 * scale, label
+    # binned power (FP64 sums of FP32 modes)
+    prel = np.abs(g["p_cdm"][ok] / ref["p_cdm"][ok] - 1.0)
+    assert prel.max() <= 2e-6, (label, prel.max())
+    assert np.all(g["p_cdm"][~ok] == 0)
+    # neutrino amplitude of eq. (P-final), FP64
+    nrel = np.abs(g["pnu_half"][ok] / ref["pnu_half"][ok] - 1.0)
+    print(f"  {label}: P_cdm max rel {prel.max():.2e}, P_nu max rel {nrel.max():.2e}",
+          flush=True)
+    assert nrel.max() <= TOL_NU, (label, nrel.max())
+    rrel = np.abs(g["ratio"][ok] / ref["ratio"][ok] - 1.0)
+    assert rrel.max() <= 2e-5, (label, rrel.max())
+    # history row appended at a_now
+    assert len(g["hist_a"]) == hist_len + 1, label
+    hrel = np.abs(g["hist_pm"][-1][ok] / ref["pm_half_now"][ok] - 1.0)
+    assert hrel.max() <= 1e-5, (label, hrel.max())
+    # acceleration grids and particle accelerations
+    assert rms_rel(g["grids"], ref["grids"]) <= TOL_FORCE_RMS, label
+    ferr = rms_rel(g["acc"], ref["acc"])
+    assert ferr <= TOL_FORCE_RMS, (label, ferr)
+    return ferr, nrel.max()
+
+
+CASES = [
+    # n_side, n_mesh, box, bins, J, a_lo, a_now, m_nu, sigma, seed, Q, iters, deconv, extra, edges
+    (32, 32, 128.0, 32, 16, 0.01, 0.5, 0.3, 0.2, 0, 8, 1, True, 0, False),
+    (32, 32, 128.0, 32, 16, 0.01, 0.5, 0.3, 0.2, 1, 1, 1, True, 0, False),
+    (32, 32, 128.0, 32, 16, 0.01, 0.5, 0.3, 0.2, 2, 8, 2, True, 0, False),
+    (32, 32, 128.0, 32, 16, 0.01, 0.5, 0.3, 0.2, 3, 8, 1, False, 0, False),
+    (32, 32, 128.0, 32, 16, 0.01, 0.5, 0.3, 0.2, 4, 8, 1, True, 37, True),
+    (8, 8, 32.0, 5, 6, 0.02, 0.3, 0.6, 0.3, 5, 4, 1, True, 13, True),
+    (16, 16, 64.0, 12, 10, 0.01, 1.0, 0.15, 0.3, 6, 8, 1, True, 0, True),
+    (32, 64, 256.0, 48, 30, 0.01, 1.0, 0.45, 0.3, 7, 8, 1, True, 999, False),
+    (64, 128, 256.0, 40, 24, 0.01, 0.8, 0.3, 0.3, 8, 8, 1, True, 0, False),
+    (64, 64, 256.0, 48, 100, 0.01, 1.0, 0.05, 0.3, 9, 8, 1, True, 0, False),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"N{c[1]}-np{c[0]}-s{c[9]}" for c in CASES])
+def test_step_matches_oracle(case):
+    (ns, nm, box, nb, J, alo, anow, mnu, sig, seed, Q, it, dec, extra, edges) = case
+    print(f"case N={nm} np={ns} seed={seed} Q={Q} iters={it} deconv={dec}", flush=True)
+    pos = make_inputs(ns, box, sig, seed, extra_random=extra, edges=edges, n_mesh=nm)
+    hist, ref = oracle_case(pos, nm, box, nb, J, alo, anow, mnu, Q, it, dec)
+    out = gpu_case(pos[None], nm, box, nb, J, anow, [mnu], [hist], Q, it, dec)
+    edges_, counts, kmean = out["bins"]
+    assert np.array_equal(edges_, ref["edges"])
+    assert np.array_equal(counts, ref["counts"])
+    ok = counts > 0
+    # FP64 means summed in different orders (numpy by mode, the library by |n|^2)
+    assert np.allclose(kmean[ok], ref["k_mean"][ok], rtol=1e-12, atol=0)
+    ferr, nerr = _check_box(out["boxes"][0], ref, J - 1, str(case))
+    print(f"  force rms rel {ferr:.2e}  nu max rel {nerr:.2e}", flush=True)
+
+
+def test_batched_boxes_with_different_masses():
+    nm, box, nb, J, anow = 32, 128.0, 24, 20, 1.0
+    masses = [0.05, 0.3, 0.6]
+    pos_b, hists, refs = [], [], []
+    for i, m in enumerate(masses):
+        p = make_inputs(32, box, 0.3, 100 + i)
+        h, r = oracle_case(p, nm, box, nb, J, 0.01, anow, m)
+        pos_b.append(p)
+        hists.append(h)
+        refs.append(r)
+    out = gpu_case(np.stack(pos_b), nm, box, nb, J, anow, masses, hists)
+    for i in range(len(masses)):
+        _check_box(out["boxes"][i], refs[i], J - 1, f"box {i}")
+
+
+def test_zero_mass_is_plain_pm():
+    nm, box = 32, 128.0
+    pos = make_inputs(32, box, 0.2, 21)
+    hist, ref = oracle_case(pos, nm, box, 16, 8, 0.05, 0.5, 0.0)
+    out = gpu_case(pos[None], nm, box, 16, 8, 0.5, [0.0], [hist])
+    assert rms_rel(out["boxes"][0]["acc"], ref["acc"]) <= TOL_FORCE_RMS
+
+
+def test_non_finite_position_is_skipped_and_reported():
+    import torch
+    from paper_1209_0461_amd import PMNu, PMNuError, binding
+    import oracle.pm as opm
+    nm, box = 16, 64.0
+    pos = make_inputs(16, box, 0.2, 31)
+    bad = pos.copy()
+    bad[7] = [np.nan, 1.0, 1.0]
+    ctx = PMNu(nm, len(bad), box, 8, 8, [0.3])
+    p = torch.from_numpy(bad).cuda()
+    ctx.deposit(p)
+    rho = torch.empty(nm ** 3, device="cuda")
+    binding.pm_nu_copy_density(ctx.h, 0, rho)
+    with pytest.raises(PMNuError) as e:
+        ctx.spectrum(0)
+    assert e.value.code == -8
+    ctx.spectrum(0)   # the flag is cleared once reported
+    ref = opm.cic_deposit(np.delete(pos, 7, axis=0), nm, box)
+    assert np.abs(rho.cpu().numpy().reshape(ref.shape) - ref).max() < 1e-5
+    ctx.close()
+
+
+def test_call_order_is_enforced():
+    import torch
+    from paper_1209_0461_amd import PMNu, PMNuError
+    ctx = PMNu(16, 4096, 64.0, 8, 8, [0.3])
+    p = torch.from_numpy(make_inputs(16, 64.0, 0.2, 1)).cuda()
+    acc = torch.zeros_like(p)
+    with pytest.raises(PMNuError) as e:
+        ctx.response(0.5)
+    assert e.value.code == -4
+    with pytest.raises(PMNuError) as e:
+        ctx.force(p, acc, 0.5)
+    assert e.value.code in (-1, -4)
+    ctx.deposit(p)
+    with pytest.raises(PMNuError) as e:   # no history stored yet
+        ctx.response(0.5)
+    assert e.value.code == -5
+    ctx.close()
+
+
+def test_recompute_at_same_time_is_idempotent():
+    """A second step at the same a_now recomputes (does not append) the current node."""
+    import torch
+    from paper_1209_0461_amd import PMNu
+    nm, box, nb, J = 32, 128.0, 16, 12
+    pos = make_inputs(32, box, 0.2, 41)
+    hist, ref = oracle_case(pos, nm, box, nb, J, 0.01, 0.5, 0.3)
+    ctx = PMNu(nm, len(pos), box, nb, J + 2, [0.3])
+    ctx.set_history(0, hist)
+    p = torch.from_numpy(pos).cuda()
+    acc = torch.zeros_like(p)
+    results = []
+    for _ in range(3):
+        ctx.step(p, acc, 0.5)
+        torch.cuda.synchronize()
+        results.append((acc.cpu().numpy().copy(), ctx.spectrum(0)["pnu_half"].copy()))
+        assert len(ctx.history(0)[0]) == J
+    for a, pn in results[1:]:
+        assert rms_rel(a, results[0][0]) < 1e-6
+        assert np.allclose(pn, results[0][1], rtol=1e-12, atol=0)
+    assert rms_rel(results[-1][0], ref["acc"]) <= TOL_FORCE_RMS
+    ctx.close()
+
+
+def test_graph_replay_matches_eager():
+    import torch
+    from paper_1209_0461_amd import PMNu, binding
+    nm, box, nb, J = 32, 128.0, 16, 12
+    pos = make_inputs(32, box, 0.2, 51)
+    hist, ref = oracle_case(pos, nm, box, nb, J, 0.01, 0.5, 0.3)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = PMNu(nm, len(pos), box, nb, J + 2, [0.3])
+        ctx.set_history(0, hist)
+        p = torch.from_numpy(pos).cuda()
+        acc = torch.zeros_like(p)
+        ctx.step(p, acc, 0.5)
+        stream.synchronize()
+        eager = acc.cpu().numpy().copy()
+        binding.pm_nu_graph_capture(ctx.h, p, acc, 0.5)
+        for rep in range(3):
+            acc.zero_()
+            binding.pm_nu_graph_launch(ctx.h)
+            stream.synchronize()
+            got = acc.cpu().numpy()
+            assert rms_rel(got, eager) < 1e-6, rep
+            assert rms_rel(got, ref["acc"]) <= TOL_FORCE_RMS
+            # eager work between replays
+            ctx.step(p, acc, 0.5)
+            stream.synchronize()
+    ctx.close()
+
+
+def test_timing_records_every_stage():
+    import torch
+    from paper_1209_0461_amd import PMNu, binding
+    nm, box, nb, J = 32, 128.0, 16, 12
+    pos = make_inputs(32, box, 0.2, 61)
+    hist, _ = oracle_case(pos, nm, box, nb, J, 0.01, 0.5, 0.3)
+    ctx = PMNu(nm, len(pos), box, nb, J + 2, [0.3])
+    ctx.set_history(0, hist)
+    p = torch.from_numpy(pos).cuda()
+    acc = torch.zeros_like(p)
+    binding.pm_nu_set_timing(ctx.h, True)
+    for _ in range(2):
+        ctx.step(p, acc, 0.5)
+    t = binding.pm_nu_read_timing(ctx.h)
+    for stage in ("cic_deposit", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x_bin", "nu_response",
+                  "rtable", "inv_x_green", "fft_inv_y", "fft_inv_z", "cic_interp"):
+        ms, n = t[stage]
+        assert n == 2 and ms > 0, stage
+    assert binding.pm_nu_read_timing(ctx.h)["cic_deposit"][1] == 0
+    ctx.close()
