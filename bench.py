@@ -87,16 +87,17 @@ def load_traffic(workload, kernel):
         return None
 
 
-def make_workload(name, mass_index):
+def make_workload(name, mass_index, order):
     from synth import CONFIGS, batched_lattices, zeldovich_lattice
     cfg = dict(CONFIGS[name])
     if cfg["n_boxes"] == 1:
         m = cfg["m_nu"][mass_index % len(cfg["m_nu"])]
         seed = cfg["seeds"][mass_index % len(cfg["seeds"])]
-        pos = zeldovich_lattice(cfg["n_side"], cfg["box"], cfg["sigma_cells"], seed)[None]
+        pos = zeldovich_lattice(cfg["n_side"], cfg["box"], cfg["sigma_cells"], seed,
+                                order=order)[None]
         masses = np.array([m])
     else:
-        pos, masses = batched_lattices(cfg)
+        pos, masses = batched_lattices(cfg, order=order)
     return cfg, np.ascontiguousarray(pos), masses
 
 
@@ -123,6 +124,9 @@ def main():
     ap.add_argument("--mass-index", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the step as a HIP graph")
+    ap.add_argument("--order", default="morton", choices=["morton", "c"],
+                    help="particle order of the synthetic lattice (space-filling curve or C)")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -149,7 +153,7 @@ def main():
         return
 
     from synth import log_spaced_nodes, synthetic_history
-    cfg, pos_np, masses = make_workload(args.workload, args.mass_index)
+    cfg, pos_np, masses = make_workload(args.workload, args.mass_index, args.order)
     nbox, npart = pos_np.shape[0], pos_np.shape[1]
     n_mesh, nbins, J = cfg["n_mesh"], cfg["n_kbins"], cfg["n_hist"]
     a_now = cfg["a_now"]
@@ -169,6 +173,9 @@ def main():
             h = synthetic_history(kmean, np.sqrt(pc), nodes, float(masses[b]))
             ctx.set_history(b, h)
             hists.append(h)
+        if not args.no_autotune:
+            binding.pm_nu_autotune(ctx.h, pos, acc, a_now)
+        tuning = json.loads(binding.pm_nu_tuning(ctx.h))
         for _ in range(args.warmup):
             ctx.step(pos, acc, a_now)
         if args.graph:
@@ -213,7 +220,8 @@ def main():
                                f"M_nu={','.join(f'{m:.3g}' for m in masses[:4])}"
                                + ("..." if nbox > 4 else "") + " eV",
                    "n_mesh": n_mesh, "n_particles": npart * nbox, "n_boxes": nbox,
-                   "graph": bool(args.graph)},
+                   "graph": bool(args.graph), "particle_order": args.order,
+                   "launch": tuning},
         "particle_updates_per_s": value * npart * nbox,
         "finite": finite,
     }

@@ -1,6 +1,7 @@
-// Launch-shape autotuner: times the candidate block sizes of the particle kernels with
-// HIP events on the context's own buffers and keeps the fastest; the choice can be
-// cached as JSON keyed by (device name, N, n_boxes).
+// Launch-shape autotuner: times the candidate launch shapes of the particle kernels (the
+// deposit's chunking mode / block size, the interpolation's block size) with HIP events
+// on the context's own buffers and keeps the fastest; the choice can be cached as JSON
+// lines keyed by (device name, N, n_boxes, particles per box).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -21,32 +22,36 @@ std::string cache_key(const Ctx& c) {
   std::string dev = "unknown";
   if (hipGetDeviceProperties(&prop, c.device) == hipSuccess) dev = prop.gcnArchName;
   std::ostringstream o;
-  o << dev << "/N" << c.N << "/boxes" << c.nbox;
+  o << dev << "/N" << c.N << "/boxes" << c.nbox << "/np" << c.Np;
   return o.str();
 }
 
 std::string tuning_json(const Ctx& c) {
   std::ostringstream o;
-  o << "{\"deposit_block\": " << c.tune.deposit_block << ", \"interp_block\": "
-    << c.tune.interp_block << "}";
+  o << "{\"deposit_mode\": " << c.tune.deposit_mode << ", \"deposit_block\": "
+    << c.tune.deposit_block << ", \"interp_block\": " << c.tune.interp_block << "}";
   return o.str();
 }
 
-// Minimal reader for the cache file: lines "key deposit_block interp_block".
+int json_int(const std::string& line, const char* field, int fallback) {
+  const std::string f = std::string("\"") + field + "\": ";
+  const size_t p = line.find(f);
+  return p == std::string::npos ? fallback : std::atoi(line.c_str() + p + f.size());
+}
+
+// Cache file: one JSON object per line,
+// {"key": "...", "deposit_mode": M, "deposit_block": D, "interp_block": I}
 bool read_cache(const char* path, const std::string& key, Tuning& t) {
   std::ifstream f(path);
   if (!f) return false;
   std::string line;
   while (std::getline(f, line)) {
-    // format: {"key": "...", "deposit_block": D, "interp_block": I}
     if (line.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
-    int d = 0, i = 0;
-    const size_t pd = line.find("\"deposit_block\": ");
-    const size_t pi = line.find("\"interp_block\": ");
-    if (pd == std::string::npos || pi == std::string::npos) continue;
-    d = std::atoi(line.c_str() + pd + 17);
-    i = std::atoi(line.c_str() + pi + 16);
-    if (d >= 64 && d <= 1024 && i >= 64 && i <= 1024) {
+    const int m = json_int(line, "deposit_mode", -1);
+    const int d = json_int(line, "deposit_block", -1);
+    const int i = json_int(line, "interp_block", -1);
+    if (m >= 0 && m <= 3 && d >= 64 && d <= 1024 && i >= 64 && i <= 1024) {
+      t.deposit_mode = m;
       t.deposit_block = d;
       t.interp_block = i;
       return true;
@@ -66,8 +71,9 @@ void write_cache(const char* path, const std::string& key, const Tuning& t) {
   }
   std::ofstream f(path, std::ios::trunc);
   for (const std::string& l : keep) f << l << "\n";
-  f << "{\"key\": \"" << key << "\", \"deposit_block\": " << t.deposit_block
-    << ", \"interp_block\": " << t.interp_block << "}\n";
+  f << "{\"key\": \"" << key << "\", \"deposit_mode\": " << t.deposit_mode
+    << ", \"deposit_block\": " << t.deposit_block << ", \"interp_block\": " << t.interp_block
+    << "}\n";
 }
 
 }  // namespace
@@ -83,6 +89,8 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
   if (cache_path && read_cache(cache_path, key, c->tune)) return PM_NU_OK;
   const bool was_timing = c->timer.enabled;
   c->timer.enabled = false;
+  struct DepCand { int mode, block; };
+  const DepCand dep[] = {{0, 256}, {0, 512}, {1, 256}, {2, 256}, {3, 256}};
   const int blocks[] = {128, 256, 512, 1024};
   hipEvent_t e0, e1;
   PMNU_HIP(hipEventCreate(&e0));
@@ -90,34 +98,42 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
   int rc = pm_nu_step(ctx, pos, acc, a_now);   // warm everything up once
   if (rc) return rc;
   const double inv_cell = c->N / c->cfg.box_size;
-  float best_d = 1e30f, best_i = 1e30f;
-  Tuning best = c->tune;
-  for (int bsz : blocks) {
-    float tot_d = 0.f, tot_i = 0.f;
-    for (int rep = 0; rep < 3; ++rep) {
-      PMNU_HIP(launch_fill_zero(c->rho, c->M * c->nbox * 8, c->stream));
-      PMNU_HIP(hipEventRecord(e0, c->stream));
-      PMNU_HIP(launch_deposit(pos, c->rho, c->Np, c->nbox, c->N, inv_cell, c->d_flags, bsz, 1,
-                              c->stream));
-      PMNU_HIP(hipEventRecord(e1, c->stream));
-      PMNU_HIP(hipEventSynchronize(e1));
+  auto time_ms = [&](auto&& launch) -> float {
+    float tot = 0.f;
+    for (int rep = 0; rep < 4; ++rep) {
+      if (launch(true) != hipSuccess) return 1e30f;
+      if (hipEventRecord(e0, c->stream) != hipSuccess) return 1e30f;
+      if (launch(false) != hipSuccess) return 1e30f;
+      if (hipEventRecord(e1, c->stream) != hipSuccess) return 1e30f;
+      if (hipEventSynchronize(e1) != hipSuccess) return 1e30f;
       float ms = 0.f;
-      PMNU_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (rep) tot_d += ms;
-      PMNU_HIP(hipEventRecord(e0, c->stream));
-      PMNU_HIP(launch_interp(pos, c->force, acc, c->Np, c->nbox, c->N, inv_cell, bsz, 1,
-                             c->stream));
-      PMNU_HIP(hipEventRecord(e1, c->stream));
-      PMNU_HIP(hipEventSynchronize(e1));
-      PMNU_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (rep) tot_i += ms;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (rep) tot += ms;
     }
-    if (tot_d < best_d) {
-      best_d = tot_d;
-      best.deposit_block = bsz;
+    return tot;
+  };
+  Tuning best = c->tune;
+  float best_d = 1e30f, best_i = 1e30f;
+  for (const DepCand& d : dep) {
+    const float ms = time_ms([&](bool prep) -> hipError_t {
+      if (prep) return launch_fill_zero(c->rho, c->M * c->nbox * 8, c->stream);
+      return launch_deposit(pos, c->rho, c->Np, c->nbox, c->N, inv_cell, c->d_flags, d.mode,
+                            d.block, c->stream);
+    });
+    if (ms < best_d) {
+      best_d = ms;
+      best.deposit_mode = d.mode;
+      best.deposit_block = d.block;
     }
-    if (tot_i < best_i) {
-      best_i = tot_i;
+  }
+  for (int bsz : blocks) {
+    const float ms = time_ms([&](bool prep) -> hipError_t {
+      if (prep) return hipSuccess;
+      return launch_interp(pos, c->force, acc, c->Np, c->nbox, c->N, inv_cell, bsz, 1,
+                           c->stream);
+    });
+    if (ms < best_i) {
+      best_i = ms;
       best.interp_block = bsz;
     }
   }

@@ -18,7 +18,8 @@
 //                   fields F1 = phi, F2 = -i k_x phi, inverse FFT along kx
 //           inv_y   G1 = IFFT_y F1, G2 = IFFT_y(-i k_y F1), G3 = IFFT_y F2
 //           inv_z   complex-to-real along z of -i k_z G1, G2, G3 (two rows per complex
-//                   FFT), transposed back to [x][y][z]: the acceleration grids g_z, g_y, g_x
+//                   FFT), transposed back to [x][y][z] with the three acceleration
+//                   components (g_x, g_y, g_z) interleaved per node
 // Since the derivative along an axis commutes with the transforms along the other axes,
 // this needs 2 + 3 intermediate fields instead of 3 + 3 + 3.
 #include "fft_lds.hpp"
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(NT) void inv_y_kernel(float2* __restrict__ f1,
   }
 }
 
-// out: [3][nbox][x][y][z] with component 0 = g_x (from G3), 1 = g_y (G2), 2 = g_z (G1).
+// out: [nbox][x][y][z][3] with component 0 = g_x (from G3), 1 = g_y (G2), 2 = g_z (G1).
 template <int N>
 __global__ __launch_bounds__(NT) void inv_z_kernel(const float2* __restrict__ g1,
                                                    const float2* __restrict__ g2,
@@ -244,12 +245,14 @@ __global__ __launch_bounds__(NT) void inv_z_kernel(const float2* __restrict__ g1
   }
   __syncthreads();
   fft_lines<N, NL, NT, +1>(lds, tw);
-  const size_t m = static_cast<size_t>(N) * N * N;
+  // interleaved output: (g_x, g_y, g_z) of node (x, y, z) are 3 consecutive floats, so the
+  // TY rows of this workgroup are one contiguous block of TY * N * 3 floats
+  float* dst = out + ((static_cast<size_t>(box) * N + x) * N + y0) * N * 3;
   for (int t = threadIdx.x; t < ROWS * N; t += NT) {
-    const int e = t % N, row = t / N, comp = row / TY, y = row % TY;
+    const int comp = t % 3, ye = t / 3, e = ye % N, y = ye / N;
+    const int row = comp * TY + y;
     const float2 z = lds[e * ES + (row >> 1)];
-    out[(static_cast<size_t>(comp) * nbox + box) * m + (static_cast<size_t>(x) * N + y0 + y) * N +
-        e] = (row & 1) ? z.y : z.x;
+    dst[t] = (row & 1) ? z.y : z.x;
   }
 }
 

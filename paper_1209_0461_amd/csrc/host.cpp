@@ -277,7 +277,7 @@ int do_deposit(Ctx& c, const float* pos) {
   const int64_t cells = c.M * c.nbox;
   TIMED(c, ST_ZERO, launch_fill_zero(c.rho, cells * 8, c.stream));
   TIMED(c, ST_DEPOSIT, launch_deposit(pos, c.rho, c.Np, c.nbox, c.N, c.N / c.cfg.box_size,
-                                      c.d_flags, c.tune.deposit_block, c.tune.deposit_ppt,
+                                      c.d_flags, c.tune.deposit_mode, c.tune.deposit_block,
                                       c.stream));
   const double scale = static_cast<double>(c.M) / static_cast<double>(c.Np) / kFixScale;
   TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, c.rho, c.ck[0], c.tw, scale, c.nbox, c.stream));
@@ -638,8 +638,9 @@ int pm_nu_copy_force_grid(pm_nu_ctx* ctx, int box, int axis, float* out) {
   GET_CTX(ctx);
   if (box < 0 || box >= c->nbox || axis < 0 || axis > 2 || !out)
     return set_error(PM_NU_EINVAL, "bad box/axis/out");
-  PMNU_HIP(hipMemcpyAsync(out, c->force + (static_cast<size_t>(axis) * c->nbox + box) * c->M,
-                          c->M * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+  hipError_t e = launch_extract_component(c->force + static_cast<size_t>(box) * c->M * 3, out,
+                                          c->M, axis, c->stream);
+  if (e != hipSuccess) return set_error(PM_NU_EHIP, "copy_force_grid: %s", hipGetErrorString(e));
   return PM_NU_OK;
 }
 

@@ -29,8 +29,8 @@ struct RespBox {
 
 // Launch shapes chosen by the autotuner (defaults are safe for every N).
 struct Tuning {
-  int deposit_block = 256;
-  int deposit_ppt = 1;       // particles per thread in the deposit
+  int deposit_mode = 3;      // see launch_deposit
+  int deposit_block = 256;   // block size of mode 0
   int interp_block = 256;
   int interp_ppt = 1;
 };
@@ -68,7 +68,7 @@ struct Ctx {
   // device buffers
   unsigned long long* rho = nullptr;   // [nbox][M] deposit, fixed point (unit 2^-40)
   float2* ck[3] = {nullptr, nullptr, nullptr};   // [nbox][NK][N][N]
-  float* force = nullptr;          // [3][nbox][M]
+  float* force = nullptr;          // [nbox][M][3] accelerations, components interleaved
   double* bin_partial = nullptr;   // [nbox][n_partial][B]
   uint16_t* bin_of_n2 = nullptr;   // [n2max+1]
   double* d_counts = nullptr;      // [B]
@@ -129,8 +129,12 @@ constexpr double kFixScale = 1099511627776.0;   // 2^40: fixed-point unit of the
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
 hipError_t launch_fixed_to_float(const unsigned long long* src, float* dst, int64_t n,
                                  hipStream_t s);
+hipError_t launch_extract_component(const float* src, float* dst, int64_t n, int comp,
+                                   hipStream_t s);
+// mode 0: one thread per particle, 8 global atomics each; modes 1-3: LDS-privatised
+// chunks of 1024 / 2048 / 4096 particles (global atomics for chunks that do not fit)
 hipError_t launch_deposit(const float* pos, unsigned long long* rho, int64_t np, int nbox, int N,
-                          double inv_cell, int* flags, int block, int ppt, hipStream_t s);
+                          double inv_cell, int* flags, int mode, int block, hipStream_t s);
 hipError_t launch_interp(const float* pos, const float* force, float* acc, int64_t np,
                          int nbox, int N, double inv_cell, int block, int ppt,
                          hipStream_t s);

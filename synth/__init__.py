@@ -6,8 +6,8 @@ builds smooth power-spectrum histories of the shape a simulation would have stor
 Everything it returns is plain NumPy data that both the HIP library and the FP64 oracle
 consume unchanged.
 """
-from .ics import zeldovich_lattice, batched_lattices, CONFIGS
+from .ics import zeldovich_lattice, batched_lattices, morton_codes, CONFIGS
 from .history import synthetic_history, log_spaced_nodes
 
-__all__ = ["zeldovich_lattice", "batched_lattices", "synthetic_history",
+__all__ = ["zeldovich_lattice", "batched_lattices", "morton_codes", "synthetic_history",
            "log_spaced_nodes", "CONFIGS"]

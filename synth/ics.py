@@ -16,8 +16,10 @@ Recipe (all in FP64 with ``numpy.random.default_rng(seed)``):
 The lattice sits at cell centres: a lattice on the mesh nodes makes the cloud-in-cell
 density of the unperturbed lattice non-smooth at first order in psi.
 
-Particles are returned in C order of their lattice index (i, j, l) -> (i*n + j)*n + l and
-position component 0 belongs to lattice axis i.
+Particle order: ``order="morton"`` (default) lists the particles along the Morton (Z-order)
+curve of their lattice index, the way a TreePM code keeps its particles sorted along a
+space-filling curve for domain decomposition; ``order="c"`` gives C order of the lattice
+index (i, j, l) -> (i*n + j)*n + l. Position component 0 belongs to lattice axis i.
 """
 import numpy as np
 
@@ -43,7 +45,19 @@ CONFIGS = {
 }
 
 
-def zeldovich_lattice(n_side, box, sigma_cells, seed, spectral_index=-2.0):
+def morton_codes(n_side):
+    """Morton code of every lattice site, in C order of (i, j, l); bits of i are the most
+    significant of each triple."""
+    p = int(n_side).bit_length() - 1
+    idx = np.arange(n_side, dtype=np.uint64)
+    spread = np.zeros(n_side, dtype=np.uint64)
+    for b in range(p):
+        spread |= ((idx >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b)
+    return ((spread[:, None, None] << np.uint64(2)) | (spread[None, :, None] << np.uint64(1))
+            | spread[None, None, :]).reshape(-1)
+
+
+def zeldovich_lattice(n_side, box, sigma_cells, seed, spectral_index=-2.0, order="morton"):
     """Return FP32 positions, shape (n_side**3, 3), in [0, box)."""
     n = int(n_side)
     if n < 2 or n & (n - 1):
@@ -82,10 +96,16 @@ def zeldovich_lattice(n_side, box, sigma_cells, seed, spectral_index=-2.0):
     pos = np.mod(psi.reshape(-1, 3), box).astype(np.float32)
     pos[pos >= np.float32(box)] = np.float32(0.0)  # an FP32 round-up to L wraps to 0
     pos[pos < 0] = np.float32(0.0)
+    if order == "morton":
+        out = np.empty_like(pos)
+        out[morton_codes(n).astype(np.int64)] = pos
+        pos = out
+    elif order != "c":
+        raise ValueError("order must be 'morton' or 'c'")
     return np.ascontiguousarray(pos)
 
 
-def batched_lattices(cfg):
+def batched_lattices(cfg, order="morton"):
     """Positions (n_boxes, n_side**3, 3) FP32 and per-box total neutrino masses [eV]."""
     nb = cfg["n_boxes"]
     if cfg.get("m_nu") is not None:
@@ -95,5 +115,5 @@ def batched_lattices(cfg):
         masses = np.random.default_rng(cfg["m_nu_seed"]).uniform(lo, hi, size=nb)
     seeds = cfg.get("seeds") or tuple(cfg["seed0"] + b for b in range(nb))
     pos = np.stack([zeldovich_lattice(cfg["n_side"], cfg["box"], cfg["sigma_cells"],
-                                      seeds[b % len(seeds)]) for b in range(nb)])
+                                      seeds[b % len(seeds)], order=order) for b in range(nb)])
     return pos, masses
