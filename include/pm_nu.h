@@ -173,40 +173,61 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
 /* Current launch-shape choice as a short JSON text (host buffer of cap bytes, sync). */
 int pm_nu_tuning(pm_nu_ctx* ctx, char* out, size_t cap);
 
+/* Change the total neutrino mass of one box (eV, >= 0) between steps (sync). */
+int pm_nu_set_mass(pm_nu_ctx* ctx, int box, double m_nu_total);
+
+/* ---- binned power from elsewhere ------------------------------------------------------- */
+/* Set P_cdm(k_b) of one box (host) [B] in place of a deposit, for a response computed
+ * from a spectrum measured elsewhere (or for building the surrogate's training set). The
+ * response may follow; the force may not (it needs the modes of a deposit). Empty bins
+ * are ignored (sync). */
+int pm_nu_set_power(pm_nu_ctx* ctx, int box, const double* p_cdm);
+
 /* ---- learned surrogate for the history integral (not in the paper) -------------------- */
-/* A fully connected network 11 -> 128 -> 128 -> 128 -> 1, GELU hidden activations,
- * bfloat16 weights and activations on the matrix cores with FP32 accumulation, FP32
- * master weights. Inputs per (box, bin): ln k_b, ln a, M_nu, and the 8 latest stored
- * amplitudes P_M^{1/2}(a_{n-m})/P_cdm^{1/2}(a_now), m = 1..8; output
- * y = ln(R_b (1 + k_b/k_fs(a))^2), i.e. R relative to the Appendix A approximation.
- * Features are standardised with the mean/scale stored with the weights. */
-enum { PM_NU_SUR_IN = 11, PM_NU_SUR_HIDDEN = 128 };
-/* Number of FP32 values in a weight blob: 34689 parameters + 2*11 feature stats +
- * 2 target stats. */
+/* A fully connected network 11 -> 128 -> 128 -> 128 -> 1, GELU after each hidden layer,
+ * weights and layer inputs rounded to bfloat16 with FP32 accumulation (matrix cores in
+ * training), FP32 master weights and Adam moments. Inputs per (box, bin):
+ *   ln k_b, ln a_now, M_nu [eV], and P_M^{1/2}(a_{n-m}) / P_cdm^{1/2}(a_now) for the
+ *   m = 1..8 latest stored nodes,
+ * standardised with the stored mean/scale. Output (after un-standardising):
+ *   y = ln(R (1 + k_b/k_fs(a_now))^2),
+ * i.e. R relative to the Appendix A approximation 1/(1 + k/k_fs)^2 with k_fs of
+ * eq. (kfs-formal) for one species of mass M_nu/n_species. In the step (response_mode 1)
+ * a bin whose inputs fall outside the training range (5% margin), or with fewer than 9
+ * stored nodes, uses the exact integral instead; response_mode 2 runs both and keeps the
+ * exact result. Blob layout (FP32): W1[11][128], b1[128], W2[128][128], b2, W3[128][128],
+ * b3, W4[128], b4, then feature mean[11], scale[11], min[11], max[11], target mean, scale. */
+enum { PM_NU_SUR_IN = 11, PM_NU_SUR_HIDDEN = 128, PM_NU_SUR_PARAMS = 34689 };
+/* Number of FP32 values in a weight blob (34689 + 4*11 + 2). */
 int64_t pm_nu_surrogate_blob_floats(void);
-/* Load weights (host) [pm_nu_surrogate_blob_floats()] (sync). */
+/* Load weights and statistics (host) (sync). */
 int pm_nu_surrogate_load(pm_nu_ctx* ctx, const float* blob, int64_t n_floats);
-/* Copy the current weights out (host) (sync). */
+/* Copy the current weights and statistics out (host) (sync). */
 int pm_nu_surrogate_save(pm_nu_ctx* ctx, float* blob, int64_t n_floats);
-/* Initialise weights (seeded) and the feature/target standardisation from a dataset
- * x (dev) [n][11], y (dev) [n] (sync). */
+/* Training rows for the step's current state: runs the exact response at a_now (after
+ * pm_nu_deposit or pm_nu_set_power for every box, history set) and writes the inputs
+ * x (dev) [n_boxes*B][11] and targets y (dev) [n_boxes*B] in row box*B + b; rows that
+ * cannot be used (empty bin, fewer than 9 stored nodes, no neutrinos) get y = NaN. */
+int pm_nu_surrogate_dataset(pm_nu_ctx* ctx, double a_now, float* x, float* y);
+/* Initialise weights (seeded, uniform +-sqrt(6/(fan_in+fan_out))) and the feature and
+ * target statistics from the n rows of x (dev) [n][11], y (dev) [n] (sync). */
 int pm_nu_surrogate_init(pm_nu_ctx* ctx, const float* x, const float* y, int64_t n,
                          uint64_t seed);
-/* Train on x (dev) [n][11], y (dev) [n] with Adam (lr, betas 0.9/0.999) for `epochs`
- * passes in minibatches of `batch` (multiple of 64), shuffled per epoch with `seed`.
- * *loss_out (host) gets the mean squared error of the last epoch (sync). */
+/* Adam (lr, betas 0.9/0.999, eps 1e-8) on the mean squared error of the standardised
+ * target over x (dev) [n][11], y (dev) [n]: `epochs` passes in minibatches of `batch`
+ * rows (a multiple of 32), reshuffled every epoch from `seed`; the learning rate decays
+ * by half-cosine to lr/100 over the call. *loss_out (host) = mean loss of the last epoch
+ * (sync). */
 int pm_nu_surrogate_train(pm_nu_ctx* ctx, const float* x, const float* y, int64_t n,
                           int epochs, int batch, float lr, uint64_t seed, float* loss_out);
-/* Network output for x (dev) [n][11] into y (dev) [n] (raw features, not standardised). */
+/* Network output y (dev) [n] (un-standardised) for raw inputs x (dev) [n][11]. */
 int pm_nu_surrogate_predict(pm_nu_ctx* ctx, const float* x, float* y, int64_t n);
-/* One forward + backward of the MSE loss on x (dev) [n][11], y (dev) [n] with the current
- * weights; writes the FP32 gradients (dev) [34689] in blob order and the loss (host). */
+/* Mean squared error of the standardised target over x (dev) [n][11], y (dev) [n] and its
+ * FP32 gradient (dev) [34689] in blob order, with the current weights (sync). */
 int pm_nu_surrogate_grad(pm_nu_ctx* ctx, const float* x, const float* y, int64_t n,
                          float* grad, float* loss_out);
-/* Features (dev) [n_boxes][B][11] of the current step (after pm_nu_deposit, history
- * set), as the response would feed them to the network. */
-int pm_nu_surrogate_features(pm_nu_ctx* ctx, double a_now, float* x);
-/* Ratios of the check mode (response_mode 2): exact R and surrogate R (host) [B]. */
+/* After a response in mode 2: exact and surrogate R of one box (host) [B] (sync);
+ * bins that used the exact fallback report the same value twice. */
 int pm_nu_get_surrogate_check(pm_nu_ctx* ctx, int box, double* ratio_exact,
                               double* ratio_surrogate);
 

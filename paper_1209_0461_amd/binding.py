@@ -71,7 +71,9 @@ SIGNATURES = {
                                      ctypes.c_uint64, _F]),
     "pm_nu_surrogate_predict": (_INT, [_P, _P, _P, ctypes.c_int64]),
     "pm_nu_surrogate_grad": (_INT, [_P, _P, _P, ctypes.c_int64, _P, _F]),
-    "pm_nu_surrogate_features": (_INT, [_P, ctypes.c_double, _P]),
+    "pm_nu_surrogate_dataset": (_INT, [_P, ctypes.c_double, _P, _P]),
+    "pm_nu_set_power": (_INT, [_P, _INT, _D]),
+    "pm_nu_set_mass": (_INT, [_P, _INT, ctypes.c_double]),
     "pm_nu_get_surrogate_check": (_INT, [_P, _INT, _D, _D]),
 }
 
@@ -293,8 +295,17 @@ def pm_nu_surrogate_grad(h, x, y, grad):
     return float(loss.value)
 
 
-def pm_nu_surrogate_features(h, a_now, x):
-    _check(load_library().pm_nu_surrogate_features(h, float(a_now), _dev(x)))
+def pm_nu_surrogate_dataset(h, a_now, x, y):
+    _check(load_library().pm_nu_surrogate_dataset(h, float(a_now), _dev(x), _dev(y)))
+
+
+def pm_nu_set_mass(h, box, m_nu_total):
+    _check(load_library().pm_nu_set_mass(h, box, float(m_nu_total)))
+
+
+def pm_nu_set_power(h, box, p_cdm):
+    p = _f64(p_cdm).reshape(-1)
+    _check(load_library().pm_nu_set_power(h, box, _dptr(p)))
 
 
 def pm_nu_get_surrogate_check(h, box, n_kbins):

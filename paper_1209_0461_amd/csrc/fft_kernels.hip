@@ -3,20 +3,24 @@
 // first inverse pass (gfx950, FP32 data, FP64 bin sums).
 //
 // Layouts (per box b):
-//   real grid  [b][x][y][z]                 (z contiguous)
-//   modes      [b][kz][kx][ky], kz in [0, N/2], kx, ky in [0, N)   (ky contiguous)
-// Putting the half-length axis kz outermost keeps every row a power of two long and
-// aligned; numpy's rfftn order [kx][ky][kz] is produced only by launch_copy_modes.
+//   real grid      [b][x][y][z]                 (z contiguous)
+//   modes          [b][kz][kx][ky], kz in [0, N/2], kx, ky in [0, N)   (ky contiguous)
+//   z-side fields  [b][x][kz][ky]               (the planes next to the real grid)
+// Every row is a power of two long and aligned. The passes along z work inside one
+// contiguous x-slab of the z-side layout; the passes along y move whole rows between the
+// two complex layouts (transposing [x][kz] <-> [kz][x] at row granularity); the passes
+// along x work inside one contiguous kz-slab. numpy's rfftn order [kx][ky][kz] is
+// produced only by launch_copy_modes.
 //
 // Forward:  fwd_z   delta = rho/rho_bar - 1 from the fixed-point density, real rows along
-//                   z -> half spectra (two rows per complex FFT), written transposed into
-//                   [kz][x][y]
-//           fwd_y   complex FFT of every contiguous ky row
+//                   z -> half spectra (two rows per complex FFT), written as [x][kz][y]
+//           fwd_y   complex FFT of every contiguous y row, written to [kz][x][ky]
 //           fwd_x   complex FFT along kx (tile of N x TX), then the FP64 mode sums per
 //                   k-bin: sum w |delta_k|^2, w = 1 on the kz = 0, N/2 planes, else 2
 // Inverse:  inv_x   delta_M = T(|n|^2) delta_cdm, phi = -C T delta/(k^2 W^2), and the two
 //                   fields F1 = phi, F2 = -i k_x phi, inverse FFT along kx
-//           inv_y   G1 = IFFT_y F1, G2 = IFFT_y(-i k_y F1), G3 = IFFT_y F2
+//           inv_y   G1 = IFFT_y F1, G2 = IFFT_y(-i k_y F1), G3 = IFFT_y F2, written to
+//                   [x][kz][y]
 //           inv_z   complex-to-real along z of -i k_z G1, G2, G3 (two rows per complex
 //                   FFT), transposed back to [x][y][z] with the three acceleration
 //                   components (g_x, g_y, g_z) interleaved per node
@@ -74,22 +78,31 @@ __global__ __launch_bounds__(NT) void fwd_z_kernel(const unsigned long long* __r
       const float2 d = csub(zk, zn);                        // B = (Z_k - conj Z_{N-k})/(2i)
       r = make_float2(0.5f * d.y, -0.5f * d.x);
     }
-    out[((static_cast<size_t>(box) * NK + k) * N + x) * N + y0 + row] = r;
+    out[((static_cast<size_t>(box) * N + x) * NK + k) * N + y0 + row] = r;
   }
 }
 
+// in: rows of [box][x][kz] (flattened, NL consecutive rows per workgroup);
+// out: the same rows at [box][kz][x].
 template <int N>
-__global__ __launch_bounds__(NT) void fwd_y_kernel(float2* __restrict__ data,
+__global__ __launch_bounds__(NT) void fwd_y_kernel(const float2* __restrict__ in,
+                                                   float2* __restrict__ out,
                                                    const float2* __restrict__ twg) {
-  constexpr int NL = Shape<N>::FY_NL, ES = NL + 1;
+  constexpr int NL = Shape<N>::FY_NL, ES = NL + 1, NK = Shape<N>::NK;
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
   load_twiddles<N, NT>(tw, twg);
-  float2* base = data + static_cast<size_t>(blockIdx.x) * NL * N;
-  for (int t = threadIdx.x; t < NL * N; t += NT) lds[(t % N) * ES + t / N] = base[t];
+  const size_t r0 = static_cast<size_t>(blockIdx.x) * NL;
+  const float2* src = in + r0 * N;
+  for (int t = threadIdx.x; t < NL * N; t += NT) lds[(t % N) * ES + t / N] = src[t];
   __syncthreads();
   fft_lines<N, NL, NT, -1>(lds, tw);
-  for (int t = threadIdx.x; t < NL * N; t += NT) base[t] = lds[(t % N) * ES + t / N];
+  for (int t = threadIdx.x; t < NL * N; t += NT) {
+    const size_t r = r0 + t / N;
+    const size_t box = r / (static_cast<size_t>(N) * NK), rem = r % (static_cast<size_t>(N) * NK);
+    const size_t x = rem / NK, kz = rem % NK;
+    out[((box * NK + kz) * N + x) * N + t % N] = lds[(t % N) * ES + t / N];
+  }
 }
 
 template <int N>
@@ -171,10 +184,13 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
   }
 }
 
+// in: rows of [box][kz][x] (flattened); out: G1, G2, G3 rows at [box][x][kz].
 template <int N>
-__global__ __launch_bounds__(NT) void inv_y_kernel(float2* __restrict__ f1,
-                                                   float2* __restrict__ f2,
+__global__ __launch_bounds__(NT) void inv_y_kernel(const float2* __restrict__ f1,
+                                                   const float2* __restrict__ f2,
+                                                   float2* __restrict__ g1,
                                                    float2* __restrict__ g2,
+                                                   float2* __restrict__ g3,
                                                    const float2* __restrict__ twg, float kf) {
   constexpr int NLR = Shape<N>::IY_NL, NL = 3 * NLR, ES = NL + 1;
   __shared__ float2 lds[N * ES];
@@ -191,11 +207,16 @@ __global__ __launch_bounds__(NT) void inv_y_kernel(float2* __restrict__ f1,
   }
   __syncthreads();
   fft_lines<N, NL, NT, +1>(lds, tw);
+  constexpr int NK = Shape<N>::NK;
   for (int t = threadIdx.x; t < NLR * N; t += NT) {
     const int l = t / N, e = t % N;
-    f1[off + t] = lds[e * ES + l];
-    g2[off + t] = lds[e * ES + NLR + l];
-    f2[off + t] = lds[e * ES + 2 * NLR + l];
+    const size_t r = static_cast<size_t>(blockIdx.x) * NLR + l;
+    const size_t box = r / (static_cast<size_t>(NK) * N), rem = r % (static_cast<size_t>(NK) * N);
+    const size_t kz = rem / N, x = rem % N;
+    const size_t o = ((box * N + x) * NK + kz) * N + e;
+    g1[o] = lds[e * ES + l];
+    g2[o] = lds[e * ES + NLR + l];
+    g3[o] = lds[e * ES + 2 * NLR + l];
   }
 }
 
@@ -218,7 +239,7 @@ __global__ __launch_bounds__(NT) void inv_z_kernel(const float2* __restrict__ g1
   // the real parts of A and B at k = 0 and k = N/2 share slots 0 and N/2.
   for (int t = threadIdx.x; t < NK * ROWS; t += NT) {
     const int y = t % TY, k = (t / TY) % NK, comp = t / (TY * NK);
-    const size_t gi = ((static_cast<size_t>(box) * NK + k) * N + x) * N + y0 + y;
+    const size_t gi = ((static_cast<size_t>(box) * N + x) * NK + k) * N + y0 + y;
     float2 v;
     if (comp == 0) {
       v = g3[gi];
@@ -294,10 +315,11 @@ template <int N> struct FwdZ {
   }
 };
 template <int N> struct FwdY {
-  static hipError_t run(float2* data, const float2* tw, int nbox, hipStream_t s) {
+  static hipError_t run(const float2* in, float2* out, const float2* tw, int nbox,
+                        hipStream_t s) {
     dim3 grid(static_cast<unsigned>(static_cast<int64_t>(nbox) * Shape<N>::NK * N /
                                     Shape<N>::FY_NL));
-    hipLaunchKernelGGL(fwd_y_kernel<N>, grid, dim3(NT), 0, s, data, tw);
+    hipLaunchKernelGGL(fwd_y_kernel<N>, grid, dim3(NT), 0, s, in, out, tw);
     return hipGetLastError();
   }
 };
@@ -321,11 +343,11 @@ template <int N> struct InvX {
   }
 };
 template <int N> struct InvY {
-  static hipError_t run(float2* f1, float2* f2, float2* g2, const float2* tw, float kf,
-                        int nbox, hipStream_t s) {
+  static hipError_t run(const float2* f1, const float2* f2, float2* g1, float2* g2, float2* g3,
+                        const float2* tw, float kf, int nbox, hipStream_t s) {
     dim3 grid(static_cast<unsigned>(static_cast<int64_t>(nbox) * Shape<N>::NK * N /
                                     Shape<N>::IY_NL));
-    hipLaunchKernelGGL(inv_y_kernel<N>, grid, dim3(NT), 0, s, f1, f2, g2, tw, kf);
+    hipLaunchKernelGGL(inv_y_kernel<N>, grid, dim3(NT), 0, s, f1, f2, g1, g2, g3, tw, kf);
     return hipGetLastError();
   }
 };
@@ -356,8 +378,9 @@ hipError_t launch_fwd_z(int n, const unsigned long long* rho, float2* out, const
                         double scale, int nbox, hipStream_t s) {
   return dispatch_n<FwdZ>(n, rho, out, tw, scale, nbox, s);
 }
-hipError_t launch_fwd_y(int n, float2* data, const float2* tw, int nbox, hipStream_t s) {
-  return dispatch_n<FwdY>(n, data, tw, nbox, s);
+hipError_t launch_fwd_y(int n, const float2* in, float2* out, const float2* tw, int nbox,
+                        hipStream_t s) {
+  return dispatch_n<FwdY>(n, in, out, tw, nbox, s);
 }
 hipError_t launch_fwd_x_bin(int n, float2* data, const float2* tw, const uint16_t* bin_of_n2,
                             double* partial, int nbins, int nbox, hipStream_t s) {
@@ -373,9 +396,9 @@ hipError_t launch_inv_x(int n, const float2* dk, float2* f1, float2* f2, const f
                         float cfac, float kf, int nbox, hipStream_t s) {
   return dispatch_n<InvX>(n, dk, f1, f2, tw, rtable, n2max, inv_w2, cfac, kf, nbox, s);
 }
-hipError_t launch_inv_y(int n, float2* f1, float2* f2, float2* g2, const float2* tw, float kf,
-                        int nbox, hipStream_t s) {
-  return dispatch_n<InvY>(n, f1, f2, g2, tw, kf, nbox, s);
+hipError_t launch_inv_y(int n, const float2* f1, const float2* f2, float2* g1, float2* g2,
+                        float2* g3, const float2* tw, float kf, int nbox, hipStream_t s) {
+  return dispatch_n<InvY>(n, f1, f2, g1, g2, g3, tw, kf, nbox, s);
 }
 hipError_t launch_inv_z(int n, const float2* g1, const float2* g2, const float2* g3, float* out,
                         const float2* tw, float kf, int nbox, hipStream_t s) {

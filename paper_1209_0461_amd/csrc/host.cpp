@@ -99,6 +99,16 @@ const GaussLegendre& gl16() {
 
 double hubble(double a, double om) { return kH0 * std::sqrt(om / (a * a * a) + 1.0 - om); }
 
+// k_fs(a) = sqrt(3/2 Omega_M(a) <v^-2>) a H, <v^-2> = 2 ln2/(3 zeta(3)) (m a / T_nu0)^2
+double k_free_streaming(double a, double m_single, double om) {
+  if (!(m_single > 0.0)) return 0.0;
+  const double e2 = om / (a * a * a) + 1.0 - om;
+  const double om_a = om / (a * a * a * e2);
+  const double v2 = (2.0 * std::log(2.0) / (3.0 * 1.2020569031595942)) *
+                    std::pow(m_single * a / kTnu0, 2);
+  return std::sqrt(1.5 * om_a * v2) * a * kH0 * std::sqrt(e2);
+}
+
 // s(a2) - s(a1) = int da / (a^3 H) = int dln a / (a^2 H), over a short interval in ln a.
 double ds_interval(double a1, double a2, double om) {
   const GaussLegendre& g = gl16();
@@ -249,6 +259,9 @@ int prepare_time_grid(Ctx& c, double a_now) {
     rb[b].t_over_m = c.t_over_m[b];
     rb[b].ds_ic = dsb[0];
     rb[b].a_i = nd[0];
+    rb[b].kfs = k_free_streaming(a_now, c.m_nu[b] / c.cfg.n_species, om);
+    rb[b].m_total = c.m_nu[b];
+    rb[b].a_now = a_now;
     rb[b].nq = nq;
     rb[b].n_cur = n;
   }
@@ -262,6 +275,8 @@ int prepare_time_grid(Ctx& c, double a_now) {
   return PM_NU_OK;
 }
 
+}  // namespace
+
 #define TIMED(ctx, stage, launch)                                                      \
   do {                                                                                 \
     timer_begin(ctx, stage);                                                           \
@@ -272,6 +287,8 @@ int prepare_time_grid(Ctx& c, double a_now) {
                        hipGetErrorString(e_));                                         \
   } while (0)
 
+namespace {
+
 int do_deposit(Ctx& c, const float* pos) {
   if (!pos) return set_error(PM_NU_EINVAL, "pos is NULL");
   const int64_t cells = c.M * c.nbox;
@@ -280,16 +297,19 @@ int do_deposit(Ctx& c, const float* pos) {
                                       c.d_flags, c.tune.deposit_mode, c.tune.deposit_block,
                                       c.stream));
   const double scale = static_cast<double>(c.M) / static_cast<double>(c.Np) / kFixScale;
-  TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, c.rho, c.ck[0], c.tw, scale, c.nbox, c.stream));
-  TIMED(c, ST_FFT_Y, launch_fwd_y(c.N, c.ck[0], c.tw, c.nbox, c.stream));
+  TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, c.rho, c.ck[1], c.tw, scale, c.nbox, c.stream));
+  TIMED(c, ST_FFT_Y, launch_fwd_y(c.N, c.ck[1], c.ck[0], c.tw, c.nbox, c.stream));
   TIMED(c, ST_FFT_X_BIN, launch_fwd_x_bin(c.N, c.ck[0], c.tw, c.bin_of_n2, c.bin_partial,
                                           c.B, c.nbox, c.stream));
   c.stage = 1;
+  c.modes_valid = true;
   c.pos_dep = pos;
   return PM_NU_OK;
 }
 
-int do_response(Ctx& c, double a_now) {
+}  // namespace
+
+int do_response_mode(Ctx& c, double a_now, int mode) {
   if (c.stage < 1) return set_error(PM_NU_ESTATE, "pm_nu_response needs pm_nu_deposit first");
   if (!(a_now > 0.0) || !std::isfinite(a_now)) return set_error(PM_NU_EINVAL, "bad a_now");
   if (!c.capturing) {
@@ -299,11 +319,16 @@ int do_response(Ctx& c, double a_now) {
     return set_error(PM_NU_ESTATE, "time grid not prepared before capture");
   }
   const double norm = std::pow(c.cfg.box_size, 3) / (static_cast<double>(c.M) * c.M);
-  TIMED(c, ST_RESPONSE,
-        launch_response(c.d_resp, c.bin_partial, c.n_partial, c.d_counts, c.d_kmean,
-                        c.hist_pm, c.hist_pnu, c.ic_pnu, c.ic_theta, c.tg_ds, c.tg_w, c.B,
-                        c.Jcap, c.qcap, c.Q, c.cfg.iterations, norm, c.nbox, c.pcdm, c.pnu,
-                        c.ratio, c.stream));
+  if (mode == 0) {
+    TIMED(c, ST_RESPONSE,
+          launch_response(c.d_resp, c.bin_partial, c.n_partial, c.d_counts, c.d_kmean,
+                          c.hist_pm, c.hist_pnu, c.ic_pnu, c.ic_theta, c.tg_ds, c.tg_w, c.B,
+                          c.Jcap, c.qcap, c.Q, c.cfg.iterations, norm, c.nbox, c.pcdm, c.pnu,
+                          c.ratio, c.stream));
+  } else {
+    int rc = surrogate_launch(c, mode, norm);
+    if (rc) return rc;
+  }
   TIMED(c, ST_RTABLE,
         launch_rtable(c.ratio, c.d_kmean, c.d_nonempty, static_cast<int>(c.nonempty.size()),
                       c.d_resp, c.B, c.n2max, 2.0 * kPi / c.cfg.box_size, c.nbox, c.rtable,
@@ -323,8 +348,12 @@ int do_response(Ctx& c, double a_now) {
   return PM_NU_OK;
 }
 
+namespace {
+
 int do_force(Ctx& c, const float* pos, float* acc, double a_now) {
   if (c.stage != 2) return set_error(PM_NU_ESTATE, "pm_nu_force needs pm_nu_response first");
+  if (!c.modes_valid)
+    return set_error(PM_NU_ESTATE, "pm_nu_force needs the modes of a deposit (the power was set)");
   if (a_now != c.a_resp)
     return set_error(PM_NU_ESTATE, "pm_nu_force a_now differs from the response's");
   if (!pos || !acc) return set_error(PM_NU_EINVAL, "pos/acc is NULL");
@@ -333,8 +362,9 @@ int do_force(Ctx& c, const float* pos, float* acc, double a_now) {
   TIMED(c, ST_INV_X_GREEN,
         launch_inv_x(c.N, c.ck[0], c.ck[1], c.ck[2], c.tw, c.rtable, c.n2max, c.inv_w2,
                      static_cast<float>(cgreen), kf, c.nbox, c.stream));
-  TIMED(c, ST_INV_Y, launch_inv_y(c.N, c.ck[1], c.ck[2], c.ck[0], c.tw, kf, c.nbox, c.stream));
-  TIMED(c, ST_INV_Z, launch_inv_z(c.N, c.ck[1], c.ck[0], c.ck[2], c.force, c.tw, kf, c.nbox,
+  TIMED(c, ST_INV_Y, launch_inv_y(c.N, c.ck[1], c.ck[2], c.ck[0], c.ck[3], c.ck[4], c.tw, kf,
+                                  c.nbox, c.stream));
+  TIMED(c, ST_INV_Z, launch_inv_z(c.N, c.ck[0], c.ck[3], c.ck[4], c.force, c.tw, kf, c.nbox,
                                   c.stream));
   TIMED(c, ST_INTERP, launch_interp(pos, c.force, acc, c.Np, c.nbox, c.N,
                                     c.N / c.cfg.box_size, c.tune.interp_block,
@@ -348,7 +378,8 @@ void free_ctx(Ctx* c) {
   if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
   if (c->graph) hipGraphDestroy(c->graph);
   for (hipEvent_t e : c->timer.pool) hipEventDestroy(e);
-  void* bufs[] = {c->rho, c->ck[0], c->ck[1], c->ck[2], c->force, c->bin_partial,
+  void* bufs[] = {c->rho, c->ck[0], c->ck[1], c->ck[2], c->ck[3], c->ck[4], c->force,
+                  c->bin_partial,
                   c->bin_of_n2, c->d_counts, c->d_kmean, c->d_nonempty, c->pcdm, c->pnu,
                   c->ratio, c->hist_pm, c->hist_pnu, c->ic_pnu, c->ic_theta, c->tg_ds,
                   c->tg_w, c->d_resp, c->rtable, c->tw, c->inv_w2, c->d_flags};
@@ -358,10 +389,6 @@ void free_ctx(Ctx* c) {
 }
 
 }  // namespace
-
-// Surrogate hooks (surrogate.cpp)
-void surrogate_free(Ctx& c);
-int surrogate_response(Ctx& c, double a_now);
 
 }  // namespace pmnu
 
@@ -444,7 +471,7 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
     }                                     \
   } while (0)
   ALLOC(c->rho, nb * c->M);
-  for (int i = 0; i < 3; ++i) ALLOC(c->ck[i], nb * c->MH);
+  for (int i = 0; i < 5; ++i) ALLOC(c->ck[i], nb * c->MH);
   ALLOC(c->force, 3 * nb * c->M);
   ALLOC(c->bin_partial, nb * c->n_partial * B);
   ALLOC(c->bin_of_n2, static_cast<size_t>(c->n2max) + 1);
@@ -580,8 +607,41 @@ int pm_nu_deposit(pm_nu_ctx* ctx, const float* pos) {
 
 int pm_nu_response(pm_nu_ctx* ctx, double a_now) {
   GET_CTX(ctx);
-  if (c->cfg.response_mode != 0) return surrogate_response(*c, a_now);
-  return do_response(*c, a_now);
+  return do_response_mode(*c, a_now, c->cfg.response_mode);
+}
+
+int pm_nu_set_mass(pm_nu_ctx* ctx, int box, double m_nu_total) {
+  GET_CTX(ctx);
+  if (box < 0 || box >= c->nbox) return set_error(PM_NU_EINVAL, "box %d out of range", box);
+  if (!(m_nu_total >= 0.0) || !std::isfinite(m_nu_total))
+    return set_error(PM_NU_EINVAL, "m_nu_total must be >= 0");
+  const double h = c->cfg.hubble;
+  c->m_nu[box] = m_nu_total;
+  c->f_nu[box] = m_nu_total / (93.14 * c->cfg.omega_m * h * h);
+  const double m1 = m_nu_total / c->cfg.n_species;
+  c->t_over_m[box] = m1 > 0 ? kTnu0 / m1 : 0.0;
+  c->tg_a_now = -1.0;   // the per-box constants of the response are rebuilt
+  return PM_NU_OK;
+}
+
+int pm_nu_set_power(pm_nu_ctx* ctx, int box, const double* p_cdm) {
+  GET_CTX(ctx);
+  if (box < 0 || box >= c->nbox || !p_cdm) return set_error(PM_NU_EINVAL, "bad box/p_cdm");
+  // The response sums the per-workgroup partial mode sums of each bin: put the whole sum
+  // sum w |delta_k|^2 = P C_b N^6 / L^3 in the first partial and zero the others.
+  const double norm = std::pow(c->cfg.box_size, 3) / (static_cast<double>(c->M) * c->M);
+  std::vector<double> part(static_cast<size_t>(c->n_partial) * c->B, 0.0);
+  for (int b = 0; b < c->B; ++b) {
+    if (!std::isfinite(p_cdm[b]) || p_cdm[b] < 0.0)
+      return set_error(PM_NU_EINVAL, "p_cdm[%d] must be finite and >= 0", b);
+    if (c->counts[b] > 0) part[b] = p_cdm[b] * c->counts[b] / norm;
+  }
+  PMNU_HIP(hipStreamSynchronize(c->stream));
+  PMNU_HIP(hipMemcpy(c->bin_partial + static_cast<size_t>(box) * c->n_partial * c->B, part.data(),
+                     part.size() * sizeof(double), hipMemcpyHostToDevice));
+  c->stage = 1;
+  c->modes_valid = false;
+  return PM_NU_OK;
 }
 
 int pm_nu_force(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now) {

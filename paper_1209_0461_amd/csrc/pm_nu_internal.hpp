@@ -22,9 +22,11 @@ struct RespBox {
   double t_over_m;   // T_nu0 / m_single
   double ds_ic;      // s(a_now) - s(a_i)
   double a_i;        // scale factor of node 0
+  double kfs;        // free-streaming wavenumber k_fs(a_now) [h/Mpc] (0 without neutrinos)
+  double m_total;    // total neutrino mass [eV]
+  double a_now;      // scale factor of the current step
   int nq;            // sub-nodes of the quadrature (current step included)
   int n_cur;         // history row of the current step
-  int pad0, pad1;
 };
 
 // Launch shapes chosen by the autotuner (defaults are safe for every N).
@@ -67,7 +69,9 @@ struct Ctx {
 
   // device buffers
   unsigned long long* rho = nullptr;   // [nbox][M] deposit, fixed point (unit 2^-40)
-  float2* ck[3] = {nullptr, nullptr, nullptr};   // [nbox][NK][N][N]
+  // complex fields, (N/2+1) N^2 each per box: ck[0] holds the modes [kz][kx][ky] from the
+  // forward transform to the first inverse pass; the others hold intermediates
+  float2* ck[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   float* force = nullptr;          // [nbox][M][3] accelerations, components interleaved
   double* bin_partial = nullptr;   // [nbox][n_partial][B]
   uint16_t* bin_of_n2 = nullptr;   // [n2max+1]
@@ -93,6 +97,7 @@ struct Ctx {
   std::vector<std::vector<double>> hist_a;   // committed node scale factors per box
   std::vector<int> has_ic;
   int stage = 0;                   // 0: idle, 1: deposited, 2: responded
+  bool modes_valid = false;        // the modes come from a deposit (not pm_nu_set_power)
   double a_resp = 0.0;
   const float* pos_dep = nullptr;
   // time-grid cache: valid for (a_now, history version)
@@ -122,6 +127,11 @@ int set_error(int code, const char* fmt, ...);
 // Event-bracketed launch helpers (host.cpp)
 void timer_begin(Ctx& c, int stage);
 void timer_end(Ctx& c);
+// Response at a_now with the exact integral (mode 0) or the surrogate (modes 1, 2).
+int do_response_mode(Ctx& c, double a_now, int mode);
+// surrogate.cpp: the kernel launch of the surrogate response (modes 1, 2)
+int surrogate_launch(Ctx& c, int mode, double norm);
+void surrogate_free(Ctx& c);
 
 // ---- kernel launchers (each returns hipGetLastError() of its launch) -----------------
 // grid_kernels.hip
@@ -141,15 +151,16 @@ hipError_t launch_interp(const float* pos, const float* force, float* acc, int64
 // fft_kernels.hip
 hipError_t launch_fwd_z(int N, const unsigned long long* rho, float2* out, const float2* tw,
                         double scale, int nbox, hipStream_t s);
-hipError_t launch_fwd_y(int N, float2* data, const float2* tw, int nbox, hipStream_t s);
+hipError_t launch_fwd_y(int N, const float2* in, float2* out, const float2* tw, int nbox,
+                        hipStream_t s);
 hipError_t launch_fwd_x_bin(int N, float2* data, const float2* tw, const uint16_t* bin_of_n2,
                             double* partial, int B, int nbox, hipStream_t s);
 int fwd_x_partials(int N);   // partial bin sums per box written by launch_fwd_x_bin
 hipError_t launch_inv_x(int N, const float2* dk, float2* f1, float2* f2, const float2* tw,
                         const float* rtable, int n2max, const float* inv_w2,
                         float cfac, float kf, int nbox, hipStream_t s);
-hipError_t launch_inv_y(int N, float2* f1, float2* f2, float2* g2, const float2* tw, float kf,
-                        int nbox, hipStream_t s);
+hipError_t launch_inv_y(int N, const float2* f1, const float2* f2, float2* g1, float2* g2,
+                        float2* g3, const float2* tw, float kf, int nbox, hipStream_t s);
 hipError_t launch_inv_z(int N, const float2* g1, const float2* g2, const float2* g3,
                         float* out, const float2* tw, float kf, int nbox, hipStream_t s);
 hipError_t launch_copy_modes(int N, const float2* ck, float2* out, int box, hipStream_t s);
@@ -161,6 +172,24 @@ hipError_t launch_response(const RespBox* boxes, const double* partial, int n_pa
                            int B, int Jcap, int qcap, int Q, int iterations, double norm,
                            int nbox, double* pcdm, double* pnu, double* ratio,
                            hipStream_t s);
+// mlp_kernels.hip
+hipError_t launch_mlp_train(const float* P, const float* x, const float* y, const int* perm,
+                            int64_t row0, int64_t count, float inv_batch, float* grad,
+                            float* loss_sum, hipStream_t s);
+hipError_t launch_mlp_predict(const float* P, const float* x, float* y, int64_t n, hipStream_t s);
+hipError_t launch_adam(float* P, const float* g, float* m, float* v, int n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_surrogate_response(const float* P, int mode, const RespBox* boxes,
+                                     const double* partial, int n_partial, const double* counts,
+                                     const double* kmean, double* hist_pm, double* hist_pnu,
+                                     const double* ic_pnu, const double* ic_theta,
+                                     const double* tg_ds, const double* tg_w, int nbins, int jcap,
+                                     int qcap, int q_sub, int iterations, double norm, int nbox,
+                                     double* pcdm, double* pnu, double* ratio, double* chk_exact,
+                                     double* chk_sur, hipStream_t s);
+hipError_t launch_surrogate_dataset(const RespBox* boxes, const double* pcdm, const double* ratio,
+                                    const double* kmean, const double* hist_pm, int nbins,
+                                    int jcap, int nbox, float* x, float* y, hipStream_t s);
 hipError_t launch_rtable(const double* ratio, const double* kmean, const int* nonempty,
                          int n_nonempty, const RespBox* boxes, int B, int n2max, double kf,
                          int nbox, float* rtable, hipStream_t s);

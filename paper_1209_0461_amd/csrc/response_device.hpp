@@ -1,0 +1,80 @@
+// Device pieces of the neutrino response shared by the exact and the surrogate kernels
+// (FP64, one workgroup of RT threads per (k-bin, box)).
+#pragma once
+#include "pm_nu_internal.hpp"
+
+namespace pmnu {
+
+constexpr int RT = 256;
+
+// Rational fit of the free-streaming kernel I(x), the paper's Appendix C eq. (fit).
+__device__ __forceinline__ double i_fit(double x) {
+  const double x2 = x * x, x4 = x2 * x2;
+  const double num = 1.0 + 0.0168 * x2 + 0.0407 * x4;
+  const double den = 1.0 + 2.1734 * x2 + 1.6787 * pow(x, 4.1811) + 0.1467 * x4 * x4;
+  return num / den;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the workgroup (RT threads); every thread gets the result.
+__device__ __forceinline__ double block_sum_d(double v, double* red) {
+  v = wave_sum_d(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < RT / 64; ++w) s += red[w];
+  return s;
+}
+
+// sum over the per-workgroup partial mode sums of bin b: sum w |delta_k|^2
+__device__ __forceinline__ double bin_mode_sum(const double* partial, int n_partial, int nbins,
+                                               int box, int b, double* red) {
+  double s = 0.0;
+  const double* pp = partial + static_cast<size_t>(box) * n_partial * nbins + b;
+  for (int i = threadIdx.x; i < n_partial; i += RT) s += pp[static_cast<size_t>(i) * nbins];
+  return block_sum_d(s, red);
+}
+
+// eq. (P-final) for one bin: the initial-condition term plus the trapezoid sum over the
+// sub-nodes, iterated `iterations` times on the current node (every thread gets it).
+__device__ __forceinline__ double exact_pnu(const RespBox& bx, double k, double pcdm_half,
+                                            double pnu_prev, double ic_pnu, double ic_theta,
+                                            const double* hpm, int nbins, int b,
+                                            const double* ds, const double* w, int q_sub,
+                                            int iterations, double* red) {
+  if (bx.t_over_m <= 0.0) return 0.0;   // no massive neutrinos: the term drops out
+  const double kt = k * bx.t_over_m;
+  const double inv_q = 1.0 / q_sub;
+  const double ic = i_fit(kt * bx.ds_ic) * ic_pnu * (1.0 - bx.ds_ic * bx.a_i * ic_theta);
+  double pnu_guess = pnu_prev, pnu = 0.0;
+  for (int it = 0; it < iterations; ++it) {
+    const double a_cur = (1.0 - bx.f_nu) * pcdm_half + bx.f_nu * pnu_guess;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < bx.nq; q += RT) {
+      const double d = ds[q];
+      const int j = q / q_sub, r = q - j * q_sub;
+      const double aj = (j < bx.n_cur) ? hpm[static_cast<size_t>(j) * nbins + b] : a_cur;
+      double amp = aj;
+      if (r != 0) {
+        const double aj1 =
+            (j + 1 < bx.n_cur) ? hpm[static_cast<size_t>(j + 1) * nbins + b] : a_cur;
+        const double t = r * inv_q;
+        amp = (1.0 - t) * aj + t * aj1;
+      }
+      acc += w[q] * i_fit(kt * d) * d * amp;
+    }
+    pnu = ic + block_sum_d(acc, red);
+    pnu_guess = pnu;
+  }
+  return pnu;
+}
+
+}  // namespace pmnu

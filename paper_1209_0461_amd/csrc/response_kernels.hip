@@ -19,38 +19,10 @@
 //
 // rtable_kernel: T(n^2) = (1 - f_nu) + f_nu R(|k|) for every integer n^2 in [0, 3N^2/4]
 // with R linear in ln k between the means of the non-empty bins, held at the end values.
-#include "pm_nu_internal.hpp"
+#include "response_device.hpp"
 
 namespace pmnu {
 namespace {
-
-constexpr int RT = 256;
-
-__device__ __forceinline__ double i_fit(double x) {
-  const double x2 = x * x, x4 = x2 * x2;
-  const double num = 1.0 + 0.0168 * x2 + 0.0407 * x4;
-  const double den = 1.0 + 2.1734 * x2 + 1.6787 * pow(x, 4.1811) + 0.1467 * x4 * x4;
-  return num / den;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Sum over the workgroup (RT threads); every thread gets the result.
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int w = 0; w < RT / 64; ++w) s += red[w];
-  return s;
-}
 
 __global__ __launch_bounds__(RT) void response_kernel(
     const RespBox* __restrict__ boxes, const double* __restrict__ partial, int n_partial,
@@ -64,15 +36,12 @@ __global__ __launch_bounds__(RT) void response_kernel(
   const int b = blockIdx.x, box = blockIdx.y;
   const RespBox bx = boxes[box];
   const size_t ob = static_cast<size_t>(box) * nbins + b;
-
-  // 1. binned CDM power
-  double s = 0.0;
-  const double* pp = partial + static_cast<size_t>(box) * n_partial * nbins + b;
-  for (int i = threadIdx.x; i < n_partial; i += RT) s += pp[static_cast<size_t>(i) * nbins];
-  s = block_sum(s, red);
-  const double cb = counts[b];
   double* hpm = hist_pm + static_cast<size_t>(box) * jcap * nbins;
   double* hpn = hist_pnu + static_cast<size_t>(box) * jcap * nbins;
+
+  // 1. binned CDM power
+  const double s = bin_mode_sum(partial, n_partial, nbins, box, b, red);
+  const double cb = counts[b];
   if (!(cb > 0.0)) {
     if (threadIdx.x == 0) {
       pcdm_out[ob] = 0.0;
@@ -85,37 +54,12 @@ __global__ __launch_bounds__(RT) void response_kernel(
   }
   const double pcdm = norm * s / cb;
   const double pcdm_half = sqrt(pcdm);
-  const double k = kmean[b];
-  const double kt = k * bx.t_over_m;
 
-  // 2. history integral; the kernel factor does not depend on the iteration
-  const double* ds = tg_ds + static_cast<size_t>(box) * qcap;
-  const double* w = tg_w + static_cast<size_t>(box) * qcap;
-  const double inv_q = 1.0 / q_sub;
-  double pnu_guess = hpn[static_cast<size_t>(bx.n_cur - 1) * nbins + b];
-  double pnu = 0.0;
-  const double ic = bx.t_over_m <= 0.0 ? 0.0 : i_fit(kt * bx.ds_ic) * ic_pnu[ob] *
-                    (1.0 - bx.ds_ic * bx.a_i * ic_theta[ob]);
-  // without massive neutrinos (t_over_m = 0, f_nu = 0) the neutrino term drops out
-  for (int it = 0; it < (bx.t_over_m > 0.0 ? iterations : 0); ++it) {
-    const double a_cur = (1.0 - bx.f_nu) * pcdm_half + bx.f_nu * pnu_guess;
-    double acc = 0.0;
-    for (int q = threadIdx.x; q < bx.nq; q += RT) {
-      const double d = ds[q];
-      const int j = q / q_sub, r = q - j * q_sub;
-      const double t = r * inv_q;
-      const double aj = (j < bx.n_cur) ? hpm[static_cast<size_t>(j) * nbins + b] : a_cur;
-      double amp = aj;
-      if (r != 0) {
-        const double aj1 =
-            (j + 1 < bx.n_cur) ? hpm[static_cast<size_t>(j + 1) * nbins + b] : a_cur;
-        amp = (1.0 - t) * aj + t * aj1;
-      }
-      acc += w[q] * i_fit(kt * d) * d * amp;
-    }
-    pnu = ic + block_sum(acc, red);
-    pnu_guess = pnu;
-  }
+  // 2. history integral
+  const double pnu = exact_pnu(bx, kmean[b], pcdm_half,
+                               hpn[static_cast<size_t>(bx.n_cur - 1) * nbins + b], ic_pnu[ob],
+                               ic_theta[ob], hpm, nbins, b, tg_ds + static_cast<size_t>(box) * qcap,
+                               tg_w + static_cast<size_t>(box) * qcap, q_sub, iterations, red);
   if (threadIdx.x == 0) {
     pcdm_out[ob] = pcdm;
     pnu_out[ob] = pnu;
