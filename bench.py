@@ -101,6 +101,44 @@ def make_workload(name, mass_index, order):
     return cfg, np.ascontiguousarray(pos), masses
 
 
+SURROGATE_BLOB = os.path.join(ROOT, "paper_1209_0461_amd", "data", "surrogate_pm256.npy")
+
+
+def measure_surrogate(ctx, binding, pos, acc, a_now, steps, stream, timing_exact):
+    """Same step with the surrogate response: accuracy of R against the exact integral
+    (check mode, every box and non-empty bin) and the timed step."""
+    binding.pm_nu_surrogate_load(ctx.h, np.load(SURROGATE_BLOB))
+    binding.pm_nu_set_response_mode(ctx.h, 2)
+    ctx.step(pos, acc, a_now)
+    _, counts, _ = ctx.bins()
+    ok = counts > 0
+    errs = []
+    for b in range(ctx.n_boxes):
+        ex, su = binding.pm_nu_get_surrogate_check(ctx.h, b, ctx.cfg.n_kbins)
+        errs.append(np.abs(su[ok] / ex[ok] - 1.0))
+    errs = np.concatenate(errs)
+    binding.pm_nu_set_response_mode(ctx.h, 1)
+    for _ in range(3):
+        ctx.step(pos, acc, a_now)
+    stream.synchronize()
+    binding.pm_nu_read_timing(ctx.h)
+    binding.pm_nu_set_timing(ctx.h, True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step(pos, acc, a_now)
+    stream.synchronize()
+    dt = time.perf_counter() - t0
+    t = binding.pm_nu_read_timing(ctx.h)
+    binding.pm_nu_set_timing(ctx.h, False)
+    binding.pm_nu_set_response_mode(ctx.h, 0)
+    sur_ms = t["surrogate"][0] / max(1, t["surrogate"][1])
+    ex_ms = timing_exact["nu_response"][0] / max(1, timing_exact["nu_response"][1])
+    return {"steps_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps,
+            "response_ms_exact": ex_ms, "response_ms_surrogate": sur_ms,
+            "R_max_rel_err": float(errs.max()), "R_rms_rel_err": float(np.sqrt(np.mean(errs ** 2))),
+            "bar": 1e-3}
+
+
 def cpu_baseline(cfg, pos, masses, hists):
     """Time the FP64 oracle on one full step of box 0 (single-threaded NumPy)."""
     import oracle.step as ostep
@@ -127,6 +165,8 @@ def main():
     ap.add_argument("--order", default="morton", choices=["morton", "c"],
                     help="particle order of the synthetic lattice (space-filling curve or C)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate-versus-integral measurement")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -199,6 +239,10 @@ def main():
         binding.pm_nu_set_timing(ctx.h, False)
         sp = ctx.spectrum(0)
         finite = bool(np.isfinite(acc.cpu().numpy()).all() and np.isfinite(sp["ratio"]).all())
+        surrogate = None
+        if os.path.exists(SURROGATE_BLOB) and not args.no_surrogate and not args.graph:
+            surrogate = measure_surrogate(ctx, binding, pos, acc, a_now, args.steps, stream,
+                                          timing)
 
     from paper_1209_0461_amd.binding import load_library  # noqa: F401
     n_partial = (n_mesh // min(16 if n_mesh <= 256 else 8, n_mesh)) * (n_mesh // 2 + 1)
@@ -237,6 +281,8 @@ def main():
                            "traffic": load_traffic(args.workload, dom),
                            "algorithmic_bytes_per_launch": sb[dom]}
         out["stages"] = stages
+    if surrogate is not None:
+        out["surrogate"] = surrogate
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, pos_np, masses, hists)
     ctx.close()

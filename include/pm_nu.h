@@ -170,8 +170,17 @@ int pm_nu_graph_launch(pm_nu_ctx* ctx);
  * as JSON keyed by (device name, N, n_boxes) (sync). */
 int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
                    const char* cache_path);
+/* Set the launch shapes directly: deposit_mode 0 (one thread per particle, global atomics)
+ * or 1/2/3 (LDS-privatised chunks of 1024/2048/4096 particles), interp_mode 0 (direct
+ * gather) or 1/2/3 (LDS-staged chunks), block sizes of the mode-0 kernels (64..1024). */
+int pm_nu_set_launch(pm_nu_ctx* ctx, int deposit_mode, int deposit_block, int interp_mode,
+                     int interp_block);
 /* Current launch-shape choice as a short JSON text (host buffer of cap bytes, sync). */
 int pm_nu_tuning(pm_nu_ctx* ctx, char* out, size_t cap);
+
+/* Switch the response between the exact integral (0), the surrogate (1) and the surrogate
+ * checked against the exact integral (2) between steps. */
+int pm_nu_set_response_mode(pm_nu_ctx* ctx, int mode);
 
 /* Change the total neutrino mass of one box (eV, >= 0) between steps (sync). */
 int pm_nu_set_mass(pm_nu_ctx* ctx, int box, double m_nu_total);

@@ -63,6 +63,7 @@ SIGNATURES = {
     "pm_nu_graph_launch": (_INT, [_P]),
     "pm_nu_autotune": (_INT, [_P, _P, _P, ctypes.c_double, ctypes.c_char_p]),
     "pm_nu_tuning": (_INT, [_P, ctypes.c_char_p, ctypes.c_size_t]),
+    "pm_nu_set_launch": (_INT, [_P, _INT, _INT, _INT, _INT]),
     "pm_nu_surrogate_blob_floats": (ctypes.c_int64, []),
     "pm_nu_surrogate_load": (_INT, [_P, _F, ctypes.c_int64]),
     "pm_nu_surrogate_save": (_INT, [_P, _F, ctypes.c_int64]),
@@ -74,6 +75,7 @@ SIGNATURES = {
     "pm_nu_surrogate_dataset": (_INT, [_P, ctypes.c_double, _P, _P]),
     "pm_nu_set_power": (_INT, [_P, _INT, _D]),
     "pm_nu_set_mass": (_INT, [_P, _INT, ctypes.c_double]),
+    "pm_nu_set_response_mode": (_INT, [_P, _INT]),
     "pm_nu_get_surrogate_check": (_INT, [_P, _INT, _D, _D]),
 }
 
@@ -251,6 +253,11 @@ def pm_nu_autotune(h, pos, acc, a_now, cache_path=None):
     _check(load_library().pm_nu_autotune(h, _dev(pos), _dev(acc), float(a_now), cp))
 
 
+def pm_nu_set_launch(h, deposit_mode, deposit_block, interp_mode, interp_block):
+    _check(load_library().pm_nu_set_launch(h, int(deposit_mode), int(deposit_block),
+                                           int(interp_mode), int(interp_block)))
+
+
 def pm_nu_tuning(h):
     buf = ctypes.create_string_buffer(1024)
     _check(load_library().pm_nu_tuning(h, buf, 1024))
@@ -297,6 +304,10 @@ def pm_nu_surrogate_grad(h, x, y, grad):
 
 def pm_nu_surrogate_dataset(h, a_now, x, y):
     _check(load_library().pm_nu_surrogate_dataset(h, float(a_now), _dev(x), _dev(y)))
+
+
+def pm_nu_set_response_mode(h, mode):
+    _check(load_library().pm_nu_set_response_mode(h, int(mode)))
 
 
 def pm_nu_set_mass(h, box, m_nu_total):

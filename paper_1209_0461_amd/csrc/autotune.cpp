@@ -29,7 +29,8 @@ std::string cache_key(const Ctx& c) {
 std::string tuning_json(const Ctx& c) {
   std::ostringstream o;
   o << "{\"deposit_mode\": " << c.tune.deposit_mode << ", \"deposit_block\": "
-    << c.tune.deposit_block << ", \"interp_block\": " << c.tune.interp_block << "}";
+    << c.tune.deposit_block << ", \"interp_mode\": " << c.tune.interp_mode
+    << ", \"interp_block\": " << c.tune.interp_block << "}";
   return o.str();
 }
 
@@ -49,10 +50,12 @@ bool read_cache(const char* path, const std::string& key, Tuning& t) {
     if (line.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
     const int m = json_int(line, "deposit_mode", -1);
     const int d = json_int(line, "deposit_block", -1);
+    const int im = json_int(line, "interp_mode", -1);
     const int i = json_int(line, "interp_block", -1);
-    if (m >= 0 && m <= 3 && d >= 64 && d <= 1024 && i >= 64 && i <= 1024) {
+    if (m >= 0 && m <= 3 && d >= 64 && d <= 1024 && im >= 0 && im <= 3 && i >= 64 && i <= 1024) {
       t.deposit_mode = m;
       t.deposit_block = d;
+      t.interp_mode = im;
       t.interp_block = i;
       return true;
     }
@@ -72,8 +75,8 @@ void write_cache(const char* path, const std::string& key, const Tuning& t) {
   std::ofstream f(path, std::ios::trunc);
   for (const std::string& l : keep) f << l << "\n";
   f << "{\"key\": \"" << key << "\", \"deposit_mode\": " << t.deposit_mode
-    << ", \"deposit_block\": " << t.deposit_block << ", \"interp_block\": " << t.interp_block
-    << "}\n";
+    << ", \"deposit_block\": " << t.deposit_block << ", \"interp_mode\": " << t.interp_mode
+    << ", \"interp_block\": " << t.interp_block << "}\n";
 }
 
 }  // namespace
@@ -91,7 +94,7 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
   c->timer.enabled = false;
   struct DepCand { int mode, block; };
   const DepCand dep[] = {{0, 256}, {0, 512}, {1, 256}, {2, 256}, {3, 256}};
-  const int blocks[] = {128, 256, 512, 1024};
+  const DepCand itp[] = {{0, 128}, {0, 256}, {1, 256}, {2, 256}, {3, 256}};
   hipEvent_t e0, e1;
   PMNU_HIP(hipEventCreate(&e0));
   PMNU_HIP(hipEventCreate(&e1));
@@ -126,15 +129,16 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
       best.deposit_block = d.block;
     }
   }
-  for (int bsz : blocks) {
+  for (const DepCand& d : itp) {
     const float ms = time_ms([&](bool prep) -> hipError_t {
       if (prep) return hipSuccess;
-      return launch_interp(pos, c->force, acc, c->Np, c->nbox, c->N, inv_cell, bsz, 1,
+      return launch_interp(pos, c->force, acc, c->Np, c->nbox, c->N, inv_cell, d.mode, d.block,
                            c->stream);
     });
     if (ms < best_i) {
       best_i = ms;
-      best.interp_block = bsz;
+      best.interp_mode = d.mode;
+      best.interp_block = d.block;
     }
   }
   hipEventDestroy(e0);
@@ -145,6 +149,21 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
   rc = pm_nu_step(ctx, pos, acc, a_now);
   if (rc) return rc;
   if (cache_path) write_cache(cache_path, key, c->tune);
+  return PM_NU_OK;
+}
+
+int pm_nu_set_launch(pm_nu_ctx* ctx, int deposit_mode, int deposit_block, int interp_mode,
+                     int interp_block) {
+  Ctx* c = reinterpret_cast<Ctx*>(ctx);
+  if (!c) return set_error(PM_NU_EINVAL, "ctx is NULL");
+  auto block_ok = [](int b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
+  if (deposit_mode < 0 || deposit_mode > 3 || interp_mode < 0 || interp_mode > 3 ||
+      !block_ok(deposit_block) || !block_ok(interp_block))
+    return set_error(PM_NU_EINVAL, "bad launch shape");
+  c->tune.deposit_mode = deposit_mode;
+  c->tune.deposit_block = deposit_block;
+  c->tune.interp_mode = interp_mode;
+  c->tune.interp_block = interp_block;
   return PM_NU_OK;
 }
 

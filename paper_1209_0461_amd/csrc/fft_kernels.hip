@@ -39,7 +39,7 @@ template <int N> struct Shape {
   static constexpr int FZ_TY = N <= 32 ? N : (N <= 256 ? 32 : 16);   // real rows per WG
   static constexpr int FY_NL = N <= 256 ? (N < 16 ? N : 16) : 8;      // rows per WG
   static constexpr int FX_TX = N < 16 ? N : (N <= 256 ? 16 : 8);      // ky columns per WG
-  static constexpr int IX_TX = N < 8 ? N : (N <= 256 ? 8 : 4);
+  static constexpr int IX_TX = N < 16 ? N : (N <= 256 ? 16 : 8);
   static constexpr int IY_NL = N < 8 ? N : (N <= 256 ? 8 : 4);
   static constexpr int IZ_TY = N < 16 ? N : (N <= 256 ? 16 : 8);
 };
@@ -57,13 +57,17 @@ __global__ __launch_bounds__(NT) void fwd_z_kernel(const unsigned long long* __r
   __shared__ float2 tw[N];
   const int y0 = blockIdx.x * TY, x = blockIdx.y, box = blockIdx.z;
   load_twiddles<N, NT>(tw, twg);
-  const unsigned long long* src = rho + ((static_cast<size_t>(box) * N + x) * N + y0) * N;
+  const ulonglong2* src = reinterpret_cast<const ulonglong2*>(
+      rho + ((static_cast<size_t>(box) * N + x) * N + y0) * N);
   float* ldsf = reinterpret_cast<float*>(lds);
-  for (int t = threadIdx.x; t < TY * N; t += NT) {
-    const int row = t / N, e = t % N;
+  for (int t = threadIdx.x; t < TY * N / 2; t += NT) {
+    const int row = (2 * t) / N, e = (2 * t) % N;
+    const ulonglong2 v = src[t];
     // delta = rho / rho_bar - 1 from the exact fixed-point sum, rounded once to FP32
     ldsf[(e * ES + (row >> 1)) * 2 + (row & 1)] =
-        static_cast<float>(static_cast<double>(src[t]) * scale - 1.0);
+        static_cast<float>(static_cast<double>(v.x) * scale - 1.0);
+    ldsf[((e + 1) * ES + (row >> 1)) * 2 + (row & 1)] =
+        static_cast<float>(static_cast<double>(v.y) * scale - 1.0);
   }
   __syncthreads();
   fft_lines<N, NL, NT, -1>(lds, tw);
@@ -93,15 +97,23 @@ __global__ __launch_bounds__(NT) void fwd_y_kernel(const float2* __restrict__ in
   __shared__ float2 tw[N];
   load_twiddles<N, NT>(tw, twg);
   const size_t r0 = static_cast<size_t>(blockIdx.x) * NL;
-  const float2* src = in + r0 * N;
-  for (int t = threadIdx.x; t < NL * N; t += NT) lds[(t % N) * ES + t / N] = src[t];
+  const float4* src = reinterpret_cast<const float4*>(in + r0 * N);
+  for (int t = threadIdx.x; t < NL * N / 2; t += NT) {
+    const int e = (2 * t) % N, l = (2 * t) / N;
+    const float4 v = src[t];
+    lds[e * ES + l] = make_float2(v.x, v.y);
+    lds[(e + 1) * ES + l] = make_float2(v.z, v.w);
+  }
   __syncthreads();
   fft_lines<N, NL, NT, -1>(lds, tw);
-  for (int t = threadIdx.x; t < NL * N; t += NT) {
-    const size_t r = r0 + t / N;
+  for (int t = threadIdx.x; t < NL * N / 2; t += NT) {
+    const int e = (2 * t) % N, l = (2 * t) / N;
+    const size_t r = r0 + l;
     const size_t box = r / (static_cast<size_t>(N) * NK), rem = r % (static_cast<size_t>(N) * NK);
     const size_t x = rem / NK, kz = rem % NK;
-    out[((box * NK + kz) * N + x) * N + t % N] = lds[(t % N) * ES + t / N];
+    const float2 a = lds[e * ES + l], b = lds[(e + 1) * ES + l];
+    *reinterpret_cast<float4*>(out + ((box * NK + kz) * N + x) * N + e) =
+        make_float4(a.x, a.y, b.x, b.y);
   }
 }
 
@@ -125,16 +137,34 @@ __global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data
   __syncthreads();
   fft_lines<N, TX, NT, -1>(lds, tw);
   const double w = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
+  // store the tile back, then bin it: each thread walks a run of consecutive k_x at one
+  // k_y, where |n|^2 changes slowly, and adds to the LDS bin only when the bin changes
   for (int t = threadIdx.x; t < N * TX; t += NT) {
     const int y = t % TX, x = t / TX;
-    const float2 v = lds[x * ES + y];
-    base[static_cast<size_t>(x) * N + y] = v;
-    const int nx = signed_index(x, N), ny = signed_index(y0 + y, N);
-    const int n2 = nx * nx + ny * ny + kz * kz;
-    if (n2 > 0) {
-      const double re = v.x, im = v.y;
-      atomicAdd(&bins[bin_of_n2[n2]], w * (re * re + im * im));
+    base[static_cast<size_t>(x) * N + y] = lds[x * ES + y];
+  }
+  constexpr int RUNS = NT / TX;                        // runs per k_y column
+  constexpr int RUN = (N + RUNS - 1) / RUNS;           // k_x values per run
+  for (int t = threadIdx.x; t < TX * RUNS; t += NT) {
+    const int y = t % TX, run = t / TX;
+    const int ny = signed_index(y0 + y, N);
+    int cur = -1;
+    double acc = 0.0;
+    for (int x = run * RUN; x < min(N, run * RUN + RUN); ++x) {
+      const int nx = signed_index(x, N);
+      const int n2 = nx * nx + ny * ny + kz * kz;
+      if (n2 == 0) continue;
+      const int b = bin_of_n2[n2];
+      const float2 v = lds[x * ES + y];
+      const double p = w * (static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y);
+      if (b != cur) {
+        if (cur >= 0) atomicAdd(&bins[cur], acc);
+        cur = b;
+        acc = 0.0;
+      }
+      acc += p;
     }
+    if (cur >= 0) atomicAdd(&bins[cur], acc);
   }
   __syncthreads();
   const int wg = blockIdx.y * gridDim.x + blockIdx.x;
@@ -197,26 +227,38 @@ __global__ __launch_bounds__(NT) void inv_y_kernel(const float2* __restrict__ f1
   __shared__ float2 tw[N];
   load_twiddles<N, NT>(tw, twg);
   const size_t off = static_cast<size_t>(blockIdx.x) * NLR * N;
-  for (int t = threadIdx.x; t < NLR * N; t += NT) {
-    const int l = t / N, e = t % N;
-    const float2 a = f1[off + t];
-    lds[e * ES + l] = a;
-    const float ky = (e == N / 2) ? 0.f : kf * static_cast<float>(signed_index(e, N));
-    lds[e * ES + NLR + l] = make_float2(ky * a.y, -ky * a.x);          // -i k_y F1
-    lds[e * ES + 2 * NLR + l] = f2[off + t];
+  const float4* f1v = reinterpret_cast<const float4*>(f1 + off);
+  const float4* f2v = reinterpret_cast<const float4*>(f2 + off);
+  for (int t = threadIdx.x; t < NLR * N / 2; t += NT) {
+    const int l = (2 * t) / N, e0 = (2 * t) % N;
+    const float4 a4 = f1v[t], b4 = f2v[t];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = e0 + h;
+      const float2 a = h ? make_float2(a4.z, a4.w) : make_float2(a4.x, a4.y);
+      lds[e * ES + l] = a;
+      const float ky = (e == N / 2) ? 0.f : kf * static_cast<float>(signed_index(e, N));
+      lds[e * ES + NLR + l] = make_float2(ky * a.y, -ky * a.x);        // -i k_y F1
+      lds[e * ES + 2 * NLR + l] = h ? make_float2(b4.z, b4.w) : make_float2(b4.x, b4.y);
+    }
   }
   __syncthreads();
   fft_lines<N, NL, NT, +1>(lds, tw);
   constexpr int NK = Shape<N>::NK;
-  for (int t = threadIdx.x; t < NLR * N; t += NT) {
-    const int l = t / N, e = t % N;
+  for (int t = threadIdx.x; t < NLR * N / 2; t += NT) {
+    const int l = (2 * t) / N, e = (2 * t) % N;
     const size_t r = static_cast<size_t>(blockIdx.x) * NLR + l;
     const size_t box = r / (static_cast<size_t>(NK) * N), rem = r % (static_cast<size_t>(NK) * N);
     const size_t kz = rem / N, x = rem % N;
     const size_t o = ((box * N + x) * NK + kz) * N + e;
-    g1[o] = lds[e * ES + l];
-    g2[o] = lds[e * ES + NLR + l];
-    g3[o] = lds[e * ES + 2 * NLR + l];
+    float2 a = lds[e * ES + l], b = lds[(e + 1) * ES + l];
+    *reinterpret_cast<float4*>(g1 + o) = make_float4(a.x, a.y, b.x, b.y);
+    a = lds[e * ES + NLR + l];
+    b = lds[(e + 1) * ES + NLR + l];
+    *reinterpret_cast<float4*>(g2 + o) = make_float4(a.x, a.y, b.x, b.y);
+    a = lds[e * ES + 2 * NLR + l];
+    b = lds[(e + 1) * ES + 2 * NLR + l];
+    *reinterpret_cast<float4*>(g3 + o) = make_float4(a.x, a.y, b.x, b.y);
   }
 }
 
@@ -268,12 +310,18 @@ __global__ __launch_bounds__(NT) void inv_z_kernel(const float2* __restrict__ g1
   fft_lines<N, NL, NT, +1>(lds, tw);
   // interleaved output: (g_x, g_y, g_z) of node (x, y, z) are 3 consecutive floats, so the
   // TY rows of this workgroup are one contiguous block of TY * N * 3 floats
-  float* dst = out + ((static_cast<size_t>(box) * N + x) * N + y0) * N * 3;
-  for (int t = threadIdx.x; t < ROWS * N; t += NT) {
-    const int comp = t % 3, ye = t / 3, e = ye % N, y = ye / N;
-    const int row = comp * TY + y;
-    const float2 z = lds[e * ES + (row >> 1)];
-    dst[t] = (row & 1) ? z.y : z.x;
+  float4* dst = reinterpret_cast<float4*>(out + ((static_cast<size_t>(box) * N + x) * N + y0) * N * 3);
+  for (int t4 = threadIdx.x; t4 < ROWS * N / 4; t4 += NT) {
+    float v[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int t = 4 * t4 + h;
+      const int comp = t % 3, ye = t / 3, e = ye % N, y = ye / N;
+      const int row = comp * TY + y;
+      const float2 z = lds[e * ES + (row >> 1)];
+      v[h] = (row & 1) ? z.y : z.x;
+    }
+    dst[t4] = make_float4(v[0], v[1], v[2], v[3]);
   }
 }
 

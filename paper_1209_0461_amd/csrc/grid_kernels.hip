@@ -288,6 +288,141 @@ __global__ __launch_bounds__(1024) void interp_kernel(const float* __restrict__ 
   }
 }
 
+// Interpolation with the chunk's bounding-box tile of the acceleration grid staged in LDS
+// (rows of 3*ez consecutive floats, coalesced), PPT = CH / 256 particles per thread kept
+// in registers; chunks whose box does not fit gather straight from HBM.
+template <int CH, int CAP>
+__global__ __launch_bounds__(256) void interp_tiled_kernel(const float* __restrict__ pos,
+                                                           const float* __restrict__ force,
+                                                           float* __restrict__ acc, int64_t np,
+                                                           int n, double inv_cell,
+                                                           int64_t chunks_per_box) {
+  constexpr int NT = 256, NW = NT / 64, PPT = CH / NT;
+  __shared__ float tile[CAP * 3];
+  __shared__ int red[6][NW];
+  __shared__ int ref_s[3];
+  const int tid = threadIdx.x;
+  const int64_t box = blockIdx.x / chunks_per_box;
+  const int64_t c0 = (blockIdx.x - box * chunks_per_box) * CH;
+  const int cnt = static_cast<int>(min(static_cast<int64_t>(CH), np - c0));
+  const float* p = pos + (box * np + c0) * 3;
+  float* a_out = acc + (box * np + c0) * 3;
+  const int nmask = n - 1, half = n / 2;
+  const float* g = force + box * static_cast<int64_t>(n) * n * n * 3;
+  float px[PPT], py[PPT], pz[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int j = tid + q * NT;
+    if (j < cnt) {
+      px[q] = p[3 * j];
+      py[q] = p[3 * j + 1];
+      pz[q] = p[3 * j + 2];
+    } else {
+      px[q] = py[q] = pz[q] = __builtin_nanf("");
+    }
+  }
+  if (tid == 0) {
+    const bool ok = isfinite(px[0]) && isfinite(py[0]) && isfinite(pz[0]);
+    ref_s[0] = ok ? cell_of(px[0], inv_cell, nmask) : 0;
+    ref_s[1] = ok ? cell_of(py[0], inv_cell, nmask) : 0;
+    ref_s[2] = ok ? cell_of(pz[0], inv_cell, nmask) : 0;
+  }
+  __syncthreads();
+  const int r0 = ref_s[0], r1 = ref_s[1], r2 = ref_s[2];
+  int mn0 = 1 << 30, mn1 = 1 << 30, mn2 = 1 << 30, mx0 = -(1 << 30), mx1 = -(1 << 30),
+      mx2 = -(1 << 30);
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    if (!(isfinite(px[q]) && isfinite(py[q]) && isfinite(pz[q]))) continue;
+    const int a = ((cell_of(px[q], inv_cell, nmask) - r0 + half) & nmask) - half;
+    const int b = ((cell_of(py[q], inv_cell, nmask) - r1 + half) & nmask) - half;
+    const int c = ((cell_of(pz[q], inv_cell, nmask) - r2 + half) & nmask) - half;
+    mn0 = min(mn0, a); mx0 = max(mx0, a);
+    mn1 = min(mn1, b); mx1 = max(mx1, b);
+    mn2 = min(mn2, c); mx2 = max(mx2, c);
+  }
+  mn0 = wave_min(mn0); mn1 = wave_min(mn1); mn2 = wave_min(mn2);
+  mx0 = wave_max(mx0); mx1 = wave_max(mx1); mx2 = wave_max(mx2);
+  const int lane = tid & 63, wv = tid >> 6;
+  if (lane == 0) {
+    red[0][wv] = mn0; red[1][wv] = mn1; red[2][wv] = mn2;
+    red[3][wv] = mx0; red[4][wv] = mx1; red[5][wv] = mx2;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    mn0 = min(mn0, red[0][w]); mn1 = min(mn1, red[1][w]); mn2 = min(mn2, red[2][w]);
+    mx0 = max(mx0, red[3][w]); mx1 = max(mx1, red[4][w]); mx2 = max(mx2, red[5][w]);
+  }
+  const bool any = mn0 <= mx0;
+  const int ex = any ? mx0 - mn0 + 2 : 0, ey = any ? mx1 - mn1 + 2 : 0,
+            ez = any ? mx2 - mn2 + 2 : 0;
+  const int64_t vol = static_cast<int64_t>(ex) * ey * ez;
+  const bool use_tile = any && vol <= CAP;
+  if (use_tile) {
+    const int gx0 = r0 + mn0, gy0 = r1 + mn1, gz0 = r2 + mn2;
+    const int row3 = 3 * ez;
+    for (int t = tid; t < vol * 3; t += NT) {
+      const int row = t / row3, w = t - row * row3;
+      const int tz = w / 3, comp = w - tz * 3;
+      const int ty = row % ey, tx = row / ey;
+      const int gx = (gx0 + tx) & nmask, gy = (gy0 + ty) & nmask, gz = (gz0 + tz) & nmask;
+      tile[t] = g[((static_cast<int64_t>(gx) * n + gy) * n + gz) * 3 + comp];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int j = tid + q * NT;
+    if (j >= cnt) continue;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    if (isfinite(px[q]) && isfinite(py[q]) && isfinite(pz[q])) {
+      Corner c;
+      cic_axis(px[q], inv_cell, nmask, c.lo[0], c.hi[0], c.w[0][0], c.w[0][1]);
+      cic_axis(py[q], inv_cell, nmask, c.lo[1], c.hi[1], c.w[1][0], c.w[1][1]);
+      cic_axis(pz[q], inv_cell, nmask, c.lo[2], c.hi[2], c.w[2][0], c.w[2][1]);
+      if (use_tile) {
+        const int ta = ((c.lo[0] - r0 + half) & nmask) - half - mn0;
+        const int tb = ((c.lo[1] - r1 + half) & nmask) - half - mn1;
+        const int tc = ((c.lo[2] - r2 + half) & nmask) - half - mn2;
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx) {
+#pragma unroll
+          for (int cy = 0; cy < 2; ++cy) {
+            const float wxy = c.w[0][cx] * c.w[1][cy];
+            const float* v = tile + 3 * (((ta + cx) * ey + (tb + cy)) * ez + tc);
+            a0 += wxy * (c.w[2][0] * v[0] + c.w[2][1] * v[3]);
+            a1 += wxy * (c.w[2][0] * v[1] + c.w[2][1] * v[4]);
+            a2 += wxy * (c.w[2][0] * v[2] + c.w[2][1] * v[5]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx) {
+          const int ix = cx ? c.hi[0] : c.lo[0];
+#pragma unroll
+          for (int cy = 0; cy < 2; ++cy) {
+            const int iy = cy ? c.hi[1] : c.lo[1];
+            const float wxy = c.w[0][cx] * c.w[1][cy];
+            const int64_t row = (static_cast<int64_t>(ix) * n + iy) * n;
+#pragma unroll
+            for (int cz = 0; cz < 2; ++cz) {
+              const float* v = g + 3 * (row + (cz ? c.hi[2] : c.lo[2]));
+              const float w = wxy * c.w[2][cz];
+              a0 += w * v[0];
+              a1 += w * v[1];
+              a2 += w * v[2];
+            }
+          }
+        }
+      }
+    }
+    a_out[3 * j] = a0;
+    a_out[3 * j + 1] = a1;
+    a_out[3 * j + 2] = a2;
+  }
+}
+
 __global__ void fixed_to_float_kernel(const unsigned long long* __restrict__ src,
                                       float* __restrict__ dst, int64_t n) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
@@ -363,12 +498,26 @@ hipError_t launch_deposit(const float* pos, unsigned long long* rho, int64_t np,
   }
 }
 
-hipError_t launch_interp(const float* pos, const float* force, float* acc, int64_t np,
-                         int nbox, int n, double inv_cell, int block, int ppt,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(interp_kernel, dim3(grid_blocks(np * nbox, block, ppt)), dim3(block), 0,
-                     s, pos, force, acc, np, nbox, n, inv_cell);
+template <int CH, int CAP>
+hipError_t launch_interp_tiled(const float* pos, const float* force, float* acc, int64_t np,
+                               int nbox, int n, double inv_cell, hipStream_t s) {
+  const int64_t chunks = (np + CH - 1) / CH;
+  hipLaunchKernelGGL((interp_tiled_kernel<CH, CAP>), dim3(static_cast<unsigned>(chunks * nbox)),
+                     dim3(256), 0, s, pos, force, acc, np, n, inv_cell, chunks);
   return hipGetLastError();
+}
+
+hipError_t launch_interp(const float* pos, const float* force, float* acc, int64_t np,
+                         int nbox, int n, double inv_cell, int mode, int block, hipStream_t s) {
+  switch (mode) {
+    case 1: return launch_interp_tiled<1024, 2560>(pos, force, acc, np, nbox, n, inv_cell, s);
+    case 2: return launch_interp_tiled<2048, 4608>(pos, force, acc, np, nbox, n, inv_cell, s);
+    case 3: return launch_interp_tiled<4096, 8192>(pos, force, acc, np, nbox, n, inv_cell, s);
+    default:
+      hipLaunchKernelGGL(interp_kernel, dim3(grid_blocks(np * nbox, block, 1)), dim3(block), 0,
+                         s, pos, force, acc, np, nbox, n, inv_cell);
+      return hipGetLastError();
+  }
 }
 
 }  // namespace pmnu

@@ -367,8 +367,8 @@ int do_force(Ctx& c, const float* pos, float* acc, double a_now) {
   TIMED(c, ST_INV_Z, launch_inv_z(c.N, c.ck[0], c.ck[3], c.ck[4], c.force, c.tw, kf, c.nbox,
                                   c.stream));
   TIMED(c, ST_INTERP, launch_interp(pos, c.force, acc, c.Np, c.nbox, c.N,
-                                    c.N / c.cfg.box_size, c.tune.interp_block,
-                                    c.tune.interp_ppt, c.stream));
+                                    c.N / c.cfg.box_size, c.tune.interp_mode,
+                                    c.tune.interp_block, c.stream));
   c.stage = 0;
   return PM_NU_OK;
 }
@@ -608,6 +608,13 @@ int pm_nu_deposit(pm_nu_ctx* ctx, const float* pos) {
 int pm_nu_response(pm_nu_ctx* ctx, double a_now) {
   GET_CTX(ctx);
   return do_response_mode(*c, a_now, c->cfg.response_mode);
+}
+
+int pm_nu_set_response_mode(pm_nu_ctx* ctx, int mode) {
+  GET_CTX(ctx);
+  if (mode < 0 || mode > 2) return set_error(PM_NU_EINVAL, "response_mode must be 0, 1 or 2");
+  c->cfg.response_mode = mode;
+  return PM_NU_OK;
 }
 
 int pm_nu_set_mass(pm_nu_ctx* ctx, int box, double m_nu_total) {

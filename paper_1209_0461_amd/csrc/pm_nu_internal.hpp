@@ -33,8 +33,8 @@ struct RespBox {
 struct Tuning {
   int deposit_mode = 3;      // see launch_deposit
   int deposit_block = 256;   // block size of mode 0
-  int interp_block = 256;
-  int interp_ppt = 1;
+  int interp_mode = 1;       // see launch_interp
+  int interp_block = 256;    // block size of mode 0
 };
 
 struct Timer {
@@ -145,9 +145,10 @@ hipError_t launch_extract_component(const float* src, float* dst, int64_t n, int
 // chunks of 1024 / 2048 / 4096 particles (global atomics for chunks that do not fit)
 hipError_t launch_deposit(const float* pos, unsigned long long* rho, int64_t np, int nbox, int N,
                           double inv_cell, int* flags, int mode, int block, hipStream_t s);
+// mode 0: one thread per particle gathering from HBM; modes 1-3: chunks of 1024 / 2048 /
+// 4096 particles with their bounding-box tile of the acceleration grid staged in LDS
 hipError_t launch_interp(const float* pos, const float* force, float* acc, int64_t np,
-                         int nbox, int N, double inv_cell, int block, int ppt,
-                         hipStream_t s);
+                         int nbox, int N, double inv_cell, int mode, int block, hipStream_t s);
 // fft_kernels.hip
 hipError_t launch_fwd_z(int N, const unsigned long long* rho, float2* out, const float2* tw,
                         double scale, int nbox, hipStream_t s);

@@ -214,3 +214,31 @@ def test_timing_records_every_stage():
         assert n == 2 and ms > 0, stage
     assert binding.pm_nu_read_timing(ctx.h)["cic_deposit"][1] == 0
     ctx.close()
+
+
+@pytest.mark.parametrize("order", ["morton", "c", "shuffled"])
+def test_every_launch_mode_matches_oracle(order):
+    """All deposit and interpolation modes, on particle orders that take the LDS paths
+    (Morton), partly the fallback (C order: slab chunks) and only the fallback (shuffled)."""
+    import torch
+    from paper_1209_0461_amd import PMNu, binding
+    from synth import zeldovich_lattice
+    nm, box, nb, J = 32, 128.0, 16, 10
+    pos = zeldovich_lattice(32, box, 0.3, 71, order="morton" if order == "morton" else "c")
+    if order == "shuffled":
+        pos = pos[np.random.default_rng(3).permutation(len(pos))]
+    pos = np.ascontiguousarray(np.concatenate([pos, make_inputs(8, box, 0.2, 5)[:77]]))
+    hist, ref = oracle_case(pos, nm, box, nb, J, 0.02, 0.7, 0.3)
+    ctx = PMNu(nm, len(pos), box, nb, J + 2, [0.3])
+    ctx.set_history(0, hist)
+    p = torch.from_numpy(pos).cuda()
+    acc = torch.zeros_like(p)
+    for dm, im in ((0, 0), (1, 1), (2, 2), (3, 3), (1, 0), (0, 2)):
+        binding.pm_nu_set_launch(ctx.h, dm, 256, im, 256)
+        ctx.step(p, acc, 0.7)
+        torch.cuda.synchronize()
+        ok = ref["counts"] > 0
+        sp = ctx.spectrum(0)
+        assert np.abs(sp["p_cdm"][ok] / ref["p_cdm"][ok] - 1).max() <= 2e-6, (order, dm, im)
+        assert rms_rel(acc.cpu().numpy(), ref["acc"]) <= TOL_FORCE_RMS, (order, dm, im)
+    ctx.close()
