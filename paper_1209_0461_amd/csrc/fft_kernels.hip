@@ -167,9 +167,11 @@ __global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data
     if (cur >= 0) atomicAdd(&bins[cur], acc);
   }
   __syncthreads();
+  // partial sums stored bin-major, [box][bin][workgroup], for contiguous reads per bin
   const int wg = blockIdx.y * gridDim.x + blockIdx.x;
-  double* dst = partial + (static_cast<size_t>(box) * gridDim.x * gridDim.y + wg) * nbins;
-  for (int b = threadIdx.x; b < nbins; b += NT) dst[b] = bins[b];
+  const size_t n_wg = static_cast<size_t>(gridDim.x) * gridDim.y;
+  double* dst = partial + static_cast<size_t>(box) * nbins * n_wg + wg;
+  for (int b = threadIdx.x; b < nbins; b += NT) dst[b * n_wg] = bins[b];
 }
 
 // ------------------------------------------------------------------------ inverse ----

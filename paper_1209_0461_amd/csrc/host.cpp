@@ -330,7 +330,7 @@ int do_response_mode(Ctx& c, double a_now, int mode) {
     if (rc) return rc;
   }
   TIMED(c, ST_RTABLE,
-        launch_rtable(c.ratio, c.d_kmean, c.d_nonempty, static_cast<int>(c.nonempty.size()),
+        launch_rtable(c.ratio, c.d_lnk, c.d_nonempty, static_cast<int>(c.nonempty.size()),
                       c.d_resp, c.B, c.n2max, 2.0 * kPi / c.cfg.box_size, c.nbox, c.rtable,
                       c.stream));
   // commit the node on the host side (the kernel wrote row n_cur)
@@ -380,7 +380,7 @@ void free_ctx(Ctx* c) {
   for (hipEvent_t e : c->timer.pool) hipEventDestroy(e);
   void* bufs[] = {c->rho, c->ck[0], c->ck[1], c->ck[2], c->ck[3], c->ck[4], c->force,
                   c->bin_partial,
-                  c->bin_of_n2, c->d_counts, c->d_kmean, c->d_nonempty, c->pcdm, c->pnu,
+                  c->bin_of_n2, c->d_counts, c->d_kmean, c->d_lnk, c->d_nonempty, c->pcdm, c->pnu,
                   c->ratio, c->hist_pm, c->hist_pnu, c->ic_pnu, c->ic_theta, c->tg_ds,
                   c->tg_w, c->d_resp, c->rtable, c->tw, c->inv_w2, c->d_flags};
   for (void* p : bufs)
@@ -477,6 +477,7 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   ALLOC(c->bin_of_n2, static_cast<size_t>(c->n2max) + 1);
   ALLOC(c->d_counts, B);
   ALLOC(c->d_kmean, B);
+  ALLOC(c->d_lnk, B);
   ALLOC(c->d_nonempty, B);
   ALLOC(c->pcdm, nb * B);
   ALLOC(c->pnu, nb * B);
@@ -515,12 +516,18 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   e = e ? e : hipMemcpy(c->inv_w2, iw.data(), iw.size() * sizeof(float), hipMemcpyHostToDevice);
   e = e ? e : hipMemcpy(c->d_counts, c->counts.data(), B * sizeof(double), hipMemcpyHostToDevice);
   e = e ? e : hipMemcpy(c->d_kmean, c->kmean.data(), B * sizeof(double), hipMemcpyHostToDevice);
+  std::vector<double> lnk(B, 0.0);
+  for (size_t b = 0; b < B; ++b) lnk[b] = c->kmean[b] > 0 ? std::log(c->kmean[b]) : 0.0;
+  e = e ? e : hipMemcpy(c->d_lnk, lnk.data(), B * sizeof(double), hipMemcpyHostToDevice);
   e = e ? e : hipMemcpy(c->d_nonempty, ne.data(), B * sizeof(int), hipMemcpyHostToDevice);
   e = e ? e : hipMemset(c->d_flags, 0, sizeof(int));
   e = e ? e : hipMemset(c->hist_pm, 0, nb * c->Jcap * B * sizeof(double));
   e = e ? e : hipMemset(c->hist_pnu, 0, nb * c->Jcap * B * sizeof(double));
   e = e ? e : hipMemset(c->ic_pnu, 0, nb * B * sizeof(double));
   e = e ? e : hipMemset(c->ic_theta, 0, nb * B * sizeof(double));
+  e = e ? e : hipMemset(c->pcdm, 0, nb * B * sizeof(double));
+  e = e ? e : hipMemset(c->pnu, 0, nb * B * sizeof(double));
+  e = e ? e : hipMemset(c->ratio, 0, nb * B * sizeof(double));
   e = e ? e : hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_ctx(c);
@@ -634,14 +641,14 @@ int pm_nu_set_mass(pm_nu_ctx* ctx, int box, double m_nu_total) {
 int pm_nu_set_power(pm_nu_ctx* ctx, int box, const double* p_cdm) {
   GET_CTX(ctx);
   if (box < 0 || box >= c->nbox || !p_cdm) return set_error(PM_NU_EINVAL, "bad box/p_cdm");
-  // The response sums the per-workgroup partial mode sums of each bin: put the whole sum
-  // sum w |delta_k|^2 = P C_b N^6 / L^3 in the first partial and zero the others.
+  // The response sums the per-workgroup partial mode sums of each bin ([bin][workgroup]):
+  // put the whole sum w |delta_k|^2 = P C_b N^6 / L^3 in the first partial, zero the rest.
   const double norm = std::pow(c->cfg.box_size, 3) / (static_cast<double>(c->M) * c->M);
   std::vector<double> part(static_cast<size_t>(c->n_partial) * c->B, 0.0);
   for (int b = 0; b < c->B; ++b) {
     if (!std::isfinite(p_cdm[b]) || p_cdm[b] < 0.0)
       return set_error(PM_NU_EINVAL, "p_cdm[%d] must be finite and >= 0", b);
-    if (c->counts[b] > 0) part[b] = p_cdm[b] * c->counts[b] / norm;
+    if (c->counts[b] > 0) part[static_cast<size_t>(b) * c->n_partial] = p_cdm[b] * c->counts[b] / norm;
   }
   PMNU_HIP(hipStreamSynchronize(c->stream));
   PMNU_HIP(hipMemcpy(c->bin_partial + static_cast<size_t>(box) * c->n_partial * c->B, part.data(),
@@ -669,6 +676,13 @@ int pm_nu_get_spectrum(pm_nu_ctx* ctx, int box, double* p_cdm, double* pnu_half,
                        double* ratio) {
   GET_CTX(ctx);
   if (box < 0 || box >= c->nbox) return set_error(PM_NU_EINVAL, "box %d out of range", box);
+  if (c->stage == 1) {
+    // deposited (or power set) but no response yet: reduce the bin partials now
+    const double norm = std::pow(c->cfg.box_size, 3) / (static_cast<double>(c->M) * c->M);
+    hipError_t e = launch_bin_power(c->bin_partial, c->n_partial, c->d_counts, c->B, norm,
+                                    c->nbox, c->pcdm, c->stream);
+    if (e != hipSuccess) return set_error(PM_NU_EHIP, "bin power: %s", hipGetErrorString(e));
+  }
   PMNU_HIP(hipStreamSynchronize(c->stream));
   const size_t B = c->B;
   if (p_cdm) PMNU_HIP(hipMemcpy(p_cdm, c->pcdm + box * B, B * sizeof(double), hipMemcpyDeviceToHost));

@@ -77,6 +77,7 @@ struct Ctx {
   uint16_t* bin_of_n2 = nullptr;   // [n2max+1]
   double* d_counts = nullptr;      // [B]
   double* d_kmean = nullptr;       // [B]
+  double* d_lnk = nullptr;         // [B] ln of the bin means (0 for empty bins)
   int* d_nonempty = nullptr;       // [B]
   double* pcdm = nullptr;          // [nbox][B]
   double* pnu = nullptr;           // [nbox][B]
@@ -191,7 +192,9 @@ hipError_t launch_surrogate_response(const float* P, int mode, const RespBox* bo
 hipError_t launch_surrogate_dataset(const RespBox* boxes, const double* pcdm, const double* ratio,
                                     const double* kmean, const double* hist_pm, int nbins,
                                     int jcap, int nbox, float* x, float* y, hipStream_t s);
-hipError_t launch_rtable(const double* ratio, const double* kmean, const int* nonempty,
+hipError_t launch_bin_power(const double* partial, int n_partial, const double* counts,
+                            int nbins, double norm, int nbox, double* pcdm, hipStream_t s);
+hipError_t launch_rtable(const double* ratio, const double* lnk, const int* nonempty,
                          int n_nonempty, const RespBox* boxes, int B, int n2max, double kf,
                          int nbox, float* rtable, hipStream_t s);
 

@@ -34,12 +34,13 @@ __device__ __forceinline__ double block_sum_d(double v, double* red) {
   return s;
 }
 
-// sum over the per-workgroup partial mode sums of bin b: sum w |delta_k|^2
+// sum over the per-workgroup partial mode sums of bin b ([box][bin][workgroup]):
+// sum w |delta_k|^2
 __device__ __forceinline__ double bin_mode_sum(const double* partial, int n_partial, int nbins,
                                                int box, int b, double* red) {
   double s = 0.0;
-  const double* pp = partial + static_cast<size_t>(box) * n_partial * nbins + b;
-  for (int i = threadIdx.x; i < n_partial; i += RT) s += pp[static_cast<size_t>(i) * nbins];
+  const double* pp = partial + (static_cast<size_t>(box) * nbins + b) * n_partial;
+  for (int i = threadIdx.x; i < n_partial; i += RT) s += pp[i];
   return block_sum_d(s, red);
 }
 

@@ -69,8 +69,22 @@ __global__ __launch_bounds__(RT) void response_kernel(
   }
 }
 
+// P_cdm(k_b) from the deposit's partial sums alone (for reading the spectrum before a
+// response): one workgroup per (bin, box).
+__global__ __launch_bounds__(RT) void bin_power_kernel(const double* __restrict__ partial,
+                                                      int n_partial,
+                                                      const double* __restrict__ counts,
+                                                      int nbins, double norm,
+                                                      double* __restrict__ pcdm_out) {
+  __shared__ double red[RT / 64];
+  const int b = blockIdx.x, box = blockIdx.y;
+  const double s = bin_mode_sum(partial, n_partial, nbins, box, b, red);
+  if (threadIdx.x == 0)
+    pcdm_out[static_cast<size_t>(box) * nbins + b] = counts[b] > 0.0 ? norm * s / counts[b] : 0.0;
+}
+
 __global__ __launch_bounds__(256) void rtable_kernel(const double* __restrict__ ratio,
-                                                     const double* __restrict__ kmean,
+                                                     const double* __restrict__ lnk,
                                                      const int* __restrict__ nonempty,
                                                      int n_nonempty,
                                                      const RespBox* __restrict__ boxes,
@@ -86,8 +100,8 @@ __global__ __launch_bounds__(256) void rtable_kernel(const double* __restrict__ 
     r = rb[nonempty[0]];
   } else {
     const double lk = log(kf * sqrt(static_cast<double>(n2)));
-    const double lo = log(kmean[nonempty[0]]);
-    const double hi = log(kmean[nonempty[n_nonempty - 1]]);
+    const double lo = lnk[nonempty[0]];
+    const double hi = lnk[nonempty[n_nonempty - 1]];
     if (lk <= lo) {
       r = rb[nonempty[0]];
     } else if (lk >= hi) {
@@ -96,9 +110,9 @@ __global__ __launch_bounds__(256) void rtable_kernel(const double* __restrict__ 
       int a = 0, z = n_nonempty - 1;   // log k of nonempty[a] <= lk < that of nonempty[z]
       while (z - a > 1) {
         const int mid = (a + z) >> 1;
-        if (log(kmean[nonempty[mid]]) <= lk) a = mid; else z = mid;
+        if (lnk[nonempty[mid]] <= lk) a = mid; else z = mid;
       }
-      const double la = log(kmean[nonempty[a]]), lz = log(kmean[nonempty[z]]);
+      const double la = lnk[nonempty[a]], lz = lnk[nonempty[z]];
       const double t = (lk - la) / (lz - la);
       r = rb[nonempty[a]] + t * (rb[nonempty[z]] - rb[nonempty[a]]);
     }
@@ -122,11 +136,18 @@ hipError_t launch_response(const RespBox* boxes, const double* partial, int n_pa
   return hipGetLastError();
 }
 
-hipError_t launch_rtable(const double* ratio, const double* kmean, const int* nonempty,
+hipError_t launch_bin_power(const double* partial, int n_partial, const double* counts,
+                            int nbins, double norm, int nbox, double* pcdm, hipStream_t s) {
+  hipLaunchKernelGGL(bin_power_kernel, dim3(nbins, nbox), dim3(RT), 0, s, partial, n_partial,
+                     counts, nbins, norm, pcdm);
+  return hipGetLastError();
+}
+
+hipError_t launch_rtable(const double* ratio, const double* lnk, const int* nonempty,
                          int n_nonempty, const RespBox* boxes, int nbins, int n2max, double kf,
                          int nbox, float* rtable, hipStream_t s) {
   dim3 grid((n2max + 1 + 255) / 256, nbox);
-  hipLaunchKernelGGL(rtable_kernel, grid, dim3(256), 0, s, ratio, kmean, nonempty, n_nonempty,
+  hipLaunchKernelGGL(rtable_kernel, grid, dim3(256), 0, s, ratio, lnk, nonempty, n_nonempty,
                      boxes, nbins, n2max, kf, rtable);
   return hipGetLastError();
 }

@@ -32,7 +32,10 @@ def build_training_set(n_rows, seed=4000, geometry=PM256, boxes_per_batch=16, j_
     nb = boxes_per_batch * g["n_kbins"]
     xb = torch.empty((nb, binding.SUR_IN), device="cuda")
     yb = torch.empty(nb, device="cuda")
-    xs, ys, have = [], [], 0
+    xs, ys, have, batches = [], [], 0, 0
+    import sys
+    import time
+    t0 = time.perf_counter()
     while have < n_rows:
         j = g["n_hist"] - 1 if rng.random() < p_last else int(rng.integers(j_min, g["n_hist"]))
         masses, hists, powers = surrogate_batch(kmean, nodes, j, boxes_per_batch, rng,
@@ -46,6 +49,10 @@ def build_training_set(n_rows, seed=4000, geometry=PM256, boxes_per_batch=16, j_
         xs.append(xb[keep].clone())
         ys.append(yb[keep].clone())
         have += int(keep.sum())
+        batches += 1
+        if batches % 200 == 0:
+            print(f"training set: {have} rows after {batches} batches, "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     ctx.close()
     return torch.cat(xs)[:n_rows].contiguous(), torch.cat(ys)[:n_rows].contiguous()
 

@@ -242,3 +242,21 @@ def test_every_launch_mode_matches_oracle(order):
         assert np.abs(sp["p_cdm"][ok] / ref["p_cdm"][ok] - 1).max() <= 2e-6, (order, dm, im)
         assert rms_rel(acc.cpu().numpy(), ref["acc"]) <= TOL_FORCE_RMS, (order, dm, im)
     ctx.close()
+
+
+def test_spectrum_after_deposit_alone_matches_oracle():
+    """The binned power is available right after pm_nu_deposit, before any response, in a
+    fresh context (it used to be produced only by the response)."""
+    import torch
+    from paper_1209_0461_amd import PMNu
+    import oracle.step as ostep
+    nm, box, nb = 32, 128.0, 24
+    pos = make_inputs(32, box, 0.3, 81)
+    ref = ostep.spectrum(pos, nm, box, nb)
+    ctx = PMNu(nm, len(pos), box, nb, 8, [0.3])
+    assert np.all(ctx.spectrum(0)["p_cdm"] == 0)          # nothing deposited yet
+    ctx.deposit(torch.from_numpy(pos).cuda())
+    got = ctx.spectrum(0)["p_cdm"]
+    ok = ref["counts"] > 0
+    assert np.abs(got[ok] / ref["p_cdm"][ok] - 1).max() <= 2e-6
+    ctx.close()
