@@ -170,9 +170,11 @@ int pm_nu_graph_launch(pm_nu_ctx* ctx);
  * as JSON keyed by (device name, N, n_boxes) (sync). */
 int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
                    const char* cache_path);
-/* Set the launch shapes directly: deposit_mode 0 (one thread per particle, global atomics)
- * or 1/2/3 (LDS-privatised chunks of 1024/2048/4096 particles), interp_mode 0 (direct
- * gather) or 1/2/3 (LDS-staged chunks), block sizes of the mode-0 kernels (64..1024). */
+/* Set the launch shapes directly: deposit_mode 0 (one thread per particle, global atomics;
+ * deposit_block = threads per workgroup) or 1/2/3 (LDS-privatised chunks of 1024/2048/4096
+ * particles), interp_mode 0 (direct gather; interp_block = particles per workgroup, rounded
+ * down to 256, 512 or 1024) or 1/2/3 (LDS-staged chunks). Blocks: multiples of 64 in
+ * 64..1024. */
 int pm_nu_set_launch(pm_nu_ctx* ctx, int deposit_mode, int deposit_block, int interp_mode,
                      int interp_block);
 /* Current launch-shape choice as a short JSON text (host buffer of cap bytes, sync). */

@@ -94,7 +94,7 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
   c->timer.enabled = false;
   struct DepCand { int mode, block; };
   const DepCand dep[] = {{0, 256}, {0, 512}, {1, 256}, {2, 256}, {3, 256}};
-  const DepCand itp[] = {{0, 128}, {0, 256}, {1, 256}, {2, 256}, {3, 256}};
+  const DepCand itp[] = {{0, 256}, {0, 512}, {0, 1024}, {1, 256}, {2, 256}, {3, 256}};
   hipEvent_t e0, e1;
   PMNU_HIP(hipEventCreate(&e0));
   PMNU_HIP(hipEventCreate(&e1));

@@ -39,7 +39,7 @@ template <int N> struct Shape {
   static constexpr int FZ_TY = N <= 32 ? N : (N <= 256 ? 32 : 16);   // real rows per WG
   static constexpr int FY_NL = N <= 256 ? (N < 16 ? N : 16) : 8;      // rows per WG
   static constexpr int FX_TX = N < 16 ? N : (N <= 256 ? 16 : 8);      // ky columns per WG
-  static constexpr int IX_TX = N < 16 ? N : (N <= 256 ? 16 : 8);
+  static constexpr int IX_TX = N < 16 ? N : 8;
   static constexpr int IY_NL = N < 8 ? N : (N <= 256 ? 8 : 4);
   static constexpr int IZ_TY = N < 16 ? N : (N <= 256 ? 16 : 8);
 };
@@ -130,18 +130,33 @@ __global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data
   load_twiddles<N, NT>(tw, twg);
   for (int b = threadIdx.x; b < nbins; b += NT) bins[b] = 0.0;
   float2* base = data + ((static_cast<size_t>(box) * NK + kz) * N) * N + y0;
-  for (int t = threadIdx.x; t < N * TX; t += NT) {
-    const int y = t % TX, x = t / TX;
-    lds[x * ES + y] = base[static_cast<size_t>(x) * N + y];
+  // float4 = two consecutive k_y; all loads in flight before the LDS stores
+  constexpr int P = TX / 2, IT = (N * P + NT - 1) / NT;
+  static_assert(TX % 2 == 0 && NT % P == 0, "k_y pairs");
+  const int py = 2 * (threadIdx.x % P);
+  float4 v[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int x = (threadIdx.x + i * NT) / P;
+    if (x < N) v[i] = *reinterpret_cast<const float4*>(base + static_cast<size_t>(x) * N + py);
+  }
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int x = (threadIdx.x + i * NT) / P;
+    if (x < N) {
+      lds[x * ES + py] = make_float2(v[i].x, v[i].y);
+      lds[x * ES + py + 1] = make_float2(v[i].z, v[i].w);
+    }
   }
   __syncthreads();
   fft_lines<N, TX, NT, -1>(lds, tw);
   const double w = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
   // store the tile back, then bin it: each thread walks a run of consecutive k_x at one
   // k_y, where |n|^2 changes slowly, and adds to the LDS bin only when the bin changes
-  for (int t = threadIdx.x; t < N * TX; t += NT) {
-    const int y = t % TX, x = t / TX;
-    base[static_cast<size_t>(x) * N + y] = lds[x * ES + y];
+  for (int t = threadIdx.x; t < N * P; t += NT) {
+    const int x = t / P, y = 2 * (t % P);
+    const float2 a = lds[x * ES + y], b = lds[x * ES + y + 1];
+    *reinterpret_cast<float4*>(base + static_cast<size_t>(x) * N + y) = make_float4(a.x, a.y, b.x, b.y);
   }
   constexpr int RUNS = NT / TX;                        // runs per k_y column
   constexpr int RUN = (N + RUNS - 1) / RUNS;           // k_x values per run
@@ -191,28 +206,48 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
   const size_t off = ((static_cast<size_t>(box) * NK + kz) * N) * N + y0;
   const float* rt = rtable + static_cast<size_t>(box) * (n2max + 1);
   const float wz = inv_w2[kz];
-  for (int t = threadIdx.x; t < N * TX; t += NT) {
-    const int y = t % TX, x = t / TX;
-    const float2 v = dk[off + static_cast<size_t>(x) * N + y];
-    const int nx = signed_index(x, N), ny = signed_index(y0 + y, N);
-    const int n2 = nx * nx + ny * ny + kz * kz;
-    float2 phi = make_float2(0.f, 0.f);
-    if (n2 > 0) {
-      // phi = -C T(n^2) delta / (k^2 W^2), k^2 = kf^2 n^2
-      const float g = -c * rt[n2] * inv_w2[x] * inv_w2[y0 + y] * wz /
-                      (kf * kf * static_cast<float>(n2));
-      phi = cscale(v, g);
-    }
-    lds[x * ES + y] = phi;
+  constexpr int P = TX / 2, IT = (N * P + NT - 1) / NT;
+  static_assert(TX % 2 == 0 && NT % P == 0, "k_y pairs");
+  const int py = 2 * (threadIdx.x % P);
+  float4 v[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int x = (threadIdx.x + i * NT) / P;
+    if (x < N) v[i] = *reinterpret_cast<const float4*>(dk + off + static_cast<size_t>(x) * N + py);
+  }
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int x = (threadIdx.x + i * NT) / P;
+    if (x >= N) break;
+    const int nx = signed_index(x, N);
     const float kx = (x == N / 2) ? 0.f : kf * static_cast<float>(nx);
-    lds[x * ES + TX + y] = make_float2(kx * phi.y, -kx * phi.x);     // -i k_x phi
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int y = py + h;
+      const float2 d = h ? make_float2(v[i].z, v[i].w) : make_float2(v[i].x, v[i].y);
+      const int ny = signed_index(y0 + y, N);
+      const int n2 = nx * nx + ny * ny + kz * kz;
+      float2 phi = make_float2(0.f, 0.f);
+      if (n2 > 0) {
+        // phi = -C T(n^2) delta / (k^2 W^2), k^2 = kf^2 n^2
+        const float g = -c * rt[n2] * inv_w2[x] * inv_w2[y0 + y] * wz /
+                        (kf * kf * static_cast<float>(n2));
+        phi = cscale(d, g);
+      }
+      lds[x * ES + y] = phi;
+      lds[x * ES + TX + y] = make_float2(kx * phi.y, -kx * phi.x);     // -i k_x phi
+    }
   }
   __syncthreads();
   fft_lines<N, NL, NT, +1>(lds, tw);
-  for (int t = threadIdx.x; t < N * TX; t += NT) {
-    const int y = t % TX, x = t / TX;
-    f1[off + static_cast<size_t>(x) * N + y] = lds[x * ES + y];
-    f2[off + static_cast<size_t>(x) * N + y] = lds[x * ES + TX + y];
+  for (int t = threadIdx.x; t < N * P; t += NT) {
+    const int x = t / P, y = 2 * (t % P);
+    const size_t o = off + static_cast<size_t>(x) * N + y;
+    float2 a = lds[x * ES + y], b = lds[x * ES + y + 1];
+    *reinterpret_cast<float4*>(f1 + o) = make_float4(a.x, a.y, b.x, b.y);
+    a = lds[x * ES + TX + y];
+    b = lds[x * ES + TX + y + 1];
+    *reinterpret_cast<float4*>(f2 + o) = make_float4(a.x, a.y, b.x, b.y);
   }
 }
 
@@ -274,31 +309,47 @@ __global__ __launch_bounds__(NT) void inv_z_kernel(const float2* __restrict__ g1
                                                    int nbox) {
   constexpr int TY = Shape<N>::IZ_TY, ROWS = 3 * TY, NL = ROWS / 2, ES = NL + 1;
   constexpr int NK = Shape<N>::NK;
+  static_assert(TY % 2 == 0 && NT % (TY / 2) == 0, "row pairs per float4");
+  // Loads: float4 = the values of one k at two consecutive y (a row pair), for the three
+  // fields; all issued before any LDS store so that many are in flight per thread.
+  constexpr int PAIRS = TY / 2, PER_COMP = NK * PAIRS, TOTAL = 3 * PER_COMP;
+  constexpr int IT = (TOTAL + NT - 1) / NT;
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
   const int y0 = blockIdx.x * TY, x = blockIdx.y, box = blockIdx.z;
   load_twiddles<N, NT>(tw, twg);
+  const size_t plane = ((static_cast<size_t>(box) * N + x) * NK) * N + y0;   // (k = 0, y0)
+  const int pr = threadIdx.x % PAIRS;                 // row pair within the field
+  float4 v[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int t = threadIdx.x + i * NT;
+    const int comp = t / PER_COMP, k = (t - comp * PER_COMP) / PAIRS;
+    const float2* src = comp == 0 ? g3 : (comp == 1 ? g2 : g1);
+    if (t < TOTAL)
+      v[i] = *reinterpret_cast<const float4*>(src + plane + static_cast<size_t>(k) * N + 2 * pr);
+  }
   float* ldsf = reinterpret_cast<float*>(lds);
   // Half spectra of row pair p: A[k] at slot k and B[k] at slot N-k for 0 < k < N/2;
   // the real parts of A and B at k = 0 and k = N/2 share slots 0 and N/2.
-  for (int t = threadIdx.x; t < NK * ROWS; t += NT) {
-    const int y = t % TY, k = (t / TY) % NK, comp = t / (TY * NK);
-    const size_t gi = ((static_cast<size_t>(box) * N + x) * NK + k) * N + y0 + y;
-    float2 v;
-    if (comp == 0) {
-      v = g3[gi];
-    } else if (comp == 1) {
-      v = g2[gi];
-    } else {
-      const float2 a = g1[gi];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int t = threadIdx.x + i * NT;
+    if (t >= TOTAL) break;
+    const int comp = t / PER_COMP, k = (t - comp * PER_COMP) / PAIRS;
+    float2 a = make_float2(v[i].x, v[i].y), b = make_float2(v[i].z, v[i].w);
+    if (comp == 2) {                                   // -i k_z G1
       const float kz = (k == N / 2) ? 0.f : kf * static_cast<float>(k);
-      v = make_float2(kz * a.y, -kz * a.x);                            // -i k_z G1
+      a = make_float2(kz * a.y, -kz * a.x);
+      b = make_float2(kz * b.y, -kz * b.x);
     }
-    const int row = comp * TY + y, p = row >> 1;
+    const int p = comp * PAIRS + pr;                   // rows 2p (A) and 2p + 1 (B)
     if (k == 0 || k == N / 2) {
-      ldsf[(k * ES + p) * 2 + (row & 1)] = v.x;
+      ldsf[(k * ES + p) * 2] = a.x;
+      ldsf[(k * ES + p) * 2 + 1] = b.x;
     } else {
-      lds[((row & 1) ? N - k : k) * ES + p] = v;
+      lds[k * ES + p] = a;
+      lds[(N - k) * ES + p] = b;
     }
   }
   __syncthreads();
@@ -310,20 +361,25 @@ __global__ __launch_bounds__(NT) void inv_z_kernel(const float2* __restrict__ g1
   }
   __syncthreads();
   fft_lines<N, NL, NT, +1>(lds, tw);
-  // interleaved output: (g_x, g_y, g_z) of node (x, y, z) are 3 consecutive floats, so the
-  // TY rows of this workgroup are one contiguous block of TY * N * 3 floats
+  // interleaved output: (g_x, g_y, g_z) of node (x, y, z) are 3 consecutive floats; a
+  // thread writes 4 consecutive nodes of one row as three float4
   float4* dst = reinterpret_cast<float4*>(out + ((static_cast<size_t>(box) * N + x) * N + y0) * N * 3);
-  for (int t4 = threadIdx.x; t4 < ROWS * N / 4; t4 += NT) {
-    float v[4];
+  constexpr int QUADS = TY * N / 4;
+  for (int q = threadIdx.x; q < QUADS; q += NT) {
+    const int y = q / (N / 4), z0 = 4 * (q % (N / 4));
+    float o[12];
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int t = 4 * t4 + h;
-      const int comp = t % 3, ye = t / 3, e = ye % N, y = ye / N;
-      const int row = comp * TY + y;
-      const float2 z = lds[e * ES + (row >> 1)];
-      v[h] = (row & 1) ? z.y : z.x;
+    for (int comp = 0; comp < 3; ++comp) {
+      const int row = comp * TY + y, p = row >> 1;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const float2 zz = lds[(z0 + h) * ES + p];
+        o[3 * h + comp] = (row & 1) ? zz.y : zz.x;
+      }
     }
-    dst[t4] = make_float4(v[0], v[1], v[2], v[3]);
+    dst[3 * q] = make_float4(o[0], o[1], o[2], o[3]);
+    dst[3 * q + 1] = make_float4(o[4], o[5], o[6], o[7]);
+    dst[3 * q + 2] = make_float4(o[8], o[9], o[10], o[11]);
   }
 }
 

@@ -26,34 +26,24 @@
 namespace pmnu {
 namespace {
 
-struct Corner {
-  int lo[3], hi[3];
-  float w[3][2];
-};
-
-
-__device__ __forceinline__ void cic_axis64(float x, double inv_cell, int nmask, int& lo,
-                                           int& hi, double& w0, double& w1) {
+// Per axis: lower node (mod N) and the fraction beyond it, in FP64 (u = x N / L is exact
+// for an FP32 coordinate times an FP64 inverse cell size up to the product's rounding).
+__device__ __forceinline__ void axis64(float x, double inv_cell, int nmask, int& i, double& d) {
   const double u = static_cast<double>(x) * inv_cell;
   const double f = floor(u);
-  const double d = u - f;
-  const int i = static_cast<int>(static_cast<long long>(f) & nmask);
-  lo = i;
-  hi = (i + 1) & nmask;
-  w0 = 1.0 - d;
-  w1 = d;
+  d = u - f;
+  i = static_cast<int>(static_cast<long long>(f) & nmask);
 }
 
-__device__ __forceinline__ void cic_axis(float x, double inv_cell, int nmask, int& lo,
-                                         int& hi, float& w0, float& w1) {
-  const double u = static_cast<double>(x) * inv_cell;
-  const double f = floor(u);
-  const float d = static_cast<float>(u - f);
-  const int i = static_cast<int>(static_cast<long long>(f) & nmask);
-  lo = i;
-  hi = (i + 1) & nmask;
-  w0 = 1.0f - d;
-  w1 = d;
+// Round-to-nearest-even of 0 <= v < 2^52 as an integer: adding 2^52 leaves the rounded
+// value in the low mantissa bits (same result as __double2ll_rn, far fewer instructions).
+__device__ __forceinline__ unsigned long long fix_rn(double v) {
+  return static_cast<unsigned long long>(__double_as_longlong(v + 4503599627370496.0)) -
+         0x4330000000000000ull;
+}
+
+__device__ __forceinline__ bool finite3(float x, float y, float z) {
+  return isfinite(x) && isfinite(y) && isfinite(z);
 }
 
 __global__ void fill_zero_kernel(float4* __restrict__ p, int64_t n4) {
@@ -68,41 +58,50 @@ __global__ void fill_zero_tail_kernel(float* __restrict__ p, int64_t start, int6
   if (i < n) p[i] = 0.f;
 }
 
+// The eight fixed-point contributions of one particle, added straight to HBM.
+__device__ __forceinline__ void deposit_global(unsigned long long* g, int n, const int (&i)[3],
+                                               const double (&d)[3], int nmask) {
+  const double wx[2] = {(1.0 - d[0]) * kFixScale, d[0] * kFixScale};
+  const double wy[2] = {1.0 - d[1], d[1]};
+  const int iz0 = i[2], iz1 = (i[2] + 1) & nmask;
+#pragma unroll
+  for (int cx = 0; cx < 2; ++cx) {
+    const int ix = (i[0] + cx) & nmask;
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy) {
+      const int iy = (i[1] + cy) & nmask;
+      const double wxy = wx[cx] * wy[cy];
+      const unsigned row = (static_cast<unsigned>(ix) * n + iy) * n;
+      atomicAdd(g + row + iz0, fix_rn(wxy * (1.0 - d[2])));
+      atomicAdd(g + row + iz1, fix_rn(wxy * d[2]));
+    }
+  }
+}
+
 __global__ __launch_bounds__(1024) void deposit_kernel(const float* __restrict__ pos,
-                                                       unsigned long long* __restrict__ rho,
-                                                       int64_t np,
-                                                       int nbox, int n, double inv_cell,
-                                                       int* __restrict__ flags) {
+                                                      unsigned long long* __restrict__ rho,
+                                                      int64_t np, int nbox, int n,
+                                                      double inv_cell, int* __restrict__ flags) {
   const int64_t total = np * nbox;
   const int64_t m = static_cast<int64_t>(n) * n * n;
   const int nmask = n - 1;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
-       i += stride) {
-    const float x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
-    if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
-      atomicOr(flags, 1);
+  bool bad = false;
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < total;
+       k += stride) {
+    const float x = pos[3 * k], y = pos[3 * k + 1], z = pos[3 * k + 2];
+    if (!finite3(x, y, z)) {
+      bad = true;
       continue;
     }
-    int lo[3], hi[3];
-    double w[3][2];
-    cic_axis64(x, inv_cell, nmask, lo[0], hi[0], w[0][0], w[0][1]);
-    cic_axis64(y, inv_cell, nmask, lo[1], hi[1], w[1][0], w[1][1]);
-    cic_axis64(z, inv_cell, nmask, lo[2], hi[2], w[2][0], w[2][1]);
-    unsigned long long* g = rho + (i / np) * m;
-#pragma unroll
-    for (int cx = 0; cx < 2; ++cx) {
-      const int ix = cx ? hi[0] : lo[0];
-#pragma unroll
-      for (int cy = 0; cy < 2; ++cy) {
-        const int iy = cy ? hi[1] : lo[1];
-        const double wxy = w[0][cx] * w[1][cy] * kFixScale;
-        const int64_t row = (static_cast<int64_t>(ix) * n + iy) * n;
-        atomicAdd(g + row + lo[2], static_cast<unsigned long long>(__double2ll_rn(wxy * w[2][0])));
-        atomicAdd(g + row + hi[2], static_cast<unsigned long long>(__double2ll_rn(wxy * w[2][1])));
-      }
-    }
+    int i[3];
+    double d[3];
+    axis64(x, inv_cell, nmask, i[0], d[0]);
+    axis64(y, inv_cell, nmask, i[1], d[1]);
+    axis64(z, inv_cell, nmask, i[2], d[2]);
+    deposit_global(rho + (k / np) * m, n, i, d, nmask);
   }
+  if (bad) atomicOr(flags, 1);
 }
 
 __device__ __forceinline__ int wave_min(int v) {
@@ -116,310 +115,349 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-__device__ __forceinline__ int cell_of(float x, double inv_cell, int nmask) {
-  return static_cast<int>(static_cast<long long>(floor(static_cast<double>(x) * inv_cell)) & nmask);
+// Chunk of PPT * 256 consecutive particles held in registers (lower node and fraction per
+// axis) and the periodic bounding box of their lower nodes relative to the first particle's
+// node. Every thread computes the same reference node, so no barrier is needed for it.
+template <int PPT>
+struct Chunk {
+  int i[PPT][3];
+  double d[PPT][3];
+  bool ok[PPT];
+  int r[3];
+  int mn[3], ext[3];   // box origin (relative to r) and extent in nodes, upper neighbours included
+  bool any;
+};
+
+template <int PPT>
+__device__ __forceinline__ void load_chunk(Chunk<PPT>& c, const float* p, int cnt, double inv_cell,
+                                           int nmask, int (*red)[4], bool& bad) {
+  constexpr int NT = 256;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, half = (nmask + 1) / 2;
+  {
+    const float x = p[0], y = p[1], z = p[2];
+    const bool ok0 = finite3(x, y, z);
+    double dd;
+    axis64(ok0 ? x : 0.f, inv_cell, nmask, c.r[0], dd);
+    axis64(ok0 ? y : 0.f, inv_cell, nmask, c.r[1], dd);
+    axis64(ok0 ? z : 0.f, inv_cell, nmask, c.r[2], dd);
+  }
+  int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int j = tid + q * NT;
+    float x = 0.f, y = 0.f, z = 0.f;
+    if (j < cnt) {
+      x = p[3 * j];
+      y = p[3 * j + 1];
+      z = p[3 * j + 2];
+    }
+    c.ok[q] = j < cnt && finite3(x, y, z);
+    bad |= (j < cnt) && !c.ok[q];
+    axis64(c.ok[q] ? x : 0.f, inv_cell, nmask, c.i[q][0], c.d[q][0]);
+    axis64(c.ok[q] ? y : 0.f, inv_cell, nmask, c.i[q][1], c.d[q][1]);
+    axis64(c.ok[q] ? z : 0.f, inv_cell, nmask, c.i[q][2], c.d[q][2]);
+    if (c.ok[q]) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int rel = ((c.i[q][a] - c.r[a] + half) & nmask) - half;
+        mn[a] = min(mn[a], rel);
+        mx[a] = max(mx[a], rel);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    mn[a] = wave_min(mn[a]);
+    mx[a] = wave_max(mx[a]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      red[a][wv] = mn[a];
+      red[3 + a][wv] = mx[a];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+      mn[a] = min(mn[a], red[a][w]);
+      mx[a] = max(mx[a], red[3 + a][w]);
+    }
+  }
+  c.any = mn[0] <= mx[0];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    c.mn[a] = mn[a];
+    c.ext[a] = c.any ? mx[a] - mn[a] + 2 : 0;
+  }
 }
 
-// 8 global atomics for one particle
-__device__ __forceinline__ void deposit_global(unsigned long long* g, float x, float y, float z,
-                                               int n, double inv_cell, int nmask) {
-  int lo[3], hi[3];
-  double w[3][2];
-  cic_axis64(x, inv_cell, nmask, lo[0], hi[0], w[0][0], w[0][1]);
-  cic_axis64(y, inv_cell, nmask, lo[1], hi[1], w[1][0], w[1][1]);
-  cic_axis64(z, inv_cell, nmask, lo[2], hi[2], w[2][0], w[2][1]);
-#pragma unroll
-  for (int cx = 0; cx < 2; ++cx) {
-    const int ix = cx ? hi[0] : lo[0];
-#pragma unroll
-    for (int cy = 0; cy < 2; ++cy) {
-      const int iy = cy ? hi[1] : lo[1];
-      const double wxy = w[0][cx] * w[1][cy] * kFixScale;
-      const int64_t row = (static_cast<int64_t>(ix) * n + iy) * n;
-      atomicAdd(g + row + lo[2], static_cast<unsigned long long>(__double2ll_rn(wxy * w[2][0])));
-      atomicAdd(g + row + hi[2], static_cast<unsigned long long>(__double2ll_rn(wxy * w[2][1])));
+// Walks the rows (tx, ty) of an ex x ey x ez box with the lanes of a wave spread over
+// (row, z): lane l takes z = l mod ez of row l / ez, so short rows keep the wave busy
+// without a division per node. Calls f(tx, ty, tz, linear index).
+template <typename F>
+__device__ __forceinline__ void for_box_nodes(int ex, int ey, int ez, F f) {
+  constexpr int NW = 256 / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (ez <= 64) {
+    const int rpi = 64 / ez, dr = lane / ez, tz = lane - dr * ez;
+    if (dr >= rpi) return;
+    const int step = NW * rpi;
+    int r = wv * rpi + dr;
+    int tx = r / ey, ty = r - tx * ey;
+    while (tx < ex) {
+      f(tx, ty, tz, r * ez + tz);
+      r += step;
+      ty += step;
+      while (ty >= ey) {
+        ty -= ey;
+        ++tx;
+      }
+    }
+  } else {
+    for (int r = wv; r < ex * ey; r += NW) {
+      const int tx = r / ey, ty = r - tx * ey;
+      for (int tz = lane; tz < ez; tz += 64) f(tx, ty, tz, r * ez + tz);
     }
   }
 }
 
+// Deposit with the accumulation privatised in LDS: a workgroup takes CH consecutive
+// particles; if their box (upper neighbours included) fits in CAP nodes, it sums the
+// chunk's fixed-point weights there with 64-bit LDS atomics and adds every non-zero node
+// to HBM with one global atomic. Chunks that are not spatially compact (particles in
+// arbitrary order) take the per-particle global-atomic path, so the result does not depend
+// on the order; the speed does. Particles kept along a space-filling curve (as tree codes
+// keep them) give compact chunks.
 template <int CH, int CAP>
 __global__ __launch_bounds__(256) void deposit_tiled_kernel(const float* __restrict__ pos,
                                                             unsigned long long* __restrict__ rho,
                                                             int64_t np, int n, double inv_cell,
                                                             int* __restrict__ flags,
                                                             int64_t chunks_per_box) {
-  constexpr int NT = 256, NW = NT / 64;
+  constexpr int NT = 256, PPT = CH / NT;
   __shared__ unsigned long long tile[CAP];
-  __shared__ int red[6][NW];
-  __shared__ int ref_s[3];
+  __shared__ int red[6][4];
   const int tid = threadIdx.x;
   const int64_t box = blockIdx.x / chunks_per_box;
   const int64_t c0 = (blockIdx.x - box * chunks_per_box) * CH;
   const int cnt = static_cast<int>(min(static_cast<int64_t>(CH), np - c0));
-  const float* p = pos + (box * np + c0) * 3;
-  const int nmask = n - 1, half = n / 2;
+  const int nmask = n - 1;
   unsigned long long* g = rho + box * static_cast<int64_t>(n) * n * n;
-  if (tid == 0) {
-    const float x = p[0], y = p[1], z = p[2];
-    const bool ok = isfinite(x) && isfinite(y) && isfinite(z);
-    ref_s[0] = ok ? cell_of(x, inv_cell, nmask) : 0;
-    ref_s[1] = ok ? cell_of(y, inv_cell, nmask) : 0;
-    ref_s[2] = ok ? cell_of(z, inv_cell, nmask) : 0;
-  }
-  __syncthreads();
-  const int r0 = ref_s[0], r1 = ref_s[1], r2 = ref_s[2];
-  int mn0 = 1 << 30, mn1 = 1 << 30, mn2 = 1 << 30, mx0 = -(1 << 30), mx1 = -(1 << 30),
-      mx2 = -(1 << 30);
+  Chunk<PPT> c;
   bool bad = false;
-  for (int j = tid; j < cnt; j += NT) {
-    const float x = p[3 * j], y = p[3 * j + 1], z = p[3 * j + 2];
-    if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
-      bad = true;
-      continue;
-    }
-    const int a = ((cell_of(x, inv_cell, nmask) - r0 + half) & nmask) - half;
-    const int b = ((cell_of(y, inv_cell, nmask) - r1 + half) & nmask) - half;
-    const int c = ((cell_of(z, inv_cell, nmask) - r2 + half) & nmask) - half;
-    mn0 = min(mn0, a); mx0 = max(mx0, a);
-    mn1 = min(mn1, b); mx1 = max(mx1, b);
-    mn2 = min(mn2, c); mx2 = max(mx2, c);
-  }
+  load_chunk<PPT>(c, pos + (box * np + c0) * 3, cnt, inv_cell, nmask, red, bad);
   if (bad) atomicOr(flags, 1);
-  mn0 = wave_min(mn0); mn1 = wave_min(mn1); mn2 = wave_min(mn2);
-  mx0 = wave_max(mx0); mx1 = wave_max(mx1); mx2 = wave_max(mx2);
-  const int lane = tid & 63, wv = tid >> 6;
-  if (lane == 0) {
-    red[0][wv] = mn0; red[1][wv] = mn1; red[2][wv] = mn2;
-    red[3][wv] = mx0; red[4][wv] = mx1; red[5][wv] = mx2;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    mn0 = min(mn0, red[0][w]); mn1 = min(mn1, red[1][w]); mn2 = min(mn2, red[2][w]);
-    mx0 = max(mx0, red[3][w]); mx1 = max(mx1, red[4][w]); mx2 = max(mx2, red[5][w]);
-  }
-  if (mn0 > mx0) return;   // no finite particle in the chunk
-  const int ex = mx0 - mn0 + 2, ey = mx1 - mn1 + 2, ez = mx2 - mn2 + 2;
-  const int64_t vol = static_cast<int64_t>(ex) * ey * ez;
-  if (vol <= CAP) {
+  const int ex = c.ext[0], ey = c.ext[1], ez = c.ext[2];
+  const int vol = ex * ey * ez;
+  if (c.any && vol <= CAP && ex <= n && ey <= n && ez <= n) {
     for (int t = tid; t < vol; t += NT) tile[t] = 0ull;
     __syncthreads();
-    for (int j = tid; j < cnt; j += NT) {
-      const float x = p[3 * j], y = p[3 * j + 1], z = p[3 * j + 2];
-      if (!(isfinite(x) && isfinite(y) && isfinite(z))) continue;
-      int lo[3], hi[3];
-      double w[3][2];
-      cic_axis64(x, inv_cell, nmask, lo[0], hi[0], w[0][0], w[0][1]);
-      cic_axis64(y, inv_cell, nmask, lo[1], hi[1], w[1][0], w[1][1]);
-      cic_axis64(z, inv_cell, nmask, lo[2], hi[2], w[2][0], w[2][1]);
-      const int a = ((lo[0] - r0 + half) & nmask) - half - mn0;
-      const int b = ((lo[1] - r1 + half) & nmask) - half - mn1;
-      const int c = ((lo[2] - r2 + half) & nmask) - half - mn2;
+    const int half = n / 2;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      if (!c.ok[q]) continue;
+      int t[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) t[a] = ((c.i[q][a] - c.r[a] + half) & nmask) - half - c.mn[a];
+      const double wx[2] = {(1.0 - c.d[q][0]) * kFixScale, c.d[q][0] * kFixScale};
+      const double wy[2] = {1.0 - c.d[q][1], c.d[q][1]};
+      const double wz0 = 1.0 - c.d[q][2], wz1 = c.d[q][2];
+      const int base = (t[0] * ey + t[1]) * ez + t[2];
 #pragma unroll
       for (int cx = 0; cx < 2; ++cx) {
 #pragma unroll
         for (int cy = 0; cy < 2; ++cy) {
-          const double wxy = w[0][cx] * w[1][cy] * kFixScale;
-          const int base = ((a + cx) * ey + (b + cy)) * ez + c;
-          atomicAdd(&tile[base], static_cast<unsigned long long>(__double2ll_rn(wxy * w[2][0])));
-          atomicAdd(&tile[base + 1],
-                    static_cast<unsigned long long>(__double2ll_rn(wxy * w[2][1])));
+          const double wxy = wx[cx] * wy[cy];
+          const int o = base + (cx * ey + cy) * ez;
+          atomicAdd(&tile[o], fix_rn(wxy * wz0));
+          atomicAdd(&tile[o + 1], fix_rn(wxy * wz1));
         }
       }
     }
     __syncthreads();
-    const int gx0 = r0 + mn0, gy0 = r1 + mn1, gz0 = r2 + mn2;
-    for (int t = tid; t < vol; t += NT) {
-      const unsigned long long v = tile[t];
-      if (v == 0ull) continue;
-      const int tz = t % ez, txy = t / ez, ty = txy % ey, tx = txy / ey;
-      const int gx = (gx0 + tx) & nmask, gy = (gy0 + ty) & nmask, gz = (gz0 + tz) & nmask;
-      atomicAdd(g + (static_cast<int64_t>(gx) * n + gy) * n + gz, v);
-    }
+    const int gx0 = c.r[0] + c.mn[0], gy0 = c.r[1] + c.mn[1], gz0 = c.r[2] + c.mn[2];
+    for_box_nodes(ex, ey, ez, [&](int tx, int ty, int tz, int li) {
+      const unsigned long long v = tile[li];
+      if (v == 0ull) return;
+      const unsigned gx = (gx0 + tx) & nmask, gy = (gy0 + ty) & nmask, gz = (gz0 + tz) & nmask;
+      atomicAdd(g + (gx * n + gy) * n + gz, v);
+    });
   } else {
-    for (int j = tid; j < cnt; j += NT) {
-      const float x = p[3 * j], y = p[3 * j + 1], z = p[3 * j + 2];
-      if (!(isfinite(x) && isfinite(y) && isfinite(z))) continue;
-      deposit_global(g, x, y, z, n, inv_cell, nmask);
-    }
+#pragma unroll
+    for (int q = 0; q < PPT; ++q)
+      if (c.ok[q]) deposit_global(g, n, c.i[q], c.d[q], nmask);
   }
 }
 
-__global__ __launch_bounds__(1024) void interp_kernel(const float* __restrict__ pos,
-                                                      const float* __restrict__ force,
-                                                      float* __restrict__ acc, int64_t np,
-                                                      int nbox, int n, double inv_cell) {
-  const int64_t total = np * nbox;
-  const int64_t m = static_cast<int64_t>(n) * n * n;
-  const int nmask = n - 1;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
-       i += stride) {
-    const float x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-    if (isfinite(x) && isfinite(y) && isfinite(z)) {
-      Corner c;
-      cic_axis(x, inv_cell, nmask, c.lo[0], c.hi[0], c.w[0][0], c.w[0][1]);
-      cic_axis(y, inv_cell, nmask, c.lo[1], c.hi[1], c.w[1][0], c.w[1][1]);
-      cic_axis(z, inv_cell, nmask, c.lo[2], c.hi[2], c.w[2][0], c.w[2][1]);
-      const float* g = force + (i / np) * m * 3;   // [x][y][z][3] per box
+// FP32 corner weights of one particle (the fraction rounded once to FP32).
+struct Corner {
+  int i[3];
+  float w[3][2];
+};
+
+__device__ __forceinline__ void corner_of(float x, float y, float z, double inv_cell, int nmask,
+                                          Corner& c) {
+  double d;
+  axis64(x, inv_cell, nmask, c.i[0], d);
+  c.w[0][1] = static_cast<float>(d);
+  c.w[0][0] = 1.0f - c.w[0][1];
+  axis64(y, inv_cell, nmask, c.i[1], d);
+  c.w[1][1] = static_cast<float>(d);
+  c.w[1][0] = 1.0f - c.w[1][1];
+  axis64(z, inv_cell, nmask, c.i[2], d);
+  c.w[2][1] = static_cast<float>(d);
+  c.w[2][0] = 1.0f - c.w[2][1];
+}
+
+// Gather of the interleaved acceleration grid ([x][y][z][3] per box) at the 8 corners.
+__device__ __forceinline__ void gather_global(const float* g, int n, int nmask, const Corner& c,
+                                              float& a0, float& a1, float& a2) {
+  const int iz0 = c.i[2], iz1 = (c.i[2] + 1) & nmask;
 #pragma unroll
-      for (int cx = 0; cx < 2; ++cx) {
-        const int ix = cx ? c.hi[0] : c.lo[0];
+  for (int cx = 0; cx < 2; ++cx) {
+    const int ix = (c.i[0] + cx) & nmask;
 #pragma unroll
-        for (int cy = 0; cy < 2; ++cy) {
-          const int iy = cy ? c.hi[1] : c.lo[1];
-          const float wxy = c.w[0][cx] * c.w[1][cy];
-          const int64_t row = (static_cast<int64_t>(ix) * n + iy) * n;
+    for (int cy = 0; cy < 2; ++cy) {
+      const int iy = (c.i[1] + cy) & nmask;
+      const float wxy = c.w[0][cx] * c.w[1][cy];
+      const unsigned row = (static_cast<unsigned>(ix) * n + iy) * n;
 #pragma unroll
-          for (int cz = 0; cz < 2; ++cz) {
-            const float* v = g + 3 * (row + (cz ? c.hi[2] : c.lo[2]));
-            const float w = wxy * c.w[2][cz];
-            a0 += w * v[0];
-            a1 += w * v[1];
-            a2 += w * v[2];
-          }
-        }
+      for (int cz = 0; cz < 2; ++cz) {
+        const float* v = g + 3 * (row + (cz ? iz1 : iz0));
+        const float w = wxy * c.w[2][cz];
+        a0 += w * v[0];
+        a1 += w * v[1];
+        a2 += w * v[2];
       }
     }
-    acc[3 * i] = a0;
-    acc[3 * i + 1] = a1;
-    acc[3 * i + 2] = a2;
   }
 }
 
-// Interpolation with the chunk's bounding-box tile of the acceleration grid staged in LDS
-// (rows of 3*ez consecutive floats, coalesced), PPT = CH / 256 particles per thread kept
-// in registers; chunks whose box does not fit gather straight from HBM.
+// Workgroups are handed to the XCDs in turn; remapping the block index gives each XCD one
+// contiguous run of chunks, so neighbouring chunks (which share grid lines) hit the same L2.
+__device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t nblocks) {
+  constexpr int kXcd = 8;
+  const int64_t per = (nblocks + kXcd - 1) / kXcd;
+  return (b % kXcd) * per + b / kXcd;
+}
+
+// Direct interpolation: PPT particles per thread (strided by the block size inside a
+// contiguous chunk), gathering from HBM through the caches.
+template <int PPT>
+__global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ pos,
+                                                     const float* __restrict__ force,
+                                                     float* __restrict__ acc, int64_t np, int n,
+                                                     double inv_cell, int64_t chunks_per_box,
+                                                     int64_t nchunks) {
+  constexpr int NT = 256, CH = NT * PPT;
+  const int64_t chunk = xcd_chunk(blockIdx.x, gridDim.x);
+  if (chunk >= nchunks) return;
+  const int64_t box = chunk / chunks_per_box;
+  const int64_t c0 = (chunk - box * chunks_per_box) * CH;
+  const int cnt = static_cast<int>(min(static_cast<int64_t>(CH), np - c0));
+  const float* p = pos + (box * np + c0) * 3;
+  float* out = acc + (box * np + c0) * 3;
+  const float* g = force + box * static_cast<int64_t>(n) * n * n * 3;
+  const int nmask = n - 1;
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int j = threadIdx.x + q * NT;
+    if (j >= cnt) break;
+    const float x = p[3 * j], y = p[3 * j + 1], z = p[3 * j + 2];
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    if (finite3(x, y, z)) {
+      Corner c;
+      corner_of(x, y, z, inv_cell, nmask, c);
+      gather_global(g, n, nmask, c, a0, a1, a2);
+    }
+    out[3 * j] = a0;
+    out[3 * j + 1] = a1;
+    out[3 * j + 2] = a2;
+  }
+}
+
+// Interpolation with the chunk's box of the acceleration grid staged in LDS (rows of
+// 3 * ez consecutive floats); chunks whose box does not fit gather straight from HBM.
 template <int CH, int CAP>
 __global__ __launch_bounds__(256) void interp_tiled_kernel(const float* __restrict__ pos,
                                                            const float* __restrict__ force,
                                                            float* __restrict__ acc, int64_t np,
                                                            int n, double inv_cell,
-                                                           int64_t chunks_per_box) {
-  constexpr int NT = 256, NW = NT / 64, PPT = CH / NT;
+                                                           int64_t chunks_per_box,
+                                                           int64_t nchunks) {
+  constexpr int NT = 256, PPT = CH / NT;
   __shared__ float tile[CAP * 3];
-  __shared__ int red[6][NW];
-  __shared__ int ref_s[3];
+  __shared__ int red[6][4];
   const int tid = threadIdx.x;
-  const int64_t box = blockIdx.x / chunks_per_box;
-  const int64_t c0 = (blockIdx.x - box * chunks_per_box) * CH;
+  const int64_t chunk = xcd_chunk(blockIdx.x, gridDim.x);
+  if (chunk >= nchunks) return;
+  const int64_t box = chunk / chunks_per_box;
+  const int64_t c0 = (chunk - box * chunks_per_box) * CH;
   const int cnt = static_cast<int>(min(static_cast<int64_t>(CH), np - c0));
-  const float* p = pos + (box * np + c0) * 3;
-  float* a_out = acc + (box * np + c0) * 3;
-  const int nmask = n - 1, half = n / 2;
+  float* out = acc + (box * np + c0) * 3;
+  const int nmask = n - 1;
   const float* g = force + box * static_cast<int64_t>(n) * n * n * 3;
-  float px[PPT], py[PPT], pz[PPT];
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    const int j = tid + q * NT;
-    if (j < cnt) {
-      px[q] = p[3 * j];
-      py[q] = p[3 * j + 1];
-      pz[q] = p[3 * j + 2];
-    } else {
-      px[q] = py[q] = pz[q] = __builtin_nanf("");
-    }
-  }
-  if (tid == 0) {
-    const bool ok = isfinite(px[0]) && isfinite(py[0]) && isfinite(pz[0]);
-    ref_s[0] = ok ? cell_of(px[0], inv_cell, nmask) : 0;
-    ref_s[1] = ok ? cell_of(py[0], inv_cell, nmask) : 0;
-    ref_s[2] = ok ? cell_of(pz[0], inv_cell, nmask) : 0;
-  }
-  __syncthreads();
-  const int r0 = ref_s[0], r1 = ref_s[1], r2 = ref_s[2];
-  int mn0 = 1 << 30, mn1 = 1 << 30, mn2 = 1 << 30, mx0 = -(1 << 30), mx1 = -(1 << 30),
-      mx2 = -(1 << 30);
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    if (!(isfinite(px[q]) && isfinite(py[q]) && isfinite(pz[q]))) continue;
-    const int a = ((cell_of(px[q], inv_cell, nmask) - r0 + half) & nmask) - half;
-    const int b = ((cell_of(py[q], inv_cell, nmask) - r1 + half) & nmask) - half;
-    const int c = ((cell_of(pz[q], inv_cell, nmask) - r2 + half) & nmask) - half;
-    mn0 = min(mn0, a); mx0 = max(mx0, a);
-    mn1 = min(mn1, b); mx1 = max(mx1, b);
-    mn2 = min(mn2, c); mx2 = max(mx2, c);
-  }
-  mn0 = wave_min(mn0); mn1 = wave_min(mn1); mn2 = wave_min(mn2);
-  mx0 = wave_max(mx0); mx1 = wave_max(mx1); mx2 = wave_max(mx2);
-  const int lane = tid & 63, wv = tid >> 6;
-  if (lane == 0) {
-    red[0][wv] = mn0; red[1][wv] = mn1; red[2][wv] = mn2;
-    red[3][wv] = mx0; red[4][wv] = mx1; red[5][wv] = mx2;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    mn0 = min(mn0, red[0][w]); mn1 = min(mn1, red[1][w]); mn2 = min(mn2, red[2][w]);
-    mx0 = max(mx0, red[3][w]); mx1 = max(mx1, red[4][w]); mx2 = max(mx2, red[5][w]);
-  }
-  const bool any = mn0 <= mx0;
-  const int ex = any ? mx0 - mn0 + 2 : 0, ey = any ? mx1 - mn1 + 2 : 0,
-            ez = any ? mx2 - mn2 + 2 : 0;
-  const int64_t vol = static_cast<int64_t>(ex) * ey * ez;
-  const bool use_tile = any && vol <= CAP;
+  Chunk<PPT> c;
+  bool bad = false;
+  load_chunk<PPT>(c, pos + (box * np + c0) * 3, cnt, inv_cell, nmask, red, bad);
+  const int ex = c.ext[0], ey = c.ext[1], ez = c.ext[2];
+  const int vol = ex * ey * ez;
+  const bool use_tile = c.any && vol <= CAP && ex <= n && ey <= n && ez <= n;
   if (use_tile) {
-    const int gx0 = r0 + mn0, gy0 = r1 + mn1, gz0 = r2 + mn2;
-    const int row3 = 3 * ez;
-    for (int t = tid; t < vol * 3; t += NT) {
-      const int row = t / row3, w = t - row * row3;
-      const int tz = w / 3, comp = w - tz * 3;
-      const int ty = row % ey, tx = row / ey;
-      const int gx = (gx0 + tx) & nmask, gy = (gy0 + ty) & nmask, gz = (gz0 + tz) & nmask;
-      tile[t] = g[((static_cast<int64_t>(gx) * n + gy) * n + gz) * 3 + comp];
-    }
+    const int gx0 = c.r[0] + c.mn[0], gy0 = c.r[1] + c.mn[1], gz0 = c.r[2] + c.mn[2];
+    for_box_nodes(ex, ey, ez, [&](int tx, int ty, int tz, int li) {
+      const unsigned gx = (gx0 + tx) & nmask, gy = (gy0 + ty) & nmask, gz = (gz0 + tz) & nmask;
+      const float* v = g + 3 * ((gx * n + gy) * n + gz);
+      tile[3 * li] = v[0];
+      tile[3 * li + 1] = v[1];
+      tile[3 * li + 2] = v[2];
+    });
     __syncthreads();
   }
+  const int half = n / 2;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     const int j = tid + q * NT;
     if (j >= cnt) continue;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-    if (isfinite(px[q]) && isfinite(py[q]) && isfinite(pz[q])) {
-      Corner c;
-      cic_axis(px[q], inv_cell, nmask, c.lo[0], c.hi[0], c.w[0][0], c.w[0][1]);
-      cic_axis(py[q], inv_cell, nmask, c.lo[1], c.hi[1], c.w[1][0], c.w[1][1]);
-      cic_axis(pz[q], inv_cell, nmask, c.lo[2], c.hi[2], c.w[2][0], c.w[2][1]);
+    if (c.ok[q]) {
+      Corner k;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        k.i[a] = c.i[q][a];
+        k.w[a][1] = static_cast<float>(c.d[q][a]);
+        k.w[a][0] = 1.0f - k.w[a][1];
+      }
       if (use_tile) {
-        const int ta = ((c.lo[0] - r0 + half) & nmask) - half - mn0;
-        const int tb = ((c.lo[1] - r1 + half) & nmask) - half - mn1;
-        const int tc = ((c.lo[2] - r2 + half) & nmask) - half - mn2;
+        int t[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) t[a] = ((k.i[a] - c.r[a] + half) & nmask) - half - c.mn[a];
+        const int base = (t[0] * ey + t[1]) * ez + t[2];
 #pragma unroll
         for (int cx = 0; cx < 2; ++cx) {
 #pragma unroll
           for (int cy = 0; cy < 2; ++cy) {
-            const float wxy = c.w[0][cx] * c.w[1][cy];
-            const float* v = tile + 3 * (((ta + cx) * ey + (tb + cy)) * ez + tc);
-            a0 += wxy * (c.w[2][0] * v[0] + c.w[2][1] * v[3]);
-            a1 += wxy * (c.w[2][0] * v[1] + c.w[2][1] * v[4]);
-            a2 += wxy * (c.w[2][0] * v[2] + c.w[2][1] * v[5]);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int cx = 0; cx < 2; ++cx) {
-          const int ix = cx ? c.hi[0] : c.lo[0];
-#pragma unroll
-          for (int cy = 0; cy < 2; ++cy) {
-            const int iy = cy ? c.hi[1] : c.lo[1];
-            const float wxy = c.w[0][cx] * c.w[1][cy];
-            const int64_t row = (static_cast<int64_t>(ix) * n + iy) * n;
+            const float wxy = k.w[0][cx] * k.w[1][cy];
+            const float* v = tile + 3 * (base + (cx * ey + cy) * ez);
 #pragma unroll
             for (int cz = 0; cz < 2; ++cz) {
-              const float* v = g + 3 * (row + (cz ? c.hi[2] : c.lo[2]));
-              const float w = wxy * c.w[2][cz];
-              a0 += w * v[0];
-              a1 += w * v[1];
-              a2 += w * v[2];
+              const float w = wxy * k.w[2][cz];
+              a0 += w * v[3 * cz];
+              a1 += w * v[3 * cz + 1];
+              a2 += w * v[3 * cz + 2];
             }
           }
         }
+      } else {
+        gather_global(g, n, nmask, k, a0, a1, a2);
       }
     }
-    a_out[3 * j] = a0;
-    a_out[3 * j + 1] = a1;
-    a_out[3 * j + 2] = a2;
+    out[3 * j] = a0;
+    out[3 * j + 1] = a1;
+    out[3 * j + 2] = a2;
   }
 }
 
@@ -498,15 +536,29 @@ hipError_t launch_deposit(const float* pos, unsigned long long* rho, int64_t np,
   }
 }
 
+// Blocks rounded up to whole XCD rounds; the extra blocks exit at once.
+int xcd_blocks(int64_t nchunks) { return static_cast<int>((nchunks + 7) / 8 * 8); }
+
 template <int CH, int CAP>
 hipError_t launch_interp_tiled(const float* pos, const float* force, float* acc, int64_t np,
                                int nbox, int n, double inv_cell, hipStream_t s) {
   const int64_t chunks = (np + CH - 1) / CH;
-  hipLaunchKernelGGL((interp_tiled_kernel<CH, CAP>), dim3(static_cast<unsigned>(chunks * nbox)),
-                     dim3(256), 0, s, pos, force, acc, np, n, inv_cell, chunks);
+  hipLaunchKernelGGL((interp_tiled_kernel<CH, CAP>), dim3(xcd_blocks(chunks * nbox)), dim3(256),
+                     0, s, pos, force, acc, np, n, inv_cell, chunks, chunks * nbox);
   return hipGetLastError();
 }
 
+template <int PPT>
+hipError_t launch_interp_direct(const float* pos, const float* force, float* acc, int64_t np,
+                                int nbox, int n, double inv_cell, hipStream_t s) {
+  const int64_t chunks = (np + 256 * PPT - 1) / (256 * PPT);
+  hipLaunchKernelGGL((interp_kernel<PPT>), dim3(xcd_blocks(chunks * nbox)), dim3(256), 0, s, pos,
+                     force, acc, np, n, inv_cell, chunks, chunks * nbox);
+  return hipGetLastError();
+}
+
+// mode 0: direct gather, `block` = particles per workgroup (256, 512 or 1024);
+// modes 1-3: LDS-staged boxes of 1024 / 2048 / 4096 particles.
 hipError_t launch_interp(const float* pos, const float* force, float* acc, int64_t np,
                          int nbox, int n, double inv_cell, int mode, int block, hipStream_t s) {
   switch (mode) {
@@ -514,9 +566,9 @@ hipError_t launch_interp(const float* pos, const float* force, float* acc, int64
     case 2: return launch_interp_tiled<2048, 4608>(pos, force, acc, np, nbox, n, inv_cell, s);
     case 3: return launch_interp_tiled<4096, 8192>(pos, force, acc, np, nbox, n, inv_cell, s);
     default:
-      hipLaunchKernelGGL(interp_kernel, dim3(grid_blocks(np * nbox, block, 1)), dim3(block), 0,
-                         s, pos, force, acc, np, nbox, n, inv_cell);
-      return hipGetLastError();
+      if (block >= 1024) return launch_interp_direct<4>(pos, force, acc, np, nbox, n, inv_cell, s);
+      if (block >= 512) return launch_interp_direct<2>(pos, force, acc, np, nbox, n, inv_cell, s);
+      return launch_interp_direct<1>(pos, force, acc, np, nbox, n, inv_cell, s);
   }
 }
 
