@@ -75,13 +75,37 @@ def source_sha(name):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(workload, kernel):
+def kernel_name(stage, tuning, n_mesh):
+    """Name (with template arguments) of the kernel a stage launches, as rocprofv3 lists it."""
+    dep = {1: "<1024, 2560, 256>", 2: "<2048, 4608, 256>", 3: "<4096, 8192, 256>",
+           4: "<4096, 8192, 512>", 5: "<8192, 16384, 1024>"}
+    itp = {1: "<1024, 2560>", 2: "<2048, 4608>", 3: "<4096, 8192>"}
+    if stage == "cic_deposit":
+        m = tuning["deposit_mode"]
+        return "deposit_tiled_kernel" + dep[m] if m else "deposit_kernel"
+    if stage == "cic_interp":
+        m = tuning["interp_mode"]
+        if m:
+            return "interp_tiled_kernel" + itp[m]
+        return "interp_kernel<%d>" % max(1, min(4, tuning["interp_block"] // 256))
+    fixed = {"zero_mesh": "fill_zero_kernel", "nu_response": "response_kernel",
+             "rtable": "rtable_kernel"}
+    if stage in fixed:
+        return fixed[stage]
+    fft = {"fft_fwd_z": "fwd_z_kernel", "fft_fwd_y": "fwd_y_kernel",
+           "fft_fwd_x_bin": "fwd_x_bin_kernel", "inv_x_green": "inv_x_kernel",
+           "fft_inv_y": "inv_y_kernel", "fft_inv_z": "inv_z_kernel"}
+    return "%s<%d>" % (fft[stage], n_mesh)
+
+
+def load_traffic(workload, stage, kernel):
+    """Measured HBM bytes per launch (profiles/traffic.json), or None when there is no
+    record for this kernel or its source changed after the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-        rec = t[workload][kernel]
-        if rec.get("source_sha") != source_sha(KERNEL_SOURCES[kernel]):
-            return None       # kernel changed since the counters were taken
+            rec = json.load(f)[workload]["kernels"][stage][kernel]
+        if rec.get("source_sha") != source_sha(KERNEL_SOURCES[stage]):
+            return None
         return rec["bytes_per_launch"]
     except Exception:
         return None
@@ -104,7 +128,7 @@ def make_workload(name, mass_index, order):
 SURROGATE_BLOB = os.path.join(ROOT, "paper_1209_0461_amd", "data", "surrogate_pm256.npy")
 
 
-def measure_surrogate(ctx, binding, pos, acc, a_now, steps, stream, timing_exact):
+def measure_surrogate(ctx, binding, pos, acc, a_now, steps, stream, timing_exact, names):
     """Same step with the surrogate response: accuracy of R against the exact integral
     (check mode, every box and non-empty bin) and the timed step."""
     binding.pm_nu_surrogate_load(ctx.h, np.load(SURROGATE_BLOB))
@@ -122,7 +146,7 @@ def measure_surrogate(ctx, binding, pos, acc, a_now, steps, stream, timing_exact
         ctx.step(pos, acc, a_now)
     stream.synchronize()
     binding.pm_nu_read_timing(ctx.h)
-    binding.pm_nu_set_timing(ctx.h, True)
+    binding.pm_nu_set_timing_mask(ctx.h, 1 << names.index("surrogate"))
     t0 = time.perf_counter()
     for _ in range(steps):
         ctx.step(pos, acc, a_now)
@@ -223,8 +247,17 @@ def main():
             for _ in range(args.warmup):
                 binding.pm_nu_graph_launch(ctx.h)
         stream.synchronize()
+        # per-stage profile: an event pair around every kernel, on untimed eager steps
         binding.pm_nu_read_timing(ctx.h)
-        binding.pm_nu_set_timing(ctx.h, not args.graph)
+        binding.pm_nu_set_timing(ctx.h, True)
+        for _ in range(min(args.steps, 10)):
+            ctx.step(pos, acc, a_now)
+        stream.synchronize()
+        timing = binding.pm_nu_read_timing(ctx.h)
+        names = list(timing)
+        dom = max((k for k in names if timing[k][1] > 0), key=lambda k: timing[k][0])
+        # timed region: events only around the dominant kernel (graph replays carry none)
+        binding.pm_nu_set_timing_mask(ctx.h, 0 if args.graph else 1 << names.index(dom))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -235,14 +268,18 @@ def main():
         stream.synchronize()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        timing = binding.pm_nu_read_timing(ctx.h)
+        timed = binding.pm_nu_read_timing(ctx.h)
         binding.pm_nu_set_timing(ctx.h, False)
+        if timed[dom][1] > 0:
+            dom_ms, dom_source = timed[dom][0] / timed[dom][1], "timed region"
+        else:
+            dom_ms, dom_source = timing[dom][0] / timing[dom][1], "eager profile steps"
         sp = ctx.spectrum(0)
         finite = bool(np.isfinite(acc.cpu().numpy()).all() and np.isfinite(sp["ratio"]).all())
         surrogate = None
         if os.path.exists(SURROGATE_BLOB) and not args.no_surrogate and not args.graph:
             surrogate = measure_surrogate(ctx, binding, pos, acc, a_now, args.steps, stream,
-                                          timing)
+                                          timing, names)
 
     from paper_1209_0461_amd.binding import load_library  # noqa: F401
     n_partial = (n_mesh // min(16 if n_mesh <= 256 else 8, n_mesh)) * (n_mesh // 2 + 1)
@@ -274,13 +311,20 @@ def main():
                        "achieved_gbs": step_bytes * value / 1e9,
                        "frac": step_bytes * value / 1e9 / HBM_PEAK_GBS}
     if stages:
-        dom = max(stages, key=lambda k: stages[k]["ms_per_launch"] * stages[k]["launches"])
-        ach = sb[dom] / (stages[dom]["ms_per_launch"] * 1e-3) / 1e9
-        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach,
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                           "traffic": load_traffic(args.workload, dom),
+        ach = sb[dom] / (dom_ms * 1e-3) / 1e9
+        kname = kernel_name(dom, tuning, n_mesh)
+        traffic = load_traffic(args.workload, dom, kname)
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "kernel_name": kname,
+                           "ms_per_launch": dom_ms, "timing": f"HIP events, {dom_source}",
+                           "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBS,
+                           "traffic": traffic,
+                           "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, "
+                                           "copy-calibrated)",
                            "algorithmic_bytes_per_launch": sb[dom]}
         out["stages"] = stages
+        out["stages_note"] = ("per-stage HIP event pairs around every kernel on "
+                              f"{min(args.steps, 10)} eager steps before the timed region")
     if surrogate is not None:
         out["surrogate"] = surrogate
     if not args.no_cpu_baseline:

@@ -149,6 +149,9 @@ int pm_nu_copy_force_grid(pm_nu_ctx* ctx, int box, int axis, float* out);
 /* ---- per-kernel timing with HIP events on the library's stream ---------------------- */
 /* enable != 0 starts recording an event pair around every kernel launch. */
 int pm_nu_set_timing(pm_nu_ctx* ctx, int enable);
+/* Record event pairs only around the stages whose bit is set (bit i = the i-th stage as
+ * listed by pm_nu_read_timing); 0 stops recording. Fewer events, less overhead. */
+int pm_nu_set_timing_mask(pm_nu_ctx* ctx, uint32_t stage_mask);
 /* (sync) Sums of kernel times [ms] and launch counts per stage since the last read,
  * then resets them. names[i] are static strings. Arrays hold *n_stages entries on
  * input (capacity) and output (count). */
@@ -171,8 +174,8 @@ int pm_nu_graph_launch(pm_nu_ctx* ctx);
 int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
                    const char* cache_path);
 /* Set the launch shapes directly: deposit_mode 0 (one thread per particle, global atomics;
- * deposit_block = threads per workgroup) or 1/2/3 (LDS-privatised chunks of 1024/2048/4096
- * particles), interp_mode 0 (direct gather; interp_block = particles per workgroup, rounded
+ * deposit_block = threads per workgroup) or 1..5 (LDS-privatised chunks of 1024/2048/4096
+ * particles on 256 threads, 4096 on 512 threads, 8192 on 1024 threads), interp_mode 0 (direct gather; interp_block = particles per workgroup, rounded
  * down to 256, 512 or 1024) or 1/2/3 (LDS-staged chunks). Blocks: multiples of 64 in
  * 64..1024. */
 int pm_nu_set_launch(pm_nu_ctx* ctx, int deposit_mode, int deposit_block, int interp_mode,

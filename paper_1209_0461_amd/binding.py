@@ -58,6 +58,7 @@ SIGNATURES = {
     "pm_nu_copy_modes": (_INT, [_P, _INT, _P]),
     "pm_nu_copy_force_grid": (_INT, [_P, _INT, _INT, _P]),
     "pm_nu_set_timing": (_INT, [_P, _INT]),
+    "pm_nu_set_timing_mask": (_INT, [_P, ctypes.c_uint32]),
     "pm_nu_read_timing": (_INT, [_P, ctypes.POINTER(_INT), ctypes.POINTER(ctypes.c_char_p), _D, _I64]),
     "pm_nu_graph_capture": (_INT, [_P, _P, _P, ctypes.c_double]),
     "pm_nu_graph_launch": (_INT, [_P]),
@@ -228,6 +229,10 @@ def pm_nu_copy_force_grid(h, box, axis, out):
 
 def pm_nu_set_timing(h, enable):
     _check(load_library().pm_nu_set_timing(h, 1 if enable else 0))
+
+
+def pm_nu_set_timing_mask(h, stage_mask):
+    _check(load_library().pm_nu_set_timing_mask(h, int(stage_mask) & 0xFFFFFFFF))
 
 
 def pm_nu_read_timing(h):

@@ -28,11 +28,13 @@ namespace {
 
 // Per axis: lower node (mod N) and the fraction beyond it, in FP64 (u = x N / L is exact
 // for an FP32 coordinate times an FP64 inverse cell size up to the product's rounding).
+// The node index comes from adding 1.5 * 2^52, which leaves floor(u) in two's complement
+// in the low bits for |u| < 2^51; the mask keeps any index in range.
 __device__ __forceinline__ void axis64(float x, double inv_cell, int nmask, int& i, double& d) {
   const double u = static_cast<double>(x) * inv_cell;
   const double f = floor(u);
   d = u - f;
-  i = static_cast<int>(static_cast<long long>(f) & nmask);
+  i = static_cast<int>(__double2loint(f + 6755399441055744.0)) & nmask;
 }
 
 // Round-to-nearest-even of 0 <= v < 2^52 as an integer: adding 2^52 leaves the rounded
@@ -120,18 +122,16 @@ __device__ __forceinline__ int wave_max(int v) {
 // node. Every thread computes the same reference node, so no barrier is needed for it.
 template <int PPT>
 struct Chunk {
-  int i[PPT][3];
-  double d[PPT][3];
+  float p[PPT][3];
   bool ok[PPT];
   int r[3];
   int mn[3], ext[3];   // box origin (relative to r) and extent in nodes, upper neighbours included
   bool any;
 };
 
-template <int PPT>
+template <int PPT, int NT = 256>
 __device__ __forceinline__ void load_chunk(Chunk<PPT>& c, const float* p, int cnt, double inv_cell,
-                                           int nmask, int (*red)[4], bool& bad) {
-  constexpr int NT = 256;
+                                           int nmask, int (*red)[NT / 64], bool& bad) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, half = (nmask + 1) / 2;
   {
     const float x = p[0], y = p[1], z = p[2];
@@ -141,25 +141,29 @@ __device__ __forceinline__ void load_chunk(Chunk<PPT>& c, const float* p, int cn
     axis64(ok0 ? y : 0.f, inv_cell, nmask, c.r[1], dd);
     axis64(ok0 ? z : 0.f, inv_cell, nmask, c.r[2], dd);
   }
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int j = tid + q * NT;
+    c.p[q][0] = c.p[q][1] = c.p[q][2] = 0.f;
+    if (j < cnt) {
+      c.p[q][0] = p[3 * j];
+      c.p[q][1] = p[3 * j + 1];
+      c.p[q][2] = p[3 * j + 2];
+    }
+  }
   int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     const int j = tid + q * NT;
-    float x = 0.f, y = 0.f, z = 0.f;
-    if (j < cnt) {
-      x = p[3 * j];
-      y = p[3 * j + 1];
-      z = p[3 * j + 2];
-    }
-    c.ok[q] = j < cnt && finite3(x, y, z);
+    c.ok[q] = j < cnt && finite3(c.p[q][0], c.p[q][1], c.p[q][2]);
     bad |= (j < cnt) && !c.ok[q];
-    axis64(c.ok[q] ? x : 0.f, inv_cell, nmask, c.i[q][0], c.d[q][0]);
-    axis64(c.ok[q] ? y : 0.f, inv_cell, nmask, c.i[q][1], c.d[q][1]);
-    axis64(c.ok[q] ? z : 0.f, inv_cell, nmask, c.i[q][2], c.d[q][2]);
     if (c.ok[q]) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const int rel = ((c.i[q][a] - c.r[a] + half) & nmask) - half;
+        int i;
+        double d;
+        axis64(c.p[q][a], inv_cell, nmask, i, d);
+        const int rel = ((i - c.r[a] + half) & nmask) - half;
         mn[a] = min(mn[a], rel);
         mx[a] = max(mx[a], rel);
       }
@@ -197,9 +201,9 @@ __device__ __forceinline__ void load_chunk(Chunk<PPT>& c, const float* p, int cn
 // Walks the rows (tx, ty) of an ex x ey x ez box with the lanes of a wave spread over
 // (row, z): lane l takes z = l mod ez of row l / ez, so short rows keep the wave busy
 // without a division per node. Calls f(tx, ty, tz, linear index).
-template <typename F>
+template <int NT = 256, typename F>
 __device__ __forceinline__ void for_box_nodes(int ex, int ey, int ez, F f) {
-  constexpr int NW = 256 / 64;
+  constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (ez <= 64) {
     const int rpi = 64 / ez, dr = lane / ez, tz = lane - dr * ez;
@@ -231,15 +235,15 @@ __device__ __forceinline__ void for_box_nodes(int ex, int ey, int ez, F f) {
 // arbitrary order) take the per-particle global-atomic path, so the result does not depend
 // on the order; the speed does. Particles kept along a space-filling curve (as tree codes
 // keep them) give compact chunks.
-template <int CH, int CAP>
-__global__ __launch_bounds__(256) void deposit_tiled_kernel(const float* __restrict__ pos,
-                                                            unsigned long long* __restrict__ rho,
-                                                            int64_t np, int n, double inv_cell,
-                                                            int* __restrict__ flags,
-                                                            int64_t chunks_per_box) {
-  constexpr int NT = 256, PPT = CH / NT;
+template <int CH, int CAP, int NT>
+__global__ __launch_bounds__(NT) void deposit_tiled_kernel(const float* __restrict__ pos,
+                                                           unsigned long long* __restrict__ rho,
+                                                           int64_t np, int n, double inv_cell,
+                                                           int* __restrict__ flags,
+                                                           int64_t chunks_per_box) {
+  constexpr int PPT = CH / NT;
   __shared__ unsigned long long tile[CAP];
-  __shared__ int red[6][4];
+  __shared__ int red[6][NT / 64];
   const int tid = threadIdx.x;
   const int64_t box = blockIdx.x / chunks_per_box;
   const int64_t c0 = (blockIdx.x - box * chunks_per_box) * CH;
@@ -248,7 +252,7 @@ __global__ __launch_bounds__(256) void deposit_tiled_kernel(const float* __restr
   unsigned long long* g = rho + box * static_cast<int64_t>(n) * n * n;
   Chunk<PPT> c;
   bool bad = false;
-  load_chunk<PPT>(c, pos + (box * np + c0) * 3, cnt, inv_cell, nmask, red, bad);
+  load_chunk<PPT, NT>(c, pos + (box * np + c0) * 3, cnt, inv_cell, nmask, red, bad);
   if (bad) atomicOr(flags, 1);
   const int ex = c.ext[0], ey = c.ext[1], ez = c.ext[2];
   const int vol = ex * ey * ez;
@@ -260,11 +264,16 @@ __global__ __launch_bounds__(256) void deposit_tiled_kernel(const float* __restr
     for (int q = 0; q < PPT; ++q) {
       if (!c.ok[q]) continue;
       int t[3];
+      double d[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) t[a] = ((c.i[q][a] - c.r[a] + half) & nmask) - half - c.mn[a];
-      const double wx[2] = {(1.0 - c.d[q][0]) * kFixScale, c.d[q][0] * kFixScale};
-      const double wy[2] = {1.0 - c.d[q][1], c.d[q][1]};
-      const double wz0 = 1.0 - c.d[q][2], wz1 = c.d[q][2];
+      for (int a = 0; a < 3; ++a) {
+        int i;
+        axis64(c.p[q][a], inv_cell, nmask, i, d[a]);
+        t[a] = ((i - c.r[a] + half) & nmask) - half - c.mn[a];
+      }
+      const double wx[2] = {(1.0 - d[0]) * kFixScale, d[0] * kFixScale};
+      const double wy[2] = {1.0 - d[1], d[1]};
+      const double wz0 = 1.0 - d[2], wz1 = d[2];
       const int base = (t[0] * ey + t[1]) * ez + t[2];
 #pragma unroll
       for (int cx = 0; cx < 2; ++cx) {
@@ -279,7 +288,7 @@ __global__ __launch_bounds__(256) void deposit_tiled_kernel(const float* __restr
     }
     __syncthreads();
     const int gx0 = c.r[0] + c.mn[0], gy0 = c.r[1] + c.mn[1], gz0 = c.r[2] + c.mn[2];
-    for_box_nodes(ex, ey, ez, [&](int tx, int ty, int tz, int li) {
+    for_box_nodes<NT>(ex, ey, ez, [&](int tx, int ty, int tz, int li) {
       const unsigned long long v = tile[li];
       if (v == 0ull) return;
       const unsigned gx = (gx0 + tx) & nmask, gy = (gy0 + ty) & nmask, gz = (gz0 + tz) & nmask;
@@ -287,8 +296,14 @@ __global__ __launch_bounds__(256) void deposit_tiled_kernel(const float* __restr
     });
   } else {
 #pragma unroll
-    for (int q = 0; q < PPT; ++q)
-      if (c.ok[q]) deposit_global(g, n, c.i[q], c.d[q], nmask);
+    for (int q = 0; q < PPT; ++q) {
+      if (!c.ok[q]) continue;
+      int i[3];
+      double d[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) axis64(c.p[q][a], inv_cell, nmask, i[a], d[a]);
+      deposit_global(g, n, i, d, nmask);
+    }
   }
 }
 
@@ -390,7 +405,7 @@ __global__ __launch_bounds__(256) void interp_tiled_kernel(const float* __restri
                                                            int64_t nchunks) {
   constexpr int NT = 256, PPT = CH / NT;
   __shared__ float tile[CAP * 3];
-  __shared__ int red[6][4];
+  __shared__ int red[6][256 / 64];
   const int tid = threadIdx.x;
   const int64_t chunk = xcd_chunk(blockIdx.x, gridDim.x);
   if (chunk >= nchunks) return;
@@ -408,13 +423,42 @@ __global__ __launch_bounds__(256) void interp_tiled_kernel(const float* __restri
   const bool use_tile = c.any && vol <= CAP && ex <= n && ey <= n && ez <= n;
   if (use_tile) {
     const int gx0 = c.r[0] + c.mn[0], gy0 = c.r[1] + c.mn[1], gz0 = c.r[2] + c.mn[2];
-    for_box_nodes(ex, ey, ez, [&](int tx, int ty, int tz, int li) {
-      const unsigned gx = (gx0 + tx) & nmask, gy = (gy0 + ty) & nmask, gz = (gz0 + tz) & nmask;
-      const float* v = g + 3 * ((gx * n + gy) * n + gz);
-      tile[3 * li] = v[0];
-      tile[3 * li + 1] = v[1];
-      tile[3 * li + 2] = v[2];
-    });
+    constexpr int RMAX = 32;                 // rows per wave held in registers
+    const int rows = ex * ey;
+    if (3 * ez <= 64 && rows <= 4 * RMAX) {
+      // one row (3 ez consecutive floats, contiguous in HBM unless z wraps) per wave and
+      // step; all of a wave's row loads are in flight before the LDS stores
+      const int lane = tid & 63, wv = tid >> 6;
+      const int tz = lane / 3, comp = lane - 3 * tz;
+      const bool on = lane < 3 * ez;
+      const unsigned gz = (gz0 + tz) & nmask;
+      float vals[RMAX];
+      int tx = wv / ey, ty = wv - (wv / ey) * ey;
+#pragma unroll
+      for (int i = 0; i < RMAX; ++i) {
+        if (on && wv + 4 * i < rows) {
+          const unsigned gx = (gx0 + tx) & nmask, gy = (gy0 + ty) & nmask;
+          vals[i] = g[3 * ((gx * n + gy) * n + gz) + comp];
+        }
+        ty += 4;
+        while (ty >= ey) {
+          ty -= ey;
+          ++tx;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < RMAX; ++i)
+        if (on && wv + 4 * i < rows) tile[(wv + 4 * i) * 3 * ez + lane] = vals[i];
+    } else {
+      for_box_nodes(ex, ey, ez, [&](int tx, int ty, int tz, int li) {
+        const unsigned gx = (gx0 + tx) & nmask, gy = (gy0 + ty) & nmask,
+                       gz = (gz0 + tz) & nmask;
+        const float* v = g + 3 * ((gx * n + gy) * n + gz);
+        tile[3 * li] = v[0];
+        tile[3 * li + 1] = v[1];
+        tile[3 * li + 2] = v[2];
+      });
+    }
     __syncthreads();
   }
   const int half = n / 2;
@@ -425,12 +469,7 @@ __global__ __launch_bounds__(256) void interp_tiled_kernel(const float* __restri
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
     if (c.ok[q]) {
       Corner k;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        k.i[a] = c.i[q][a];
-        k.w[a][1] = static_cast<float>(c.d[q][a]);
-        k.w[a][0] = 1.0f - k.w[a][1];
-      }
+      corner_of(c.p[q][0], c.p[q][1], c.p[q][2], inv_cell, nmask, k);
       if (use_tile) {
         int t[3];
 #pragma unroll
@@ -514,21 +553,27 @@ hipError_t launch_fixed_to_float(const unsigned long long* src, float* dst, int6
   return hipGetLastError();
 }
 
-template <int CH, int CAP>
+template <int CH, int CAP, int NT>
 hipError_t launch_tiled(const float* pos, unsigned long long* rho, int64_t np, int nbox, int n,
                         double inv_cell, int* flags, hipStream_t s) {
   const int64_t chunks = (np + CH - 1) / CH;
-  hipLaunchKernelGGL((deposit_tiled_kernel<CH, CAP>), dim3(static_cast<unsigned>(chunks * nbox)),
-                     dim3(256), 0, s, pos, rho, np, n, inv_cell, flags, chunks);
+  hipLaunchKernelGGL((deposit_tiled_kernel<CH, CAP, NT>),
+                     dim3(static_cast<unsigned>(chunks * nbox)), dim3(NT), 0, s, pos, rho, np, n,
+                     inv_cell, flags, chunks);
   return hipGetLastError();
 }
 
+// mode 0: one thread per particle, global atomics (`block` threads per workgroup);
+// modes 1-5: LDS-privatised chunks of 1024 / 2048 / 4096 particles with 256 threads, 4096
+// with 512 threads, 8192 with 1024 threads.
 hipError_t launch_deposit(const float* pos, unsigned long long* rho, int64_t np, int nbox, int n,
                           double inv_cell, int* flags, int mode, int block, hipStream_t s) {
   switch (mode) {
-    case 1: return launch_tiled<1024, 2560>(pos, rho, np, nbox, n, inv_cell, flags, s);
-    case 2: return launch_tiled<2048, 4608>(pos, rho, np, nbox, n, inv_cell, flags, s);
-    case 3: return launch_tiled<4096, 8192>(pos, rho, np, nbox, n, inv_cell, flags, s);
+    case 1: return launch_tiled<1024, 2560, 256>(pos, rho, np, nbox, n, inv_cell, flags, s);
+    case 2: return launch_tiled<2048, 4608, 256>(pos, rho, np, nbox, n, inv_cell, flags, s);
+    case 3: return launch_tiled<4096, 8192, 256>(pos, rho, np, nbox, n, inv_cell, flags, s);
+    case 4: return launch_tiled<4096, 8192, 512>(pos, rho, np, nbox, n, inv_cell, flags, s);
+    case 5: return launch_tiled<8192, 16384, 1024>(pos, rho, np, nbox, n, inv_cell, flags, s);
     default:
       hipLaunchKernelGGL(deposit_kernel, dim3(grid_blocks(np * nbox, block, 1)), dim3(block), 0,
                          s, pos, rho, np, nbox, n, inv_cell, flags);

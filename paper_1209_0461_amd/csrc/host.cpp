@@ -34,8 +34,9 @@ int set_error(int code, const char* fmt, ...) {
 }
 
 void timer_begin(Ctx& c, int stage) {
-  if (!c.timer.enabled || c.capturing) return;
   Timer& t = c.timer;
+  t.open = false;
+  if (!t.enabled || c.capturing || !((t.mask >> stage) & 1u)) return;
   if (2 * (t.used + 1) > t.pool.size()) {
     for (int i = 0; i < 2; ++i) {
       hipEvent_t e;
@@ -46,11 +47,13 @@ void timer_begin(Ctx& c, int stage) {
   if (t.stage_of.size() <= t.used) t.stage_of.resize(t.used + 1);
   t.stage_of[t.used] = stage;
   (void)hipEventRecord(t.pool[2 * t.used], c.stream);
+  t.open = true;
 }
 
 void timer_end(Ctx& c) {
-  if (!c.timer.enabled || c.capturing) return;
   Timer& t = c.timer;
+  if (!t.open) return;
+  t.open = false;
   if (2 * t.used + 1 >= t.pool.size()) return;
   (void)hipEventRecord(t.pool[2 * t.used + 1], c.stream);
   ++t.used;
@@ -728,6 +731,14 @@ int pm_nu_copy_force_grid(pm_nu_ctx* ctx, int box, int axis, float* out) {
 int pm_nu_set_timing(pm_nu_ctx* ctx, int enable) {
   GET_CTX(ctx);
   c->timer.enabled = enable != 0;
+  c->timer.mask = ~0u;
+  return PM_NU_OK;
+}
+
+int pm_nu_set_timing_mask(pm_nu_ctx* ctx, uint32_t stage_mask) {
+  GET_CTX(ctx);
+  c->timer.enabled = stage_mask != 0;
+  c->timer.mask = stage_mask;
   return PM_NU_OK;
 }
 

@@ -9,10 +9,11 @@
 // dZ rounded to bfloat16 as MFMA operand), and adds its share of the gradient to an FP32
 // buffer with global atomics. adam_kernel applies one Adam step to the FP32 masters.
 //
-// Inference inside the step is latency bound (one row per k-bin): the surrogate response
-// kernel evaluates the network for its bin as a chain of GEMVs with the same bfloat16
-// rounding, falling back to the exact integral (response_device.hpp) for inputs outside
-// the training range.
+// Inside the step the network sees one row per k-bin: surrogate_infer_kernel takes the
+// bins of a box in tiles of 32 rows through the same MFMA forward pass, with the weights
+// staged from a bfloat16 image packed once per weight change, and a second kernel falls
+// back to the exact integral (response_device.hpp) for the bins whose inputs are outside
+// the training range (or for every bin when checking).
 #include "response_device.hpp"
 #include "surrogate_layout.hpp"
 
@@ -65,17 +66,29 @@ struct Smem {
   unsigned short x[TB * 16];          // standardised inputs, K padded to 16 (bf16)
   unsigned short h[3][TB * 128];      // inputs of layers 2, 3, 4: H1, H2, H3 (bf16)
   float z[3][TB * 128];               // pre-activations Z1..Z3, later dZ (FP32)
-  unsigned short w[128 * 128];        // one staged weight matrix as [out][in] (bf16)
+  alignas(16) unsigned short w[128 * 128];   // one staged weight matrix as [out][in] (bf16)
   unsigned short d[TB * 128];         // dZ of the current layer (bf16)
   float y[TB];
   float dy[TB];
 };
 
-// W[in][out] (FP32 master, row-major) -> S.w[out*kin + in] (bf16); rows in >= nin are 0
+// W[in][out] (FP32 master, row-major) -> S.w[out*kin + in] (bf16); rows in >= nin are 0.
+// Loads go out in batches of 16 per thread before their LDS stores.
 __device__ __forceinline__ void stage_weights(Smem& S, const float* W, int nin, int kin) {
-  for (int t = threadIdx.x; t < kin * 128; t += NT) {
-    const int i = t / 128, o = t % 128;
-    S.w[o * kin + i] = (i < nin) ? f2bf(W[i * 128 + o]) : static_cast<unsigned short>(0);
+  constexpr int BATCH = 16;
+  const int total = kin * 128;
+  for (int t0 = 0; t0 < total; t0 += BATCH * NT) {
+    float v[BATCH];
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) {
+      const int t = t0 + threadIdx.x + q * NT, i = t / 128, o = t % 128;
+      v[q] = (t < total && i < nin) ? W[i * 128 + o] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) {
+      const int t = t0 + threadIdx.x + q * NT, i = t / 128, o = t % 128;
+      if (t < total) S.w[o * kin + i] = f2bf(v[q]);
+    }
   }
 }
 
@@ -98,33 +111,9 @@ __device__ __forceinline__ void dense_gelu(Smem& S, const unsigned short* Hin, i
   }
 }
 
-// Forward pass of up to TB rows starting at row0 (through perm if given). Leaves y (the
-// standardised output) in S.y.
-__device__ void forward_tile(Smem& S, const float* P, const float* x, const int* perm,
-                             int64_t row0, int count) {
+// output layer: 8 lanes per sample, 16 products each, FP32
+__device__ __forceinline__ void output_layer(Smem& S, const float* P) {
   const int tid = threadIdx.x;
-  for (int t = tid; t < TB * 16; t += NT) {
-    const int s = t >> 4, i = t & 15;
-    float v = 0.f;
-    if (i < kSurIn && s < count) {
-      const int64_t r = perm ? perm[row0 + s] : row0 + s;
-      v = (x[r * kSurIn + i] - P[kOffMu + i]) / P[kOffSigma + i];
-    }
-    S.x[t] = f2bf(v);
-  }
-  stage_weights(S, P + kOffW1, kSurIn, 16);
-  __syncthreads();
-  dense_gelu(S, S.x, 16, P + kOffB1, S.z[0], S.h[0]);
-  __syncthreads();
-  stage_weights(S, P + kOffW2, 128, 128);
-  __syncthreads();
-  dense_gelu(S, S.h[0], 128, P + kOffB2, S.z[1], S.h[1]);
-  __syncthreads();
-  stage_weights(S, P + kOffW3, 128, 128);
-  __syncthreads();
-  dense_gelu(S, S.h[1], 128, P + kOffB3, S.z[2], S.h[2]);
-  __syncthreads();
-  // output layer: 8 lanes per sample, 16 products each, FP32
   {
     const int s = tid >> 3, part = tid & 7;
     float acc = 0.f;
@@ -137,6 +126,66 @@ __device__ void forward_tile(Smem& S, const float* P, const float* x, const int*
     if (part == 0) S.y[s] = acc + P[kOffB4];
   }
   __syncthreads();
+}
+
+// bfloat16 image of W1..W3 in the staged layout ([out][in], the first layer's K padded to
+// 16), so that inference stages a layer with 16-byte copies
+constexpr int kPackW1 = 0;
+constexpr int kPackW2 = kPackW1 + 128 * 16;
+constexpr int kPackW3 = kPackW2 + 128 * 128;
+constexpr int kPackSize = kPackW3 + 128 * 128;
+
+template <int N>
+__device__ __forceinline__ void stage_packed(Smem& S, const unsigned short* Q) {
+  constexpr int V = N / 8, IT = (V + NT - 1) / NT;
+  const uint4* src = reinterpret_cast<const uint4*>(Q);
+  uint4* dst = reinterpret_cast<uint4*>(S.w);
+  uint4 r[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int t = threadIdx.x + i * NT;
+    if (t < V) r[i] = src[t];
+  }
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int t = threadIdx.x + i * NT;
+    if (t < V) dst[t] = r[i];
+  }
+}
+
+// Layers 1-3 of the forward pass on S.x (already standardised, bf16); weights staged from
+// the FP32 masters P, or from the packed image Q when given.
+__device__ __forceinline__ void hidden_layers(Smem& S, const float* P, const unsigned short* Q) {
+  if (Q) stage_packed<128 * 16>(S, Q + kPackW1); else stage_weights(S, P + kOffW1, kSurIn, 16);
+  __syncthreads();
+  dense_gelu(S, S.x, 16, P + kOffB1, S.z[0], S.h[0]);
+  __syncthreads();
+  if (Q) stage_packed<128 * 128>(S, Q + kPackW2); else stage_weights(S, P + kOffW2, 128, 128);
+  __syncthreads();
+  dense_gelu(S, S.h[0], 128, P + kOffB2, S.z[1], S.h[1]);
+  __syncthreads();
+  if (Q) stage_packed<128 * 128>(S, Q + kPackW3); else stage_weights(S, P + kOffW3, 128, 128);
+  __syncthreads();
+  dense_gelu(S, S.h[1], 128, P + kOffB3, S.z[2], S.h[2]);
+  __syncthreads();
+  output_layer(S, P);
+}
+
+// Forward pass of up to TB rows starting at row0 (through perm if given). Leaves y (the
+// standardised output) in S.y.
+__device__ __forceinline__ void forward_tile(Smem& S, const float* P, const float* x, const int* perm,
+                             int64_t row0, int count) {
+  const int tid = threadIdx.x;
+  for (int t = tid; t < TB * 16; t += NT) {
+    const int s = t >> 4, i = t & 15;
+    float v = 0.f;
+    if (i < kSurIn && s < count) {
+      const int64_t r = perm ? perm[row0 + s] : row0 + s;
+      v = (x[r * kSurIn + i] - P[kOffMu + i]) / P[kOffSigma + i];
+    }
+    S.x[t] = f2bf(v);
+  }
+  hidden_layers(S, P, nullptr);
 }
 
 // dW (kin x 128) += Hin^T dZ for the 32-row tile (rows i < nin), with atomics
@@ -301,41 +350,6 @@ __device__ __forceinline__ double approx_factor(double k, double kfs) {
   return 1.0 / (t * t);
 }
 
-// Single-row forward pass by the whole workgroup (GEMVs, bf16 weights and inputs, FP32
-// accumulation). f: raw features (LDS). Returns the un-standardised output to every thread.
-__device__ float mlp_single(const float* P, const float* f, float* h0, float* h1, float* red) {
-  const int j = threadIdx.x;
-  if (j < 128) {
-    float z = P[kOffB1 + j];
-    for (int i = 0; i < kSurIn; ++i)
-      z += bfr((f[i] - P[kOffMu + i]) / P[kOffSigma + i]) * bfr(P[kOffW1 + i * 128 + j]);
-    h0[j] = bfr(gelu(z));
-  }
-  __syncthreads();
-  if (j < 128) {
-    float z = P[kOffB2 + j];
-    for (int i = 0; i < 128; ++i) z += h0[i] * bfr(P[kOffW2 + i * 128 + j]);
-    h1[j] = bfr(gelu(z));
-  }
-  __syncthreads();
-  if (j < 128) {
-    float z = P[kOffB3 + j];
-    for (int i = 0; i < 128; ++i) z += h1[i] * bfr(P[kOffW3 + i * 128 + j]);
-    h0[j] = bfr(gelu(z));   // h0 is free again
-  }
-  __syncthreads();
-  float part = (j < 128) ? h0[j] * bfr(P[kOffW4 + j]) : 0.f;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-  if ((j & 63) == 0) red[j >> 6] = part;
-  __syncthreads();
-  float s = 0.f;
-#pragma unroll
-  for (int w = 0; w < NT / 64; ++w) s += red[w];
-  const float ystd = s + P[kOffB4];
-  return ystd * P[kOffYSigma] + P[kOffYMu];
-}
-
 __device__ __forceinline__ bool in_range(const float* P, const float* f) {
   for (int i = 0; i < kSurIn; ++i) {
     const float lo = P[kOffMin + i], hi = P[kOffMax + i], mg = 0.05f * (hi - lo);
@@ -344,72 +358,117 @@ __device__ __forceinline__ bool in_range(const float* P, const float* f) {
   return true;
 }
 
-// One workgroup per (bin, box), like the exact response kernel. mode 1: surrogate with the
-// exact fallback; mode 2: both, the exact result is used and both are recorded.
-__global__ __launch_bounds__(RT) void surrogate_response_kernel(
-    const float* __restrict__ P, int mode, const RespBox* __restrict__ boxes,
-    const double* __restrict__ partial, int n_partial, const double* __restrict__ counts,
-    const double* __restrict__ kmean, double* __restrict__ hist_pm, double* __restrict__ hist_pnu,
-    const double* __restrict__ ic_pnu, const double* __restrict__ ic_theta,
-    const double* __restrict__ tg_ds, const double* __restrict__ tg_w, int nbins, int jcap,
-    int qcap, int q_sub, int iterations, double norm, double* __restrict__ pcdm_out,
-    double* __restrict__ pnu_out, double* __restrict__ ratio_out,
-    double* __restrict__ chk_exact, double* __restrict__ chk_sur) {
-  __shared__ double red[RT / 64];
-  __shared__ float redf[RT / 64];
-  __shared__ float feat[kSurIn];
-  __shared__ float h0[128], h1[128];
-  __shared__ int use_net;
-  const int b = blockIdx.x, box = blockIdx.y;
+__global__ void pack_weights_kernel(const float* __restrict__ P, unsigned short* __restrict__ Q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kPackW2) {
+    const int o = i / 16, in = i % 16;
+    Q[i] = in < kSurIn ? f2bf(P[kOffW1 + in * 128 + o]) : static_cast<unsigned short>(0);
+  } else if (i < kPackW3) {
+    const int j = i - kPackW2, o = j / 128, in = j % 128;
+    Q[i] = f2bf(P[kOffW2 + in * 128 + o]);
+  } else if (i < kPackSize) {
+    const int j = i - kPackW3, o = j / 128, in = j % 128;
+    Q[i] = f2bf(P[kOffW3 + in * 128 + o]);
+  }
+}
+
+// Network inference for the bins of one box, TB bins per workgroup: the features from
+// P_cdm (already reduced from the deposit's partial sums) and the stored history, then the
+// forward pass on the matrix cores. Writes the network's R (NaN where the inputs are
+// unusable) with its use flag; in mode 1 it also finishes the bins it can answer.
+__global__ __launch_bounds__(NT) void surrogate_infer_kernel(
+    const float* __restrict__ P, const unsigned short* __restrict__ Q, int mode,
+    const RespBox* __restrict__ boxes, const double* __restrict__ counts,
+    const double* __restrict__ kmean, double* __restrict__ hist_pm,
+    double* __restrict__ hist_pnu, int nbins, int jcap, const double* __restrict__ pcdm,
+    double* __restrict__ pnu_out, double* __restrict__ ratio_out, double* __restrict__ sur_r,
+    int* __restrict__ sur_use) {
+  __shared__ Smem S;
+  __shared__ double ph_s[TB];
+  __shared__ int ok_s[TB];
+  const int tid = threadIdx.x;
+  const int box = blockIdx.y, b0 = blockIdx.x * TB;
+  const int cnt = min(TB, nbins - b0);
   const RespBox bx = boxes[box];
-  const size_t ob = static_cast<size_t>(box) * nbins + b;
   double* hpm = hist_pm + static_cast<size_t>(box) * jcap * nbins;
   double* hpn = hist_pnu + static_cast<size_t>(box) * jcap * nbins;
-  const double s = bin_mode_sum(partial, n_partial, nbins, box, b, red);
-  const double cb = counts[b];
-  if (!(cb > 0.0)) {
+  if (tid < cnt) ph_s[tid] = sqrt(pcdm[static_cast<size_t>(box) * nbins + b0 + tid]);
+  __syncthreads();
+  if (tid < TB) {
+    float f[kSurIn];
+    bool ok = false;
+    if (tid < cnt && counts[b0 + tid] > 0.0)
+      ok = make_features(bx, kmean[b0 + tid], ph_s[tid], hpm, nbins, b0 + tid, f) &&
+           in_range(P, f);
+    ok_s[tid] = ok ? 1 : 0;
+    for (int i = 0; i < 16; ++i)
+      S.x[tid * 16 + i] =
+          f2bf(ok && i < kSurIn ? (f[i] - P[kOffMu + i]) / P[kOffSigma + i] : 0.f);
+  }
+  hidden_layers(S, P, Q);   // begins with a barrier-protected staging step
+  if (tid < cnt) {
+    const int b = b0 + tid;
+    const size_t ob = static_cast<size_t>(box) * nbins + b;
+    const bool ok = ok_s[tid] != 0;
+    const double k = kmean[b];
+    const double r = ok ? exp(static_cast<double>(S.y[tid] * P[kOffYSigma] + P[kOffYMu])) *
+                              approx_factor(k, bx.kfs)
+                        : __builtin_nan("");
+    sur_r[ob] = r;
+    sur_use[ob] = ok ? 1 : 0;
+    if (ok && mode == 1) {
+      const double ph = ph_s[tid], pnu = r * ph;
+      pnu_out[ob] = pnu;
+      ratio_out[ob] = r;
+      hpm[static_cast<size_t>(bx.n_cur) * nbins + b] = (1.0 - bx.f_nu) * ph + bx.f_nu * pnu;
+      hpn[static_cast<size_t>(bx.n_cur) * nbins + b] = pnu;
+    }
+  }
+}
+
+// One workgroup per (bin, box): the exact integral for the bins the network did not answer
+// (mode 1) or for every bin (mode 2, which keeps the exact result and records both).
+__global__ __launch_bounds__(RT) void surrogate_finish_kernel(
+    int mode, const RespBox* __restrict__ boxes, const double* __restrict__ counts,
+    const double* __restrict__ kmean, double* __restrict__ hist_pm,
+    double* __restrict__ hist_pnu, const double* __restrict__ ic_pnu,
+    const double* __restrict__ ic_theta, const double* __restrict__ tg_ds,
+    const double* __restrict__ tg_w, int nbins, int jcap, int qcap, int q_sub, int iterations,
+    const double* __restrict__ pcdm_in, double* __restrict__ pnu_out,
+    double* __restrict__ ratio_out, const double* __restrict__ sur_r,
+    const int* __restrict__ sur_use, double* __restrict__ chk_exact,
+    double* __restrict__ chk_sur) {
+  __shared__ double red[RT / 64];
+  const int b = blockIdx.x, box = blockIdx.y;
+  const size_t ob = static_cast<size_t>(box) * nbins + b;
+  const bool net = sur_use[ob] != 0;
+  if (mode == 1 && net) return;                   // answered by the network
+  const RespBox bx = boxes[box];
+  double* hpm = hist_pm + static_cast<size_t>(box) * jcap * nbins;
+  double* hpn = hist_pnu + static_cast<size_t>(box) * jcap * nbins;
+  const size_t row = static_cast<size_t>(bx.n_cur) * nbins + b;
+  if (!(counts[b] > 0.0)) {
     if (threadIdx.x == 0) {
-      pcdm_out[ob] = 0.0;
-      pnu_out[ob] = 0.0;
-      ratio_out[ob] = 0.0;
-      hpm[static_cast<size_t>(bx.n_cur) * nbins + b] = 0.0;
-      hpn[static_cast<size_t>(bx.n_cur) * nbins + b] = 0.0;
+      pnu_out[ob] = ratio_out[ob] = 0.0;
+      hpm[row] = hpn[row] = 0.0;
       if (chk_exact) chk_exact[ob] = chk_sur[ob] = 0.0;
     }
     return;
   }
-  const double pcdm = norm * s / cb;
-  const double pcdm_half = sqrt(pcdm);
-  const double k = kmean[b];
+  const double ph = sqrt(pcdm_in[ob]);
+  const double pnu = exact_pnu(bx, kmean[b], ph, hpn[static_cast<size_t>(bx.n_cur - 1) * nbins + b],
+                               ic_pnu[ob], ic_theta[ob], hpm, nbins, b,
+                               tg_ds + static_cast<size_t>(box) * qcap,
+                               tg_w + static_cast<size_t>(box) * qcap, q_sub, iterations, red);
   if (threadIdx.x == 0) {
-    float f[kSurIn];
-    const bool ok = make_features(bx, k, pcdm_half, hpm, nbins, b, f) && in_range(P, f);
-    for (int i = 0; i < kSurIn; ++i) feat[i] = f[i];
-    use_net = ok ? 1 : 0;
-  }
-  __syncthreads();
-  const bool net = use_net != 0;
-  double r_sur = 0.0, pnu_exact = 0.0;
-  if (net) r_sur = exp(static_cast<double>(mlp_single(P, feat, h0, h1, redf))) *
-                   approx_factor(k, bx.kfs);
-  const bool need_exact = !net || mode == 2;
-  if (need_exact)
-    pnu_exact = exact_pnu(bx, k, pcdm_half, hpn[static_cast<size_t>(bx.n_cur - 1) * nbins + b],
-                          ic_pnu[ob], ic_theta[ob], hpm, nbins, b,
-                          tg_ds + static_cast<size_t>(box) * qcap,
-                          tg_w + static_cast<size_t>(box) * qcap, q_sub, iterations, red);
-  if (threadIdx.x == 0) {
-    const double r_exact = pnu_exact / pcdm_half;
-    const double r = (mode == 1 && net) ? r_sur : r_exact;
-    const double pnu = r * pcdm_half;
-    pcdm_out[ob] = pcdm;
+    const double r = pnu / ph;
     pnu_out[ob] = pnu;
     ratio_out[ob] = r;
-    hpm[static_cast<size_t>(bx.n_cur) * nbins + b] = (1.0 - bx.f_nu) * pcdm_half + bx.f_nu * pnu;
-    hpn[static_cast<size_t>(bx.n_cur) * nbins + b] = pnu;
+    hpm[row] = (1.0 - bx.f_nu) * ph + bx.f_nu * pnu;
+    hpn[row] = pnu;
     if (chk_exact) {
-      chk_exact[ob] = r_exact;
-      chk_sur[ob] = net ? r_sur : r_exact;
+      chk_exact[ob] = r;
+      chk_sur[ob] = net ? sur_r[ob] : r;
     }
   }
 }
@@ -457,18 +516,34 @@ hipError_t launch_adam(float* P, const float* g, float* m, float* v, int n, floa
   return hipGetLastError();
 }
 
-hipError_t launch_surrogate_response(const float* P, int mode, const RespBox* boxes,
-                                     const double* partial, int n_partial, const double* counts,
-                                     const double* kmean, double* hist_pm, double* hist_pnu,
-                                     const double* ic_pnu, const double* ic_theta,
-                                     const double* tg_ds, const double* tg_w, int nbins, int jcap,
-                                     int qcap, int q_sub, int iterations, double norm, int nbox,
-                                     double* pcdm, double* pnu, double* ratio, double* chk_exact,
-                                     double* chk_sur, hipStream_t s) {
-  hipLaunchKernelGGL(surrogate_response_kernel, dim3(nbins, nbox), dim3(RT), 0, s, P, mode,
-                     boxes, partial, n_partial, counts, kmean, hist_pm, hist_pnu, ic_pnu, ic_theta,
-                     tg_ds, tg_w, nbins, jcap, qcap, q_sub, iterations, norm, pcdm, pnu, ratio,
-                     chk_exact, chk_sur);
+hipError_t launch_pack_weights(const float* P, unsigned short* Q, hipStream_t s) {
+  hipLaunchKernelGGL(pack_weights_kernel, dim3((kPackSize + 255) / 256), dim3(256), 0, s, P, Q);
+  return hipGetLastError();
+}
+
+int64_t packed_weight_count() { return kPackSize; }
+
+hipError_t launch_surrogate_response(const float* P, const unsigned short* Q, int mode,
+                                     const RespBox* boxes, const double* partial, int n_partial,
+                                     const double* counts, const double* kmean, double* hist_pm,
+                                     double* hist_pnu, const double* ic_pnu,
+                                     const double* ic_theta, const double* tg_ds,
+                                     const double* tg_w, int nbins, int jcap, int qcap,
+                                     int q_sub, int iterations, double norm, int nbox,
+                                     double* pcdm, double* pnu, double* ratio, double* sur_r,
+                                     int* sur_use, double* chk_exact, double* chk_sur,
+                                     hipStream_t s) {
+  hipError_t e = launch_bin_power(partial, n_partial, counts, nbins, norm, nbox, pcdm, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(surrogate_infer_kernel, dim3((nbins + TB - 1) / TB, nbox), dim3(NT), 0, s,
+                     P, Q, mode, boxes, counts, kmean, hist_pm, hist_pnu, nbins, jcap, pcdm, pnu,
+                     ratio, sur_r, sur_use);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(surrogate_finish_kernel, dim3(nbins, nbox), dim3(RT), 0, s, mode, boxes,
+                     counts, kmean, hist_pm, hist_pnu, ic_pnu, ic_theta, tg_ds, tg_w, nbins,
+                     jcap, qcap, q_sub, iterations, pcdm, pnu, ratio, sur_r, sur_use, chk_exact,
+                     chk_sur);
   return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ struct RespBox {
 
 // Launch shapes chosen by the autotuner (defaults are safe for every N).
 struct Tuning {
-  int deposit_mode = 3;      // see launch_deposit
+  int deposit_mode = 2;      // see launch_deposit
   int deposit_block = 256;   // block size of mode 0
   int interp_mode = 1;       // see launch_interp
   int interp_block = 256;    // block size of mode 0
@@ -39,6 +39,8 @@ struct Tuning {
 
 struct Timer {
   bool enabled = false;
+  unsigned mask = ~0u;            // stages that get an event pair (bit = Stage)
+  bool open = false;              // an event pair was begun and not yet ended
   std::vector<hipEvent_t> pool;   // events recorded since the last read
   std::vector<int> stage_of;      // stage of each event pair
   size_t used = 0;                // pairs in use
@@ -181,14 +183,18 @@ hipError_t launch_mlp_train(const float* P, const float* x, const float* y, cons
 hipError_t launch_mlp_predict(const float* P, const float* x, float* y, int64_t n, hipStream_t s);
 hipError_t launch_adam(float* P, const float* g, float* m, float* v, int n, float lr, float b1,
                        float b2, float eps, float c1, float c2, hipStream_t s);
-hipError_t launch_surrogate_response(const float* P, int mode, const RespBox* boxes,
-                                     const double* partial, int n_partial, const double* counts,
-                                     const double* kmean, double* hist_pm, double* hist_pnu,
-                                     const double* ic_pnu, const double* ic_theta,
-                                     const double* tg_ds, const double* tg_w, int nbins, int jcap,
-                                     int qcap, int q_sub, int iterations, double norm, int nbox,
-                                     double* pcdm, double* pnu, double* ratio, double* chk_exact,
-                                     double* chk_sur, hipStream_t s);
+hipError_t launch_pack_weights(const float* P, unsigned short* Q, hipStream_t s);
+int64_t packed_weight_count();
+hipError_t launch_surrogate_response(const float* P, const unsigned short* Q, int mode,
+                                     const RespBox* boxes, const double* partial, int n_partial,
+                                     const double* counts, const double* kmean, double* hist_pm,
+                                     double* hist_pnu, const double* ic_pnu,
+                                     const double* ic_theta, const double* tg_ds,
+                                     const double* tg_w, int nbins, int jcap, int qcap,
+                                     int q_sub, int iterations, double norm, int nbox,
+                                     double* pcdm, double* pnu, double* ratio, double* sur_r,
+                                     int* sur_use, double* chk_exact, double* chk_sur,
+                                     hipStream_t s);
 hipError_t launch_surrogate_dataset(const RespBox* boxes, const double* pcdm, const double* ratio,
                                     const double* kmean, const double* hist_pm, int nbins,
                                     int jcap, int nbox, float* x, float* y, hipStream_t s);

@@ -25,6 +25,10 @@ struct Surrogate {
   int64_t perm_cap = 0;
   double* chk_exact = nullptr; // [nbox][B]
   double* chk_sur = nullptr;   // [nbox][B]
+  unsigned short* packed = nullptr;  // bf16 image of W1..W3 for inference
+  double* sur_r = nullptr;     // [nbox][B] the network's R of the last response
+  int* sur_use = nullptr;      // [nbox][B] 1 where the network answered
+  bool packed_valid = false;   // cleared whenever the FP32 masters change
   bool loaded = false;
   int64_t step = 0;
 };
@@ -32,7 +36,8 @@ struct Surrogate {
 void surrogate_free(Ctx& c) {
   Surrogate* s = c.sur;
   if (!s) return;
-  void* bufs[] = {s->P, s->g, s->m, s->v, s->loss, s->perm, s->chk_exact, s->chk_sur};
+  void* bufs[] = {s->P, s->g, s->m, s->v, s->loss, s->perm, s->chk_exact, s->chk_sur,
+                  s->packed, s->sur_r, s->sur_use};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   delete s;
@@ -53,6 +58,9 @@ int ensure(Ctx& c) {
   if (!e) e = hipMalloc(&s->loss, sizeof(float));
   if (!e) e = hipMalloc(&s->chk_exact, nb * sizeof(double));
   if (!e) e = hipMalloc(&s->chk_sur, nb * sizeof(double));
+  if (!e) e = hipMalloc(&s->packed, packed_weight_count() * sizeof(unsigned short));
+  if (!e) e = hipMalloc(&s->sur_r, nb * sizeof(double));
+  if (!e) e = hipMalloc(&s->sur_use, nb * sizeof(int));
   if (!e) e = hipMemset(s->P, 0, kSurBlob * sizeof(float));
   if (!e) e = hipMemset(s->chk_exact, 0, nb * sizeof(double));
   if (!e) e = hipMemset(s->chk_sur, 0, nb * sizeof(double));
@@ -68,6 +76,7 @@ int reset_optimizer(Ctx& c) {
   PMNU_HIP(hipMemset(s->m, 0, kSurParams * sizeof(float)));
   PMNU_HIP(hipMemset(s->v, 0, kSurParams * sizeof(float)));
   s->step = 0;
+  s->packed_valid = false;
   return PM_NU_OK;
 }
 
@@ -91,12 +100,17 @@ int surrogate_launch(Ctx& c, int mode, double norm) {
   int rc = need_loaded(&c);
   if (rc) return rc;
   Surrogate* s = c.sur;
+  if (!s->packed_valid) {
+    hipError_t e = launch_pack_weights(s->P, s->packed, c.stream);
+    if (e != hipSuccess) return set_error(PM_NU_EHIP, "weight packing: %s", hipGetErrorString(e));
+    s->packed_valid = true;
+  }
   timer_begin(c, ST_SURROGATE);
   hipError_t e = launch_surrogate_response(
-      s->P, mode, c.d_resp, c.bin_partial, c.n_partial, c.d_counts, c.d_kmean, c.hist_pm,
-      c.hist_pnu, c.ic_pnu, c.ic_theta, c.tg_ds, c.tg_w, c.B, c.Jcap, c.qcap, c.Q,
-      c.cfg.iterations, norm, c.nbox, c.pcdm, c.pnu, c.ratio, s->chk_exact, s->chk_sur,
-      c.stream);
+      s->P, s->packed, mode, c.d_resp, c.bin_partial, c.n_partial, c.d_counts, c.d_kmean,
+      c.hist_pm, c.hist_pnu, c.ic_pnu, c.ic_theta, c.tg_ds, c.tg_w, c.B, c.Jcap, c.qcap, c.Q,
+      c.cfg.iterations, norm, c.nbox, c.pcdm, c.pnu, c.ratio, s->sur_r, s->sur_use,
+      s->chk_exact, s->chk_sur, c.stream);
   timer_end(c);
   if (e != hipSuccess) return set_error(PM_NU_EHIP, "surrogate response: %s", hipGetErrorString(e));
   return PM_NU_OK;
@@ -239,6 +253,7 @@ int pm_nu_surrogate_train(pm_nu_ctx* ctx, const float* x, const float* y, int64_
           static_cast<float>(lr * (0.01 + 0.99 * 0.5 * (1.0 + std::cos(kPi * frac))));
       const float c1 = static_cast<float>(1.0 - std::pow(0.9, static_cast<double>(s->step)));
       const float c2 = static_cast<float>(1.0 - std::pow(0.999, static_cast<double>(s->step)));
+      s->packed_valid = false;
       SUR_LAUNCH(launch_adam(s->P, s->g, s->m, s->v, kSurParams, lr_t, 0.9f, 0.999f, 1e-8f, c1, c2,
                              c->stream));
     }

@@ -1,7 +1,7 @@
 """Build the surrogate's training set with the exact integral and train the network on the
 GPU, then write the weight blob.
 
-    python -m paper_1209_0461_amd.train_surrogate --rows 1000000 --epochs 40 --out blob.npy
+    python -m paper_1209_0461_amd.train_surrogate --out paper_1209_0461_amd/data/surrogate_pm256.npy
 
 Prints one JSON line: training loss, held-out (10%) error of y = ln(R (1 + k/k_fs)^2),
 which is also the relative error of R, and the time of each phase.
@@ -15,9 +15,9 @@ import numpy as np
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--rows", type=int, default=1_000_000)
-    ap.add_argument("--epochs", type=int, default=40)
-    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--rows", type=int, default=4_000_000)
+    ap.add_argument("--epochs", type=int, default=1500)
+    ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=4000)
     ap.add_argument("--out", required=True)

@@ -233,14 +233,15 @@ def test_every_launch_mode_matches_oracle(order):
     ctx.set_history(0, hist)
     p = torch.from_numpy(pos).cuda()
     acc = torch.zeros_like(p)
-    for dm, im in ((0, 0), (1, 1), (2, 2), (3, 3), (1, 0), (0, 2)):
-        binding.pm_nu_set_launch(ctx.h, dm, 256, im, 256)
+    for dm, im, ib in ((0, 0, 256), (1, 1, 256), (2, 2, 256), (3, 3, 256), (1, 0, 512),
+                       (0, 2, 256), (4, 0, 1024), (5, 1, 256)):
+        binding.pm_nu_set_launch(ctx.h, dm, 256, im, ib)
         ctx.step(p, acc, 0.7)
         torch.cuda.synchronize()
         ok = ref["counts"] > 0
         sp = ctx.spectrum(0)
-        assert np.abs(sp["p_cdm"][ok] / ref["p_cdm"][ok] - 1).max() <= 2e-6, (order, dm, im)
-        assert rms_rel(acc.cpu().numpy(), ref["acc"]) <= TOL_FORCE_RMS, (order, dm, im)
+        assert np.abs(sp["p_cdm"][ok] / ref["p_cdm"][ok] - 1).max() <= 2e-6, (order, dm, im, ib)
+        assert rms_rel(acc.cpu().numpy(), ref["acc"]) <= TOL_FORCE_RMS, (order, dm, im, ib)
     ctx.close()
 
 
