@@ -35,19 +35,23 @@ KERNEL_SOURCES = {
     "fft_fwd_y": "fft_kernels.hip", "fft_fwd_x_bin": "fft_kernels.hip",
     "inv_x_green": "fft_kernels.hip", "fft_inv_y": "fft_kernels.hip",
     "fft_inv_z": "fft_kernels.hip", "nu_response": "response_kernels.hip",
-    "rtable": "response_kernels.hip",
+    "rtable": "response_kernels.hip", "patch_reduce": "grid_kernels.hip",
 }
 
 
-def stage_bytes(n_mesh, n_part, nbox, nbins, n_hist, n_partial):
+def stage_bytes(n_mesh, n_part, nbox, nbins, n_hist, n_partial, deposit_mode=0):
     """Algorithmic bytes per launch of every kernel: each input read once, each output
-    written once (FP32 grids, complex64 modes, FP32 positions/accelerations)."""
+    written once (FP32 grids, complex64 modes, FP32 positions/accelerations). The patch
+    deposit (mode 6) splits the deposit into reading the positions (cic_deposit) and
+    writing the density contrast (patch_reduce)."""
     m = n_mesh ** 3 * nbox
     mh = n_mesh * n_mesh * (n_mesh // 2 + 1) * nbox
     npt = n_part * nbox
+    patch = deposit_mode == 6
     return {
         "zero_mesh": 4 * m,
-        "cic_deposit": 12 * npt + 4 * m,
+        "cic_deposit": 12 * npt + (0 if patch else 4 * m),
+        "patch_reduce": 4 * m,
         "fft_fwd_z": 4 * m + 8 * mh,
         "fft_fwd_y": 16 * mh,
         "fft_fwd_x_bin": 16 * mh + 8 * n_partial * nbins * nbox,
@@ -77,11 +81,13 @@ def source_sha(name):
 
 def kernel_name(stage, tuning, n_mesh):
     """Name (with template arguments) of the kernel a stage launches, as rocprofv3 lists it."""
-    dep = {1: "<1024, 2560, 256>", 2: "<2048, 4608, 256>", 3: "<4096, 8192, 256>",
-           4: "<4096, 8192, 512>", 5: "<8192, 16384, 1024>"}
+    dep = {1: "<1024, 3328, 256>", 2: "<2048, 5120, 256>", 3: "<4096, 9216, 256>",
+           4: "<4096, 9216, 512>", 5: "<8192, 18432, 1024>"}
     itp = {1: "<1024, 2560>", 2: "<2048, 4608>", 3: "<4096, 8192>"}
     if stage == "cic_deposit":
         m = tuning["deposit_mode"]
+        if m == 6:
+            return "deposit_patch_kernel<4096, 9216, 512>"
         return "deposit_tiled_kernel" + dep[m] if m else "deposit_kernel"
     if stage == "cic_interp":
         m = tuning["interp_mode"]
@@ -89,12 +95,14 @@ def kernel_name(stage, tuning, n_mesh):
             return "interp_tiled_kernel" + itp[m]
         return "interp_kernel<%d>" % max(1, min(4, tuning["interp_block"] // 256))
     fixed = {"zero_mesh": "fill_zero_kernel", "nu_response": "response_kernel",
-             "rtable": "rtable_kernel"}
+             "rtable": "rtable_kernel", "patch_reduce": "patch_reduce_kernel"}
     if stage in fixed:
         return fixed[stage]
     fft = {"fft_fwd_z": "fwd_z_kernel", "fft_fwd_y": "fwd_y_kernel",
            "fft_fwd_x_bin": "fwd_x_bin_kernel", "inv_x_green": "inv_x_kernel",
            "fft_inv_y": "inv_y_kernel", "fft_inv_z": "inv_z_kernel"}
+    if stage == "fft_fwd_z":
+        return "fwd_z_kernel<%d, %s>" % (n_mesh, "true" if tuning["deposit_mode"] == 6 else "false")
     return "%s<%d>" % (fft[stage], n_mesh)
 
 
@@ -283,7 +291,7 @@ def main():
 
     from paper_1209_0461_amd.binding import load_library  # noqa: F401
     n_partial = (n_mesh // min(16 if n_mesh <= 256 else 8, n_mesh)) * (n_mesh // 2 + 1)
-    sb = stage_bytes(n_mesh, npart, nbox, nbins, J, n_partial)
+    sb = stage_bytes(n_mesh, npart, nbox, nbins, J, n_partial, tuning["deposit_mode"])
     stages = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1],
                   "gbs": sb.get(k, 0) / (v[0] / v[1] * 1e-3) / 1e9 if k in sb else None}
               for k, v in timing.items() if v[1] > 0}

@@ -174,8 +174,10 @@ int pm_nu_graph_launch(pm_nu_ctx* ctx);
 int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
                    const char* cache_path);
 /* Set the launch shapes directly: deposit_mode 0 (one thread per particle, global atomics;
- * deposit_block = threads per workgroup) or 1..5 (LDS-privatised chunks of 1024/2048/4096
- * particles on 256 threads, 4096 on 512 threads, 8192 on 1024 threads), interp_mode 0 (direct gather; interp_block = particles per workgroup, rounded
+ * deposit_block = threads per workgroup), 1..5 (LDS-privatised chunks of 1024/2048/4096
+ * particles on 256 threads, 4096 on 512 threads, 8192 on 1024 threads, flushed with global
+ * atomics) or 6 (chunks of 4096 written to per-chunk patches and summed per 16^3 coarse
+ * cell without atomics; chunks that do not fit use atomics on a side grid), interp_mode 0 (direct gather; interp_block = particles per workgroup, rounded
  * down to 256, 512 or 1024) or 1/2/3 (LDS-staged chunks). Blocks: multiples of 64 in
  * 64..1024. */
 int pm_nu_set_launch(pm_nu_ctx* ctx, int deposit_mode, int deposit_block, int interp_mode,

@@ -47,27 +47,55 @@ template <int N> struct Shape {
 __device__ __forceinline__ int signed_index(int i, int n) { return i < n / 2 ? i : i - n; }
 
 // ------------------------------------------------------------------------ forward ----
-template <int N>
-__global__ __launch_bounds__(NT) void fwd_z_kernel(const unsigned long long* __restrict__ rho,
+// Input: the fixed-point density (DELTA = false; delta = rho / rho_bar - 1 is formed here
+// from the exact sum and rounded once to FP32) or delta already in FP32 (DELTA = true;
+// then thread 0 of the first workgroup also clears the side-grid counter of the patch
+// deposit, whose last reader ran before this kernel).
+template <int N, bool DELTA>
+__global__ __launch_bounds__(NT) void fwd_z_kernel(const void* __restrict__ in,
                                                    float2* __restrict__ out,
                                                    const float2* __restrict__ twg,
-                                                   double scale) {
+                                                   double scale, int* __restrict__ reset) {
   constexpr int TY = Shape<N>::FZ_TY, NL = TY / 2, ES = NL + 1, NK = Shape<N>::NK;
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
   const int y0 = blockIdx.x * TY, x = blockIdx.y, box = blockIdx.z;
   load_twiddles<N, NT>(tw, twg);
-  const ulonglong2* src = reinterpret_cast<const ulonglong2*>(
-      rho + ((static_cast<size_t>(box) * N + x) * N + y0) * N);
+  const size_t off = ((static_cast<size_t>(box) * N + x) * N + y0) * N;
   float* ldsf = reinterpret_cast<float*>(lds);
-  for (int t = threadIdx.x; t < TY * N / 2; t += NT) {
-    const int row = (2 * t) / N, e = (2 * t) % N;
-    const ulonglong2 v = src[t];
-    // delta = rho / rho_bar - 1 from the exact fixed-point sum, rounded once to FP32
-    ldsf[(e * ES + (row >> 1)) * 2 + (row & 1)] =
-        static_cast<float>(static_cast<double>(v.x) * scale - 1.0);
-    ldsf[((e + 1) * ES + (row >> 1)) * 2 + (row & 1)] =
-        static_cast<float>(static_cast<double>(v.y) * scale - 1.0);
+  if constexpr (DELTA) {
+    if (reset && threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0)
+      *reset = 0;
+    const float4* src = reinterpret_cast<const float4*>(static_cast<const float*>(in) + off);
+    constexpr int IT = (TY * N / 4 + NT - 1) / NT;
+    float4 v[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int t = threadIdx.x + i * NT;
+      if (t < TY * N / 4) v[i] = src[t];
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int t = threadIdx.x + i * NT;
+      if (t >= TY * N / 4) break;
+      const int row = (4 * t) / N, e = (4 * t) % N, sl = row & 1, p = row >> 1;
+      ldsf[(e * ES + p) * 2 + sl] = v[i].x;
+      ldsf[((e + 1) * ES + p) * 2 + sl] = v[i].y;
+      ldsf[((e + 2) * ES + p) * 2 + sl] = v[i].z;
+      ldsf[((e + 3) * ES + p) * 2 + sl] = v[i].w;
+    }
+  } else {
+    const ulonglong2* src =
+        reinterpret_cast<const ulonglong2*>(static_cast<const unsigned long long*>(in) + off);
+    for (int t = threadIdx.x; t < TY * N / 2; t += NT) {
+      const int row = (2 * t) / N, e = (2 * t) % N;
+      const ulonglong2 v = src[t];
+      // delta = rho / rho_bar - 1 from the exact fixed-point sum, rounded once to FP32
+      ldsf[(e * ES + (row >> 1)) * 2 + (row & 1)] =
+          static_cast<float>(static_cast<double>(v.x) * scale - 1.0);
+      ldsf[((e + 1) * ES + (row >> 1)) * 2 + (row & 1)] =
+          static_cast<float>(static_cast<double>(v.y) * scale - 1.0);
+    }
   }
   __syncthreads();
   fft_lines<N, NL, NT, -1>(lds, tw);
@@ -413,10 +441,15 @@ hipError_t dispatch_n(int n, A... args) {
 }
 
 template <int N> struct FwdZ {
-  static hipError_t run(const unsigned long long* rho, float2* out, const float2* tw,
-                        double scale, int nbox, hipStream_t s) {
+  static hipError_t run(const unsigned long long* rho, const float* delta, int* reset,
+                        float2* out, const float2* tw, double scale, int nbox, hipStream_t s) {
     dim3 grid(N / Shape<N>::FZ_TY, N, nbox);
-    hipLaunchKernelGGL(fwd_z_kernel<N>, grid, dim3(NT), 0, s, rho, out, tw, scale);
+    if (delta)
+      hipLaunchKernelGGL((fwd_z_kernel<N, true>), grid, dim3(NT), 0, s, delta, out, tw, scale,
+                         reset);
+    else
+      hipLaunchKernelGGL((fwd_z_kernel<N, false>), grid, dim3(NT), 0, s, rho, out, tw, scale,
+                         reset);
     return hipGetLastError();
   }
 };
@@ -480,9 +513,9 @@ template <int N> struct Partials {
 
 }  // namespace
 
-hipError_t launch_fwd_z(int n, const unsigned long long* rho, float2* out, const float2* tw,
-                        double scale, int nbox, hipStream_t s) {
-  return dispatch_n<FwdZ>(n, rho, out, tw, scale, nbox, s);
+hipError_t launch_fwd_z(int n, const unsigned long long* rho, const float* delta, int* reset,
+                        float2* out, const float2* tw, double scale, int nbox, hipStream_t s) {
+  return dispatch_n<FwdZ>(n, rho, delta, reset, out, tw, scale, nbox, s);
 }
 hipError_t launch_fwd_y(int n, const float2* in, float2* out, const float2* tw, int nbox,
                         hipStream_t s) {

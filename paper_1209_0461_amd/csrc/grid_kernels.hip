@@ -190,11 +190,13 @@ __device__ __forceinline__ void load_chunk(Chunk<PPT>& c, const float* p, int cn
       mx[a] = max(mx[a], red[3 + a][w]);
     }
   }
-  c.any = mn[0] <= mx[0];
+  // the box is the same for the whole workgroup: keep it in scalar registers
+  c.any = __builtin_amdgcn_readfirstlane(mn[0] <= mx[0] ? 1 : 0) != 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    c.mn[a] = mn[a];
-    c.ext[a] = c.any ? mx[a] - mn[a] + 2 : 0;
+    c.r[a] = __builtin_amdgcn_readfirstlane(c.r[a]);
+    c.mn[a] = __builtin_amdgcn_readfirstlane(mn[a]);
+    c.ext[a] = c.any ? __builtin_amdgcn_readfirstlane(mx[a] - mn[a] + 2) : 0;
   }
 }
 
@@ -255,7 +257,15 @@ __global__ __launch_bounds__(NT) void deposit_tiled_kernel(const float* __restri
   load_chunk<PPT, NT>(c, pos + (box * np + c0) * 3, cnt, inv_cell, nmask, red, bad);
   if (bad) atomicOr(flags, 1);
   const int ex = c.ext[0], ey = c.ext[1], ez = c.ext[2];
-  const int vol = ex * ey * ez;
+  // Tile strides padded so that a wave's 16-lane groups of particles along the curve
+  // (2 x 2 x 4 blocks of nodes for lattice-ordered chunks) hit 16 distinct 8-byte bank
+  // slots: z stride = 4 (mod 8), y stride = 2 (mod 4). Unpadded if the padding does not fit.
+  int sz = ez + ((12 - ez % 8) % 8), sy = ey + ((6 - ey % 4) % 4);
+  if (ex * sy * sz > CAP) {
+    sz = ez;
+    sy = ey;
+  }
+  const int vol = ex * sy * sz;
   if (c.any && vol <= CAP && ex <= n && ey <= n && ez <= n) {
     for (int t = tid; t < vol; t += NT) tile[t] = 0ull;
     __syncthreads();
@@ -274,13 +284,13 @@ __global__ __launch_bounds__(NT) void deposit_tiled_kernel(const float* __restri
       const double wx[2] = {(1.0 - d[0]) * kFixScale, d[0] * kFixScale};
       const double wy[2] = {1.0 - d[1], d[1]};
       const double wz0 = 1.0 - d[2], wz1 = d[2];
-      const int base = (t[0] * ey + t[1]) * ez + t[2];
+      const int base = (t[0] * sy + t[1]) * sz + t[2];
 #pragma unroll
       for (int cx = 0; cx < 2; ++cx) {
 #pragma unroll
         for (int cy = 0; cy < 2; ++cy) {
           const double wxy = wx[cx] * wy[cy];
-          const int o = base + (cx * ey + cy) * ez;
+          const int o = base + (cx * sy + cy) * sz;
           atomicAdd(&tile[o], fix_rn(wxy * wz0));
           atomicAdd(&tile[o + 1], fix_rn(wxy * wz1));
         }
@@ -288,8 +298,8 @@ __global__ __launch_bounds__(NT) void deposit_tiled_kernel(const float* __restri
     }
     __syncthreads();
     const int gx0 = c.r[0] + c.mn[0], gy0 = c.r[1] + c.mn[1], gz0 = c.r[2] + c.mn[2];
-    for_box_nodes<NT>(ex, ey, ez, [&](int tx, int ty, int tz, int li) {
-      const unsigned long long v = tile[li];
+    for_box_nodes<NT>(ex, ey, ez, [&](int tx, int ty, int tz, int) {
+      const unsigned long long v = tile[(tx * sy + ty) * sz + tz];
       if (v == 0ull) return;
       const unsigned gx = (gx0 + tx) & nmask, gy = (gy0 + ty) & nmask, gz = (gz0 + tz) & nmask;
       atomicAdd(g + (gx * n + gy) * n + gz, v);
@@ -305,6 +315,256 @@ __global__ __launch_bounds__(NT) void deposit_tiled_kernel(const float* __restri
       deposit_global(g, n, i, d, nmask);
     }
   }
+}
+
+// ---------------------------------------------------------------- patch deposit ----
+// Deposit without global atomics. D1: each chunk sums its particles in an LDS tile as
+// above, writes the tile (its box, unpadded) to its own patch slot with plain stores and
+// registers the patch in every coarse cell (CB^3 nodes) that the box overlaps. D2: one
+// workgroup per coarse cell adds up the registered patches in exact integers and writes
+// delta = rho / rho_bar - 1 once, rounded to FP32. Chunks that cannot be patched (box too
+// large, or a coarse cell's list full) add their weights with global atomics to a side
+// grid kept at zero, which D2 folds in (and clears) only when such chunks exist.
+constexpr int kPatchList = 32;      // patches per coarse cell
+constexpr int kPatchRegMax = 27;    // coarse cells per patch
+
+__device__ __forceinline__ int ceil_div_pow2(int a, int lg) { return (a + (1 << lg) - 1) >> lg; }
+
+template <int CH, int CAP, int NT>
+__global__ __launch_bounds__(NT) void deposit_patch_kernel(
+    const float* __restrict__ pos, unsigned long long* __restrict__ patches,
+    int4* __restrict__ hdr, int* __restrict__ status, int* __restrict__ reg_count,
+    int* __restrict__ reg_list, unsigned long long* __restrict__ rho_fb, int* __restrict__ n_fb,
+    int64_t np, int n, double inv_cell, int* __restrict__ flags, int64_t chunks_per_box,
+    int cb_lg) {
+  constexpr int PPT = CH / NT;
+  __shared__ unsigned long long tile[CAP];
+  __shared__ int red[6][NT / 64];
+  __shared__ int s_fail;
+  const int tid = threadIdx.x;
+  const int64_t chunk = blockIdx.x;
+  const int64_t box = chunk / chunks_per_box;
+  const int64_t c0 = (chunk - box * chunks_per_box) * CH;
+  const int cnt = static_cast<int>(min(static_cast<int64_t>(CH), np - c0));
+  const int nmask = n - 1;
+  const int64_t m = static_cast<int64_t>(n) * n * n;
+  unsigned long long* fb = rho_fb + box * m;
+  if (tid == 0) s_fail = 0;
+  Chunk<PPT> c;
+  bool bad = false;
+  load_chunk<PPT, NT>(c, pos + (box * np + c0) * 3, cnt, inv_cell, nmask, red, bad);
+  if (bad) atomicOr(flags, 1);
+  const int ex = c.ext[0], ey = c.ext[1], ez = c.ext[2];
+  int sz = ez + ((12 - ez % 8) % 8), sy = ey + ((6 - ey % 4) % 4);
+  if (ex * sy * sz > CAP) {
+    sz = ez;
+    sy = ey;
+  }
+  const int vol = ex * sy * sz;
+  const int gx0 = (c.r[0] + c.mn[0]) & nmask, gy0 = (c.r[1] + c.mn[1]) & nmask,
+            gz0 = (c.r[2] + c.mn[2]) & nmask;
+  const int nc = n >> cb_lg;
+  const int rx = min(nc, ceil_div_pow2((gx0 & ((1 << cb_lg) - 1)) + ex, cb_lg));
+  const int ry = min(nc, ceil_div_pow2((gy0 & ((1 << cb_lg) - 1)) + ey, cb_lg));
+  const int rz = min(nc, ceil_div_pow2((gz0 & ((1 << cb_lg) - 1)) + ez, cb_lg));
+  const bool fits = c.any && vol <= CAP && ex <= n && ey <= n && ez <= n &&
+                    rx * ry * rz <= kPatchRegMax;
+  if (fits) {
+    // register the patch in the coarse cells its box overlaps
+    const int64_t cells = static_cast<int64_t>(nc) * nc * nc;
+    const int fx = gx0 >> cb_lg, fy = gy0 >> cb_lg, fz = gz0 >> cb_lg;
+    for (int t = tid; t < rx * ry * rz; t += NT) {
+      const int iz = t % rz, ixy = t / rz, iy = ixy % ry, ix = ixy / ry;
+      const int64_t cell = box * cells +
+                           ((static_cast<int64_t>((fx + ix) % nc) * nc + (fy + iy) % nc) * nc +
+                            (fz + iz) % nc);
+      const int slot = atomicAdd(reg_count + cell, 1);
+      if (slot < kPatchList)
+        reg_list[cell * kPatchList + slot] = static_cast<int>(chunk);
+      else
+        s_fail = 1;
+    }
+    for (int t = tid; t < vol; t += NT) tile[t] = 0ull;
+    __syncthreads();
+    const int half = n / 2;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      if (!c.ok[q]) continue;
+      int t[3];
+      double d[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        int i;
+        axis64(c.p[q][a], inv_cell, nmask, i, d[a]);
+        t[a] = ((i - c.r[a] + half) & nmask) - half - c.mn[a];
+      }
+      const double wx[2] = {(1.0 - d[0]) * kFixScale, d[0] * kFixScale};
+      const double wy[2] = {1.0 - d[1], d[1]};
+      const double wz0 = 1.0 - d[2], wz1 = d[2];
+      const int base = (t[0] * sy + t[1]) * sz + t[2];
+#pragma unroll
+      for (int cx = 0; cx < 2; ++cx) {
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy) {
+          const double wxy = wx[cx] * wy[cy];
+          const int o = base + (cx * sy + cy) * sz;
+          atomicAdd(&tile[o], fix_rn(wxy * wz0));
+          atomicAdd(&tile[o + 1], fix_rn(wxy * wz1));
+        }
+      }
+    }
+    __syncthreads();
+    if (s_fail == 0) {
+      unsigned long long* pat = patches + chunk * CAP;
+      for_box_nodes<NT>(ex, ey, ez, [&](int tx, int ty, int tz, int li) {
+        pat[li] = tile[(tx * sy + ty) * sz + tz];
+      });
+      if (tid == 0) {
+        hdr[chunk] = make_int4(gx0, gy0, gz0, ex | (ey << 10) | (ez << 20));
+        status[chunk] = 0;
+      }
+      return;
+    }
+    // a coarse cell's list was full: add the tile to the side grid instead
+    for_box_nodes<NT>(ex, ey, ez, [&](int tx, int ty, int tz, int) {
+      const unsigned long long v = tile[(tx * sy + ty) * sz + tz];
+      if (v == 0ull) return;
+      const unsigned gx = (gx0 + tx) & nmask, gy = (gy0 + ty) & nmask, gz = (gz0 + tz) & nmask;
+      atomicAdd(fb + (gx * n + gy) * n + gz, v);
+    });
+  } else {
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      if (!c.ok[q]) continue;
+      int i[3];
+      double d[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) axis64(c.p[q][a], inv_cell, nmask, i[a], d[a]);
+      deposit_global(fb, n, i, d, nmask);
+    }
+  }
+  if (tid == 0) {
+    status[chunk] = 1;
+    atomicAdd(n_fb, 1);
+  }
+}
+
+// Up to two pieces of the overlap of a periodic patch interval [p, p + e) with the cell
+// interval [cs, cs + cb) on an axis of length n (e <= n): patch-local start, cell-local
+// start and length of each.
+struct Pieces {
+  int cnt;
+  int pl[2], cl[2], len[2];
+};
+__device__ __forceinline__ Pieces overlap(int p, int e, int cs, int cb, int n) {
+  Pieces r;
+  r.cnt = 0;
+  const int d2 = (p - cs + n) & (n - 1);        // cell-local index of the patch start
+  if (d2 < cb) {
+    r.pl[r.cnt] = 0;
+    r.cl[r.cnt] = d2;
+    r.len[r.cnt] = min(e, cb - d2);
+    ++r.cnt;
+  }
+  const int w = n - d2;                         // patch-local index where it re-enters
+  if (d2 != 0 && w < e) {
+    r.pl[r.cnt] = w;
+    r.cl[r.cnt] = 0;
+    r.len[r.cnt] = min(e - w, cb);
+    ++r.cnt;
+  }
+  return r;
+}
+
+// D2: one workgroup of 256 threads per (coarse cell, box), CB = 1 << cb_lg <= 16. Thread
+// (iy, iz) owns the column x = 0..CB-1 of the cell and keeps its sums in registers; for
+// each patch it issues the loads of the whole column at once (whether x lies in the patch
+// is the same for every thread, so that test is a scalar branch).
+__global__ __launch_bounds__(256) void patch_reduce_kernel(
+    const unsigned long long* __restrict__ patches, int pcap, const int4* __restrict__ hdr,
+    const int* __restrict__ status, int* __restrict__ reg_count,
+    const int* __restrict__ reg_list, unsigned long long* __restrict__ rho_fb,
+    const int* __restrict__ n_fb, float* __restrict__ delta, int n, int cb_lg, double scale) {
+  constexpr int CBM = 16;
+  const int tid = threadIdx.x;
+  const int cb = 1 << cb_lg, nc = n >> cb_lg;
+  const int64_t cells = static_cast<int64_t>(nc) * nc * nc;
+  const int64_t box = blockIdx.y;
+  const int64_t cell = box * cells + blockIdx.x;
+  const int ccz = (blockIdx.x % nc) << cb_lg, ccy = ((blockIdx.x / nc) % nc) << cb_lg,
+            ccx = (blockIdx.x / (nc * nc)) << cb_lg;
+  const int iy = tid >> cb_lg, iz = tid & (cb - 1);
+  const bool on = tid < cb * cb;
+  unsigned long long acc[CBM];
+#pragma unroll
+  for (int x = 0; x < CBM; ++x) acc[x] = 0ull;
+  // the cell's patch list, with each patch's status and header, fetched in parallel once
+  __shared__ int4 s_hdr[kPatchList];
+  __shared__ int s_chunk[kPatchList];
+  const int cntr = __builtin_amdgcn_readfirstlane(min(reg_count[cell], kPatchList));
+  if (tid < cntr) {
+    const int chunk = reg_list[cell * kPatchList + tid];
+    s_chunk[tid] = status[chunk] ? -1 : chunk;  // -1: added through the side grid instead
+    s_hdr[tid] = hdr[chunk];
+  }
+  __syncthreads();
+  for (int e = 0; e < cntr; ++e) {
+    const int chunk = __builtin_amdgcn_readfirstlane(s_chunk[e]);
+    if (chunk < 0) continue;
+    const int4 h = s_hdr[e];
+    const int ex = h.w & 1023, ey = (h.w >> 10) & 1023, ez = h.w >> 20;
+    const Pieces px = overlap(h.x, ex, ccx, cb, n), py = overlap(h.y, ey, ccy, cb, n),
+                 pz = overlap(h.z, ez, ccz, cb, n);
+    // this thread's row (y, z) inside the patch, if any
+    int ly = -1, lz = -1;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (q < py.cnt && iy >= py.cl[q] && iy < py.cl[q] + py.len[q]) ly = py.pl[q] + iy - py.cl[q];
+      if (q < pz.cnt && iz >= pz.cl[q] && iz < pz.cl[q] + pz.len[q]) lz = pz.pl[q] + iz - pz.cl[q];
+    }
+    const bool lane_in = on && ly >= 0 && lz >= 0;
+    const unsigned long long* row =
+        patches + static_cast<int64_t>(chunk) * pcap + (lane_in ? ly * ez + lz : 0);
+    const int xs = ey * ez;                     // patch stride along x
+    unsigned long long v[CBM];
+#pragma unroll
+    for (int x = 0; x < CBM; ++x) {
+      int lx = -1;                              // patch-local x of cell-local x (uniform)
+      if (x < cb) {
+        if (px.cnt > 0 && x >= px.cl[0] && x < px.cl[0] + px.len[0]) lx = px.pl[0] + x - px.cl[0];
+        if (px.cnt > 1 && x >= px.cl[1] && x < px.cl[1] + px.len[1]) lx = px.pl[1] + x - px.cl[1];
+      }
+      v[x] = (lx >= 0 && lane_in) ? row[lx * xs] : 0ull;
+    }
+#pragma unroll
+    for (int x = 0; x < CBM; ++x) acc[x] += v[x];
+  }
+  const bool fold = *n_fb > 0;
+  if (on) {
+    const int64_t m = static_cast<int64_t>(n) * n * n;
+    const int64_t col = box * m + static_cast<int64_t>(ccy + iy) * n + ccz + iz;
+#pragma unroll
+    for (int x = 0; x < CBM; ++x) {
+      if (x >= cb) break;
+      const int64_t node = col + static_cast<int64_t>(ccx + x) * n * n;
+      unsigned long long val = acc[x];
+      if (fold) {
+        val += rho_fb[node];
+        rho_fb[node] = 0ull;
+      }
+      // exact integer sum, rounded once: delta = rho / rho_bar - 1
+      delta[node] = static_cast<float>(static_cast<double>(val) * scale - 1.0);
+    }
+  }
+  if (tid == 0) reg_count[cell] = 0;            // ready for the next deposit
+}
+
+__global__ void delta_to_density_kernel(const float* __restrict__ delta, float* __restrict__ out,
+                                        int64_t n, float rho_bar) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += stride)
+    out[i] = (delta[i] + 1.0f) * rho_bar;
 }
 
 // FP32 corner weights of one particle (the fraction rounded once to FP32).
@@ -428,17 +688,19 @@ __global__ __launch_bounds__(256) void interp_tiled_kernel(const float* __restri
     if (3 * ez <= 64 && rows <= 4 * RMAX) {
       // one row (3 ez consecutive floats, contiguous in HBM unless z wraps) per wave and
       // step; all of a wave's row loads are in flight before the LDS stores
-      const int lane = tid & 63, wv = tid >> 6;
+      const int lane = tid & 63;
+      const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar row walk
       const int tz = lane / 3, comp = lane - 3 * tz;
       const bool on = lane < 3 * ez;
-      const unsigned gz = (gz0 + tz) & nmask;
+      const unsigned lane_off = 3 * ((gz0 + tz) & nmask) + comp;
       float vals[RMAX];
       int tx = wv / ey, ty = wv - (wv / ey) * ey;
 #pragma unroll
       for (int i = 0; i < RMAX; ++i) {
-        if (on && wv + 4 * i < rows) {
+        if (wv + 4 * i < rows) {
           const unsigned gx = (gx0 + tx) & nmask, gy = (gy0 + ty) & nmask;
-          vals[i] = g[3 * ((gx * n + gy) * n + gz) + comp];
+          const float* rowp = g + 3 * static_cast<size_t>((gx * n + gy) * n);
+          if (on) vals[i] = rowp[lane_off];
         }
         ty += 4;
         while (ty >= ey) {
@@ -569,16 +831,54 @@ hipError_t launch_tiled(const float* pos, unsigned long long* rho, int64_t np, i
 hipError_t launch_deposit(const float* pos, unsigned long long* rho, int64_t np, int nbox, int n,
                           double inv_cell, int* flags, int mode, int block, hipStream_t s) {
   switch (mode) {
-    case 1: return launch_tiled<1024, 2560, 256>(pos, rho, np, nbox, n, inv_cell, flags, s);
-    case 2: return launch_tiled<2048, 4608, 256>(pos, rho, np, nbox, n, inv_cell, flags, s);
-    case 3: return launch_tiled<4096, 8192, 256>(pos, rho, np, nbox, n, inv_cell, flags, s);
-    case 4: return launch_tiled<4096, 8192, 512>(pos, rho, np, nbox, n, inv_cell, flags, s);
-    case 5: return launch_tiled<8192, 16384, 1024>(pos, rho, np, nbox, n, inv_cell, flags, s);
+    case 1: return launch_tiled<1024, 3328, 256>(pos, rho, np, nbox, n, inv_cell, flags, s);
+    case 2: return launch_tiled<2048, 5120, 256>(pos, rho, np, nbox, n, inv_cell, flags, s);
+    case 3: return launch_tiled<4096, 9216, 256>(pos, rho, np, nbox, n, inv_cell, flags, s);
+    case 4: return launch_tiled<4096, 9216, 512>(pos, rho, np, nbox, n, inv_cell, flags, s);
+    case 5: return launch_tiled<8192, 18432, 1024>(pos, rho, np, nbox, n, inv_cell, flags, s);
     default:
       hipLaunchKernelGGL(deposit_kernel, dim3(grid_blocks(np * nbox, block, 1)), dim3(block), 0,
                          s, pos, rho, np, nbox, n, inv_cell, flags);
       return hipGetLastError();
   }
+}
+
+int patch_cb_log2(int n) { return n >= 16 ? 4 : 3; }
+int64_t patch_coarse_cells(int n) {
+  const int64_t nc = n >> patch_cb_log2(n);
+  return nc * nc * nc;
+}
+int64_t patch_chunks(int64_t np) { return (np + kPatchCH - 1) / kPatchCH; }
+
+hipError_t launch_deposit_patch(const float* pos, unsigned long long* patches, int4* hdr,
+                                int* status, int* reg_count, int* reg_list,
+                                unsigned long long* rho_fb, int* n_fb, int64_t np, int nbox,
+                                int n, double inv_cell, int* flags, hipStream_t s) {
+  const int64_t chunks = patch_chunks(np);
+  hipLaunchKernelGGL((deposit_patch_kernel<kPatchCH, kPatchCap, kPatchNT>),
+                     dim3(static_cast<unsigned>(chunks * nbox)), dim3(kPatchNT), 0, s, pos,
+                     patches, hdr, status, reg_count, reg_list, rho_fb, n_fb, np, n, inv_cell,
+                     flags, chunks, patch_cb_log2(n));
+  return hipGetLastError();
+}
+
+hipError_t launch_patch_reduce(const unsigned long long* patches, const int4* hdr,
+                               const int* status, int* reg_count, const int* reg_list,
+                               unsigned long long* rho_fb, const int* n_fb, float* delta,
+                               int nbox, int n, double scale, hipStream_t s) {
+  hipLaunchKernelGGL(patch_reduce_kernel,
+                     dim3(static_cast<unsigned>(patch_coarse_cells(n)), nbox), dim3(256), 0, s,
+                     patches, kPatchCap, hdr, status, reg_count, reg_list, rho_fb, n_fb, delta, n,
+                     patch_cb_log2(n), scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_delta_to_density(const float* delta, float* out, int64_t n, float rho_bar,
+                                   hipStream_t s) {
+  int blocks = static_cast<int>(std::min<int64_t>((n + 255) / 256, 8192));
+  hipLaunchKernelGGL(delta_to_density_kernel, dim3(blocks), dim3(256), 0, s, delta, out, n,
+                     rho_bar);
+  return hipGetLastError();
 }
 
 // Blocks rounded up to whole XCD rounds; the extra blocks exit at once.

@@ -17,7 +17,8 @@ namespace pmnu {
 
 const char* const kStageNames[ST_COUNT] = {
     "zero_mesh", "cic_deposit", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x_bin", "nu_response",
-    "rtable", "inv_x_green", "fft_inv_y", "fft_inv_z", "cic_interp", "surrogate"};
+    "rtable", "inv_x_green", "fft_inv_y", "fft_inv_z", "cic_interp", "surrogate",
+    "patch_reduce"};
 
 namespace {
 thread_local std::string g_err = "no error";
@@ -295,12 +296,27 @@ namespace {
 int do_deposit(Ctx& c, const float* pos) {
   if (!pos) return set_error(PM_NU_EINVAL, "pos is NULL");
   const int64_t cells = c.M * c.nbox;
-  TIMED(c, ST_ZERO, launch_fill_zero(c.rho, cells * 8, c.stream));
-  TIMED(c, ST_DEPOSIT, launch_deposit(pos, c.rho, c.Np, c.nbox, c.N, c.N / c.cfg.box_size,
-                                      c.d_flags, c.tune.deposit_mode, c.tune.deposit_block,
-                                      c.stream));
+  const double inv_cell = c.N / c.cfg.box_size;
   const double scale = static_cast<double>(c.M) / static_cast<double>(c.Np) / kFixScale;
-  TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, c.rho, c.ck[1], c.tw, scale, c.nbox, c.stream));
+  if (c.tune.deposit_mode == 6) {
+    TIMED(c, ST_DEPOSIT,
+          launch_deposit_patch(pos, c.patches, c.patch_hdr, c.patch_status, c.reg_count,
+                               c.reg_list, c.rho_fb, c.n_fb, c.Np, c.nbox, c.N, inv_cell,
+                               c.d_flags, c.stream));
+    TIMED(c, ST_PATCH_REDUCE,
+          launch_patch_reduce(c.patches, c.patch_hdr, c.patch_status, c.reg_count, c.reg_list,
+                              c.rho_fb, c.n_fb, c.delta, c.nbox, c.N, scale, c.stream));
+    TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, nullptr, c.delta, c.n_fb, c.ck[1], c.tw, scale,
+                                    c.nbox, c.stream));
+    c.density_is_delta = true;
+  } else {
+    TIMED(c, ST_ZERO, launch_fill_zero(c.rho, cells * 8, c.stream));
+    TIMED(c, ST_DEPOSIT, launch_deposit(pos, c.rho, c.Np, c.nbox, c.N, inv_cell, c.d_flags,
+                                        c.tune.deposit_mode, c.tune.deposit_block, c.stream));
+    TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, c.rho, nullptr, nullptr, c.ck[1], c.tw, scale,
+                                    c.nbox, c.stream));
+    c.density_is_delta = false;
+  }
   TIMED(c, ST_FFT_Y, launch_fwd_y(c.N, c.ck[1], c.ck[0], c.tw, c.nbox, c.stream));
   TIMED(c, ST_FFT_X_BIN, launch_fwd_x_bin(c.N, c.ck[0], c.tw, c.bin_of_n2, c.bin_partial,
                                           c.B, c.nbox, c.stream));
@@ -385,7 +401,9 @@ void free_ctx(Ctx* c) {
                   c->bin_partial,
                   c->bin_of_n2, c->d_counts, c->d_kmean, c->d_lnk, c->d_nonempty, c->pcdm, c->pnu,
                   c->ratio, c->hist_pm, c->hist_pnu, c->ic_pnu, c->ic_theta, c->tg_ds,
-                  c->tg_w, c->d_resp, c->rtable, c->tw, c->inv_w2, c->d_flags};
+                  c->tg_w, c->d_resp, c->rtable, c->tw, c->inv_w2, c->d_flags, c->patches,
+                  c->patch_hdr, c->patch_status, c->reg_count, c->reg_list, c->rho_fb, c->n_fb,
+                  c->delta};
   for (void* p : bufs)
     if (p) hipFree(p);
   delete c;
@@ -496,6 +514,18 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   ALLOC(c->tw, static_cast<size_t>(c->N));
   ALLOC(c->inv_w2, static_cast<size_t>(c->N));
   ALLOC(c->d_flags, 1);
+  {
+    const size_t chunks = nb * static_cast<size_t>(patch_chunks(c->Np));
+    const size_t coarse = nb * static_cast<size_t>(patch_coarse_cells(c->N));
+    ALLOC(c->patches, chunks * kPatchCap);
+    ALLOC(c->patch_hdr, chunks);
+    ALLOC(c->patch_status, chunks);
+    ALLOC(c->reg_count, coarse);
+    ALLOC(c->reg_list, coarse * 32);
+    ALLOC(c->rho_fb, nb * c->M);
+    ALLOC(c->n_fb, 1);
+    ALLOC(c->delta, nb * c->M);
+  }
 #undef ALLOC
   build_bins(*c);
   if (c->nonempty.empty()) {
@@ -531,6 +561,10 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   e = e ? e : hipMemset(c->pcdm, 0, nb * B * sizeof(double));
   e = e ? e : hipMemset(c->pnu, 0, nb * B * sizeof(double));
   e = e ? e : hipMemset(c->ratio, 0, nb * B * sizeof(double));
+  // the patch deposit keeps these at zero between deposits
+  e = e ? e : hipMemset(c->reg_count, 0, nb * patch_coarse_cells(c->N) * sizeof(int));
+  e = e ? e : hipMemset(c->rho_fb, 0, nb * c->M * sizeof(unsigned long long));
+  e = e ? e : hipMemset(c->n_fb, 0, sizeof(int));
   e = e ? e : hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_ctx(c);
@@ -704,7 +738,12 @@ int pm_nu_get_spectrum(pm_nu_ctx* ctx, int box, double* p_cdm, double* pnu_half,
 int pm_nu_copy_density(pm_nu_ctx* ctx, int box, float* out) {
   GET_CTX(ctx);
   if (box < 0 || box >= c->nbox || !out) return set_error(PM_NU_EINVAL, "bad box/out");
-  hipError_t e = launch_fixed_to_float(c->rho + box * c->M, out, c->M, c->stream);
+  hipError_t e =
+      c->density_is_delta
+          ? launch_delta_to_density(c->delta + box * c->M, out, c->M,
+                                    static_cast<float>(static_cast<double>(c->Np) / c->M),
+                                    c->stream)
+          : launch_fixed_to_float(c->rho + box * c->M, out, c->M, c->stream);
   if (e != hipSuccess) return set_error(PM_NU_EHIP, "copy_density: %s", hipGetErrorString(e));
   return PM_NU_OK;
 }

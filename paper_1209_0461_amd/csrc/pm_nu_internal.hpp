@@ -31,7 +31,7 @@ struct RespBox {
 
 // Launch shapes chosen by the autotuner (defaults are safe for every N).
 struct Tuning {
-  int deposit_mode = 2;      // see launch_deposit
+  int deposit_mode = 4;      // see launch_deposit
   int deposit_block = 256;   // block size of mode 0
   int interp_mode = 1;       // see launch_interp
   int interp_block = 256;    // block size of mode 0
@@ -48,7 +48,7 @@ struct Timer {
 
 enum Stage {
   ST_ZERO = 0, ST_DEPOSIT, ST_FFT_Z, ST_FFT_Y, ST_FFT_X_BIN, ST_RESPONSE, ST_RTABLE,
-  ST_INV_X_GREEN, ST_INV_Y, ST_INV_Z, ST_INTERP, ST_SURROGATE, ST_COUNT
+  ST_INV_X_GREEN, ST_INV_Y, ST_INV_Z, ST_INTERP, ST_SURROGATE, ST_PATCH_REDUCE, ST_COUNT
 };
 extern const char* const kStageNames[ST_COUNT];
 
@@ -95,6 +95,16 @@ struct Ctx {
   float2* tw = nullptr;            // [N] exp(-2 pi i m/N)
   float* inv_w2 = nullptr;         // [N] 1/sinc^4(pi n/N) per axis index (or 1)
   int* d_flags = nullptr;          // [1] bit 0: non-finite position seen
+  // patch deposit (deposit mode 6)
+  unsigned long long* patches = nullptr;   // [chunks][kPatchCap] per-chunk tiles
+  int4* patch_hdr = nullptr;       // [chunks] box origin and packed extents
+  int* patch_status = nullptr;     // [chunks] 0 patched, 1 through the side grid
+  int* reg_count = nullptr;        // [nbox][coarse cells] patches registered
+  int* reg_list = nullptr;         // [nbox][coarse cells][32] chunk ids
+  unsigned long long* rho_fb = nullptr;    // [nbox][M] side grid, kept at zero
+  int* n_fb = nullptr;             // [1] chunks that used the side grid this deposit
+  float* delta = nullptr;          // [nbox][M] delta in FP32 (mode 6)
+  bool density_is_delta = false;   // the last deposit wrote delta (mode 6), not rho
 
   // host state
   std::vector<std::vector<double>> hist_a;   // committed node scale factors per box
@@ -139,6 +149,9 @@ void surrogate_free(Ctx& c);
 // ---- kernel launchers (each returns hipGetLastError() of its launch) -----------------
 // grid_kernels.hip
 constexpr double kFixScale = 1099511627776.0;   // 2^40: fixed-point unit of the deposit
+// patch deposit (deposit mode 6): chunk of particles, LDS tile / patch capacity in nodes,
+// threads per workgroup
+constexpr int kPatchCH = 4096, kPatchCap = 9216, kPatchNT = 512;
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
 hipError_t launch_fixed_to_float(const unsigned long long* src, float* dst, int64_t n,
                                  hipStream_t s);
@@ -146,6 +159,7 @@ hipError_t launch_extract_component(const float* src, float* dst, int64_t n, int
                                    hipStream_t s);
 // mode 0: one thread per particle, 8 global atomics each; modes 1-3: LDS-privatised
 // chunks of 1024 / 2048 / 4096 particles (global atomics for chunks that do not fit)
+// modes 0-5 (mode 6 is the patch deposit, launched by launch_deposit_patch)
 hipError_t launch_deposit(const float* pos, unsigned long long* rho, int64_t np, int nbox, int N,
                           double inv_cell, int* flags, int mode, int block, hipStream_t s);
 // mode 0: one thread per particle gathering from HBM; modes 1-3: chunks of 1024 / 2048 /
@@ -153,8 +167,10 @@ hipError_t launch_deposit(const float* pos, unsigned long long* rho, int64_t np,
 hipError_t launch_interp(const float* pos, const float* force, float* acc, int64_t np,
                          int nbox, int N, double inv_cell, int mode, int block, hipStream_t s);
 // fft_kernels.hip
-hipError_t launch_fwd_z(int N, const unsigned long long* rho, float2* out, const float2* tw,
-                        double scale, int nbox, hipStream_t s);
+// input: the fixed-point density rho, or (if delta is not NULL) delta in FP32; reset (may
+// be NULL) is cleared by the kernel when reading delta
+hipError_t launch_fwd_z(int N, const unsigned long long* rho, const float* delta, int* reset,
+                        float2* out, const float2* tw, double scale, int nbox, hipStream_t s);
 hipError_t launch_fwd_y(int N, const float2* in, float2* out, const float2* tw, int nbox,
                         hipStream_t s);
 hipError_t launch_fwd_x_bin(int N, float2* data, const float2* tw, const uint16_t* bin_of_n2,
@@ -198,6 +214,19 @@ hipError_t launch_surrogate_response(const float* P, const unsigned short* Q, in
 hipError_t launch_surrogate_dataset(const RespBox* boxes, const double* pcdm, const double* ratio,
                                     const double* kmean, const double* hist_pm, int nbins,
                                     int jcap, int nbox, float* x, float* y, hipStream_t s);
+int patch_cb_log2(int n);
+int64_t patch_coarse_cells(int n);
+int64_t patch_chunks(int64_t np);
+hipError_t launch_deposit_patch(const float* pos, unsigned long long* patches, int4* hdr,
+                                int* status, int* reg_count, int* reg_list,
+                                unsigned long long* rho_fb, int* n_fb, int64_t np, int nbox,
+                                int n, double inv_cell, int* flags, hipStream_t s);
+hipError_t launch_patch_reduce(const unsigned long long* patches, const int4* hdr,
+                               const int* status, int* reg_count, const int* reg_list,
+                               unsigned long long* rho_fb, const int* n_fb, float* delta,
+                               int nbox, int n, double scale, hipStream_t s);
+hipError_t launch_delta_to_density(const float* delta, float* out, int64_t n, float rho_bar,
+                                   hipStream_t s);
 hipError_t launch_bin_power(const double* partial, int n_partial, const double* counts,
                             int nbins, double norm, int nbox, double* pcdm, hipStream_t s);
 hipError_t launch_rtable(const double* ratio, const double* lnk, const int* nonempty,

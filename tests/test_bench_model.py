@@ -27,6 +27,8 @@ def test_stage_bytes_sum_covers_the_step():
     sb = b.stage_bytes(256, 256 ** 3, 1, 64, 200, 1032)
     assert sb["cic_interp"] == 24 * 256 ** 3 + 12 * 256 ** 3
     assert sb["cic_deposit"] == 12 * 256 ** 3 + 4 * 256 ** 3
+    sp = b.stage_bytes(256, 256 ** 3, 1, 64, 200, 1032, deposit_mode=6)
+    assert sp["cic_deposit"] + sp["patch_reduce"] == sb["cic_deposit"]
 
 
 def test_traffic_table_from_counter_csvs(tmp_path):
@@ -35,7 +37,7 @@ def test_traffic_table_from_counter_csvs(tmp_path):
     import bench
     import bench_traffic
     hdr = '"Dispatch_Id","Kernel_Name","Counter_Name","Counter_Value"\n'
-    dep = "void pmnu::(anonymous namespace)::deposit_tiled_kernel<2048, 4608, 256>(float const*)"
+    dep = "void pmnu::(anonymous namespace)::deposit_tiled_kernel<2048, 5120, 256>(float const*)"
     fz = "void pmnu::(anonymous namespace)::fwd_z_kernel<256>(unsigned long long const*)"
     cp = "__amd_rocclr_copyBuffer"
 
@@ -57,9 +59,12 @@ def test_traffic_table_from_counter_csvs(tmp_path):
         sys.argv = argv
     t = json.loads(out.read_text())["pm256"]
     assert t["calibration"]["fetch_factor"] == 2.0 and t["calibration"]["write_factor"] == 1.0
-    rec = t["kernels"]["cic_deposit"]["deposit_tiled_kernel<2048, 4608, 256>"]
+    rec = t["kernels"]["cic_deposit"]["deposit_tiled_kernel<2048, 5120, 256>"]
     assert rec["fetch_bytes"] == 2.0 * 1024 * 200.0 and rec["write_bytes"] == 1024 * 400.0
     assert t["kernels"]["fft_fwd_z"]["fwd_z_kernel<256>"]["bytes_per_launch"] == 1024 * 125.0
     assert bench.kernel_name("cic_deposit", {"deposit_mode": 2}, 256) == \
-        "deposit_tiled_kernel<2048, 4608, 256>"
+        "deposit_tiled_kernel<2048, 5120, 256>"
     assert bench.kernel_name("fft_inv_z", {}, 512) == "inv_z_kernel<512>"
+    assert bench.kernel_name("fft_fwd_z", {"deposit_mode": 6}, 256) == "fwd_z_kernel<256, true>"
+    assert bench.kernel_name("cic_deposit", {"deposit_mode": 6}, 256) == \
+        "deposit_patch_kernel<4096, 9216, 512>"

@@ -234,7 +234,7 @@ def test_every_launch_mode_matches_oracle(order):
     p = torch.from_numpy(pos).cuda()
     acc = torch.zeros_like(p)
     for dm, im, ib in ((0, 0, 256), (1, 1, 256), (2, 2, 256), (3, 3, 256), (1, 0, 512),
-                       (0, 2, 256), (4, 0, 1024), (5, 1, 256)):
+                       (0, 2, 256), (4, 0, 1024), (5, 1, 256), (6, 1, 256), (6, 0, 256)):
         binding.pm_nu_set_launch(ctx.h, dm, 256, im, ib)
         ctx.step(p, acc, 0.7)
         torch.cuda.synchronize()
@@ -260,4 +260,36 @@ def test_spectrum_after_deposit_alone_matches_oracle():
     got = ctx.spectrum(0)["p_cdm"]
     ok = ref["counts"] > 0
     assert np.abs(got[ok] / ref["p_cdm"][ok] - 1).max() <= 2e-6
+    ctx.close()
+
+
+def test_patch_deposit_side_grid_on_crowded_cells():
+    """Deposit mode 6 with 40 chunks of particles packed into a few cells: the coarse cell's
+    patch list overflows, those chunks go through the side grid, and the result still
+    matches the oracle; a following deposit of an ordinary lattice finds the side grid
+    cleared."""
+    import torch
+    from paper_1209_0461_amd import PMNu, binding
+    from synth import zeldovich_lattice
+    nm, box, nb, J = 32, 128.0, 16, 10
+    rng = np.random.default_rng(12)
+    crowd = (40.0 + 10.0 * rng.random((40 * 4096, 3))).astype(np.float32)   # 2.5 cells wide
+    lattice = zeldovich_lattice(32, box, 0.3, 72)
+    lattice = np.concatenate([lattice] * 5)[: len(crowd)]   # same count, ordinary spread
+    ctx = PMNu(nm, len(crowd), box, nb, J + 2, [0.3])
+    binding.pm_nu_set_launch(ctx.h, 6, 256, 1, 256)
+    for pos in (crowd, lattice, crowd):
+        hist, ref = oracle_case(pos, nm, box, nb, J, 0.02, 0.7, 0.3)
+        ctx.set_history(0, hist)
+        p = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
+        acc = torch.zeros_like(p)
+        ctx.step(p, acc, 0.7)
+        torch.cuda.synchronize()
+        ok = ref["counts"] > 0
+        sp = ctx.spectrum(0)
+        assert np.abs(sp["p_cdm"][ok] / ref["p_cdm"][ok] - 1).max() <= 2e-6
+        assert rms_rel(acc.cpu().numpy(), ref["acc"]) <= TOL_FORCE_RMS
+        rho = torch.empty(nm ** 3, device="cuda")
+        binding.pm_nu_copy_density(ctx.h, 0, rho)
+        assert abs(float(rho.double().sum()) / len(pos) - 1.0) < 1e-5
     ctx.close()
