@@ -4,7 +4,7 @@
 //
 // Layouts (per box b):
 //   real grid      [b][x][y][z]                 (z contiguous)
-//   modes          [b][kz][kx][ky], kz in [0, N/2], kx, ky in [0, N)   (ky contiguous)
+//   y-side fields  [b][kz][x][ky], kz in [0, N/2], x, ky in [0, N)   (ky contiguous)
 //   z-side fields  [b][x][kz][ky]               (the planes next to the real grid)
 // Every row is a power of two long and aligned. The passes along z work inside one
 // contiguous x-slab of the z-side layout; the passes along y move whole rows between the
@@ -12,13 +12,17 @@
 // along x work inside one contiguous kz-slab. numpy's rfftn order [kx][ky][kz] is
 // produced only by launch_copy_modes.
 //
-// Forward:  fwd_z   delta = rho/rho_bar - 1 from the fixed-point density, real rows along
-//                   z -> half spectra (two rows per complex FFT), written as [x][kz][y]
+// Forward:  fwd_z   delta (from the fixed-point density, or given in FP32), real rows
+//                   along z -> half spectra (two rows per complex FFT), written as
+//                   [x][kz][y]
 //           fwd_y   complex FFT of every contiguous y row, written to [kz][x][ky]
-//           fwd_x   complex FFT along kx (tile of N x TX), then the FP64 mode sums per
-//                   k-bin: sum w |delta_k|^2, w = 1 on the kz = 0, N/2 planes, else 2
-// Inverse:  inv_x   delta_M = T(|n|^2) delta_cdm, phi = -C T delta/(k^2 W^2), and the two
-//                   fields F1 = phi, F2 = -i k_x phi, inverse FFT along kx
+//           fwd_x   complex FFT along x (tile of N x TX) in LDS and the FP64 mode sums
+//                   per k-bin: sum w |delta_k|^2, w = 1 on the kz = 0, N/2 planes, else 2;
+//                   the transformed tile is not stored (the inverse pass redoes it,
+//                   which costs arithmetic but saves writing the whole field)
+// Inverse:  inv_x   FFT along x again, delta_M = T(|n|^2) delta_cdm,
+//                   phi = -C delta_M/(k^2 W^2), and the two fields F1 = phi,
+//                   F2 = -i k_x phi, inverse FFT along kx
 //           inv_y   G1 = IFFT_y F1, G2 = IFFT_y(-i k_y F1), G3 = IFFT_y F2, written to
 //                   [x][kz][y]
 //           inv_z   complex-to-real along z of -i k_z G1, G2, G3 (two rows per complex
@@ -145,7 +149,9 @@ __global__ __launch_bounds__(NT) void fwd_y_kernel(const float2* __restrict__ in
   }
 }
 
-template <int N>
+// STORE: write the transformed tile back (only for reading the modes out); BIN: the mode
+// sums per k-bin (the step bins without storing; the inverse pass redoes the x transform).
+template <int N, bool STORE, bool BIN>
 __global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data,
                                                        const float2* __restrict__ twg,
                                                        const uint16_t* __restrict__ bin_of_n2,
@@ -156,7 +162,8 @@ __global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data
   extern __shared__ double bins[];
   const int y0 = blockIdx.x * TX, kz = blockIdx.y, box = blockIdx.z;
   load_twiddles<N, NT>(tw, twg);
-  for (int b = threadIdx.x; b < nbins; b += NT) bins[b] = 0.0;
+  if constexpr (BIN)
+    for (int b = threadIdx.x; b < nbins; b += NT) bins[b] = 0.0;
   float2* base = data + ((static_cast<size_t>(box) * NK + kz) * N) * N + y0;
   // float4 = two consecutive k_y; all loads in flight before the LDS stores
   constexpr int P = TX / 2, IT = (N * P + NT - 1) / NT;
@@ -181,11 +188,15 @@ __global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data
   const double w = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
   // store the tile back, then bin it: each thread walks a run of consecutive k_x at one
   // k_y, where |n|^2 changes slowly, and adds to the LDS bin only when the bin changes
-  for (int t = threadIdx.x; t < N * P; t += NT) {
-    const int x = t / P, y = 2 * (t % P);
-    const float2 a = lds[x * ES + y], b = lds[x * ES + y + 1];
-    *reinterpret_cast<float4*>(base + static_cast<size_t>(x) * N + y) = make_float4(a.x, a.y, b.x, b.y);
+  if constexpr (STORE) {
+    for (int t = threadIdx.x; t < N * P; t += NT) {
+      const int x = t / P, y = 2 * (t % P);
+      const float2 a = lds[x * ES + y], b = lds[x * ES + y + 1];
+      *reinterpret_cast<float4*>(base + static_cast<size_t>(x) * N + y) =
+          make_float4(a.x, a.y, b.x, b.y);
+    }
   }
+  if constexpr (!BIN) return;
   constexpr int RUNS = NT / TX;                        // runs per k_y column
   constexpr int RUN = (N + RUNS - 1) / RUNS;           // k_x values per run
   for (int t = threadIdx.x; t < TX * RUNS; t += NT) {
@@ -225,15 +236,24 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
                                                    const float2* __restrict__ twg,
                                                    const float* __restrict__ rtable, int n2max,
                                                    const float* __restrict__ inv_w2,
-                                                   float c, float kf) {
+                                                   float c, float kf, int nbox) {
   constexpr int TX = Shape<N>::IX_TX, NL = 2 * TX, ES = NL + 1, NK = Shape<N>::NK;
+  constexpr int NYB = N / TX;
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
-  const int y0 = blockIdx.x * TX, kz = blockIdx.y, box = blockIdx.z;
+  // Workgroups go to the 8 XCDs in turn; the remap gives each XCD a contiguous run of
+  // (k_y block, k_z) tiles, so the two workgroups writing the halves of a 128-byte line
+  // (TX = 8 complex values = 64 bytes per row) share one L2 instead of each fetching it.
+  const int total = NYB * NK * nbox, per = static_cast<int>(gridDim.x) / 8;
+  const int lid = static_cast<int>(blockIdx.x);
+  const int logical = (lid % 8) * per + lid / 8;
+  if (logical >= total) return;
+  const int y0 = (logical % NYB) * TX, kz = (logical / NYB) % NK, box = logical / (NYB * NK);
   load_twiddles<N, NT>(tw, twg);
   const size_t off = ((static_cast<size_t>(box) * NK + kz) * N) * N + y0;
   const float* rt = rtable + static_cast<size_t>(box) * (n2max + 1);
   const float wz = inv_w2[kz];
+  // the tile holds x (real space) by k_y: forward transform along x first (lines 0..TX-1)
   constexpr int P = TX / 2, IT = (N * P + NT - 1) / NT;
   static_assert(TX % 2 == 0 && NT % P == 0, "k_y pairs");
   const int py = 2 * (threadIdx.x % P);
@@ -246,25 +266,28 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
     const int x = (threadIdx.x + i * NT) / P;
-    if (x >= N) break;
-    const int nx = signed_index(x, N);
-    const float kx = (x == N / 2) ? 0.f : kf * static_cast<float>(nx);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int y = py + h;
-      const float2 d = h ? make_float2(v[i].z, v[i].w) : make_float2(v[i].x, v[i].y);
-      const int ny = signed_index(y0 + y, N);
-      const int n2 = nx * nx + ny * ny + kz * kz;
-      float2 phi = make_float2(0.f, 0.f);
-      if (n2 > 0) {
-        // phi = -C T(n^2) delta / (k^2 W^2), k^2 = kf^2 n^2
-        const float g = -c * rt[n2] * inv_w2[x] * inv_w2[y0 + y] * wz /
-                        (kf * kf * static_cast<float>(n2));
-        phi = cscale(d, g);
-      }
-      lds[x * ES + y] = phi;
-      lds[x * ES + TX + y] = make_float2(kx * phi.y, -kx * phi.x);     // -i k_x phi
+    if (x < N) {
+      lds[x * ES + py] = make_float2(v[i].x, v[i].y);
+      lds[x * ES + py + 1] = make_float2(v[i].z, v[i].w);
     }
+  }
+  __syncthreads();
+  fft_lines<N, TX, NT, -1, ES>(lds, tw);
+  // delta_M -> phi and -i k_x phi, in place on the (k_x, k_y) tile
+  for (int t = threadIdx.x; t < N * TX; t += NT) {
+    const int y = t % TX, x = t / TX;
+    const int nx = signed_index(x, N), ny = signed_index(y0 + y, N);
+    const int n2 = nx * nx + ny * ny + kz * kz;
+    float2 phi = make_float2(0.f, 0.f);
+    if (n2 > 0) {
+      // phi = -C T(n^2) delta / (k^2 W^2), k^2 = kf^2 n^2
+      const float g = -c * rt[n2] * inv_w2[x] * inv_w2[y0 + y] * wz /
+                      (kf * kf * static_cast<float>(n2));
+      phi = cscale(lds[x * ES + y], g);
+    }
+    const float kx = (x == N / 2) ? 0.f : kf * static_cast<float>(nx);
+    lds[x * ES + y] = phi;
+    lds[x * ES + TX + y] = make_float2(kx * phi.y, -kx * phi.x);     // -i k_x phi
   }
   __syncthreads();
   fft_lines<N, NL, NT, +1>(lds, tw);
@@ -463,11 +486,16 @@ template <int N> struct FwdY {
   }
 };
 template <int N> struct FwdX {
+  // partial != NULL: bin without storing (the step); NULL: store the modes, no binning
   static hipError_t run(float2* data, const float2* tw, const uint16_t* bins, double* partial,
                         int nbins, int nbox, hipStream_t s) {
     dim3 grid(N / Shape<N>::FX_TX, Shape<N>::NK, nbox);
-    hipLaunchKernelGGL(fwd_x_bin_kernel<N>, grid, dim3(NT), nbins * sizeof(double), s, data,
-                       tw, bins, partial, nbins);
+    if (partial)
+      hipLaunchKernelGGL((fwd_x_bin_kernel<N, false, true>), grid, dim3(NT),
+                         nbins * sizeof(double), s, data, tw, bins, partial, nbins);
+    else
+      hipLaunchKernelGGL((fwd_x_bin_kernel<N, true, false>), grid, dim3(NT), 0, s, data, tw,
+                         bins, partial, nbins);
     return hipGetLastError();
   }
 };
@@ -475,9 +503,10 @@ template <int N> struct InvX {
   static hipError_t run(const float2* dk, float2* f1, float2* f2, const float2* tw,
                         const float* rt, int n2max, const float* iw, float cfac,
                         float kf, int nbox, hipStream_t s) {
-    dim3 grid(N / Shape<N>::IX_TX, Shape<N>::NK, nbox);
+    const int total = N / Shape<N>::IX_TX * Shape<N>::NK * nbox;
+    dim3 grid((total + 7) / 8 * 8);   // whole rounds over the 8 XCDs; extra blocks exit
     hipLaunchKernelGGL(inv_x_kernel<N>, grid, dim3(NT), 0, s, dk, f1, f2, tw, rt, n2max, iw,
-                       cfac, kf);
+                       cfac, kf, nbox);
     return hipGetLastError();
   }
 };

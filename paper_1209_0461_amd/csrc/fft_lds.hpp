@@ -134,9 +134,8 @@ __host__ __device__ constexpr int plan_ns(int n, int pass) {
 }
 
 // One Stockham pass over all NL lines; NT threads cooperate. tw[m] = exp(-2 pi i m / N).
-template <int N, int NL, int NT, int R, int NS, int DIR>
+template <int N, int NL, int NT, int R, int NS, int DIR, int ES>
 __device__ __forceinline__ void stockham_pass(float2* lds, const float2* tw) {
-  constexpr int ES = NL + 1;
   constexpr int NB = N / R;                 // butterflies per line
   constexpr int TOTAL = NL * NB;
   constexpr int CNT = (TOTAL + NT - 1) / NT;
@@ -175,19 +174,20 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const float2* tw) {
   __syncthreads();
 }
 
-template <int N, int NL, int NT, int DIR, int PASS>
+template <int N, int NL, int NT, int DIR, int PASS, int ES>
 __device__ __forceinline__ void fft_passes(float2* lds, const float2* tw) {
   if constexpr (plan_radix(N, PASS) != 0) {
-    stockham_pass<N, NL, NT, plan_radix(N, PASS), plan_ns(N, PASS), DIR>(lds, tw);
-    fft_passes<N, NL, NT, DIR, PASS + 1>(lds, tw);
+    stockham_pass<N, NL, NT, plan_radix(N, PASS), plan_ns(N, PASS), DIR, ES>(lds, tw);
+    fft_passes<N, NL, NT, DIR, PASS + 1, ES>(lds, tw);
   }
 }
 
-// Transform all NL lines in place. Caller must __syncthreads() before (data written) and
-// may read the result after return (the last pass ends with a barrier).
-template <int N, int NL, int NT, int DIR>
+// Transform lines 0..NL-1 in place (element stride ES, NL + 1 unless the lines are the
+// first NL of a wider layout). Caller must __syncthreads() before (data written) and may
+// read the result after return (the last pass ends with a barrier).
+template <int N, int NL, int NT, int DIR, int ES = NL + 1>
 __device__ __forceinline__ void fft_lines(float2* lds, const float2* tw) {
-  fft_passes<N, NL, NT, DIR, 0>(lds, tw);
+  fft_passes<N, NL, NT, DIR, 0, ES>(lds, tw);
 }
 
 // Load the N-entry twiddle table exp(-2 pi i m / N) into LDS.

@@ -752,7 +752,14 @@ int pm_nu_copy_modes(pm_nu_ctx* ctx, int box, float* out) {
   GET_CTX(ctx);
   if (box < 0 || box >= c->nbox || !out) return set_error(PM_NU_EINVAL, "bad box/out");
   if (c->stage < 1) return set_error(PM_NU_ESTATE, "modes are valid after pm_nu_deposit");
-  hipError_t e = launch_copy_modes(c->N, c->ck[0], reinterpret_cast<float2*>(out), box, c->stream);
+  // the step keeps the field before its x transform (the inverse pass redoes it): transform
+  // a copy along x here and read the modes from it
+  const size_t bytes = static_cast<size_t>(c->nbox) * c->MH * sizeof(float2);
+  PMNU_HIP(hipMemcpyAsync(c->ck[2], c->ck[0], bytes, hipMemcpyDeviceToDevice, c->stream));
+  hipError_t e = launch_fwd_x_bin(c->N, c->ck[2], c->tw, c->bin_of_n2, nullptr, c->B, c->nbox,
+                                  c->stream);
+  if (e == hipSuccess)
+    e = launch_copy_modes(c->N, c->ck[2], reinterpret_cast<float2*>(out), box, c->stream);
   if (e != hipSuccess) return set_error(PM_NU_EHIP, "copy_modes: %s", hipGetErrorString(e));
   return PM_NU_OK;
 }

@@ -71,8 +71,9 @@ struct Ctx {
 
   // device buffers
   unsigned long long* rho = nullptr;   // [nbox][M] deposit, fixed point (unit 2^-40)
-  // complex fields, (N/2+1) N^2 each per box: ck[0] holds the modes [kz][kx][ky] from the
-  // forward transform to the first inverse pass; the others hold intermediates
+  // complex fields, (N/2+1) N^2 each per box: ck[0] holds the field transformed along z
+  // and y, [kz][x][ky], from the forward passes to the first inverse pass (which applies
+  // the x transform itself); the others hold intermediates
   float2* ck[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   float* force = nullptr;          // [nbox][M][3] accelerations, components interleaved
   double* bin_partial = nullptr;   // [nbox][n_partial][B]
@@ -173,6 +174,8 @@ hipError_t launch_fwd_z(int N, const unsigned long long* rho, const float* delta
                         float2* out, const float2* tw, double scale, int nbox, hipStream_t s);
 hipError_t launch_fwd_y(int N, const float2* in, float2* out, const float2* tw, int nbox,
                         hipStream_t s);
+// partial != NULL: FFT along x and the mode sums per bin, data left unchanged (the step);
+// partial == NULL: FFT along x stored in place, no sums (reading the modes out)
 hipError_t launch_fwd_x_bin(int N, float2* data, const float2* tw, const uint16_t* bin_of_n2,
                             double* partial, int B, int nbox, hipStream_t s);
 int fwd_x_partials(int N);   // partial bin sums per box written by launch_fwd_x_bin
