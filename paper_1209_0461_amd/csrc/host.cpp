@@ -141,8 +141,8 @@ int validate(const pm_nu_config* c) {
   if (!(c->omega_m > 0.0 && c->omega_m <= 1.0))
     return set_error(PM_NU_EINVAL, "omega_m must be in (0, 1]");
   if (!(c->hubble > 0.0)) return set_error(PM_NU_EINVAL, "hubble must be positive");
-  if (c->n_kbins < 1 || c->n_kbins > 1024)
-    return set_error(PM_NU_EINVAL, "n_kbins must be in [1, 1024]");
+  if (c->n_kbins < 1 || c->n_kbins > kMaxBins)
+    return set_error(PM_NU_EINVAL, "n_kbins must be in [1, %d]", kMaxBins);
   if (c->max_history < 2) return set_error(PM_NU_EINVAL, "max_history must be >= 2");
   if (c->substeps < 1 || c->substeps > 1024)
     return set_error(PM_NU_EINVAL, "substeps must be in [1, 1024]");

@@ -150,6 +150,7 @@ void surrogate_free(Ctx& c);
 // ---- kernel launchers (each returns hipGetLastError() of its launch) -----------------
 // grid_kernels.hip
 constexpr double kFixScale = 1099511627776.0;   // 2^40: fixed-point unit of the deposit
+constexpr int kMaxBins = 1024;                   // largest n_kbins
 // patch deposit (deposit mode 6): chunk of particles, LDS tile / patch capacity in nodes,
 // threads per workgroup
 constexpr int kPatchCH = 4096, kPatchCap = 9216, kPatchNT = 512;

@@ -38,9 +38,19 @@ __device__ __forceinline__ double block_sum_d(double v, double* red) {
 // sum w |delta_k|^2
 __device__ __forceinline__ double bin_mode_sum(const double* partial, int n_partial, int nbins,
                                                int box, int b, double* red) {
+  constexpr int U = 8;                       // loads in flight per thread
   double s = 0.0;
   const double* pp = partial + (static_cast<size_t>(box) * nbins + b) * n_partial;
-  for (int i = threadIdx.x; i < n_partial; i += RT) s += pp[i];
+  for (int i0 = 0; i0 < n_partial; i0 += U * RT) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + threadIdx.x + u * RT;
+      v[u] = i < n_partial ? pp[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[u];
+  }
   return block_sum_d(s, red);
 }
 
@@ -59,18 +69,31 @@ __device__ __forceinline__ double exact_pnu(const RespBox& bx, double k, double 
   for (int it = 0; it < iterations; ++it) {
     const double a_cur = (1.0 - bx.f_nu) * pcdm_half + bx.f_nu * pnu_guess;
     double acc = 0.0;
-    for (int q = threadIdx.x; q < bx.nq; q += RT) {
-      const double d = ds[q];
-      const int j = q / q_sub, r = q - j * q_sub;
-      const double aj = (j < bx.n_cur) ? hpm[static_cast<size_t>(j) * nbins + b] : a_cur;
-      double amp = aj;
-      if (r != 0) {
-        const double aj1 =
-            (j + 1 < bx.n_cur) ? hpm[static_cast<size_t>(j + 1) * nbins + b] : a_cur;
-        const double t = r * inv_q;
-        amp = (1.0 - t) * aj + t * aj1;
+    constexpr int U = 4;                     // sub-nodes per thread whose loads go out together
+    for (int q0 = 0; q0 < bx.nq; q0 += U * RT) {
+      double d[U], wq[U], a0[U], a1[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + threadIdx.x + u * RT;
+        const int j = q / q_sub;
+        const bool in = q < bx.nq;
+        d[u] = in ? ds[q] : 0.0;
+        wq[u] = in ? w[q] : 0.0;
+        a0[u] = (in && j < bx.n_cur) ? hpm[static_cast<size_t>(j) * nbins + b] : a_cur;
+        a1[u] = (in && j + 1 < bx.n_cur) ? hpm[static_cast<size_t>(j + 1) * nbins + b] : a_cur;
       }
-      acc += w[q] * i_fit(kt * d) * d * amp;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + threadIdx.x + u * RT;
+        if (q >= bx.nq) continue;
+        const int j = q / q_sub, r = q - j * q_sub;
+        double amp = a0[u];
+        if (r != 0) {
+          const double t = r * inv_q;
+          amp = (1.0 - t) * a0[u] + t * a1[u];
+        }
+        acc += wq[u] * i_fit(kt * d[u]) * d[u] * amp;
+      }
     }
     pnu = ic + block_sum_d(acc, red);
     pnu_guess = pnu;

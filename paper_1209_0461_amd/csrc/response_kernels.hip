@@ -90,31 +90,36 @@ __global__ __launch_bounds__(256) void rtable_kernel(const double* __restrict__ 
                                                      const RespBox* __restrict__ boxes,
                                                      int nbins, int n2max, double kf,
                                                      float* __restrict__ rtable) {
+  // ln k and R of the non-empty bins, staged once per workgroup (the search runs in LDS)
+  __shared__ double s_lk[kMaxBins], s_r[kMaxBins];
   const int box = blockIdx.y;
+  const double* rb = ratio + static_cast<size_t>(box) * nbins;
+  for (int i = threadIdx.x; i < n_nonempty; i += blockDim.x) {
+    const int b = nonempty[i];
+    s_lk[i] = lnk[b];
+    s_r[i] = rb[b];
+  }
+  __syncthreads();
   const int n2 = blockIdx.x * blockDim.x + threadIdx.x;
   if (n2 > n2max) return;
   const double f = boxes[box].f_nu;
-  const double* rb = ratio + static_cast<size_t>(box) * nbins;
   double r;
   if (n2 == 0) {
-    r = rb[nonempty[0]];
+    r = s_r[0];
   } else {
     const double lk = log(kf * sqrt(static_cast<double>(n2)));
-    const double lo = lnk[nonempty[0]];
-    const double hi = lnk[nonempty[n_nonempty - 1]];
-    if (lk <= lo) {
-      r = rb[nonempty[0]];
-    } else if (lk >= hi) {
-      r = rb[nonempty[n_nonempty - 1]];
+    if (lk <= s_lk[0]) {
+      r = s_r[0];
+    } else if (lk >= s_lk[n_nonempty - 1]) {
+      r = s_r[n_nonempty - 1];
     } else {
-      int a = 0, z = n_nonempty - 1;   // log k of nonempty[a] <= lk < that of nonempty[z]
+      int a = 0, z = n_nonempty - 1;   // s_lk[a] <= lk < s_lk[z]
       while (z - a > 1) {
         const int mid = (a + z) >> 1;
-        if (lnk[nonempty[mid]] <= lk) a = mid; else z = mid;
+        if (s_lk[mid] <= lk) a = mid; else z = mid;
       }
-      const double la = lnk[nonempty[a]], lz = lnk[nonempty[z]];
-      const double t = (lk - la) / (lz - la);
-      r = rb[nonempty[a]] + t * (rb[nonempty[z]] - rb[nonempty[a]]);
+      const double t = (lk - s_lk[a]) / (s_lk[z] - s_lk[a]);
+      r = s_r[a] + t * (s_r[z] - s_r[a]);
     }
   }
   rtable[static_cast<size_t>(box) * (n2max + 1) + n2] = static_cast<float>((1.0 - f) + f * r);
