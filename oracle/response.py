@@ -72,7 +72,8 @@ def sub_grid(a_nodes, substeps, omega_m):
 
 def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
                  pnu_half_init, theta_over_delta_init, a_now, m_nu_total, omega_m,
-                 hubble, substeps, iterations=1, n_species=3, f_nu=None):
+                 hubble, substeps, iterations=1, n_species=3, f_nu=None, species=None,
+                 pnu_half_init_species=None):
     """P_nu^{1/2}(k_b, a_now) for every bin, eq. (P-final).
 
     hist_a (n,), hist_pm_half (n, B): stored nodes strictly before a_now (hist_a[0] = a_i).
@@ -81,13 +82,24 @@ def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
     f_nu. Empty bins (counts == 0) give 0 everywhere. Without massive neutrinos
     (m_nu_total = 0, so f_nu = 0) the neutrino term of Sec. 4.3 (iv) drops out: P_nu^{1/2}
     and R are reported as 0 and the stored node is P_cdm^{1/2}.
+
+    species: masses of individual species [eV] (mass hierarchy, Sec. 6.2); by default
+    n_species equal masses m_nu_total / n_species. Each species free-streams with its own
+    kernel I(k (s - s') T_nu0 / m_s) and the neutrino density contrast is the mean over
+    species weighted by their share of the neutrino density, m_s / M_nu (non-relativistic);
+    a massless species adds nothing. pnu_half_init_species (n_species, B): initial
+    amplitude of each species (default: pnu_half_init for all).
     """
     k = np.asarray(k_mean, dtype=np.float64)
     ok = np.asarray(counts) > 0
     pcdm_half = np.asarray(pcdm_half, dtype=np.float64)
+    if species is None:
+        masses = np.full(n_species, m_nu_total / n_species)
+    else:
+        masses = np.asarray(species, dtype=np.float64)
+        m_nu_total = masses.sum()
     fn = f_nu_of(m_nu_total, omega_m, hubble) if f_nu is None else f_nu
-    m1 = m_nu_total / n_species
-    if m1 <= 0.0:
+    if m_nu_total <= 0.0:
         zero = np.zeros_like(k)
         return dict(pnu_half=zero, ratio=zero.copy(),
                     pm_half_now=np.where(ok, pcdm_half, 0.0), f_nu=0.0)
@@ -96,13 +108,21 @@ def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
     pref = 1.5 * omega_m * H0 * H0
     measure = g["w"] / (g["a"] * hubble_rate(g["a"], omega_m))     # d ln a / (a H)
     hist = np.asarray(hist_pm_half, dtype=np.float64)
+    if species is None:
+        # equal masses: one kernel
+        groups = [(1.0, masses[0], np.asarray(pnu_half_init))]
+    else:
+        ics = (np.asarray(pnu_half_init_species, dtype=np.float64)
+               if pnu_half_init_species is not None
+               else np.tile(np.asarray(pnu_half_init, dtype=np.float64), (len(masses), 1)))
+        groups = [(m / m_nu_total, m, ics[i]) for i, m in enumerate(masses) if m > 0.0]
 
     # initial-condition term: I(x_i) P_nu^{1/2}(a_i) {1 - (s - s_i) a_i [theta/delta]_i}
-    x_i = k * g["ds"][0] * T_NU0 / m1
-    ic = I_fit(x_i) * np.asarray(pnu_half_init) * (
-        1.0 - g["ds"][0] * nodes[0] * np.asarray(theta_over_delta_init))
+    phase = 1.0 - g["ds"][0] * nodes[0] * np.asarray(theta_over_delta_init)
+    ic = sum(w * I_fit(k * g["ds"][0] * T_NU0 / m) * p0 for w, m, p0 in groups) * phase
 
-    kernel = I_fit(np.outer(g["ds"] * T_NU0 / m1, k)) * g["ds"][:, None]   # (q, B)
+    kernel = sum(w * I_fit(np.outer(g["ds"] * T_NU0 / m, k)) for w, m, _ in groups)
+    kernel = kernel * g["ds"][:, None]                                 # (q, B)
 
     pnu_guess = np.asarray(pnu_half_prev, dtype=np.float64)
     for _ in range(max(1, iterations)):
@@ -121,13 +141,15 @@ def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
 
 def replay_history(k_mean, counts, cdm_half, a_nodes, pnu_half_init,
                    theta_over_delta_init, m_nu_total, omega_m, hubble, substeps,
-                   n_species=3, f_nu=None):
+                   n_species=3, f_nu=None, species=None):
     """A self-consistent stored history: the neutrino amplitude at every node computed by
     eq. (P-final) from the earlier nodes, as the step-by-step loop of Sec. 4.3 would.
 
     cdm_half (n_nodes, B): CDM amplitudes at every node a_nodes[j].
     Returns pm_half (n_nodes, B) and pnu_half (n_nodes, B).
     """
+    if species is not None:
+        m_nu_total = float(np.sum(species))
     fn = f_nu_of(m_nu_total, omega_m, hubble) if f_nu is None else f_nu
     n = len(a_nodes)
     B = len(k_mean)
@@ -138,7 +160,8 @@ def replay_history(k_mean, counts, cdm_half, a_nodes, pnu_half_init,
     for j in range(1, n):
         r = nu_amplitude(k_mean, counts, cdm_half[j], a_nodes[:j], pm[:j], pnu[j - 1],
                          pnu_half_init, theta_over_delta_init, a_nodes[j], m_nu_total,
-                         omega_m, hubble, substeps, n_species=n_species, f_nu=fn)
+                         omega_m, hubble, substeps, n_species=n_species, f_nu=fn,
+                         species=species)
         pnu[j] = r["pnu_half"]
         pm[j] = r["pm_half_now"]
     return pm, pnu

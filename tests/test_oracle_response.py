@@ -147,3 +147,68 @@ def test_massless_neutrinos_drop_out():
                               [1, 1], [0, 0], 0.5, 0.0, 0.3, 0.7, 4)
     assert r["f_nu"] == 0.0 and np.all(r["pnu_half"] == 0) and np.all(r["ratio"] == 0)
     assert np.array_equal(r["pm_half_now"], [2.0, 3.0])
+
+
+# ---- mass hierarchy (Sec. 6.2): species with their own masses -------------------------------
+
+def _eds_species(k, masses, a0, an, J, Q=8):
+    nodes = log_spaced_nodes(a0, an, J)
+    B = len(k)
+    r = response.nu_amplitude(k, np.ones(B), an * np.ones(B), nodes[:-1],
+                              nodes[:-1, None] * np.ones((1, B)), np.zeros(B), np.zeros(B),
+                              np.zeros(B), an, 0.0, 1.0, 0.7, Q, f_nu=0.0, species=masses)
+    return r["pnu_half"] / an
+
+
+@pytest.mark.parametrize("which", ["hierarchy_normal_eV", "hierarchy_inverted_eV"])
+def test_hierarchy_eds_is_the_mass_weighted_closed_form(which):
+    """EdS with delta_M ~ a: each species follows Appendix A's closed form with its own mass,
+    and the neutrino contrast is their mean weighted by m_s / M_nu (a massless species adds
+    nothing). The paper's normal and inverted hierarchies of M_nu = 0.1 eV."""
+    masses = GOLD[which]["value"]
+    M = sum(masses)
+    k = np.array([0.01, 0.1, 0.5])
+    a0, an = 0.01, 0.5
+    ref = sum(m / M * np.array([_eds_closed_form(kk, m, a0, an) for kk in k])
+              for m in masses if m > 0)
+    got = _eds_species(k, masses, a0, an, 400)
+    assert np.allclose(got, ref, rtol=2e-5)
+
+
+def test_hierarchy_reduces_to_the_degenerate_and_single_species_cases():
+    """Equal masses give the default degenerate computation; one massive species among
+    massless ones gives a single species of that mass."""
+    om = 0.3
+    nodes = log_spaced_nodes(0.01, 1.0, 40)
+    k = np.geomspace(0.0123, 2.7, 12)
+    pcdm = 30.0 / k
+    h = synthetic_history(k, pcdm, nodes, 0.3, om)
+    kw = dict(k_mean=k, counts=np.ones(12), pcdm_half=pcdm, hist_a=h["a"],
+              hist_pm_half=h["pm_half"], pnu_half_prev=h["pnu_half"][-1],
+              pnu_half_init=h["pnu_half_init"], theta_over_delta_init=h["theta_over_delta_init"],
+              a_now=1.0, omega_m=om, hubble=0.7, substeps=4)
+    degenerate = response.nu_amplitude(m_nu_total=0.3, n_species=3, **kw)["pnu_half"]
+    three = response.nu_amplitude(m_nu_total=0.0, species=[0.1, 0.1, 0.1], **kw)["pnu_half"]
+    assert np.allclose(three, degenerate, rtol=1e-13, atol=0.0)
+    one = response.nu_amplitude(m_nu_total=0.3, n_species=1, **kw)["pnu_half"]
+    lone = response.nu_amplitude(m_nu_total=0.0, species=[0.0, 0.3, 0.0], **kw)["pnu_half"]
+    assert np.allclose(lone, one, rtol=1e-13, atol=0.0)
+
+
+def test_hierarchy_species_initial_amplitudes_enter_with_their_weights():
+    """With no source term the neutrino amplitude is the weighted sum of each species'
+    initial-condition term I(x_i,s) P_s {1 - (s - s_i) a_i theta} (eq. (deltaI-nu))."""
+    nodes = np.array([0.01, 0.02])
+    k = np.array([0.05, 0.3])
+    masses = [0.02, 0.08]
+    ics = np.array([[1.0, 2.0], [3.0, 5.0]])
+    theta = np.array([-0.4, -0.4])
+    with np.errstate(divide="ignore", invalid="ignore"):     # P_cdm = 0: R is undefined
+        r = response.nu_amplitude(k, [1, 1], [0.0, 0.0], nodes[:-1], np.zeros((1, 2)),
+                                  [0.0, 0.0], [0.0, 0.0], theta, nodes[-1], 0.0, 0.3, 0.7, 2,
+                                  f_nu=0.0, species=masses, pnu_half_init_species=ics)
+    ds = integrate.quad(lambda a: 1.0 / (a ** 3 * bg.hubble_rate(a, 0.3)), 0.01, 0.02,
+                        epsrel=1e-13)[0]
+    want = sum(m / 0.1 * kernel.I_fit(k * ds * bg.T_NU0 / m) * ics[i]
+               for i, m in enumerate(masses)) * (1.0 - ds * 0.01 * theta)
+    assert np.allclose(r["pnu_half"], want, rtol=1e-10)
