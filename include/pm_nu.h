@@ -189,8 +189,21 @@ int pm_nu_tuning(pm_nu_ctx* ctx, char* out, size_t cap);
  * checked against the exact integral (2) between steps. */
 int pm_nu_set_response_mode(pm_nu_ctx* ctx, int mode);
 
-/* Change the total neutrino mass of one box (eV, >= 0) between steps (sync). */
+/* Change the total neutrino mass of one box (eV, >= 0) between steps (sync); the box gets
+ * cfg.n_species equal masses again. */
 int pm_nu_set_mass(pm_nu_ctx* ctx, int box, double m_nu_total);
+
+/* Neutrino mass hierarchy (the paper's Sec. 6.2): give one box n_species (1..4) species
+ * with their own masses m_species[n_species] (eV, >= 0, host). Each massive species
+ * free-streams with its own kernel I(k (s - s') T_nu0 / m_s) and the neutrino contrast is
+ * the mean over species weighted by m_s / M_nu, M_nu = sum of the masses (f_nu follows M_nu);
+ * a massless species adds nothing. pnu_half_init (host, [n_species][B], or NULL) gives each
+ * species its initial amplitude; NULL uses the one of pm_nu_set_history for all (a later
+ * pm_nu_set_history resets all species to its amplitude). The surrogate answers only for
+ * three equal masses (the setting it was trained on); otherwise the exact integral runs.
+ * Sync. Errors: PM_NU_EINVAL for a bad box, count, mass or amplitude. */
+int pm_nu_set_species(pm_nu_ctx* ctx, int box, int n_species, const double* m_species,
+                      const double* pnu_half_init);
 
 /* ---- binned power from elsewhere ------------------------------------------------------- */
 /* Set P_cdm(k_b) of one box (host) [B] in place of a deposit, for a response computed

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <numeric>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -260,7 +261,16 @@ int prepare_time_grid(Ctx& c, double a_now) {
     for (int q = nq - 2; q >= 0; --q) dsb[q] = dsb[q + 1] + ds_interval(a[q], a[q + 1], om);
     for (int q = 0; q < nq; ++q) wb[q] = pref * tw[q] / (a[q] * hubble(a[q], om));
     rb[b].f_nu = c.f_nu[b];
-    rb[b].t_over_m = c.t_over_m[b];
+    const std::vector<double>& sp = c.species[b];
+    rb[b].n_sp = static_cast<int>(sp.size());
+    const double msum = std::accumulate(sp.begin(), sp.end(), 0.0);
+    for (int s = 0; s < kMaxSpecies; ++s) {
+      const bool on = s < rb[b].n_sp;
+      rb[b].w_sp[s] = on ? (rb[b].n_sp == 1 ? 1.0 : sp[s] / msum) : 0.0;
+      rb[b].tm_sp[s] = on ? kTnu0 / sp[s] : 0.0;
+    }
+    rb[b].t_over_m = rb[b].n_sp > 0 ? rb[b].tm_sp[0] : 0.0;
+    rb[b].sur_ok = c.sur_setting[b];
     rb[b].ds_ic = dsb[0];
     rb[b].a_i = nd[0];
     rb[b].kfs = k_free_streaming(a_now, c.m_nu[b] / c.cfg.n_species, om);
@@ -481,7 +491,11 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
     c->f_nu.push_back(m / (93.14 * cfg->omega_m * cfg->hubble * cfg->hubble));
     const double m1 = m / cfg->n_species;
     c->t_over_m.push_back(m1 > 0 ? kTnu0 / m1 : 0.0);
+    // n_species equal masses: one kernel with weight 1
+    c->species.push_back(m1 > 0 ? std::vector<double>{m1} : std::vector<double>{});
+    c->sur_setting.push_back(cfg->n_species == 3 ? 1 : 0);
   }
+  c->ic_base.assign(c->nbox, std::vector<double>(c->B, 0.0));
   const size_t nb = c->nbox, B = c->B;
 #define ALLOC(ptr, count)                 \
   do {                                    \
@@ -505,7 +519,7 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   ALLOC(c->ratio, nb * B);
   ALLOC(c->hist_pm, nb * c->Jcap * B);
   ALLOC(c->hist_pnu, nb * c->Jcap * B);
-  ALLOC(c->ic_pnu, nb * B);
+  ALLOC(c->ic_pnu, nb * kMaxSpecies * B);
   ALLOC(c->ic_theta, nb * B);
   ALLOC(c->tg_ds, nb * c->qcap);
   ALLOC(c->tg_w, nb * c->qcap);
@@ -556,7 +570,7 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   e = e ? e : hipMemset(c->d_flags, 0, sizeof(int));
   e = e ? e : hipMemset(c->hist_pm, 0, nb * c->Jcap * B * sizeof(double));
   e = e ? e : hipMemset(c->hist_pnu, 0, nb * c->Jcap * B * sizeof(double));
-  e = e ? e : hipMemset(c->ic_pnu, 0, nb * B * sizeof(double));
+  e = e ? e : hipMemset(c->ic_pnu, 0, nb * kMaxSpecies * B * sizeof(double));
   e = e ? e : hipMemset(c->ic_theta, 0, nb * B * sizeof(double));
   e = e ? e : hipMemset(c->pcdm, 0, nb * B * sizeof(double));
   e = e ? e : hipMemset(c->pnu, 0, nb * B * sizeof(double));
@@ -617,8 +631,11 @@ int pm_nu_set_history(pm_nu_ctx* ctx, int box, int n_nodes, const double* a,
                      hipMemcpyHostToDevice));
   PMNU_HIP(hipMemcpy(c->hist_pnu + off, pnu_half, n_nodes * B * sizeof(double),
                      hipMemcpyHostToDevice));
-  PMNU_HIP(hipMemcpy(c->ic_pnu + box * B, pnu_half_init, B * sizeof(double),
-                     hipMemcpyHostToDevice));
+  // every species starts from this amplitude (pm_nu_set_species may give their own)
+  for (int sp = 0; sp < kMaxSpecies; ++sp)
+    PMNU_HIP(hipMemcpy(c->ic_pnu + (static_cast<size_t>(box) * kMaxSpecies + sp) * B,
+                       pnu_half_init, B * sizeof(double), hipMemcpyHostToDevice));
+  c->ic_base[box].assign(pnu_half_init, pnu_half_init + B);
   PMNU_HIP(hipMemcpy(c->ic_theta + box * B, theta_over_delta_init, B * sizeof(double),
                      hipMemcpyHostToDevice));
   c->hist_a[box].assign(a, a + n_nodes);
@@ -671,6 +688,51 @@ int pm_nu_set_mass(pm_nu_ctx* ctx, int box, double m_nu_total) {
   c->f_nu[box] = m_nu_total / (93.14 * c->cfg.omega_m * h * h);
   const double m1 = m_nu_total / c->cfg.n_species;
   c->t_over_m[box] = m1 > 0 ? kTnu0 / m1 : 0.0;
+  c->species[box] = m1 > 0 ? std::vector<double>{m1} : std::vector<double>{};
+  c->sur_setting[box] = c->cfg.n_species == 3 ? 1 : 0;
+  c->tg_a_now = -1.0;   // the per-box constants of the response are rebuilt
+  return PM_NU_OK;
+}
+
+int pm_nu_set_species(pm_nu_ctx* ctx, int box, int n_species, const double* m_species,
+                      const double* pnu_half_init) {
+  GET_CTX(ctx);
+  if (box < 0 || box >= c->nbox) return set_error(PM_NU_EINVAL, "box %d out of range", box);
+  if (n_species < 1 || n_species > kMaxSpecies || !m_species)
+    return set_error(PM_NU_EINVAL, "n_species must be in [1, %d] with masses given",
+                     kMaxSpecies);
+  std::vector<double> massive;
+  std::vector<int> src;
+  double total = 0.0;
+  for (int i = 0; i < n_species; ++i) {
+    if (!(m_species[i] >= 0.0) || !std::isfinite(m_species[i]))
+      return set_error(PM_NU_EINVAL, "species masses must be finite and >= 0");
+    total += m_species[i];
+    if (m_species[i] > 0.0) {
+      massive.push_back(m_species[i]);
+      src.push_back(i);
+    }
+  }
+  const size_t B = c->B;
+  if (pnu_half_init)
+    for (size_t i = 0; i < static_cast<size_t>(n_species) * B; ++i)
+      if (!std::isfinite(pnu_half_init[i]))
+        return set_error(PM_NU_EINVAL, "species initial amplitudes must be finite");
+  PMNU_HIP(hipStreamSynchronize(c->stream));
+  // initial amplitudes of the massive species, compacted into slots 0..n-1
+  for (size_t s = 0; s < massive.size(); ++s) {
+    const double* from = pnu_half_init ? pnu_half_init + src[s] * B : c->ic_base[box].data();
+    PMNU_HIP(hipMemcpy(c->ic_pnu + (static_cast<size_t>(box) * kMaxSpecies + s) * B, from,
+                       B * sizeof(double), hipMemcpyHostToDevice));
+  }
+  const double h = c->cfg.hubble;
+  c->m_nu[box] = total;
+  c->f_nu[box] = total / (93.14 * c->cfg.omega_m * h * h);
+  c->t_over_m[box] = massive.empty() ? 0.0 : kTnu0 / massive[0];
+  c->species[box] = massive;
+  bool equal3 = n_species == 3 && massive.size() == 3 && !pnu_half_init;
+  for (size_t s = 1; equal3 && s < massive.size(); ++s) equal3 = massive[s] == massive[0];
+  c->sur_setting[box] = equal3 ? 1 : 0;
   c->tg_a_now = -1.0;   // the per-box constants of the response are rebuilt
   return PM_NU_OK;
 }

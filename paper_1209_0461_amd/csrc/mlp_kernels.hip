@@ -336,7 +336,8 @@ __global__ void adam_kernel(float* __restrict__ P, const float* __restrict__ g,
 // Features of (box, bin): ln k, ln a, M_nu, stored P_M^{1/2}(a_{n-m}) / P_cdm^{1/2}, m=1..8.
 __device__ __forceinline__ bool make_features(const RespBox& bx, double k, double pcdm_half,
                                               const double* hpm, int nbins, int b, float* f) {
-  if (bx.n_cur < kSurHistory + 1 || !(pcdm_half > 0.0) || !(bx.kfs > 0.0)) return false;
+  if (!bx.sur_ok || bx.n_cur < kSurHistory + 1 || !(pcdm_half > 0.0) || !(bx.kfs > 0.0))
+    return false;
   f[0] = static_cast<float>(log(k));
   f[1] = static_cast<float>(log(bx.a_now));
   f[2] = static_cast<float>(bx.m_total);
@@ -457,7 +458,8 @@ __global__ __launch_bounds__(RT) void surrogate_finish_kernel(
   }
   const double ph = sqrt(pcdm_in[ob]);
   const double pnu = exact_pnu(bx, kmean[b], ph, hpn[static_cast<size_t>(bx.n_cur - 1) * nbins + b],
-                               ic_pnu[ob], ic_theta[ob], hpm, nbins, b,
+                               ic_pnu + static_cast<size_t>(box) * kMaxSpecies * nbins,
+                               ic_theta[ob], hpm, nbins, b,
                                tg_ds + static_cast<size_t>(box) * qcap,
                                tg_w + static_cast<size_t>(box) * qcap, q_sub, iterations, red);
   if (threadIdx.x == 0) {

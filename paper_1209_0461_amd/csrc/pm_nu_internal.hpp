@@ -17,9 +17,15 @@ constexpr double kTnu0 = 1.95 * 8.617333262e-5;         // eV (1.95 K)
 constexpr double kPi = 3.14159265358979323846;
 
 // Per-box constants of the response kernel (device copy, one per box).
+constexpr int kMaxSpecies = 4;   // neutrino species with their own masses
+
 struct RespBox {
   double f_nu;       // Omega_nu / Omega_M
-  double t_over_m;   // T_nu0 / m_single
+  double t_over_m;   // T_nu0 / m of the first massive species (0 without neutrinos)
+  double w_sp[kMaxSpecies];    // m_s / M_nu of each massive species (equal masses: one, w = 1)
+  double tm_sp[kMaxSpecies];   // T_nu0 / m_s
+  int n_sp;          // massive species with distinct masses (0 without neutrinos)
+  int sur_ok;        // three equal masses: the setting the surrogate network was trained on
   double ds_ic;      // s(a_now) - s(a_i)
   double a_i;        // scale factor of node 0
   double kfs;        // free-streaming wavenumber k_fs(a_now) [h/Mpc] (0 without neutrinos)
@@ -65,6 +71,10 @@ struct Ctx {
   int device = 0;
 
   std::vector<double> m_nu, f_nu, t_over_m;
+  std::vector<std::vector<double>> species;   // per box: masses of the massive species [eV]
+                                              // (the default equal masses: one entry)
+  std::vector<int> sur_setting;    // per box: n_species = 3 equal masses (the network's)
+  std::vector<std::vector<double>> ic_base;   // per box: the initial amplitude of set_history
   std::vector<int64_t> edges;      // [B+1]
   std::vector<double> counts, kmean;
   std::vector<int> nonempty;       // bins with counts > 0
@@ -87,7 +97,7 @@ struct Ctx {
   double* ratio = nullptr;         // [nbox][B]
   double* hist_pm = nullptr;       // [nbox][Jcap][B]
   double* hist_pnu = nullptr;      // [nbox][Jcap][B]
-  double* ic_pnu = nullptr;        // [nbox][B]
+  double* ic_pnu = nullptr;        // [nbox][kMaxSpecies][B] per massive species
   double* ic_theta = nullptr;      // [nbox][B]
   double* tg_ds = nullptr;         // [nbox][qcap]
   double* tg_w = nullptr;          // [nbox][qcap]

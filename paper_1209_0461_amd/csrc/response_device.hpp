@@ -55,16 +55,24 @@ __device__ __forceinline__ double bin_mode_sum(const double* partial, int n_part
 }
 
 // eq. (P-final) for one bin: the initial-condition term plus the trapezoid sum over the
-// sub-nodes, iterated `iterations` times on the current node (every thread gets it).
-__device__ __forceinline__ double exact_pnu(const RespBox& bx, double k, double pcdm_half,
-                                            double pnu_prev, double ic_pnu, double ic_theta,
-                                            const double* hpm, int nbins, int b,
-                                            const double* ds, const double* w, int q_sub,
-                                            int iterations, double* red) {
-  if (bx.t_over_m <= 0.0) return 0.0;   // no massive neutrinos: the term drops out
-  const double kt = k * bx.t_over_m;
+// sub-nodes, iterated `iterations` times on the current node (every thread gets it). With
+// several species (mass hierarchy) each free-streams with its own kernel and the result is
+// their mean weighted by m_s / M_nu; the source term is the common P_M^{1/2} history, so
+// the quadrature uses the weighted sum of the kernels. ic_pnu: [kMaxSpecies][nbins] initial
+// amplitudes of this box.
+template <int NSP>   // species evaluated: 1 (equal masses) or kMaxSpecies (a hierarchy)
+__device__ __forceinline__ double exact_pnu_n(const RespBox& bx, double k, double pcdm_half,
+                                              double pnu_prev, const double* ic_pnu,
+                                              double ic_theta, const double* hpm, int nbins,
+                                              int b, const double* ds, const double* w,
+                                              int q_sub, int iterations, double* red) {
   const double inv_q = 1.0 / q_sub;
-  const double ic = i_fit(kt * bx.ds_ic) * ic_pnu * (1.0 - bx.ds_ic * bx.a_i * ic_theta);
+  double ic = 0.0;
+#pragma unroll
+  for (int sp = 0; sp < NSP; ++sp)           // constant bound: the arrays stay in registers
+    if (sp < bx.n_sp)
+      ic += bx.w_sp[sp] * i_fit(k * bx.tm_sp[sp] * bx.ds_ic) * ic_pnu[sp * nbins + b];
+  ic *= 1.0 - bx.ds_ic * bx.a_i * ic_theta;
   double pnu_guess = pnu_prev, pnu = 0.0;
   for (int it = 0; it < iterations; ++it) {
     const double a_cur = (1.0 - bx.f_nu) * pcdm_half + bx.f_nu * pnu_guess;
@@ -92,13 +100,30 @@ __device__ __forceinline__ double exact_pnu(const RespBox& bx, double k, double 
           const double t = r * inv_q;
           amp = (1.0 - t) * a0[u] + t * a1[u];
         }
-        acc += wq[u] * i_fit(kt * d[u]) * d[u] * amp;
+        double kern = 0.0;
+#pragma unroll
+        for (int sp = 0; sp < NSP; ++sp)
+          if (sp < bx.n_sp) kern += bx.w_sp[sp] * i_fit(k * bx.tm_sp[sp] * d[u]);
+        acc += wq[u] * kern * d[u] * amp;
       }
     }
     pnu = ic + block_sum_d(acc, red);
     pnu_guess = pnu;
   }
   return pnu;
+}
+
+__device__ __forceinline__ double exact_pnu(const RespBox& bx, double k, double pcdm_half,
+                                            double pnu_prev, const double* ic_pnu,
+                                            double ic_theta, const double* hpm, int nbins,
+                                            int b, const double* ds, const double* w,
+                                            int q_sub, int iterations, double* red) {
+  if (bx.n_sp <= 0) return 0.0;          // no massive neutrinos: the term drops out
+  if (bx.n_sp == 1)
+    return exact_pnu_n<1>(bx, k, pcdm_half, pnu_prev, ic_pnu, ic_theta, hpm, nbins, b, ds, w,
+                          q_sub, iterations, red);
+  return exact_pnu_n<kMaxSpecies>(bx, k, pcdm_half, pnu_prev, ic_pnu, ic_theta, hpm, nbins, b,
+                                  ds, w, q_sub, iterations, red);
 }
 
 }  // namespace pmnu
