@@ -3,9 +3,12 @@
 Units (paper Sec. 2.1): c = G = k_B = 1, comoving lengths in Mpc/h, wavenumbers in h/Mpc,
 so H0 = 100 h km/s/Mpc = 1/2997.92458 h/Mpc and time is measured in Mpc/h.
 
-The background is flat matter + Lambda with the neutrinos counted as matter (the paper's
-relativistic neutrino background, eq. (relativistic), is not part of this step).
+Two flat backgrounds: matter + Lambda with the neutrinos counted as matter (the default),
+and the one of Sec. 4.4 (`Background`), in which the massive neutrinos carry the energy
+density of eq. (relativistic) and photons and massless neutrinos add radiation.
 """
+import functools
+
 import numpy as np
 from scipy import integrate
 
@@ -22,22 +25,97 @@ def f_nu(m_nu_total, omega_m, hubble):
     return m_nu_total / (93.14 * omega_m * hubble * hubble)
 
 
-def hubble_rate(a, omega_m):
-    """H(a) [h/Mpc] for a flat matter + Lambda universe."""
+def _momentum_integral(g):
+    """int_0^inf g(q) dq for a smooth g decaying like a thermal tail (q in eV)."""
+    edges = np.array([0.0, 1.0, 4.0, 12.0, 40.0, 120.0]) * T_NU0
+    return sum(integrate.quad(g, lo, hi, epsabs=0.0, epsrel=1e-13, limit=200)[0]
+               for lo, hi in zip(edges[:-1], edges[1:]))
+
+
+def fermi_dirac(q):
+    """Relic neutrino occupation f_0(q) at temperature T_nu0 (the constant g/(2 pi)^3 of the
+    phase-space density cancels in every ratio below)."""
+    return 1.0 / (np.exp(q / T_NU0) + 1.0)
+
+
+@functools.lru_cache(maxsize=None)
+def _number_integral():
+    return _momentum_integral(lambda q: q * q * fermi_dirac(q))
+
+
+def nu_energy_over_rest(a, m):
+    """rho_nu(a) / (rest-mass density at a) for one species of mass m [eV], eq. (relativistic):
+    a^-3 int eps(q, a) f_0 4 pi q^2 dq over a^-3 m int f_0 4 pi q^2 dq, eps = sqrt(m^2 + q^2/a^2)."""
+    num = _momentum_integral(lambda q: np.sqrt(m * m + (q / a) ** 2) * q * q * fermi_dirac(q))
+    return num / (m * _number_integral())
+
+
+def massless_omega_h2():
+    """Omega h^2 a^4 of one massless species: the m -> 0 limit of
+    (m / 93.14 eV) a^-3 nu_energy_over_rest(a, m), i.e. int q^3 f_0 / int q^2 f_0 / 93.14 eV."""
+    return _momentum_integral(lambda q: q ** 3 * fermi_dirac(q)) / _number_integral() / 93.14
+
+
+def photon_omega_h2():
+    """Omega_gamma h^2 a^4: photons at T_gamma = (11/4)^{1/3} T_nu0 (two polarisations,
+    Bose-Einstein) against one neutrino species (neutrino + antineutrino, Fermi-Dirac)."""
+    t_gamma = (11.0 / 4.0) ** (1.0 / 3.0) * T_NU0
+    bose = integrate.quad(lambda q: q ** 3 / np.expm1(q / t_gamma), 0.0, 200.0 * t_gamma,
+                          epsabs=0.0, epsrel=1e-13, limit=200)[0]
+    fermi = _momentum_integral(lambda q: q ** 3 * fermi_dirac(q))
+    return massless_omega_h2() * bose / fermi
+
+
+class Background:
+    """Flat background of Sec. 4.4 with the neutrino energy density of eq. (relativistic).
+
+    masses: every neutrino species [eV] (massless ones included). Densities in units of
+    today's critical density: a species of mass m has Omega h^2 = m / 93.14 eV once
+    non-relativistic (Sec. 2.1) and Omega(a) = (m / 93.14 eV h^2) a^-3 nu_energy_over_rest;
+    massless species and photons are radiation; cold matter is Omega_M minus the neutrino
+    rest mass, so that Omega_M counts all matter; Lambda closes the budget today.
+    """
+
+    def __init__(self, omega_m, hubble, masses):
+        self.omega_m = float(omega_m)
+        self.hubble = float(hubble)
+        self.masses = tuple(float(m) for m in masses)
+        h2 = self.hubble ** 2
+        self.massive = tuple(m for m in self.masses if m > 0.0)
+        n_massless = len(self.masses) - len(self.massive)
+        self.omega_rest = tuple(m / (93.14 * h2) for m in self.massive)
+        self.omega_cb = self.omega_m - sum(self.omega_rest)
+        self.omega_rad = (photon_omega_h2() + n_massless * massless_omega_h2()) / h2
+        nu_today = sum(o * nu_energy_over_rest(1.0, m)
+                       for o, m in zip(self.omega_rest, self.massive))
+        self.omega_lambda = 1.0 - self.omega_cb - self.omega_rad - nu_today
+        self.key = ("relativistic", self.omega_m, self.hubble, self.masses)
+
+    def e2(self, a):
+        """(H(a) / H0)^2 at one scale factor."""
+        nu = sum(o * nu_energy_over_rest(a, m) for o, m in zip(self.omega_rest, self.massive))
+        return (self.omega_cb + nu) / a ** 3 + self.omega_rad / a ** 4 + self.omega_lambda
+
+
+def hubble_rate(a, omega_m, background=None):
+    """H(a) [h/Mpc]: flat matter + Lambda, or the given Background (Sec. 4.4)."""
     a = np.asarray(a, dtype=np.float64)
-    return H0 * np.sqrt(omega_m / a ** 3 + 1.0 - omega_m)
+    if background is None:
+        return H0 * np.sqrt(omega_m / a ** 3 + 1.0 - omega_m)
+    e2 = np.vectorize(background.e2, otypes=[np.float64])(a)
+    return H0 * np.sqrt(e2)
 
 
-def _ds_da(a, omega_m):
+def _ds_da(a, omega_m, background):
     # s = int dtau / a and dtau = da / (a^2 H)  =>  ds = da / (a^3 H)
-    return 1.0 / (a ** 3 * float(hubble_rate(a, omega_m)))
+    return 1.0 / (a ** 3 * float(hubble_rate(a, omega_m, background)))
 
 
-def superconformal_interval(a1, a2, omega_m):
+def superconformal_interval(a1, a2, omega_m, background=None):
     """s(a2) - s(a1) = int_{a1}^{a2} da / (a^3 H(a))  [Mpc/h], Sec. 3.2."""
     if a1 == a2:
         return 0.0
-    val, _ = integrate.quad(_ds_da, a1, a2, args=(omega_m,), epsabs=0.0,
+    val, _ = integrate.quad(_ds_da, a1, a2, args=(omega_m, background), epsabs=0.0,
                             epsrel=1e-13, limit=200)
     return val
 

@@ -21,23 +21,25 @@ spectra", Sec. 4.3 (iii), and gives no rule):
 """
 import numpy as np
 
-from .background import H0, T_NU0, f_nu as f_nu_of, hubble_rate, superconformal_interval
+from .background import (H0, T_NU0, Background, f_nu as f_nu_of, hubble_rate,
+                         superconformal_interval)
 from .kernel import I_fit
 
 _DS_CACHE = {}
 
 
-def _ds_piece(a1, a2, omega_m):
-    key = (float(a1), float(a2), float(omega_m))
+def _ds_piece(a1, a2, omega_m, background=None):
+    key = (float(a1), float(a2), float(omega_m), None if background is None else background.key)
     v = _DS_CACHE.get(key)
     if v is None:
-        v = superconformal_interval(a1, a2, omega_m)
+        v = superconformal_interval(a1, a2, omega_m, background)
         _DS_CACHE[key] = v
     return v
 
 
-def sub_grid(a_nodes, substeps, omega_m):
-    """Sub-nodes of the quadrature over nodes a_0..a_n (a_n = current step).
+def sub_grid(a_nodes, substeps, omega_m, background=None):
+    """Sub-nodes of the quadrature over nodes a_0..a_n (a_n = current step); the background
+    (default flat matter + Lambda) sets s.
 
     Returns a dict of per-sub-node arrays: a, trapezoid weight in ln a, bracketing node j,
     interpolation fraction t (amplitude = (1-t) A_j + t A_{j+1}), and s_n - s_q.
@@ -66,14 +68,14 @@ def sub_grid(a_nodes, substeps, omega_m):
     # s_n - s_q, summed backwards over the sub-intervals (each an accurate quadrature)
     ds = np.zeros(len(a_sub))
     for q in range(len(a_sub) - 2, -1, -1):
-        ds[q] = ds[q + 1] + _ds_piece(a_sub[q], a_sub[q + 1], omega_m)
+        ds[q] = ds[q + 1] + _ds_piece(a_sub[q], a_sub[q + 1], omega_m, background)
     return dict(a=a_sub, w=np.array(q_w), j=np.array(q_j), t=np.array(q_t), ds=ds)
 
 
 def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
                  pnu_half_init, theta_over_delta_init, a_now, m_nu_total, omega_m,
                  hubble, substeps, iterations=1, n_species=3, f_nu=None, species=None,
-                 pnu_half_init_species=None):
+                 pnu_half_init_species=None, relativistic=False):
     """P_nu^{1/2}(k_b, a_now) for every bin, eq. (P-final).
 
     hist_a (n,), hist_pm_half (n, B): stored nodes strictly before a_now (hist_a[0] = a_i).
@@ -89,6 +91,10 @@ def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
     species weighted by their share of the neutrino density, m_s / M_nu (non-relativistic);
     a massless species adds nothing. pnu_half_init_species (n_species, B): initial
     amplitude of each species (default: pnu_half_init for all).
+
+    relativistic: take s and dtau from the background of Sec. 4.4 (radiation, massless
+    species, and the massive species' energy density of eq. (relativistic)); f_nu and the
+    source (3/2) Omega_M H0^2 keep the non-relativistic matter density.
     """
     k = np.asarray(k_mean, dtype=np.float64)
     ok = np.asarray(counts) > 0
@@ -104,9 +110,10 @@ def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
         return dict(pnu_half=zero, ratio=zero.copy(),
                     pm_half_now=np.where(ok, pcdm_half, 0.0), f_nu=0.0)
     nodes = np.append(np.asarray(hist_a, dtype=np.float64), a_now)
-    g = sub_grid(nodes, substeps, omega_m)
+    bg = Background(omega_m, hubble, masses) if relativistic else None
+    g = sub_grid(nodes, substeps, omega_m, bg)
     pref = 1.5 * omega_m * H0 * H0
-    measure = g["w"] / (g["a"] * hubble_rate(g["a"], omega_m))     # d ln a / (a H)
+    measure = g["w"] / (g["a"] * hubble_rate(g["a"], omega_m, bg))  # d ln a / (a H)
     hist = np.asarray(hist_pm_half, dtype=np.float64)
     if species is None:
         # equal masses: one kernel
@@ -141,7 +148,7 @@ def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
 
 def replay_history(k_mean, counts, cdm_half, a_nodes, pnu_half_init,
                    theta_over_delta_init, m_nu_total, omega_m, hubble, substeps,
-                   n_species=3, f_nu=None, species=None):
+                   n_species=3, f_nu=None, species=None, relativistic=False):
     """A self-consistent stored history: the neutrino amplitude at every node computed by
     eq. (P-final) from the earlier nodes, as the step-by-step loop of Sec. 4.3 would.
 
@@ -161,7 +168,7 @@ def replay_history(k_mean, counts, cdm_half, a_nodes, pnu_half_init,
         r = nu_amplitude(k_mean, counts, cdm_half[j], a_nodes[:j], pm[:j], pnu[j - 1],
                          pnu_half_init, theta_over_delta_init, a_nodes[j], m_nu_total,
                          omega_m, hubble, substeps, n_species=n_species, f_nu=fn,
-                         species=species)
+                         species=species, relativistic=relativistic)
         pnu[j] = r["pnu_half"]
         pm[j] = r["pm_half_now"]
     return pm, pnu
