@@ -205,6 +205,22 @@ int pm_nu_set_mass(pm_nu_ctx* ctx, int box, double m_nu_total);
 int pm_nu_set_species(pm_nu_ctx* ctx, int box, int n_species, const double* m_species,
                       const double* pnu_half_init);
 
+/* ---- background expansion -------------------------------------------------------------- */
+/* Choose the flat background whose H(a) enters the time grid of eq. (P-final): the
+ * superconformal time s = int da/(a^3 H) and the measure dtau = d ln a/(a H).
+ *   relativistic = 0 (default): matter + Lambda, the neutrinos counted as matter.
+ *   relativistic = 1: the background of Sec. 4.4. Each massive species carries the energy
+ *     density of eq. (relativistic), a^-3 int sqrt(m^2 + q^2/a^2) f_0(q) 4 pi q^2 dq
+ *     (Fermi-Dirac f_0 at T_nu0 = 1.95 K), normalised so that a non-relativistic species
+ *     has Omega_nu h^2 = m/93.14 eV; photons (T_gamma = (11/4)^{1/3} T_nu0) and massless
+ *     species are radiation; cold matter is Omega_M minus the neutrino rest mass; Lambda
+ *     closes the budget today (H(1) = H0).
+ * Applies to every box from the next response. f_nu and the source of eq. (P-final) and of
+ * the Poisson equation keep Omega_M. The surrogate was trained on the default background
+ * and steps aside under the relativistic one (the exact integral runs). Sync. Errors:
+ * PM_NU_EINVAL unless relativistic is 0 or 1. */
+int pm_nu_set_background(pm_nu_ctx* ctx, int relativistic);
+
 /* ---- binned power from elsewhere ------------------------------------------------------- */
 /* Set P_cdm(k_b) of one box (host) [B] in place of a deposit, for a response computed
  * from a spectrum measured elsewhere (or for building the surrogate's training set). The

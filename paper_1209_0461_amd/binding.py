@@ -59,6 +59,7 @@ SIGNATURES = {
     "pm_nu_copy_force_grid": (_INT, [_P, _INT, _INT, _P]),
     "pm_nu_set_timing": (_INT, [_P, _INT]),
     "pm_nu_set_species": (_INT, [_P, _INT, _INT, _D, _D]),
+    "pm_nu_set_background": (_INT, [_P, _INT]),
     "pm_nu_set_timing_mask": (_INT, [_P, ctypes.c_uint32]),
     "pm_nu_read_timing": (_INT, [_P, ctypes.POINTER(_INT), ctypes.POINTER(ctypes.c_char_p), _D, _I64]),
     "pm_nu_graph_capture": (_INT, [_P, _P, _P, ctypes.c_double]),
@@ -239,6 +240,12 @@ def pm_nu_set_species(h, box, masses, pnu_half_init=None):
     ic = None if pnu_half_init is None else np.ascontiguousarray(pnu_half_init, dtype=np.float64)
     _check(load_library().pm_nu_set_species(h, int(box), len(m), _dptr(m),
                                             None if ic is None else _dptr(ic)))
+
+
+def pm_nu_set_background(h, relativistic):
+    """Background of the time grid: 0 matter + Lambda, 1 with radiation and relativistic
+    neutrinos (eq. (relativistic))."""
+    _check(load_library().pm_nu_set_background(h, 1 if relativistic else 0))
 
 
 def pm_nu_set_timing_mask(h, stage_mask):

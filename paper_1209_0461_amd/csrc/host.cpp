@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "background.hpp"
 #include "pm_nu_internal.hpp"
 
 namespace pmnu {
@@ -63,47 +64,6 @@ void timer_end(Ctx& c) {
 
 namespace {
 
-// ------------------------------------------------------------- quadrature -----------
-// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
-struct GaussLegendre {
-  std::vector<double> x, w;
-  explicit GaussLegendre(int n) : x(n), w(n) {
-    for (int i = 0; i < n; ++i) {
-      double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
-      for (int it = 0; it < 100; ++it) {
-        double p0 = 1.0, p1 = z;
-        for (int k = 2; k <= n; ++k) {
-          const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-          p0 = p1;
-          p1 = p2;
-        }
-        const double dp = n * (z * p1 - p0) / (z * z - 1.0);
-        const double dz = p1 / dp;
-        z -= dz;
-        if (std::fabs(dz) < 1e-16) {
-          double q0 = 1.0, q1 = z;
-          for (int k = 2; k <= n; ++k) {
-            const double q2 = ((2.0 * k - 1.0) * z * q1 - (k - 1.0) * q0) / k;
-            q0 = q1;
-            q1 = q2;
-          }
-          const double d = n * (z * q1 - q0) / (z * z - 1.0);
-          x[i] = z;
-          w[i] = 2.0 / ((1.0 - z * z) * d * d);
-          break;
-        }
-      }
-    }
-  }
-};
-
-const GaussLegendre& gl16() {
-  static const GaussLegendre g(16);
-  return g;
-}
-
-double hubble(double a, double om) { return kH0 * std::sqrt(om / (a * a * a) + 1.0 - om); }
-
 // k_fs(a) = sqrt(3/2 Omega_M(a) <v^-2>) a H, <v^-2> = 2 ln2/(3 zeta(3)) (m a / T_nu0)^2
 double k_free_streaming(double a, double m_single, double om) {
   if (!(m_single > 0.0)) return 0.0;
@@ -112,19 +72,6 @@ double k_free_streaming(double a, double m_single, double om) {
   const double v2 = (2.0 * std::log(2.0) / (3.0 * 1.2020569031595942)) *
                     std::pow(m_single * a / kTnu0, 2);
   return std::sqrt(1.5 * om_a * v2) * a * kH0 * std::sqrt(e2);
-}
-
-// s(a2) - s(a1) = int da / (a^3 H) = int dln a / (a^2 H), over a short interval in ln a.
-double ds_interval(double a1, double a2, double om) {
-  const GaussLegendre& g = gl16();
-  const double u1 = std::log(a1), u2 = std::log(a2);
-  const double hw = 0.5 * (u2 - u1), mid = 0.5 * (u1 + u2);
-  double s = 0.0;
-  for (size_t i = 0; i < g.x.size(); ++i) {
-    const double a = std::exp(mid + hw * g.x[i]);
-    s += g.w[i] / (a * a * hubble(a, om));
-  }
-  return s * hw;
 }
 
 bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
@@ -235,7 +182,7 @@ int prepare_time_grid(Ctx& c, double a_now) {
   bool same = (c.tg_a_now == a_now) && (c.tg_version == c.hist_version) && ncur == c.n_cur;
   if (same) return PM_NU_OK;
   const double om = c.cfg.omega_m;
-  const double pref = 1.5 * om * kH0 * kH0;
+  const double pref = 1.5 * om * kH0 * kH0;   // the source keeps all matter, Omega_M
   const int Q = c.Q;
   std::vector<double> ds(static_cast<size_t>(c.nbox) * c.qcap, 0.0);
   std::vector<double> w(static_cast<size_t>(c.nbox) * c.qcap, 0.0);
@@ -255,11 +202,13 @@ int prepare_time_grid(Ctx& c, double a_now) {
       }
     }
     a[nq - 1] = nd[n];
+    const Background bg = make_background(c.relativistic, om, c.cfg.hubble, c.species[b],
+                                          c.nu_mult[b], c.nu_massless[b]);
     double* dsb = ds.data() + static_cast<size_t>(b) * c.qcap;
     double* wb = w.data() + static_cast<size_t>(b) * c.qcap;
     dsb[nq - 1] = 0.0;
-    for (int q = nq - 2; q >= 0; --q) dsb[q] = dsb[q + 1] + ds_interval(a[q], a[q + 1], om);
-    for (int q = 0; q < nq; ++q) wb[q] = pref * tw[q] / (a[q] * hubble(a[q], om));
+    for (int q = nq - 2; q >= 0; --q) dsb[q] = dsb[q + 1] + ds_of(bg, a[q], a[q + 1]);
+    for (int q = 0; q < nq; ++q) wb[q] = pref * tw[q] / (a[q] * hubble_of(bg, a[q]));
     rb[b].f_nu = c.f_nu[b];
     const std::vector<double>& sp = c.species[b];
     rb[b].n_sp = static_cast<int>(sp.size());
@@ -270,7 +219,7 @@ int prepare_time_grid(Ctx& c, double a_now) {
       rb[b].tm_sp[s] = on ? kTnu0 / sp[s] : 0.0;
     }
     rb[b].t_over_m = rb[b].n_sp > 0 ? rb[b].tm_sp[0] : 0.0;
-    rb[b].sur_ok = c.sur_setting[b];
+    rb[b].sur_ok = c.sur_setting[b] && !c.relativistic;   // trained on matter + Lambda
     rb[b].ds_ic = dsb[0];
     rb[b].a_i = nd[0];
     rb[b].kfs = k_free_streaming(a_now, c.m_nu[b] / c.cfg.n_species, om);
@@ -493,6 +442,8 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
     c->t_over_m.push_back(m1 > 0 ? kTnu0 / m1 : 0.0);
     // n_species equal masses: one kernel with weight 1
     c->species.push_back(m1 > 0 ? std::vector<double>{m1} : std::vector<double>{});
+    c->nu_mult.push_back(cfg->n_species);
+    c->nu_massless.push_back(m1 > 0 ? 0 : cfg->n_species);
     c->sur_setting.push_back(cfg->n_species == 3 ? 1 : 0);
   }
   c->ic_base.assign(c->nbox, std::vector<double>(c->B, 0.0));
@@ -689,6 +640,8 @@ int pm_nu_set_mass(pm_nu_ctx* ctx, int box, double m_nu_total) {
   const double m1 = m_nu_total / c->cfg.n_species;
   c->t_over_m[box] = m1 > 0 ? kTnu0 / m1 : 0.0;
   c->species[box] = m1 > 0 ? std::vector<double>{m1} : std::vector<double>{};
+  c->nu_mult[box] = c->cfg.n_species;
+  c->nu_massless[box] = m1 > 0 ? 0 : c->cfg.n_species;
   c->sur_setting[box] = c->cfg.n_species == 3 ? 1 : 0;
   c->tg_a_now = -1.0;   // the per-box constants of the response are rebuilt
   return PM_NU_OK;
@@ -730,10 +683,21 @@ int pm_nu_set_species(pm_nu_ctx* ctx, int box, int n_species, const double* m_sp
   c->f_nu[box] = total / (93.14 * c->cfg.omega_m * h * h);
   c->t_over_m[box] = massive.empty() ? 0.0 : kTnu0 / massive[0];
   c->species[box] = massive;
+  c->nu_mult[box] = 1;
+  c->nu_massless[box] = n_species - static_cast<int>(massive.size());
   bool equal3 = n_species == 3 && massive.size() == 3 && !pnu_half_init;
   for (size_t s = 1; equal3 && s < massive.size(); ++s) equal3 = massive[s] == massive[0];
   c->sur_setting[box] = equal3 ? 1 : 0;
   c->tg_a_now = -1.0;   // the per-box constants of the response are rebuilt
+  return PM_NU_OK;
+}
+
+int pm_nu_set_background(pm_nu_ctx* ctx, int relativistic) {
+  GET_CTX(ctx);
+  if (relativistic != 0 && relativistic != 1)
+    return set_error(PM_NU_EINVAL, "relativistic must be 0 or 1 (got %d)", relativistic);
+  c->relativistic = relativistic == 1;
+  c->tg_a_now = -1.0;   // the time grid is rebuilt on the next response
   return PM_NU_OK;
 }
 

@@ -73,6 +73,9 @@ struct Ctx {
   std::vector<double> m_nu, f_nu, t_over_m;
   std::vector<std::vector<double>> species;   // per box: masses of the massive species [eV]
                                               // (the default equal masses: one entry)
+  std::vector<int> nu_mult;        // per box: how many species share each entry of species
+  std::vector<int> nu_massless;    // per box: massless species (radiation in the background)
+  bool relativistic = false;       // background with radiation and eq. (relativistic)
   std::vector<int> sur_setting;    // per box: n_species = 3 equal masses (the network's)
   std::vector<std::vector<double>> ic_base;   // per box: the initial amplitude of set_history
   std::vector<int64_t> edges;      // [B+1]

@@ -343,3 +343,68 @@ def test_mass_hierarchy_matches_oracle(which):
                            hist["theta_over_delta_init"], 0.8, M, 0.3, 0.7, 8)
     assert np.abs(got["pnu_half"][ok] / eq["pnu_half"][ok] - 1).max() > 100 * TOL_NU
     ctx.close()
+
+
+@pytest.mark.parametrize("masses", [None, "hierarchy_inverted_eV"])
+def test_relativistic_background_matches_oracle(masses):
+    """The background of Sec. 4.4 (radiation, massless species, and the energy density of
+    eq. (relativistic)) in the time grid, early enough (a <= 0.1) that it matters."""
+    import json
+    import os
+    import torch
+    import oracle.response as ores
+    import oracle.step as ostep
+    from paper_1209_0461_amd import PMNu, binding
+    from synth import log_spaced_nodes, synthetic_history
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+    sp_m = None if masses is None else np.array(gold[masses]["value"])
+    M = 0.3 if sp_m is None else float(sp_m.sum())
+    nm, box, nb, J, a_now = 32, 128.0, 16, 16, 0.1
+    pos = make_inputs(32, box, 0.2, 57)
+    sp = ostep.spectrum(pos, nm, box, nb)
+    nodes = log_spaced_nodes(0.005, a_now, J)
+    hist = synthetic_history(sp["k_mean"], np.sqrt(sp["p_cdm"]), nodes, M)
+    args = (sp["k_mean"], sp["counts"], np.sqrt(sp["p_cdm"]), hist["a"], hist["pm_half"],
+            hist["pnu_half"][-1], hist["pnu_half_init"], hist["theta_over_delta_init"], a_now,
+            M, 0.3, 0.7, 8)
+    r = ores.nu_amplitude(*args, species=sp_m, relativistic=True)
+    flat = ores.nu_amplitude(*args, species=sp_m)
+    forces = ostep.forces(pos, sp["delta_k"], nm, box, sp["k_mean"], sp["counts"], r["ratio"],
+                          r["f_nu"], a_now, 0.3, True)
+    ctx = PMNu(nm, len(pos), box, nb, J + 2, [M], response_mode=2)
+    binding.pm_nu_surrogate_load(ctx.h, np.load(os.path.join(
+        os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1209_0461_amd",
+        "data", "surrogate_pm256.npy")))
+    ctx.set_history(0, hist)
+    if sp_m is not None:
+        binding.pm_nu_set_species(ctx.h, 0, sp_m)
+    binding.pm_nu_set_background(ctx.h, 1)
+    p = torch.from_numpy(pos).cuda()
+    acc = torch.zeros_like(p)
+    ctx.step(p, acc, a_now)
+    torch.cuda.synchronize()
+    ok = sp["counts"] > 0
+    got = ctx.spectrum(0)
+    assert np.abs(got["pnu_half"][ok] / r["pnu_half"][ok] - 1).max() <= TOL_NU
+    assert np.abs(got["pnu_half"][ok] / flat["pnu_half"][ok] - 1).max() > 100 * TOL_NU
+    assert rms_rel(acc.cpu().numpy(), forces) <= TOL_FORCE_RMS
+    exact, sur = binding.pm_nu_get_surrogate_check(ctx.h, 0, nb)
+    assert np.array_equal(exact, sur)          # the network is not used off its background
+    # back to matter + Lambda: the oracle's flat result again (a fresh history row)
+    binding.pm_nu_set_background(ctx.h, 0)
+    ctx.set_history(0, hist)
+    if sp_m is not None:
+        binding.pm_nu_set_species(ctx.h, 0, sp_m)
+    ctx.step(p, acc, a_now)
+    torch.cuda.synchronize()
+    got = ctx.spectrum(0)
+    assert np.abs(got["pnu_half"][ok] / flat["pnu_half"][ok] - 1).max() <= TOL_NU
+    ctx.close()
+
+
+def test_background_rejects_bad_flag():
+    from paper_1209_0461_amd import PMNu, binding
+    ctx = PMNu(16, 8, 64.0, 8, 4, [0.1])
+    assert binding.ERRORS[binding.load_library().pm_nu_set_background(ctx.h, 2)] == "EINVAL"
+    assert b"relativistic" in binding.load_library().pm_nu_last_error()
+    ctx.close()
