@@ -3,8 +3,8 @@
 I(X) is the Fourier transform of the unperturbed momentum distribution, normalised so
 that I(0) = 1; for relic neutrinos it depends only on x = X T_nu0 with X = k (s - s')/m.
 The method uses the rational fit of Appendix C, eq. (fit); the paper states that the exact
-function gives the same results. The exact alternating series of Appendix C is kept here
-only so that tests can pin the fit against it.
+function gives the same results. The exact alternating series of the same appendix serves
+the tests that pin the fit and the response computed with the exact kernel.
 """
 import numpy as np
 
@@ -20,15 +20,28 @@ def I_fit(x):
     return num / den
 
 
-def I_series(x, n_terms=4000):
+def I_series(x, n_terms=64, levels=16, chunk=256):
     """Exact I(x) = 4/(3 zeta(3)) sum_{n>=1} (-1)^{n+1} n/(n^2+x^2)^2 (Appendix C).
 
-    The alternating tail is summed with the average of two consecutive partial sums,
-    which for this monotone series brings the truncation error to O(N^-4).
+    The terms grow up to n ~ x/sqrt(3) and then fall off smoothly, so the series is summed
+    plainly over N = max(n_terms, 3x + 64) terms and the alternating tail is taken from the
+    partial sums S_N ... S_{N+levels} averaged pairwise `levels` times (the Euler
+    transformation of the tail). Relative error ~1e-14 for x <= 300, ~1e-12 at x = 1e3
+    (rounding: the sum cancels to ~1/x^4 from terms ~1/x^3).
     """
     x = np.atleast_1d(np.asarray(x, dtype=np.float64))
-    n = np.arange(1, n_terms + 2, dtype=np.float64)[:, None]
-    terms = np.where(n % 2 == 1, 1.0, -1.0) * n / (n * n + x[None, :] ** 2) ** 2
-    partial = np.cumsum(terms, axis=0)
-    s = 0.5 * (partial[-1] + partial[-2])
-    return 4.0 / (3.0 * ZETA3) * s
+    out = np.empty_like(x)
+    order = np.argsort(x)
+    for c0 in range(0, len(x), chunk):
+        idx = order[c0:c0 + chunk]
+        xc = x[idx]
+        n_plain = int(max(n_terms, 3.0 * xc.max() + 64))
+        n = np.arange(1, n_plain + levels + 1, dtype=np.float64)[:, None]
+        terms = np.where(n % 2 == 1, 1.0, -1.0) * n / (n * n + xc[None, :] ** 2) ** 2
+        head = np.sum(terms[:n_plain], axis=0)
+        partial = head + np.concatenate([np.zeros((1, len(xc))),
+                                         np.cumsum(terms[n_plain:], axis=0)])
+        for _ in range(levels):
+            partial = 0.5 * (partial[1:] + partial[:-1])
+        out[idx] = 4.0 / (3.0 * ZETA3) * partial[0]
+    return out

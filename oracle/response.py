@@ -23,7 +23,7 @@ import numpy as np
 
 from .background import (H0, T_NU0, Background, f_nu as f_nu_of, hubble_rate,
                          superconformal_interval)
-from .kernel import I_fit
+from .kernel import I_fit, I_series
 
 _DS_CACHE = {}
 
@@ -75,7 +75,7 @@ def sub_grid(a_nodes, substeps, omega_m, background=None):
 def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
                  pnu_half_init, theta_over_delta_init, a_now, m_nu_total, omega_m,
                  hubble, substeps, iterations=1, n_species=3, f_nu=None, species=None,
-                 pnu_half_init_species=None, relativistic=False):
+                 pnu_half_init_species=None, relativistic=False, kernel="fit"):
     """P_nu^{1/2}(k_b, a_now) for every bin, eq. (P-final).
 
     hist_a (n,), hist_pm_half (n, B): stored nodes strictly before a_now (hist_a[0] = a_i).
@@ -95,6 +95,9 @@ def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
     relativistic: take s and dtau from the background of Sec. 4.4 (radiation, massless
     species, and the massive species' energy density of eq. (relativistic)); f_nu and the
     source (3/2) Omega_M H0^2 keep the non-relativistic matter density.
+
+    kernel: "fit" (eq. (fit), the method's choice) or "series" (the exact function of
+    Appendix C).
     """
     k = np.asarray(k_mean, dtype=np.float64)
     ok = np.asarray(counts) > 0
@@ -124,12 +127,21 @@ def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
                else np.tile(np.asarray(pnu_half_init, dtype=np.float64), (len(masses), 1)))
         groups = [(m / m_nu_total, m, ics[i]) for i, m in enumerate(masses) if m > 0.0]
 
+    if kernel == "fit":
+        I = I_fit
+    elif kernel == "series":
+        def I(x):
+            x = np.asarray(x, dtype=np.float64)
+            return I_series(x.reshape(-1)).reshape(x.shape)
+    else:
+        raise ValueError(f"kernel must be 'fit' or 'series', not {kernel!r}")
+
     # initial-condition term: I(x_i) P_nu^{1/2}(a_i) {1 - (s - s_i) a_i [theta/delta]_i}
     phase = 1.0 - g["ds"][0] * nodes[0] * np.asarray(theta_over_delta_init)
-    ic = sum(w * I_fit(k * g["ds"][0] * T_NU0 / m) * p0 for w, m, p0 in groups) * phase
+    ic = sum(w * I(k * g["ds"][0] * T_NU0 / m) * p0 for w, m, p0 in groups) * phase
 
-    kernel = sum(w * I_fit(np.outer(g["ds"] * T_NU0 / m, k)) for w, m, _ in groups)
-    kernel = kernel * g["ds"][:, None]                                 # (q, B)
+    kern = sum(w * I(np.outer(g["ds"] * T_NU0 / m, k)) for w, m, _ in groups)
+    kern = kern * g["ds"][:, None]                                     # (q, B)
 
     pnu_guess = np.asarray(pnu_half_prev, dtype=np.float64)
     for _ in range(max(1, iterations)):
@@ -137,7 +149,7 @@ def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
         table = np.vstack([hist, a_cur[None, :]])                     # (n+1, B)
         amp = ((1.0 - g["t"])[:, None] * table[g["j"]]
                + g["t"][:, None] * table[np.minimum(g["j"] + 1, len(table) - 1)])
-        integral = pref * np.sum(measure[:, None] * kernel * amp, axis=0)
+        integral = pref * np.sum(measure[:, None] * kern * amp, axis=0)
         pnu = ic + integral
         pnu_guess = pnu
     pnu = np.where(ok, pnu, 0.0)

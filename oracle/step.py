@@ -39,10 +39,11 @@ def forces(pos, delta_k, n_mesh, box, k_mean, counts, ratio, f_nu, a_now, omega_
 
 def full_step(pos, n_mesh, box, n_bins, history, a_now, m_nu_total, omega_m=0.3,
               hubble=0.7, substeps=8, iterations=1, deconvolve=True, n_species=3,
-              return_grids=False, species=None, relativistic=False):
+              return_grids=False, species=None, relativistic=False, kernel="fit"):
     """Whole step for one box. ``history`` is a dict with keys a, pm_half, pnu_half,
     pnu_half_init, theta_over_delta_init (as produced by synth.synthetic_history);
-    relativistic selects the background of Sec. 4.4 for the time grid."""
+    relativistic selects the background of Sec. 4.4 for the time grid; kernel "fit" or
+    "series" the form of I(x) (Appendix C)."""
     sp = spectrum(pos, n_mesh, box, n_bins)
     pcdm_half = np.sqrt(sp["p_cdm"])
     r = response.nu_amplitude(sp["k_mean"], sp["counts"], pcdm_half, history["a"],
@@ -50,7 +51,7 @@ def full_step(pos, n_mesh, box, n_bins, history, a_now, m_nu_total, omega_m=0.3,
                               history["pnu_half_init"], history["theta_over_delta_init"],
                               a_now, m_nu_total, omega_m, hubble, substeps,
                               iterations=iterations, n_species=n_species, species=species,
-                              relativistic=relativistic)
+                              relativistic=relativistic, kernel=kernel)
     out = forces(pos, sp["delta_k"], n_mesh, box, sp["k_mean"], sp["counts"], r["ratio"],
                  r["f_nu"], a_now, omega_m, deconvolve, return_grids)
     if return_grids:

@@ -25,24 +25,24 @@ with open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
     GOLD = json.load(_f)
 
 
-def _eds_response(k, m, a0, an, J, Q=8):
+def _eds_response(k, m, a0, an, J, Q=8, kern="fit"):
     nodes = log_spaced_nodes(a0, an, J)
     B = len(k)
     r = response.nu_amplitude(k, np.ones(B), an * np.ones(B), nodes[:-1],
                               nodes[:-1, None] * np.ones((1, B)), np.zeros(B), np.zeros(B),
-                              np.zeros(B), an, 3 * m, 1.0, 0.7, Q, f_nu=0.0)
+                              np.zeros(B), an, 3 * m, 1.0, 0.7, Q, f_nu=0.0, kernel=kern)
     return r["pnu_half"] / an
 
 
-def _eds_closed_form(k, m, a0, an):
+def _eds_closed_form(k, m, a0, an, I=kernel.I_fit):
     """F_fin = (6/x_k^2) int_0^{x_max} x I(x) / (1 + x/x_k)^4 dx (Appendix A), with
     x_k = 2 k T/(m a^2 H) and x_max = k (s - s_i) T / m, s = -2/(H0 sqrt(a)) in EdS."""
     T = bg.T_NU0
     h = bg.H0 * an ** -1.5
     xk = 2 * k * T / (m * an ** 2 * h)
     xmax = k * (2.0 / bg.H0) * (a0 ** -0.5 - an ** -0.5) * T / m
-    val = integrate.quad(lambda x: x * kernel.I_fit(x) / (1 + x / xk) ** 4, 0, xmax,
-                         limit=500, epsrel=1e-12)[0]
+    val = integrate.quad(lambda x: x * float(np.asarray(I(x)).reshape(-1)[0]) / (1 + x / xk) ** 4,
+                         0, xmax, limit=500, epsrel=1e-12)[0]
     return 6.0 / xk ** 2 * val
 
 
@@ -57,6 +57,20 @@ def test_eds_closed_form_second_order_convergence():
     assert np.all(errs[-1] < 2e-5)
     ratio = errs[:-1] / errs[1:]
     assert np.all((ratio > 3.6) & (ratio < 4.4))
+
+
+def test_eds_closed_form_with_the_exact_kernel():
+    """Appendix A's closed form holds for any I: with the exact series of Appendix C in both
+    the closed form and the quadrature."""
+    k = np.array([0.02, 0.2, 1.0])
+    m, a0, an = 0.1, 0.01, 0.5
+    ref = np.array([_eds_closed_form(kk, m, a0, an, kernel.I_series) for kk in k])
+    got = _eds_response(k, m, a0, an, 400, kern="series")
+    assert np.allclose(got, ref, rtol=2e-5)
+    # and the fit's response stays within the fit's own accuracy of the exact one (App. C)
+    fit = _eds_response(k, m, a0, an, 400)
+    assert np.all(np.abs(fit / got - 1) < GOLD["fit_rel_err_all_x"]["tol"])
+    assert np.abs(fit / got - 1).max() > 1e-5          # but they are different kernels
 
 
 def test_eds_closed_form_other_mass():
