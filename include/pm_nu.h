@@ -221,6 +221,23 @@ int pm_nu_set_species(pm_nu_ctx* ctx, int box, int n_species, const double* m_sp
  * PM_NU_EINVAL unless relativistic is 0 or 1. */
 int pm_nu_set_background(pm_nu_ctx* ctx, int relativistic);
 
+/* ---- free-streaming kernel I(x) ------------------------------------------------------- */
+/* Choose I(x) in eq. (P-final) for every box from the next response:
+ *   series = 0 (default): the rational fit eq. (fit) of Appendix C;
+ *   series = 1: the exact function of Appendix C, 4/(3 zeta(3)) sum_{n>=1} (-1)^{n+1}
+ *     n/(n^2+x^2)^2, summed with the alternating-series acceleration of Cohen, Rodriguez
+ *     Villegas and Zagier (32 terms; relative error at rounding level for x <= 1e3 and
+ *     below 1e-12 for x <= 1e4).
+ * The surrogate was trained with the fit and steps aside under the series. Sync.
+ * Errors: PM_NU_EINVAL unless series is 0 or 1. */
+int pm_nu_set_kernel(pm_nu_ctx* ctx, int series);
+
+/* I(x) at n points (series as above): x and out are device arrays of n doubles, launched
+ * on `stream` (NULL: the default stream) and not waited for. A diagnostic of the device
+ * kernels; needs no context. Errors: PM_NU_EINVAL for n < 0, a NULL array with n > 0 or a
+ * bad flag; PM_NU_EHIP if the launch fails. */
+int pm_nu_kernel_values(const double* x, int64_t n, int series, double* out, void* stream);
+
 /* ---- binned power from elsewhere ------------------------------------------------------- */
 /* Set P_cdm(k_b) of one box (host) [B] in place of a deposit, for a response computed
  * from a spectrum measured elsewhere (or for building the surrogate's training set). The

@@ -60,6 +60,8 @@ SIGNATURES = {
     "pm_nu_set_timing": (_INT, [_P, _INT]),
     "pm_nu_set_species": (_INT, [_P, _INT, _INT, _D, _D]),
     "pm_nu_set_background": (_INT, [_P, _INT]),
+    "pm_nu_set_kernel": (_INT, [_P, _INT]),
+    "pm_nu_kernel_values": (_INT, [_P, ctypes.c_int64, _INT, _P, _P]),
     "pm_nu_set_timing_mask": (_INT, [_P, ctypes.c_uint32]),
     "pm_nu_read_timing": (_INT, [_P, ctypes.POINTER(_INT), ctypes.POINTER(ctypes.c_char_p), _D, _I64]),
     "pm_nu_graph_capture": (_INT, [_P, _P, _P, ctypes.c_double]),
@@ -246,6 +248,21 @@ def pm_nu_set_background(h, relativistic):
     """Background of the time grid: 0 matter + Lambda, 1 with radiation and relativistic
     neutrinos (eq. (relativistic))."""
     _check(load_library().pm_nu_set_background(h, 1 if relativistic else 0))
+
+
+def pm_nu_set_kernel(h, series):
+    """I(x) in the history integral: 0 the fit eq. (fit), 1 the exact series (Appendix C)."""
+    _check(load_library().pm_nu_set_kernel(h, 1 if series else 0))
+
+
+def pm_nu_kernel_values(x, out, series, stream=None):
+    """I(x) on the device: x and out are float64 device tensors of the same length."""
+    import torch
+    if x.dtype != torch.float64 or out.dtype != torch.float64 or out.numel() != x.numel():
+        raise ValueError("x and out must be float64 tensors of the same length")
+    st = stream if stream is not None else current_stream_handle()
+    _check(load_library().pm_nu_kernel_values(_dev(x), int(x.numel()), 1 if series else 0,
+                                              _dev(out), st))
 
 
 def pm_nu_set_timing_mask(h, stage_mask):

@@ -219,7 +219,9 @@ int prepare_time_grid(Ctx& c, double a_now) {
       rb[b].tm_sp[s] = on ? kTnu0 / sp[s] : 0.0;
     }
     rb[b].t_over_m = rb[b].n_sp > 0 ? rb[b].tm_sp[0] : 0.0;
-    rb[b].sur_ok = c.sur_setting[b] && !c.relativistic;   // trained on matter + Lambda
+    // the network was trained on matter + Lambda with the fit for I(x)
+    rb[b].sur_ok = c.sur_setting[b] && !c.relativistic && !c.series;
+    rb[b].series = c.series ? 1 : 0;
     rb[b].ds_ic = dsb[0];
     rb[b].a_i = nd[0];
     rb[b].kfs = k_free_streaming(a_now, c.m_nu[b] / c.cfg.n_species, om);
@@ -698,6 +700,25 @@ int pm_nu_set_background(pm_nu_ctx* ctx, int relativistic) {
     return set_error(PM_NU_EINVAL, "relativistic must be 0 or 1 (got %d)", relativistic);
   c->relativistic = relativistic == 1;
   c->tg_a_now = -1.0;   // the time grid is rebuilt on the next response
+  return PM_NU_OK;
+}
+
+int pm_nu_set_kernel(pm_nu_ctx* ctx, int series) {
+  GET_CTX(ctx);
+  if (series != 0 && series != 1)
+    return set_error(PM_NU_EINVAL, "series must be 0 or 1 (got %d)", series);
+  c->series = series == 1;
+  c->tg_a_now = -1.0;   // the per-box constants of the response are rebuilt
+  return PM_NU_OK;
+}
+
+int pm_nu_kernel_values(const double* x, int64_t n, int series, double* out, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !out)))
+    return set_error(PM_NU_EINVAL, "x and out must be device arrays of n >= 0 doubles");
+  if (series != 0 && series != 1)
+    return set_error(PM_NU_EINVAL, "series must be 0 or 1 (got %d)", series);
+  hipError_t e = launch_kernel_values(x, n, series, out, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return set_error(PM_NU_EHIP, "kernel_values: %s", hipGetErrorString(e));
   return PM_NU_OK;
 }
 

@@ -439,7 +439,7 @@ __global__ __launch_bounds__(RT) void surrogate_finish_kernel(
     double* __restrict__ ratio_out, const double* __restrict__ sur_r,
     const int* __restrict__ sur_use, double* __restrict__ chk_exact,
     double* __restrict__ chk_sur) {
-  __shared__ double red[RT / 64];
+  __shared__ double red[2 * RT / 64];
   const int b = blockIdx.x, box = blockIdx.y;
   const size_t ob = static_cast<size_t>(box) * nbins + b;
   const bool net = sur_use[ob] != 0;

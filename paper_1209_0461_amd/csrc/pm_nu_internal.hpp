@@ -33,6 +33,7 @@ struct RespBox {
   double a_now;      // scale factor of the current step
   int nq;            // sub-nodes of the quadrature (current step included)
   int n_cur;         // history row of the current step
+  int series;        // 1: exact series for I(x), 0: the fit eq. (fit)
 };
 
 // Launch shapes chosen by the autotuner (defaults are safe for every N).
@@ -76,6 +77,7 @@ struct Ctx {
   std::vector<int> nu_mult;        // per box: how many species share each entry of species
   std::vector<int> nu_massless;    // per box: massless species (radiation in the background)
   bool relativistic = false;       // background with radiation and eq. (relativistic)
+  bool series = false;             // exact I(x) series instead of the fit
   std::vector<int> sur_setting;    // per box: n_species = 3 equal masses (the network's)
   std::vector<std::vector<double>> ic_base;   // per box: the initial amplitude of set_history
   std::vector<int64_t> edges;      // [B+1]
@@ -244,6 +246,8 @@ hipError_t launch_patch_reduce(const unsigned long long* patches, const int4* hd
                                int nbox, int n, double scale, hipStream_t s);
 hipError_t launch_delta_to_density(const float* delta, float* out, int64_t n, float rho_bar,
                                    hipStream_t s);
+hipError_t launch_kernel_values(const double* x, int64_t n, int series, double* out,
+                                hipStream_t s);
 hipError_t launch_bin_power(const double* partial, int n_partial, const double* counts,
                             int nbins, double norm, int nbox, double* pcdm, hipStream_t s);
 hipError_t launch_rtable(const double* ratio, const double* lnk, const int* nonempty,

@@ -15,6 +15,56 @@ __device__ __forceinline__ double i_fit(double x) {
   return num / den;
 }
 
+// The exact kernel of Appendix C, I(x) = 4/(3 zeta(3)) sum_{n>=1} (-1)^{n+1} n/(n^2+x^2)^2,
+// summed with the alternating-series acceleration of Cohen, Rodriguez Villegas and Zagier
+// (Experimental Math. 9 (2000) 3, their Algorithm 1): sum_{k>=0} (-1)^k a_k ~ sum_k c_k a_k/d
+// over n terms. It applies because a_k = (k+1)/((k+1)^2+x^2)^2 = int_0^1 t^k w(t) dt with
+// w(e^-u) = u sin(xu)/(2x), and the error is below 2 int|w| / (3+sqrt 8)^n: with n = 32 the
+// relative error stays below ~1e-15 x^3, i.e. at rounding level up to x ~ 1e3 (where I is
+// already ~3e-13) and below 1e-12 up to x ~ 1e4.
+constexpr int kSeriesTerms = 32;
+struct SeriesWeights {
+  double w[kSeriesTerms];   // c_k / d times 4/(3 zeta(3)), signs included
+};
+constexpr SeriesWeights series_weights() {
+  SeriesWeights s{};
+  const int n = kSeriesTerms;
+  // d = ((3+sqrt 8)^n + (3-sqrt 8)^n) / 2 = u_n / 2 with u_0 = 2, u_1 = 6, u_n = 6u_{n-1} - u_{n-2}
+  double u0 = 2.0, u1 = 6.0;
+  for (int i = 1; i < n; ++i) {
+    const double u2 = 6.0 * u1 - u0;
+    u0 = u1;
+    u1 = u2;
+  }
+  const double d = 0.5 * u1;
+  double b = -1.0, c = -d;
+  for (int k = 0; k < n; ++k) {
+    c = b - c;
+    s.w[k] = c / d * (4.0 / (3.0 * 1.2020569031595942));
+    b = (k + n) * (k - n) * b / ((k + 0.5) * (k + 1.0));
+  }
+  return s;
+}
+
+__device__ __forceinline__ double i_series(double x) {
+  constexpr SeriesWeights W = series_weights();
+  const double x2 = x * x;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kSeriesTerms; ++k) {
+    const double n = k + 1.0;
+    const double r = 1.0 / (n * n + x2);
+    s += W.w[k] * n * r * r;
+  }
+  return s;
+}
+
+template <bool SERIES>
+__device__ __forceinline__ double i_kernel(double x) {
+  if constexpr (SERIES) return i_series(x);
+  else return i_fit(x);
+}
+
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -31,6 +81,26 @@ __device__ __forceinline__ double block_sum_d(double v, double* red) {
   double s = 0.0;
 #pragma unroll
   for (int w = 0; w < RT / 64; ++w) s += red[w];
+  return s;
+}
+
+// Two sums over the workgroup at once; every thread gets both.
+__device__ __forceinline__ double2 block_sum_d2(double2 v, double* red) {
+  v.x = wave_sum_d(v.x);
+  v.y = wave_sum_d(v.y);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    red[2 * wave] = v.x;
+    red[2 * wave + 1] = v.y;
+  }
+  __syncthreads();
+  double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int w = 0; w < RT / 64; ++w) {
+    s.x += red[2 * w];
+    s.y += red[2 * w + 1];
+  }
   return s;
 }
 
@@ -60,7 +130,13 @@ __device__ __forceinline__ double bin_mode_sum(const double* partial, int n_part
 // their mean weighted by m_s / M_nu; the source term is the common P_M^{1/2} history, so
 // the quadrature uses the weighted sum of the kernels. ic_pnu: [kMaxSpecies][nbins] initial
 // amplitudes of this box.
-template <int NSP>   // species evaluated: 1 (equal masses) or kMaxSpecies (a hierarchy)
+//
+// The sum is linear in the unknown current node A_n = (1 - f_nu) P_cdm^{1/2} + f_nu P_nu^{1/2}
+// (it enters only the last stored interval), so one pass gathers the part from the stored
+// nodes and the coefficient of A_n; each iteration of Appendix B is then a scalar update
+// and the kernel is evaluated once whatever the number of iterations.
+// red: 2 * RT / 64 doubles.
+template <int NSP, bool SERIES>   // species: 1 (equal masses) or kMaxSpecies; exact kernel
 __device__ __forceinline__ double exact_pnu_n(const RespBox& bx, double k, double pcdm_half,
                                               double pnu_prev, const double* ic_pnu,
                                               double ic_theta, const double* hpm, int nbins,
@@ -71,43 +147,49 @@ __device__ __forceinline__ double exact_pnu_n(const RespBox& bx, double k, doubl
 #pragma unroll
   for (int sp = 0; sp < NSP; ++sp)           // constant bound: the arrays stay in registers
     if (sp < bx.n_sp)
-      ic += bx.w_sp[sp] * i_fit(k * bx.tm_sp[sp] * bx.ds_ic) * ic_pnu[sp * nbins + b];
+      ic += bx.w_sp[sp] * i_kernel<SERIES>(k * bx.tm_sp[sp] * bx.ds_ic) * ic_pnu[sp * nbins + b];
   ic *= 1.0 - bx.ds_ic * bx.a_i * ic_theta;
+  double known = 0.0, coef = 0.0;
+  constexpr int U = 4;                       // sub-nodes per thread whose loads go out together
+  for (int q0 = 0; q0 < bx.nq; q0 += U * RT) {
+    double d[U], wq[U], a0[U], a1[U];
+    bool c0[U], c1[U];                       // the bracketing node is the current one
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + threadIdx.x + u * RT;
+      const int j = q / q_sub;
+      const bool in = q < bx.nq;
+      d[u] = in ? ds[q] : 0.0;
+      wq[u] = in ? w[q] : 0.0;
+      c0[u] = !(j < bx.n_cur);
+      c1[u] = !(j + 1 < bx.n_cur);
+      a0[u] = (in && !c0[u]) ? hpm[static_cast<size_t>(j) * nbins + b] : 0.0;
+      a1[u] = (in && !c1[u]) ? hpm[static_cast<size_t>(j + 1) * nbins + b] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + threadIdx.x + u * RT;
+      if (q >= bx.nq) continue;
+      const int j = q / q_sub, r = q - j * q_sub;
+      const double t = r * inv_q;
+      // amplitude = (1 - t) A_j + t A_{j+1}, with A_n split off
+      const double amp = (r != 0) ? (1.0 - t) * a0[u] + t * a1[u] : a0[u];
+      const double cur = (c0[u] ? (r != 0 ? 1.0 - t : 1.0) : 0.0) +
+                         ((r != 0 && c1[u]) ? t : 0.0);
+      double kern = 0.0;
+#pragma unroll
+      for (int sp = 0; sp < NSP; ++sp)
+        if (sp < bx.n_sp) kern += bx.w_sp[sp] * i_kernel<SERIES>(k * bx.tm_sp[sp] * d[u]);
+      const double g = wq[u] * kern * d[u];
+      known += g * amp;
+      coef += g * cur;
+    }
+  }
+  const double2 sums = block_sum_d2(make_double2(known, coef), red);
   double pnu_guess = pnu_prev, pnu = 0.0;
   for (int it = 0; it < iterations; ++it) {
     const double a_cur = (1.0 - bx.f_nu) * pcdm_half + bx.f_nu * pnu_guess;
-    double acc = 0.0;
-    constexpr int U = 4;                     // sub-nodes per thread whose loads go out together
-    for (int q0 = 0; q0 < bx.nq; q0 += U * RT) {
-      double d[U], wq[U], a0[U], a1[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int q = q0 + threadIdx.x + u * RT;
-        const int j = q / q_sub;
-        const bool in = q < bx.nq;
-        d[u] = in ? ds[q] : 0.0;
-        wq[u] = in ? w[q] : 0.0;
-        a0[u] = (in && j < bx.n_cur) ? hpm[static_cast<size_t>(j) * nbins + b] : a_cur;
-        a1[u] = (in && j + 1 < bx.n_cur) ? hpm[static_cast<size_t>(j + 1) * nbins + b] : a_cur;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int q = q0 + threadIdx.x + u * RT;
-        if (q >= bx.nq) continue;
-        const int j = q / q_sub, r = q - j * q_sub;
-        double amp = a0[u];
-        if (r != 0) {
-          const double t = r * inv_q;
-          amp = (1.0 - t) * a0[u] + t * a1[u];
-        }
-        double kern = 0.0;
-#pragma unroll
-        for (int sp = 0; sp < NSP; ++sp)
-          if (sp < bx.n_sp) kern += bx.w_sp[sp] * i_fit(k * bx.tm_sp[sp] * d[u]);
-        acc += wq[u] * kern * d[u] * amp;
-      }
-    }
-    pnu = ic + block_sum_d(acc, red);
+    pnu = ic + sums.x + sums.y * a_cur;
     pnu_guess = pnu;
   }
   return pnu;
@@ -119,11 +201,16 @@ __device__ __forceinline__ double exact_pnu(const RespBox& bx, double k, double 
                                             int b, const double* ds, const double* w,
                                             int q_sub, int iterations, double* red) {
   if (bx.n_sp <= 0) return 0.0;          // no massive neutrinos: the term drops out
-  if (bx.n_sp == 1)
-    return exact_pnu_n<1>(bx, k, pcdm_half, pnu_prev, ic_pnu, ic_theta, hpm, nbins, b, ds, w,
-                          q_sub, iterations, red);
-  return exact_pnu_n<kMaxSpecies>(bx, k, pcdm_half, pnu_prev, ic_pnu, ic_theta, hpm, nbins, b,
-                                  ds, w, q_sub, iterations, red);
+#define PMNU_EXACT_PNU(NSP, SERIES)                                                        \
+  exact_pnu_n<NSP, SERIES>(bx, k, pcdm_half, pnu_prev, ic_pnu, ic_theta, hpm, nbins, b, ds, \
+                           w, q_sub, iterations, red)
+  if (bx.series) {
+    if (bx.n_sp == 1) return PMNU_EXACT_PNU(1, true);
+    return PMNU_EXACT_PNU(kMaxSpecies, true);
+  }
+  if (bx.n_sp == 1) return PMNU_EXACT_PNU(1, false);
+  return PMNU_EXACT_PNU(kMaxSpecies, false);
+#undef PMNU_EXACT_PNU
 }
 
 }  // namespace pmnu

@@ -13,9 +13,11 @@
 //      and the previous iteration's P_nu^{1/2} after that;
 //   3. writes P_nu^{1/2}, R = P_nu^{1/2}/P_cdm^{1/2}, and the new history row.
 // Lanes stride over the sub-nodes; sums are reduced across the wave and the workgroup
-// in FP64 in a fixed order.
+// in FP64 in a fixed order. The sum is gathered as a part from the stored nodes plus a
+// coefficient of the current node, so iterations do not evaluate the kernel again.
 //
-// I(x) is the rational fit of the paper's Appendix C, eq. (fit).
+// I(x) is the rational fit of the paper's Appendix C, eq. (fit), or (per box) the exact
+// alternating series of the same appendix, accelerated.
 //
 // rtable_kernel: T(n^2) = (1 - f_nu) + f_nu R(|k|) for every integer n^2 in [0, 3N^2/4]
 // with R linear in ln k between the means of the non-empty bins, held at the end values.
@@ -32,7 +34,7 @@ __global__ __launch_bounds__(RT) void response_kernel(
     const double* __restrict__ tg_ds, const double* __restrict__ tg_w, int nbins, int jcap,
     int qcap, int q_sub, int iterations, double norm, double* __restrict__ pcdm_out,
     double* __restrict__ pnu_out, double* __restrict__ ratio_out) {
-  __shared__ double red[RT / 64];
+  __shared__ double red[2 * RT / 64];
   const int b = blockIdx.x, box = blockIdx.y;
   const RespBox bx = boxes[box];
   const size_t ob = static_cast<size_t>(box) * nbins + b;
@@ -126,7 +128,25 @@ __global__ __launch_bounds__(256) void rtable_kernel(const double* __restrict__ 
   rtable[static_cast<size_t>(box) * (n2max + 1) + n2] = static_cast<float>((1.0 - f) + f * r);
 }
 
+// I(x) at n points, the fit or the exact series (a diagnostic of the device kernels).
+__global__ __launch_bounds__(256) void kernel_values_kernel(const double* __restrict__ x,
+                                                            int64_t n, int series,
+                                                            double* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = series ? i_series(x[i]) : i_fit(x[i]);
+}
+
 }  // namespace
+
+hipError_t launch_kernel_values(const double* x, int64_t n, int series, double* out,
+                                hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(kernel_values_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                     s, x, n, series, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_response(const RespBox* boxes, const double* partial, int n_partial,
                            const double* counts, const double* kmean, const double* hist_pm,

@@ -408,3 +408,84 @@ def test_background_rejects_bad_flag():
     assert binding.ERRORS[binding.load_library().pm_nu_set_background(ctx.h, 2)] == "EINVAL"
     assert b"relativistic" in binding.load_library().pm_nu_last_error()
     ctx.close()
+
+
+def test_kernel_values_match_oracle():
+    """I(x) on the device against the oracle: the fit (same formula, FP64) and the exact
+    series of Appendix C (accelerated on the device, Euler-transformed in the oracle)."""
+    import torch
+    from oracle import kernel
+    from paper_1209_0461_amd import binding
+    x = np.concatenate([np.linspace(0.0, 5.0, 2001), np.geomspace(5.0, 1e4, 3000)])
+    xd = torch.from_numpy(x).cuda()
+    out = torch.empty_like(xd)
+    binding.pm_nu_kernel_values(xd, out, series=False)
+    torch.cuda.synchronize()
+    fit = out.cpu().numpy()
+    assert np.abs(fit / kernel.I_fit(x) - 1).max() <= 1e-13
+    binding.pm_nu_kernel_values(xd, out, series=True)
+    torch.cuda.synchronize()
+    ser = out.cpu().numpy()
+    ref = kernel.I_series(x)
+    small = x <= 1e3
+    assert np.abs(ser[small] / ref[small] - 1).max() <= 1e-11
+    assert np.abs(ser[~small] / ref[~small] - 1).max() <= 1e-8   # the oracle's own rounding
+    assert ser[0] == pytest.approx(1.0, rel=1e-15)
+    empty = torch.empty(0, dtype=torch.float64, device="cuda")
+    binding.pm_nu_kernel_values(empty, empty, series=True)      # n = 0 is a no-op
+
+
+@pytest.mark.parametrize("iters,masses,relativistic",
+                         [(1, None, False), (3, None, False),
+                          (2, "hierarchy_normal_eV", True)])
+def test_exact_kernel_matches_oracle(iters, masses, relativistic):
+    """The exact I(x) of Appendix C in eq. (P-final), with 1-3 iterations of Appendix B, and
+    combined with a hierarchy and the relativistic background."""
+    import json
+    import os
+    import torch
+    import oracle.response as ores
+    import oracle.step as ostep
+    from paper_1209_0461_amd import PMNu, binding
+    from synth import log_spaced_nodes, synthetic_history
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+    sp_m = None if masses is None else np.array(gold[masses]["value"])
+    M = 0.3 if sp_m is None else float(sp_m.sum())
+    nm, box, nb, J, a_now = 32, 128.0, 16, 16, 0.5
+    pos = make_inputs(32, box, 0.2, 61)
+    sp = ostep.spectrum(pos, nm, box, nb)
+    nodes = log_spaced_nodes(0.01, a_now, J)
+    hist = synthetic_history(sp["k_mean"], np.sqrt(sp["p_cdm"]), nodes, M)
+    args = (sp["k_mean"], sp["counts"], np.sqrt(sp["p_cdm"]), hist["a"], hist["pm_half"],
+            hist["pnu_half"][-1], hist["pnu_half_init"], hist["theta_over_delta_init"], a_now,
+            M, 0.3, 0.7, 8)
+    kw = dict(iterations=iters, species=sp_m, relativistic=relativistic)
+    r = ores.nu_amplitude(*args, kernel="series", **kw)
+    fit = ores.nu_amplitude(*args, **kw)
+    forces = ostep.forces(pos, sp["delta_k"], nm, box, sp["k_mean"], sp["counts"], r["ratio"],
+                          r["f_nu"], a_now, 0.3, True)
+    ctx = PMNu(nm, len(pos), box, nb, J + 2, [M], iterations=iters)
+    ctx.set_history(0, hist)
+    if sp_m is not None:
+        binding.pm_nu_set_species(ctx.h, 0, sp_m)
+    binding.pm_nu_set_background(ctx.h, relativistic)
+    binding.pm_nu_set_kernel(ctx.h, 1)
+    p = torch.from_numpy(pos).cuda()
+    acc = torch.zeros_like(p)
+    ctx.step(p, acc, a_now)
+    torch.cuda.synchronize()
+    ok = sp["counts"] > 0
+    got = ctx.spectrum(0)
+    err = np.abs(got["pnu_half"][ok] / r["pnu_half"][ok] - 1).max()
+    print(f"  exact kernel, iterations {iters}: P_nu max rel {err:.2e}", flush=True)
+    assert err <= TOL_NU
+    assert np.abs(got["pnu_half"][ok] / fit["pnu_half"][ok] - 1).max() > 100 * TOL_NU
+    assert rms_rel(acc.cpu().numpy(), forces) <= TOL_FORCE_RMS
+    ctx.close()
+
+
+def test_kernel_flag_is_checked():
+    from paper_1209_0461_amd import PMNu, binding
+    ctx = PMNu(16, 8, 64.0, 8, 4, [0.1])
+    assert binding.ERRORS[binding.load_library().pm_nu_set_kernel(ctx.h, 5)] == "EINVAL"
+    ctx.close()
