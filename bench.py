@@ -171,6 +171,43 @@ def measure_surrogate(ctx, binding, pos, acc, a_now, steps, stream, timing_exact
             "bar": 1e-3}
 
 
+def measure_variants(ctx, binding, pos, acc, a_now, stream, names, steps=20):
+    """Appendix C (the exact I(x) in place of the fit) and Appendix B (more iterations of
+    the implicit current node): the response kernel's time and the change each makes to
+    P_nu^{1/2} and to the force, against the default step (fit, one iteration)."""
+    import torch
+
+    def run(series, iterations):
+        binding.pm_nu_set_kernel(ctx.h, series)
+        binding.pm_nu_set_iterations(ctx.h, iterations)
+        for _ in range(3):
+            ctx.step(pos, acc, a_now)
+        stream.synchronize()
+        binding.pm_nu_read_timing(ctx.h)
+        binding.pm_nu_set_timing_mask(ctx.h, 1 << names.index("nu_response"))
+        for _ in range(steps):
+            ctx.step(pos, acc, a_now)
+        stream.synchronize()
+        t = binding.pm_nu_read_timing(ctx.h)
+        binding.pm_nu_set_timing(ctx.h, False)
+        pn = np.concatenate([ctx.spectrum(b)["pnu_half"] for b in range(ctx.n_boxes)])
+        return t["nu_response"][0] / max(1, t["nu_response"][1]), pn, acc.clone()
+
+    base_ms, base_pn, base_acc = run(0, 1)
+    ok = base_pn != 0
+    out = {"fit_1_iteration": {"response_ms": base_ms}}
+    for name, series, iterations in (("exact_kernel", 1, 1), ("fit_2_iterations", 0, 2),
+                                     ("exact_kernel_2_iterations", 1, 2)):
+        ms, pn, a = run(series, iterations)
+        out[name] = {"response_ms": ms,
+                     "pnu_half_max_rel_change": float(np.abs(pn[ok] / base_pn[ok] - 1).max()),
+                     "force_rms_rel_change": float(torch.sqrt(((a - base_acc) ** 2).sum()
+                                                              / (base_acc ** 2).sum()))}
+    binding.pm_nu_set_kernel(ctx.h, 0)
+    binding.pm_nu_set_iterations(ctx.h, 1)
+    return out
+
+
 def cpu_baseline(cfg, pos, masses, hists):
     """Time the FP64 oracle on one full step of box 0 (single-threaded NumPy)."""
     import oracle.step as ostep
@@ -199,6 +236,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate-versus-integral measurement")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the exact-kernel and second-iteration measurement")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -288,6 +327,9 @@ def main():
         if os.path.exists(SURROGATE_BLOB) and not args.no_surrogate and not args.graph:
             surrogate = measure_surrogate(ctx, binding, pos, acc, a_now, args.steps, stream,
                                           timing, names)
+        variants = None
+        if not args.no_variants:
+            variants = measure_variants(ctx, binding, pos, acc, a_now, stream, names)
 
     from paper_1209_0461_amd.binding import load_library  # noqa: F401
     n_partial = (n_mesh // min(16 if n_mesh <= 256 else 8, n_mesh)) * (n_mesh // 2 + 1)
@@ -335,6 +377,8 @@ def main():
                               f"{min(args.steps, 10)} eager steps before the timed region")
     if surrogate is not None:
         out["surrogate"] = surrogate
+    if variants is not None:
+        out["variants"] = variants
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, pos_np, masses, hists)
     ctx.close()

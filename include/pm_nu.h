@@ -161,7 +161,10 @@ int pm_nu_read_timing(pm_nu_ctx* ctx, int* n_stages, const char** names, double*
 /* ---- HIP graph of a whole step (for batched small boxes and launch-bound loops) ------ */
 /* Capture deposit + response + force at a_now for the given pointers into a graph
  * (sync). The time grid for a_now is prepared before capture. Replays recompute the
- * node a_now each time. */
+ * node a_now each time. Any later call that changes what a step computes (set_history,
+ * set_mass, set_species, set_background, set_kernel, set_iterations, set_response_mode,
+ * set_power, set_launch, autotune, surrogate load/init/train) discards the graph; launch
+ * then fails with PM_NU_ESTATE until the step is captured again. */
 int pm_nu_graph_capture(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now);
 /* Launch the captured graph on the stream. */
 int pm_nu_graph_launch(pm_nu_ctx* ctx);
@@ -237,6 +240,12 @@ int pm_nu_set_kernel(pm_nu_ctx* ctx, int series);
  * kernels; needs no context. Errors: PM_NU_EINVAL for n < 0, a NULL array with n > 0 or a
  * bad flag; PM_NU_EHIP if the launch fails. */
 int pm_nu_kernel_values(const double* x, int64_t n, int series, double* out, void* stream);
+
+/* Iterations of the implicit equation for the current node (Sec. 4.3 (iii), Appendix B),
+ * as pm_nu_config.iterations, from the next response. The quadrature is gathered once as
+ * a stored-node part plus a coefficient of the current node, so each further iteration is a
+ * scalar update. Sync. Errors: PM_NU_EINVAL outside [1, 16]. */
+int pm_nu_set_iterations(pm_nu_ctx* ctx, int iterations);
 
 /* ---- binned power from elsewhere ------------------------------------------------------- */
 /* Set P_cdm(k_b) of one box (host) [B] in place of a deposit, for a response computed

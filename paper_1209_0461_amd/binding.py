@@ -61,6 +61,7 @@ SIGNATURES = {
     "pm_nu_set_species": (_INT, [_P, _INT, _INT, _D, _D]),
     "pm_nu_set_background": (_INT, [_P, _INT]),
     "pm_nu_set_kernel": (_INT, [_P, _INT]),
+    "pm_nu_set_iterations": (_INT, [_P, _INT]),
     "pm_nu_kernel_values": (_INT, [_P, ctypes.c_int64, _INT, _P, _P]),
     "pm_nu_set_timing_mask": (_INT, [_P, ctypes.c_uint32]),
     "pm_nu_read_timing": (_INT, [_P, ctypes.POINTER(_INT), ctypes.POINTER(ctypes.c_char_p), _D, _I64]),
@@ -253,6 +254,11 @@ def pm_nu_set_background(h, relativistic):
 def pm_nu_set_kernel(h, series):
     """I(x) in the history integral: 0 the fit eq. (fit), 1 the exact series (Appendix C)."""
     _check(load_library().pm_nu_set_kernel(h, 1 if series else 0))
+
+
+def pm_nu_set_iterations(h, iterations):
+    """Iterations of the implicit current node (Appendix B), 1..16."""
+    _check(load_library().pm_nu_set_iterations(h, int(iterations)))
 
 
 def pm_nu_kernel_values(x, out, series, stream=None):

@@ -88,6 +88,7 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
   Ctx* c = reinterpret_cast<Ctx*>(ctx);
   if (!c) return set_error(PM_NU_EINVAL, "ctx is NULL");
   if (!pos || !acc) return set_error(PM_NU_EINVAL, "pos/acc is NULL");
+  drop_graph(*c);   // the launch shapes may change
   const std::string key = cache_key(*c);
   if (cache_path && read_cache(cache_path, key, c->tune)) return PM_NU_OK;
   const bool was_timing = c->timer.enabled;
@@ -166,6 +167,7 @@ int pm_nu_set_launch(pm_nu_ctx* ctx, int deposit_mode, int deposit_block, int in
                      int interp_block) {
   Ctx* c = reinterpret_cast<Ctx*>(ctx);
   if (!c) return set_error(PM_NU_EINVAL, "ctx is NULL");
+  drop_graph(*c);   // a captured step keeps its launch shapes
   auto block_ok = [](int b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
   if (deposit_mode < 0 || deposit_mode > 6 || interp_mode < 0 || interp_mode > 3 ||
       !block_ok(deposit_block) || !block_ok(interp_block))

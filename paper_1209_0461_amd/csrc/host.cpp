@@ -62,6 +62,13 @@ void timer_end(Ctx& c) {
   ++t.used;
 }
 
+void drop_graph(Ctx& c) {
+  if (c.graph_exec) hipGraphExecDestroy(c.graph_exec);
+  if (c.graph) hipGraphDestroy(c.graph);
+  c.graph_exec = nullptr;
+  c.graph = nullptr;
+}
+
 namespace {
 
 // k_fs(a) = sqrt(3/2 Omega_M(a) <v^-2>) a H, <v^-2> = 2 ln2/(3 zeta(3)) (m a / T_nu0)^2
@@ -568,6 +575,7 @@ int pm_nu_set_history(pm_nu_ctx* ctx, int box, int n_nodes, const double* a,
                       const double* pm_half, const double* pnu_half,
                       const double* pnu_half_init, const double* theta_over_delta_init) {
   GET_CTX(ctx);
+  drop_graph(*c);   // a captured step would not see the change
   if (box < 0 || box >= c->nbox) return set_error(PM_NU_EINVAL, "box %d out of range", box);
   if (n_nodes < 1 || n_nodes >= c->Jcap)
     return set_error(PM_NU_EHISTORY, "n_nodes must be in [1, max_history-1] (got %d)", n_nodes);
@@ -626,6 +634,7 @@ int pm_nu_response(pm_nu_ctx* ctx, double a_now) {
 
 int pm_nu_set_response_mode(pm_nu_ctx* ctx, int mode) {
   GET_CTX(ctx);
+  drop_graph(*c);   // a captured step would not see the change
   if (mode < 0 || mode > 2) return set_error(PM_NU_EINVAL, "response_mode must be 0, 1 or 2");
   c->cfg.response_mode = mode;
   return PM_NU_OK;
@@ -633,6 +642,7 @@ int pm_nu_set_response_mode(pm_nu_ctx* ctx, int mode) {
 
 int pm_nu_set_mass(pm_nu_ctx* ctx, int box, double m_nu_total) {
   GET_CTX(ctx);
+  drop_graph(*c);   // a captured step would not see the change
   if (box < 0 || box >= c->nbox) return set_error(PM_NU_EINVAL, "box %d out of range", box);
   if (!(m_nu_total >= 0.0) || !std::isfinite(m_nu_total))
     return set_error(PM_NU_EINVAL, "m_nu_total must be >= 0");
@@ -652,6 +662,7 @@ int pm_nu_set_mass(pm_nu_ctx* ctx, int box, double m_nu_total) {
 int pm_nu_set_species(pm_nu_ctx* ctx, int box, int n_species, const double* m_species,
                       const double* pnu_half_init) {
   GET_CTX(ctx);
+  drop_graph(*c);   // a captured step would not see the change
   if (box < 0 || box >= c->nbox) return set_error(PM_NU_EINVAL, "box %d out of range", box);
   if (n_species < 1 || n_species > kMaxSpecies || !m_species)
     return set_error(PM_NU_EINVAL, "n_species must be in [1, %d] with masses given",
@@ -696,6 +707,7 @@ int pm_nu_set_species(pm_nu_ctx* ctx, int box, int n_species, const double* m_sp
 
 int pm_nu_set_background(pm_nu_ctx* ctx, int relativistic) {
   GET_CTX(ctx);
+  drop_graph(*c);   // a captured step would not see the change
   if (relativistic != 0 && relativistic != 1)
     return set_error(PM_NU_EINVAL, "relativistic must be 0 or 1 (got %d)", relativistic);
   c->relativistic = relativistic == 1;
@@ -705,10 +717,20 @@ int pm_nu_set_background(pm_nu_ctx* ctx, int relativistic) {
 
 int pm_nu_set_kernel(pm_nu_ctx* ctx, int series) {
   GET_CTX(ctx);
+  drop_graph(*c);   // a captured step would not see the change
   if (series != 0 && series != 1)
     return set_error(PM_NU_EINVAL, "series must be 0 or 1 (got %d)", series);
   c->series = series == 1;
   c->tg_a_now = -1.0;   // the per-box constants of the response are rebuilt
+  return PM_NU_OK;
+}
+
+int pm_nu_set_iterations(pm_nu_ctx* ctx, int iterations) {
+  GET_CTX(ctx);
+  drop_graph(*c);   // a captured step would not see the change
+  if (iterations < 1 || iterations > 16)
+    return set_error(PM_NU_EINVAL, "iterations must be in [1, 16] (got %d)", iterations);
+  c->cfg.iterations = iterations;
   return PM_NU_OK;
 }
 
@@ -724,6 +746,7 @@ int pm_nu_kernel_values(const double* x, int64_t n, int series, double* out, voi
 
 int pm_nu_set_power(pm_nu_ctx* ctx, int box, const double* p_cdm) {
   GET_CTX(ctx);
+  drop_graph(*c);   // a captured step would not see the change
   if (box < 0 || box >= c->nbox || !p_cdm) return set_error(PM_NU_EINVAL, "bad box/p_cdm");
   // The response sums the per-workgroup partial mode sums of each bin ([bin][workgroup]):
   // put the whole sum w |delta_k|^2 = P C_b N^6 / L^3 in the first partial, zero the rest.
@@ -902,7 +925,9 @@ int pm_nu_graph_capture(pm_nu_ctx* ctx, const float* pos, float* acc, double a_n
 
 int pm_nu_graph_launch(pm_nu_ctx* ctx) {
   GET_CTX(ctx);
-  if (!c->graph_exec) return set_error(PM_NU_ESTATE, "no captured graph");
+  if (!c->graph_exec)
+    return set_error(PM_NU_ESTATE,
+                     "no captured graph (none captured, or a setting changed since capture)");
   PMNU_HIP(hipGraphLaunch(c->graph_exec, c->stream));
   return PM_NU_OK;
 }

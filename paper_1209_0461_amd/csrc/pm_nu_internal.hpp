@@ -156,6 +156,8 @@ int set_error(int code, const char* fmt, ...);
 // Event-bracketed launch helpers (host.cpp)
 void timer_begin(Ctx& c, int stage);
 void timer_end(Ctx& c);
+// Discard a captured step graph (after any change that the captured launches would miss).
+void drop_graph(Ctx& c);
 // Response at a_now with the exact integral (mode 0) or the surrogate (modes 1, 2).
 int do_response_mode(Ctx& c, double a_now, int mode);
 // surrogate.cpp: the kernel launch of the surrogate response (modes 1, 2)

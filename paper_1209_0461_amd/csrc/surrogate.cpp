@@ -127,6 +127,7 @@ int64_t pm_nu_surrogate_blob_floats(void) { return kSurBlob; }
 int pm_nu_surrogate_load(pm_nu_ctx* ctx, const float* blob, int64_t n_floats) {
   Ctx* c = reinterpret_cast<Ctx*>(ctx);
   if (!c || !blob) return set_error(PM_NU_EINVAL, "ctx/blob is NULL");
+  drop_graph(*c);   // new weights
   if (n_floats != kSurBlob)
     return set_error(PM_NU_EINVAL, "blob must hold %d floats (got %lld)", kSurBlob,
                      static_cast<long long>(n_floats));
@@ -157,6 +158,7 @@ int pm_nu_surrogate_init(pm_nu_ctx* ctx, const float* x, const float* y, int64_t
                          uint64_t seed) {
   Ctx* c = reinterpret_cast<Ctx*>(ctx);
   if (!c || !x || !y || n < 2) return set_error(PM_NU_EINVAL, "bad arguments");
+  drop_graph(*c);   // new weights
   int rc = ensure(*c);
   if (rc) return rc;
   PMNU_HIP(hipStreamSynchronize(c->stream));
@@ -216,6 +218,7 @@ int pm_nu_surrogate_train(pm_nu_ctx* ctx, const float* x, const float* y, int64_
   Ctx* c = reinterpret_cast<Ctx*>(ctx);
   int rc = need_loaded(c);
   if (rc) return rc;
+  drop_graph(*c);   // new weights
   if (!x || !y || n < 1 || epochs < 1 || batch < 32 || batch % 32 || !(lr > 0.f))
     return set_error(PM_NU_EINVAL, "bad training arguments");
   if (n > (1ll << 31) - 1) return set_error(PM_NU_EINVAL, "too many rows");

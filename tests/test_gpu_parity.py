@@ -191,6 +191,17 @@ def test_graph_replay_matches_eager():
             # eager work between replays
             ctx.step(p, acc, 0.5)
             stream.synchronize()
+        # a setting changed after capture discards the graph; a new capture follows it
+        pnu_fit = ctx.spectrum(0)["pnu_half"]
+        binding.pm_nu_set_kernel(ctx.h, 1)
+        with pytest.raises(binding.PMNuError, match="setting changed"):
+            binding.pm_nu_graph_launch(ctx.h)
+        binding.pm_nu_graph_capture(ctx.h, p, acc, 0.5)
+        binding.pm_nu_graph_launch(ctx.h)
+        stream.synchronize()
+        ok = ref["counts"] > 0
+        pnu_ser = ctx.spectrum(0)["pnu_half"]
+        assert np.abs(pnu_ser[ok] / pnu_fit[ok] - 1).max() > 1e-4
     ctx.close()
 
 
