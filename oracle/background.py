@@ -111,6 +111,16 @@ def _ds_da(a, omega_m, background):
     return 1.0 / (a ** 3 * float(hubble_rate(a, omega_m, background)))
 
 
+def kick_interval(a1, a2, omega_m, background=None):
+    """int_{a1}^{a2} da / (a^2 H(a)) [Mpc/h]: with ds = da/(a^3 H) and d^2x/ds^2 = a^2 g,
+    g = -grad phi ~ 1/a, a kick holding a g fixed changes dx/ds by (a g) times this."""
+    if a1 == a2:
+        return 0.0
+    val, _ = integrate.quad(lambda a: 1.0 / (a * a * float(hubble_rate(a, omega_m, background))),
+                            a1, a2, epsabs=0.0, epsrel=1e-13, limit=200)
+    return val
+
+
 def superconformal_interval(a1, a2, omega_m, background=None):
     """s(a2) - s(a1) = int_{a1}^{a2} da / (a^3 H(a))  [Mpc/h], Sec. 3.2."""
     if a1 == a2:

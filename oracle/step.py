@@ -1,4 +1,5 @@
-"""One PM + linear-response-neutrino step in the order of Sec. 4.3 (ii)-(iv), FP64.
+"""One PM + linear-response-neutrino step in the order of Sec. 4.3 (ii)-(iv), and the loop
+that repeats it, FP64.
 
   (ii)  CDM density by cloud-in-cell, its Fourier transform and binned power spectrum
   (iii) P_nu^{1/2} from eq. (P-final) over the stored history (one iteration by default)
@@ -8,6 +9,7 @@
 """
 import numpy as np
 
+from . import background as bgmod
 from . import pm, response
 
 
@@ -62,3 +64,41 @@ def full_step(pos, n_mesh, box, n_bins, history, a_now, m_nu_total, omega_m=0.3,
     sp.update(r)
     sp["acc"] = acc
     return sp
+
+
+def advance(pos, vel, acc, history, a_steps, n_mesh, box, n_bins, m_nu_total, omega_m=0.3,
+            hubble=0.7, substeps=8, iterations=1, deconvolve=True, n_species=3, species=None,
+            relativistic=False, kernel="fit"):
+    """Repeat steps (ii)-(iv) of Sec. 4.3 along a_steps with kick-drift-kick leapfrog steps in
+    the superconformal time s (ds = dt/a^2, Sec. 3.2), in which comoving positions obey
+    d^2x/ds^2 = a^2 g with g the force of full_step (g = -grad phi, phi ~ 1/a).
+
+    Reading (the paper's N-body code is Gadget-3, whose integrator it does not restate):
+    within one step a0 -> a1, with a_m = sqrt(a0 a1), a g is held at its value at the
+    start (end) of each half: u += a0 g(a0) int_{a0}^{a_m} da/(a^2 H); x += u (s(a1) - s(a0));
+    g(a1) from full_step at a1, which also stores the node a1; u += a1 g(a1) int_{a_m}^{a1}
+    da/(a^2 H). Positions wrap into [0, box).
+
+    pos, vel, acc (N, 3): positions, u = dx/ds and the force at a_steps[0]. Returns the
+    positions, velocities and force at a_steps[-1] (FP64) and the extended history.
+    """
+    masses = (np.asarray(species, dtype=np.float64) if species is not None
+              else np.full(n_species, m_nu_total / n_species))
+    bg = bgmod.Background(omega_m, hubble, masses) if relativistic else None
+    x = np.asarray(pos, dtype=np.float64).copy()
+    u = np.asarray(vel, dtype=np.float64).copy()
+    g = np.asarray(acc, dtype=np.float64).copy()
+    hist = {k: np.array(v, dtype=np.float64, copy=True) for k, v in history.items()}
+    for a0, a1 in zip(a_steps[:-1], a_steps[1:]):
+        am = np.sqrt(a0 * a1)
+        u += a0 * bgmod.kick_interval(a0, am, omega_m, bg) * g
+        x = np.mod(x + bgmod.superconformal_interval(a0, a1, omega_m, bg) * u, box)
+        r = full_step(x, n_mesh, box, n_bins, hist, a1, m_nu_total, omega_m, hubble, substeps,
+                      iterations, deconvolve, n_species, species=species,
+                      relativistic=relativistic, kernel=kernel)
+        g = r["acc"]
+        u += a1 * bgmod.kick_interval(am, a1, omega_m, bg) * g
+        hist["a"] = np.append(hist["a"], a1)
+        hist["pm_half"] = np.vstack([hist["pm_half"], r["pm_half_now"][None, :]])
+        hist["pnu_half"] = np.vstack([hist["pnu_half"], r["pnu_half"][None, :]])
+    return x, u, g, hist

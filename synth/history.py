@@ -33,6 +33,11 @@ def _e(a, om):
     return np.sqrt(om / a ** 3 + 1.0 - om)
 
 
+def hubble_rate(a, om):
+    """H(a) [h/Mpc] of a flat matter + Lambda background (input recipes only)."""
+    return _H0 * _e(a, om)
+
+
 def _growth_integral(a, om):
     val, _ = integrate.quad(lambda x: 1.0 / (x * _e(x, om)) ** 3, 0.0, a,
                             epsabs=0.0, epsrel=1e-12, limit=200)

@@ -57,8 +57,10 @@ def morton_codes(n_side):
             | spread[None, None, :]).reshape(-1)
 
 
-def zeldovich_lattice(n_side, box, sigma_cells, seed, spectral_index=-2.0, order="morton"):
-    """Return FP32 positions, shape (n_side**3, 3), in [0, box)."""
+def zeldovich_lattice(n_side, box, sigma_cells, seed, spectral_index=-2.0, order="morton",
+                      return_displacement=False):
+    """Return FP32 positions, shape (n_side**3, 3), in [0, box); with return_displacement
+    also the FP64 displacement of every particle (same order)."""
     n = int(n_side)
     if n < 2 or n & (n - 1):
         raise ValueError("n_side must be a power of two >= 2")
@@ -89,6 +91,7 @@ def zeldovich_lattice(n_side, box, sigma_cells, seed, spectral_index=-2.0, order
     del dk
     rms = np.sqrt(np.mean(np.sum(psi * psi, axis=-1)))
     psi *= (sigma_cells * spacing) / rms
+    disp = psi.reshape(-1, 3).copy() if return_displacement else None
     grid = (np.arange(n, dtype=np.float64) + 0.5) * spacing
     psi[..., 0] += grid[:, None, None]
     psi[..., 1] += grid[None, :, None]
@@ -97,12 +100,36 @@ def zeldovich_lattice(n_side, box, sigma_cells, seed, spectral_index=-2.0, order
     pos[pos >= np.float32(box)] = np.float32(0.0)  # an FP32 round-up to L wraps to 0
     pos[pos < 0] = np.float32(0.0)
     if order == "morton":
+        codes = morton_codes(n).astype(np.int64)
         out = np.empty_like(pos)
-        out[morton_codes(n).astype(np.int64)] = pos
+        out[codes] = pos
         pos = out
+        if disp is not None:
+            d = np.empty_like(disp)
+            d[codes] = disp
+            disp = d
     elif order != "c":
         raise ValueError("order must be 'morton' or 'c'")
+    if return_displacement:
+        return np.ascontiguousarray(pos), disp
     return np.ascontiguousarray(pos)
+
+
+def zeldovich_ics(n_side, box, sigma_cells, seed, a, omega_m=0.3, spectral_index=-2.0,
+                  order="morton"):
+    """Positions and growing-mode velocities at scale factor a, both FP32 (n_side**3, 3).
+
+    The lattice is displaced by psi (RMS sigma_cells cells); in the Zel'dovich growing mode
+    x = q + (D/D(a)) psi, so the velocity in superconformal time s (ds = dt/a^2) is
+    u = dx/ds = a^2 dx/dt = a^2 H(a) f(a) psi, with H and f = dln D/dln a of a flat
+    matter + Lambda background.
+    """
+    from .history import growth, hubble_rate
+    pos, disp = zeldovich_lattice(n_side, box, sigma_cells, seed, spectral_index, order,
+                                  return_displacement=True)
+    _, f = growth(np.array([a]), omega_m)
+    vel = (a * a * hubble_rate(a, omega_m) * f[0]) * disp
+    return pos, np.ascontiguousarray(vel.astype(np.float32))
 
 
 def batched_lattices(cfg, order="morton"):
