@@ -166,8 +166,30 @@ int pm_nu_read_timing(pm_nu_ctx* ctx, int* n_stages, const char** names, double*
  * set_power, set_launch, autotune, surrogate load/init/train) discards the graph; launch
  * then fails with PM_NU_ESTATE until the step is captured again. */
 int pm_nu_graph_capture(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now);
-/* Launch the captured graph on the stream. */
+/* Launch the captured graph on the stream. An eager response at another a_now (which moves
+ * the history on) also discards the graph. */
 int pm_nu_graph_launch(pm_nu_ctx* ctx);
+
+/* ---- time stepping: the loop of Sec. 4.3 (ii)-(iv) ------------------------------------ */
+/* Advance the particles from a_steps[0] to a_steps[n_steps] by n_steps kick-drift-kick
+ * leapfrog steps in the superconformal time s (ds = dt/a^2, Sec. 3.2), in which comoving
+ * positions obey d^2x/ds^2 = a^2 acc, acc being the force of pm_nu_step (so a acc is what
+ * stays constant in the linear matter era). One step a0 -> a1, a_m = sqrt(a0 a1):
+ *   u += a0 acc(a0) int_{a0}^{a_m} da/(a^2 H);   x += u int_{a0}^{a1} da/(a^3 H), wrapped;
+ *   acc(a1) from deposit -> response -> force at a1 (the response stores the node a1);
+ *   u += a1 acc(a1) int_{a_m}^{a1} da/(a^2 H).
+ * The two half kicks that meet between steps are applied as one. H(a) is the background of
+ * pm_nu_set_background.
+ *   pos (dev) [n_boxes][N_p][3] in [0, L); vel (dev) same layout, u = dx/ds = a^2 dx/dt
+ *   [dimensionless with c = 1]; acc (dev): on entry the force at a_steps[0] for these
+ *   positions (pm_nu_step at a_steps[0]), on exit the force at a_steps[n_steps]. All three
+ *   16-byte aligned; updated in place.
+ *   a_steps (host) [n_steps + 1], increasing, a_steps[1] after the last stored node.
+ * Velocities leave synchronised with positions at a_steps[n_steps]. Sync per step (the time
+ * grid of each new a is built on the host). Errors: PM_NU_EINVAL for bad arguments,
+ * PM_NU_EHISTORY if the history lacks room for n_steps nodes, then those of the step. */
+int pm_nu_advance(pm_nu_ctx* ctx, float* pos, float* vel, float* acc, const double* a_steps,
+                  int n_steps);
 
 /* ---- launch-shape autotuning ----------------------------------------------------------- */
 /* Time the candidate launch shapes of the tunable kernels on this context's buffers with

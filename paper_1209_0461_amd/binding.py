@@ -62,6 +62,7 @@ SIGNATURES = {
     "pm_nu_set_background": (_INT, [_P, _INT]),
     "pm_nu_set_kernel": (_INT, [_P, _INT]),
     "pm_nu_set_iterations": (_INT, [_P, _INT]),
+    "pm_nu_advance": (_INT, [_P, _P, _P, _P, _D, _INT]),
     "pm_nu_kernel_values": (_INT, [_P, ctypes.c_int64, _INT, _P, _P]),
     "pm_nu_set_timing_mask": (_INT, [_P, ctypes.c_uint32]),
     "pm_nu_read_timing": (_INT, [_P, ctypes.POINTER(_INT), ctypes.POINTER(ctypes.c_char_p), _D, _I64]),
@@ -261,6 +262,14 @@ def pm_nu_set_iterations(h, iterations):
     _check(load_library().pm_nu_set_iterations(h, int(iterations)))
 
 
+def pm_nu_advance(h, pos, vel, acc, a_steps):
+    """Kick-drift-kick steps through a_steps (host sequence, len n_steps + 1); pos, vel, acc
+    are device tensors updated in place (acc must hold the force at a_steps[0])."""
+    a = np.ascontiguousarray(a_steps, dtype=np.float64)
+    _check(load_library().pm_nu_advance(h, _dev(pos), _dev(vel), _dev(acc), _dptr(a),
+                                        len(a) - 1))
+
+
 def pm_nu_kernel_values(x, out, series, stream=None):
     """I(x) on the device: x and out are float64 device tensors of the same length."""
     import torch
@@ -422,6 +431,12 @@ class PMNu:
 
     def history(self, box):
         return pm_nu_get_history(self.h, box, self.cfg.max_history, self.cfg.n_kbins)
+
+    def advance(self, pos, vel, acc, a_steps):
+        """Kick-drift-kick steps through a_steps; acc must hold the force at a_steps[0]."""
+        for t, name in ((pos, "pos"), (vel, "vel"), (acc, "acc")):
+            self._check_particles(t, name)
+        pm_nu_advance(self.h, pos, vel, acc, a_steps)
 
     def _check_particles(self, t, name):
         import torch

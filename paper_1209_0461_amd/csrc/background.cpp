@@ -167,4 +167,16 @@ double ds_of(const Background& bg, double a1, double a2) {
   return s * hw;
 }
 
+double kick_of(const Background& bg, double a1, double a2) {
+  const GaussLegendre& g = gl16();
+  const double u1 = std::log(a1), u2 = std::log(a2);
+  const double hw = 0.5 * (u2 - u1), mid = 0.5 * (u1 + u2);
+  double s = 0.0;
+  for (size_t i = 0; i < g.x.size(); ++i) {
+    const double a = std::exp(mid + hw * g.x[i]);
+    s += g.w[i] / (a * hubble_of(bg, a));
+  }
+  return s * hw;
+}
+
 }  // namespace pmnu

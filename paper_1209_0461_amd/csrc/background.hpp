@@ -38,6 +38,10 @@ double hubble_of(const Background& bg, double a);
 // s(a2) - s(a1) over a short interval (16-point Gauss-Legendre in ln a).
 double ds_of(const Background& bg, double a1, double a2);
 
+// int_{a1}^{a2} da / (a^2 H) over a short interval (the kick factor of the leapfrog in s:
+// du/ds = a^2 acc with a acc held fixed, Delta u = (a acc) int da / (a^2 H)).
+double kick_of(const Background& bg, double a1, double a2);
+
 // E(y) = int_0^inf sqrt(x^2 + y^2) x^2 / (e^x + 1) dx, y = m a / T_nu0: the energy
 // integral of eq. (relativistic) in units of T_nu0^4/a^4 (up to the Fermi-Dirac prefactor).
 double fd_energy(double y);

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <numeric>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -20,7 +21,7 @@ namespace pmnu {
 const char* const kStageNames[ST_COUNT] = {
     "zero_mesh", "cic_deposit", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x_bin", "nu_response",
     "rtable", "inv_x_green", "fft_inv_y", "fft_inv_z", "cic_interp", "surrogate",
-    "patch_reduce"};
+    "patch_reduce", "kick_drift"};
 
 namespace {
 thread_local std::string g_err = "no error";
@@ -300,6 +301,8 @@ int do_response_mode(Ctx& c, double a_now, int mode) {
   if (c.stage < 1) return set_error(PM_NU_ESTATE, "pm_nu_response needs pm_nu_deposit first");
   if (!(a_now > 0.0) || !std::isfinite(a_now)) return set_error(PM_NU_EINVAL, "bad a_now");
   if (!c.capturing) {
+    // an eager step at another a moves the history past what a captured graph recomputes
+    if (c.graph_exec && a_now != c.graph_a) drop_graph(c);
     int rc = prepare_time_grid(c, a_now);
     if (rc) return rc;
   } else if (c.tg_a_now != a_now) {
@@ -371,7 +374,7 @@ void free_ctx(Ctx* c) {
                   c->ratio, c->hist_pm, c->hist_pnu, c->ic_pnu, c->ic_theta, c->tg_ds,
                   c->tg_w, c->d_resp, c->rtable, c->tw, c->inv_w2, c->d_flags, c->patches,
                   c->patch_hdr, c->patch_status, c->reg_count, c->reg_list, c->rho_fb, c->n_fb,
-                  c->delta};
+                  c->delta, c->d_kd};
   for (void* p : bufs)
     if (p) hipFree(p);
   delete c;
@@ -500,6 +503,7 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
     ALLOC(c->n_fb, 1);
     ALLOC(c->delta, nb * c->M);
   }
+  ALLOC(c->d_kd, 2 * nb);
 #undef ALLOC
   build_bins(*c);
   if (c->nonempty.empty()) {
@@ -779,6 +783,75 @@ int pm_nu_step(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now) {
   return pm_nu_force(ctx, pos, acc, a_now);
 }
 
+namespace {
+
+// Kick and drift factors of every box, uploaded for the next kick_drift launch (the stream is
+// idle: the previous step's time grid upload waited for it).
+int upload_kd(Ctx& c, const std::vector<double>& kd) {
+  PMNU_HIP(hipStreamSynchronize(c.stream));
+  PMNU_HIP(hipMemcpy(c.d_kd, kd.data(), kd.size() * sizeof(double), hipMemcpyHostToDevice));
+  return PM_NU_OK;
+}
+
+}  // namespace
+
+int pm_nu_advance(pm_nu_ctx* ctx, float* pos, float* vel, float* acc, const double* a_steps,
+                  int n_steps) {
+  GET_CTX(ctx);
+  if (!pos || !vel || !acc || !a_steps || n_steps < 1)
+    return set_error(PM_NU_EINVAL, "pos, vel, acc and a_steps are needed, n_steps >= 1");
+  for (const void* p : {static_cast<const void*>(pos), static_cast<const void*>(vel),
+                        static_cast<const void*>(acc)})
+    if (reinterpret_cast<uintptr_t>(p) % 16)
+      return set_error(PM_NU_EINVAL, "pos, vel and acc must be 16-byte aligned");
+  for (int j = 0; j <= n_steps; ++j)
+    if (!(a_steps[j] > 0.0) || !std::isfinite(a_steps[j]) || (j && !(a_steps[j] > a_steps[j - 1])))
+      return set_error(PM_NU_EINVAL, "a_steps must be finite, positive and increasing");
+  for (int b = 0; b < c->nbox; ++b) {
+    const std::vector<double>& ha = c->hist_a[b];
+    if (ha.empty()) return set_error(PM_NU_EHISTORY, "box %d has no stored history", b);
+    if (a_steps[1] <= ha.back() * (1.0 + 1e-12))
+      return set_error(PM_NU_EHISTORY, "box %d: a_steps[1]=%g does not follow the last stored "
+                       "node %g", b, a_steps[1], ha.back());
+    if (static_cast<int>(ha.size()) + n_steps > c->Jcap)
+      return set_error(PM_NU_EHISTORY, "box %d: %d more nodes do not fit the history (%d of %d "
+                       "used)", b, n_steps, static_cast<int>(ha.size()), c->Jcap);
+  }
+  std::vector<Background> bg(c->nbox);
+  for (int b = 0; b < c->nbox; ++b)
+    bg[b] = make_background(c->relativistic, c->cfg.omega_m, c->cfg.hubble, c->species[b],
+                            c->nu_mult[b], c->nu_massless[b]);
+  const float L = static_cast<float>(c->cfg.box_size);
+  std::vector<double> kd(2 * static_cast<size_t>(c->nbox));
+  double a_mid_prev = a_steps[0];    // the first kick starts at a_steps[0]
+  for (int j = 0; j < n_steps; ++j) {
+    const double a0 = a_steps[j], a1 = a_steps[j + 1], am = std::sqrt(a0 * a1);
+    // the closing half kick of the previous step and the opening one of this step both
+    // use the force at a0: one kick over [a_mid_prev, am]
+    for (int b = 0; b < c->nbox; ++b) {
+      kd[2 * b] = a0 * kick_of(bg[b], a_mid_prev, am);
+      kd[2 * b + 1] = ds_of(bg[b], a0, a1);
+    }
+    int rc = upload_kd(*c, kd);
+    if (rc) return rc;
+    TIMED(*c, ST_KICK_DRIFT, launch_kick_drift(pos, vel, acc, c->d_kd, c->Np, c->nbox, L, true,
+                                               c->stream));
+    rc = pm_nu_step(ctx, pos, acc, a1);
+    if (rc) return rc;
+    a_mid_prev = am;
+  }
+  const double an = a_steps[n_steps];
+  for (int b = 0; b < c->nbox; ++b) {
+    kd[2 * b] = an * kick_of(bg[b], a_mid_prev, an);
+    kd[2 * b + 1] = 0.0;
+  }
+  int rc = upload_kd(*c, kd);
+  if (rc) return rc;
+  TIMED(*c, ST_KICK_DRIFT, launch_kick_drift(pos, vel, acc, c->d_kd, c->Np, c->nbox, L, false,
+                                             c->stream));
+  return PM_NU_OK;
+}
+
 int pm_nu_get_spectrum(pm_nu_ctx* ctx, int box, double* p_cdm, double* pnu_half,
                        double* ratio) {
   GET_CTX(ctx);
@@ -920,6 +993,7 @@ int pm_nu_graph_capture(pm_nu_ctx* ctx, const float* pos, float* acc, double a_n
   if (e != hipSuccess) return set_error(PM_NU_EHIP, "end capture: %s", hipGetErrorString(e));
   c->graph = g;
   PMNU_HIP(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+  c->graph_a = a_now;
   return PM_NU_OK;
 }
 

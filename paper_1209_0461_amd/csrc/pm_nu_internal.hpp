@@ -55,7 +55,8 @@ struct Timer {
 
 enum Stage {
   ST_ZERO = 0, ST_DEPOSIT, ST_FFT_Z, ST_FFT_Y, ST_FFT_X_BIN, ST_RESPONSE, ST_RTABLE,
-  ST_INV_X_GREEN, ST_INV_Y, ST_INV_Z, ST_INTERP, ST_SURROGATE, ST_PATCH_REDUCE, ST_COUNT
+  ST_INV_X_GREEN, ST_INV_Y, ST_INV_Z, ST_INTERP, ST_SURROGATE, ST_PATCH_REDUCE, ST_KICK_DRIFT,
+  ST_COUNT
 };
 extern const char* const kStageNames[ST_COUNT];
 
@@ -120,6 +121,7 @@ struct Ctx {
   unsigned long long* rho_fb = nullptr;    // [nbox][M] side grid, kept at zero
   int* n_fb = nullptr;             // [1] chunks that used the side grid this deposit
   float* delta = nullptr;          // [nbox][M] delta in FP32 (mode 6)
+  double* d_kd = nullptr;          // [nbox][2] kick and drift factors of the leapfrog
   bool density_is_delta = false;   // the last deposit wrote delta (mode 6), not rho
 
   // host state
@@ -138,6 +140,7 @@ struct Ctx {
   Timer timer;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  double graph_a = -1.0;           // a_now of the captured step
   bool capturing = false;
 
   Surrogate* sur = nullptr;
@@ -248,6 +251,9 @@ hipError_t launch_patch_reduce(const unsigned long long* patches, const int4* hd
                                int nbox, int n, double scale, hipStream_t s);
 hipError_t launch_delta_to_density(const float* delta, float* out, int64_t n, float rho_bar,
                                    hipStream_t s);
+hipError_t launch_kick_drift(float* pos, float* vel, const float* acc, const double* kd,
+                             int64_t n_particles, int nbox, float box, bool drift,
+                             hipStream_t s);
 hipError_t launch_kernel_values(const double* x, int64_t n, int series, double* out,
                                 hipStream_t s);
 hipError_t launch_bin_power(const double* partial, int n_partial, const double* counts,

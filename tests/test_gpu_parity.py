@@ -500,3 +500,61 @@ def test_kernel_flag_is_checked():
     ctx = PMNu(16, 8, 64.0, 8, 4, [0.1])
     assert binding.ERRORS[binding.load_library().pm_nu_set_kernel(ctx.h, 5)] == "EINVAL"
     ctx.close()
+
+
+@pytest.mark.parametrize("masses,relativistic", [((0.3,), False), ((0.1, 0.6), True)])
+def test_advance_matches_oracle(masses, relativistic):
+    """Several kick-drift-kick steps through the C ABI (positions, velocities, forces and the
+    history rows each step stores) against the oracle's loop, per box."""
+    import torch
+    import oracle.step as ostep
+    from paper_1209_0461_amd import PMNu, binding
+    from synth import log_spaced_nodes, synthetic_history, zeldovich_ics
+    nm, box, nb, a0 = 32, 128.0, 16, 0.1
+    steps = np.geomspace(a0, 0.2, 5)
+    nbox = len(masses)
+    ics = [zeldovich_ics(32, box, 0.3, 71 + b, a0) for b in range(nbox)]
+    pos = np.stack([p for p, _ in ics])
+    vel = np.stack([v for _, v in ics])
+    ctx = PMNu(nm, pos.shape[1], box, nb, 20, list(masses))
+    binding.pm_nu_set_background(ctx.h, relativistic)
+    refs = []
+    for b in range(nbox):
+        sp = ostep.spectrum(pos[b], nm, box, nb)
+        hist = synthetic_history(sp["k_mean"], np.sqrt(sp["p_cdm"]),
+                                 log_spaced_nodes(0.01, a0, 10), masses[b])
+        ctx.set_history(b, hist)
+        r = ostep.full_step(pos[b], nm, box, nb, hist, a0, masses[b], relativistic=relativistic)
+        h = dict(hist)
+        h["a"] = np.append(hist["a"], a0)
+        h["pm_half"] = np.vstack([hist["pm_half"], r["pm_half_now"]])
+        h["pnu_half"] = np.vstack([hist["pnu_half"], r["pnu_half"]])
+        refs.append(ostep.advance(pos[b], vel[b], r["acc"], h, steps, nm, box, nb, masses[b],
+                                  relativistic=relativistic))
+    p = torch.from_numpy(pos).cuda()
+    v = torch.from_numpy(vel).cuda()
+    acc = torch.zeros_like(p)
+    ctx.step(p, acc, a0)
+    binding.pm_nu_advance(ctx.h, p, v, acc, steps)
+    torch.cuda.synchronize()
+    pg, vg, ag = p.cpu().numpy(), v.cpu().numpy(), acc.cpu().numpy()
+    cell = box / nm
+    for b in range(nbox):
+        x1, u1, g1, h1 = refs[b]
+        dx = np.mod(pg[b] - x1 + box / 2, box) - box / 2
+        assert np.abs(dx).max() <= 1e-4 * cell, (b, np.abs(dx).max())
+        assert np.all((pg[b] >= 0) & (pg[b] < box))
+        assert rms_rel(vg[b], u1) <= 1e-4, b
+        assert rms_rel(ag[b], g1) <= TOL_FORCE_RMS, b
+        a, pm, pn = ctx.history(b)
+        assert np.allclose(a[-len(steps):], steps, rtol=1e-15)
+        ok = pn[-1] > 0
+        for j in range(1, len(steps) + 1):
+            assert np.abs(pn[-j][ok] / h1["pnu_half"][-j][ok] - 1).max() <= 1e-5, (b, j)
+            assert np.abs(pm[-j][ok] / h1["pm_half"][-j][ok] - 1).max() <= 1e-5, (b, j)
+        print(f"  box {b}: |dx|max/cell {np.abs(dx).max() / cell:.1e}, "
+              f"u rms {rms_rel(vg[b], u1):.1e}", flush=True)
+    # the history is full after (capacity - stored) more steps
+    with pytest.raises(binding.PMNuError, match="history"):
+        binding.pm_nu_advance(ctx.h, p, v, acc, np.geomspace(0.2, 0.5, 10))
+    ctx.close()
