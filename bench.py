@@ -208,6 +208,52 @@ def measure_variants(ctx, binding, pos, acc, a_now, stream, names, steps=20):
     return out
 
 
+def measure_loop(cfg, pos, masses, stream, n_steps=50, a_start=0.5):
+    """The loop of Sec. 4.3 through pm_nu_advance: n_steps kick-drift-kick steps from a_start
+    to cfg["a_now"] after a stored history from cfg["a_lo"] to a_start, on a context of its
+    own. Reports steps/s of the whole loop (host time grid and uploads included) and the
+    kick-drift kernel's time (HIP events)."""
+    import torch
+    from paper_1209_0461_amd import PMNu, binding
+    from synth import log_spaced_nodes, synthetic_history
+    nbox = pos.shape[0]
+    J = cfg["n_hist"]
+    ctx = PMNu(cfg["n_mesh"], pos.shape[1], cfg["box"], cfg["n_kbins"], J + n_steps + 2,
+               list(masses), substeps=cfg["substeps"])
+    p = pos.clone()
+    vel = torch.zeros_like(p)
+    acc = torch.zeros_like(p)
+    ctx.deposit(p)
+    _, _, kmean = ctx.bins()
+    nodes = log_spaced_nodes(cfg["a_lo"], a_start, J)
+    for b in range(nbox):
+        h = synthetic_history(kmean, np.sqrt(ctx.spectrum(b)["p_cdm"]), nodes, float(masses[b]))
+        ctx.set_history(b, h)
+    ctx.step(p, acc, a_start)
+    a_steps = np.geomspace(a_start, cfg["a_now"], n_steps + 1)
+    ctx.advance(p, vel, acc, a_steps[:3])        # warm-up (also moves the history on)
+    stream.synchronize()
+    names = list(binding.pm_nu_read_timing(ctx.h))
+    binding.pm_nu_set_timing_mask(ctx.h, 1 << names.index("kick_drift"))
+    t0 = time.perf_counter()
+    ctx.advance(p, vel, acc, a_steps[2:])
+    stream.synchronize()
+    dt = time.perf_counter() - t0
+    t = binding.pm_nu_read_timing(ctx.h)
+    binding.pm_nu_set_timing(ctx.h, False)
+    n = n_steps - 2
+    kd_ms = t["kick_drift"][0] / max(1, t["kick_drift"][1])
+    kd_bytes = 60 * pos.shape[1] * nbox          # x, u, acc in; x, u out (FP32)
+    finite = bool(torch.isfinite(p).all() and torch.isfinite(vel).all())
+    ctx.close()
+    return {"steps": n, "a": [float(a_steps[2]), float(a_steps[-1])],
+            "steps_per_s": n / dt, "ms_per_step": 1e3 * dt / n,
+            "kick_drift_ms": kd_ms, "kick_drift_gbs": kd_bytes / (kd_ms * 1e-3) / 1e9,
+            "particle_updates_per_s": n / dt * pos.shape[1] * nbox, "finite": finite,
+            "note": "HIP events around the kick-drift kernels only; each step's time grid is "
+                    "built on the host and copied in stream order"}
+
+
 def cpu_baseline(cfg, pos, masses, hists):
     """Time the FP64 oracle on one full step of box 0 (single-threaded NumPy)."""
     import oracle.step as ostep
@@ -236,6 +282,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate-versus-integral measurement")
+    ap.add_argument("--no-loop", action="store_true",
+                    help="skip the time-stepping loop measurement")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the exact-kernel and second-iteration measurement")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -330,6 +378,9 @@ def main():
         variants = None
         if not args.no_variants:
             variants = measure_variants(ctx, binding, pos, acc, a_now, stream, names)
+        loop = None
+        if not args.no_loop and not args.graph:
+            loop = measure_loop(cfg, pos, masses, stream)
 
     from paper_1209_0461_amd.binding import load_library  # noqa: F401
     n_partial = (n_mesh // min(16 if n_mesh <= 256 else 8, n_mesh)) * (n_mesh // 2 + 1)
@@ -379,6 +430,8 @@ def main():
         out["surrogate"] = surrogate
     if variants is not None:
         out["variants"] = variants
+    if loop is not None:
+        out["loop"] = loop
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, pos_np, masses, hists)
     ctx.close()

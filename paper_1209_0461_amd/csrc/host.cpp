@@ -180,6 +180,22 @@ int nodes_for(const Ctx& c, int box, double a_now, std::vector<double>& nodes, i
 }
 
 // Time grid of eq. (P-final) for every box at a_now (host FP64, uploaded when changed).
+// Sub-nodes of one interval [a_lo, a_hi] of the quadrature (Q steps in ln a): their scale
+// factors, the s difference to the next sub-node, and 1/(a H).
+void interval_nodes(const Background& bg, double a_lo, double a_hi, int Q, double* a,
+                    double* seg, double* hinv) {
+  const double u0 = std::log(a_lo), u1 = std::log(a_hi);
+  const double h = (u1 - u0) / Q;
+  for (int r = 0; r < Q; ++r) a[r] = (r == 0) ? a_lo : std::exp(u0 + r * h);
+  for (int r = 0; r < Q; ++r) {
+    seg[r] = ds_of(bg, a[r], r + 1 < Q ? a[r + 1] : a_hi);
+    hinv[r] = 1.0 / (a[r] * hubble_of(bg, a[r]));
+  }
+}
+
+// Time grid of eq. (P-final) for every box at a_now (host FP64). The sub-intervals between
+// stored nodes are kept per box and only the newest interval, to a_now, is integrated
+// afresh; the arrays go to the device by stream-ordered copies from pinned staging.
 int prepare_time_grid(Ctx& c, double a_now) {
   std::vector<std::vector<double>> all_nodes(c.nbox);
   std::vector<int> ncur(c.nbox);
@@ -192,56 +208,84 @@ int prepare_time_grid(Ctx& c, double a_now) {
   const double om = c.cfg.omega_m;
   const double pref = 1.5 * om * kH0 * kH0;   // the source keeps all matter, Omega_M
   const int Q = c.Q;
-  std::vector<double> ds(static_cast<size_t>(c.nbox) * c.qcap, 0.0);
-  std::vector<double> w(static_cast<size_t>(c.nbox) * c.qcap, 0.0);
-  std::vector<RespBox> rb(c.nbox);
+  const size_t qcap = static_cast<size_t>(c.qcap);
+  PMNU_HIP(hipEventSynchronize(c.ev_tg));     // the staging's previous upload has run
+  double* ds_all = c.h_tg;
+  double* w_all = c.h_tg + c.nbox * qcap;
+  std::vector<double> tw, a_last(Q), seg_last(Q), hinv_last(Q);
   for (int b = 0; b < c.nbox; ++b) {
     const std::vector<double>& nd = all_nodes[b];
     const int n = ncur[b];
     const int nq = n * Q + 1;
-    std::vector<double> a(nq), tw(nq, 0.0);
-    for (int j = 0; j < n; ++j) {
-      const double u0 = std::log(nd[j]), u1 = std::log(nd[j + 1]);
-      const double h = (u1 - u0) / Q;
-      for (int r = 0; r < Q; ++r) {
-        a[j * Q + r] = (r == 0) ? nd[j] : std::exp(u0 + r * h);
-        tw[j * Q + r] += (r == 0) ? 0.5 * h : h;
-        tw[j * Q + r + 1] += (r == Q - 1) ? 0.5 * h : 0.0;
-      }
-    }
-    a[nq - 1] = nd[n];
     const Background bg = make_background(c.relativistic, om, c.cfg.hubble, c.species[b],
                                           c.nu_mult[b], c.nu_massless[b]);
-    double* dsb = ds.data() + static_cast<size_t>(b) * c.qcap;
-    double* wb = w.data() + static_cast<size_t>(b) * c.qcap;
+    TgCache& cc = c.tgc[b];
+    if (cc.bg_version != c.bg_version) {
+      cc = TgCache();
+      cc.bg_version = c.bg_version;
+    }
+    size_t keep = 0;   // leading stored nodes the cache was built from
+    while (keep < cc.nodes.size() && keep < static_cast<size_t>(n) && cc.nodes[keep] == nd[keep])
+      ++keep;
+    const int kept = keep > 0 ? static_cast<int>(keep) - 1 : 0;   // intervals still valid
+    cc.a.resize(static_cast<size_t>(kept) * Q);
+    cc.seg.resize(cc.a.size());
+    cc.hinv.resize(cc.a.size());
+    for (int jj = kept; jj + 1 < n; ++jj) {                       // stored intervals to add
+      const size_t o = cc.a.size();
+      cc.a.resize(o + Q);
+      cc.seg.resize(o + Q);
+      cc.hinv.resize(o + Q);
+      interval_nodes(bg, nd[jj], nd[jj + 1], Q, &cc.a[o], &cc.seg[o], &cc.hinv[o]);
+    }
+    cc.nodes.assign(nd.begin(), nd.begin() + n);
+    interval_nodes(bg, nd[n - 1], nd[n], Q, a_last.data(), seg_last.data(), hinv_last.data());
+    const int q_last = (n - 1) * Q;   // first sub-node of the interval to a_now
+    tw.assign(nq, 0.0);
+    for (int jj = 0; jj < n; ++jj) {
+      const double h = (std::log(nd[jj + 1]) - std::log(nd[jj])) / Q;
+      for (int r = 0; r < Q; ++r) {
+        tw[jj * Q + r] += (r == 0) ? 0.5 * h : h;
+        tw[jj * Q + r + 1] += (r == Q - 1) ? 0.5 * h : 0.0;
+      }
+    }
+    double* dsb = ds_all + b * qcap;
+    double* wb = w_all + b * qcap;
     dsb[nq - 1] = 0.0;
-    for (int q = nq - 2; q >= 0; --q) dsb[q] = dsb[q + 1] + ds_of(bg, a[q], a[q + 1]);
-    for (int q = 0; q < nq; ++q) wb[q] = pref * tw[q] / (a[q] * hubble_of(bg, a[q]));
-    rb[b].f_nu = c.f_nu[b];
+    for (int q = nq - 2; q >= 0; --q)
+      dsb[q] = dsb[q + 1] + (q < q_last ? cc.seg[q] : seg_last[q - q_last]);
+    for (int q = 0; q < nq - 1; ++q)
+      wb[q] = pref * tw[q] * (q < q_last ? cc.hinv[q] : hinv_last[q - q_last]);
+    wb[nq - 1] = pref * tw[nq - 1] / (nd[n] * hubble_of(bg, nd[n]));
+    RespBox& rb = c.h_resp[b];
+    rb = RespBox();
+    rb.f_nu = c.f_nu[b];
     const std::vector<double>& sp = c.species[b];
-    rb[b].n_sp = static_cast<int>(sp.size());
+    rb.n_sp = static_cast<int>(sp.size());
     const double msum = std::accumulate(sp.begin(), sp.end(), 0.0);
     for (int s = 0; s < kMaxSpecies; ++s) {
-      const bool on = s < rb[b].n_sp;
-      rb[b].w_sp[s] = on ? (rb[b].n_sp == 1 ? 1.0 : sp[s] / msum) : 0.0;
-      rb[b].tm_sp[s] = on ? kTnu0 / sp[s] : 0.0;
+      const bool on = s < rb.n_sp;
+      rb.w_sp[s] = on ? (rb.n_sp == 1 ? 1.0 : sp[s] / msum) : 0.0;
+      rb.tm_sp[s] = on ? kTnu0 / sp[s] : 0.0;
     }
-    rb[b].t_over_m = rb[b].n_sp > 0 ? rb[b].tm_sp[0] : 0.0;
+    rb.t_over_m = rb.n_sp > 0 ? rb.tm_sp[0] : 0.0;
     // the network was trained on matter + Lambda with the fit for I(x)
-    rb[b].sur_ok = c.sur_setting[b] && !c.relativistic && !c.series;
-    rb[b].series = c.series ? 1 : 0;
-    rb[b].ds_ic = dsb[0];
-    rb[b].a_i = nd[0];
-    rb[b].kfs = k_free_streaming(a_now, c.m_nu[b] / c.cfg.n_species, om);
-    rb[b].m_total = c.m_nu[b];
-    rb[b].a_now = a_now;
-    rb[b].nq = nq;
-    rb[b].n_cur = n;
+    rb.sur_ok = c.sur_setting[b] && !c.relativistic && !c.series;
+    rb.series = c.series ? 1 : 0;
+    rb.ds_ic = dsb[0];
+    rb.a_i = nd[0];
+    rb.kfs = k_free_streaming(a_now, c.m_nu[b] / c.cfg.n_species, om);
+    rb.m_total = c.m_nu[b];
+    rb.a_now = a_now;
+    rb.nq = nq;
+    rb.n_cur = n;
   }
-  PMNU_HIP(hipStreamSynchronize(c.stream));
-  PMNU_HIP(hipMemcpy(c.tg_ds, ds.data(), ds.size() * sizeof(double), hipMemcpyHostToDevice));
-  PMNU_HIP(hipMemcpy(c.tg_w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
-  PMNU_HIP(hipMemcpy(c.d_resp, rb.data(), rb.size() * sizeof(RespBox), hipMemcpyHostToDevice));
+  const size_t bytes = c.nbox * qcap * sizeof(double);
+  PMNU_HIP(hipMemcpyAsync(c.tg_ds, ds_all, bytes, hipMemcpyHostToDevice, c.stream));
+  PMNU_HIP(hipMemcpyAsync(c.tg_w, w_all, bytes, hipMemcpyHostToDevice, c.stream));
+  PMNU_HIP(hipMemcpyAsync(c.d_resp, c.h_resp, c.nbox * sizeof(RespBox), hipMemcpyHostToDevice,
+                          c.stream));
+  PMNU_HIP(hipEventRecord(c.ev_tg, c.stream));
   c.tg_a_now = a_now;
   c.tg_version = c.hist_version;
   c.n_cur = ncur;
@@ -377,6 +421,11 @@ void free_ctx(Ctx* c) {
                   c->delta, c->d_kd};
   for (void* p : bufs)
     if (p) hipFree(p);
+  for (void* p : {static_cast<void*>(c->h_tg), static_cast<void*>(c->h_resp),
+                  static_cast<void*>(c->h_kd)})
+    if (p) hipHostFree(p);
+  if (c->ev_tg) hipEventDestroy(c->ev_tg);
+  if (c->ev_kd) hipEventDestroy(c->ev_kd);
   delete c;
 }
 
@@ -505,6 +554,17 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   }
   ALLOC(c->d_kd, 2 * nb);
 #undef ALLOC
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_tg), 2 * nb * c->qcap * sizeof(double)) !=
+          hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->h_resp), nb * sizeof(RespBox)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->h_kd), 2 * nb * sizeof(double)) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_tg, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_kd, hipEventDisableTiming) != hipSuccess) {
+    free_ctx(c);
+    return set_error(PM_NU_ENOMEM, "pinned staging or events could not be created");
+  }
+  std::memset(c->h_tg, 0, 2 * nb * c->qcap * sizeof(double));
+  c->tgc.resize(c->nbox);
   build_bins(*c);
   if (c->nonempty.empty()) {
     free_ctx(c);
@@ -647,6 +707,7 @@ int pm_nu_set_response_mode(pm_nu_ctx* ctx, int mode) {
 int pm_nu_set_mass(pm_nu_ctx* ctx, int box, double m_nu_total) {
   GET_CTX(ctx);
   drop_graph(*c);   // a captured step would not see the change
+  ++c->bg_version;   // H(a) may change
   if (box < 0 || box >= c->nbox) return set_error(PM_NU_EINVAL, "box %d out of range", box);
   if (!(m_nu_total >= 0.0) || !std::isfinite(m_nu_total))
     return set_error(PM_NU_EINVAL, "m_nu_total must be >= 0");
@@ -667,6 +728,7 @@ int pm_nu_set_species(pm_nu_ctx* ctx, int box, int n_species, const double* m_sp
                       const double* pnu_half_init) {
   GET_CTX(ctx);
   drop_graph(*c);   // a captured step would not see the change
+  ++c->bg_version;   // H(a) may change
   if (box < 0 || box >= c->nbox) return set_error(PM_NU_EINVAL, "box %d out of range", box);
   if (n_species < 1 || n_species > kMaxSpecies || !m_species)
     return set_error(PM_NU_EINVAL, "n_species must be in [1, %d] with masses given",
@@ -712,6 +774,7 @@ int pm_nu_set_species(pm_nu_ctx* ctx, int box, int n_species, const double* m_sp
 int pm_nu_set_background(pm_nu_ctx* ctx, int relativistic) {
   GET_CTX(ctx);
   drop_graph(*c);   // a captured step would not see the change
+  ++c->bg_version;   // H(a) may change
   if (relativistic != 0 && relativistic != 1)
     return set_error(PM_NU_EINVAL, "relativistic must be 0 or 1 (got %d)", relativistic);
   c->relativistic = relativistic == 1;
@@ -785,11 +848,14 @@ int pm_nu_step(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now) {
 
 namespace {
 
-// Kick and drift factors of every box, uploaded for the next kick_drift launch (the stream is
-// idle: the previous step's time grid upload waited for it).
+// Kick and drift factors of every box, copied in stream order ahead of the next kick_drift
+// launch.
 int upload_kd(Ctx& c, const std::vector<double>& kd) {
-  PMNU_HIP(hipStreamSynchronize(c.stream));
-  PMNU_HIP(hipMemcpy(c.d_kd, kd.data(), kd.size() * sizeof(double), hipMemcpyHostToDevice));
+  PMNU_HIP(hipEventSynchronize(c.ev_kd));     // the staging's previous upload has run
+  std::copy(kd.begin(), kd.end(), c.h_kd);
+  PMNU_HIP(hipMemcpyAsync(c.d_kd, c.h_kd, kd.size() * sizeof(double), hipMemcpyHostToDevice,
+                          c.stream));
+  PMNU_HIP(hipEventRecord(c.ev_kd, c.stream));
   return PM_NU_OK;
 }
 

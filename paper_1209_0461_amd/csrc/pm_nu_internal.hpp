@@ -62,6 +62,14 @@ extern const char* const kStageNames[ST_COUNT];
 
 struct Surrogate;  // defined in surrogate.cpp
 
+// Per box: the quadrature sub-nodes of the intervals between stored history nodes (they do
+// not change as the history grows, only the interval to the current step does).
+struct TgCache {
+  std::vector<double> nodes;            // the stored nodes they were built from
+  std::vector<double> a, seg, hinv;     // per sub-node: a, s to the next sub-node, 1/(a H)
+  int64_t bg_version = -1;              // Ctx::bg_version they were built with
+};
+
 struct Ctx {
   pm_nu_config cfg{};
   int N = 0, NK = 0, nbox = 0, B = 0, Jcap = 0, Q = 0;
@@ -122,6 +130,11 @@ struct Ctx {
   int* n_fb = nullptr;             // [1] chunks that used the side grid this deposit
   float* delta = nullptr;          // [nbox][M] delta in FP32 (mode 6)
   double* d_kd = nullptr;          // [nbox][2] kick and drift factors of the leapfrog
+  // pinned staging of the host-built arrays (copied in stream order) and the last copies
+  double* h_tg = nullptr;          // ds [nbox][qcap], then w [nbox][qcap]
+  RespBox* h_resp = nullptr;       // [nbox]
+  double* h_kd = nullptr;          // [nbox][2]
+  hipEvent_t ev_tg = nullptr, ev_kd = nullptr;
   bool density_is_delta = false;   // the last deposit wrote delta (mode 6), not rho
 
   // host state
@@ -133,6 +146,8 @@ struct Ctx {
   const float* pos_dep = nullptr;
   // time-grid cache: valid for (a_now, history version)
   double tg_a_now = -1.0;
+  std::vector<TgCache> tgc;        // per box
+  int64_t bg_version = 0;          // bumped whenever H(a) of a box may change
   int64_t hist_version = 0, tg_version = -1;
   std::vector<int> n_cur;          // row of the current step per box (valid after prepare)
 
