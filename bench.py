@@ -36,6 +36,7 @@ KERNEL_SOURCES = {
     "inv_x_green": "fft_kernels.hip", "fft_inv_y": "fft_kernels.hip",
     "fft_inv_z": "fft_kernels.hip", "nu_response": "response_kernels.hip",
     "rtable": "response_kernels.hip", "patch_reduce": "grid_kernels.hip",
+    "kick_drift": "advance_kernels.hip",
 }
 
 
@@ -83,7 +84,7 @@ def kernel_name(stage, tuning, n_mesh):
     """Name (with template arguments) of the kernel a stage launches, as rocprofv3 lists it."""
     dep = {1: "<1024, 3328, 256>", 2: "<2048, 5120, 256>", 3: "<4096, 9216, 256>",
            4: "<4096, 9216, 512>", 5: "<8192, 18432, 1024>"}
-    itp = {1: "<1024, 2560>", 2: "<2048, 4608>", 3: "<4096, 8192>"}
+    itp = {1: "<1024, 2560, false>", 2: "<2048, 4608, false>", 3: "<4096, 8192, false>"}
     if stage == "cic_deposit":
         m = tuning["deposit_mode"]
         if m == 6:
@@ -93,7 +94,7 @@ def kernel_name(stage, tuning, n_mesh):
         m = tuning["interp_mode"]
         if m:
             return "interp_tiled_kernel" + itp[m]
-        return "interp_kernel<%d>" % max(1, min(4, tuning["interp_block"] // 256))
+        return "interp_kernel<%d, false>" % max(1, min(4, tuning["interp_block"] // 256))
     fixed = {"zero_mesh": "fill_zero_kernel", "nu_response": "response_kernel",
              "rtable": "rtable_kernel", "patch_reduce": "patch_reduce_kernel"}
     if stage in fixed:
@@ -212,7 +213,7 @@ def measure_loop(cfg, pos, masses, stream, n_steps=50, a_start=0.5):
     """The loop of Sec. 4.3 through pm_nu_advance: n_steps kick-drift-kick steps from a_start
     to cfg["a_now"] after a stored history from cfg["a_lo"] to a_start, on a context of its
     own. Reports steps/s of the whole loop (host time grid and uploads included) and the
-    kick-drift kernel's time (HIP events)."""
+    time of the interpolation, which carries the leapfrog (HIP events)."""
     import torch
     from paper_1209_0461_amd import PMNu, binding
     from synth import log_spaced_nodes, synthetic_history
@@ -234,7 +235,7 @@ def measure_loop(cfg, pos, masses, stream, n_steps=50, a_start=0.5):
     ctx.advance(p, vel, acc, a_steps[:3])        # warm-up (also moves the history on)
     stream.synchronize()
     names = list(binding.pm_nu_read_timing(ctx.h))
-    binding.pm_nu_set_timing_mask(ctx.h, 1 << names.index("kick_drift"))
+    binding.pm_nu_set_timing_mask(ctx.h, 1 << names.index("cic_interp"))
     t0 = time.perf_counter()
     ctx.advance(p, vel, acc, a_steps[2:])
     stream.synchronize()
@@ -242,16 +243,19 @@ def measure_loop(cfg, pos, masses, stream, n_steps=50, a_start=0.5):
     t = binding.pm_nu_read_timing(ctx.h)
     binding.pm_nu_set_timing(ctx.h, False)
     n = n_steps - 2
-    kd_ms = t["kick_drift"][0] / max(1, t["kick_drift"][1])
-    kd_bytes = 60 * pos.shape[1] * nbox          # x, u, acc in; x, u out (FP32)
+    it_ms = t["cic_interp"][0] / max(1, t["cic_interp"][1])
+    # interpolation with the leapfrog applied: x, u in and x, u out per particle besides the
+    # 8 corners of the acceleration grid (the grid counted once, as in the step)
+    it_bytes = (48 * pos.shape[1] + 12 * cfg["n_mesh"] ** 3) * nbox
     finite = bool(torch.isfinite(p).all() and torch.isfinite(vel).all())
     ctx.close()
     return {"steps": n, "a": [float(a_steps[2]), float(a_steps[-1])],
             "steps_per_s": n / dt, "ms_per_step": 1e3 * dt / n,
-            "kick_drift_ms": kd_ms, "kick_drift_gbs": kd_bytes / (kd_ms * 1e-3) / 1e9,
+            "interp_leapfrog_ms": it_ms, "interp_leapfrog_gbs": it_bytes / (it_ms * 1e-3) / 1e9,
             "particle_updates_per_s": n / dt * pos.shape[1] * nbox, "finite": finite,
-            "note": "HIP events around the kick-drift kernels only; each step's time grid is "
-                    "built on the host and copied in stream order"}
+            "note": "HIP events around the interpolation only, which applies each step's "
+                    "kick and next drift; each step's time grid is built on the host and "
+                    "copied in stream order"}
 
 
 def cpu_baseline(cfg, pos, masses, hists):

@@ -1,4 +1,5 @@
-// Leapfrog updates of the particles in the superconformal time s (gfx950).
+// Leapfrog updates of the particles in the superconformal time s (gfx950). Later kicks and
+// drifts are applied by the interpolation itself; this kernel serves the first one.
 //
 // kick_drift_kernel: u += K_b acc, then (if drift) x += D_b u wrapped into [0, L), on the
 // flat [box][particle][3] arrays; K_b, D_b per box. Every float is independent, so each
@@ -10,13 +11,6 @@
 
 namespace pmnu {
 namespace {
-
-__device__ __forceinline__ float wrap_into(float x, float L) {
-  if (x >= 0.f && x < L) return x;
-  x = fmodf(x, L);                 // exact
-  if (x < 0.f) x += L;
-  return x < L ? x : 0.f;          // x + L may round up to L
-}
 
 template <bool DRIFT>
 __global__ __launch_bounds__(256) void kick_drift_kernel(float* __restrict__ pos,
@@ -48,10 +42,10 @@ __global__ __launch_bounds__(256) void kick_drift_kernel(float* __restrict__ pos
     v.w += kk[3] * a.w;
     reinterpret_cast<float4*>(vel)[t] = v;
     if (DRIFT) {
-      x.x = wrap_into(x.x + dd[0] * v.x, L);
-      x.y = wrap_into(x.y + dd[1] * v.y, L);
-      x.z = wrap_into(x.z + dd[2] * v.z, L);
-      x.w = wrap_into(x.w + dd[3] * v.w, L);
+      x.x = wrap_box(x.x + dd[0] * v.x, L);
+      x.y = wrap_box(x.y + dd[1] * v.y, L);
+      x.z = wrap_box(x.z + dd[2] * v.z, L);
+      x.w = wrap_box(x.w + dd[3] * v.w, L);
       reinterpret_cast<float4*>(pos)[t] = x;
     }
   } else {
@@ -59,7 +53,7 @@ __global__ __launch_bounds__(256) void kick_drift_kernel(float* __restrict__ pos
       const double2 f = kd[j < edge ? b0 : b0 + 1];
       const float v = vel[j] + static_cast<float>(f.x) * acc[j];
       vel[j] = v;
-      if (DRIFT) pos[j] = wrap_into(pos[j] + static_cast<float>(f.y) * v, L);
+      if (DRIFT) pos[j] = wrap_box(pos[j] + static_cast<float>(f.y) * v, L);
     }
   }
 }

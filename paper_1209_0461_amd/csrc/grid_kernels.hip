@@ -621,12 +621,38 @@ __device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t nblocks) {
 
 // Direct interpolation: PPT particles per thread (strided by the block size inside a
 // contiguous chunk), gathering from HBM through the caches.
-template <int PPT>
-__global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ pos,
+// The end of the interpolation for particle gi (global index) at position (x, y, z): store
+// the acceleration, or apply the leapfrog of pm_nu_advance (u += K acc; x += D u).
+template <bool LEAP>
+__device__ __forceinline__ void finish_particle(const Leap& lp, float* __restrict__ acc,
+                                                int64_t gi, float x, float y, float z,
+                                                float a0, float a1, float a2, float kk,
+                                                float dd) {
+  if (!LEAP || lp.store_acc) {
+    acc[3 * gi] = a0;
+    acc[3 * gi + 1] = a1;
+    acc[3 * gi + 2] = a2;
+  }
+  if (!LEAP) return;
+  float* u = lp.vel + 3 * gi;
+  const float u0 = u[0] + kk * a0, u1 = u[1] + kk * a1, u2 = u[2] + kk * a2;
+  u[0] = u0;
+  u[1] = u1;
+  u[2] = u2;
+  if (lp.pos) {
+    float* px = lp.pos + 3 * gi;
+    px[0] = wrap_box(x + dd * u0, lp.box);
+    px[1] = wrap_box(y + dd * u1, lp.box);
+    px[2] = wrap_box(z + dd * u2, lp.box);
+  }
+}
+
+template <int PPT, bool LEAP>
+__global__ __launch_bounds__(256) void interp_kernel(const float* pos,
                                                      const float* __restrict__ force,
                                                      float* __restrict__ acc, int64_t np, int n,
                                                      double inv_cell, int64_t chunks_per_box,
-                                                     int64_t nchunks) {
+                                                     int64_t nchunks, Leap lp) {
   constexpr int NT = 256, CH = NT * PPT;
   const int64_t chunk = xcd_chunk(blockIdx.x, gridDim.x);
   if (chunk >= nchunks) return;
@@ -634,9 +660,13 @@ __global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ p
   const int64_t c0 = (chunk - box * chunks_per_box) * CH;
   const int cnt = static_cast<int>(min(static_cast<int64_t>(CH), np - c0));
   const float* p = pos + (box * np + c0) * 3;
-  float* out = acc + (box * np + c0) * 3;
   const float* g = force + box * static_cast<int64_t>(n) * n * n * 3;
   const int nmask = n - 1;
+  float kk = 0.f, dd = 0.f;
+  if (LEAP) {
+    kk = static_cast<float>(lp.kd[2 * box]);
+    dd = static_cast<float>(lp.kd[2 * box + 1]);
+  }
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     const int j = threadIdx.x + q * NT;
@@ -648,21 +678,19 @@ __global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ p
       corner_of(x, y, z, inv_cell, nmask, c);
       gather_global(g, n, nmask, c, a0, a1, a2);
     }
-    out[3 * j] = a0;
-    out[3 * j + 1] = a1;
-    out[3 * j + 2] = a2;
+    finish_particle<LEAP>(lp, acc, box * np + c0 + j, x, y, z, a0, a1, a2, kk, dd);
   }
 }
 
 // Interpolation with the chunk's box of the acceleration grid staged in LDS (rows of
 // 3 * ez consecutive floats); chunks whose box does not fit gather straight from HBM.
-template <int CH, int CAP>
-__global__ __launch_bounds__(256) void interp_tiled_kernel(const float* __restrict__ pos,
+template <int CH, int CAP, bool LEAP>
+__global__ __launch_bounds__(256) void interp_tiled_kernel(const float* pos,
                                                            const float* __restrict__ force,
                                                            float* __restrict__ acc, int64_t np,
                                                            int n, double inv_cell,
                                                            int64_t chunks_per_box,
-                                                           int64_t nchunks) {
+                                                           int64_t nchunks, Leap lp) {
   constexpr int NT = 256, PPT = CH / NT;
   __shared__ float tile[CAP * 3];
   __shared__ int red[6][256 / 64];
@@ -672,9 +700,13 @@ __global__ __launch_bounds__(256) void interp_tiled_kernel(const float* __restri
   const int64_t box = chunk / chunks_per_box;
   const int64_t c0 = (chunk - box * chunks_per_box) * CH;
   const int cnt = static_cast<int>(min(static_cast<int64_t>(CH), np - c0));
-  float* out = acc + (box * np + c0) * 3;
   const int nmask = n - 1;
   const float* g = force + box * static_cast<int64_t>(n) * n * n * 3;
+  float kk = 0.f, dd = 0.f;
+  if (LEAP) {
+    kk = static_cast<float>(lp.kd[2 * box]);
+    dd = static_cast<float>(lp.kd[2 * box + 1]);
+  }
   Chunk<PPT> c;
   bool bad = false;
   load_chunk<PPT>(c, pos + (box * np + c0) * 3, cnt, inv_cell, nmask, red, bad);
@@ -756,9 +788,8 @@ __global__ __launch_bounds__(256) void interp_tiled_kernel(const float* __restri
         gather_global(g, n, nmask, k, a0, a1, a2);
       }
     }
-    out[3 * j] = a0;
-    out[3 * j + 1] = a1;
-    out[3 * j + 2] = a2;
+    finish_particle<LEAP>(lp, acc, box * np + c0 + j, c.p[q][0], c.p[q][1], c.p[q][2], a0, a1,
+                          a2, kk, dd);
   }
 }
 
@@ -886,34 +917,49 @@ int xcd_blocks(int64_t nchunks) { return static_cast<int>((nchunks + 7) / 8 * 8)
 
 template <int CH, int CAP>
 hipError_t launch_interp_tiled(const float* pos, const float* force, float* acc, int64_t np,
-                               int nbox, int n, double inv_cell, hipStream_t s) {
+                               int nbox, int n, double inv_cell, const Leap* lp, hipStream_t s) {
   const int64_t chunks = (np + CH - 1) / CH;
-  hipLaunchKernelGGL((interp_tiled_kernel<CH, CAP>), dim3(xcd_blocks(chunks * nbox)), dim3(256),
-                     0, s, pos, force, acc, np, n, inv_cell, chunks, chunks * nbox);
+  const dim3 grid(xcd_blocks(chunks * nbox));
+  if (lp)
+    hipLaunchKernelGGL((interp_tiled_kernel<CH, CAP, true>), grid, dim3(256), 0, s, pos, force,
+                       acc, np, n, inv_cell, chunks, chunks * nbox, *lp);
+  else
+    hipLaunchKernelGGL((interp_tiled_kernel<CH, CAP, false>), grid, dim3(256), 0, s, pos, force,
+                       acc, np, n, inv_cell, chunks, chunks * nbox, Leap());
   return hipGetLastError();
 }
 
 template <int PPT>
 hipError_t launch_interp_direct(const float* pos, const float* force, float* acc, int64_t np,
-                                int nbox, int n, double inv_cell, hipStream_t s) {
+                                int nbox, int n, double inv_cell, const Leap* lp,
+                                hipStream_t s) {
   const int64_t chunks = (np + 256 * PPT - 1) / (256 * PPT);
-  hipLaunchKernelGGL((interp_kernel<PPT>), dim3(xcd_blocks(chunks * nbox)), dim3(256), 0, s, pos,
-                     force, acc, np, n, inv_cell, chunks, chunks * nbox);
+  const dim3 grid(xcd_blocks(chunks * nbox));
+  if (lp)
+    hipLaunchKernelGGL((interp_kernel<PPT, true>), grid, dim3(256), 0, s, pos, force, acc, np, n,
+                       inv_cell, chunks, chunks * nbox, *lp);
+  else
+    hipLaunchKernelGGL((interp_kernel<PPT, false>), grid, dim3(256), 0, s, pos, force, acc, np,
+                       n, inv_cell, chunks, chunks * nbox, Leap());
   return hipGetLastError();
 }
 
 // mode 0: direct gather, `block` = particles per workgroup (256, 512 or 1024);
-// modes 1-3: LDS-staged boxes of 1024 / 2048 / 4096 particles.
+// modes 1-3: LDS-staged boxes of 1024 / 2048 / 4096 particles. lp (may be NULL): the
+// leapfrog applied with each acceleration.
 hipError_t launch_interp(const float* pos, const float* force, float* acc, int64_t np,
-                         int nbox, int n, double inv_cell, int mode, int block, hipStream_t s) {
+                         int nbox, int n, double inv_cell, int mode, int block, hipStream_t s,
+                         const Leap* lp) {
   switch (mode) {
-    case 1: return launch_interp_tiled<1024, 2560>(pos, force, acc, np, nbox, n, inv_cell, s);
-    case 2: return launch_interp_tiled<2048, 4608>(pos, force, acc, np, nbox, n, inv_cell, s);
-    case 3: return launch_interp_tiled<4096, 8192>(pos, force, acc, np, nbox, n, inv_cell, s);
+    case 1: return launch_interp_tiled<1024, 2560>(pos, force, acc, np, nbox, n, inv_cell, lp, s);
+    case 2: return launch_interp_tiled<2048, 4608>(pos, force, acc, np, nbox, n, inv_cell, lp, s);
+    case 3: return launch_interp_tiled<4096, 8192>(pos, force, acc, np, nbox, n, inv_cell, lp, s);
     default:
-      if (block >= 1024) return launch_interp_direct<4>(pos, force, acc, np, nbox, n, inv_cell, s);
-      if (block >= 512) return launch_interp_direct<2>(pos, force, acc, np, nbox, n, inv_cell, s);
-      return launch_interp_direct<1>(pos, force, acc, np, nbox, n, inv_cell, s);
+      if (block >= 1024)
+        return launch_interp_direct<4>(pos, force, acc, np, nbox, n, inv_cell, lp, s);
+      if (block >= 512)
+        return launch_interp_direct<2>(pos, force, acc, np, nbox, n, inv_cell, lp, s);
+      return launch_interp_direct<1>(pos, force, acc, np, nbox, n, inv_cell, lp, s);
   }
 }
 

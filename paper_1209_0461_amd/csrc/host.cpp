@@ -384,7 +384,7 @@ int do_response_mode(Ctx& c, double a_now, int mode) {
 
 namespace {
 
-int do_force(Ctx& c, const float* pos, float* acc, double a_now) {
+int do_force(Ctx& c, const float* pos, float* acc, double a_now, const Leap* lp = nullptr) {
   if (c.stage != 2) return set_error(PM_NU_ESTATE, "pm_nu_force needs pm_nu_response first");
   if (!c.modes_valid)
     return set_error(PM_NU_ESTATE, "pm_nu_force needs the modes of a deposit (the power was set)");
@@ -402,7 +402,7 @@ int do_force(Ctx& c, const float* pos, float* acc, double a_now) {
                                   c.stream));
   TIMED(c, ST_INTERP, launch_interp(pos, c.force, acc, c.Np, c.nbox, c.N,
                                     c.N / c.cfg.box_size, c.tune.interp_mode,
-                                    c.tune.interp_block, c.stream));
+                                    c.tune.interp_block, c.stream, lp));
   c.stage = 0;
   return PM_NU_OK;
 }
@@ -889,32 +889,41 @@ int pm_nu_advance(pm_nu_ctx* ctx, float* pos, float* vel, float* acc, const doub
                             c->nu_mult[b], c->nu_massless[b]);
   const float L = static_cast<float>(c->cfg.box_size);
   std::vector<double> kd(2 * static_cast<size_t>(c->nbox));
-  double a_mid_prev = a_steps[0];    // the first kick starts at a_steps[0]
-  for (int j = 0; j < n_steps; ++j) {
-    const double a0 = a_steps[j], a1 = a_steps[j + 1], am = std::sqrt(a0 * a1);
-    // the closing half kick of the previous step and the opening one of this step both
-    // use the force at a0: one kick over [a_mid_prev, am]
-    for (int b = 0; b < c->nbox; ++b) {
-      kd[2 * b] = a0 * kick_of(bg[b], a_mid_prev, am);
-      kd[2 * b + 1] = ds_of(bg[b], a0, a1);
-    }
-    int rc = upload_kd(*c, kd);
-    if (rc) return rc;
-    TIMED(*c, ST_KICK_DRIFT, launch_kick_drift(pos, vel, acc, c->d_kd, c->Np, c->nbox, L, true,
-                                               c->stream));
-    rc = pm_nu_step(ctx, pos, acc, a1);
-    if (rc) return rc;
-    a_mid_prev = am;
-  }
-  const double an = a_steps[n_steps];
+  auto a_mid = [&](int j) { return std::sqrt(a_steps[j] * a_steps[j + 1]); };
+  // opening half kick with the given force, and the first drift
   for (int b = 0; b < c->nbox; ++b) {
-    kd[2 * b] = an * kick_of(bg[b], a_mid_prev, an);
-    kd[2 * b + 1] = 0.0;
+    kd[2 * b] = a_steps[0] * kick_of(bg[b], a_steps[0], a_mid(0));
+    kd[2 * b + 1] = ds_of(bg[b], a_steps[0], a_steps[1]);
   }
   int rc = upload_kd(*c, kd);
   if (rc) return rc;
-  TIMED(*c, ST_KICK_DRIFT, launch_kick_drift(pos, vel, acc, c->d_kd, c->Np, c->nbox, L, false,
+  TIMED(*c, ST_KICK_DRIFT, launch_kick_drift(pos, vel, acc, c->d_kd, c->Np, c->nbox, L, true,
                                              c->stream));
+  for (int j = 0; j < n_steps; ++j) {
+    const double a1 = a_steps[j + 1];
+    rc = do_deposit(*c, pos);
+    if (rc) return rc;
+    rc = do_response_mode(*c, a1, c->cfg.response_mode);
+    if (rc) return rc;
+    // the interpolation applies the force at a1 at once: the closing half kick of this step
+    // with the opening one of the next and the next drift, or (last step) the closing half
+    // kick alone, storing the force
+    const bool last = j + 1 == n_steps;
+    for (int b = 0; b < c->nbox; ++b) {
+      kd[2 * b] = a1 * kick_of(bg[b], a_mid(j), last ? a1 : a_mid(j + 1));
+      kd[2 * b + 1] = last ? 0.0 : ds_of(bg[b], a1, a_steps[j + 2]);
+    }
+    rc = upload_kd(*c, kd);
+    if (rc) return rc;
+    Leap lp;
+    lp.vel = vel;
+    lp.pos = last ? nullptr : pos;
+    lp.kd = c->d_kd;
+    lp.box = L;
+    lp.store_acc = last ? 1 : 0;
+    rc = do_force(*c, pos, acc, a1, &lp);
+    if (rc) return rc;
+  }
   return PM_NU_OK;
 }
 

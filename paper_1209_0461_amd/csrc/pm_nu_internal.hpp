@@ -36,6 +36,25 @@ struct RespBox {
   int series;        // 1: exact series for I(x), 0: the fit eq. (fit)
 };
 
+// A coordinate moved back into [0, L) (exact: fmodf; x + L may round up to L, which wraps to 0).
+__device__ __forceinline__ float wrap_box(float x, float L) {
+  if (x >= 0.f && x < L) return x;
+  x = fmodf(x, L);
+  if (x < 0.f) x += L;
+  return x < L ? x : 0.f;
+}
+
+// What the interpolation does with each particle's acceleration: store it (a step), or also
+// apply the leapfrog of pm_nu_advance on the spot, u += K_b acc and, between steps,
+// x += D_b u wrapped into [0, L) (positions updated in place).
+struct Leap {
+  float* vel = nullptr;          // null: store the acceleration only
+  float* pos = nullptr;          // null: no drift
+  const double* kd = nullptr;    // [nbox][2] K_b, D_b
+  float box = 0.f;
+  int store_acc = 1;
+};
+
 // Launch shapes chosen by the autotuner (defaults are safe for every N).
 struct Tuning {
   int deposit_mode = 4;      // see launch_deposit
@@ -200,9 +219,11 @@ hipError_t launch_extract_component(const float* src, float* dst, int64_t n, int
 hipError_t launch_deposit(const float* pos, unsigned long long* rho, int64_t np, int nbox, int N,
                           double inv_cell, int* flags, int mode, int block, hipStream_t s);
 // mode 0: one thread per particle gathering from HBM; modes 1-3: chunks of 1024 / 2048 /
-// 4096 particles with their bounding-box tile of the acceleration grid staged in LDS
+// 4096 particles with their bounding-box tile of the acceleration grid staged in LDS; lp
+// (may be NULL) applies the leapfrog of pm_nu_advance with each acceleration
 hipError_t launch_interp(const float* pos, const float* force, float* acc, int64_t np,
-                         int nbox, int N, double inv_cell, int mode, int block, hipStream_t s);
+                         int nbox, int N, double inv_cell, int mode, int block, hipStream_t s,
+                         const Leap* lp = nullptr);
 // fft_kernels.hip
 // input: the fixed-point density rho, or (if delta is not NULL) delta in FP32; reset (may
 // be NULL) is cleared by the kernel when reading delta
