@@ -226,3 +226,12 @@ def test_hierarchy_species_initial_amplitudes_enter_with_their_weights():
     want = sum(m / 0.1 * kernel.I_fit(k * ds * bg.T_NU0 / m) * ics[i]
                for i, m in enumerate(masses)) * (1.0 - ds * 0.01 * theta)
     assert np.allclose(r["pnu_half"], want, rtol=1e-10)
+
+
+def test_response_at_the_first_node_is_the_initial_amplitude():
+    """At tau = tau_i eq. (P-final) has no interval to integrate and I(0) = 1."""
+    k = np.array([0.01, 0.3, 2.0])
+    init = np.array([0.7, 0.4, 0.05])
+    r = response.nu_amplitude(k, np.ones(3), np.ones(3), np.zeros(0), np.zeros((0, 3)),
+                              np.zeros(3), init, np.full(3, -3e-4), 0.02, 0.3, 0.3, 0.7, 8)
+    assert np.array_equal(r["pnu_half"], init)
