@@ -111,11 +111,12 @@ int pm_nu_deposit(pm_nu_ctx* ctx, const float* pos);
 
 /* Stage (iii) at scale factor a_now, which must not precede the last stored node.
  * Evaluates eq. (P-final) in FP64 by the trapezoid rule in ln a (Q steps per history
- * interval, P_M^{1/2} linear in ln a between nodes, dtau = dln a/(a H), flat matter +
- * Lambda H(a)), using P_nu(a_now) ~ P_nu(previous node) inside the integral for the
- * first iteration (Sec. 4.3 (iii), Appendix B). Writes P_nu^{1/2}, R_b and appends the
+ * interval, P_M^{1/2} linear in ln a between nodes, dtau = dln a/(a H), H(a) of
+ * pm_nu_set_background), using P_nu(a_now) ~ P_nu(previous node) inside the integral for
+ * the first iteration (Sec. 4.3 (iii), Appendix B). Writes P_nu^{1/2}, R_b and appends the
  * node a_now with P_M^{1/2} = (1-f_nu) P_cdm^{1/2} + f_nu P_nu^{1/2}; if a_now equals
- * the last stored node that node is recomputed from the ones before it instead. A box
+ * the last stored node that node is recomputed from the ones before it instead (when it is
+ * the only node, a_now = a_i and P_nu^{1/2} is the initial amplitude: the start of a run). A box
  * with m_nu_total = 0 has f_nu = 0: its P_nu^{1/2} and R read 0 and the step is plain CDM.
  * Needs pm_nu_deposit first. */
 int pm_nu_response(pm_nu_ctx* ctx, double a_now);

@@ -170,7 +170,8 @@ int nodes_for(const Ctx& c, int box, double a_now, std::vector<double>& nodes, i
   else if (a_now < ha.back())
     return set_error(PM_NU_EHISTORY, "a_now=%g precedes the last stored node %g of box %d",
                      a_now, ha.back(), box);
-  if (m < 1) return set_error(PM_NU_EHISTORY, "box %d: no stored node before a_now", box);
+  // m = 0: a_now is the first stored node, where eq. (P-final) reduces to the initial
+  // amplitude (no interval to integrate over)
   if (static_cast<int>(m) >= c.Jcap)
     return set_error(PM_NU_EHISTORY, "box %d: history full (%d nodes)", box, c.Jcap);
   nodes.assign(ha.begin(), ha.begin() + m);
@@ -239,7 +240,8 @@ int prepare_time_grid(Ctx& c, double a_now) {
       interval_nodes(bg, nd[jj], nd[jj + 1], Q, &cc.a[o], &cc.seg[o], &cc.hinv[o]);
     }
     cc.nodes.assign(nd.begin(), nd.begin() + n);
-    interval_nodes(bg, nd[n - 1], nd[n], Q, a_last.data(), seg_last.data(), hinv_last.data());
+    if (n > 0)
+      interval_nodes(bg, nd[n - 1], nd[n], Q, a_last.data(), seg_last.data(), hinv_last.data());
     const int q_last = (n - 1) * Q;   // first sub-node of the interval to a_now
     tw.assign(nq, 0.0);
     for (int jj = 0; jj < n; ++jj) {

@@ -457,7 +457,7 @@ __global__ __launch_bounds__(RT) void surrogate_finish_kernel(
     return;
   }
   const double ph = sqrt(pcdm_in[ob]);
-  const double pnu = exact_pnu(bx, kmean[b], ph, hpn[static_cast<size_t>(bx.n_cur - 1) * nbins + b],
+  const double pnu = exact_pnu(bx, kmean[b], ph, (bx.n_cur > 0 ? hpn[static_cast<size_t>(bx.n_cur - 1) * nbins + b] : 0.0),
                                ic_pnu + static_cast<size_t>(box) * kMaxSpecies * nbins,
                                ic_theta[ob], hpm, nbins, b,
                                tg_ds + static_cast<size_t>(box) * qcap,

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(RT) void response_kernel(
 
   // 2. history integral
   const double pnu = exact_pnu(bx, kmean[b], pcdm_half,
-                               hpn[static_cast<size_t>(bx.n_cur - 1) * nbins + b],
+                               (bx.n_cur > 0 ? hpn[static_cast<size_t>(bx.n_cur - 1) * nbins + b] : 0.0),
                                ic_pnu + static_cast<size_t>(box) * kMaxSpecies * nbins,
                                ic_theta[ob], hpm, nbins, b, tg_ds + static_cast<size_t>(box) * qcap,
                                tg_w + static_cast<size_t>(box) * qcap, q_sub, iterations, red);
