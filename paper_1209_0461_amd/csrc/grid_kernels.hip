@@ -458,34 +458,36 @@ struct Pieces {
 };
 __device__ __forceinline__ Pieces overlap(int p, int e, int cs, int cb, int n) {
   Pieces r;
-  r.cnt = 0;
   const int d2 = (p - cs + n) & (n - 1);        // cell-local index of the patch start
-  if (d2 < cb) {
-    r.pl[r.cnt] = 0;
-    r.cl[r.cnt] = d2;
-    r.len[r.cnt] = min(e, cb - d2);
-    ++r.cnt;
-  }
   const int w = n - d2;                         // patch-local index where it re-enters
-  if (d2 != 0 && w < e) {
-    r.pl[r.cnt] = w;
-    r.cl[r.cnt] = 0;
-    r.len[r.cnt] = min(e - w, cb);
-    ++r.cnt;
-  }
+  const bool first = d2 < cb;                   // [p, ...) starts inside the cell
+  const bool second = d2 != 0 && w < e;         // the patch wraps back into the cell
+  const int len_a = min(e, cb - d2), len_b = min(e - w, cb);
+  // fixed slots (no indexed writes, which would go to scratch)
+  r.cnt = static_cast<int>(first) + static_cast<int>(second);
+  r.pl[0] = first ? 0 : w;
+  r.cl[0] = first ? d2 : 0;
+  r.len[0] = first ? len_a : len_b;
+  r.pl[1] = w;
+  r.cl[1] = 0;
+  r.len[1] = len_b;
   return r;
 }
 
-// D2: one workgroup of 256 threads per (coarse cell, box), CB = 1 << cb_lg <= 16. Thread
-// (iy, iz) owns the column x = 0..CB-1 of the cell and keeps its sums in registers; for
-// each patch it issues the loads of the whole column at once (whether x lies in the patch
-// is the same for every thread, so that test is a scalar branch).
+// D2: one workgroup of 256 threads per (coarse cell, box), CB = 1 << cb_lg <= 16. A cell
+// is mostly covered by one patch (the chunk whose block it is) and touched by a few others
+// in thin layers (their halos). The largest overlap goes through registers: thread
+// (iy, iz) owns the column x = 0..CB-1 and loads it from that patch. The nodes of every
+// other overlap form one list over which all threads stride, adding into an LDS copy of the
+// cell with 64-bit LDS atomics. Every thread issues all of its loads (its column and up to
+// kBatch list items) before it uses any, so each workgroup waits on few load latencies.
+// The sums are exact integers.
 __global__ __launch_bounds__(256) void patch_reduce_kernel(
     const unsigned long long* __restrict__ patches, int pcap, const int4* __restrict__ hdr,
     const int* __restrict__ status, int* __restrict__ reg_count,
     const int* __restrict__ reg_list, unsigned long long* __restrict__ rho_fb,
     const int* __restrict__ n_fb, float* __restrict__ delta, int n, int cb_lg, double scale) {
-  constexpr int CBM = 16;
+  constexpr int CBM = 16, kBatch = 8;
   const int tid = threadIdx.x;
   const int cb = 1 << cb_lg, nc = n >> cb_lg;
   const int64_t cells = static_cast<int64_t>(nc) * nc * nc;
@@ -495,28 +497,72 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
             ccx = (blockIdx.x / (nc * nc)) << cb_lg;
   const int iy = tid >> cb_lg, iz = tid & (cb - 1);
   const bool on = tid < cb * cb;
+  const int vol_cell = cb * cb * cb;
+  __shared__ unsigned long long s_acc[CBM * CBM * CBM];   // [x][y][z] of the cell
+  __shared__ int4 s_hdr[kPatchList];
+  __shared__ int s_chunk[kPatchList];
+  __shared__ int s_off[kPatchList + 1];    // list offsets of the non-home overlaps
+  __shared__ int s_home;
+  for (int i = tid; i < vol_cell; i += 256) s_acc[i] = 0ull;
+  if (tid < 64) {
+    // wave 0: the cell's patches (list row and count fetched together), their headers,
+    // overlap volumes, the home patch and the offsets of the others in the item list
+    const int cnt_raw = reg_count[cell];
+    const int listed = tid < kPatchList ? reg_list[cell * kPatchList + tid] : 0;
+    const int cntr = min(cnt_raw, kPatchList);
+    int vol = -1;
+    int4 h = make_int4(0, 0, 0, 0);
+    int chunk = -1;
+    if (tid < cntr) {
+      h = hdr[listed];
+      chunk = status[listed] == 0 ? listed : -1;   // else added through the side grid
+      if (chunk >= 0) {
+        const int ex = h.w & 1023, ey = (h.w >> 10) & 1023, ez = h.w >> 20;
+        const Pieces px = overlap(h.x, ex, ccx, cb, n), py = overlap(h.y, ey, ccy, cb, n),
+                     pz = overlap(h.z, ez, ccz, cb, n);
+        int lx = 0, ly = 0, lz = 0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {           // constant bounds: no indexed scratch
+          lx += q < px.cnt ? px.len[q] : 0;
+          ly += q < py.cnt ? py.len[q] : 0;
+          lz += q < pz.cnt ? pz.len[q] : 0;
+        }
+        vol = lx * ly * lz;
+      }
+      s_hdr[tid] = h;
+      s_chunk[tid] = chunk;
+    }
+    // home: the largest volume, ties to the lowest index
+    int key = vol > 0 ? (vol << 6) | (63 - tid) : -1;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) key = max(key, __shfl_xor(key, off, 64));
+    const int home = key >= 0 ? 63 - (key & 63) : -1;
+    // exclusive prefix of the other overlaps' volumes
+    int w = (vol > 0 && tid != home) ? vol : 0;
+    int incl = w;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t = __shfl_up(incl, off, 64);
+      if (tid >= off) incl += t;
+    }
+    if (tid < kPatchList) s_off[tid] = incl - w;
+    if (tid == kPatchList - 1) s_off[kPatchList] = incl;
+    if (tid == 0) s_home = home;
+  }
+  __syncthreads();
+  const int home = s_home;
+  const int total = s_off[kPatchList];
+  // the home patch's column loads go out first
   unsigned long long acc[CBM];
 #pragma unroll
   for (int x = 0; x < CBM; ++x) acc[x] = 0ull;
-  // the cell's patch list, with each patch's status and header, fetched in parallel once
-  __shared__ int4 s_hdr[kPatchList];
-  __shared__ int s_chunk[kPatchList];
-  const int cntr = __builtin_amdgcn_readfirstlane(min(reg_count[cell], kPatchList));
-  if (tid < cntr) {
-    const int chunk = reg_list[cell * kPatchList + tid];
-    s_chunk[tid] = status[chunk] ? -1 : chunk;  // -1: added through the side grid instead
-    s_hdr[tid] = hdr[chunk];
-  }
-  __syncthreads();
-  for (int e = 0; e < cntr; ++e) {
-    const int chunk = __builtin_amdgcn_readfirstlane(s_chunk[e]);
-    if (chunk < 0) continue;
-    const int4 h = s_hdr[e];
+  if (home >= 0) {
+    const int chunk = s_chunk[home];
+    const int4 h = s_hdr[home];
     const int ex = h.w & 1023, ey = (h.w >> 10) & 1023, ez = h.w >> 20;
     const Pieces px = overlap(h.x, ex, ccx, cb, n), py = overlap(h.y, ey, ccy, cb, n),
                  pz = overlap(h.z, ez, ccz, cb, n);
-    // this thread's row (y, z) inside the patch, if any
-    int ly = -1, lz = -1;
+    int ly = -1, lz = -1;                       // this thread's row (y, z) inside the patch
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       if (q < py.cnt && iy >= py.cl[q] && iy < py.cl[q] + py.len[q]) ly = py.pl[q] + iy - py.cl[q];
@@ -526,7 +572,6 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
     const unsigned long long* row =
         patches + static_cast<int64_t>(chunk) * pcap + (lane_in ? ly * ez + lz : 0);
     const int xs = ey * ez;                     // patch stride along x
-    unsigned long long v[CBM];
 #pragma unroll
     for (int x = 0; x < CBM; ++x) {
       int lx = -1;                              // patch-local x of cell-local x (uniform)
@@ -534,11 +579,67 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
         if (px.cnt > 0 && x >= px.cl[0] && x < px.cl[0] + px.len[0]) lx = px.pl[0] + x - px.cl[0];
         if (px.cnt > 1 && x >= px.cl[1] && x < px.cl[1] + px.len[1]) lx = px.pl[1] + x - px.cl[1];
       }
-      v[x] = (lx >= 0 && lane_in) ? row[lx * xs] : 0ull;
+      acc[x] = (lx >= 0 && lane_in) ? row[lx * xs] : 0ull;
+    }
+  }
+  // the other overlaps: kBatch items per thread per round, all loads before the adds
+  for (int base = 0; base < total; base += kBatch * 256) {
+    unsigned long long v[kBatch];
+    int li[kBatch];
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r) {
+      const int i = base + r * 256 + tid;
+      li[r] = -1;
+      v[r] = 0ull;
+      if (i < total) {
+        int e = 0;                              // the patch: last offset <= i
+#pragma unroll
+        for (int step = kPatchList / 2; step > 0; step >>= 1)
+          if (s_off[e + step] <= i) e += step;
+        const int4 h = s_hdr[e];
+        const int ex = h.w & 1023, ey = (h.w >> 10) & 1023, ez = h.w >> 20;
+        const Pieces px = overlap(h.x, ex, ccx, cb, n), py = overlap(h.y, ey, ccy, cb, n),
+                     pz = overlap(h.z, ez, ccz, cb, n);
+        int rem = i - s_off[e];                 // index inside this patch's pieces
+        int ix = 0, iy2 = 0, iz2 = 0, cx = 0, cy = 0, cz = 0;
+        bool found = false;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              if (found || a >= px.cnt || b >= py.cnt || c >= pz.cnt) continue;
+              const int Lx = px.len[a], Ly = py.len[b], Lz = pz.len[c];
+              const int V = Lx * Ly * Lz;
+              if (rem >= V) {
+                rem -= V;
+                continue;
+              }
+              // exact: rem < 4096 and the divisors are at most 16
+              const int t = static_cast<int>((rem + 0.5f) * (1.0f / Lz));
+              const int z = rem - t * Lz;
+              const int x = static_cast<int>((t + 0.5f) * (1.0f / Ly));
+              const int y = t - x * Ly;
+              ix = px.pl[a] + x;
+              iy2 = py.pl[b] + y;
+              iz2 = pz.pl[c] + z;
+              cx = px.cl[a] + x;
+              cy = py.cl[b] + y;
+              cz = pz.cl[c] + z;
+              found = true;
+            }
+        if (found) {
+          v[r] = patches[static_cast<int64_t>(s_chunk[e]) * pcap + (ix * ey + iy2) * ez + iz2];
+          li[r] = (cx * cb + cy) * cb + cz;
+        }
+      }
     }
 #pragma unroll
-    for (int x = 0; x < CBM; ++x) acc[x] += v[x];
+    for (int r = 0; r < kBatch; ++r)
+      if (li[r] >= 0) atomicAdd(&s_acc[li[r]], v[r]);
   }
+  __syncthreads();
   const bool fold = *n_fb > 0;
   if (on) {
     const int64_t m = static_cast<int64_t>(n) * n * n;
@@ -547,7 +648,7 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
     for (int x = 0; x < CBM; ++x) {
       if (x >= cb) break;
       const int64_t node = col + static_cast<int64_t>(ccx + x) * n * n;
-      unsigned long long val = acc[x];
+      unsigned long long val = acc[x] + s_acc[(x * cb + iy) * cb + iz];
       if (fold) {
         val += rho_fb[node];
         rho_fb[node] = 0ull;
