@@ -209,7 +209,7 @@ def measure_variants(ctx, binding, pos, acc, a_now, stream, names, steps=20):
     return out
 
 
-def measure_loop(cfg, pos, masses, stream, n_steps=50, a_start=0.5):
+def measure_loop(cfg, pos, masses, stream, tuning, n_steps=50, a_start=0.5):
     """The loop of Sec. 4.3 through pm_nu_advance: n_steps kick-drift-kick steps from a_start
     to cfg["a_now"] after a stored history from cfg["a_lo"] to a_start, on a context of its
     own. Reports steps/s of the whole loop (host time grid and uploads included) and the
@@ -221,6 +221,8 @@ def measure_loop(cfg, pos, masses, stream, n_steps=50, a_start=0.5):
     J = cfg["n_hist"]
     ctx = PMNu(cfg["n_mesh"], pos.shape[1], cfg["box"], cfg["n_kbins"], J + n_steps + 2,
                list(masses), substeps=cfg["substeps"])
+    binding.pm_nu_set_launch(ctx.h, tuning["deposit_mode"], tuning["deposit_block"],
+                             tuning["interp_mode"], tuning["interp_block"])   # the step's shapes
     p = pos.clone()
     vel = torch.zeros_like(p)
     acc = torch.zeros_like(p)
@@ -384,7 +386,7 @@ def main():
             variants = measure_variants(ctx, binding, pos, acc, a_now, stream, names)
         loop = None
         if not args.no_loop and not args.graph:
-            loop = measure_loop(cfg, pos, masses, stream)
+            loop = measure_loop(cfg, pos, masses, stream, tuning)
 
     from paper_1209_0461_amd.binding import load_library  # noqa: F401
     n_partial = (n_mesh // min(16 if n_mesh <= 256 else 8, n_mesh)) * (n_mesh // 2 + 1)

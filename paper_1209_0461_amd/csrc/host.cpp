@@ -492,6 +492,8 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   c->n2max = 3 * c->N * c->N / 4;
   c->qcap = (c->Jcap - 1) * c->Q + 1;
   c->n_partial = fwd_x_partials(c->N);
+  // the patch deposit is the faster one once the mesh holds many coarse cells
+  c->tune.deposit_mode = c->N >= 64 ? 6 : 4;
   c->stream = static_cast<hipStream_t>(cfg->stream);
   c->m_nu.assign(m_nu_total, m_nu_total + c->nbox);
   for (int b = 0; b < c->nbox; ++b) {

@@ -502,8 +502,9 @@ def test_kernel_flag_is_checked():
     ctx.close()
 
 
-@pytest.mark.parametrize("masses,relativistic", [((0.3,), False), ((0.1, 0.6), True)])
-def test_advance_matches_oracle(masses, relativistic):
+@pytest.mark.parametrize("masses,relativistic,deposit_mode",
+                         [((0.3,), False, 4), ((0.3,), False, 6), ((0.1, 0.6), True, 6)])
+def test_advance_matches_oracle(masses, relativistic, deposit_mode):
     """Several kick-drift-kick steps through the C ABI (positions, velocities, forces and the
     history rows each step stores) against the oracle's loop, per box."""
     import torch
@@ -517,6 +518,7 @@ def test_advance_matches_oracle(masses, relativistic):
     pos = np.stack([p for p, _ in ics])
     vel = np.stack([v for _, v in ics])
     ctx = PMNu(nm, pos.shape[1], box, nb, 20, list(masses))
+    binding.pm_nu_set_launch(ctx.h, deposit_mode, 256, 1, 256)
     binding.pm_nu_set_background(ctx.h, relativistic)
     refs = []
     for b in range(nbox):
