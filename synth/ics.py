@@ -115,20 +115,77 @@ def zeldovich_lattice(n_side, box, sigma_cells, seed, spectral_index=-2.0, order
     return np.ascontiguousarray(pos)
 
 
+def second_order_displacement(psi1, box):
+    """The second-order Lagrangian displacement of a first-order one on an n^3 lattice.
+
+    psi1 (n, n, n, 3): the first-order displacement in length units, psi1 = -grad phi1.
+    Second-order Lagrangian perturbation theory (Scoccimarro 1998) adds psi2 = D2 grad phi2
+    with lap phi2 = sum_{i<j} (phi1_ii phi1_jj - phi1_ij^2) and D2 = -(3/7) D1^2 (the
+    matter-era value); in terms of psi1 (already multiplied by D1) this is
+    psi2 = -(3/7) grad phi2[phi1]. Derivatives are spectral; returns psi2 (n, n, n, 3).
+    """
+    n = psi1.shape[0]
+    k1 = 2 * np.pi / box * np.fft.fftfreq(n, d=1.0 / n)
+    kz = 2 * np.pi / box * np.arange(n // 2 + 1, dtype=np.float64)
+    kv = (k1[:, None, None], k1[None, :, None], kz[None, None, :])
+    pk = [np.fft.rfftn(psi1[..., i]) for i in range(3)]
+
+    def deriv(i, j):                          # d psi1_i / d q_j = -phi1_ij
+        return np.fft.irfftn(1j * kv[j] * pk[i], s=(n, n, n), axes=(0, 1, 2))
+
+    m = {(i, j): deriv(i, j) for i in range(3) for j in range(i, 3)}
+    src = (m[0, 0] * m[1, 1] - m[0, 1] ** 2 + m[0, 0] * m[2, 2] - m[0, 2] ** 2
+           + m[1, 1] * m[2, 2] - m[1, 2] ** 2)
+    del m, pk
+    k2 = kv[0] ** 2 + kv[1] ** 2 + kv[2] ** 2
+    inv_k2 = np.zeros_like(k2)
+    inv_k2[k2 > 0] = 1.0 / k2[k2 > 0]
+    phi2_k = -np.fft.rfftn(src) * inv_k2      # lap phi2 = src
+    psi2 = np.empty_like(psi1)
+    for i in range(3):
+        psi2[..., i] = -(3.0 / 7.0) * np.fft.irfftn(1j * kv[i] * phi2_k, s=(n, n, n),
+                                                     axes=(0, 1, 2))
+    return psi2
+
+
 def zeldovich_ics(n_side, box, sigma_cells, seed, a, omega_m=0.3, spectral_index=-2.0,
-                  order="morton"):
+                  order="morton", second_order=False):
     """Positions and growing-mode velocities at scale factor a, both FP32 (n_side**3, 3).
 
     The lattice is displaced by psi (RMS sigma_cells cells); in the Zel'dovich growing mode
     x = q + (D/D(a)) psi, so the velocity in superconformal time s (ds = dt/a^2) is
     u = dx/ds = a^2 dx/dt = a^2 H(a) f(a) psi, with H and f = dln D/dln a of a flat
-    matter + Lambda background.
+    matter + Lambda background. With second_order the second-order displacement psi2
+    (second_order_displacement, scaled by Omega_M(a)^(-1/143)) is added, moving with
+    f2 = 2 Omega_M(a)^(6/11): u = a^2 H (f psi + f2 psi2).
     """
     from .history import growth, hubble_rate
     pos, disp = zeldovich_lattice(n_side, box, sigma_cells, seed, spectral_index, order,
                                   return_displacement=True)
     _, f = growth(np.array([a]), omega_m)
-    vel = (a * a * hubble_rate(a, omega_m) * f[0]) * disp
+    ah = a * a * hubble_rate(a, omega_m)
+    vel = (ah * f[0]) * disp
+    if second_order:
+        n = int(n_side)
+        codes = morton_codes(n).astype(np.int64) if order == "morton" else None
+        psi1 = disp if codes is None else disp[codes]              # back to C order
+        psi2 = second_order_displacement(psi1.reshape(n, n, n, 3), box).reshape(-1, 3)
+        om_a = omega_m / (omega_m + (1.0 - omega_m) * a ** 3)
+        psi2 *= om_a ** (-1.0 / 143.0)
+        grid = (np.arange(n, dtype=np.float64) + 0.5) * (box / n)
+        q = np.stack(np.meshgrid(grid, grid, grid, indexing="ij"), -1).reshape(-1, 3)
+        x = np.mod(q + psi1 + psi2, box).astype(np.float32)
+        x[x >= np.float32(box)] = np.float32(0.0)                  # FP32 round-up wraps to 0
+        v2 = (ah * 2.0 * om_a ** (6.0 / 11.0)) * psi2
+        if codes is not None:
+            pos = np.empty_like(x)
+            pos[codes] = x
+            tmp = np.empty_like(v2)
+            tmp[codes] = v2
+            v2 = tmp
+        else:
+            pos = x
+        vel = vel + v2
     return pos, np.ascontiguousarray(vel.astype(np.float32))
 
 
