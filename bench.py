@@ -84,7 +84,7 @@ def kernel_name(stage, tuning, n_mesh):
     """Name (with template arguments) of the kernel a stage launches, as rocprofv3 lists it."""
     dep = {1: "<1024, 3328, 256>", 2: "<2048, 5120, 256>", 3: "<4096, 9216, 256>",
            4: "<4096, 9216, 512>", 5: "<8192, 18432, 1024>"}
-    itp = {1: "<1024, 2560, false>", 2: "<2048, 4608, false>", 3: "<4096, 8192, false>"}
+    itp = {1: "<1024, 2048, false>", 2: "<2048, 4608, false>", 3: "<4096, 8192, false>"}
     if stage == "cic_deposit":
         m = tuning["deposit_mode"]
         if m == 6:

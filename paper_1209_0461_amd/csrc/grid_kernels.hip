@@ -1046,13 +1046,14 @@ hipError_t launch_interp_direct(const float* pos, const float* force, float* acc
 }
 
 // mode 0: direct gather, `block` = particles per workgroup (256, 512 or 1024);
-// modes 1-3: LDS-staged boxes of 1024 / 2048 / 4096 particles. lp (may be NULL): the
-// leapfrog applied with each acceleration.
+// modes 1-3: LDS-staged boxes of 1024 / 2048 / 4096 particles (mode 1's tile of 2048 nodes,
+// 24 KB, leaves room for six workgroups per CU). lp (may be NULL): the leapfrog applied
+// with each acceleration.
 hipError_t launch_interp(const float* pos, const float* force, float* acc, int64_t np,
                          int nbox, int n, double inv_cell, int mode, int block, hipStream_t s,
                          const Leap* lp) {
   switch (mode) {
-    case 1: return launch_interp_tiled<1024, 2560>(pos, force, acc, np, nbox, n, inv_cell, lp, s);
+    case 1: return launch_interp_tiled<1024, 2048>(pos, force, acc, np, nbox, n, inv_cell, lp, s);
     case 2: return launch_interp_tiled<2048, 4608>(pos, force, acc, np, nbox, n, inv_cell, lp, s);
     case 3: return launch_interp_tiled<4096, 8192>(pos, force, acc, np, nbox, n, inv_cell, lp, s);
     default:
