@@ -43,12 +43,12 @@ KERNEL_SOURCES = {
 def stage_bytes(n_mesh, n_part, nbox, nbins, n_hist, n_partial, deposit_mode=0):
     """Algorithmic bytes per launch of every kernel: each input read once, each output
     written once (FP32 grids, complex64 modes, FP32 positions/accelerations). The patch
-    deposit (mode 6) splits the deposit into reading the positions (cic_deposit) and
+    deposit (modes 6, 7) splits the deposit into reading the positions (cic_deposit) and
     writing the density contrast (patch_reduce)."""
     m = n_mesh ** 3 * nbox
     mh = n_mesh * n_mesh * (n_mesh // 2 + 1) * nbox
     npt = n_part * nbox
-    patch = deposit_mode == 6
+    patch = deposit_mode >= 6
     return {
         "zero_mesh": 4 * m,
         "cic_deposit": 12 * npt + (0 if patch else 4 * m),
@@ -87,8 +87,8 @@ def kernel_name(stage, tuning, n_mesh):
     itp = {1: "<1024, 2048, false>", 2: "<2048, 4608, false>", 3: "<4096, 8192, false>"}
     if stage == "cic_deposit":
         m = tuning["deposit_mode"]
-        if m == 6:
-            return "deposit_patch_kernel<4096, 9216, 512>"
+        if m >= 6:
+            return "deposit_patch_kernel<4096, %d, 512>" % (6144 if m == 6 else 9216)
         return "deposit_tiled_kernel" + dep[m] if m else "deposit_kernel"
     if stage == "cic_interp":
         m = tuning["interp_mode"]
@@ -103,7 +103,7 @@ def kernel_name(stage, tuning, n_mesh):
            "fft_fwd_x_bin": "fwd_x_bin_kernel", "inv_x_green": "inv_x_kernel",
            "fft_inv_y": "inv_y_kernel", "fft_inv_z": "inv_z_kernel"}
     if stage == "fft_fwd_z":
-        return "fwd_z_kernel<%d, %s>" % (n_mesh, "true" if tuning["deposit_mode"] == 6 else "false")
+        return "fwd_z_kernel<%d, %s>" % (n_mesh, "true" if tuning["deposit_mode"] >= 6 else "false")
     return "%s<%d>" % (fft[stage], n_mesh)
 
 

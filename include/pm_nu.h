@@ -202,8 +202,9 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
 /* Set the launch shapes directly: deposit_mode 0 (one thread per particle, global atomics;
  * deposit_block = threads per workgroup), 1..5 (LDS-privatised chunks of 1024/2048/4096
  * particles on 256 threads, 4096 on 512 threads, 8192 on 1024 threads, flushed with global
- * atomics) or 6 (chunks of 4096 written to per-chunk patches and summed per 16^3 coarse
- * cell without atomics; chunks that do not fit use atomics on a side grid), interp_mode
+ * atomics), 6 (chunks of 4096 written to per-chunk patches and summed per 16^3 coarse
+ * cell without atomics; chunks whose box exceeds 6144 nodes use atomics on a side grid) or
+ * 7 (as 6 with room for boxes of 9216 nodes, at lower occupancy), interp_mode
  * 0 (direct gather; interp_block = particles per workgroup, rounded down to 256, 512 or
  * 1024) or 1/2/3 (LDS-staged chunks). Blocks: multiples of 64 in 64..1024. Until this or
  * pm_nu_autotune is called: deposit_mode 6 for N >= 64 (4 below, where one coarse cell

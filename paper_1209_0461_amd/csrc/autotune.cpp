@@ -52,7 +52,7 @@ bool read_cache(const char* path, const std::string& key, Tuning& t) {
     const int d = json_int(line, "deposit_block", -1);
     const int im = json_int(line, "interp_mode", -1);
     const int i = json_int(line, "interp_block", -1);
-    if (m >= 0 && m <= 6 && d >= 64 && d <= 1024 && im >= 0 && im <= 3 && i >= 64 && i <= 1024) {
+    if (m >= 0 && m <= 7 && d >= 64 && d <= 1024 && im >= 0 && im <= 3 && i >= 64 && i <= 1024) {
       t.deposit_mode = m;
       t.deposit_block = d;
       t.interp_mode = im;
@@ -94,7 +94,8 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
   const bool was_timing = c->timer.enabled;
   c->timer.enabled = false;
   struct DepCand { int mode, block; };
-  const DepCand dep[] = {{0, 256}, {1, 256}, {2, 256}, {3, 256}, {4, 256}, {5, 256}, {6, 256}};
+  const DepCand dep[] = {{0, 256}, {1, 256}, {2, 256}, {3, 256}, {4, 256}, {5, 256}, {6, 256},
+                         {7, 256}};
   const DepCand itp[] = {{0, 256}, {0, 512}, {0, 1024}, {1, 256}, {2, 256}, {3, 256}};
   hipEvent_t e0, e1;
   PMNU_HIP(hipEventCreate(&e0));
@@ -169,7 +170,7 @@ int pm_nu_set_launch(pm_nu_ctx* ctx, int deposit_mode, int deposit_block, int in
   if (!c) return set_error(PM_NU_EINVAL, "ctx is NULL");
   drop_graph(*c);   // a captured step keeps its launch shapes
   auto block_ok = [](int b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
-  if (deposit_mode < 0 || deposit_mode > 6 || interp_mode < 0 || interp_mode > 3 ||
+  if (deposit_mode < 0 || deposit_mode > 7 || interp_mode < 0 || interp_mode > 3 ||
       !block_ok(deposit_block) || !block_ok(interp_block))
     return set_error(PM_NU_EINVAL, "bad launch shape");
   c->tune.deposit_mode = deposit_mode;

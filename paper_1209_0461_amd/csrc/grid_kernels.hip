@@ -415,7 +415,7 @@ __global__ __launch_bounds__(NT) void deposit_patch_kernel(
     }
     __syncthreads();
     if (s_fail == 0) {
-      unsigned long long* pat = patches + chunk * CAP;
+      unsigned long long* pat = patches + chunk * kPatchCap;   // stored patch stride
       for_box_nodes<NT>(ex, ey, ez, [&](int tx, int ty, int tz, int li) {
         pat[li] = tile[(tx * sy + ty) * sz + tz];
       });
@@ -985,12 +985,18 @@ int64_t patch_chunks(int64_t np) { return (np + kPatchCH - 1) / kPatchCH; }
 hipError_t launch_deposit_patch(const float* pos, unsigned long long* patches, int4* hdr,
                                 int* status, int* reg_count, int* reg_list,
                                 unsigned long long* rho_fb, int* n_fb, int64_t np, int nbox,
-                                int n, double inv_cell, int* flags, hipStream_t s) {
+                                int n, double inv_cell, int* flags, bool big_tile,
+                                hipStream_t s) {
   const int64_t chunks = patch_chunks(np);
-  hipLaunchKernelGGL((deposit_patch_kernel<kPatchCH, kPatchCap, kPatchNT>),
-                     dim3(static_cast<unsigned>(chunks * nbox)), dim3(kPatchNT), 0, s, pos,
-                     patches, hdr, status, reg_count, reg_list, rho_fb, n_fb, np, n, inv_cell,
-                     flags, chunks, patch_cb_log2(n));
+  const dim3 grid(static_cast<unsigned>(chunks * nbox));
+  if (big_tile)
+    hipLaunchKernelGGL((deposit_patch_kernel<kPatchCH, kPatchCap, kPatchNT>), grid,
+                       dim3(kPatchNT), 0, s, pos, patches, hdr, status, reg_count, reg_list,
+                       rho_fb, n_fb, np, n, inv_cell, flags, chunks, patch_cb_log2(n));
+  else
+    hipLaunchKernelGGL((deposit_patch_kernel<kPatchCH, kPatchTile, kPatchNT>), grid,
+                       dim3(kPatchNT), 0, s, pos, patches, hdr, status, reg_count, reg_list,
+                       rho_fb, n_fb, np, n, inv_cell, flags, chunks, patch_cb_log2(n));
   return hipGetLastError();
 }
 

@@ -313,11 +313,11 @@ int do_deposit(Ctx& c, const float* pos) {
   const int64_t cells = c.M * c.nbox;
   const double inv_cell = c.N / c.cfg.box_size;
   const double scale = static_cast<double>(c.M) / static_cast<double>(c.Np) / kFixScale;
-  if (c.tune.deposit_mode == 6) {
+  if (c.tune.deposit_mode >= 6) {
     TIMED(c, ST_DEPOSIT,
           launch_deposit_patch(pos, c.patches, c.patch_hdr, c.patch_status, c.reg_count,
                                c.reg_list, c.rho_fb, c.n_fb, c.Np, c.nbox, c.N, inv_cell,
-                               c.d_flags, c.stream));
+                               c.d_flags, c.tune.deposit_mode == 7, c.stream));
     TIMED(c, ST_PATCH_REDUCE,
           launch_patch_reduce(c.patches, c.patch_hdr, c.patch_status, c.reg_count, c.reg_list,
                               c.rho_fb, c.n_fb, c.delta, c.nbox, c.N, scale, c.stream));

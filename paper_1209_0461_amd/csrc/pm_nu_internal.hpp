@@ -139,7 +139,7 @@ struct Ctx {
   float2* tw = nullptr;            // [N] exp(-2 pi i m/N)
   float* inv_w2 = nullptr;         // [N] 1/sinc^4(pi n/N) per axis index (or 1)
   int* d_flags = nullptr;          // [1] bit 0: non-finite position seen
-  // patch deposit (deposit mode 6)
+  // patch deposit (deposit modes 6 and 7)
   unsigned long long* patches = nullptr;   // [chunks][kPatchCap] per-chunk tiles
   int4* patch_hdr = nullptr;       // [chunks] box origin and packed extents
   int* patch_status = nullptr;     // [chunks] 0 patched, 1 through the side grid
@@ -147,14 +147,14 @@ struct Ctx {
   int* reg_list = nullptr;         // [nbox][coarse cells][32] chunk ids
   unsigned long long* rho_fb = nullptr;    // [nbox][M] side grid, kept at zero
   int* n_fb = nullptr;             // [1] chunks that used the side grid this deposit
-  float* delta = nullptr;          // [nbox][M] delta in FP32 (mode 6)
+  float* delta = nullptr;          // [nbox][M] delta in FP32 (modes 6, 7)
   double* d_kd = nullptr;          // [nbox][2] kick and drift factors of the leapfrog
   // pinned staging of the host-built arrays (copied in stream order) and the last copies
   double* h_tg = nullptr;          // ds [nbox][qcap], then w [nbox][qcap]
   RespBox* h_resp = nullptr;       // [nbox]
   double* h_kd = nullptr;          // [nbox][2]
   hipEvent_t ev_tg = nullptr, ev_kd = nullptr;
-  bool density_is_delta = false;   // the last deposit wrote delta (mode 6), not rho
+  bool density_is_delta = false;   // the last deposit wrote delta (modes 6, 7), not rho
 
   // host state
   std::vector<std::vector<double>> hist_a;   // committed node scale factors per box
@@ -207,7 +207,10 @@ constexpr double kFixScale = 1099511627776.0;   // 2^40: fixed-point unit of the
 constexpr int kMaxBins = 1024;                   // largest n_kbins
 // patch deposit (deposit mode 6): chunk of particles, LDS tile / patch capacity in nodes,
 // threads per workgroup
-constexpr int kPatchCH = 4096, kPatchCap = 9216, kPatchNT = 512;
+// patch deposit: chunks of kPatchCH particles on kPatchNT threads; the LDS tile holds
+// kPatchTile nodes (mode 6, three workgroups per CU) or kPatchCap (mode 7, room for larger
+// boxes); a stored patch has room for kPatchCap nodes
+constexpr int kPatchCH = 4096, kPatchCap = 9216, kPatchTile = 6144, kPatchNT = 512;
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
 hipError_t launch_fixed_to_float(const unsigned long long* src, float* dst, int64_t n,
                                  hipStream_t s);
@@ -215,7 +218,7 @@ hipError_t launch_extract_component(const float* src, float* dst, int64_t n, int
                                    hipStream_t s);
 // mode 0: one thread per particle, 8 global atomics each; modes 1-3: LDS-privatised
 // chunks of 1024 / 2048 / 4096 particles (global atomics for chunks that do not fit)
-// modes 0-5 (mode 6 is the patch deposit, launched by launch_deposit_patch)
+// modes 0-5 (modes 6 and 7 are the patch deposit, launched by launch_deposit_patch)
 hipError_t launch_deposit(const float* pos, unsigned long long* rho, int64_t np, int nbox, int N,
                           double inv_cell, int* flags, int mode, int block, hipStream_t s);
 // mode 0: one thread per particle gathering from HBM; modes 1-3: chunks of 1024 / 2048 /
@@ -277,10 +280,12 @@ hipError_t launch_surrogate_dataset(const RespBox* boxes, const double* pcdm, co
 int patch_cb_log2(int n);
 int64_t patch_coarse_cells(int n);
 int64_t patch_chunks(int64_t np);
+// big_tile: the kPatchCap-node LDS tile (mode 7) instead of kPatchTile (mode 6)
 hipError_t launch_deposit_patch(const float* pos, unsigned long long* patches, int4* hdr,
                                 int* status, int* reg_count, int* reg_list,
                                 unsigned long long* rho_fb, int* n_fb, int64_t np, int nbox,
-                                int n, double inv_cell, int* flags, hipStream_t s);
+                                int n, double inv_cell, int* flags, bool big_tile,
+                                hipStream_t s);
 hipError_t launch_patch_reduce(const unsigned long long* patches, const int4* hdr,
                                const int* status, int* reg_count, const int* reg_list,
                                unsigned long long* rho_fb, const int* n_fb, float* delta,

@@ -67,4 +67,7 @@ def test_traffic_table_from_counter_csvs(tmp_path):
     assert bench.kernel_name("fft_inv_z", {}, 512) == "inv_z_kernel<512>"
     assert bench.kernel_name("fft_fwd_z", {"deposit_mode": 6}, 256) == "fwd_z_kernel<256, true>"
     assert bench.kernel_name("cic_deposit", {"deposit_mode": 6}, 256) == \
+        "deposit_patch_kernel<4096, 6144, 512>"
+    assert bench.kernel_name("cic_deposit", {"deposit_mode": 7}, 256) == \
         "deposit_patch_kernel<4096, 9216, 512>"
+    assert bench.kernel_name("fft_fwd_z", {"deposit_mode": 7}, 256) == "fwd_z_kernel<256, true>"

@@ -245,7 +245,7 @@ def test_every_launch_mode_matches_oracle(order):
     p = torch.from_numpy(pos).cuda()
     acc = torch.zeros_like(p)
     for dm, im, ib in ((0, 0, 256), (1, 1, 256), (2, 2, 256), (3, 3, 256), (1, 0, 512),
-                       (0, 2, 256), (4, 0, 1024), (5, 1, 256), (6, 1, 256), (6, 0, 256)):
+                       (0, 2, 256), (4, 0, 1024), (5, 1, 256), (6, 1, 256), (6, 0, 256), (7, 1, 256)):
         binding.pm_nu_set_launch(ctx.h, dm, 256, im, ib)
         ctx.step(p, acc, 0.7)
         torch.cuda.synchronize()
