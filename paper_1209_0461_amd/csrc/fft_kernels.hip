@@ -59,7 +59,8 @@ template <int N, bool DELTA>
 __global__ __launch_bounds__(NT) void fwd_z_kernel(const void* __restrict__ in,
                                                    float2* __restrict__ out,
                                                    const float2* __restrict__ twg,
-                                                   double scale, int* __restrict__ reset) {
+                                                   double scale, int* __restrict__ reset,
+                                                   int* __restrict__ clear, int n_clear) {
   constexpr int TY = Shape<N>::FZ_TY, NL = TY / 2, ES = NL + 1, NK = Shape<N>::NK;
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
@@ -70,6 +71,11 @@ __global__ __launch_bounds__(NT) void fwd_z_kernel(const void* __restrict__ in,
   if constexpr (DELTA) {
     if (reset && threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0)
       *reset = 0;
+    // the patch registry's counts, read for the last time by the reduce before this kernel
+    const int64_t gid =
+        ((static_cast<int64_t>(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) *
+            NT + threadIdx.x;
+    if (clear && gid < n_clear) clear[gid] = 0;
     const float4* src = reinterpret_cast<const float4*>(static_cast<const float*>(in) + off);
     constexpr int IT = (TY * N / 4 + NT - 1) / NT;
     float4 v[IT];
@@ -465,14 +471,17 @@ hipError_t dispatch_n(int n, A... args) {
 
 template <int N> struct FwdZ {
   static hipError_t run(const unsigned long long* rho, const float* delta, int* reset,
-                        float2* out, const float2* tw, double scale, int nbox, hipStream_t s) {
+                        int* clear, int n_clear, float2* out, const float2* tw, double scale,
+                        int nbox, hipStream_t s) {
     dim3 grid(N / Shape<N>::FZ_TY, N, nbox);
+    if (static_cast<int64_t>(grid.x) * grid.y * grid.z * NT < n_clear)
+      return hipErrorInvalidValue;                 // every count needs a thread to clear it
     if (delta)
       hipLaunchKernelGGL((fwd_z_kernel<N, true>), grid, dim3(NT), 0, s, delta, out, tw, scale,
-                         reset);
+                         reset, clear, n_clear);
     else
       hipLaunchKernelGGL((fwd_z_kernel<N, false>), grid, dim3(NT), 0, s, rho, out, tw, scale,
-                         reset);
+                         reset, clear, n_clear);
     return hipGetLastError();
   }
 };
@@ -543,8 +552,9 @@ template <int N> struct Partials {
 }  // namespace
 
 hipError_t launch_fwd_z(int n, const unsigned long long* rho, const float* delta, int* reset,
-                        float2* out, const float2* tw, double scale, int nbox, hipStream_t s) {
-  return dispatch_n<FwdZ>(n, rho, delta, reset, out, tw, scale, nbox, s);
+                        int* clear, int n_clear, float2* out, const float2* tw, double scale,
+                        int nbox, hipStream_t s) {
+  return dispatch_n<FwdZ>(n, rho, delta, reset, clear, n_clear, out, tw, scale, nbox, s);
 }
 hipError_t launch_fwd_y(int n, const float2* in, float2* out, const float2* tw, int nbox,
                         hipStream_t s) {

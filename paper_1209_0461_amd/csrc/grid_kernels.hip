@@ -474,31 +474,36 @@ __device__ __forceinline__ Pieces overlap(int p, int e, int cs, int cb, int n) {
   return r;
 }
 
-// D2: one workgroup of 256 threads per (coarse cell, box), CB = 1 << cb_lg <= 16. A cell
+// D2: one workgroup of 256 threads per (slab of XD x-planes of a coarse cell, box), CB =
+// 1 << cb_lg <= 16, XD <= CB (halving the slab halves the LDS copy and doubles the
+// workgroups, which hides more of the load latency). A cell
 // is mostly covered by one patch (the chunk whose block it is) and touched by a few others
 // in thin layers (their halos). The largest overlap goes through registers: thread
-// (iy, iz) owns the column x = 0..CB-1 and loads it from that patch. The nodes of every
+// (iy, iz) owns the slab's column x = 0..XD-1 and loads it from that patch. The nodes of every
 // other overlap form one list over which all threads stride, adding into an LDS copy of the
 // cell with 64-bit LDS atomics. Every thread issues all of its loads (its column and up to
 // kBatch list items) before it uses any, so each workgroup waits on few load latencies.
 // The sums are exact integers.
+template <int XD>
 __global__ __launch_bounds__(256) void patch_reduce_kernel(
     const unsigned long long* __restrict__ patches, int pcap, const int4* __restrict__ hdr,
-    const int* __restrict__ status, int* __restrict__ reg_count,
+    const int* __restrict__ status, const int* __restrict__ reg_count,
     const int* __restrict__ reg_list, unsigned long long* __restrict__ rho_fb,
     const int* __restrict__ n_fb, float* __restrict__ delta, int n, int cb_lg, double scale) {
   constexpr int CBM = 16, kBatch = 8;
   const int tid = threadIdx.x;
   const int cb = 1 << cb_lg, nc = n >> cb_lg;
+  const int slabs = cb / XD;
   const int64_t cells = static_cast<int64_t>(nc) * nc * nc;
   const int64_t box = blockIdx.y;
-  const int64_t cell = box * cells + blockIdx.x;
-  const int ccz = (blockIdx.x % nc) << cb_lg, ccy = ((blockIdx.x / nc) % nc) << cb_lg,
-            ccx = (blockIdx.x / (nc * nc)) << cb_lg;
+  const int cix = blockIdx.x / slabs;
+  const int64_t cell = box * cells + cix;
+  const int ccz = (cix % nc) << cb_lg, ccy = ((cix / nc) % nc) << cb_lg,
+            ccx = ((cix / (nc * nc)) << cb_lg) + (blockIdx.x - cix * slabs) * XD;  // slab's x0
   const int iy = tid >> cb_lg, iz = tid & (cb - 1);
   const bool on = tid < cb * cb;
-  const int vol_cell = cb * cb * cb;
-  __shared__ unsigned long long s_acc[CBM * CBM * CBM];   // [x][y][z] of the cell
+  const int vol_cell = XD * cb * cb;
+  __shared__ unsigned long long s_acc[XD * CBM * CBM];    // [x][y][z] of the slab
   __shared__ int4 s_hdr[kPatchList];
   __shared__ int s_chunk[kPatchList];
   __shared__ int s_off[kPatchList + 1];    // list offsets of the non-home overlaps
@@ -518,7 +523,7 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
       chunk = status[listed] == 0 ? listed : -1;   // else added through the side grid
       if (chunk >= 0) {
         const int ex = h.w & 1023, ey = (h.w >> 10) & 1023, ez = h.w >> 20;
-        const Pieces px = overlap(h.x, ex, ccx, cb, n), py = overlap(h.y, ey, ccy, cb, n),
+        const Pieces px = overlap(h.x, ex, ccx, XD, n), py = overlap(h.y, ey, ccy, cb, n),
                      pz = overlap(h.z, ez, ccz, cb, n);
         int lx = 0, ly = 0, lz = 0;
 #pragma unroll
@@ -553,14 +558,14 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
   const int home = s_home;
   const int total = s_off[kPatchList];
   // the home patch's column loads go out first
-  unsigned long long acc[CBM];
+  unsigned long long acc[XD];
 #pragma unroll
-  for (int x = 0; x < CBM; ++x) acc[x] = 0ull;
+  for (int x = 0; x < XD; ++x) acc[x] = 0ull;
   if (home >= 0) {
     const int chunk = s_chunk[home];
     const int4 h = s_hdr[home];
     const int ex = h.w & 1023, ey = (h.w >> 10) & 1023, ez = h.w >> 20;
-    const Pieces px = overlap(h.x, ex, ccx, cb, n), py = overlap(h.y, ey, ccy, cb, n),
+    const Pieces px = overlap(h.x, ex, ccx, XD, n), py = overlap(h.y, ey, ccy, cb, n),
                  pz = overlap(h.z, ez, ccz, cb, n);
     int ly = -1, lz = -1;                       // this thread's row (y, z) inside the patch
 #pragma unroll
@@ -573,12 +578,10 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
         patches + static_cast<int64_t>(chunk) * pcap + (lane_in ? ly * ez + lz : 0);
     const int xs = ey * ez;                     // patch stride along x
 #pragma unroll
-    for (int x = 0; x < CBM; ++x) {
-      int lx = -1;                              // patch-local x of cell-local x (uniform)
-      if (x < cb) {
-        if (px.cnt > 0 && x >= px.cl[0] && x < px.cl[0] + px.len[0]) lx = px.pl[0] + x - px.cl[0];
-        if (px.cnt > 1 && x >= px.cl[1] && x < px.cl[1] + px.len[1]) lx = px.pl[1] + x - px.cl[1];
-      }
+    for (int x = 0; x < XD; ++x) {
+      int lx = -1;                              // patch-local x of slab-local x (uniform)
+      if (px.cnt > 0 && x >= px.cl[0] && x < px.cl[0] + px.len[0]) lx = px.pl[0] + x - px.cl[0];
+      if (px.cnt > 1 && x >= px.cl[1] && x < px.cl[1] + px.len[1]) lx = px.pl[1] + x - px.cl[1];
       acc[x] = (lx >= 0 && lane_in) ? row[lx * xs] : 0ull;
     }
   }
@@ -598,7 +601,7 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
           if (s_off[e + step] <= i) e += step;
         const int4 h = s_hdr[e];
         const int ex = h.w & 1023, ey = (h.w >> 10) & 1023, ez = h.w >> 20;
-        const Pieces px = overlap(h.x, ex, ccx, cb, n), py = overlap(h.y, ey, ccy, cb, n),
+        const Pieces px = overlap(h.x, ex, ccx, XD, n), py = overlap(h.y, ey, ccy, cb, n),
                      pz = overlap(h.z, ez, ccz, cb, n);
         int rem = i - s_off[e];                 // index inside this patch's pieces
         int ix = 0, iy2 = 0, iz2 = 0, cx = 0, cy = 0, cz = 0;
@@ -645,8 +648,7 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
     const int64_t m = static_cast<int64_t>(n) * n * n;
     const int64_t col = box * m + static_cast<int64_t>(ccy + iy) * n + ccz + iz;
 #pragma unroll
-    for (int x = 0; x < CBM; ++x) {
-      if (x >= cb) break;
+    for (int x = 0; x < XD; ++x) {
       const int64_t node = col + static_cast<int64_t>(ccx + x) * n * n;
       unsigned long long val = acc[x] + s_acc[(x * cb + iy) * cb + iz];
       if (fold) {
@@ -657,7 +659,8 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
       delta[node] = static_cast<float>(static_cast<double>(val) * scale - 1.0);
     }
   }
-  if (tid == 0) reg_count[cell] = 0;            // ready for the next deposit
+  // reg_count is cleared by the next kernel (the first forward FFT pass): the other slabs of
+  // this cell may still read it
 }
 
 __global__ void delta_to_density_kernel(const float* __restrict__ delta, float* __restrict__ out,
@@ -1004,10 +1007,12 @@ hipError_t launch_patch_reduce(const unsigned long long* patches, const int4* hd
                                const int* status, int* reg_count, const int* reg_list,
                                unsigned long long* rho_fb, const int* n_fb, float* delta,
                                int nbox, int n, double scale, hipStream_t s) {
-  hipLaunchKernelGGL(patch_reduce_kernel,
-                     dim3(static_cast<unsigned>(patch_coarse_cells(n)), nbox), dim3(256), 0, s,
-                     patches, kPatchCap, hdr, status, reg_count, reg_list, rho_fb, n_fb, delta, n,
-                     patch_cb_log2(n), scale);
+  // slabs of 8 x-planes: half a 16^3 cell (a whole 8^3 one)
+  const int slabs = (1 << patch_cb_log2(n)) / 8;
+  hipLaunchKernelGGL(patch_reduce_kernel<8>,
+                     dim3(static_cast<unsigned>(patch_coarse_cells(n) * slabs), nbox), dim3(256),
+                     0, s, patches, kPatchCap, hdr, status, reg_count, reg_list, rho_fb, n_fb,
+                     delta, n, patch_cb_log2(n), scale);
   return hipGetLastError();
 }
 

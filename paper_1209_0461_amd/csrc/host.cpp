@@ -321,15 +321,16 @@ int do_deposit(Ctx& c, const float* pos) {
     TIMED(c, ST_PATCH_REDUCE,
           launch_patch_reduce(c.patches, c.patch_hdr, c.patch_status, c.reg_count, c.reg_list,
                               c.rho_fb, c.n_fb, c.delta, c.nbox, c.N, scale, c.stream));
-    TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, nullptr, c.delta, c.n_fb, c.ck[1], c.tw, scale,
-                                    c.nbox, c.stream));
+    TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, nullptr, c.delta, c.n_fb, c.reg_count,
+                                    static_cast<int>(c.nbox * patch_coarse_cells(c.N)), c.ck[1],
+                                    c.tw, scale, c.nbox, c.stream));
     c.density_is_delta = true;
   } else {
     TIMED(c, ST_ZERO, launch_fill_zero(c.rho, cells * 8, c.stream));
     TIMED(c, ST_DEPOSIT, launch_deposit(pos, c.rho, c.Np, c.nbox, c.N, inv_cell, c.d_flags,
                                         c.tune.deposit_mode, c.tune.deposit_block, c.stream));
-    TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, c.rho, nullptr, nullptr, c.ck[1], c.tw, scale,
-                                    c.nbox, c.stream));
+    TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, c.rho, nullptr, nullptr, nullptr, 0, c.ck[1], c.tw,
+                                    scale, c.nbox, c.stream));
     c.density_is_delta = false;
   }
   TIMED(c, ST_FFT_Y, launch_fwd_y(c.N, c.ck[1], c.ck[0], c.tw, c.nbox, c.stream));

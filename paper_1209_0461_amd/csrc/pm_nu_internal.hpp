@@ -229,9 +229,11 @@ hipError_t launch_interp(const float* pos, const float* force, float* acc, int64
                          const Leap* lp = nullptr);
 // fft_kernels.hip
 // input: the fixed-point density rho, or (if delta is not NULL) delta in FP32; reset (may
-// be NULL) is cleared by the kernel when reading delta
+// be NULL) is cleared by the kernel when reading delta, and so are the n_clear ints at clear
+// (NULL: none); a clear larger than the launch's thread count is rejected
 hipError_t launch_fwd_z(int N, const unsigned long long* rho, const float* delta, int* reset,
-                        float2* out, const float2* tw, double scale, int nbox, hipStream_t s);
+                        int* clear, int n_clear, float2* out, const float2* tw, double scale,
+                        int nbox, hipStream_t s);
 hipError_t launch_fwd_y(int N, const float2* in, float2* out, const float2* tw, int nbox,
                         hipStream_t s);
 // partial != NULL: FFT along x and the mode sums per bin, data left unchanged (the step);
