@@ -320,11 +320,13 @@ __global__ __launch_bounds__(NT) void deposit_tiled_kernel(const float* __restri
 // ---------------------------------------------------------------- patch deposit ----
 // Deposit without global atomics. D1: each chunk sums its particles in an LDS tile as
 // above, writes the tile (its box, unpadded) to its own patch slot with plain stores and
-// registers the patch in every coarse cell (CB^3 nodes) that the box overlaps. D2: one
-// workgroup per coarse cell adds up the registered patches in exact integers and writes
-// delta = rho / rho_bar - 1 once, rounded to FP32. Chunks that cannot be patched (box too
-// large, or a coarse cell's list full) add their weights with global atomics to a side
-// grid kept at zero, which D2 folds in (and clears) only when such chunks exist.
+// registers the patch in every coarse cell (CB^3 nodes) that the box overlaps; a registry
+// entry carries everything D2 needs (chunk, box origin, extents). D2: one workgroup per
+// slab of a coarse cell adds up the registered patches in exact integers and writes
+// delta = rho / rho_bar - 1 once, rounded to FP32. Weights that cannot go through a patch
+// (a box too large: the whole chunk; a coarse cell whose list is full: the box's part in
+// that cell) are added with global atomics to a side grid kept at zero, which D2 folds in
+// (and clears) only when something was added to it.
 constexpr int kPatchList = 32;      // patches per coarse cell
 constexpr int kPatchRegMax = 27;    // coarse cells per patch
 
@@ -333,14 +335,14 @@ __device__ __forceinline__ int ceil_div_pow2(int a, int lg) { return (a + (1 << 
 template <int CH, int CAP, int NT>
 __global__ __launch_bounds__(NT) void deposit_patch_kernel(
     const float* __restrict__ pos, unsigned long long* __restrict__ patches,
-    int4* __restrict__ hdr, int* __restrict__ status, int* __restrict__ reg_count,
-    int* __restrict__ reg_list, unsigned long long* __restrict__ rho_fb, int* __restrict__ n_fb,
+    int* __restrict__ reg_count, int4* __restrict__ reg_list,
+    unsigned long long* __restrict__ rho_fb, int* __restrict__ n_fb,
     int64_t np, int n, double inv_cell, int* __restrict__ flags, int64_t chunks_per_box,
     int cb_lg) {
   constexpr int PPT = CH / NT;
   __shared__ unsigned long long tile[CAP];
   __shared__ int red[6][NT / 64];
-  __shared__ int s_fail;
+  __shared__ unsigned s_over;          // bit t: registry cell t of the box was full
   const int tid = threadIdx.x;
   const int64_t chunk = blockIdx.x;
   const int64_t box = chunk / chunks_per_box;
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(NT) void deposit_patch_kernel(
   const int nmask = n - 1;
   const int64_t m = static_cast<int64_t>(n) * n * n;
   unsigned long long* fb = rho_fb + box * m;
-  if (tid == 0) s_fail = 0;
+  if (tid == 0) s_over = 0u;
   Chunk<PPT> c;
   bool bad = false;
   load_chunk<PPT, NT>(c, pos + (box * np + c0) * 3, cnt, inv_cell, nmask, red, bad);
@@ -370,9 +372,11 @@ __global__ __launch_bounds__(NT) void deposit_patch_kernel(
   const bool fits = c.any && vol <= CAP && ex <= n && ey <= n && ez <= n &&
                     rx * ry * rz <= kPatchRegMax;
   if (fits) {
-    // register the patch in the coarse cells its box overlaps
+    // register the patch in the coarse cells its box overlaps (origin and extents < 1024)
     const int64_t cells = static_cast<int64_t>(nc) * nc * nc;
     const int fx = gx0 >> cb_lg, fy = gy0 >> cb_lg, fz = gz0 >> cb_lg;
+    const int4 entry = make_int4(static_cast<int>(chunk), gx0 | (gy0 << 10) | (gz0 << 20),
+                                 ex | (ey << 10) | (ez << 20), 0);
     for (int t = tid; t < rx * ry * rz; t += NT) {
       const int iz = t % rz, ixy = t / rz, iy = ixy % ry, ix = ixy / ry;
       const int64_t cell = box * cells +
@@ -380,9 +384,9 @@ __global__ __launch_bounds__(NT) void deposit_patch_kernel(
                             (fz + iz) % nc);
       const int slot = atomicAdd(reg_count + cell, 1);
       if (slot < kPatchList)
-        reg_list[cell * kPatchList + slot] = static_cast<int>(chunk);
+        reg_list[cell * kPatchList + slot] = entry;
       else
-        s_fail = 1;
+        atomicOr(&s_over, 1u << t);             // t < kPatchRegMax <= 32
     }
     for (int t = tid; t < vol; t += NT) tile[t] = 0ull;
     __syncthreads();
@@ -414,19 +418,21 @@ __global__ __launch_bounds__(NT) void deposit_patch_kernel(
       }
     }
     __syncthreads();
-    if (s_fail == 0) {
-      unsigned long long* pat = patches + chunk * kPatchCap;   // stored patch stride
-      for_box_nodes<NT>(ex, ey, ez, [&](int tx, int ty, int tz, int li) {
-        pat[li] = tile[(tx * sy + ty) * sz + tz];
-      });
-      if (tid == 0) {
-        hdr[chunk] = make_int4(gx0, gy0, gz0, ex | (ey << 10) | (ez << 20));
-        status[chunk] = 0;
-      }
-      return;
-    }
-    // a coarse cell's list was full: add the tile to the side grid instead
+    unsigned long long* pat = patches + chunk * kPatchCap;     // stored patch stride
+    for_box_nodes<NT>(ex, ey, ez, [&](int tx, int ty, int tz, int li) {
+      pat[li] = tile[(tx * sy + ty) * sz + tz];
+    });
+    const unsigned over = s_over;
+    if (over == 0u) return;
+    // coarse cells whose list was full: the box's part in them goes to the side grid
+    const int cbm = (1 << cb_lg) - 1;
     for_box_nodes<NT>(ex, ey, ez, [&](int tx, int ty, int tz, int) {
+      int ix = ((gx0 & cbm) + tx) >> cb_lg, iy = ((gy0 & cbm) + ty) >> cb_lg,
+          iz = ((gz0 & cbm) + tz) >> cb_lg;
+      ix -= ix >= nc ? nc : 0;                  // a box as wide as the mesh wraps onto fx
+      iy -= iy >= nc ? nc : 0;
+      iz -= iz >= nc ? nc : 0;
+      if (!((over >> ((ix * ry + iy) * rz + iz)) & 1u)) return;
       const unsigned long long v = tile[(tx * sy + ty) * sz + tz];
       if (v == 0ull) return;
       const unsigned gx = (gx0 + tx) & nmask, gy = (gy0 + ty) & nmask, gz = (gz0 + tz) & nmask;
@@ -443,10 +449,7 @@ __global__ __launch_bounds__(NT) void deposit_patch_kernel(
       deposit_global(fb, n, i, d, nmask);
     }
   }
-  if (tid == 0) {
-    status[chunk] = 1;
-    atomicAdd(n_fb, 1);
-  }
+  if (tid == 0) atomicAdd(n_fb, 1);
 }
 
 // Up to two pieces of the overlap of a periodic patch interval [p, p + e) with the cell
@@ -486,9 +489,8 @@ __device__ __forceinline__ Pieces overlap(int p, int e, int cs, int cb, int n) {
 // The sums are exact integers.
 template <int XD>
 __global__ __launch_bounds__(256) void patch_reduce_kernel(
-    const unsigned long long* __restrict__ patches, int pcap, const int4* __restrict__ hdr,
-    const int* __restrict__ status, const int* __restrict__ reg_count,
-    const int* __restrict__ reg_list, unsigned long long* __restrict__ rho_fb,
+    const unsigned long long* __restrict__ patches, int pcap, const int* __restrict__ reg_count,
+    const int4* __restrict__ reg_list, unsigned long long* __restrict__ rho_fb,
     const int* __restrict__ n_fb, float* __restrict__ delta, int n, int cb_lg, double scale) {
   constexpr int CBM = 16, kBatch = 8;
   const int tid = threadIdx.x;
@@ -510,30 +512,29 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
   __shared__ int s_home;
   for (int i = tid; i < vol_cell; i += 256) s_acc[i] = 0ull;
   if (tid < 64) {
-    // wave 0: the cell's patches (list row and count fetched together), their headers,
-    // overlap volumes, the home patch and the offsets of the others in the item list
+    // wave 0: the cell's patches (list row and count fetched together), their overlap
+    // volumes, the home patch and the offsets of the others in the item list
     const int cnt_raw = reg_count[cell];
-    const int listed = tid < kPatchList ? reg_list[cell * kPatchList + tid] : 0;
+    const int4 listed =
+        tid < kPatchList ? reg_list[cell * kPatchList + tid] : make_int4(0, 0, 0, 0);
     const int cntr = min(cnt_raw, kPatchList);
     int vol = -1;
     int4 h = make_int4(0, 0, 0, 0);
     int chunk = -1;
     if (tid < cntr) {
-      h = hdr[listed];
-      chunk = status[listed] == 0 ? listed : -1;   // else added through the side grid
-      if (chunk >= 0) {
-        const int ex = h.w & 1023, ey = (h.w >> 10) & 1023, ez = h.w >> 20;
-        const Pieces px = overlap(h.x, ex, ccx, XD, n), py = overlap(h.y, ey, ccy, cb, n),
-                     pz = overlap(h.z, ez, ccz, cb, n);
-        int lx = 0, ly = 0, lz = 0;
+      chunk = listed.x;
+      h = make_int4(listed.y & 1023, (listed.y >> 10) & 1023, listed.y >> 20, listed.z);
+      const int ex = h.w & 1023, ey = (h.w >> 10) & 1023, ez = h.w >> 20;
+      const Pieces px = overlap(h.x, ex, ccx, XD, n), py = overlap(h.y, ey, ccy, cb, n),
+                   pz = overlap(h.z, ez, ccz, cb, n);
+      int lx = 0, ly = 0, lz = 0;
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {           // constant bounds: no indexed scratch
-          lx += q < px.cnt ? px.len[q] : 0;
-          ly += q < py.cnt ? py.len[q] : 0;
-          lz += q < pz.cnt ? pz.len[q] : 0;
-        }
-        vol = lx * ly * lz;
+      for (int q = 0; q < 2; ++q) {           // constant bounds: no indexed scratch
+        lx += q < px.cnt ? px.len[q] : 0;
+        ly += q < py.cnt ? py.len[q] : 0;
+        lz += q < pz.cnt ? pz.len[q] : 0;
       }
+      vol = lx * ly * lz;
       s_hdr[tid] = h;
       s_chunk[tid] = chunk;
     }
@@ -985,34 +986,34 @@ int64_t patch_coarse_cells(int n) {
 }
 int64_t patch_chunks(int64_t np) { return (np + kPatchCH - 1) / kPatchCH; }
 
-hipError_t launch_deposit_patch(const float* pos, unsigned long long* patches, int4* hdr,
-                                int* status, int* reg_count, int* reg_list,
-                                unsigned long long* rho_fb, int* n_fb, int64_t np, int nbox,
-                                int n, double inv_cell, int* flags, bool big_tile,
-                                hipStream_t s) {
+hipError_t launch_deposit_patch(const float* pos, unsigned long long* patches, int* reg_count,
+                                int4* reg_list, unsigned long long* rho_fb, int* n_fb,
+                                int64_t np, int nbox, int n, double inv_cell, int* flags,
+                                bool big_tile, hipStream_t s) {
+  if (n > 1024) return hipErrorInvalidValue;     // registry entries pack indices in 10 bits
   const int64_t chunks = patch_chunks(np);
   const dim3 grid(static_cast<unsigned>(chunks * nbox));
   if (big_tile)
     hipLaunchKernelGGL((deposit_patch_kernel<kPatchCH, kPatchCap, kPatchNT>), grid,
-                       dim3(kPatchNT), 0, s, pos, patches, hdr, status, reg_count, reg_list,
-                       rho_fb, n_fb, np, n, inv_cell, flags, chunks, patch_cb_log2(n));
+                       dim3(kPatchNT), 0, s, pos, patches, reg_count, reg_list, rho_fb, n_fb,
+                       np, n, inv_cell, flags, chunks, patch_cb_log2(n));
   else
     hipLaunchKernelGGL((deposit_patch_kernel<kPatchCH, kPatchTile, kPatchNT>), grid,
-                       dim3(kPatchNT), 0, s, pos, patches, hdr, status, reg_count, reg_list,
-                       rho_fb, n_fb, np, n, inv_cell, flags, chunks, patch_cb_log2(n));
+                       dim3(kPatchNT), 0, s, pos, patches, reg_count, reg_list, rho_fb, n_fb,
+                       np, n, inv_cell, flags, chunks, patch_cb_log2(n));
   return hipGetLastError();
 }
 
-hipError_t launch_patch_reduce(const unsigned long long* patches, const int4* hdr,
-                               const int* status, int* reg_count, const int* reg_list,
-                               unsigned long long* rho_fb, const int* n_fb, float* delta,
-                               int nbox, int n, double scale, hipStream_t s) {
+hipError_t launch_patch_reduce(const unsigned long long* patches, const int* reg_count,
+                               const int4* reg_list, unsigned long long* rho_fb,
+                               const int* n_fb, float* delta, int nbox, int n, double scale,
+                               hipStream_t s) {
   // slabs of 8 x-planes: half a 16^3 cell (a whole 8^3 one)
   const int slabs = (1 << patch_cb_log2(n)) / 8;
   hipLaunchKernelGGL(patch_reduce_kernel<8>,
                      dim3(static_cast<unsigned>(patch_coarse_cells(n) * slabs), nbox), dim3(256),
-                     0, s, patches, kPatchCap, hdr, status, reg_count, reg_list, rho_fb, n_fb,
-                     delta, n, patch_cb_log2(n), scale);
+                     0, s, patches, kPatchCap, reg_count, reg_list, rho_fb, n_fb, delta, n,
+                     patch_cb_log2(n), scale);
   return hipGetLastError();
 }
 

@@ -315,12 +315,12 @@ int do_deposit(Ctx& c, const float* pos) {
   const double scale = static_cast<double>(c.M) / static_cast<double>(c.Np) / kFixScale;
   if (c.tune.deposit_mode >= 6) {
     TIMED(c, ST_DEPOSIT,
-          launch_deposit_patch(pos, c.patches, c.patch_hdr, c.patch_status, c.reg_count,
-                               c.reg_list, c.rho_fb, c.n_fb, c.Np, c.nbox, c.N, inv_cell,
-                               c.d_flags, c.tune.deposit_mode == 7, c.stream));
+          launch_deposit_patch(pos, c.patches, c.reg_count, c.reg_list, c.rho_fb, c.n_fb,
+                               c.Np, c.nbox, c.N, inv_cell, c.d_flags,
+                               c.tune.deposit_mode == 7, c.stream));
     TIMED(c, ST_PATCH_REDUCE,
-          launch_patch_reduce(c.patches, c.patch_hdr, c.patch_status, c.reg_count, c.reg_list,
-                              c.rho_fb, c.n_fb, c.delta, c.nbox, c.N, scale, c.stream));
+          launch_patch_reduce(c.patches, c.reg_count, c.reg_list, c.rho_fb, c.n_fb, c.delta,
+                              c.nbox, c.N, scale, c.stream));
     TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, nullptr, c.delta, c.n_fb, c.reg_count,
                                     static_cast<int>(c.nbox * patch_coarse_cells(c.N)), c.ck[1],
                                     c.tw, scale, c.nbox, c.stream));
@@ -420,7 +420,7 @@ void free_ctx(Ctx* c) {
                   c->bin_of_n2, c->d_counts, c->d_kmean, c->d_lnk, c->d_nonempty, c->pcdm, c->pnu,
                   c->ratio, c->hist_pm, c->hist_pnu, c->ic_pnu, c->ic_theta, c->tg_ds,
                   c->tg_w, c->d_resp, c->rtable, c->tw, c->inv_w2, c->d_flags, c->patches,
-                  c->patch_hdr, c->patch_status, c->reg_count, c->reg_list, c->rho_fb, c->n_fb,
+                  c->reg_count, c->reg_list, c->rho_fb, c->n_fb,
                   c->delta, c->d_kd};
   for (void* p : bufs)
     if (p) hipFree(p);
@@ -549,8 +549,6 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
     const size_t chunks = nb * static_cast<size_t>(patch_chunks(c->Np));
     const size_t coarse = nb * static_cast<size_t>(patch_coarse_cells(c->N));
     ALLOC(c->patches, chunks * kPatchCap);
-    ALLOC(c->patch_hdr, chunks);
-    ALLOC(c->patch_status, chunks);
     ALLOC(c->reg_count, coarse);
     ALLOC(c->reg_list, coarse * 32);
     ALLOC(c->rho_fb, nb * c->M);

@@ -141,10 +141,8 @@ struct Ctx {
   int* d_flags = nullptr;          // [1] bit 0: non-finite position seen
   // patch deposit (deposit modes 6 and 7)
   unsigned long long* patches = nullptr;   // [chunks][kPatchCap] per-chunk tiles
-  int4* patch_hdr = nullptr;       // [chunks] box origin and packed extents
-  int* patch_status = nullptr;     // [chunks] 0 patched, 1 through the side grid
   int* reg_count = nullptr;        // [nbox][coarse cells] patches registered
-  int* reg_list = nullptr;         // [nbox][coarse cells][32] chunk ids
+  int4* reg_list = nullptr;        // [nbox][coarse cells][32] (chunk, origin, extents, 0)
   unsigned long long* rho_fb = nullptr;    // [nbox][M] side grid, kept at zero
   int* n_fb = nullptr;             // [1] chunks that used the side grid this deposit
   float* delta = nullptr;          // [nbox][M] delta in FP32 (modes 6, 7)
@@ -282,16 +280,16 @@ hipError_t launch_surrogate_dataset(const RespBox* boxes, const double* pcdm, co
 int patch_cb_log2(int n);
 int64_t patch_coarse_cells(int n);
 int64_t patch_chunks(int64_t np);
-// big_tile: the kPatchCap-node LDS tile (mode 7) instead of kPatchTile (mode 6)
-hipError_t launch_deposit_patch(const float* pos, unsigned long long* patches, int4* hdr,
-                                int* status, int* reg_count, int* reg_list,
-                                unsigned long long* rho_fb, int* n_fb, int64_t np, int nbox,
-                                int n, double inv_cell, int* flags, bool big_tile,
-                                hipStream_t s);
-hipError_t launch_patch_reduce(const unsigned long long* patches, const int4* hdr,
-                               const int* status, int* reg_count, const int* reg_list,
-                               unsigned long long* rho_fb, const int* n_fb, float* delta,
-                               int nbox, int n, double scale, hipStream_t s);
+// big_tile: the kPatchCap-node LDS tile (mode 7) instead of kPatchTile (mode 6); reg_list
+// entries are (chunk, packed box origin, packed extents, 0), n <= 1024
+hipError_t launch_deposit_patch(const float* pos, unsigned long long* patches, int* reg_count,
+                                int4* reg_list, unsigned long long* rho_fb, int* n_fb,
+                                int64_t np, int nbox, int n, double inv_cell, int* flags,
+                                bool big_tile, hipStream_t s);
+hipError_t launch_patch_reduce(const unsigned long long* patches, const int* reg_count,
+                               const int4* reg_list, unsigned long long* rho_fb,
+                               const int* n_fb, float* delta, int nbox, int n, double scale,
+                               hipStream_t s);
 hipError_t launch_delta_to_density(const float* delta, float* out, int64_t n, float rho_bar,
                                    hipStream_t s);
 hipError_t launch_kick_drift(float* pos, float* vel, const float* acc, const double* kd,

@@ -278,7 +278,9 @@ def test_patch_deposit_side_grid_on_crowded_cells():
     """Deposit mode 6 with 40 chunks of particles packed into a few cells: the coarse cell's
     patch list overflows, those chunks go through the side grid, and the result still
     matches the oracle; a following deposit of an ordinary lattice finds the side grid
-    cleared."""
+    cleared. In the last input half of the chunks straddle two coarse cells of which only
+    one overflows: such a chunk's patch serves the other cell, and only its part in the full
+    cell goes through the side grid."""
     import torch
     from paper_1209_0461_amd import PMNu, binding
     from synth import zeldovich_lattice
@@ -287,9 +289,11 @@ def test_patch_deposit_side_grid_on_crowded_cells():
     crowd = (40.0 + 10.0 * rng.random((40 * 4096, 3))).astype(np.float32)   # 2.5 cells wide
     lattice = zeldovich_lattice(32, box, 0.3, 72)
     lattice = np.concatenate([lattice] * 5)[: len(crowd)]   # same count, ordinary spread
+    straddle = crowd.copy()                                 # x nodes 15-17: cells 0 and 1
+    straddle[: 20 * 4096, 0] += 20.0
     ctx = PMNu(nm, len(crowd), box, nb, J + 2, [0.3])
     binding.pm_nu_set_launch(ctx.h, 6, 256, 1, 256)
-    for pos in (crowd, lattice, crowd):
+    for pos in (crowd, lattice, straddle):
         hist, ref = oracle_case(pos, nm, box, nb, J, 0.02, 0.7, 0.3)
         ctx.set_history(0, hist)
         p = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
