@@ -120,16 +120,20 @@ __device__ __forceinline__ int wave_max(int v) {
 // Chunk of PPT * 256 consecutive particles held in registers (lower node and fraction per
 // axis) and the periodic bounding box of their lower nodes relative to the first particle's
 // node. Every thread computes the same reference node, so no barrier is needed for it.
+// With KEEP the lower node (relative to r, three 10-bit fields offset by 512) and the FP32
+// fraction of every particle are kept, so users need not find them again.
 template <int PPT>
 struct Chunk {
   float p[PPT][3];
   bool ok[PPT];
+  int rel[PPT];
+  float f[PPT][3];
   int r[3];
   int mn[3], ext[3];   // box origin (relative to r) and extent in nodes, upper neighbours included
   bool any;
 };
 
-template <int PPT, int NT = 256>
+template <int PPT, int NT = 256, bool KEEP = false>
 __device__ __forceinline__ void load_chunk(Chunk<PPT>& c, const float* p, int cnt, double inv_cell,
                                            int nmask, int (*red)[NT / 64], bool& bad) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, half = (nmask + 1) / 2;
@@ -157,6 +161,7 @@ __device__ __forceinline__ void load_chunk(Chunk<PPT>& c, const float* p, int cn
     const int j = tid + q * NT;
     c.ok[q] = j < cnt && finite3(c.p[q][0], c.p[q][1], c.p[q][2]);
     bad |= (j < cnt) && !c.ok[q];
+    if (KEEP) c.rel[q] = 0;
     if (c.ok[q]) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -166,6 +171,10 @@ __device__ __forceinline__ void load_chunk(Chunk<PPT>& c, const float* p, int cn
         const int rel = ((i - c.r[a] + half) & nmask) - half;
         mn[a] = min(mn[a], rel);
         mx[a] = max(mx[a], rel);
+        if (KEEP) {
+          c.rel[q] |= (rel + 512) << (10 * a);      // -256 <= rel < 256
+          c.f[q][a] = static_cast<float>(d);
+        }
       }
     }
   }
@@ -345,7 +354,8 @@ __global__ __launch_bounds__(NT) void deposit_patch_kernel(
   __shared__ unsigned s_over;          // bit t: registry cell t of the box was full
   const int tid = threadIdx.x;
   const int64_t chunk = blockIdx.x;
-  const int64_t box = chunk / chunks_per_box;
+  // grid sizes stay below 2^31 blocks: a 32-bit division suffices
+  const int64_t box = static_cast<uint32_t>(chunk) / static_cast<uint32_t>(chunks_per_box);
   const int64_t c0 = (chunk - box * chunks_per_box) * CH;
   const int cnt = static_cast<int>(min(static_cast<int64_t>(CH), np - c0));
   const int nmask = n - 1;
@@ -761,7 +771,8 @@ __global__ __launch_bounds__(256) void interp_kernel(const float* pos,
   constexpr int NT = 256, CH = NT * PPT;
   const int64_t chunk = xcd_chunk(blockIdx.x, gridDim.x);
   if (chunk >= nchunks) return;
-  const int64_t box = chunk / chunks_per_box;
+  // grid sizes stay below 2^31 blocks: a 32-bit division suffices
+  const int64_t box = static_cast<uint32_t>(chunk) / static_cast<uint32_t>(chunks_per_box);
   const int64_t c0 = (chunk - box * chunks_per_box) * CH;
   const int cnt = static_cast<int>(min(static_cast<int64_t>(CH), np - c0));
   const float* p = pos + (box * np + c0) * 3;
@@ -802,7 +813,8 @@ __global__ __launch_bounds__(256) void interp_tiled_kernel(const float* pos,
   const int tid = threadIdx.x;
   const int64_t chunk = xcd_chunk(blockIdx.x, gridDim.x);
   if (chunk >= nchunks) return;
-  const int64_t box = chunk / chunks_per_box;
+  // grid sizes stay below 2^31 blocks: a 32-bit division suffices
+  const int64_t box = static_cast<uint32_t>(chunk) / static_cast<uint32_t>(chunks_per_box);
   const int64_t c0 = (chunk - box * chunks_per_box) * CH;
   const int cnt = static_cast<int>(min(static_cast<int64_t>(CH), np - c0));
   const int nmask = n - 1;
@@ -814,7 +826,7 @@ __global__ __launch_bounds__(256) void interp_tiled_kernel(const float* pos,
   }
   Chunk<PPT> c;
   bool bad = false;
-  load_chunk<PPT>(c, pos + (box * np + c0) * 3, cnt, inv_cell, nmask, red, bad);
+  load_chunk<PPT, 256, true>(c, pos + (box * np + c0) * 3, cnt, inv_cell, nmask, red, bad);
   const int ex = c.ext[0], ey = c.ext[1], ez = c.ext[2];
   const int vol = ex * ey * ez;
   const bool use_tile = c.any && vol <= CAP && ex <= n && ey <= n && ez <= n;
@@ -860,19 +872,24 @@ __global__ __launch_bounds__(256) void interp_tiled_kernel(const float* pos,
     }
     __syncthreads();
   }
-  const int half = n / 2;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     const int j = tid + q * NT;
     if (j >= cnt) continue;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
     if (c.ok[q]) {
-      Corner k;
-      corner_of(c.p[q][0], c.p[q][1], c.p[q][2], inv_cell, nmask, k);
+      Corner k;                                  // from the node and fraction kept above
+      int rel[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        rel[a] = ((c.rel[q] >> (10 * a)) & 1023) - 512;
+        k.w[a][1] = c.f[q][a];
+        k.w[a][0] = 1.0f - k.w[a][1];
+      }
       if (use_tile) {
         int t[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) t[a] = ((k.i[a] - c.r[a] + half) & nmask) - half - c.mn[a];
+        for (int a = 0; a < 3; ++a) t[a] = rel[a] - c.mn[a];
         const int base = (t[0] * ey + t[1]) * ez + t[2];
 #pragma unroll
         for (int cx = 0; cx < 2; ++cx) {
@@ -890,6 +907,8 @@ __global__ __launch_bounds__(256) void interp_tiled_kernel(const float* pos,
           }
         }
       } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) k.i[a] = (c.r[a] + rel[a]) & nmask;
         gather_global(g, n, nmask, k, a0, a1, a2);
       }
     }
