@@ -170,6 +170,23 @@ __global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data
   load_twiddles<N, NT>(tw, twg);
   if constexpr (BIN)
     for (int b = threadIdx.x; b < nbins; b += NT) bins[b] = 0.0;
+  // binning: thread t walks a run of RUN consecutive k_x at k_y = y0 + t % TX, where |n|^2
+  // changes slowly; the run's bin indices are fetched here so that their latency hides
+  // behind the loads and the transform (-1: no mode)
+  constexpr int RUNS = NT / TX;                        // runs per k_y column
+  constexpr int RUN = (N + RUNS - 1) / RUNS;           // k_x values per run
+  static_assert(TX * RUNS == NT, "one run per thread");
+  [[maybe_unused]] const int by = threadIdx.x % TX, bx0 = (threadIdx.x / TX) * RUN;
+  [[maybe_unused]] int bk[RUN];
+  if constexpr (BIN) {
+    const int ny = signed_index(y0 + by, N);
+#pragma unroll
+    for (int u = 0; u < RUN; ++u) {
+      const int nx = signed_index(bx0 + u, N);
+      const int n2 = nx * nx + ny * ny + kz * kz;
+      bk[u] = (bx0 + u < N && n2 > 0) ? static_cast<int>(bin_of_n2[n2]) : -1;
+    }
+  }
   float2* base = data + ((static_cast<size_t>(box) * NK + kz) * N) * N + y0;
   // float4 = two consecutive k_y; all loads in flight before the LDS stores
   constexpr int P = TX / 2, IT = (N * P + NT - 1) / NT;
@@ -192,8 +209,7 @@ __global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data
   __syncthreads();
   fft_lines<N, TX, NT, -1>(lds, tw);
   const double w = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
-  // store the tile back, then bin it: each thread walks a run of consecutive k_x at one
-  // k_y, where |n|^2 changes slowly, and adds to the LDS bin only when the bin changes
+  // store the tile back, then bin it, adding to the LDS bin only when the bin changes
   if constexpr (STORE) {
     for (int t = threadIdx.x; t < N * P; t += NT) {
       const int x = t / P, y = 2 * (t % P);
@@ -203,19 +219,14 @@ __global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data
     }
   }
   if constexpr (!BIN) return;
-  constexpr int RUNS = NT / TX;                        // runs per k_y column
-  constexpr int RUN = (N + RUNS - 1) / RUNS;           // k_x values per run
-  for (int t = threadIdx.x; t < TX * RUNS; t += NT) {
-    const int y = t % TX, run = t / TX;
-    const int ny = signed_index(y0 + y, N);
+  {
     int cur = -1;
     double acc = 0.0;
-    for (int x = run * RUN; x < min(N, run * RUN + RUN); ++x) {
-      const int nx = signed_index(x, N);
-      const int n2 = nx * nx + ny * ny + kz * kz;
-      if (n2 == 0) continue;
-      const int b = bin_of_n2[n2];
-      const float2 v = lds[x * ES + y];
+#pragma unroll
+    for (int u = 0; u < RUN; ++u) {
+      const int b = bk[u];
+      if (b < 0) continue;
+      const float2 v = lds[(bx0 + u) * ES + by];
       const double p = w * (static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y);
       if (b != cur) {
         if (cur >= 0) atomicAdd(&bins[cur], acc);
@@ -247,6 +258,7 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
   constexpr int NYB = N / TX;
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
+  __shared__ float s_iw[N];
   // Workgroups go to the 8 XCDs in turn; the remap gives each XCD a contiguous run of
   // (k_y block, k_z) tiles, so the two workgroups writing the halves of a 128-byte line
   // (TX = 8 complex values = 64 bytes per row) share one L2 instead of each fetching it.
@@ -256,9 +268,22 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
   if (logical >= total) return;
   const int y0 = (logical % NYB) * TX, kz = (logical / NYB) % NK, box = logical / (NYB * NK);
   load_twiddles<N, NT>(tw, twg);
+  for (int m = threadIdx.x; m < N; m += NT) s_iw[m] = inv_w2[m];
   const size_t off = ((static_cast<size_t>(box) * NK + kz) * N) * N + y0;
   const float* rt = rtable + static_cast<size_t>(box) * (n2max + 1);
   const float wz = inv_w2[kz];
+  // T(n^2) of this thread's Green's-function modes, fetched before the transform so that
+  // the gathers' latency hides behind it (0: the k = 0 mode)
+  constexpr int GI = (N * TX + NT - 1) / NT;
+  float tv[GI];
+#pragma unroll
+  for (int i = 0; i < GI; ++i) {
+    const int t = threadIdx.x + i * NT;
+    const int y = t % TX, x = t / TX;
+    const int nx = signed_index(x, N), ny = signed_index(y0 + y, N);
+    const int n2 = nx * nx + ny * ny + kz * kz;
+    tv[i] = (t < N * TX && n2 > 0) ? rt[n2] : 0.f;
+  }
   // the tile holds x (real space) by k_y: forward transform along x first (lines 0..TX-1)
   constexpr int P = TX / 2, IT = (N * P + NT - 1) / NT;
   static_assert(TX % 2 == 0 && NT % P == 0, "k_y pairs");
@@ -280,14 +305,17 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
   __syncthreads();
   fft_lines<N, TX, NT, -1, ES>(lds, tw);
   // delta_M -> phi and -i k_x phi, in place on the (k_x, k_y) tile
-  for (int t = threadIdx.x; t < N * TX; t += NT) {
+#pragma unroll
+  for (int i = 0; i < GI; ++i) {
+    const int t = threadIdx.x + i * NT;
+    if (t >= N * TX) break;
     const int y = t % TX, x = t / TX;
     const int nx = signed_index(x, N), ny = signed_index(y0 + y, N);
     const int n2 = nx * nx + ny * ny + kz * kz;
     float2 phi = make_float2(0.f, 0.f);
     if (n2 > 0) {
       // phi = -C T(n^2) delta / (k^2 W^2), k^2 = kf^2 n^2
-      const float g = -c * rt[n2] * inv_w2[x] * inv_w2[y0 + y] * wz /
+      const float g = -c * tv[i] * s_iw[x] * s_iw[y0 + y] * wz /
                       (kf * kf * static_cast<float>(n2));
       phi = cscale(lds[x * ES + y], g);
     }

@@ -489,20 +489,22 @@ __device__ __forceinline__ Pieces overlap(int p, int e, int cs, int cb, int n) {
 
 // D2: one workgroup of 256 threads per (slab of XD x-planes of a coarse cell, box), CB =
 // 1 << cb_lg <= 16, XD <= CB (halving the slab halves the LDS copy and doubles the
-// workgroups, which hides more of the load latency). A cell
-// is mostly covered by one patch (the chunk whose block it is) and touched by a few others
-// in thin layers (their halos). The largest overlap goes through registers: thread
-// (iy, iz) owns the slab's column x = 0..XD-1 and loads it from that patch. The nodes of every
-// other overlap form one list over which all threads stride, adding into an LDS copy of the
-// cell with 64-bit LDS atomics. Every thread issues all of its loads (its column and up to
-// kBatch list items) before it uses any, so each workgroup waits on few load latencies.
-// The sums are exact integers.
+// workgroups, which hides more of the load latency). A cell is mostly covered by one patch
+// (the chunk whose block it is) and touched by a few others in thin layers (their halos).
+// The largest overlap goes through registers: thread (iy, iz) owns the slab's column
+// x = 0..XD-1 and loads it from that patch. Every other overlap is cut into boxes (up to
+// two periodic pieces per axis), which wave 0 lists once in LDS with their item offsets,
+// sizes and source and destination bases; all threads then stride over the flat item list,
+// find an item's box by bisection and add the node into an LDS copy of the slab with
+// 64-bit LDS atomics. Every thread issues all of its loads (its column and up to kBatch
+// list items) before it uses any, so each workgroup waits on few load latencies. The sums
+// are exact integers.
 template <int XD>
 __global__ __launch_bounds__(256) void patch_reduce_kernel(
     const unsigned long long* __restrict__ patches, int pcap, const int* __restrict__ reg_count,
     const int4* __restrict__ reg_list, unsigned long long* __restrict__ rho_fb,
     const int* __restrict__ n_fb, float* __restrict__ delta, int n, int cb_lg, double scale) {
-  constexpr int CBM = 16, kBatch = 8;
+  constexpr int CBM = 16, kBatch = 8, kPieces = kPatchList * 8;
   const int tid = threadIdx.x;
   const int cb = 1 << cb_lg, nc = n >> cb_lg;
   const int slabs = cb / XD;
@@ -516,27 +518,32 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
   const bool on = tid < cb * cb;
   const int vol_cell = XD * cb * cb;
   __shared__ unsigned long long s_acc[XD * CBM * CBM];    // [x][y][z] of the slab
-  __shared__ int4 s_hdr[kPatchList];
-  __shared__ int s_chunk[kPatchList];
-  __shared__ int s_off[kPatchList + 1];    // list offsets of the non-home overlaps
-  __shared__ int s_home;
+  // the piece list: item offset (INT_MAX past the end), Lz | Ly << 8, source base
+  // (patch element of the piece's first node), strides ez | (ey ez) << 10, LDS base
+  __shared__ int p_off[kPieces + 1];
+  __shared__ int p_dim[kPieces];
+  __shared__ long long p_src[kPieces];
+  __shared__ int p_str[kPieces];
+  __shared__ int p_dst[kPieces];
+  __shared__ int4 s_home;                  // home patch: chunk, origin, extents; chunk < 0: none
+  __shared__ int s_total;                  // items in the piece list
   for (int i = tid; i < vol_cell; i += 256) s_acc[i] = 0ull;
   if (tid < 64) {
     // wave 0: the cell's patches (list row and count fetched together), their overlap
-    // volumes, the home patch and the offsets of the others in the item list
+    // pieces, the home patch and the piece list of the others
     const int cnt_raw = reg_count[cell];
     const int4 listed =
-        tid < kPatchList ? reg_list[cell * kPatchList + tid] : make_int4(0, 0, 0, 0);
-    const int cntr = min(cnt_raw, kPatchList);
+        tid < kPatchList ? reg_list[cell * kPatchList + tid] : make_int4(-1, 0, 0, 0);
+    const bool mine = tid < min(cnt_raw, kPatchList);
+    const int gx = listed.y & 1023, gy = (listed.y >> 10) & 1023, gz = listed.y >> 20;
+    const int ex = listed.z & 1023, ey = (listed.z >> 10) & 1023, ez = listed.z >> 20;
+    Pieces px, py, pz;
+    px.cnt = py.cnt = pz.cnt = 0;
     int vol = -1;
-    int4 h = make_int4(0, 0, 0, 0);
-    int chunk = -1;
-    if (tid < cntr) {
-      chunk = listed.x;
-      h = make_int4(listed.y & 1023, (listed.y >> 10) & 1023, listed.y >> 20, listed.z);
-      const int ex = h.w & 1023, ey = (h.w >> 10) & 1023, ez = h.w >> 20;
-      const Pieces px = overlap(h.x, ex, ccx, XD, n), py = overlap(h.y, ey, ccy, cb, n),
-                   pz = overlap(h.z, ez, ccz, cb, n);
+    if (mine) {
+      px = overlap(gx, ex, ccx, XD, n);
+      py = overlap(gy, ey, ccy, cb, n);
+      pz = overlap(gz, ez, ccz, cb, n);
       int lx = 0, ly = 0, lz = 0;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {           // constant bounds: no indexed scratch
@@ -545,39 +552,63 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
         lz += q < pz.cnt ? pz.len[q] : 0;
       }
       vol = lx * ly * lz;
-      s_hdr[tid] = h;
-      s_chunk[tid] = chunk;
     }
     // home: the largest volume, ties to the lowest index
     int key = vol > 0 ? (vol << 6) | (63 - tid) : -1;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) key = max(key, __shfl_xor(key, off, 64));
     const int home = key >= 0 ? 63 - (key & 63) : -1;
-    // exclusive prefix of the other overlaps' volumes
-    int w = (vol > 0 && tid != home) ? vol : 0;
-    int incl = w;
+    if (tid == 0) s_home = make_int4(-1, 0, 0, 0);
+    if (tid == home) s_home = listed;
+    // exclusive prefixes of the others' piece counts and volumes
+    const bool other = vol > 0 && tid != home;
+    const int np_mine = other ? px.cnt * py.cnt * pz.cnt : 0;
+    int inc_p = np_mine, inc_v = other ? vol : 0;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      const int t = __shfl_up(incl, off, 64);
-      if (tid >= off) incl += t;
+      const int tp = __shfl_up(inc_p, off, 64), tv = __shfl_up(inc_v, off, 64);
+      if (tid >= off) {
+        inc_p += tp;
+        inc_v += tv;
+      }
     }
-    if (tid < kPatchList) s_off[tid] = incl - w;
-    if (tid == kPatchList - 1) s_off[kPatchList] = incl;
-    if (tid == 0) s_home = home;
+    const int n_pieces = __shfl(inc_p, 63, 64);
+    if (tid == 63) s_total = inc_v;
+    int slot = inc_p - np_mine;
+    int item = inc_v - (other ? vol : 0);
+    if (other) {
+      const long long src0 = static_cast<long long>(listed.x) * pcap;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            if (a >= px.cnt || b >= py.cnt || c >= pz.cnt) continue;
+            const int Lx = px.len[a], Ly = py.len[b], Lz = pz.len[c];
+            p_off[slot] = item;
+            p_dim[slot] = Lz | (Ly << 8);
+            p_src[slot] = src0 + (px.pl[a] * ey + py.pl[b]) * ez + pz.pl[c];
+            p_str[slot] = ez | ((ey * ez) << 10);
+            p_dst[slot] = (px.cl[a] * cb + py.cl[b]) * cb + pz.cl[c];
+            item += Lx * Ly * Lz;
+            ++slot;
+          }
+    }
+    for (int i = n_pieces + tid; i <= kPieces; i += 64) p_off[i] = 0x7fffffff;
   }
   __syncthreads();
-  const int home = s_home;
-  const int total = s_off[kPatchList];
+  const int total = s_total;
   // the home patch's column loads go out first
   unsigned long long acc[XD];
 #pragma unroll
   for (int x = 0; x < XD; ++x) acc[x] = 0ull;
-  if (home >= 0) {
-    const int chunk = s_chunk[home];
-    const int4 h = s_hdr[home];
-    const int ex = h.w & 1023, ey = (h.w >> 10) & 1023, ez = h.w >> 20;
-    const Pieces px = overlap(h.x, ex, ccx, XD, n), py = overlap(h.y, ey, ccy, cb, n),
-                 pz = overlap(h.z, ez, ccz, cb, n);
+  const int4 hl = s_home;
+  if (hl.x >= 0) {
+    const int hx = hl.y & 1023, hy = (hl.y >> 10) & 1023, hz = hl.y >> 20;
+    const int ex = hl.z & 1023, ey = (hl.z >> 10) & 1023, ez = hl.z >> 20;
+    const Pieces px = overlap(hx, ex, ccx, XD, n), py = overlap(hy, ey, ccy, cb, n),
+                 pz = overlap(hz, ez, ccz, cb, n);
     int ly = -1, lz = -1;                       // this thread's row (y, z) inside the patch
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -586,7 +617,7 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
     }
     const bool lane_in = on && ly >= 0 && lz >= 0;
     const unsigned long long* row =
-        patches + static_cast<int64_t>(chunk) * pcap + (lane_in ? ly * ez + lz : 0);
+        patches + static_cast<int64_t>(hl.x) * pcap + (lane_in ? ly * ez + lz : 0);
     const int xs = ey * ez;                     // patch stride along x
 #pragma unroll
     for (int x = 0; x < XD; ++x) {
@@ -606,47 +637,20 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
       li[r] = -1;
       v[r] = 0ull;
       if (i < total) {
-        int e = 0;                              // the patch: last offset <= i
+        int e = 0;                              // the piece: last offset <= i
 #pragma unroll
-        for (int step = kPatchList / 2; step > 0; step >>= 1)
-          if (s_off[e + step] <= i) e += step;
-        const int4 h = s_hdr[e];
-        const int ex = h.w & 1023, ey = (h.w >> 10) & 1023, ez = h.w >> 20;
-        const Pieces px = overlap(h.x, ex, ccx, XD, n), py = overlap(h.y, ey, ccy, cb, n),
-                     pz = overlap(h.z, ez, ccz, cb, n);
-        int rem = i - s_off[e];                 // index inside this patch's pieces
-        int ix = 0, iy2 = 0, iz2 = 0, cx = 0, cy = 0, cz = 0;
-        bool found = false;
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              if (found || a >= px.cnt || b >= py.cnt || c >= pz.cnt) continue;
-              const int Lx = px.len[a], Ly = py.len[b], Lz = pz.len[c];
-              const int V = Lx * Ly * Lz;
-              if (rem >= V) {
-                rem -= V;
-                continue;
-              }
-              // exact: rem < 4096 and the divisors are at most 16
-              const int t = static_cast<int>((rem + 0.5f) * (1.0f / Lz));
-              const int z = rem - t * Lz;
-              const int x = static_cast<int>((t + 0.5f) * (1.0f / Ly));
-              const int y = t - x * Ly;
-              ix = px.pl[a] + x;
-              iy2 = py.pl[b] + y;
-              iz2 = pz.pl[c] + z;
-              cx = px.cl[a] + x;
-              cy = py.cl[b] + y;
-              cz = pz.cl[c] + z;
-              found = true;
-            }
-        if (found) {
-          v[r] = patches[static_cast<int64_t>(s_chunk[e]) * pcap + (ix * ey + iy2) * ez + iz2];
-          li[r] = (cx * cb + cy) * cb + cz;
-        }
+        for (int step = kPieces / 2; step > 0; step >>= 1)
+          if (p_off[e + step] <= i) e += step;
+        const int rem = i - p_off[e];
+        const int dim = p_dim[e], str = p_str[e];
+        const int Lz = dim & 255, Ly = dim >> 8;
+        // exact: rem < 4096 and the divisors are at most 16
+        const int t = static_cast<int>((rem + 0.5f) * (1.0f / Lz));
+        const int z = rem - t * Lz;
+        const int x = static_cast<int>((t + 0.5f) * (1.0f / Ly));
+        const int y = t - x * Ly;
+        v[r] = patches[p_src[e] + x * (str >> 10) + y * (str & 1023) + z];
+        li[r] = p_dst[e] + (x * cb + y) * cb + z;
       }
     }
 #pragma unroll
