@@ -96,7 +96,7 @@ def kernel_name(stage, tuning, n_mesh):
             return "interp_tiled_kernel" + itp[m]
         return "interp_kernel<%d, false>" % max(1, min(4, tuning["interp_block"] // 256))
     fixed = {"zero_mesh": "fill_zero_kernel", "nu_response": "response_kernel",
-             "rtable": "rtable_kernel", "patch_reduce": "patch_reduce_kernel"}
+             "rtable": "rtable_kernel", "patch_reduce": "patch_reduce_kernel<8>"}
     if stage in fixed:
         return fixed[stage]
     fft = {"fft_fwd_z": "fwd_z_kernel", "fft_fwd_y": "fwd_y_kernel",
