@@ -136,11 +136,22 @@ __global__ __launch_bounds__(NT) void fwd_y_kernel(const float2* __restrict__ in
   load_twiddles<N, NT>(tw, twg);
   const size_t r0 = static_cast<size_t>(blockIdx.x) * NL;
   const float4* src = reinterpret_cast<const float4*>(in + r0 * N);
-  for (int t = threadIdx.x; t < NL * N / 2; t += NT) {
-    const int e = (2 * t) % N, l = (2 * t) / N;
-    const float4 v = src[t];
-    lds[e * ES + l] = make_float2(v.x, v.y);
-    lds[(e + 1) * ES + l] = make_float2(v.z, v.w);
+  // all of a thread's loads in flight before the LDS stores
+  constexpr int IT = (NL * N / 2 + NT - 1) / NT;
+  float4 v[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int t = threadIdx.x + i * NT;
+    if (t < NL * N / 2) v[i] = src[t];
+  }
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int t = threadIdx.x + i * NT;
+    if (t < NL * N / 2) {
+      const int e = (2 * t) % N, l = (2 * t) / N;
+      lds[e * ES + l] = make_float2(v[i].x, v[i].y);
+      lds[(e + 1) * ES + l] = make_float2(v[i].z, v[i].w);
+    }
   }
   __syncthreads();
   fft_lines<N, NL, NT, -1>(lds, tw);
@@ -351,9 +362,23 @@ __global__ __launch_bounds__(NT) void inv_y_kernel(const float2* __restrict__ f1
   const size_t off = static_cast<size_t>(blockIdx.x) * NLR * N;
   const float4* f1v = reinterpret_cast<const float4*>(f1 + off);
   const float4* f2v = reinterpret_cast<const float4*>(f2 + off);
-  for (int t = threadIdx.x; t < NLR * N / 2; t += NT) {
+  // all of a thread's loads in flight before the LDS stores
+  constexpr int IT = (NLR * N / 2 + NT - 1) / NT;
+  float4 va[IT], vb[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int t = threadIdx.x + i * NT;
+    if (t < NLR * N / 2) {
+      va[i] = f1v[t];
+      vb[i] = f2v[t];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int t = threadIdx.x + i * NT;
+    if (t >= NLR * N / 2) continue;
     const int l = (2 * t) / N, e0 = (2 * t) % N;
-    const float4 a4 = f1v[t], b4 = f2v[t];
+    const float4 a4 = va[i], b4 = vb[i];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int e = e0 + h;
