@@ -135,36 +135,18 @@ constexpr int kPackW2 = kPackW1 + 128 * 16;
 constexpr int kPackW3 = kPackW2 + 128 * 128;
 constexpr int kPackSize = kPackW3 + 128 * 128;
 
-template <int N>
-__device__ __forceinline__ void stage_packed(Smem& S, const unsigned short* Q) {
-  constexpr int V = N / 8, IT = (V + NT - 1) / NT;
-  const uint4* src = reinterpret_cast<const uint4*>(Q);
-  uint4* dst = reinterpret_cast<uint4*>(S.w);
-  uint4 r[IT];
-#pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int t = threadIdx.x + i * NT;
-    if (t < V) r[i] = src[t];
-  }
-#pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int t = threadIdx.x + i * NT;
-    if (t < V) dst[t] = r[i];
-  }
-}
-
 // Layers 1-3 of the forward pass on S.x (already standardised, bf16); weights staged from
-// the FP32 masters P, or from the packed image Q when given.
-__device__ __forceinline__ void hidden_layers(Smem& S, const float* P, const unsigned short* Q) {
-  if (Q) stage_packed<128 * 16>(S, Q + kPackW1); else stage_weights(S, P + kOffW1, kSurIn, 16);
+// the FP32 masters P.
+__device__ __forceinline__ void hidden_layers(Smem& S, const float* P) {
+  stage_weights(S, P + kOffW1, kSurIn, 16);
   __syncthreads();
   dense_gelu(S, S.x, 16, P + kOffB1, S.z[0], S.h[0]);
   __syncthreads();
-  if (Q) stage_packed<128 * 128>(S, Q + kPackW2); else stage_weights(S, P + kOffW2, 128, 128);
+  stage_weights(S, P + kOffW2, 128, 128);
   __syncthreads();
   dense_gelu(S, S.h[0], 128, P + kOffB2, S.z[1], S.h[1]);
   __syncthreads();
-  if (Q) stage_packed<128 * 128>(S, Q + kPackW3); else stage_weights(S, P + kOffW3, 128, 128);
+  stage_weights(S, P + kOffW3, 128, 128);
   __syncthreads();
   dense_gelu(S, S.h[1], 128, P + kOffB3, S.z[2], S.h[2]);
   __syncthreads();
@@ -185,7 +167,7 @@ __device__ __forceinline__ void forward_tile(Smem& S, const float* P, const floa
     }
     S.x[t] = f2bf(v);
   }
-  hidden_layers(S, P, nullptr);
+  hidden_layers(S, P);
 }
 
 // dW (kin x 128) += Hin^T dZ for the 32-row tile (rows i < nin), with atomics
@@ -373,10 +355,58 @@ __global__ void pack_weights_kernel(const float* __restrict__ P, unsigned short*
   }
 }
 
+// Inference-only shared memory: all three packed weight matrices at once, activations
+// ping-ponged between two buffers, no pre-activations kept.
+struct SmemInfer {
+  unsigned short x[TB * 16];
+  unsigned short h[2][TB * 128];
+  alignas(16) unsigned short w[kPackSize];   // W1 | W2 | W3 as packed ([out][in])
+  float b[3][128];                           // b1, b2, b3
+  float tail[kSurBlob - kOffW4];             // the FP32 blob from W4 on (W4, b4, scalers)
+  float y[TB];
+};
+
+// acc += A(16 x K) * B(K x 16) with A = act[row][k] and B(k, n) = W[n][k], both bf16 rows of
+// length K in LDS: each lane's four consecutive k of a row are one 8-byte read. Same
+// operands, in the same order, as mma16 with (sam, sak) = (K, 1) and (sbk, sbn) = (1, K).
+template <int K>
+__device__ __forceinline__ f32x4 mma16_rows(const unsigned short* A, const unsigned short* W,
+                                            f32x4 acc) {
+  const int l = threadIdx.x & 63, r = l & 15, kb = (l >> 4) << 2;
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const bf16x4 a = *reinterpret_cast<const bf16x4*>(A + r * K + k0 + kb);
+    const bf16x4 b = *reinterpret_cast<const bf16x4*>(W + r * K + k0 + kb);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// GELU(H W + b) (bf16) for the 32 x 128 tile, as dense_gelu without keeping Z
+template <int K>
+__device__ __forceinline__ void dense_gelu_rows(const unsigned short* Hin,
+                                                const unsigned short* W, const float* bias,
+                                                unsigned short* Hout) {
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int t = wv; t < 16; t += NT / 64) {
+    const int mt = t >> 3, nt = t & 7;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mma16_rows<K>(Hin + mt * 16 * K, W + nt * 16 * K, acc);
+    const int col = nt * 16 + (l & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = mt * 16 + ((l >> 4) << 2) + q;
+      Hout[row * 128 + col] = f2bf(gelu(acc[q] + bias[col]));
+    }
+  }
+}
+
 // Network inference for the bins of one box, TB bins per workgroup: the features from
 // P_cdm (already reduced from the deposit's partial sums) and the stored history, then the
-// forward pass on the matrix cores. Writes the network's R (NaN where the inputs are
-// unusable) with its use flag; in mode 1 it also finishes the bins it can answer.
+// forward pass on the matrix cores. The loads of the whole packed weight image go out
+// first, so that they are in flight while the features are gathered. Writes the network's
+// R (NaN where the inputs are unusable) with its use flag; in mode 1 it also finishes the
+// bins it can answer. The arithmetic is that of the training kernels' forward pass.
 __global__ __launch_bounds__(NT) void surrogate_infer_kernel(
     const float* __restrict__ P, const unsigned short* __restrict__ Q, int mode,
     const RespBox* __restrict__ boxes, const double* __restrict__ counts,
@@ -384,12 +414,42 @@ __global__ __launch_bounds__(NT) void surrogate_infer_kernel(
     double* __restrict__ hist_pnu, int nbins, int jcap, const double* __restrict__ pcdm,
     double* __restrict__ pnu_out, double* __restrict__ ratio_out, double* __restrict__ sur_r,
     int* __restrict__ sur_use) {
-  __shared__ Smem S;
+  __shared__ SmemInfer S;
   __shared__ double ph_s[TB];
   __shared__ int ok_s[TB];
   const int tid = threadIdx.x;
   const int box = blockIdx.y, b0 = blockIdx.x * TB;
   const int cnt = min(TB, nbins - b0);
+  constexpr int WV = kPackSize / 8, WIT = (WV + NT - 1) / NT;   // 16-byte pieces
+  constexpr int TV = kSurBlob - kOffW4;
+  static_assert(3 * 128 + TV <= 3 * NT, "three values per thread");
+  uint4 wr[WIT];
+  float pr[3];
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(Q);
+#pragma unroll
+    for (int i = 0; i < WIT; ++i) {
+      const int t = tid + i * NT;
+      if (t < WV) wr[i] = src[t];
+    }
+    // slot t of 3 * 128 + TV: the biases, then the tail of the blob
+    auto src_of = [&](int t) {
+      return t < 128 ? kOffB1 + t : t < 256 ? kOffB2 + t - 128
+                                            : t < 384 ? kOffB3 + t - 256 : kOffW4 + t - 384;
+    };
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int t = tid + i * NT;
+      if (t < 384 + TV) pr[i] = P[src_of(t)];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int t = tid + i * NT;
+      if (t < 384) S.b[t / 128][t % 128] = pr[i];
+      else if (t < 384 + TV) S.tail[t - 384] = pr[i];
+    }
+  }
+  const float* Ps = S.tail - kOffW4;         // blob offsets from W4 on, in LDS
   const RespBox bx = boxes[box];
   double* hpm = hist_pm + static_cast<size_t>(box) * jcap * nbins;
   double* hpn = hist_pnu + static_cast<size_t>(box) * jcap * nbins;
@@ -400,19 +460,46 @@ __global__ __launch_bounds__(NT) void surrogate_infer_kernel(
     bool ok = false;
     if (tid < cnt && counts[b0 + tid] > 0.0)
       ok = make_features(bx, kmean[b0 + tid], ph_s[tid], hpm, nbins, b0 + tid, f) &&
-           in_range(P, f);
+           in_range(Ps, f);
     ok_s[tid] = ok ? 1 : 0;
     for (int i = 0; i < 16; ++i)
       S.x[tid * 16 + i] =
-          f2bf(ok && i < kSurIn ? (f[i] - P[kOffMu + i]) / P[kOffSigma + i] : 0.f);
+          f2bf(ok && i < kSurIn ? (f[i] - Ps[kOffMu + i]) / Ps[kOffSigma + i] : 0.f);
   }
-  hidden_layers(S, P, Q);   // begins with a barrier-protected staging step
+  {
+    uint4* dst = reinterpret_cast<uint4*>(S.w);
+#pragma unroll
+    for (int i = 0; i < WIT; ++i) {
+      const int t = tid + i * NT;
+      if (t < WV) dst[t] = wr[i];
+    }
+  }
+  __syncthreads();
+  dense_gelu_rows<16>(S.x, S.w + kPackW1, S.b[0], S.h[0]);
+  __syncthreads();
+  dense_gelu_rows<128>(S.h[0], S.w + kPackW2, S.b[1], S.h[1]);
+  __syncthreads();
+  dense_gelu_rows<128>(S.h[1], S.w + kPackW3, S.b[2], S.h[0]);
+  __syncthreads();
+  {
+    // output layer: 8 lanes per sample, 16 products each, FP32 (as output_layer)
+    const int s = tid >> 3, part = tid & 7;
+    float acc = 0.f;
+#pragma unroll
+    for (int j = part * 16; j < part * 16 + 16; ++j)
+      acc += bf2f(S.h[0][s * 128 + j]) * bfr(Ps[kOffW4 + j]);
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 4, 64);
+    if (part == 0) S.y[s] = acc + Ps[kOffB4];
+  }
+  __syncthreads();
   if (tid < cnt) {
     const int b = b0 + tid;
     const size_t ob = static_cast<size_t>(box) * nbins + b;
     const bool ok = ok_s[tid] != 0;
     const double k = kmean[b];
-    const double r = ok ? exp(static_cast<double>(S.y[tid] * P[kOffYSigma] + P[kOffYMu])) *
+    const double r = ok ? exp(static_cast<double>(S.y[tid] * Ps[kOffYSigma] + Ps[kOffYMu])) *
                               approx_factor(k, bx.kfs)
                         : __builtin_nan("");
     sur_r[ob] = r;
