@@ -9,11 +9,11 @@
 // dZ rounded to bfloat16 as MFMA operand), and adds its share of the gradient to an FP32
 // buffer with global atomics. adam_kernel applies one Adam step to the FP32 masters.
 //
-// Inside the step the network sees one row per k-bin: surrogate_infer_kernel takes the
-// bins of a box in tiles of 32 rows through the same MFMA forward pass, with the weights
-// staged from a bfloat16 image packed once per weight change, and a second kernel falls
-// back to the exact integral (response_device.hpp) for the bins whose inputs are outside
-// the training range (or for every bin when checking).
+// Inside the step the network sees one row per k-bin: surrogate_response_kernel, one
+// workgroup per (bin, box), forms P_cdm, takes the bin's row through the same MFMA forward
+// pass with the weights staged at once from a bfloat16 image packed once per weight
+// change, and falls back to the exact integral (response_device.hpp) in the same
+// workgroup when the inputs are outside the training range (or when checking).
 #include "response_device.hpp"
 #include "surrogate_layout.hpp"
 
@@ -355,15 +355,15 @@ __global__ void pack_weights_kernel(const float* __restrict__ P, unsigned short*
   }
 }
 
-// Inference-only shared memory: all three packed weight matrices at once, activations
-// ping-ponged between two buffers, no pre-activations kept.
+// Inference-only shared memory for one bin: all three packed weight matrices at once, the
+// biases and the tail of the blob, activations of one 16-row tile ping-ponged.
 struct SmemInfer {
-  unsigned short x[TB * 16];
-  unsigned short h[2][TB * 128];
+  unsigned short x[16 * 16];
+  unsigned short h[2][16 * 128];
   alignas(16) unsigned short w[kPackSize];   // W1 | W2 | W3 as packed ([out][in])
   float b[3][128];                           // b1, b2, b3
   float tail[kSurBlob - kOffW4];             // the FP32 blob from W4 on (W4, b4, scalers)
-  float y[TB];
+  float y;
 };
 
 // acc += A(16 x K) * B(K x 16) with A = act[row][k] and B(k, n) = W[n][k], both bf16 rows of
@@ -382,69 +382,70 @@ __device__ __forceinline__ f32x4 mma16_rows(const unsigned short* A, const unsig
   return acc;
 }
 
-// GELU(H W + b) (bf16) for the 32 x 128 tile, as dense_gelu without keeping Z
+// GELU(H W + b) (bf16) for one 16 x 128 tile of rows, as dense_gelu without keeping Z
 template <int K>
 __device__ __forceinline__ void dense_gelu_rows(const unsigned short* Hin,
                                                 const unsigned short* W, const float* bias,
                                                 unsigned short* Hout) {
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int t = wv; t < 16; t += NT / 64) {
-    const int mt = t >> 3, nt = t & 7;
+  for (int nt = wv; nt < 8; nt += RT / 64) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    acc = mma16_rows<K>(Hin + mt * 16 * K, W + nt * 16 * K, acc);
+    acc = mma16_rows<K>(Hin, W + nt * 16 * K, acc);
     const int col = nt * 16 + (l & 15);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int row = mt * 16 + ((l >> 4) << 2) + q;
+      const int row = ((l >> 4) << 2) + q;
       Hout[row * 128 + col] = f2bf(gelu(acc[q] + bias[col]));
     }
   }
 }
 
-// Network inference for the bins of one box, TB bins per workgroup: the features from
-// P_cdm (already reduced from the deposit's partial sums) and the stored history, then the
-// forward pass on the matrix cores. The loads of the whole packed weight image go out
-// first, so that they are in flight while the features are gathered. Writes the network's
-// R (NaN where the inputs are unusable) with its use flag; in mode 1 it also finishes the
-// bins it can answer. The arithmetic is that of the training kernels' forward pass.
-__global__ __launch_bounds__(NT) void surrogate_infer_kernel(
+// The surrogate's response, one workgroup per (bin, box): P_cdm from the deposit's partial
+// sums, the network's R for the bin (features from P_cdm and the stored history, forward
+// pass on the matrix cores; the arithmetic of the training kernels' forward pass), and the
+// exact integral (response_device.hpp) when the network cannot answer (inputs outside the
+// training range) or when checking (mode 2, which keeps the exact result and records
+// both). The whole packed weight image is staged first (one unrolled copy: the compiler
+// issues the loads ahead of the LDS stores).
+__global__ __launch_bounds__(RT) void surrogate_response_kernel(
     const float* __restrict__ P, const unsigned short* __restrict__ Q, int mode,
-    const RespBox* __restrict__ boxes, const double* __restrict__ counts,
-    const double* __restrict__ kmean, double* __restrict__ hist_pm,
-    double* __restrict__ hist_pnu, int nbins, int jcap, const double* __restrict__ pcdm,
+    const RespBox* __restrict__ boxes, const double* __restrict__ partial, int n_partial,
+    const double* __restrict__ counts, const double* __restrict__ kmean,
+    double* __restrict__ hist_pm, double* __restrict__ hist_pnu,
+    const double* __restrict__ ic_pnu, const double* __restrict__ ic_theta,
+    const double* __restrict__ tg_ds, const double* __restrict__ tg_w, int nbins, int jcap,
+    int qcap, int q_sub, int iterations, double norm, double* __restrict__ pcdm_out,
     double* __restrict__ pnu_out, double* __restrict__ ratio_out, double* __restrict__ sur_r,
-    int* __restrict__ sur_use) {
+    int* __restrict__ sur_use, double* __restrict__ chk_exact, double* __restrict__ chk_sur) {
   __shared__ SmemInfer S;
-  __shared__ double ph_s[TB];
-  __shared__ int ok_s[TB];
+  __shared__ double red[2 * RT / 64];
+  __shared__ int s_ok;
   const int tid = threadIdx.x;
-  const int box = blockIdx.y, b0 = blockIdx.x * TB;
-  const int cnt = min(TB, nbins - b0);
-  constexpr int WV = kPackSize / 8, WIT = (WV + NT - 1) / NT;   // 16-byte pieces
+  const int b = blockIdx.x, box = blockIdx.y;
+  const size_t ob = static_cast<size_t>(box) * nbins + b;
+  constexpr int WV = kPackSize / 8, WIT = (WV + RT - 1) / RT;   // 16-byte pieces
   constexpr int TV = kSurBlob - kOffW4;
-  static_assert(3 * 128 + TV <= 3 * NT, "three values per thread");
-  uint4 wr[WIT];
-  float pr[3];
+  static_assert(3 * 128 + TV <= 3 * RT, "three values per thread");
   {
+    static_assert(WV % RT == 0, "whole rounds");
     const uint4* src = reinterpret_cast<const uint4*>(Q);
+    uint4* dst = reinterpret_cast<uint4*>(S.w);
 #pragma unroll
-    for (int i = 0; i < WIT; ++i) {
-      const int t = tid + i * NT;
-      if (t < WV) wr[i] = src[t];
-    }
+    for (int i = 0; i < WIT; ++i) dst[tid + i * RT] = src[tid + i * RT];
     // slot t of 3 * 128 + TV: the biases, then the tail of the blob
     auto src_of = [&](int t) {
       return t < 128 ? kOffB1 + t : t < 256 ? kOffB2 + t - 128
                                             : t < 384 ? kOffB3 + t - 256 : kOffW4 + t - 384;
     };
+    float pr[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const int t = tid + i * NT;
+      const int t = tid + i * RT;
       if (t < 384 + TV) pr[i] = P[src_of(t)];
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const int t = tid + i * NT;
+      const int t = tid + i * RT;
       if (t < 384) S.b[t / 128][t % 128] = pr[i];
       else if (t < 384 + TV) S.tail[t - 384] = pr[i];
     }
@@ -453,103 +454,77 @@ __global__ __launch_bounds__(NT) void surrogate_infer_kernel(
   const RespBox bx = boxes[box];
   double* hpm = hist_pm + static_cast<size_t>(box) * jcap * nbins;
   double* hpn = hist_pnu + static_cast<size_t>(box) * jcap * nbins;
-  if (tid < cnt) ph_s[tid] = sqrt(pcdm[static_cast<size_t>(box) * nbins + b0 + tid]);
-  __syncthreads();
-  if (tid < TB) {
-    float f[kSurIn];
-    bool ok = false;
-    if (tid < cnt && counts[b0 + tid] > 0.0)
-      ok = make_features(bx, kmean[b0 + tid], ph_s[tid], hpm, nbins, b0 + tid, f) &&
-           in_range(Ps, f);
-    ok_s[tid] = ok ? 1 : 0;
-    for (int i = 0; i < 16; ++i)
-      S.x[tid * 16 + i] =
-          f2bf(ok && i < kSurIn ? (f[i] - Ps[kOffMu + i]) / Ps[kOffSigma + i] : 0.f);
-  }
-  {
-    uint4* dst = reinterpret_cast<uint4*>(S.w);
-#pragma unroll
-    for (int i = 0; i < WIT; ++i) {
-      const int t = tid + i * NT;
-      if (t < WV) dst[t] = wr[i];
-    }
-  }
-  __syncthreads();
-  dense_gelu_rows<16>(S.x, S.w + kPackW1, S.b[0], S.h[0]);
-  __syncthreads();
-  dense_gelu_rows<128>(S.h[0], S.w + kPackW2, S.b[1], S.h[1]);
-  __syncthreads();
-  dense_gelu_rows<128>(S.h[1], S.w + kPackW3, S.b[2], S.h[0]);
-  __syncthreads();
-  {
-    // output layer: 8 lanes per sample, 16 products each, FP32 (as output_layer)
-    const int s = tid >> 3, part = tid & 7;
-    float acc = 0.f;
-#pragma unroll
-    for (int j = part * 16; j < part * 16 + 16; ++j)
-      acc += bf2f(S.h[0][s * 128 + j]) * bfr(Ps[kOffW4 + j]);
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
-    acc += __shfl_xor(acc, 4, 64);
-    if (part == 0) S.y[s] = acc + Ps[kOffB4];
-  }
-  __syncthreads();
-  if (tid < cnt) {
-    const int b = b0 + tid;
-    const size_t ob = static_cast<size_t>(box) * nbins + b;
-    const bool ok = ok_s[tid] != 0;
-    const double k = kmean[b];
-    const double r = ok ? exp(static_cast<double>(S.y[tid] * Ps[kOffYSigma] + Ps[kOffYMu])) *
-                              approx_factor(k, bx.kfs)
-                        : __builtin_nan("");
-    sur_r[ob] = r;
-    sur_use[ob] = ok ? 1 : 0;
-    if (ok && mode == 1) {
-      const double ph = ph_s[tid], pnu = r * ph;
-      pnu_out[ob] = pnu;
-      ratio_out[ob] = r;
-      hpm[static_cast<size_t>(bx.n_cur) * nbins + b] = (1.0 - bx.f_nu) * ph + bx.f_nu * pnu;
-      hpn[static_cast<size_t>(bx.n_cur) * nbins + b] = pnu;
-    }
-  }
-}
-
-// One workgroup per (bin, box): the exact integral for the bins the network did not answer
-// (mode 1) or for every bin (mode 2, which keeps the exact result and records both).
-__global__ __launch_bounds__(RT) void surrogate_finish_kernel(
-    int mode, const RespBox* __restrict__ boxes, const double* __restrict__ counts,
-    const double* __restrict__ kmean, double* __restrict__ hist_pm,
-    double* __restrict__ hist_pnu, const double* __restrict__ ic_pnu,
-    const double* __restrict__ ic_theta, const double* __restrict__ tg_ds,
-    const double* __restrict__ tg_w, int nbins, int jcap, int qcap, int q_sub, int iterations,
-    const double* __restrict__ pcdm_in, double* __restrict__ pnu_out,
-    double* __restrict__ ratio_out, const double* __restrict__ sur_r,
-    const int* __restrict__ sur_use, double* __restrict__ chk_exact,
-    double* __restrict__ chk_sur) {
-  __shared__ double red[2 * RT / 64];
-  const int b = blockIdx.x, box = blockIdx.y;
-  const size_t ob = static_cast<size_t>(box) * nbins + b;
-  const bool net = sur_use[ob] != 0;
-  if (mode == 1 && net) return;                   // answered by the network
-  const RespBox bx = boxes[box];
-  double* hpm = hist_pm + static_cast<size_t>(box) * jcap * nbins;
-  double* hpn = hist_pnu + static_cast<size_t>(box) * jcap * nbins;
   const size_t row = static_cast<size_t>(bx.n_cur) * nbins + b;
-  if (!(counts[b] > 0.0)) {
-    if (threadIdx.x == 0) {
+  const double cb = counts[b];
+  const double msum = bin_mode_sum(partial, n_partial, nbins, box, b, red);   // has barriers
+  const double pcdm = cb > 0.0 ? norm * msum / cb : 0.0;
+  if (!(cb > 0.0)) {
+    if (tid == 0) {
+      pcdm_out[ob] = 0.0;
+      sur_r[ob] = __builtin_nan("");
+      sur_use[ob] = 0;
       pnu_out[ob] = ratio_out[ob] = 0.0;
       hpm[row] = hpn[row] = 0.0;
       if (chk_exact) chk_exact[ob] = chk_sur[ob] = 0.0;
     }
     return;
   }
-  const double ph = sqrt(pcdm_in[ob]);
-  const double pnu = exact_pnu(bx, kmean[b], ph, (bx.n_cur > 0 ? hpn[static_cast<size_t>(bx.n_cur - 1) * nbins + b] : 0.0),
+  const double ph = sqrt(pcdm);
+  if (tid == 0) {
+    float f[kSurIn];
+    const bool ok = make_features(bx, kmean[b], ph, hpm, nbins, b, f) && in_range(Ps, f);
+    s_ok = ok ? 1 : 0;
+    for (int i = 0; i < 16; ++i)
+      S.x[i] = f2bf(ok && i < kSurIn ? (f[i] - Ps[kOffMu + i]) / Ps[kOffSigma + i] : 0.f);
+  } else if (tid < 16 * 16) {
+    S.x[tid] = 0;                            // rows 1..15 of the tile
+  }
+  __syncthreads();
+  const bool ok = s_ok != 0;
+  double r_net = __builtin_nan("");
+  if (ok) {
+    dense_gelu_rows<16>(S.x, S.w + kPackW1, S.b[0], S.h[0]);
+    __syncthreads();
+    dense_gelu_rows<128>(S.h[0], S.w + kPackW2, S.b[1], S.h[1]);
+    __syncthreads();
+    dense_gelu_rows<128>(S.h[1], S.w + kPackW3, S.b[2], S.h[0]);
+    __syncthreads();
+    if (tid < 8) {
+      // output layer: 8 lanes, 16 products each, FP32 (as output_layer)
+      float acc = 0.f;
+#pragma unroll
+      for (int j = tid * 16; j < tid * 16 + 16; ++j)
+        acc += bf2f(S.h[0][j]) * bfr(Ps[kOffW4 + j]);
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      acc += __shfl_xor(acc, 4, 64);
+      if (tid == 0) S.y = acc + Ps[kOffB4];
+    }
+    __syncthreads();
+    r_net = exp(static_cast<double>(S.y * Ps[kOffYSigma] + Ps[kOffYMu])) *
+            approx_factor(kmean[b], bx.kfs);
+  }
+  if (tid == 0) {
+    pcdm_out[ob] = pcdm;
+    sur_r[ob] = r_net;
+    sur_use[ob] = ok ? 1 : 0;
+  }
+  if (ok && mode == 1) {                     // answered by the network
+    if (tid == 0) {
+      const double pnu = r_net * ph;
+      pnu_out[ob] = pnu;
+      ratio_out[ob] = r_net;
+      hpm[row] = (1.0 - bx.f_nu) * ph + bx.f_nu * pnu;
+      hpn[row] = pnu;
+    }
+    return;
+  }
+  const double pnu = exact_pnu(bx, kmean[b], ph, (bx.n_cur > 0 ? hpn[row - nbins] : 0.0),
                                ic_pnu + static_cast<size_t>(box) * kMaxSpecies * nbins,
                                ic_theta[ob], hpm, nbins, b,
                                tg_ds + static_cast<size_t>(box) * qcap,
                                tg_w + static_cast<size_t>(box) * qcap, q_sub, iterations, red);
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     const double r = pnu / ph;
     pnu_out[ob] = pnu;
     ratio_out[ob] = r;
@@ -557,7 +532,7 @@ __global__ __launch_bounds__(RT) void surrogate_finish_kernel(
     hpn[row] = pnu;
     if (chk_exact) {
       chk_exact[ob] = r;
-      chk_sur[ob] = net ? sur_r[ob] : r;
+      chk_sur[ob] = ok ? r_net : r;
     }
   }
 }
@@ -622,17 +597,10 @@ hipError_t launch_surrogate_response(const float* P, const unsigned short* Q, in
                                      double* pcdm, double* pnu, double* ratio, double* sur_r,
                                      int* sur_use, double* chk_exact, double* chk_sur,
                                      hipStream_t s) {
-  hipError_t e = launch_bin_power(partial, n_partial, counts, nbins, norm, nbox, pcdm, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(surrogate_infer_kernel, dim3((nbins + TB - 1) / TB, nbox), dim3(NT), 0, s,
-                     P, Q, mode, boxes, counts, kmean, hist_pm, hist_pnu, nbins, jcap, pcdm, pnu,
-                     ratio, sur_r, sur_use);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(surrogate_finish_kernel, dim3(nbins, nbox), dim3(RT), 0, s, mode, boxes,
-                     counts, kmean, hist_pm, hist_pnu, ic_pnu, ic_theta, tg_ds, tg_w, nbins,
-                     jcap, qcap, q_sub, iterations, pcdm, pnu, ratio, sur_r, sur_use, chk_exact,
-                     chk_sur);
+  hipLaunchKernelGGL(surrogate_response_kernel, dim3(nbins, nbox), dim3(RT), 0, s, P, Q, mode,
+                     boxes, partial, n_partial, counts, kmean, hist_pm, hist_pnu, ic_pnu,
+                     ic_theta, tg_ds, tg_w, nbins, jcap, qcap, q_sub, iterations, norm, pcdm,
+                     pnu, ratio, sur_r, sur_use, chk_exact, chk_sur);
   return hipGetLastError();
 }
 
