@@ -471,25 +471,18 @@ __global__ __launch_bounds__(NT) void inv_z_kernel(const float2* __restrict__ g1
   }
   __syncthreads();
   fft_lines<N, NL, NT, +1>(lds, tw);
-  // interleaved output: (g_x, g_y, g_z) of node (x, y, z) are 3 consecutive floats; a
-  // thread writes 4 consecutive nodes of one row as three float4
-  float4* dst = reinterpret_cast<float4*>(out + ((static_cast<size_t>(box) * N + x) * N + y0) * N * 3);
-  constexpr int QUADS = TY * N / 4;
-  for (int q = threadIdx.x; q < QUADS; q += NT) {
-    const int y = q / (N / 4), z0 = 4 * (q % (N / 4));
-    float o[12];
+  // interleaved output: (g_x, g_y, g_z) of node (x, y, z) are 3 consecutive floats. One
+  // lane per node, consecutive lanes at consecutive z: the LDS reads of a wave then fall in
+  // distinct banks (four nodes per lane, as float4 stores, put a wave's reads on 8 banks)
+  float* dst = out + ((static_cast<size_t>(box) * N + x) * N + y0) * N * 3;
+  constexpr int NODES = TY * N;
+  for (int n = threadIdx.x; n < NODES; n += NT) {
+    const int y = n / N, z = n % N;
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
-      const int row = comp * TY + y, p = row >> 1;
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const float2 zz = lds[(z0 + h) * ES + p];
-        o[3 * h + comp] = (row & 1) ? zz.y : zz.x;
-      }
+      const int row = comp * TY + y;
+      dst[3 * n + comp] = ldsf[(z * ES + (row >> 1)) * 2 + (row & 1)];
     }
-    dst[3 * q] = make_float4(o[0], o[1], o[2], o[3]);
-    dst[3 * q + 1] = make_float4(o[4], o[5], o[6], o[7]);
-    dst[3 * q + 2] = make_float4(o[8], o[9], o[10], o[11]);
   }
 }
 
