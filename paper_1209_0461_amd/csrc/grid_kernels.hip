@@ -428,10 +428,33 @@ __global__ __launch_bounds__(NT) void deposit_patch_kernel(
       }
     }
     __syncthreads();
+    // the patch (the box unpadded): consecutive lanes at consecutive nodes, four nodes per
+    // thread per round with their LDS reads ahead of the stores. Node li of the box is
+    // (tx, ty, tz) = (li / (ey ez), li / ez % ey, li % ez); the FP32 quotients are exact
+    // (li < 2^14 and the fractional part of (li + 1/2) / e is at least 1 / (2e)).
     unsigned long long* pat = patches + chunk * kPatchCap;     // stored patch stride
-    for_box_nodes<NT>(ex, ey, ez, [&](int tx, int ty, int tz, int li) {
-      pat[li] = tile[(tx * sy + ty) * sz + tz];
-    });
+    {
+      const int volp = ex * ey * ez;
+      const float inv_ez = 1.0f / static_cast<float>(ez), inv_ey = 1.0f / static_cast<float>(ey);
+      for (int l0 = tid; l0 < volp; l0 += 4 * NT) {
+        unsigned long long val[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int li = l0 + u * NT;
+          val[u] = 0ull;
+          if (li < volp) {
+            const int t = static_cast<int>((static_cast<float>(li) + 0.5f) * inv_ez);
+            const int tz = li - t * ez;
+            const int tx = static_cast<int>((static_cast<float>(t) + 0.5f) * inv_ey);
+            const int ty = t - tx * ey;
+            val[u] = tile[(tx * sy + ty) * sz + tz];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (l0 + u * NT < volp) pat[l0 + u * NT] = val[u];
+      }
+    }
     const unsigned over = s_over;
     if (over == 0u) return;
     // coarse cells whose list was full: the box's part in them goes to the side grid
