@@ -44,7 +44,7 @@ template <int N> struct Shape {
   static constexpr int FY_NL = N <= 256 ? (N < 16 ? N : 16) : 8;      // rows per WG
   static constexpr int FX_TX = N < 16 ? N : (N <= 256 ? 16 : 8);      // ky columns per WG
   static constexpr int IX_TX = N < 16 ? N : 8;
-  static constexpr int IY_NL = N < 8 ? N : (N <= 256 ? 8 : 4);
+  static constexpr int IY_NL = N < 8 ? N : 4;
   static constexpr int IZ_TY = N < 16 ? N : (N <= 256 ? 16 : 8);
 };
 
