@@ -203,7 +203,8 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
  * deposit_block = threads per workgroup), 1..5 (LDS-privatised chunks of 1024/2048/4096
  * particles on 256 threads, 4096 on 512 threads, 8192 on 1024 threads, flushed with global
  * atomics), 6 (chunks of 4096 written to per-chunk patches and summed per 16^3 coarse
- * cell without atomics; chunks whose box exceeds 6144 nodes use atomics on a side grid) or
+ * cell without atomics; a chunk whose box exceeds 6144 nodes, or its part in a coarse cell
+ * already listing 32 patches, goes through atomics on a side grid) or
  * 7 (as 6 with room for boxes of 9216 nodes, at lower occupancy), interp_mode
  * 0 (direct gather; interp_block = particles per workgroup, rounded down to 256, 512 or
  * 1024) or 1/2/3 (LDS-staged chunks). Blocks: multiples of 64 in 64..1024. Until this or
