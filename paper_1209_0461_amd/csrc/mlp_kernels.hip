@@ -476,8 +476,8 @@ __global__ __launch_bounds__(RT) void surrogate_response_kernel(
     s_ok = ok ? 1 : 0;
     for (int i = 0; i < 16; ++i)
       S.x[i] = f2bf(ok && i < kSurIn ? (f[i] - Ps[kOffMu + i]) / Ps[kOffSigma + i] : 0.f);
-  } else if (tid < 16 * 16) {
-    S.x[tid] = 0;                            // rows 1..15 of the tile
+  } else if (tid >= 16 && tid < 16 * 16) {
+    S.x[tid] = 0;                            // rows 1..15 of the tile (row 0: thread 0)
   }
   __syncthreads();
   const bool ok = s_ok != 0;
