@@ -533,10 +533,17 @@ __global__ __launch_bounds__(256) void patch_reduce_kernel(
   const int slabs = cb / XD;
   const int64_t cells = static_cast<int64_t>(nc) * nc * nc;
   const int64_t box = blockIdx.y;
-  const int cix = blockIdx.x / slabs;
+  // workgroups go to the 8 XCDs in turn: each XCD takes a contiguous run of slabs instead,
+  // so that neighbouring cells (which read the same patches' halo lines) share an L2; a
+  // ragged tail keeps its own index
+  const int nb = gridDim.x, per = nb / 8;
+  const int bid = static_cast<int>(blockIdx.x) < per * 8
+                      ? static_cast<int>(blockIdx.x % 8) * per + static_cast<int>(blockIdx.x / 8)
+                      : static_cast<int>(blockIdx.x);
+  const int cix = bid / slabs;
   const int64_t cell = box * cells + cix;
   const int ccz = (cix % nc) << cb_lg, ccy = ((cix / nc) % nc) << cb_lg,
-            ccx = ((cix / (nc * nc)) << cb_lg) + (blockIdx.x - cix * slabs) * XD;  // slab's x0
+            ccx = ((cix / (nc * nc)) << cb_lg) + (bid - cix * slabs) * XD;  // slab's x0
   const int iy = tid >> cb_lg, iz = tid & (cb - 1);
   const bool on = tid < cb * cb;
   const int vol_cell = XD * cb * cb;
