@@ -81,7 +81,8 @@ def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
     hist_a (n,), hist_pm_half (n, B): stored nodes strictly before a_now (hist_a[0] = a_i).
     pnu_half_prev (B,): P_nu^{1/2} at the last stored node (the first-iteration guess).
     Returns dict: pnu_half, ratio = P_nu^{1/2}/P_cdm^{1/2}, pm_half_now (the node to store),
-    f_nu. Empty bins (counts == 0) give 0 everywhere. Without massive neutrinos
+    f_nu. Empty bins (counts == 0) give 0 everywhere; a bin with P_cdm = 0 (no CDM mode to
+    put the neutrinos in phase with, eq. (phases)) has R = 0. Without massive neutrinos
     (m_nu_total = 0, so f_nu = 0) the neutrino term of Sec. 4.3 (iv) drops out: P_nu^{1/2}
     and R are reported as 0 and the stored node is P_cdm^{1/2}.
 
@@ -153,7 +154,10 @@ def nu_amplitude(k_mean, counts, pcdm_half, hist_a, hist_pm_half, pnu_half_prev,
         pnu = ic + integral
         pnu_guess = pnu
     pnu = np.where(ok, pnu, 0.0)
-    ratio = np.where(ok, pnu / np.where(ok, pcdm_half, 1.0), 0.0)
+    # R_b carries the neutrino amplitude on the CDM modes of the bin (eq. (phases)); a bin
+    # whose CDM modes are all zero has no phase to carry it, and R_b reads 0 there
+    has_cdm = ok & (pcdm_half > 0.0)
+    ratio = np.where(has_cdm, pnu / np.where(has_cdm, pcdm_half, 1.0), 0.0)
     pm_now = np.where(ok, (1.0 - fn) * pcdm_half + fn * pnu, 0.0)
     return dict(pnu_half=pnu, ratio=ratio, pm_half_now=pm_now, f_nu=fn)
 

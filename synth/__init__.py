@@ -8,7 +8,8 @@ Everything it returns is plain NumPy data that both the HIP library and the FP64
 consume unchanged.
 """
 from .ics import zeldovich_lattice, zeldovich_ics, batched_lattices, morton_codes, CONFIGS
-from .history import synthetic_history, log_spaced_nodes
+from .history import synthetic_history, log_spaced_nodes, growth_history, free_streaming_ic
 
 __all__ = ["zeldovich_lattice", "zeldovich_ics", "batched_lattices", "morton_codes",
-           "synthetic_history", "log_spaced_nodes", "CONFIGS"]
+           "synthetic_history", "log_spaced_nodes", "growth_history", "free_streaming_ic",
+           "CONFIGS"]

@@ -65,6 +65,31 @@ def free_streaming_k(a, m_nu_single, om):
     return np.sqrt(1.5 * om_a * v2) * a * _H0 * e
 
 
+def growth_history(pcdm_half_now, a_nodes, omega_m=0.3):
+    """CDM amplitudes at every node (J, B): D(a_j) / D(a_now) times the amplitude now
+    (a_now = a_nodes[-1]), and the growing-mode [theta/delta]_i at a_nodes[0] (h/Mpc).
+
+    These are the CDM rows a self-consistent history is replayed from: the stored total
+    at each node is then computed by the method itself, node by node."""
+    amp_now = np.asarray(pcdm_half_now, dtype=np.float64)
+    a = np.asarray(a_nodes, dtype=np.float64)
+    d, f = growth(a, omega_m)
+    cdm = (d / d[-1])[:, None] * amp_now[None, :]
+    theta = -f[0] * a[0] * _H0 * _e(a[0], omega_m)
+    return np.ascontiguousarray(cdm), np.full(amp_now.shape, theta)
+
+
+def free_streaming_ic(k_mean, cdm_half_init, a_init, m_nu_total, omega_m=0.3, n_species=3):
+    """Initial neutrino amplitude: the CDM amplitude at a_init times Appendix A's simple
+    all-scale approximation 1 / (1 + k / k_fs(a_init))^2 (0 without neutrinos)."""
+    k = np.asarray(k_mean, dtype=np.float64)
+    m1 = m_nu_total / n_species
+    if m1 <= 0:
+        return np.zeros_like(k)
+    kfs = free_streaming_k(np.float64(a_init), m1, omega_m)
+    return np.asarray(cdm_half_init, dtype=np.float64) / (1.0 + k / kfs) ** 2
+
+
 def synthetic_history(k_mean, pcdm_half_now, a_nodes, m_nu_total, omega_m=0.3,
                       hubble=0.7, n_species=3):
     """History for the nodes ``a_nodes[:-1]``; ``a_nodes[-1]`` is the current step.

@@ -244,3 +244,101 @@ def test_pair_force_matches_ewald_sum(sep_cells, p0):
     ref = _ewald_acc(p1 - p0, box, c * box ** 3 / (4 * np.pi * 2))
     assert np.linalg.norm(acc[1] - ref) / np.linalg.norm(ref) < 0.025
     assert acc[1] @ (p0 - p1) > 0          # attractive
+
+
+# ----------------------------------- R(|k|) on every mode (eq. (phases), Sec. 4.3 (iv)) ----
+def _modes_lnk(n, box):
+    n2, _ = pm.mode_n2_and_weight(n)
+    with np.errstate(divide="ignore"):
+        return n2, np.log((2.0 * np.pi / box) * np.sqrt(n2.astype(np.float64)))
+
+
+@pytest.mark.parametrize("n,nb,n_empty", [(32, 32, 4), (64, 48, 6), (16, 8, 0)])
+def test_ratio_linear_in_ln_k_comes_back_on_every_mode(n, nb, n_empty):
+    """A bin ratio linear in ln k (R_b = alpha + beta ln kbar_b) is reproduced exactly on
+    every mode between the first and last non-empty bin means by interpolation in ln k
+    (not in k), and held at the end values outside them. Empty bins carry a huge value in
+    R, which must not reach any mode."""
+    box = 128.0
+    _, counts, kmean = pm.bin_geometry(n, box, nb)
+    ok = counts > 0
+    assert int((~ok).sum()) == n_empty
+    alpha, beta = 0.7, -0.15
+    lnkb = np.log(np.where(ok, kmean, 1.0))
+    ratio = np.where(ok, alpha + beta * lnkb, 1e6)
+    got = pm.ratio_on_modes(n, box, kmean, counts, ratio)
+    n2, lnk = _modes_lnk(n, box)
+    lo, hi = lnkb[ok][0], lnkb[ok][-1]
+    expect = alpha + beta * np.minimum(np.maximum(lnk, lo), hi)
+    nz = n2 > 0
+    assert np.abs(got[nz] - expect[nz]).max() < 1e-14
+    assert np.all(np.abs(got) < 2.0)                 # nothing from the empty bins
+    # modes above the last bin mean exist and take its value exactly
+    above = nz & (lnk > hi)
+    assert above.any() and np.all(got[above] == ratio[ok][-1])
+
+
+def test_ratio_on_modes_hand_computed_8_cubed():
+    """N = 8, L = 2 pi (so |k| = |n|), 8 bins. Counting the modes by hand:
+    bin 0 holds |n|^2 = 1 (6 modes), bin 1 |n|^2 = 2 (12), bin 2 |n|^2 = 3 (8) and 4 (6),
+    bin 3 |n|^2 = 5 (24) and 6 (24). Bin means: 1, sqrt 2, (8 sqrt 3 + 6*2)/14,
+    (sqrt 5 + sqrt 6)/2. The top mode |n|^2 = 48 lies above the last bin mean."""
+    n, box, nb = 8, 2.0 * np.pi, 8
+    edges, counts, kmean = pm.bin_geometry(n, box, nb)
+    assert list(edges[:5]) == [1, 2, 3, 5, 7]
+    assert list(counts[:4]) == [6, 12, 14, 48]
+    kb = np.array([1.0, np.sqrt(2.0), (8 * np.sqrt(3.0) + 12.0) / 14.0,
+                   (np.sqrt(5.0) + np.sqrt(6.0)) / 2.0])
+    assert np.allclose(kmean[:4], kb, rtol=1e-15)
+    ratio = np.array([1.0, 0.5, 0.25, 0.2, 0.15, 0.1, 0.08, 0.05])
+    got = pm.ratio_on_modes(n, box, kmean, counts, ratio)
+    nx, ny, nz = pm.mode_indices(n)
+    n2 = nx * nx + ny * ny + nz * nz
+    # single-shell bins: the modes sit exactly at the bin mean
+    assert np.all(got[n2 == 1] == 1.0) and np.all(got[n2 == 2] == 0.5)
+    # |k| = sqrt 3 between the means of bins 1 and 2
+    t3 = np.log(np.sqrt(3.0) / np.sqrt(2.0)) / np.log(kb[2] / np.sqrt(2.0))
+    assert np.allclose(got[n2 == 3], 0.5 + t3 * (0.25 - 0.5), rtol=0, atol=1e-15)
+    # |k| = 2 between the means of bins 2 and 3
+    t4 = np.log(2.0 / kb[2]) / np.log(kb[3] / kb[2])
+    assert 0.0 < t4 < 1.0
+    assert np.allclose(got[n2 == 4], 0.25 + t4 * (0.2 - 0.25), rtol=0, atol=1e-15)
+    # above the last mean: the last bin's value
+    assert kmean[-1] < np.sqrt(48.0)
+    assert np.all(got[n2 == 48] == 0.05)
+
+
+def test_ratio_between_bins_is_monotone_and_bounded():
+    """Between two neighbouring non-empty bin means the interpolant stays between their
+    values, for any R_b (a property of piecewise-linear interpolation)."""
+    n, box, nb = 32, 128.0, 32
+    _, counts, kmean = pm.bin_geometry(n, box, nb)
+    ok = counts > 0
+    rng = np.random.default_rng(5)
+    ratio = np.where(ok, rng.uniform(0.1, 1.0, nb), -1.0)
+    got = pm.ratio_on_modes(n, box, kmean, counts, ratio)
+    n2, lnk = _modes_lnk(n, box)
+    lnkb, rb = np.log(kmean[ok]), ratio[ok]
+    for i in range(len(lnkb) - 1):
+        sel = (n2 > 0) & (lnk >= lnkb[i]) & (lnk <= lnkb[i + 1])
+        lo, hi = min(rb[i], rb[i + 1]), max(rb[i], rb[i + 1])
+        assert np.all((got[sel] >= lo - 1e-15) & (got[sel] <= hi + 1e-15))
+
+
+def test_undisplaced_lattice_gives_zero_force_with_neutrinos():
+    """A lattice at cell centres deposits exactly one unit per node: delta = 0, every bin has
+    P_cdm = 0, and the force must be exactly zero even though the history gives P_nu != 0
+    (R of a bin without CDM power reads 0, not P_nu/0)."""
+    from oracle import step as ostep
+    from synth import log_spaced_nodes, synthetic_history
+    n, box, nb = 16, 64.0, 8
+    q = _lattice(n, box)
+    sp = ostep.spectrum(q, n, box, nb)
+    assert np.all(sp["p_cdm"] == 0.0)
+    nodes = log_spaced_nodes(0.01, 0.5, 10)
+    hist = synthetic_history(sp["k_mean"], np.ones(nb), nodes, 0.3)
+    r = ostep.full_step(q, n, box, nb, hist, 0.5, 0.3)
+    ok = r["counts"] > 0
+    assert np.all(r["pnu_half"][ok] > 0)
+    assert np.all(r["ratio"] == 0.0)
+    assert np.all(r["acc"] == 0.0)

@@ -235,3 +235,94 @@ def test_response_at_the_first_node_is_the_initial_amplitude():
     r = response.nu_amplitude(k, np.ones(3), np.ones(3), np.zeros(0), np.zeros((0, 3)),
                               np.zeros(3), init, np.full(3, -3e-4), 0.02, 0.3, 0.3, 0.7, 8)
     assert np.array_equal(r["pnu_half"], init)
+
+
+# ------------------------------------- self-consistent stored histories (Sec. 4.3) ----
+def _eds_replay(k, m, a0, an, J):
+    nodes = log_spaced_nodes(a0, an, J)
+    cdm = nodes[:, None] * np.ones((1, len(k)))
+    B = len(k)
+    pm, pnu = response.replay_history(k, np.ones(B), cdm, nodes, np.zeros(B), np.zeros(B),
+                                      3 * m, 1.0, 0.7, 8, f_nu=0.0)
+    return nodes, pm, pnu
+
+
+def test_replayed_history_matches_the_eds_closed_form_at_every_node():
+    """Appendix A at every stored node: in EdS with delta_M ~ a and no initial neutrino
+    perturbation, the node j of a replayed history is F_fin(k, a_j) a_j, and its error falls
+    at second order in the node spacing at the same a (J - 1 = 98 -> 196 intervals)."""
+    k = np.array([0.01, 0.1, 0.3, 1.0])
+    m, a0, an = 0.1, 0.01, 0.5
+    errs = {}
+    for J in (99, 197):
+        nodes, pm, pnu = _eds_replay(k, m, a0, an, J)
+        assert np.array_equal(pm, nodes[:, None] * np.ones((1, len(k))))   # f_nu = 0
+        step = (J - 1) // 49
+        rows = []
+        for j in (1, 6, 12, 24, 49):
+            a_j = nodes[j * step]
+            ref = np.array([_eds_closed_form(kk, m, a0, a_j) for kk in k])
+            rows.append(np.abs(pnu[j * step] / a_j / ref - 1.0))
+        errs[J] = np.array(rows)
+    assert errs[197][-1].max() < 1e-4
+    ratio = errs[99] / errs[197]
+    assert np.all((ratio > 3.5) & (ratio < 4.5))
+
+
+def test_replayed_node_depends_only_on_earlier_nodes():
+    """Causality of the loop: the node a_j of a replay over J nodes equals the last node of
+    a replay over the first j + 1 nodes only, for every j."""
+    om = 0.3
+    nodes = log_spaced_nodes(0.02, 1.0, 12)
+    k = np.array([0.005, 0.05, 0.5, 2.0])
+    d, f = growth(nodes, om)
+    cdm = (d / d[-1])[:, None] * np.array([3.0, 2.0, 1.0, 0.5])[None, :]
+    theta = np.full(4, -f[0] * nodes[0] * bg.hubble_rate(nodes[0], om))
+    ic = cdm[0] / (1.0 + k / 0.1) ** 2
+    pm, pnu = response.replay_history(k, np.ones(4), cdm, nodes, ic, theta, 0.3, om, 0.7, 4)
+    for j in range(1, len(nodes)):
+        pm_j, pnu_j = response.replay_history(k, np.ones(4), cdm[:j + 1], nodes[:j + 1], ic,
+                                              theta, 0.3, om, 0.7, 4)
+        assert np.array_equal(pm_j[-1], pm[j]) and np.array_equal(pnu_j[-1], pnu[j])
+
+
+def test_replayed_history_limits_of_the_total_matter_node():
+    """What each stored node holds, P_M^{1/2} = (1 - f_nu) P_cdm^{1/2} + f_nu P_nu^{1/2}, from
+    the two limits of Sec. 3.3: for k -> 0 the neutrinos follow the CDM (growing mode, so
+    P_M -> P_cdm and P_nu -> P_cdm at every node), for k >> k_fs they do not cluster
+    (P_nu^{1/2} < (k_fs/k)^2 P_cdm^{1/2}, so P_M^{1/2} -> (1 - f_nu) P_cdm^{1/2})."""
+    om, m_tot = 0.3, 0.6
+    nodes = log_spaced_nodes(0.01, 1.0, 120)
+    d, f = growth(nodes, om)
+    k = np.array([1e-5, 50.0])
+    cdm = (d / d[-1])[:, None] * np.ones((1, 2))
+    theta = np.full(2, -f[0] * nodes[0] * bg.hubble_rate(nodes[0], om))
+    ic = np.array([cdm[0, 0], 0.0])
+    pm, pnu = response.replay_history(k, np.ones(2), cdm, nodes, ic, theta, m_tot, om, 0.7, 8)
+    fn = bg.f_nu(m_tot, om, 0.7)
+    assert fn > 0.04
+    assert np.all(np.abs(pnu[1:, 0] / cdm[1:, 0] - 1.0) < 1e-3)
+    assert np.all(np.abs(pm[1:, 0] / cdm[1:, 0] - 1.0) < 1e-3 * fn)
+    kfs = np.array([np.sqrt(1.5 * bg.mean_inverse_v2(a, m_tot / 3)) * a * bg.hubble_rate(a, om)
+                    for a in nodes[1:]])
+    bound = (kfs / k[1]) ** 2
+    assert np.all(pnu[1:, 1] / cdm[1:, 1] < bound)
+    assert np.all(np.abs(pm[1:, 1] / ((1.0 - fn) * cdm[1:, 1]) - 1.0) < fn * bound / (1.0 - fn))
+
+
+def test_replay_with_all_matter_in_neutrinos_is_the_fluid_growing_mode():
+    """f_nu = 1 (all matter in neutrinos, the CDM rows then carry weight 1 - f_nu = 0): for
+    k -> 0 the neutrinos are the pressureless fluid of Sec. 3.3.1 and, started on the
+    growing mode, follow D(a) at every node, which needs every stored node to be the
+    replayed neutrino amplitude itself (the CDM rows here are deliberately wrong)."""
+    om = 0.3
+    nodes = log_spaced_nodes(0.01, 1.0, 150)
+    d, f = growth(nodes, om)
+    amp = d / d[-1]
+    k = np.array([1e-5])
+    theta = np.array([-f[0] * nodes[0] * bg.hubble_rate(nodes[0], om)])
+    wrong_cdm = 5.0 * amp[:, None] + 1.0
+    pm, pnu = response.replay_history(k, [1], wrong_cdm, nodes, [amp[0]], theta, 0.3, om,
+                                      0.7, 8, f_nu=1.0)
+    assert np.array_equal(pm, pnu)
+    assert np.all(np.abs(pnu[:, 0] / amp - 1.0) < 2e-4)
