@@ -134,11 +134,17 @@ int pm_nu_step(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now);
 
 /* Per-box spectra of the last step (host, sync), each [B], any may be NULL:
  * P_cdm(k_b) [(Mpc/h)^3], P_nu^{1/2}(k_b), R_b = P_nu^{1/2}/P_cdm^{1/2}. Empty bins
- * read 0. Returns PM_NU_ENONFINITE if the last deposit saw a non-finite position. */
+ * read 0; R_b reads 0 in a bin whose P_cdm is 0 (no CDM mode to carry the neutrino
+ * phase, eq. (phases)). Returns PM_NU_ENONFINITE if the last deposit saw a non-finite position. */
 int pm_nu_get_spectrum(pm_nu_ctx* ctx, int box, double* p_cdm, double* pnu_half,
                        double* ratio);
 
 /* ---- diagnostics (copies of internal state, enqueued on the stream) ---------------- */
+/* (sync) How many chunk parts the patch deposit (deposit modes 6, 7) has sent through its
+ * atomic side grid since the last call (a chunk whose bounding box exceeds the LDS tile,
+ * or its part in a coarse cell whose patch list was full); 0 when every chunk went
+ * through its patch, and always 0 for the other deposit modes. */
+int pm_nu_side_grid_uses(pm_nu_ctx* ctx, int64_t* uses);
 /* Deposited mass rho (unit mass per particle) of one box into out (dev) [N][N][N]. */
 int pm_nu_copy_density(pm_nu_ctx* ctx, int box, float* out);
 /* delta_k of one box (after pm_nu_deposit) into out (dev) as complex64 pairs in the

@@ -55,6 +55,7 @@ SIGNATURES = {
     "pm_nu_step": (_INT, [_P, _P, _P, ctypes.c_double]),
     "pm_nu_get_spectrum": (_INT, [_P, _INT, _D, _D, _D]),
     "pm_nu_copy_density": (_INT, [_P, _INT, _P]),
+    "pm_nu_side_grid_uses": (_INT, [_P, _I64]),
     "pm_nu_copy_modes": (_INT, [_P, _INT, _P]),
     "pm_nu_copy_force_grid": (_INT, [_P, _INT, _INT, _P]),
     "pm_nu_set_timing": (_INT, [_P, _INT]),
@@ -219,6 +220,12 @@ def pm_nu_get_spectrum(h, box, n_kbins):
     r = np.zeros(n_kbins)
     _check(load_library().pm_nu_get_spectrum(h, box, _dptr(p), _dptr(pn), _dptr(r)))
     return p, pn, r
+
+
+def pm_nu_side_grid_uses(h):
+    n = ctypes.c_int64(0)
+    _check(load_library().pm_nu_side_grid_uses(h, ctypes.byref(n)))
+    return int(n.value)
 
 
 def pm_nu_copy_density(h, box, out):

@@ -53,8 +53,8 @@ __device__ __forceinline__ int signed_index(int i, int n) { return i < n / 2 ? i
 // ------------------------------------------------------------------------ forward ----
 // Input: the fixed-point density (DELTA = false; delta = rho / rho_bar - 1 is formed here
 // from the exact sum and rounded once to FP32) or delta already in FP32 (DELTA = true;
-// then thread 0 of the first workgroup also clears the side-grid counter of the patch
-// deposit, whose last reader ran before this kernel).
+// then thread 0 of the first workgroup also moves the side-grid counter of the patch
+// deposit, whose last reader ran before this kernel, into its running total).
 template <int N, bool DELTA>
 __global__ __launch_bounds__(NT) void fwd_z_kernel(const void* __restrict__ in,
                                                    float2* __restrict__ out,
@@ -69,8 +69,10 @@ __global__ __launch_bounds__(NT) void fwd_z_kernel(const void* __restrict__ in,
   const size_t off = ((static_cast<size_t>(box) * N + x) * N + y0) * N;
   float* ldsf = reinterpret_cast<float*>(lds);
   if constexpr (DELTA) {
-    if (reset && threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0)
-      *reset = 0;
+    if (reset && threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) {
+      reset[1] += reset[0];
+      reset[0] = 0;
+    }
     // the patch registry's counts, read for the last time by the reduce before this kernel
     const int64_t gid =
         ((static_cast<int64_t>(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) *

@@ -552,7 +552,7 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
     ALLOC(c->reg_count, coarse);
     ALLOC(c->reg_list, coarse * 32);
     ALLOC(c->rho_fb, nb * c->M);
-    ALLOC(c->n_fb, 1);
+    ALLOC(c->n_fb, 2);
     ALLOC(c->delta, nb * c->M);
   }
   ALLOC(c->d_kd, 2 * nb);
@@ -605,7 +605,7 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   // the patch deposit keeps these at zero between deposits
   e = e ? e : hipMemset(c->reg_count, 0, nb * patch_coarse_cells(c->N) * sizeof(int));
   e = e ? e : hipMemset(c->rho_fb, 0, nb * c->M * sizeof(unsigned long long));
-  e = e ? e : hipMemset(c->n_fb, 0, sizeof(int));
+  e = e ? e : hipMemset(c->n_fb, 0, 2 * sizeof(int));
   e = e ? e : hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_ctx(c);
@@ -953,6 +953,19 @@ int pm_nu_get_spectrum(pm_nu_ctx* ctx, int box, double* p_cdm, double* pnu_half,
     PMNU_HIP(hipMemset(c->d_flags, 0, sizeof(int)));
     return set_error(PM_NU_ENONFINITE, "a non-finite particle position was skipped");
   }
+  return PM_NU_OK;
+}
+
+int pm_nu_side_grid_uses(pm_nu_ctx* ctx, int64_t* uses) {
+  GET_CTX(ctx);
+  if (!uses) return set_error(PM_NU_EINVAL, "uses is NULL");
+  *uses = 0;
+  if (!c->n_fb) return PM_NU_OK;            // no patch deposit buffers (N < 64 by default)
+  PMNU_HIP(hipStreamSynchronize(c->stream));
+  unsigned total = 0;
+  PMNU_HIP(hipMemcpy(&total, c->n_fb + 1, sizeof(unsigned), hipMemcpyDeviceToHost));
+  *uses = static_cast<int64_t>(total - c->fb_seen);   // modulo 2^32, like the device count
+  c->fb_seen = total;
   return PM_NU_OK;
 }
 

@@ -525,7 +525,7 @@ __global__ __launch_bounds__(RT) void surrogate_response_kernel(
                                tg_ds + static_cast<size_t>(box) * qcap,
                                tg_w + static_cast<size_t>(box) * qcap, q_sub, iterations, red);
   if (tid == 0) {
-    const double r = pnu / ph;
+    const double r = ph > 0.0 ? pnu / ph : 0.0;   // no CDM power in the bin: R = 0
     pnu_out[ob] = pnu;
     ratio_out[ob] = r;
     hpm[row] = (1.0 - bx.f_nu) * ph + bx.f_nu * pnu;

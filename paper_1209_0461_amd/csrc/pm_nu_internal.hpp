@@ -144,7 +144,9 @@ struct Ctx {
   int* reg_count = nullptr;        // [nbox][coarse cells] patches registered
   int4* reg_list = nullptr;        // [nbox][coarse cells][32] (chunk, origin, extents, 0)
   unsigned long long* rho_fb = nullptr;    // [nbox][M] side grid, kept at zero
-  int* n_fb = nullptr;             // [1] chunks that used the side grid this deposit
+  int* n_fb = nullptr;             // [2] chunks that used the side grid this deposit; running
+                                   // total of earlier deposits (added by the first FFT pass)
+  unsigned fb_seen = 0;            // running total at the last pm_nu_side_grid_uses
   float* delta = nullptr;          // [nbox][M] delta in FP32 (modes 6, 7)
   double* d_kd = nullptr;          // [nbox][2] kick and drift factors of the leapfrog
   // pinned staging of the host-built arrays (copied in stream order) and the last copies
@@ -226,8 +228,9 @@ hipError_t launch_interp(const float* pos, const float* force, float* acc, int64
                          int nbox, int N, double inv_cell, int mode, int block, hipStream_t s,
                          const Leap* lp = nullptr);
 // fft_kernels.hip
-// input: the fixed-point density rho, or (if delta is not NULL) delta in FP32; reset (may
-// be NULL) is cleared by the kernel when reading delta, and so are the n_clear ints at clear
+// input: the fixed-point density rho, or (if delta is not NULL) delta in FP32; reset[0] (may
+// be NULL) is added to reset[1] and cleared by the kernel when reading delta, and the n_clear
+// ints at clear are cleared
 // (NULL: none); a clear larger than the launch's thread count is rejected
 hipError_t launch_fwd_z(int N, const unsigned long long* rho, const float* delta, int* reset,
                         int* clear, int n_clear, float2* out, const float2* tw, double scale,

@@ -11,7 +11,8 @@
 //      two bracketing nodes (Q sub-nodes per interval). The current node uses
 //      (1 - f_nu) P_cdm^{1/2} + f_nu P_nu^{1/2}(previous node) on the first iteration
 //      and the previous iteration's P_nu^{1/2} after that;
-//   3. writes P_nu^{1/2}, R = P_nu^{1/2}/P_cdm^{1/2}, and the new history row.
+//   3. writes P_nu^{1/2}, R = P_nu^{1/2}/P_cdm^{1/2} (0 where P_cdm = 0), and the new
+//      history row.
 // Lanes stride over the sub-nodes; sums are reduced across the wave and the workgroup
 // in FP64 in a fixed order. The sum is gathered as a part from the stored nodes plus a
 // coefficient of the current node, so iterations do not evaluate the kernel again.
@@ -66,7 +67,8 @@ __global__ __launch_bounds__(RT) void response_kernel(
   if (threadIdx.x == 0) {
     pcdm_out[ob] = pcdm;
     pnu_out[ob] = pnu;
-    ratio_out[ob] = pnu / pcdm_half;
+    // a bin without CDM power has no phase to carry the neutrinos (eq. (phases)): R = 0
+    ratio_out[ob] = pcdm_half > 0.0 ? pnu / pcdm_half : 0.0;
     hpm[static_cast<size_t>(bx.n_cur) * nbins + b] = (1.0 - bx.f_nu) * pcdm_half + bx.f_nu * pnu;
     hpn[static_cast<size_t>(bx.n_cur) * nbins + b] = pnu;
   }

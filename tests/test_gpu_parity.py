@@ -293,7 +293,9 @@ def test_patch_deposit_side_grid_on_crowded_cells():
     straddle[: 20 * 4096, 0] += 20.0
     ctx = PMNu(nm, len(crowd), box, nb, J + 2, [0.3])
     binding.pm_nu_set_launch(ctx.h, 6, 256, 1, 256)
-    for pos in (crowd, lattice, straddle):
+    assert binding.pm_nu_side_grid_uses(ctx.h) == 0
+    # (five overlapping copies of a lattice also fill the coarse cells' lists: no claim there)
+    for pos, side in ((crowd, True), (lattice, None), (straddle, True)):
         hist, ref = oracle_case(pos, nm, box, nb, J, 0.02, 0.7, 0.3)
         ctx.set_history(0, hist)
         p = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
@@ -307,6 +309,8 @@ def test_patch_deposit_side_grid_on_crowded_cells():
         rho = torch.empty(nm ** 3, device="cuda")
         binding.pm_nu_copy_density(ctx.h, 0, rho)
         assert abs(float(rho.double().sum()) / len(pos) - 1.0) < 1e-5
+        uses = binding.pm_nu_side_grid_uses(ctx.h)
+        assert side is None or (uses > 0) == side, uses
     ctx.close()
 
 
