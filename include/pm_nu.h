@@ -139,6 +139,24 @@ int pm_nu_step(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now);
 int pm_nu_get_spectrum(pm_nu_ctx* ctx, int box, double* p_cdm, double* pnu_half,
                        double* ratio);
 
+/* ---- stage (ii) without allocation ------------------------------------------------- */
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the binned power of one box, as pm_nu_deposit
+ * followed by pm_nu_get_spectrum's p_cdm, with no context. The CIC mass of every particle
+ * (unit mass), delta = rho/rho_bar - 1, the forward real FFT and
+ * P_cdm(k_b) = (L^3/N^6) sum_b w |delta_k|^2 / C_b (FP64 sums) over the bins of
+ * pm_nu_get_bins for this N, L and B.
+ *   pos (dev) [n_particles][3] FP32 positions (wrapped into [0, L)); p_cdm (dev) [n_kbins]
+ *   FP64 output; stream: hipStream_t (NULL: the null stream). Asynchronous on the stream.
+ * Every intermediate lives in one static device array of 5 MiB per device, held until the
+ * process ends, which limits n_mesh to powers of two from 8 to 64 and n_kbins to 1..256.
+ * It allocates nothing, on the device or the host. Calls on one device share that array:
+ * calls that overlap on one device (several streams or threads) race. A non-finite
+ * position is skipped, not reported. Errors: PM_NU_EINVAL for sizes beyond those limits or
+ * bad arguments, PM_NU_EHIP if a launch fails. */
+int pm_nu_binned_power_noalloc(const float* pos, int64_t n_particles, int n_mesh,
+                               double box_size, int n_kbins, double* p_cdm, void* stream);
+
 /* ---- diagnostics (copies of internal state, enqueued on the stream) ---------------- */
 /* (sync) How many chunk parts the patch deposit (deposit modes 6, 7) has sent through its
  * atomic side grid since the last call (a chunk whose bounding box exceeds the LDS tile,

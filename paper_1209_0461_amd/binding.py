@@ -56,6 +56,8 @@ SIGNATURES = {
     "pm_nu_get_spectrum": (_INT, [_P, _INT, _D, _D, _D]),
     "pm_nu_copy_density": (_INT, [_P, _INT, _P]),
     "pm_nu_side_grid_uses": (_INT, [_P, _I64]),
+    "pm_nu_binned_power_noalloc": (_INT, [_P, ctypes.c_int64, _INT, ctypes.c_double, _INT, _P,
+                                          _P]),
     "pm_nu_copy_modes": (_INT, [_P, _INT, _P]),
     "pm_nu_copy_force_grid": (_INT, [_P, _INT, _INT, _P]),
     "pm_nu_set_timing": (_INT, [_P, _INT]),
@@ -220,6 +222,20 @@ def pm_nu_get_spectrum(h, box, n_kbins):
     r = np.zeros(n_kbins)
     _check(load_library().pm_nu_get_spectrum(h, box, _dptr(p), _dptr(pn), _dptr(r)))
     return p, pn, r
+
+
+def pm_nu_binned_power_noalloc(pos, n_mesh, box_size, n_kbins, p_cdm, stream=None):
+    """Binned P_cdm of one box without a context or any allocation: pos a float32 device
+    tensor [n][3], p_cdm a float64 device tensor [n_kbins] (written on the stream)."""
+    import torch
+    if pos.dtype != torch.float32 or pos.dim() != 2 or pos.shape[1] != 3:
+        raise ValueError("pos must be a float32 tensor of shape (n, 3)")
+    if p_cdm.dtype != torch.float64 or p_cdm.numel() != n_kbins:
+        raise ValueError("p_cdm must be a float64 tensor of n_kbins values")
+    st = stream if stream is not None else current_stream_handle()
+    _check(load_library().pm_nu_binned_power_noalloc(_dev(pos), int(pos.shape[0]), int(n_mesh),
+                                                     float(box_size), int(n_kbins),
+                                                     _dev(p_cdm), st))
 
 
 def pm_nu_side_grid_uses(h):
