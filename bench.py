@@ -10,7 +10,8 @@ Prints one JSON line. `value` is steps/s of the whole step with inputs resident 
 `roofline` is the dominant kernel's algorithmic bytes per launch over its mean launch
 time from HIP events recorded on the library's stream inside the timed region;
 `cpu_baseline` is the FP64 oracle timed on this host on one full step (single-threaded
-NumPy).
+NumPy). After the 256^3 workload, `other_workloads` carries the same measurement of the
+512^3 box and of the 64 boxes of 64^3 (through a HIP graph), each timed on its own.
 
     python bench.py [--steps K] [--warmup W] [--workload pm256|pm512|tiny32|batch64x64]
 """
@@ -274,55 +275,21 @@ def cpu_baseline(cfg, pos, masses, hists):
                       + (f"; scaled to {nbox} boxes" if nbox > 1 else "")}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="pm256")
-    ap.add_argument("--mass-index", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph", action="store_true", help="replay the step as a HIP graph")
-    ap.add_argument("--order", default="morton", choices=["morton", "c"],
-                    help="particle order of the synthetic lattice (space-filling curve or C)")
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--no-surrogate", action="store_true",
-                    help="skip the surrogate-versus-integral measurement")
-    ap.add_argument("--no-loop", action="store_true",
-                    help="skip the time-stepping loop measurement")
-    ap.add_argument("--no-variants", action="store_true",
-                    help="skip the exact-kernel and second-iteration measurement")
-    ap.add_argument("--copy-probe", type=int, default=0,
-                    help="only run a plain device copy of this many MiB (counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the step is "
-              "single-GPU in this build", file=sys.stderr)
-        sys.exit(2)
-
+def measure_workload(name, args, dev, full):
+    """Time the step of one workload on this GPU. `full` adds the surrogate, the kernel
+    variants, the stepping loop and the oracle's CPU timing (the headline workload);
+    otherwise only steps/s, the step's share of the roofline and its dominant kernel."""
     import torch
-    from paper_1209_0461_amd import PMNu, binding, LIB_PATH
-    if not os.path.exists(LIB_PATH):
-        from paper_1209_0461_amd import build
-        build.build()
-    dev = torch.device("cuda:0")
-
-    if args.copy_probe:
-        n = args.copy_probe * (1 << 20) // 4
-        a = torch.ones(n, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_mib": args.copy_probe}))
-        return
-
+    from paper_1209_0461_amd import PMNu, binding
     from synth import log_spaced_nodes, synthetic_history
-    cfg, pos_np, masses = make_workload(args.workload, args.mass_index, args.order)
+    cfg, pos_np, masses = make_workload(name, args.mass_index, args.order)
     nbox, npart = pos_np.shape[0], pos_np.shape[1]
     n_mesh, nbins, J = cfg["n_mesh"], cfg["n_kbins"], cfg["n_hist"]
     a_now = cfg["a_now"]
     nodes = log_spaced_nodes(cfg["a_lo"], a_now, J)
+    graph = args.graph if full else nbox > 1
+    steps = args.steps
+    warmup = args.warmup
 
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -341,28 +308,29 @@ def main():
         if not args.no_autotune:
             binding.pm_nu_autotune(ctx.h, pos, acc, a_now)
         tuning = json.loads(binding.pm_nu_tuning(ctx.h))
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             ctx.step(pos, acc, a_now)
-        if args.graph:
+        if graph:
             binding.pm_nu_graph_capture(ctx.h, pos, acc, a_now)
-            for _ in range(args.warmup):
+            for _ in range(warmup):
                 binding.pm_nu_graph_launch(ctx.h)
         stream.synchronize()
         # per-stage profile: an event pair around every kernel, on untimed eager steps
         binding.pm_nu_read_timing(ctx.h)
         binding.pm_nu_set_timing(ctx.h, True)
-        for _ in range(min(args.steps, 10)):
+        for _ in range(min(steps, 10)):
             ctx.step(pos, acc, a_now)
         stream.synchronize()
         timing = binding.pm_nu_read_timing(ctx.h)
         names = list(timing)
         dom = max((k for k in names if timing[k][1] > 0), key=lambda k: timing[k][0])
         # timed region: events only around the dominant kernel (graph replays carry none)
-        binding.pm_nu_set_timing_mask(ctx.h, 0 if args.graph else 1 << names.index(dom))
+        binding.pm_nu_set_timing_mask(ctx.h, 0 if graph else 1 << names.index(dom))
+        stream.synchronize()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            if args.graph:
+        for _ in range(steps):
+            if graph:
                 binding.pm_nu_graph_launch(ctx.h)
             else:
                 ctx.step(pos, acc, a_now)
@@ -376,39 +344,39 @@ def main():
         else:
             dom_ms, dom_source = timing[dom][0] / timing[dom][1], "eager profile steps"
         sp = ctx.spectrum(0)
-        finite = bool(np.isfinite(acc.cpu().numpy()).all() and np.isfinite(sp["ratio"]).all())
-        surrogate = None
-        if os.path.exists(SURROGATE_BLOB) and not args.no_surrogate and not args.graph:
-            surrogate = measure_surrogate(ctx, binding, pos, acc, a_now, args.steps, stream,
+        finite = bool(torch.isfinite(acc).all()) and bool(np.isfinite(sp["ratio"]).all())
+        surrogate = variants = loop = None
+        if full and os.path.exists(SURROGATE_BLOB) and not args.no_surrogate and not graph:
+            surrogate = measure_surrogate(ctx, binding, pos, acc, a_now, steps, stream,
                                           timing, names)
-        variants = None
-        if not args.no_variants:
+        if full and not args.no_variants:
             variants = measure_variants(ctx, binding, pos, acc, a_now, stream, names)
-        loop = None
-        if not args.no_loop and not args.graph:
+        if full and not args.no_loop and not graph:
             loop = measure_loop(cfg, pos, masses, stream, tuning)
+        ctx.close()
+        del pos, acc
+    torch.cuda.empty_cache()
 
-    from paper_1209_0461_amd.binding import load_library  # noqa: F401
     n_partial = (n_mesh // min(16 if n_mesh <= 256 else 8, n_mesh)) * (n_mesh // 2 + 1)
     sb = stage_bytes(n_mesh, npart, nbox, nbins, J, n_partial, tuning["deposit_mode"])
     stages = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1],
                   "gbs": sb.get(k, 0) / (v[0] / v[1] * 1e-3) / 1e9 if k in sb else None}
               for k, v in timing.items() if v[1] > 0}
-    value = args.steps / dt
+    value = steps / dt
     out = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+        "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * dt / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "dtype_detail": "FP32 deposit/FFT/Green/interpolation; FP64 k-bin sums and the "
                         "neutrino history integral",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {nbox} x {npart} particles on {n_mesh}^3, "
+        "config": {"workload": f"{name}: {nbox} x {npart} particles on {n_mesh}^3, "
                                f"L={cfg['box']} Mpc/h, {nbins} k-bins, {J} history nodes "
                                f"over a in [{cfg['a_lo']}, {a_now}], Q={cfg['substeps']}, "
                                f"M_nu={','.join(f'{m:.3g}' for m in masses[:4])}"
                                + ("..." if nbox > 4 else "") + " eV",
                    "n_mesh": n_mesh, "n_particles": npart * nbox, "n_boxes": nbox,
-                   "graph": bool(args.graph), "particle_order": args.order,
+                   "graph": bool(graph), "particle_order": args.order,
                    "launch": tuning},
         "particle_updates_per_s": value * npart * nbox,
         "finite": finite,
@@ -420,7 +388,7 @@ def main():
     if stages:
         ach = sb[dom] / (dom_ms * 1e-3) / 1e9
         kname = kernel_name(dom, tuning, n_mesh)
-        traffic = load_traffic(args.workload, dom, kname)
+        traffic = load_traffic(name, dom, kname)
         out["roofline"] = {"bound": "hbm", "kernel": dom, "kernel_name": kname,
                            "ms_per_launch": dom_ms, "timing": f"HIP events, {dom_source}",
                            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -431,16 +399,75 @@ def main():
                            "algorithmic_bytes_per_launch": sb[dom]}
         out["stages"] = stages
         out["stages_note"] = ("per-stage HIP event pairs around every kernel on "
-                              f"{min(args.steps, 10)} eager steps before the timed region")
+                              f"{min(steps, 10)} eager steps before the timed region")
     if surrogate is not None:
         out["surrogate"] = surrogate
     if variants is not None:
         out["variants"] = variants
     if loop is not None:
         out["loop"] = loop
-    if not args.no_cpu_baseline:
+    if full and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, pos_np, masses, hists)
-    ctx.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="pm256")
+    ap.add_argument("--mass-index", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay the step as a HIP graph")
+    ap.add_argument("--order", default="morton", choices=["morton", "c"],
+                    help="particle order of the synthetic lattice (space-filling curve or C)")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate-versus-integral measurement")
+    ap.add_argument("--no-loop", action="store_true",
+                    help="skip the time-stepping loop measurement")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the exact-kernel and second-iteration measurement")
+    ap.add_argument("--no-others", action="store_true",
+                    help="skip the 512^3 and batched workloads after the main one")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the step is "
+              "single-GPU in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1209_0461_amd import LIB_PATH
+    if not os.path.exists(LIB_PATH):
+        from paper_1209_0461_amd import build
+        build.build()
+    dev = torch.device("cuda:0")
+
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(n, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_mib": args.copy_probe}))
+        return
+
+    out = measure_workload(args.workload, args, dev, full=True)
+    if not args.no_others and args.workload == "pm256":
+        # the other single-GPU workloads, each in its own timed region, reported beside
+        # the headline (the 512^3 box eagerly, the 64 small boxes through a HIP graph)
+        out["other_workloads"] = {}
+        for other in ("pm512", "batch64x64"):
+            print(f"bench: {other}", file=sys.stderr, flush=True)
+            o = measure_workload(other, args, dev, full=False)
+            out["other_workloads"][other] = {
+                k: o[k] for k in ("value", "unit", "steps", "ms_per_step",
+                                  "particle_updates_per_s", "step_hbm", "roofline", "config",
+                                  "finite") if k in o}
     print(json.dumps(out))
 
 
