@@ -100,12 +100,16 @@ def kernel_name(stage, tuning, n_mesh):
              "rtable": "rtable_kernel", "patch_reduce": "patch_reduce_kernel<8>"}
     if stage in fixed:
         return fixed[stage]
-    fft = {"fft_fwd_z": "fwd_z_kernel", "fft_fwd_y": "fwd_y_kernel",
-           "fft_fwd_x_bin": "fwd_x_bin_kernel", "inv_x_green": "inv_x_kernel",
-           "fft_inv_y": "inv_y_kernel", "fft_inv_z": "inv_z_kernel"}
+    tiles = tuning.get("fft_tiles", {})
+    fft = {"fft_fwd_y": ("fwd_y_kernel", "fwd_y"), "inv_x_green": ("inv_x_kernel", "inv_x"),
+           "fft_inv_y": ("inv_y_kernel", "inv_y"), "fft_inv_z": ("inv_z_kernel", "inv_z")}
     if stage == "fft_fwd_z":
-        return "fwd_z_kernel<%d, %s>" % (n_mesh, "true" if tuning["deposit_mode"] >= 6 else "false")
-    return "%s<%d>" % (fft[stage], n_mesh)
+        return "fwd_z_kernel<%d, %s, %d>" % (n_mesh, "true" if tuning["deposit_mode"] >= 6
+                                             else "false", tiles.get("fwd_z", 0))
+    if stage == "fft_fwd_x_bin":
+        return "fwd_x_bin_kernel<%d, false, true, %d>" % (n_mesh, tiles.get("fwd_x", 0))
+    name, key = fft[stage]
+    return "%s<%d, %d>" % (name, n_mesh, tiles.get(key, 0))
 
 
 def load_traffic(workload, stage, kernel):
@@ -357,7 +361,7 @@ def measure_workload(name, args, dev, full):
         del pos, acc
     torch.cuda.empty_cache()
 
-    n_partial = (n_mesh // min(16 if n_mesh <= 256 else 8, n_mesh)) * (n_mesh // 2 + 1)
+    n_partial = (n_mesh // tuning["fft_tiles"]["fwd_x"]) * (n_mesh // 2 + 1)
     sb = stage_bytes(n_mesh, npart, nbox, nbins, J, n_partial, tuning["deposit_mode"])
     stages = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1],
                   "gbs": sb.get(k, 0) / (v[0] / v[1] * 1e-3) / 1e9 if k in sb else None}

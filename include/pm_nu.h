@@ -219,8 +219,10 @@ int pm_nu_advance(pm_nu_ctx* ctx, float* pos, float* vel, float* acc, const doub
 /* ---- launch-shape autotuning ----------------------------------------------------------- */
 /* Time the candidate launch shapes of the tunable kernels on this context's buffers with
  * HIP events (pos/acc (dev) as for pm_nu_step, a_now as for pm_nu_response; the history
- * must be set), keep the fastest, and if cache_path is not NULL read/write the choice
- * as JSON keyed by (device name, N, n_boxes) (sync). */
+ * must be set): the deposit mode and block, the interpolation mode and block, and the three
+ * tile candidates of each FFT pass (pm_nu_set_fft_tiles); keep the fastest of each, and if
+ * cache_path is not NULL read/write the choice as JSON keyed by (device architecture, N,
+ * n_boxes, particles per box) (sync). Ends with one full step at a_now. */
 int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
                    const char* cache_path);
 /* Set the launch shapes directly: deposit_mode 0 (one thread per particle, global atomics;
@@ -236,7 +238,17 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
  * covers the mesh), interp_mode 1. */
 int pm_nu_set_launch(pm_nu_ctx* ctx, int deposit_mode, int deposit_block, int interp_mode,
                      int interp_block);
-/* Current launch-shape choice as a short JSON text (host buffer of cap bytes, sync). */
+/* Tile candidates of the six FFT passes, candidates[6] (host) in the order fwd_z (real rows
+ * per workgroup), fwd_y (lines), fwd_x + binning (k_y columns), inv_x (k_y columns), inv_y
+ * (lines), inv_z (rows); each 0 (the default), 1 or 2, the tile sizes pm_nu_tuning reports
+ * (below N = 64 all three are the default). Every candidate computes the same transform;
+ * only the speed differs. pm_nu_autotune times them and keeps the fastest of each pass.
+ * The next step must start with pm_nu_deposit. Errors: PM_NU_EINVAL for a value outside
+ * 0..2. */
+int pm_nu_set_fft_tiles(pm_nu_ctx* ctx, const int32_t* candidates);
+/* Current launch-shape choice as a short JSON text (host buffer of cap bytes, sync):
+ * deposit and interpolation modes and blocks, the FFT tile candidates ("fft") and their
+ * tiles ("fft_tiles"). */
 int pm_nu_tuning(pm_nu_ctx* ctx, char* out, size_t cap);
 
 /* Switch the response between the exact integral (0), the surrogate (1) and the surrogate

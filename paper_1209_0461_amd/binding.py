@@ -74,6 +74,7 @@ SIGNATURES = {
     "pm_nu_autotune": (_INT, [_P, _P, _P, ctypes.c_double, ctypes.c_char_p]),
     "pm_nu_tuning": (_INT, [_P, ctypes.c_char_p, ctypes.c_size_t]),
     "pm_nu_set_launch": (_INT, [_P, _INT, _INT, _INT, _INT]),
+    "pm_nu_set_fft_tiles": (_INT, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "pm_nu_surrogate_blob_floats": (ctypes.c_int64, []),
     "pm_nu_surrogate_load": (_INT, [_P, _F, ctypes.c_int64]),
     "pm_nu_surrogate_save": (_INT, [_P, _F, ctypes.c_int64]),
@@ -333,6 +334,14 @@ def pm_nu_autotune(h, pos, acc, a_now, cache_path=None):
 def pm_nu_set_launch(h, deposit_mode, deposit_block, interp_mode, interp_block):
     _check(load_library().pm_nu_set_launch(h, int(deposit_mode), int(deposit_block),
                                            int(interp_mode), int(interp_block)))
+
+
+def pm_nu_set_fft_tiles(h, candidates):
+    """Tile candidate (0, 1 or 2) of each FFT pass: fwd_z, fwd_y, fwd_x, inv_x, inv_y, inv_z."""
+    c = np.ascontiguousarray(candidates, dtype=np.int32).reshape(-1)
+    if c.size != 6:
+        raise ValueError("six candidates are needed")
+    _check(load_library().pm_nu_set_fft_tiles(h, c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
 
 
 def pm_nu_tuning(h):

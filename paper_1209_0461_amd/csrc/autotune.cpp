@@ -1,10 +1,12 @@
 // Launch-shape autotuner: times the candidate launch shapes of the particle kernels (the
-// deposit's chunking mode / block size, the interpolation's block size) with HIP events
-// on the context's own buffers and keeps the fastest; the choice can be cached as JSON
-// lines keyed by (device name, N, n_boxes, particles per box).
+// deposit's chunking mode / block size, the interpolation's mode / block size) and the tile
+// candidates of the six FFT passes with HIP events on the context's own buffers and keeps
+// the fastest of each; the choice can be cached as JSON lines keyed by (device
+// architecture, N, n_boxes, particles per box).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <sstream>
@@ -26,12 +28,36 @@ std::string cache_key(const Ctx& c) {
   return o.str();
 }
 
+const char* const kFftPass[6] = {"fwd_z", "fwd_y", "fwd_x", "inv_x", "inv_y", "inv_z"};
+
 std::string tuning_json(const Ctx& c) {
   std::ostringstream o;
   o << "{\"deposit_mode\": " << c.tune.deposit_mode << ", \"deposit_block\": "
     << c.tune.deposit_block << ", \"interp_mode\": " << c.tune.interp_mode
-    << ", \"interp_block\": " << c.tune.interp_block << "}";
+    << ", \"interp_block\": " << c.tune.interp_block << ", \"fft\": [";
+  for (int p = 0; p < 6; ++p) o << (p ? ", " : "") << c.tune.fft[p];
+  o << "], \"fft_tiles\": {";
+  for (int p = 0; p < 6; ++p)
+    o << (p ? ", " : "") << "\"" << kFftPass[p] << "\": " << fft_tile(c.N, p, c.tune.fft[p]);
+  o << "}}";
   return o.str();
+}
+
+// The FFT candidates of a cache line: "fft": [a, b, c, d, e, f], each 0..2.
+bool json_fft(const std::string& line, int* fft) {
+  const std::string f = "\"fft\": [";
+  const size_t p = line.find(f);
+  if (p == std::string::npos) return false;
+  const char* q = line.c_str() + p + f.size();
+  for (int i = 0; i < 6; ++i) {
+    char* end = nullptr;
+    const long v = std::strtol(q, &end, 10);
+    if (end == q || v < 0 || v > 2) return false;
+    fft[i] = static_cast<int>(v);
+    q = end;
+    while (*q == ',' || *q == ' ') ++q;
+  }
+  return true;
 }
 
 int json_int(const std::string& line, const char* field, int fallback) {
@@ -52,11 +78,14 @@ bool read_cache(const char* path, const std::string& key, Tuning& t) {
     const int d = json_int(line, "deposit_block", -1);
     const int im = json_int(line, "interp_mode", -1);
     const int i = json_int(line, "interp_block", -1);
-    if (m >= 0 && m <= 7 && d >= 64 && d <= 1024 && im >= 0 && im <= 3 && i >= 64 && i <= 1024) {
+    int fft[6];
+    if (m >= 0 && m <= 7 && d >= 64 && d <= 1024 && im >= 0 && im <= 3 && i >= 64 && i <= 1024 &&
+        json_fft(line, fft)) {
       t.deposit_mode = m;
       t.deposit_block = d;
       t.interp_mode = im;
       t.interp_block = i;
+      for (int p = 0; p < 6; ++p) t.fft[p] = fft[p];
       return true;
     }
   }
@@ -76,7 +105,9 @@ void write_cache(const char* path, const std::string& key, const Tuning& t) {
   for (const std::string& l : keep) f << l << "\n";
   f << "{\"key\": \"" << key << "\", \"deposit_mode\": " << t.deposit_mode
     << ", \"deposit_block\": " << t.deposit_block << ", \"interp_mode\": " << t.interp_mode
-    << ", \"interp_block\": " << t.interp_block << "}\n";
+    << ", \"interp_block\": " << t.interp_block << ", \"fft\": [";
+  for (int p = 0; p < 6; ++p) f << (p ? ", " : "") << t.fft[p];
+  f << "]}\n";
 }
 
 }  // namespace
@@ -94,8 +125,8 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
   const bool was_timing = c->timer.enabled;
   c->timer.enabled = false;
   struct DepCand { int mode, block; };
-  const DepCand dep[] = {{0, 256}, {1, 256}, {2, 256}, {3, 256}, {4, 256}, {5, 256}, {6, 256},
-                         {7, 256}};
+  const DepCand dep[] = {{0, 256}, {0, 512}, {0, 1024}, {1, 256}, {2, 256}, {3, 256}, {4, 256},
+                         {5, 256}, {6, 256}, {7, 256}};
   const DepCand itp[] = {{0, 256}, {0, 512}, {0, 1024}, {1, 256}, {2, 256}, {3, 256}};
   hipEvent_t e0, e1;
   PMNU_HIP(hipEventCreate(&e0));
@@ -153,6 +184,50 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
       best.interp_block = d.block;
     }
   }
+  // the FFT passes, one at a time on the buffers of the step just run, each into an output
+  // other than its input (the data are whatever the step left there; the closing step below
+  // recomputes everything)
+  c->tune = best;
+  rc = pm_nu_step(ctx, pos, acc, a_now);
+  if (rc) return rc;
+  const float kf = static_cast<float>(2.0 * kPi / c->cfg.box_size);
+  const float cgreen =
+      static_cast<float>(1.5 * c->cfg.omega_m * kH0 * kH0 / a_now / static_cast<double>(c->M));
+  const double scale = static_cast<double>(c->M) / static_cast<double>(c->Np) / kFixScale;
+  for (int p = 0; p < 6; ++p) {
+    float best_ms = 1e30f;
+    for (int v = 0; v < 3; ++v) {
+      if (v > 0 && fft_tile(c->N, p, v) == fft_tile(c->N, p, 0)) continue;   // same tile
+      const float ms = time_ms([&](bool prep) -> hipError_t {
+        if (prep) return hipSuccess;
+        switch (p) {
+          case 0:   // the density as the step's deposit left it (delta or the fixed-point sum)
+            return c->density_is_delta
+                       ? launch_fwd_z(c->N, nullptr, c->delta, nullptr, nullptr, 0, c->ck[2],
+                                      c->tw, scale, c->nbox, c->stream, v)
+                       : launch_fwd_z(c->N, c->rho, nullptr, nullptr, nullptr, 0, c->ck[2],
+                                      c->tw, scale, c->nbox, c->stream, v);
+          case 1: return launch_fwd_y(c->N, c->ck[1], c->ck[2], c->tw, c->nbox, c->stream, v);
+          case 2:
+            return launch_fwd_x_bin(c->N, c->ck[0], c->tw, c->bin_of_n2, c->bin_partial, c->B,
+                                    c->nbox, c->stream, v);
+          case 3:
+            return launch_inv_x(c->N, c->ck[0], c->ck[1], c->ck[2], c->tw, c->rtable, c->n2max,
+                                c->inv_w2, cgreen, kf, c->nbox, c->stream, v);
+          case 4:
+            return launch_inv_y(c->N, c->ck[1], c->ck[2], c->ck[0], c->ck[3], c->ck[4], c->tw, kf,
+                                c->nbox, c->stream, v);
+          default:
+            return launch_inv_z(c->N, c->ck[0], c->ck[3], c->ck[4], c->force, c->tw, kf,
+                                c->nbox, c->stream, v);
+        }
+      });
+      if (ms < best_ms) {
+        best_ms = ms;
+        best.fft[p] = v;
+      }
+    }
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   c->tune = best;
@@ -177,6 +252,20 @@ int pm_nu_set_launch(pm_nu_ctx* ctx, int deposit_mode, int deposit_block, int in
   c->tune.deposit_block = deposit_block;
   c->tune.interp_mode = interp_mode;
   c->tune.interp_block = interp_block;
+  return PM_NU_OK;
+}
+
+int pm_nu_set_fft_tiles(pm_nu_ctx* ctx, const int32_t* candidates) {
+  Ctx* c = reinterpret_cast<Ctx*>(ctx);
+  if (!c) return set_error(PM_NU_EINVAL, "ctx is NULL");
+  if (!candidates) return set_error(PM_NU_EINVAL, "candidates is NULL");
+  for (int p = 0; p < 6; ++p)
+    if (candidates[p] < 0 || candidates[p] > 2)
+      return set_error(PM_NU_EINVAL, "FFT tile candidate %d of pass %d: must be 0, 1 or 2",
+                       candidates[p], p);
+  drop_graph(*c);   // a captured step keeps its launch shapes
+  for (int p = 0; p < 6; ++p) c->tune.fft[p] = candidates[p];
+  c->stage = 0;     // the next step starts with a deposit (its bin partials follow the tile)
   return PM_NU_OK;
 }
 

@@ -12,7 +12,9 @@
 // m -> 0 gives a massless species, and photons are (8/7)(11/4)^{4/3} times that.
 #pragma once
 
-#include "pm_nu_internal.hpp"
+#include <vector>
+
+#include "host_consts.hpp"
 
 namespace pmnu {
 

@@ -30,6 +30,8 @@
 //                   components (g_x, g_y, g_z) interleaved per node
 // Since the derivative along an axis commutes with the transforms along the other axes,
 // this needs 2 + 3 intermediate fields instead of 3 + 3 + 3.
+#include <type_traits>
+
 #include "fft_lds.hpp"
 #include "pm_nu_internal.hpp"
 
@@ -48,6 +50,25 @@ template <int N> struct Shape {
   static constexpr int IZ_TY = N < 16 ? N : (N <= 256 ? 16 : 8);
 };
 
+// Tile candidates of every pass for the autotuner: [0] is Shape's default, [1] and [2] the
+// alternatives (below N = 64 the tiles stay fixed). All fit the LDS of one CU and give each
+// transform line the same arithmetic, so every candidate computes the same result.
+template <int N> struct Tiles {
+  static constexpr bool kFixed = N < 64;
+  static constexpr int alt(int d, int a) { return kFixed ? d : a; }
+  static constexpr int FZ[3] = {Shape<N>::FZ_TY, alt(Shape<N>::FZ_TY, Shape<N>::FZ_TY / 2),
+                                alt(Shape<N>::FZ_TY, Shape<N>::FZ_TY * 2)};
+  static constexpr int FY[3] = {Shape<N>::FY_NL, alt(Shape<N>::FY_NL, Shape<N>::FY_NL / 2),
+                                alt(Shape<N>::FY_NL, Shape<N>::FY_NL < 16 ? Shape<N>::FY_NL * 2
+                                                                          : Shape<N>::FY_NL / 4)};
+  static constexpr int FX[3] = {Shape<N>::FX_TX, alt(Shape<N>::FX_TX, Shape<N>::FX_TX == 16 ? 8 : 16),
+                                alt(Shape<N>::FX_TX, Shape<N>::FX_TX == 16 ? 32 : 4)};
+  static constexpr int IX[3] = {Shape<N>::IX_TX, alt(Shape<N>::IX_TX, 4), alt(Shape<N>::IX_TX, 16)};
+  static constexpr int IY[3] = {Shape<N>::IY_NL, alt(Shape<N>::IY_NL, 2), alt(Shape<N>::IY_NL, 8)};
+  static constexpr int IZ[3] = {Shape<N>::IZ_TY, alt(Shape<N>::IZ_TY, Shape<N>::IZ_TY == 16 ? 8 : 16),
+                                alt(Shape<N>::IZ_TY, Shape<N>::IZ_TY == 16 ? 32 : 4)};
+};
+
 __device__ __forceinline__ int signed_index(int i, int n) { return i < n / 2 ? i : i - n; }
 
 // ------------------------------------------------------------------------ forward ----
@@ -55,13 +76,13 @@ __device__ __forceinline__ int signed_index(int i, int n) { return i < n / 2 ? i
 // from the exact sum and rounded once to FP32) or delta already in FP32 (DELTA = true;
 // then thread 0 of the first workgroup also moves the side-grid counter of the patch
 // deposit, whose last reader ran before this kernel, into its running total).
-template <int N, bool DELTA>
+template <int N, bool DELTA, int TY>
 __global__ __launch_bounds__(NT) void fwd_z_kernel(const void* __restrict__ in,
                                                    float2* __restrict__ out,
                                                    const float2* __restrict__ twg,
                                                    double scale, int* __restrict__ reset,
                                                    int* __restrict__ clear, int n_clear) {
-  constexpr int TY = Shape<N>::FZ_TY, NL = TY / 2, ES = NL + 1, NK = Shape<N>::NK;
+  constexpr int NL = TY / 2, ES = NL + 1, NK = Shape<N>::NK;
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
   const int y0 = blockIdx.x * TY, x = blockIdx.y, box = blockIdx.z;
@@ -128,11 +149,11 @@ __global__ __launch_bounds__(NT) void fwd_z_kernel(const void* __restrict__ in,
 
 // in: rows of [box][x][kz] (flattened, NL consecutive rows per workgroup);
 // out: the same rows at [box][kz][x].
-template <int N>
+template <int N, int NL>
 __global__ __launch_bounds__(NT) void fwd_y_kernel(const float2* __restrict__ in,
                                                    float2* __restrict__ out,
                                                    const float2* __restrict__ twg) {
-  constexpr int NL = Shape<N>::FY_NL, ES = NL + 1, NK = Shape<N>::NK;
+  constexpr int ES = NL + 1, NK = Shape<N>::NK;
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
   load_twiddles<N, NT>(tw, twg);
@@ -170,12 +191,12 @@ __global__ __launch_bounds__(NT) void fwd_y_kernel(const float2* __restrict__ in
 
 // STORE: write the transformed tile back (only for reading the modes out); BIN: the mode
 // sums per k-bin (the step bins without storing; the inverse pass redoes the x transform).
-template <int N, bool STORE, bool BIN>
+template <int N, bool STORE, bool BIN, int TX>
 __global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data,
                                                        const float2* __restrict__ twg,
                                                        const uint16_t* __restrict__ bin_of_n2,
                                                        double* __restrict__ partial, int nbins) {
-  constexpr int TX = Shape<N>::FX_TX, ES = TX + 1, NK = Shape<N>::NK;
+  constexpr int ES = TX + 1, NK = Shape<N>::NK;
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
   extern __shared__ double bins[];
@@ -259,7 +280,7 @@ __global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data
 }
 
 // ------------------------------------------------------------------------ inverse ----
-template <int N>
+template <int N, int TX>
 __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk,
                                                    float2* __restrict__ f1,
                                                    float2* __restrict__ f2,
@@ -267,7 +288,7 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
                                                    const float* __restrict__ rtable, int n2max,
                                                    const float* __restrict__ inv_w2,
                                                    float c, float kf, int nbox) {
-  constexpr int TX = Shape<N>::IX_TX, NL = 2 * TX, ES = NL + 1, NK = Shape<N>::NK;
+  constexpr int NL = 2 * TX, ES = NL + 1, NK = Shape<N>::NK;
   constexpr int NYB = N / TX;
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
@@ -350,14 +371,14 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
 }
 
 // in: rows of [box][kz][x] (flattened); out: G1, G2, G3 rows at [box][x][kz].
-template <int N>
+template <int N, int NLR>
 __global__ __launch_bounds__(NT) void inv_y_kernel(const float2* __restrict__ f1,
                                                    const float2* __restrict__ f2,
                                                    float2* __restrict__ g1,
                                                    float2* __restrict__ g2,
                                                    float2* __restrict__ g3,
                                                    const float2* __restrict__ twg, float kf) {
-  constexpr int NLR = Shape<N>::IY_NL, NL = 3 * NLR, ES = NL + 1;
+  constexpr int NL = 3 * NLR, ES = NL + 1;
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
   load_twiddles<N, NT>(tw, twg);
@@ -412,14 +433,14 @@ __global__ __launch_bounds__(NT) void inv_y_kernel(const float2* __restrict__ f1
 }
 
 // out: [nbox][x][y][z][3] with component 0 = g_x (from G3), 1 = g_y (G2), 2 = g_z (G1).
-template <int N>
+template <int N, int TY>
 __global__ __launch_bounds__(NT) void inv_z_kernel(const float2* __restrict__ g1,
                                                    const float2* __restrict__ g2,
                                                    const float2* __restrict__ g3,
                                                    float* __restrict__ out,
                                                    const float2* __restrict__ twg, float kf,
                                                    int nbox) {
-  constexpr int TY = Shape<N>::IZ_TY, ROWS = 3 * TY, NL = ROWS / 2, ES = NL + 1;
+  constexpr int ROWS = 3 * TY, NL = ROWS / 2, ES = NL + 1;
   constexpr int NK = Shape<N>::NK;
   static_assert(TY % 2 == 0 && NT % (TY / 2) == 0, "row pairs per float4");
   // Loads: float4 = the values of one k at two consecutive y (a row pair), for the three
@@ -503,6 +524,17 @@ __global__ void copy_modes_kernel(const float2* __restrict__ ck, float2* __restr
 }
 
 // ------------------------------------------------------------------ dispatchers ----
+// Call go(std::integral_constant<int, tile>) with tile candidate v of a pass (v outside 1..2:
+// the default, candidate 0).
+template <int T0, int T1, int T2, typename F>
+hipError_t with_tile(F&& go, int v) {
+  switch (v) {
+    case 1: return go(std::integral_constant<int, T1>{});
+    case 2: return go(std::integral_constant<int, T2>{});
+    default: return go(std::integral_constant<int, T0>{});
+  }
+}
+#define PMNU_TILES(ARR) Tiles<N>::ARR[0], Tiles<N>::ARR[1], Tiles<N>::ARR[2]
 template <template <int> class F, typename... A>
 hipError_t dispatch_n(int n, A... args) {
   switch (n) {
@@ -520,68 +552,92 @@ hipError_t dispatch_n(int n, A... args) {
 template <int N> struct FwdZ {
   static hipError_t run(const unsigned long long* rho, const float* delta, int* reset,
                         int* clear, int n_clear, float2* out, const float2* tw, double scale,
-                        int nbox, hipStream_t s) {
-    dim3 grid(N / Shape<N>::FZ_TY, N, nbox);
-    if (static_cast<int64_t>(grid.x) * grid.y * grid.z * NT < n_clear)
-      return hipErrorInvalidValue;                 // every count needs a thread to clear it
-    if (delta)
-      hipLaunchKernelGGL((fwd_z_kernel<N, true>), grid, dim3(NT), 0, s, delta, out, tw, scale,
-                         reset, clear, n_clear);
-    else
-      hipLaunchKernelGGL((fwd_z_kernel<N, false>), grid, dim3(NT), 0, s, rho, out, tw, scale,
-                         reset, clear, n_clear);
-    return hipGetLastError();
+                        int nbox, hipStream_t s, int v) {
+    auto go = [&](auto ty) -> hipError_t {
+      constexpr int TY = decltype(ty)::value;
+      dim3 grid(N / TY, N, nbox);
+      if (static_cast<int64_t>(grid.x) * grid.y * grid.z * NT < n_clear)
+        return hipErrorInvalidValue;               // every count needs a thread to clear it
+      if (delta)
+        hipLaunchKernelGGL((fwd_z_kernel<N, true, TY>), grid, dim3(NT), 0, s, delta, out, tw,
+                           scale, reset, clear, n_clear);
+      else
+        hipLaunchKernelGGL((fwd_z_kernel<N, false, TY>), grid, dim3(NT), 0, s, rho, out, tw,
+                           scale, reset, clear, n_clear);
+      return hipGetLastError();
+    };
+    return with_tile<PMNU_TILES(FZ)>(go, v);
   }
 };
 template <int N> struct FwdY {
   static hipError_t run(const float2* in, float2* out, const float2* tw, int nbox,
-                        hipStream_t s) {
-    dim3 grid(static_cast<unsigned>(static_cast<int64_t>(nbox) * Shape<N>::NK * N /
-                                    Shape<N>::FY_NL));
-    hipLaunchKernelGGL(fwd_y_kernel<N>, grid, dim3(NT), 0, s, in, out, tw);
-    return hipGetLastError();
+                        hipStream_t s, int v) {
+    auto go = [&](auto nl) -> hipError_t {
+      constexpr int NL = decltype(nl)::value;
+      dim3 grid(static_cast<unsigned>(static_cast<int64_t>(nbox) * Shape<N>::NK * N / NL));
+      hipLaunchKernelGGL((fwd_y_kernel<N, NL>), grid, dim3(NT), 0, s, in, out, tw);
+      return hipGetLastError();
+    };
+    return with_tile<PMNU_TILES(FY)>(go, v);
   }
 };
 template <int N> struct FwdX {
   // partial != NULL: bin without storing (the step); NULL: store the modes, no binning
   static hipError_t run(float2* data, const float2* tw, const uint16_t* bins, double* partial,
-                        int nbins, int nbox, hipStream_t s) {
-    dim3 grid(N / Shape<N>::FX_TX, Shape<N>::NK, nbox);
-    if (partial)
-      hipLaunchKernelGGL((fwd_x_bin_kernel<N, false, true>), grid, dim3(NT),
-                         nbins * sizeof(double), s, data, tw, bins, partial, nbins);
-    else
-      hipLaunchKernelGGL((fwd_x_bin_kernel<N, true, false>), grid, dim3(NT), 0, s, data, tw,
-                         bins, partial, nbins);
-    return hipGetLastError();
+                        int nbins, int nbox, hipStream_t s, int v) {
+    auto go = [&](auto tx) -> hipError_t {
+      constexpr int TX = decltype(tx)::value;
+      dim3 grid(N / TX, Shape<N>::NK, nbox);
+      if (partial)
+        hipLaunchKernelGGL((fwd_x_bin_kernel<N, false, true, TX>), grid, dim3(NT),
+                           nbins * sizeof(double), s, data, tw, bins, partial, nbins);
+      else
+        hipLaunchKernelGGL((fwd_x_bin_kernel<N, true, false, TX>), grid, dim3(NT), 0, s, data,
+                           tw, bins, partial, nbins);
+      return hipGetLastError();
+    };
+    return with_tile<PMNU_TILES(FX)>(go, v);
   }
 };
 template <int N> struct InvX {
   static hipError_t run(const float2* dk, float2* f1, float2* f2, const float2* tw,
                         const float* rt, int n2max, const float* iw, float cfac,
-                        float kf, int nbox, hipStream_t s) {
-    const int total = N / Shape<N>::IX_TX * Shape<N>::NK * nbox;
-    dim3 grid((total + 7) / 8 * 8);   // whole rounds over the 8 XCDs; extra blocks exit
-    hipLaunchKernelGGL(inv_x_kernel<N>, grid, dim3(NT), 0, s, dk, f1, f2, tw, rt, n2max, iw,
-                       cfac, kf, nbox);
-    return hipGetLastError();
+                        float kf, int nbox, hipStream_t s, int v) {
+    auto go = [&](auto txv) -> hipError_t {
+      constexpr int TX = decltype(txv)::value;
+      const int total = N / TX * Shape<N>::NK * nbox;
+      dim3 grid((total + 7) / 8 * 8);   // whole rounds over the 8 XCDs; extra blocks exit
+      hipLaunchKernelGGL((inv_x_kernel<N, TX>), grid, dim3(NT), 0, s, dk, f1, f2, tw, rt, n2max,
+                         iw, cfac, kf, nbox);
+      return hipGetLastError();
+    };
+    return with_tile<PMNU_TILES(IX)>(go, v);
   }
 };
 template <int N> struct InvY {
   static hipError_t run(const float2* f1, const float2* f2, float2* g1, float2* g2, float2* g3,
-                        const float2* tw, float kf, int nbox, hipStream_t s) {
-    dim3 grid(static_cast<unsigned>(static_cast<int64_t>(nbox) * Shape<N>::NK * N /
-                                    Shape<N>::IY_NL));
-    hipLaunchKernelGGL(inv_y_kernel<N>, grid, dim3(NT), 0, s, f1, f2, g1, g2, g3, tw, kf);
-    return hipGetLastError();
+                        const float2* tw, float kf, int nbox, hipStream_t s, int v) {
+    auto go = [&](auto nl) -> hipError_t {
+      constexpr int NLR = decltype(nl)::value;
+      dim3 grid(static_cast<unsigned>(static_cast<int64_t>(nbox) * Shape<N>::NK * N / NLR));
+      hipLaunchKernelGGL((inv_y_kernel<N, NLR>), grid, dim3(NT), 0, s, f1, f2, g1, g2, g3, tw,
+                         kf);
+      return hipGetLastError();
+    };
+    return with_tile<PMNU_TILES(IY)>(go, v);
   }
 };
 template <int N> struct InvZ {
   static hipError_t run(const float2* g1, const float2* g2, const float2* g3, float* out,
-                        const float2* tw, float kf, int nbox, hipStream_t s) {
-    dim3 grid(N / Shape<N>::IZ_TY, N, nbox);
-    hipLaunchKernelGGL(inv_z_kernel<N>, grid, dim3(NT), 0, s, g1, g2, g3, out, tw, kf, nbox);
-    return hipGetLastError();
+                        const float2* tw, float kf, int nbox, hipStream_t s, int v) {
+    auto go = [&](auto ty) -> hipError_t {
+      constexpr int TY = decltype(ty)::value;
+      dim3 grid(N / TY, N, nbox);
+      hipLaunchKernelGGL((inv_z_kernel<N, TY>), grid, dim3(NT), 0, s, g1, g2, g3, out, tw, kf,
+                         nbox);
+      return hipGetLastError();
+    };
+    return with_tile<PMNU_TILES(IZ)>(go, v);
   }
 };
 template <int N> struct CopyModes {
@@ -591,8 +647,25 @@ template <int N> struct CopyModes {
   }
 };
 template <int N> struct Partials {
-  static hipError_t run(int* out) {
-    *out = (N / Shape<N>::FX_TX) * Shape<N>::NK;
+  static hipError_t run(int* out, int v) {
+    return with_tile<PMNU_TILES(FX)>([&](auto tx) {
+      *out = (N / decltype(tx)::value) * Shape<N>::NK;
+      return hipSuccess;
+    }, v);
+  }
+};
+template <int N> struct TileOf {
+  static hipError_t run(int* out, int pass, int v) {
+    const int i = (v == 1 || v == 2) ? v : 0;
+    switch (pass) {
+      case 0: *out = Tiles<N>::FZ[i]; break;
+      case 1: *out = Tiles<N>::FY[i]; break;
+      case 2: *out = Tiles<N>::FX[i]; break;
+      case 3: *out = Tiles<N>::IX[i]; break;
+      case 4: *out = Tiles<N>::IY[i]; break;
+      case 5: *out = Tiles<N>::IZ[i]; break;
+      default: return hipErrorInvalidValue;
+    }
     return hipSuccess;
   }
 };
@@ -601,34 +674,39 @@ template <int N> struct Partials {
 
 hipError_t launch_fwd_z(int n, const unsigned long long* rho, const float* delta, int* reset,
                         int* clear, int n_clear, float2* out, const float2* tw, double scale,
-                        int nbox, hipStream_t s) {
-  return dispatch_n<FwdZ>(n, rho, delta, reset, clear, n_clear, out, tw, scale, nbox, s);
+                        int nbox, hipStream_t s, int v) {
+  return dispatch_n<FwdZ>(n, rho, delta, reset, clear, n_clear, out, tw, scale, nbox, s, v);
 }
 hipError_t launch_fwd_y(int n, const float2* in, float2* out, const float2* tw, int nbox,
-                        hipStream_t s) {
-  return dispatch_n<FwdY>(n, in, out, tw, nbox, s);
+                        hipStream_t s, int v) {
+  return dispatch_n<FwdY>(n, in, out, tw, nbox, s, v);
 }
 hipError_t launch_fwd_x_bin(int n, float2* data, const float2* tw, const uint16_t* bin_of_n2,
-                            double* partial, int nbins, int nbox, hipStream_t s) {
-  return dispatch_n<FwdX>(n, data, tw, bin_of_n2, partial, nbins, nbox, s);
+                            double* partial, int nbins, int nbox, hipStream_t s, int v) {
+  return dispatch_n<FwdX>(n, data, tw, bin_of_n2, partial, nbins, nbox, s, v);
 }
-int fwd_x_partials(int n) {
+int fwd_x_partials(int n, int v) {
   int out = 0;
-  if (dispatch_n<Partials>(n, &out) != hipSuccess) return 0;
+  if (dispatch_n<Partials>(n, &out, v) != hipSuccess) return 0;
+  return out;
+}
+int fft_tile(int n, int pass, int v) {
+  int out = 0;
+  if (dispatch_n<TileOf>(n, &out, pass, v) != hipSuccess) return 0;
   return out;
 }
 hipError_t launch_inv_x(int n, const float2* dk, float2* f1, float2* f2, const float2* tw,
                         const float* rtable, int n2max, const float* inv_w2,
-                        float cfac, float kf, int nbox, hipStream_t s) {
-  return dispatch_n<InvX>(n, dk, f1, f2, tw, rtable, n2max, inv_w2, cfac, kf, nbox, s);
+                        float cfac, float kf, int nbox, hipStream_t s, int v) {
+  return dispatch_n<InvX>(n, dk, f1, f2, tw, rtable, n2max, inv_w2, cfac, kf, nbox, s, v);
 }
 hipError_t launch_inv_y(int n, const float2* f1, const float2* f2, float2* g1, float2* g2,
-                        float2* g3, const float2* tw, float kf, int nbox, hipStream_t s) {
-  return dispatch_n<InvY>(n, f1, f2, g1, g2, g3, tw, kf, nbox, s);
+                        float2* g3, const float2* tw, float kf, int nbox, hipStream_t s, int v) {
+  return dispatch_n<InvY>(n, f1, f2, g1, g2, g3, tw, kf, nbox, s, v);
 }
 hipError_t launch_inv_z(int n, const float2* g1, const float2* g2, const float2* g3, float* out,
-                        const float2* tw, float kf, int nbox, hipStream_t s) {
-  return dispatch_n<InvZ>(n, g1, g2, g3, out, tw, kf, nbox, s);
+                        const float2* tw, float kf, int nbox, hipStream_t s, int v) {
+  return dispatch_n<InvZ>(n, g1, g2, g3, out, tw, kf, nbox, s, v);
 }
 hipError_t launch_copy_modes(int n, const float2* ck, float2* out, int box, hipStream_t s) {
   return dispatch_n<CopyModes>(n, ck, out, box, s);

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "background.hpp"
+#include "host_math.hpp"
 #include "pm_nu_internal.hpp"
 
 namespace pmnu {
@@ -125,39 +126,15 @@ int dalloc(T** p, size_t count) {
 
 void free_ctx(Ctx* c);
 
-// Bin geometry from the multiplicity of every integer |n|^2 (full sphere of modes).
+// Bin geometry (host_math.cpp) and its table of bins per integer |n|^2 on the device.
 void build_bins(Ctx& c) {
-  const int n = c.N, B = c.B;
-  const double r2 = 3.0 * n * n / 4.0;
-  c.edges.assign(B + 1, 0);
-  for (int b = 0; b <= B; ++b)
-    c.edges[b] = static_cast<int64_t>(std::ceil(std::pow(r2, static_cast<double>(b) / B)));
-  c.edges[0] = 1;
-  std::vector<int64_t> mult(c.n2max + 1, 0);
-  const int h = n / 2;
-  for (int i = -h; i < h; ++i)
-    for (int j = -h; j < h; ++j)
-      for (int l = -h; l < h; ++l) ++mult[i * i + j * j + l * l];
-  std::vector<uint16_t> bin(c.n2max + 1, 0);
-  c.counts.assign(B, 0.0);
-  std::vector<double> ksum(B, 0.0);
-  const double kf = 2.0 * kPi / c.cfg.box_size;
-  int b = 0;
-  for (int n2 = 1; n2 <= c.n2max; ++n2) {
-    while (b < B - 1 && n2 >= c.edges[b + 1]) ++b;
-    bin[n2] = static_cast<uint16_t>(b);
-    c.counts[b] += static_cast<double>(mult[n2]);
-    ksum[b] += static_cast<double>(mult[n2]) * kf * std::sqrt(static_cast<double>(n2));
-  }
-  c.kmean.assign(B, 0.0);
-  c.nonempty.clear();
-  for (int k = 0; k < B; ++k) {
-    if (c.counts[k] > 0) {
-      c.kmean[k] = ksum[k] / c.counts[k];
-      c.nonempty.push_back(k);
-    }
-  }
-  hipMemcpy(c.bin_of_n2, bin.data(), bin.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+  BinGeometry g = make_bin_geometry(c.N, c.cfg.box_size, c.B);
+  c.edges = g.edges;
+  c.counts = g.counts;
+  c.kmean = g.kmean;
+  c.nonempty = g.nonempty;
+  hipMemcpy(c.bin_of_n2, g.bin_of_n2.data(), g.bin_of_n2.size() * sizeof(uint16_t),
+            hipMemcpyHostToDevice);
 }
 
 // Node list of one box for a response at a_now: the stored nodes strictly before a_now
@@ -180,20 +157,6 @@ int nodes_for(const Ctx& c, int box, double a_now, std::vector<double>& nodes, i
   return PM_NU_OK;
 }
 
-// Time grid of eq. (P-final) for every box at a_now (host FP64, uploaded when changed).
-// Sub-nodes of one interval [a_lo, a_hi] of the quadrature (Q steps in ln a): their scale
-// factors, the s difference to the next sub-node, and 1/(a H).
-void interval_nodes(const Background& bg, double a_lo, double a_hi, int Q, double* a,
-                    double* seg, double* hinv) {
-  const double u0 = std::log(a_lo), u1 = std::log(a_hi);
-  const double h = (u1 - u0) / Q;
-  for (int r = 0; r < Q; ++r) a[r] = (r == 0) ? a_lo : std::exp(u0 + r * h);
-  for (int r = 0; r < Q; ++r) {
-    seg[r] = ds_of(bg, a[r], r + 1 < Q ? a[r + 1] : a_hi);
-    hinv[r] = 1.0 / (a[r] * hubble_of(bg, a[r]));
-  }
-}
-
 // Time grid of eq. (P-final) for every box at a_now (host FP64). The sub-intervals between
 // stored nodes are kept per box and only the newest interval, to a_now, is integrated
 // afresh; the arrays go to the device by stream-ordered copies from pinned staging.
@@ -213,7 +176,7 @@ int prepare_time_grid(Ctx& c, double a_now) {
   PMNU_HIP(hipEventSynchronize(c.ev_tg));     // the staging's previous upload has run
   double* ds_all = c.h_tg;
   double* w_all = c.h_tg + c.nbox * qcap;
-  std::vector<double> tw, a_last(Q), seg_last(Q), hinv_last(Q);
+  std::vector<double> a_last(Q), seg_last(Q), hinv_last(Q);
   for (int b = 0; b < c.nbox; ++b) {
     const std::vector<double>& nd = all_nodes[b];
     const int n = ncur[b];
@@ -242,23 +205,10 @@ int prepare_time_grid(Ctx& c, double a_now) {
     cc.nodes.assign(nd.begin(), nd.begin() + n);
     if (n > 0)
       interval_nodes(bg, nd[n - 1], nd[n], Q, a_last.data(), seg_last.data(), hinv_last.data());
-    const int q_last = (n - 1) * Q;   // first sub-node of the interval to a_now
-    tw.assign(nq, 0.0);
-    for (int jj = 0; jj < n; ++jj) {
-      const double h = (std::log(nd[jj + 1]) - std::log(nd[jj])) / Q;
-      for (int r = 0; r < Q; ++r) {
-        tw[jj * Q + r] += (r == 0) ? 0.5 * h : h;
-        tw[jj * Q + r + 1] += (r == Q - 1) ? 0.5 * h : 0.0;
-      }
-    }
     double* dsb = ds_all + b * qcap;
     double* wb = w_all + b * qcap;
-    dsb[nq - 1] = 0.0;
-    for (int q = nq - 2; q >= 0; --q)
-      dsb[q] = dsb[q + 1] + (q < q_last ? cc.seg[q] : seg_last[q - q_last]);
-    for (int q = 0; q < nq - 1; ++q)
-      wb[q] = pref * tw[q] * (q < q_last ? cc.hinv[q] : hinv_last[q - q_last]);
-    wb[nq - 1] = pref * tw[nq - 1] / (nd[n] * hubble_of(bg, nd[n]));
+    assemble_time_grid(bg, nd.data(), n, Q, pref, cc.seg.data(), cc.hinv.data(),
+                       seg_last.data(), hinv_last.data(), dsb, wb);
     RespBox& rb = c.h_resp[b];
     rb = RespBox();
     rb.f_nu = c.f_nu[b];
@@ -323,19 +273,22 @@ int do_deposit(Ctx& c, const float* pos) {
                               c.nbox, c.N, scale, c.stream));
     TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, nullptr, c.delta, c.n_fb, c.reg_count,
                                     static_cast<int>(c.nbox * patch_coarse_cells(c.N)), c.ck[1],
-                                    c.tw, scale, c.nbox, c.stream));
+                                    c.tw, scale, c.nbox, c.stream, c.tune.fft[0]));
     c.density_is_delta = true;
   } else {
     TIMED(c, ST_ZERO, launch_fill_zero(c.rho, cells * 8, c.stream));
     TIMED(c, ST_DEPOSIT, launch_deposit(pos, c.rho, c.Np, c.nbox, c.N, inv_cell, c.d_flags,
                                         c.tune.deposit_mode, c.tune.deposit_block, c.stream));
     TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, c.rho, nullptr, nullptr, nullptr, 0, c.ck[1], c.tw,
-                                    scale, c.nbox, c.stream));
+                                    scale, c.nbox, c.stream, c.tune.fft[0]));
     c.density_is_delta = false;
   }
-  TIMED(c, ST_FFT_Y, launch_fwd_y(c.N, c.ck[1], c.ck[0], c.tw, c.nbox, c.stream));
+  TIMED(c, ST_FFT_Y, launch_fwd_y(c.N, c.ck[1], c.ck[0], c.tw, c.nbox, c.stream,
+                                  c.tune.fft[1]));
+  // the number of partial bin sums follows the tile of this pass
+  c.n_partial = fwd_x_partials(c.N, c.tune.fft[2]);
   TIMED(c, ST_FFT_X_BIN, launch_fwd_x_bin(c.N, c.ck[0], c.tw, c.bin_of_n2, c.bin_partial,
-                                          c.B, c.nbox, c.stream));
+                                          c.B, c.nbox, c.stream, c.tune.fft[2]));
   c.stage = 1;
   c.modes_valid = true;
   c.pos_dep = pos;
@@ -398,11 +351,11 @@ int do_force(Ctx& c, const float* pos, float* acc, double a_now, const Leap* lp 
   const double cgreen = 1.5 * c.cfg.omega_m * kH0 * kH0 / a_now / static_cast<double>(c.M);
   TIMED(c, ST_INV_X_GREEN,
         launch_inv_x(c.N, c.ck[0], c.ck[1], c.ck[2], c.tw, c.rtable, c.n2max, c.inv_w2,
-                     static_cast<float>(cgreen), kf, c.nbox, c.stream));
+                     static_cast<float>(cgreen), kf, c.nbox, c.stream, c.tune.fft[3]));
   TIMED(c, ST_INV_Y, launch_inv_y(c.N, c.ck[1], c.ck[2], c.ck[0], c.ck[3], c.ck[4], c.tw, kf,
-                                  c.nbox, c.stream));
+                                  c.nbox, c.stream, c.tune.fft[4]));
   TIMED(c, ST_INV_Z, launch_inv_z(c.N, c.ck[0], c.ck[3], c.ck[4], c.force, c.tw, kf, c.nbox,
-                                  c.stream));
+                                  c.stream, c.tune.fft[5]));
   TIMED(c, ST_INTERP, launch_interp(pos, c.force, acc, c.Np, c.nbox, c.N,
                                     c.N / c.cfg.box_size, c.tune.interp_mode,
                                     c.tune.interp_block, c.stream, lp));
@@ -492,7 +445,11 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   c->MH = static_cast<int64_t>(c->NK) * c->N * c->N;
   c->n2max = 3 * c->N * c->N / 4;
   c->qcap = (c->Jcap - 1) * c->Q + 1;
-  c->n_partial = fwd_x_partials(c->N);
+  c->n_partial = fwd_x_partials(c->N, 0);
+  // room for the partial sums of every tile candidate of the binning pass
+  int max_partial = c->n_partial;
+  for (int v = 1; v < 3; ++v) max_partial = std::max(max_partial, fwd_x_partials(c->N, v));
+  c->n_partial_cap = max_partial;
   // the patch deposit is the faster one once the mesh holds many coarse cells
   c->tune.deposit_mode = c->N >= 64 ? 6 : 4;
   c->stream = static_cast<hipStream_t>(cfg->stream);
@@ -525,7 +482,7 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   ALLOC(c->rho, nb * c->M);
   for (int i = 0; i < 5; ++i) ALLOC(c->ck[i], nb * c->MH);
   ALLOC(c->force, 3 * nb * c->M);
-  ALLOC(c->bin_partial, nb * c->n_partial * B);
+  ALLOC(c->bin_partial, nb * c->n_partial_cap * B);
   ALLOC(c->bin_of_n2, static_cast<size_t>(c->n2max) + 1);
   ALLOC(c->d_counts, B);
   ALLOC(c->d_kmean, B);

@@ -8,16 +8,11 @@
 #include <vector>
 
 #include "../../include/pm_nu.h"
+#include "host_consts.hpp"
 
 namespace pmnu {
 
-constexpr double kC_KMS = 299792.458;
-constexpr double kH0 = 100.0 / kC_KMS;                 // h/Mpc, c = 1
-constexpr double kTnu0 = 1.95 * 8.617333262e-5;         // eV (1.95 K)
-constexpr double kPi = 3.14159265358979323846;
-
 // Per-box constants of the response kernel (device copy, one per box).
-constexpr int kMaxSpecies = 4;   // neutrino species with their own masses
 
 struct RespBox {
   double f_nu;       // Omega_nu / Omega_M
@@ -61,6 +56,9 @@ struct Tuning {
   int deposit_block = 256;   // block size of mode 0
   int interp_mode = 1;       // see launch_interp
   int interp_block = 256;    // block size of mode 0
+  // tile candidate (0 default, 1, 2) of each FFT pass: fwd_z, fwd_y, fwd_x, inv_x, inv_y,
+  // inv_z (fft_tile gives the tile); the same result for every candidate
+  int fft[6] = {0, 0, 0, 0, 0, 0};
 };
 
 struct Timer {
@@ -95,7 +93,8 @@ struct Ctx {
   int64_t Np = 0, M = 0, MH = 0;   // particles per box, N^3, (N/2+1) N^2
   int n2max = 0;                   // 3 N^2 / 4
   int qcap = 0;                    // sub-node capacity per box
-  int n_partial = 0;               // per-box partial bin sums
+  int n_partial = 0;               // per-box partial bin sums (of the binning pass's tile)
+  int n_partial_cap = 0;           // the most any tile candidate writes (buffer size)
   hipStream_t stream = nullptr;
   int device = 0;
 
@@ -234,21 +233,27 @@ hipError_t launch_interp(const float* pos, const float* force, float* acc, int64
 // (NULL: none); a clear larger than the launch's thread count is rejected
 hipError_t launch_fwd_z(int N, const unsigned long long* rho, const float* delta, int* reset,
                         int* clear, int n_clear, float2* out, const float2* tw, double scale,
-                        int nbox, hipStream_t s);
+                        int nbox, hipStream_t s, int v = 0);
 hipError_t launch_fwd_y(int N, const float2* in, float2* out, const float2* tw, int nbox,
-                        hipStream_t s);
+                        hipStream_t s, int v = 0);
 // partial != NULL: FFT along x and the mode sums per bin, data left unchanged (the step);
 // partial == NULL: FFT along x stored in place, no sums (reading the modes out)
 hipError_t launch_fwd_x_bin(int N, float2* data, const float2* tw, const uint16_t* bin_of_n2,
-                            double* partial, int B, int nbox, hipStream_t s);
-int fwd_x_partials(int N);   // partial bin sums per box written by launch_fwd_x_bin
+                            double* partial, int B, int nbox, hipStream_t s, int v = 0);
+// partial bin sums per box written by launch_fwd_x_bin with tile candidate v
+int fwd_x_partials(int N, int v = 0);
+// tile of FFT pass `pass` (0 fwd_z rows, 1 fwd_y lines, 2 fwd_x columns, 3 inv_x columns,
+// 4 inv_y lines, 5 inv_z rows) for candidate v (0 default, 1, 2); 0 for a bad N or pass
+int fft_tile(int N, int pass, int v);
 hipError_t launch_inv_x(int N, const float2* dk, float2* f1, float2* f2, const float2* tw,
                         const float* rtable, int n2max, const float* inv_w2,
-                        float cfac, float kf, int nbox, hipStream_t s);
+                        float cfac, float kf, int nbox, hipStream_t s, int v = 0);
 hipError_t launch_inv_y(int N, const float2* f1, const float2* f2, float2* g1, float2* g2,
-                        float2* g3, const float2* tw, float kf, int nbox, hipStream_t s);
+                        float2* g3, const float2* tw, float kf, int nbox, hipStream_t s,
+                        int v = 0);
 hipError_t launch_inv_z(int N, const float2* g1, const float2* g2, const float2* g3,
-                        float* out, const float2* tw, float kf, int nbox, hipStream_t s);
+                        float* out, const float2* tw, float kf, int nbox, hipStream_t s,
+                        int v = 0);
 hipError_t launch_copy_modes(int N, const float2* ck, float2* out, int box, hipStream_t s);
 // response_kernels.hip
 hipError_t launch_response(const RespBox* boxes, const double* partial, int n_partial,

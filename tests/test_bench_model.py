@@ -64,10 +64,16 @@ def test_traffic_table_from_counter_csvs(tmp_path):
     assert t["kernels"]["fft_fwd_z"]["fwd_z_kernel<256>"]["bytes_per_launch"] == 1024 * 125.0
     assert bench.kernel_name("cic_deposit", {"deposit_mode": 2}, 256) == \
         "deposit_tiled_kernel<2048, 5120, 256>"
-    assert bench.kernel_name("fft_inv_z", {}, 512) == "inv_z_kernel<512>"
-    assert bench.kernel_name("fft_fwd_z", {"deposit_mode": 6}, 256) == "fwd_z_kernel<256, true>"
+    tiles = {"fft_tiles": {"fwd_z": 32, "fwd_y": 16, "fwd_x": 16, "inv_x": 8, "inv_y": 4,
+                           "inv_z": 8}}
+    assert bench.kernel_name("fft_inv_z", tiles, 512) == "inv_z_kernel<512, 8>"
+    assert bench.kernel_name("fft_fwd_z", dict(tiles, deposit_mode=6), 256) == \
+        "fwd_z_kernel<256, true, 32>"
+    assert bench.kernel_name("fft_fwd_x_bin", tiles, 256) == \
+        "fwd_x_bin_kernel<256, false, true, 16>"
     assert bench.kernel_name("cic_deposit", {"deposit_mode": 6}, 256) == \
         "deposit_patch_kernel<4096, 6144, 512>"
     assert bench.kernel_name("cic_deposit", {"deposit_mode": 7}, 256) == \
         "deposit_patch_kernel<4096, 9216, 512>"
-    assert bench.kernel_name("fft_fwd_z", {"deposit_mode": 7}, 256) == "fwd_z_kernel<256, true>"
+    assert bench.kernel_name("fft_fwd_z", dict(tiles, deposit_mode=7), 256) == \
+        "fwd_z_kernel<256, true, 32>"

@@ -42,7 +42,7 @@ def _run(m_nu, pos, vel, n_mesh, box, nb, steps, f_i):
     assert len(a) == len(steps) and a[-1] == steps[-1]
     assert bool(torch.isfinite(p).all() and torch.isfinite(v).all())
     ctx.close()
-    return pm[-1], counts, kmean, rnu, theta
+    return pm, counts, kmean, rnu, theta
 
 
 def test_suppression_matches_linear_theory_on_large_scales():
@@ -56,20 +56,29 @@ def test_suppression_matches_linear_theory_on_large_scales():
     pm_nu, counts, k, rnu, theta = _run(m_nu, pos, vel, n, box, nb, steps, f_i)
     pm_0, _, _, _, _ = _run(0.0, pos, vel, n, box, nb, steps, f_i)
     ok = counts > 0
-    sim = (pm_nu[ok] / pm_0[ok]) ** 2
+    sim = (pm_nu[-1][ok] / pm_0[-1][ok]) ** 2
     a_fine = np.geomspace(a_i, 1.0, 401)
     lin = linear.linear_modes(k[ok], a_fine, m_nu, rnu[ok], theta[ok], f_i)["d_m"][-1]
     lin0 = linear.linear_modes(k[ok], a_fine, 0.0, np.zeros(ok.sum()), np.zeros(ok.sum()),
                                f_i)["d_m"][-1]
+    # the massless run's own mode coupling: its power over linear growth from the same
+    # initial amplitudes (node 0 of its history), minus one
+    eps_nl = (pm_0[-1][ok] / pm_0[0][ok]) ** 2 / lin0 ** 2 - 1.0
     lin = (lin / lin0) ** 2
     fn = m_nu / (93.14 * 0.3 * 0.49)
-    for kk, s, l in zip(k[ok], sim, lin):
-        print(f"  k {kk:.4f}  dP/P / f_nu: particles {(s - 1) / fn:+.2f}  linear {(l - 1) / fn:+.2f}",
+    # Bar per bin: at one loop the non-linear part of either run is C(k) = eps_nl P_L with
+    # two linear powers inside the mode-coupling integral, so the neutrino run's is
+    # <s s'> C with s the linear suppression of the coupled modes; the ratio then moves by
+    # eps_nl (<s s'>/s - 1), at most eps_nl * 2 (1 - min s) in size. 5e-4 covers what is
+    # left: the leapfrog's second-order error (7e-5 of the growth at 48 steps) and the
+    # history quadrature (f_nu times 4e-4 of R), both nearly common to the two runs.
+    tol = np.abs(eps_nl) * 2.0 * (1.0 - lin.min()) + 5e-4
+    for kk, s, l, e, t in zip(k[ok], sim, lin, eps_nl, tol):
+        print(f"  k {kk:.4f}  dP/P / f_nu: particles {(s - 1) / fn:+.2f}  linear {(l - 1) / fn:+.2f}"
+              f"  |ratio - 1| {abs(s / l - 1):.1e}  mode coupling {e:+.3f}  bar {t:.1e}",
               flush=True)
     large = k[ok] <= 0.1
-    # measured: 3e-3 at most (one bin near 0.05 h/Mpc, where mode coupling shifts the ratio
-    # in the same way with first- and second-order initial conditions)
-    assert np.abs(sim[large] / lin[large] - 1).max() <= 5e-3
+    assert np.all(np.abs(sim[large] / lin[large] - 1) <= tol[large])
     # the suppression is real (several f_nu) and deepens with k on linear scales
     assert np.all((lin[large] - 1) / fn < -2.0)
     # non-linear growth deepens it further on the smallest scales
