@@ -37,15 +37,16 @@ KERNEL_SOURCES = {
     "inv_x_green": "fft_kernels.hip", "fft_inv_y": "fft_kernels.hip",
     "fft_inv_z": "fft_kernels.hip", "nu_response": "response_kernels.hip",
     "rtable": "response_kernels.hip", "patch_reduce": "grid_kernels.hip",
-    "kick_drift": "advance_kernels.hip",
+    "kick_drift": "advance_kernels.hip", "patch_fwd_z": "fft_kernels.hip",
 }
 
 
 def stage_bytes(n_mesh, n_part, nbox, nbins, n_hist, n_partial, deposit_mode=0):
     """Algorithmic bytes per launch of every kernel: each input read once, each output
     written once (FP32 grids, complex64 modes, FP32 positions/accelerations). The patch
-    deposit (modes 6, 7) splits the deposit into reading the positions (cic_deposit) and
-    writing the density contrast (patch_reduce)."""
+    deposit (modes 6..9) splits the deposit into reading the positions (cic_deposit) and
+    writing the density contrast (patch_reduce), which the fused modes (8, 9) never write:
+    their patch_fwd_z goes from the deposit to the z-transformed modes."""
     m = n_mesh ** 3 * nbox
     mh = n_mesh * n_mesh * (n_mesh // 2 + 1) * nbox
     npt = n_part * nbox
@@ -55,6 +56,7 @@ def stage_bytes(n_mesh, n_part, nbox, nbins, n_hist, n_partial, deposit_mode=0):
         "cic_deposit": 12 * npt + (0 if patch else 4 * m),
         "patch_reduce": 4 * m,
         "fft_fwd_z": 4 * m + 8 * mh,
+        "patch_fwd_z": 8 * mh,
         "fft_fwd_y": 16 * mh,
         "fft_fwd_x_bin": 16 * mh + 8 * n_partial * nbins * nbox,
         "nu_response": 8 * nbox * nbins * (2 * n_hist + n_partial + 8),
@@ -89,7 +91,7 @@ def kernel_name(stage, tuning, n_mesh):
     if stage == "cic_deposit":
         m = tuning["deposit_mode"]
         if m >= 6:
-            return "deposit_patch_kernel<4096, %d, 512>" % (6144 if m == 6 else 9216)
+            return "deposit_patch_kernel<4096, %d, 512>" % (9216 if m in (7, 9) else 6144)
         return "deposit_tiled_kernel" + dep[m] if m else "deposit_kernel"
     if stage == "cic_interp":
         m = tuning["interp_mode"]
@@ -103,6 +105,8 @@ def kernel_name(stage, tuning, n_mesh):
     tiles = tuning.get("fft_tiles", {})
     fft = {"fft_fwd_y": ("fwd_y_kernel", "fwd_y"), "inv_x_green": ("inv_x_kernel", "inv_x"),
            "fft_inv_y": ("inv_y_kernel", "inv_y"), "fft_inv_z": ("inv_z_kernel", "inv_z")}
+    if stage == "patch_fwd_z":
+        return "patch_fwd_z_kernel<%d>" % n_mesh
     if stage == "fft_fwd_z":
         return "fwd_z_kernel<%d, %s, %d>" % (n_mesh, "true" if tuning["deposit_mode"] >= 6
                                              else "false", tiles.get("fwd_z", 0))

@@ -158,13 +158,19 @@ int pm_nu_binned_power_noalloc(const float* pos, int64_t n_particles, int n_mesh
                                double box_size, int n_kbins, double* p_cdm, void* stream);
 
 /* ---- diagnostics (copies of internal state, enqueued on the stream) ---------------- */
-/* (sync) How many chunk parts the patch deposit (deposit modes 6, 7) has sent through its
+/* (sync) How many chunk parts the patch deposit (deposit modes 6..9) has sent through its
  * atomic side grid since the last call (a chunk whose bounding box exceeds the LDS tile,
  * or its part in a coarse cell whose patch list was full); 0 when every chunk went
  * through its patch, and always 0 for the other deposit modes. */
 int pm_nu_side_grid_uses(pm_nu_ctx* ctx, int64_t* uses);
-/* Deposited mass rho (unit mass per particle) of one box into out (dev) [N][N][N]. */
+/* Deposited mass rho (unit mass per particle) of one box into out (dev) [N][N][N].
+ * Deposit modes 8 and 9 never write the density to HBM unless asked to by
+ * pm_nu_set_keep_density before the deposit; otherwise PM_NU_ESTATE. */
 int pm_nu_copy_density(pm_nu_ctx* ctx, int box, float* out);
+/* With deposit modes 8 and 9, also store delta at every deposit (67 MB more writes per
+ * 256^3 box) so that pm_nu_copy_density can read it (on != 0); the default is off. The
+ * other deposit modes always keep it. */
+int pm_nu_set_keep_density(pm_nu_ctx* ctx, int on);
 /* delta_k of one box (after pm_nu_deposit) into out (dev) as complex64 pairs in the
  * layout of numpy.fft.rfftn: [N][N][N/2+1][2]. */
 int pm_nu_copy_modes(pm_nu_ctx* ctx, int box, float* out);
@@ -230,8 +236,10 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
  * particles on 256 threads, 4096 on 512 threads, 8192 on 1024 threads, flushed with global
  * atomics), 6 (chunks of 4096 written to per-chunk patches and summed per 16^3 coarse
  * cell without atomics; a chunk whose box exceeds 6144 nodes, or its part in a coarse cell
- * already listing 32 patches, goes through atomics on a side grid) or
- * 7 (as 6 with room for boxes of 9216 nodes, at lower occupancy), interp_mode
+ * already listing 32 patches, goes through atomics on a side grid),
+ * 7 (as 6 with room for boxes of 9216 nodes, at lower occupancy), 8 and 9 (as 6 and 7 with
+ * the coarse-cell sums and the first forward FFT pass in one kernel, so that delta never
+ * goes to HBM; N >= 32), interp_mode
  * 0 (direct gather; interp_block = particles per workgroup, rounded down to 256, 512 or
  * 1024) or 1/2/3 (LDS-staged chunks). Blocks: multiples of 64 in 64..1024. Until this or
  * pm_nu_autotune is called: deposit_mode 6 for N >= 64 (4 below, where one coarse cell
@@ -248,7 +256,8 @@ int pm_nu_set_launch(pm_nu_ctx* ctx, int deposit_mode, int deposit_block, int in
 int pm_nu_set_fft_tiles(pm_nu_ctx* ctx, const int32_t* candidates);
 /* Current launch-shape choice as a short JSON text (host buffer of cap bytes, sync):
  * deposit and interpolation modes and blocks, the FFT tile candidates ("fft") and their
- * tiles ("fft_tiles"). */
+ * tiles ("fft_tiles"), and the threads per (bin, box) of the exact response
+ * ("response_threads": 64 when there are at least 1024 pairs, 256 otherwise). */
 int pm_nu_tuning(pm_nu_ctx* ctx, char* out, size_t cap);
 
 /* Switch the response between the exact integral (0), the surrogate (1) and the surrogate
@@ -318,21 +327,29 @@ int pm_nu_set_iterations(pm_nu_ctx* ctx, int iterations);
 int pm_nu_set_power(pm_nu_ctx* ctx, int box, const double* p_cdm);
 
 /* ---- learned surrogate for the history integral (not in the paper) -------------------- */
-/* A fully connected network 11 -> 128 -> 128 -> 128 -> 1, GELU after each hidden layer,
+/* A fully connected network 16 -> 128 -> 128 -> 128 -> 1, GELU after each hidden layer,
  * weights and layer inputs rounded to bfloat16 with FP32 accumulation (matrix cores in
- * training), FP32 master weights and Adam moments. Inputs per (box, bin):
- *   ln k_b, ln a_now, M_nu [eV], and P_M^{1/2}(a_{n-m}) / P_cdm^{1/2}(a_now) for the
- *   m = 1..8 latest stored nodes,
- * standardised with the stored mean/scale. Output (after un-standardising):
+ * training and in the step), FP32 master weights and Adam moments. Inputs per (box, bin),
+ * with a_0 < ... < a_{n-1} the stored nodes before a_now and A(u) the stored
+ * P_M^{1/2}(k_b) linear in u = ln a between them (as the history integral reads it):
+ *   ln k_b, ln a_now, M_nu [eV], ln a_now - ln a_{n-1},
+ *   P_nu^{1/2}(k_b, a_{n-1}) / P_cdm^{1/2}(k_b, a_now) (what the first iteration puts into
+ *   the current node), ln(a_now / a_0), ln(k_b (s(a_now) - s(a_{n-1})) T_nu0 / m) (the
+ *   free-streaming kernel's argument across the last interval, m = M_nu / n_species), and
+ *   A(ln a_{n-1} - L_m) / P_cdm^{1/2}(k_b, a_now) for the nine lags
+ *   L_m = 0, 0.05, 0.1, 0.2, 0.35, 0.55, 0.8, 1.2, 2.1 in ln a
+ * (lags in ln a, so the inputs mean the same for any spacing of the stored nodes; they
+ * exist once the history reaches 2.1 in ln a below its last node), standardised with the
+ * stored mean/scale. Output (after un-standardising):
  *   y = ln(R (1 + k_b/k_fs(a_now))^2),
  * i.e. R relative to the Appendix A approximation 1/(1 + k/k_fs)^2 with k_fs of
  * eq. (kfs-formal) for one species of mass M_nu/n_species. In the step (response_mode 1)
- * a bin whose inputs fall outside the training range (5% margin), or with fewer than 9
- * stored nodes, uses the exact integral instead; response_mode 2 runs both and keeps the
- * exact result. Blob layout (FP32): W1[11][128], b1[128], W2[128][128], b2, W3[128][128],
- * b3, W4[128], b4, then feature mean[11], scale[11], min[11], max[11], target mean, scale. */
-enum { PM_NU_SUR_IN = 11, PM_NU_SUR_HIDDEN = 128, PM_NU_SUR_PARAMS = 34689 };
-/* Number of FP32 values in a weight blob (34689 + 4*11 + 2). */
+ * a bin whose inputs do not exist or fall outside the training range (5% margin) uses the
+ * exact integral instead; response_mode 2 runs both and keeps the exact result. Blob layout
+ * (FP32): W1[16][128], b1[128], W2[128][128], b2, W3[128][128], b3, W4[128], b4, then
+ * feature mean[16], scale[16], min[16], max[16], target mean, scale. */
+enum { PM_NU_SUR_IN = 16, PM_NU_SUR_HIDDEN = 128, PM_NU_SUR_PARAMS = 35329 };
+/* Number of FP32 values in a weight blob (35329 + 4*16 + 2). */
 int64_t pm_nu_surrogate_blob_floats(void);
 /* Load weights and statistics (host) (sync). */
 int pm_nu_surrogate_load(pm_nu_ctx* ctx, const float* blob, int64_t n_floats);
@@ -340,24 +357,31 @@ int pm_nu_surrogate_load(pm_nu_ctx* ctx, const float* blob, int64_t n_floats);
 int pm_nu_surrogate_save(pm_nu_ctx* ctx, float* blob, int64_t n_floats);
 /* Training rows for the step's current state: runs the exact response at a_now (after
  * pm_nu_deposit or pm_nu_set_power for every box, history set) and writes the inputs
- * x (dev) [n_boxes*B][11] and targets y (dev) [n_boxes*B] in row box*B + b; rows that
- * cannot be used (empty bin, fewer than 9 stored nodes, no neutrinos) get y = NaN. */
+ * x (dev) [n_boxes*B][16] and targets y (dev) [n_boxes*B] in row box*B + b; rows that
+ * cannot be used (empty bin, inputs that do not exist, no neutrinos) get y = NaN. */
 int pm_nu_surrogate_dataset(pm_nu_ctx* ctx, double a_now, float* x, float* y);
 /* Initialise weights (seeded, uniform +-sqrt(6/(fan_in+fan_out))) and the feature and
- * target statistics from the n rows of x (dev) [n][11], y (dev) [n] (sync). */
+ * target statistics from the n rows of x (dev) [n][16], y (dev) [n] (sync). */
 int pm_nu_surrogate_init(pm_nu_ctx* ctx, const float* x, const float* y, int64_t n,
                          uint64_t seed);
 /* Adam (lr, betas 0.9/0.999, eps 1e-8) on the mean squared error of the standardised
- * target over x (dev) [n][11], y (dev) [n]: `epochs` passes in minibatches of `batch`
+ * target over x (dev) [n][16], y (dev) [n]: `epochs` passes in minibatches of `batch`
  * rows (a multiple of 32), reshuffled every epoch from `seed`; the learning rate decays
  * by half-cosine to lr/100 over the call. *loss_out (host) = mean loss of the last epoch
  * (sync). */
 int pm_nu_surrogate_train(pm_nu_ctx* ctx, const float* x, const float* y, int64_t n,
                           int epochs, int batch, float lr, uint64_t seed, float* loss_out);
-/* Network output y (dev) [n] (un-standardised) for raw inputs x (dev) [n][11]. */
+/* The same training split over several calls: epochs first_epoch .. first_epoch+epochs-1 of
+ * a run of total_epochs, the learning rate following the half-cosine of the whole run (the
+ * shuffles and Adam moments continue from the previous call). pm_nu_surrogate_train is the
+ * call with first_epoch = 0 and total_epochs = epochs. */
+int pm_nu_surrogate_train_part(pm_nu_ctx* ctx, const float* x, const float* y, int64_t n,
+                               int first_epoch, int epochs, int total_epochs, int batch,
+                               float lr, uint64_t seed, float* loss_out);
+/* Network output y (dev) [n] (un-standardised) for raw inputs x (dev) [n][16]. */
 int pm_nu_surrogate_predict(pm_nu_ctx* ctx, const float* x, float* y, int64_t n);
-/* Mean squared error of the standardised target over x (dev) [n][11], y (dev) [n] and its
- * FP32 gradient (dev) [34689] in blob order, with the current weights (sync). */
+/* Mean squared error of the standardised target over x (dev) [n][16], y (dev) [n] and its
+ * FP32 gradient (dev) [35329] in blob order, with the current weights (sync). */
 int pm_nu_surrogate_grad(pm_nu_ctx* ctx, const float* x, const float* y, int64_t n,
                          float* grad, float* loss_out);
 /* After a response in mode 2: exact and surrogate R of one box (host) [B] (sync);

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libpmnu.so")
 PM_NU_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "EHISTORY",
           -6: "ENODEV", -7: "ESURROGATE", -8: "ENONFINITE"}
-SUR_IN = 11
+SUR_IN = 16
 STAGE_CAP = 32
 
 
@@ -55,6 +55,7 @@ SIGNATURES = {
     "pm_nu_step": (_INT, [_P, _P, _P, ctypes.c_double]),
     "pm_nu_get_spectrum": (_INT, [_P, _INT, _D, _D, _D]),
     "pm_nu_copy_density": (_INT, [_P, _INT, _P]),
+    "pm_nu_set_keep_density": (_INT, [_P, _INT]),
     "pm_nu_side_grid_uses": (_INT, [_P, _I64]),
     "pm_nu_binned_power_noalloc": (_INT, [_P, ctypes.c_int64, _INT, ctypes.c_double, _INT, _P,
                                           _P]),
@@ -81,6 +82,8 @@ SIGNATURES = {
     "pm_nu_surrogate_init": (_INT, [_P, _P, _P, ctypes.c_int64, ctypes.c_uint64]),
     "pm_nu_surrogate_train": (_INT, [_P, _P, _P, ctypes.c_int64, _INT, _INT, ctypes.c_float,
                                      ctypes.c_uint64, _F]),
+    "pm_nu_surrogate_train_part": (_INT, [_P, _P, _P, ctypes.c_int64, _INT, _INT, _INT, _INT,
+                                          ctypes.c_float, ctypes.c_uint64, _F]),
     "pm_nu_surrogate_predict": (_INT, [_P, _P, _P, ctypes.c_int64]),
     "pm_nu_surrogate_grad": (_INT, [_P, _P, _P, ctypes.c_int64, _P, _F]),
     "pm_nu_surrogate_dataset": (_INT, [_P, ctypes.c_double, _P, _P]),
@@ -249,6 +252,10 @@ def pm_nu_copy_density(h, box, out):
     _check(load_library().pm_nu_copy_density(h, box, _dev(out)))
 
 
+def pm_nu_set_keep_density(h, on):
+    _check(load_library().pm_nu_set_keep_density(h, int(bool(on))))
+
+
 def pm_nu_copy_modes(h, box, out):
     _check(load_library().pm_nu_copy_modes(h, box, _dev(out)))
 
@@ -374,6 +381,15 @@ def pm_nu_surrogate_train(h, x, y, epochs, batch, lr, seed):
     _check(load_library().pm_nu_surrogate_train(h, _dev(x), _dev(y), x.shape[0], int(epochs),
                                                 int(batch), float(lr), int(seed),
                                                 ctypes.byref(loss)))
+    return float(loss.value)
+
+
+def pm_nu_surrogate_train_part(h, x, y, first_epoch, epochs, total_epochs, batch, lr, seed):
+    loss = ctypes.c_float(0.0)
+    _check(load_library().pm_nu_surrogate_train_part(h, _dev(x), _dev(y), x.shape[0],
+                                                     int(first_epoch), int(epochs),
+                                                     int(total_epochs), int(batch), float(lr),
+                                                     int(seed), ctypes.byref(loss)))
     return float(loss.value)
 
 

@@ -39,7 +39,7 @@ std::string tuning_json(const Ctx& c) {
   o << "], \"fft_tiles\": {";
   for (int p = 0; p < 6; ++p)
     o << (p ? ", " : "") << "\"" << kFftPass[p] << "\": " << fft_tile(c.N, p, c.tune.fft[p]);
-  o << "}}";
+  o << "}, \"response_threads\": " << response_threads(c.B, c.nbox) << "}";
   return o.str();
 }
 
@@ -126,7 +126,7 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
   c->timer.enabled = false;
   struct DepCand { int mode, block; };
   const DepCand dep[] = {{0, 256}, {0, 512}, {0, 1024}, {1, 256}, {2, 256}, {3, 256}, {4, 256},
-                         {5, 256}, {6, 256}, {7, 256}};
+                         {5, 256}, {6, 256}, {7, 256}, {8, 256}, {9, 256}};
   const DepCand itp[] = {{0, 256}, {0, 512}, {0, 1024}, {1, 256}, {2, 256}, {3, 256}};
   hipEvent_t e0, e1;
   PMNU_HIP(hipEventCreate(&e0));
@@ -245,7 +245,8 @@ int pm_nu_set_launch(pm_nu_ctx* ctx, int deposit_mode, int deposit_block, int in
   if (!c) return set_error(PM_NU_EINVAL, "ctx is NULL");
   drop_graph(*c);   // a captured step keeps its launch shapes
   auto block_ok = [](int b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
-  if (deposit_mode < 0 || deposit_mode > 7 || interp_mode < 0 || interp_mode > 3 ||
+  if (deposit_mode < 0 || deposit_mode > 9 || interp_mode < 0 || interp_mode > 3 ||
+      (deposit_mode >= 8 && c->N < 32) ||
       !block_ok(deposit_block) || !block_ok(interp_block))
     return set_error(PM_NU_EINVAL, "bad launch shape");
   c->tune.deposit_mode = deposit_mode;

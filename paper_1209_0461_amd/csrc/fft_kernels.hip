@@ -33,7 +33,7 @@
 #include <type_traits>
 
 #include "fft_lds.hpp"
-#include "pm_nu_internal.hpp"
+#include "patch_device.hpp"
 
 namespace pmnu {
 namespace {
@@ -147,15 +147,297 @@ __global__ __launch_bounds__(NT) void fwd_z_kernel(const void* __restrict__ in,
   }
 }
 
+// The patch deposit's second half and the first forward pass in one kernel (deposit modes
+// 8 and 9): the per-patch fixed-point sums are added up for a slab of the mesh and
+// transformed along z before delta ever reaches HBM. One workgroup per (x-plane, group of
+// CB = 16 y-rows, box): its slab is one x-plane of a column of N / CB coarse cells.
+//   1. Per coarse cell, the registered patch with the largest overlap of the slab (its
+//      "home") is found; every thread then loads the CB z-nodes of its (row, cell) runs from
+//      the home patch into registers.
+//   2. The other overlaps, cut into boxes (up to two periodic pieces per axis), are added
+//      into an LDS copy of the slab with 64-bit LDS atomics, GC cells at a time (the piece
+//      list of GC cells fits in LDS whatever the registry holds).
+//   3. Registers + LDS (+ the side grid when anything went there, which is then cleared) give
+//      the exact integer sum of each node, rounded once to delta = rho / rho_bar - 1 in FP32;
+//      the slab's 16 rows become 8 complex lines (rows 2p and 2p + 1 as real and imaginary
+//      parts) over the LDS the sums used, and the z transform and the split into the two real
+//      rows' half spectra follow as in fwd_z_kernel. The output is that of
+//      patch_reduce_kernel + fwd_z_kernel bit for bit.
+// With delta_out the slab's delta is also stored (only for reading the density back).
+// The registry counts and the side-grid count are reset by the next pass (fwd_y): the other
+// x-planes of a cell read them until this kernel ends. Workgroups of one cell column (the
+// 16 x-planes that read the same patches) run on one XCD, so its L2 serves their halos.
+template <int N>
+__global__ __launch_bounds__(NT) void patch_fwd_z_kernel(
+    const unsigned long long* __restrict__ patches, int pcap, const int* __restrict__ reg_count,
+    const int4* __restrict__ reg_list, unsigned long long* __restrict__ rho_fb,
+    const int* __restrict__ n_fb, float2* __restrict__ out, const float2* __restrict__ twg,
+    double scale, float* __restrict__ delta_out) {
+  constexpr int CB = 16, NC = N / CB, TY = CB, NL = TY / 2, ES = NL + 1, NK = Shape<N>::NK;
+  constexpr int RUNS = TY * NC;                    // (row, cell) runs of CB z-nodes
+  constexpr int RPT = (RUNS + NT - 1) / NT;        // runs per thread
+  constexpr int GC = N >= 512 ? 1 : 2;             // cells per piece list
+  constexpr int kPieces = GC * kPatchList * 8, kBatch = 8;
+  static_assert(NC >= 2 && RUNS % NT == 0 || RUNS < NT, "runs cover the threads evenly");
+  static_assert(N * ES * sizeof(float2) <= TY * N * sizeof(unsigned long long),
+                "the complex lines fit over the sums");
+  __shared__ unsigned long long s_acc[TY * N];     // [y][z]; later the complex lines
+  __shared__ float2 tw[N];
+  __shared__ int4 s_home[NC];                      // chunk < 0: no patch
+  __shared__ int p_off[kPieces + 1];
+  __shared__ int p_dim[kPieces];
+  __shared__ long long p_src[kPieces];
+  __shared__ int p_str[kPieces];
+  __shared__ int p_dst[kPieces];
+  __shared__ int s_total;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // block -> (box, cell column, x within the column, y group): consecutive dispatch ids go
+  // to the 8 XCDs in turn, so each XCD takes a contiguous run of virtual ids instead
+  const int nb = gridDim.x, per = nb / 8;
+  const int vid = static_cast<int>(blockIdx.x) < per * 8
+                      ? static_cast<int>(blockIdx.x % 8) * per + static_cast<int>(blockIdx.x / 8)
+                      : static_cast<int>(blockIdx.x);
+  const int xi = vid % CB, col = vid / CB;         // col = (cx, cy) of the cell column
+  const int cy = col % NC, cx = col / NC;
+  const int64_t box = blockIdx.y;
+  const int x = cx * CB + xi, y0 = cy * CB;
+  const int64_t cells = static_cast<int64_t>(NC) * NC * NC;
+  const int64_t cell0 = box * cells + (static_cast<int64_t>(cx) * NC + cy) * NC;  // cz = 0
+  load_twiddles<N, NT>(tw, twg);
+  for (int i = tid; i < TY * N; i += NT) s_acc[i] = 0ull;
+  // 1. homes: a half-wave per cell, its lanes over the cell's list
+  for (int c0 = 2 * wave; c0 < NC; c0 += 2 * (NT / 64)) {
+    const int c = c0 + (lane >> 5), e = lane & 31;
+    int key = -1;
+    int4 listed = make_int4(-1, 0, 0, 0);
+    if (c < NC) {
+      const int cnt = min(reg_count[cell0 + c], kPatchList);
+      if (e < cnt) {
+        listed = reg_list[(cell0 + c) * kPatchList + e];
+        const Pieces px = overlap(listed.y & 1023, listed.z & 1023, x, 1, N);
+        const Pieces py = overlap((listed.y >> 10) & 1023, (listed.z >> 10) & 1023, y0, CB, N);
+        const Pieces pz = overlap(listed.y >> 20, listed.z >> 20, c * CB, CB, N);
+        int lx = 0, ly = 0, lz = 0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          lx += q < px.cnt ? px.len[q] : 0;
+          ly += q < py.cnt ? py.len[q] : 0;
+          lz += q < pz.cnt ? pz.len[q] : 0;
+        }
+        const int vol = lx * ly * lz;
+        key = vol > 0 ? (vol << 6) | (63 - lane) : -1;
+      }
+    }
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) key = max(key, __shfl_xor(key, off, 64));
+    if (c < NC) {
+      if (e == 0) s_home[c] = make_int4(-1, 0, 0, 0);
+      if (key >= 0 && lane == 63 - (key & 63)) s_home[c] = listed;
+    }
+  }
+  __syncthreads();
+  // the home runs' loads go out first: run r = cell * TY + row (rows of a cell on
+  // neighbouring lanes read neighbouring patch rows)
+  unsigned long long hv[RPT][CB];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = tid + q * NT, c = r / TY, row = r % TY;
+#pragma unroll
+    for (int z = 0; z < CB; ++z) hv[q][z] = 0ull;
+    const int4 hl = r < RUNS ? s_home[c] : make_int4(-1, 0, 0, 0);
+    if (hl.x < 0) continue;
+    const int ex = hl.z & 1023, ey = (hl.z >> 10) & 1023, ez = hl.z >> 20;
+    const Pieces px = overlap(hl.y & 1023, ex, x, 1, N);
+    const Pieces py = overlap((hl.y >> 10) & 1023, ey, y0, CB, N);
+    const Pieces pz = overlap(hl.y >> 20, ez, c * CB, CB, N);
+    int lx = -1, ly = -1;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (k < px.cnt && px.cl[k] == 0) lx = px.pl[k];
+      if (k < py.cnt && row >= py.cl[k] && row < py.cl[k] + py.len[k])
+        ly = py.pl[k] + row - py.cl[k];
+    }
+    if (lx < 0 || ly < 0) continue;
+    const unsigned long long* src =
+        patches + static_cast<int64_t>(hl.x) * pcap + (static_cast<int64_t>(lx) * ey + ly) * ez;
+#pragma unroll
+    for (int z = 0; z < CB; ++z) {
+      int lz = -1;
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        if (k < pz.cnt && z >= pz.cl[k] && z < pz.cl[k] + pz.len[k]) lz = pz.pl[k] + z - pz.cl[k];
+      if (lz >= 0) hv[q][z] = src[lz];
+    }
+  }
+  // 2. the other overlaps, GC cells at a time
+  for (int g0 = 0; g0 < NC; g0 += GC) {
+    if (wave == 0) {
+      // lanes 32 h .. 32 h + 31: the list of cell g0 + h (h < GC)
+      const int h = lane >> 5, e = lane & 31, c = g0 + h;
+      const bool cell_on = h < GC && c < NC;
+      const int cnt = cell_on ? min(reg_count[cell0 + c], kPatchList) : 0;
+      const int4 listed = e < cnt ? reg_list[(cell0 + c) * kPatchList + e] : make_int4(-1, 0, 0, 0);
+      const int4 home = cell_on ? s_home[c] : make_int4(-1, 0, 0, 0);
+      const bool other = e < cnt && !(listed.x == home.x && listed.y == home.y);
+      Pieces px, py, pz;
+      px.cnt = py.cnt = pz.cnt = 0;
+      int vol = 0;
+      const int ex = listed.z & 1023, ey = (listed.z >> 10) & 1023, ez = listed.z >> 20;
+      if (other) {
+        px = overlap(listed.y & 1023, ex, x, 1, N);
+        py = overlap((listed.y >> 10) & 1023, ey, y0, CB, N);
+        pz = overlap(listed.y >> 20, ez, c * CB, CB, N);
+        int lx = 0, ly = 0, lz = 0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          lx += q < px.cnt ? px.len[q] : 0;
+          ly += q < py.cnt ? py.len[q] : 0;
+          lz += q < pz.cnt ? pz.len[q] : 0;
+        }
+        vol = lx * ly * lz;
+      }
+      const bool has = vol > 0;
+      const int np_mine = has ? px.cnt * py.cnt * pz.cnt : 0;
+      int inc_p = np_mine, inc_v = has ? vol : 0;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int tp = __shfl_up(inc_p, off, 64), tv = __shfl_up(inc_v, off, 64);
+        if (lane >= off) {
+          inc_p += tp;
+          inc_v += tv;
+        }
+      }
+      const int n_pieces = __shfl(inc_p, 63, 64);
+      if (lane == 63) s_total = inc_v;
+      int slot = inc_p - np_mine, item = inc_v - (has ? vol : 0);
+      if (has) {
+        const long long src0 = static_cast<long long>(listed.x) * pcap;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+              if (a >= px.cnt || b >= py.cnt || cc >= pz.cnt) continue;
+              const int Lx = px.len[a], Ly = py.len[b], Lz = pz.len[cc];
+              p_off[slot] = item;
+              p_dim[slot] = Lz | (Ly << 8);
+              p_src[slot] = src0 + (static_cast<long long>(px.pl[a]) * ey + py.pl[b]) * ez + pz.pl[cc];
+              p_str[slot] = ez | ((ey * ez) << 10);
+              // LDS node (y, z) of the piece's first node; x is the slab's plane (Lx = 1)
+              p_dst[slot] = py.cl[b] * N + c * CB + pz.cl[cc];
+              item += Lx * Ly * Lz;
+              ++slot;
+            }
+      }
+      for (int i = n_pieces + lane; i <= kPieces; i += 64) p_off[i] = 0x7fffffff;
+    }
+    __syncthreads();
+    const int total = s_total;
+    for (int base = 0; base < total; base += kBatch * NT) {
+      unsigned long long v[kBatch];
+      int li[kBatch];
+#pragma unroll
+      for (int r = 0; r < kBatch; ++r) {
+        const int i = base + r * NT + tid;
+        li[r] = -1;
+        v[r] = 0ull;
+        if (i < total) {
+          int e = 0;                              // the piece: last offset <= i
+#pragma unroll
+          for (int step = kPieces / 2; step > 0; step >>= 1)
+            if (p_off[e + step] <= i) e += step;
+          const int rem = i - p_off[e];
+          const int dim = p_dim[e], str = p_str[e];
+          const int Lz = dim & 255;
+          // exact: rem < 256 and Lz <= 16 (x is one plane, so rem = y Lz + z)
+          const int y = static_cast<int>((rem + 0.5f) * (1.0f / Lz));
+          const int z = rem - y * Lz;
+          v[r] = patches[p_src[e] + y * (str & 1023) + z];
+          li[r] = p_dst[e] + y * N + z;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kBatch; ++r)
+        if (li[r] >= 0) atomicAdd(&s_acc[li[r]], v[r]);
+    }
+    __syncthreads();
+  }
+  // 3. exact sums -> delta, then the z transform over the same LDS
+  const bool fold = *n_fb > 0;
+  const int64_t m = static_cast<int64_t>(N) * N * N;
+  float dv[RPT][CB];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = tid + q * NT, c = r / TY, row = r % TY;
+    if (r >= RUNS) continue;
+#pragma unroll
+    for (int z = 0; z < CB; ++z) {
+      unsigned long long val = hv[q][z] + s_acc[row * N + c * CB + z];
+      if (fold) {
+        const int64_t node = box * m + (static_cast<int64_t>(x) * N + y0 + row) * N + c * CB + z;
+        val += rho_fb[node];
+        rho_fb[node] = 0ull;
+      }
+      dv[q][z] = static_cast<float>(static_cast<double>(val) * scale - 1.0);
+    }
+    if (delta_out) {                               // kept for reading the density back
+      float4* dst = reinterpret_cast<float4*>(
+          delta_out + box * m + (static_cast<int64_t>(x) * N + y0 + row) * N + c * CB);
+#pragma unroll
+      for (int z = 0; z < CB; z += 4)
+        dst[z / 4] = make_float4(dv[q][z], dv[q][z + 1], dv[q][z + 2], dv[q][z + 3]);
+    }
+  }
+  __syncthreads();
+  float2* lds = reinterpret_cast<float2*>(s_acc);
+  float* ldsf = reinterpret_cast<float*>(s_acc);
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = tid + q * NT, c = r / TY, row = r % TY;
+    if (r >= RUNS) continue;
+#pragma unroll
+    for (int z = 0; z < CB; ++z) ldsf[((c * CB + z) * ES + (row >> 1)) * 2 + (row & 1)] = dv[q][z];
+  }
+  __syncthreads();
+  fft_lines<N, NL, NT, -1>(lds, tw);
+  for (int t = tid; t < NK * TY; t += NT) {
+    const int row = t % TY, k = t / TY, p = row >> 1;
+    const float2 zk = lds[k * ES + p];
+    const float2 zn = cconj(lds[((N - k) & (N - 1)) * ES + p]);
+    float2 rr;
+    if ((row & 1) == 0) {
+      rr = cscale(cadd(zk, zn), 0.5f);
+    } else {
+      const float2 d = csub(zk, zn);
+      rr = make_float2(0.5f * d.y, -0.5f * d.x);
+    }
+    out[((box * N + x) * NK + k) * N + y0 + row] = rr;
+  }
+}
+
 // in: rows of [box][x][kz] (flattened, NL consecutive rows per workgroup);
 // out: the same rows at [box][kz][x].
+// After the fused patch pass (patch_fwd_z_kernel) it also does the patch registry's
+// end-of-step work that fwd_z does otherwise: reset (n_fb: this step's side-grid count
+// into the running total) and clear (the registry counts), when given.
 template <int N, int NL>
 __global__ __launch_bounds__(NT) void fwd_y_kernel(const float2* __restrict__ in,
                                                    float2* __restrict__ out,
-                                                   const float2* __restrict__ twg) {
+                                                   const float2* __restrict__ twg,
+                                                   int* __restrict__ reset,
+                                                   int* __restrict__ clear, int n_clear) {
   constexpr int ES = NL + 1, NK = Shape<N>::NK;
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
+  if (reset && threadIdx.x == 0 && blockIdx.x == 0) {
+    reset[1] += reset[0];
+    reset[0] = 0;
+  }
+  if (clear) {
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+    if (gid < n_clear) clear[gid] = 0;
+  }
   load_twiddles<N, NT>(tw, twg);
   const size_t r0 = static_cast<size_t>(blockIdx.x) * NL;
   const float4* src = reinterpret_cast<const float4*>(in + r0 * N);
@@ -571,11 +853,14 @@ template <int N> struct FwdZ {
 };
 template <int N> struct FwdY {
   static hipError_t run(const float2* in, float2* out, const float2* tw, int nbox,
-                        hipStream_t s, int v) {
+                        hipStream_t s, int v, int* reset, int* clear, int n_clear) {
     auto go = [&](auto nl) -> hipError_t {
       constexpr int NL = decltype(nl)::value;
       dim3 grid(static_cast<unsigned>(static_cast<int64_t>(nbox) * Shape<N>::NK * N / NL));
-      hipLaunchKernelGGL((fwd_y_kernel<N, NL>), grid, dim3(NT), 0, s, in, out, tw);
+      if (static_cast<int64_t>(grid.x) * NT < n_clear)
+        return hipErrorInvalidValue;               // every count needs a thread to clear it
+      hipLaunchKernelGGL((fwd_y_kernel<N, NL>), grid, dim3(NT), 0, s, in, out, tw, reset, clear,
+                         n_clear);
       return hipGetLastError();
     };
     return with_tile<PMNU_TILES(FY)>(go, v);
@@ -678,8 +963,30 @@ hipError_t launch_fwd_z(int n, const unsigned long long* rho, const float* delta
   return dispatch_n<FwdZ>(n, rho, delta, reset, clear, n_clear, out, tw, scale, nbox, s, v);
 }
 hipError_t launch_fwd_y(int n, const float2* in, float2* out, const float2* tw, int nbox,
-                        hipStream_t s, int v) {
-  return dispatch_n<FwdY>(n, in, out, tw, nbox, s, v);
+                        hipStream_t s, int v, int* reset, int* clear, int n_clear) {
+  return dispatch_n<FwdY>(n, in, out, tw, nbox, s, v, reset, clear, n_clear);
+}
+template <int N> struct PatchFwdZ {
+  static hipError_t run(const unsigned long long* patches, int pcap, const int* reg_count,
+                        const int4* reg_list, unsigned long long* rho_fb, const int* n_fb,
+                        float2* out, const float2* tw, double scale, int nbox, hipStream_t s,
+                        float* delta_out) {
+    if constexpr (N < 32) {
+      return hipErrorInvalidValue;                 // the fused pass needs N / 16 >= 2 cells
+    } else {
+      const dim3 grid(static_cast<unsigned>(N / 16 * N), nbox);
+      hipLaunchKernelGGL(patch_fwd_z_kernel<N>, grid, dim3(NT), 0, s, patches, pcap, reg_count,
+                         reg_list, rho_fb, n_fb, out, tw, scale, delta_out);
+      return hipGetLastError();
+    }
+  }
+};
+hipError_t launch_patch_fwd_z(int n, const unsigned long long* patches, const int* reg_count,
+                              const int4* reg_list, unsigned long long* rho_fb, const int* n_fb,
+                              float2* out, const float2* tw, double scale, int nbox,
+                              hipStream_t s, float* delta_out) {
+  return dispatch_n<PatchFwdZ>(n, patches, kPatchCap, reg_count, reg_list, rho_fb, n_fb, out, tw,
+                               scale, nbox, s, delta_out);
 }
 hipError_t launch_fwd_x_bin(int n, float2* data, const float2* tw, const uint16_t* bin_of_n2,
                             double* partial, int nbins, int nbox, hipStream_t s, int v) {

@@ -21,7 +21,7 @@
 // (particles in arbitrary order) take the per-particle global-atomic path instead, so
 // the result does not depend on the order; the speed does. Particles kept along a
 // space-filling curve (as tree codes keep them) give compact chunks.
-#include "pm_nu_internal.hpp"
+#include "patch_device.hpp"
 
 namespace pmnu {
 namespace {
@@ -336,8 +336,6 @@ __global__ __launch_bounds__(NT) void deposit_tiled_kernel(const float* __restri
 // (a box too large: the whole chunk; a coarse cell whose list is full: the box's part in
 // that cell) are added with global atomics to a side grid kept at zero, which D2 folds in
 // (and clears) only when something was added to it.
-constexpr int kPatchList = 32;      // patches per coarse cell
-constexpr int kPatchRegMax = 27;    // coarse cells per patch
 
 __device__ __forceinline__ int ceil_div_pow2(int a, int lg) { return (a + (1 << lg) - 1) >> lg; }
 
@@ -483,31 +481,6 @@ __global__ __launch_bounds__(NT) void deposit_patch_kernel(
     }
   }
   if (tid == 0) atomicAdd(n_fb, 1);
-}
-
-// Up to two pieces of the overlap of a periodic patch interval [p, p + e) with the cell
-// interval [cs, cs + cb) on an axis of length n (e <= n): patch-local start, cell-local
-// start and length of each.
-struct Pieces {
-  int cnt;
-  int pl[2], cl[2], len[2];
-};
-__device__ __forceinline__ Pieces overlap(int p, int e, int cs, int cb, int n) {
-  Pieces r;
-  const int d2 = (p - cs + n) & (n - 1);        // cell-local index of the patch start
-  const int w = n - d2;                         // patch-local index where it re-enters
-  const bool first = d2 < cb;                   // [p, ...) starts inside the cell
-  const bool second = d2 != 0 && w < e;         // the patch wraps back into the cell
-  const int len_a = min(e, cb - d2), len_b = min(e - w, cb);
-  // fixed slots (no indexed writes, which would go to scratch)
-  r.cnt = static_cast<int>(first) + static_cast<int>(second);
-  r.pl[0] = first ? 0 : w;
-  r.cl[0] = first ? d2 : 0;
-  r.len[0] = first ? len_a : len_b;
-  r.pl[1] = w;
-  r.cl[1] = 0;
-  r.len[1] = len_b;
-  return r;
 }
 
 // D2: one workgroup of 256 threads per (slab of XD x-planes of a coarse cell, box), CB =

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <numeric>
 #include <cstdarg>
 #include <cstdint>
@@ -22,7 +23,7 @@ namespace pmnu {
 const char* const kStageNames[ST_COUNT] = {
     "zero_mesh", "cic_deposit", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x_bin", "nu_response",
     "rtable", "inv_x_green", "fft_inv_y", "fft_inv_z", "cic_interp", "surrogate",
-    "patch_reduce", "kick_drift"};
+    "patch_reduce", "kick_drift", "patch_fwd_z"};
 
 namespace {
 thread_local std::string g_err = "no error";
@@ -231,6 +232,32 @@ int prepare_time_grid(Ctx& c, double a_now) {
     rb.a_now = a_now;
     rb.nq = nq;
     rb.n_cur = n;
+    // the surrogate's history samples at fixed lags in ln a below the last stored node
+    rb.sur_hist = 0;
+    rb.sur_gap = n > 0 ? std::log(a_now) - std::log(nd[n - 1]) : 0.0;
+    rb.sur_ds_last = n > 0 ? dsb[(n - 1) * Q] : 0.0;
+    rb.sur_lna = std::log(a_now);
+    rb.sur_lna0 = std::log(a_now / nd[0]);
+    rb.sur_lnx0 = rb.sur_ds_last > 0.0 && rb.t_over_m > 0.0
+                      ? std::log(rb.sur_ds_last * rb.t_over_m)
+                      : -std::numeric_limits<double>::infinity();
+    if (n >= 2 && std::log(nd[n - 1]) - kSurLag[kSurLags - 1] >= std::log(nd[0])) {
+      rb.sur_hist = 1;
+      const double u_last = std::log(nd[n - 1]);
+      int j = n - 1;
+      for (int m = 0; m < kSurLags; ++m) {
+        const double u = u_last - kSurLag[m];
+        while (j > 0 && std::log(nd[j]) > u) --j;
+        if (j >= n - 1) {
+          rb.sur_j[m] = n - 1;
+          rb.sur_t[m] = 0.0;
+        } else {
+          const double u0 = std::log(nd[j]), u1 = std::log(nd[j + 1]);
+          rb.sur_j[m] = j;
+          rb.sur_t[m] = (u - u0) / (u1 - u0);
+        }
+      }
+    }
   }
   const size_t bytes = c.nbox * qcap * sizeof(double);
   PMNU_HIP(hipMemcpyAsync(c.tg_ds, ds_all, bytes, hipMemcpyHostToDevice, c.stream));
@@ -263,18 +290,28 @@ int do_deposit(Ctx& c, const float* pos) {
   const int64_t cells = c.M * c.nbox;
   const double inv_cell = c.N / c.cfg.box_size;
   const double scale = static_cast<double>(c.M) / static_cast<double>(c.Np) / kFixScale;
+  const bool fused = c.tune.deposit_mode >= 8;
+  const int n_cells = static_cast<int>(c.nbox * patch_coarse_cells(c.N));
   if (c.tune.deposit_mode >= 6) {
+    const bool big = c.tune.deposit_mode == 7 || c.tune.deposit_mode == 9;
     TIMED(c, ST_DEPOSIT,
           launch_deposit_patch(pos, c.patches, c.reg_count, c.reg_list, c.rho_fb, c.n_fb,
-                               c.Np, c.nbox, c.N, inv_cell, c.d_flags,
-                               c.tune.deposit_mode == 7, c.stream));
-    TIMED(c, ST_PATCH_REDUCE,
-          launch_patch_reduce(c.patches, c.reg_count, c.reg_list, c.rho_fb, c.n_fb, c.delta,
-                              c.nbox, c.N, scale, c.stream));
-    TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, nullptr, c.delta, c.n_fb, c.reg_count,
-                                    static_cast<int>(c.nbox * patch_coarse_cells(c.N)), c.ck[1],
-                                    c.tw, scale, c.nbox, c.stream, c.tune.fft[0]));
+                               c.Np, c.nbox, c.N, inv_cell, c.d_flags, big, c.stream));
+    if (fused) {
+      // the patch sums and the z pass in one kernel; fwd_y resets the registry
+      TIMED(c, ST_PATCH_FWD_Z,
+            launch_patch_fwd_z(c.N, c.patches, c.reg_count, c.reg_list, c.rho_fb, c.n_fb,
+                               c.ck[1], c.tw, scale, c.nbox, c.stream,
+                               c.keep_density ? c.delta : nullptr));
+    } else {
+      TIMED(c, ST_PATCH_REDUCE,
+            launch_patch_reduce(c.patches, c.reg_count, c.reg_list, c.rho_fb, c.n_fb, c.delta,
+                                c.nbox, c.N, scale, c.stream));
+      TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, nullptr, c.delta, c.n_fb, c.reg_count, n_cells,
+                                      c.ck[1], c.tw, scale, c.nbox, c.stream, c.tune.fft[0]));
+    }
     c.density_is_delta = true;
+    c.density_kept = !fused || c.keep_density;
   } else {
     TIMED(c, ST_ZERO, launch_fill_zero(c.rho, cells * 8, c.stream));
     TIMED(c, ST_DEPOSIT, launch_deposit(pos, c.rho, c.Np, c.nbox, c.N, inv_cell, c.d_flags,
@@ -282,9 +319,11 @@ int do_deposit(Ctx& c, const float* pos) {
     TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, c.rho, nullptr, nullptr, nullptr, 0, c.ck[1], c.tw,
                                     scale, c.nbox, c.stream, c.tune.fft[0]));
     c.density_is_delta = false;
+    c.density_kept = true;
   }
   TIMED(c, ST_FFT_Y, launch_fwd_y(c.N, c.ck[1], c.ck[0], c.tw, c.nbox, c.stream,
-                                  c.tune.fft[1]));
+                                  c.tune.fft[1], fused ? c.n_fb : nullptr,
+                                  fused ? c.reg_count : nullptr, fused ? n_cells : 0));
   // the number of partial bin sums follows the tile of this pass
   c.n_partial = fwd_x_partials(c.N, c.tune.fft[2]);
   TIMED(c, ST_FFT_X_BIN, launch_fwd_x_bin(c.N, c.ck[0], c.tw, c.bin_of_n2, c.bin_partial,
@@ -314,7 +353,7 @@ int do_response_mode(Ctx& c, double a_now, int mode) {
           launch_response(c.d_resp, c.bin_partial, c.n_partial, c.d_counts, c.d_kmean,
                           c.hist_pm, c.hist_pnu, c.ic_pnu, c.ic_theta, c.tg_ds, c.tg_w, c.B,
                           c.Jcap, c.qcap, c.Q, c.cfg.iterations, norm, c.nbox, c.pcdm, c.pnu,
-                          c.ratio, c.stream));
+                          c.ratio, c.stream, response_threads(c.B, c.nbox)));
   } else {
     int rc = surrogate_launch(c, mode, norm);
     if (rc) return rc;
@@ -929,6 +968,9 @@ int pm_nu_side_grid_uses(pm_nu_ctx* ctx, int64_t* uses) {
 int pm_nu_copy_density(pm_nu_ctx* ctx, int box, float* out) {
   GET_CTX(ctx);
   if (box < 0 || box >= c->nbox || !out) return set_error(PM_NU_EINVAL, "bad box/out");
+  if (c->tune.deposit_mode >= 8 && !c->density_kept)
+    return set_error(PM_NU_ESTATE, "deposit modes 8 and 9 store the density only after "
+                                   "pm_nu_set_keep_density(ctx, 1)");
   hipError_t e =
       c->density_is_delta
           ? launch_delta_to_density(c->delta + box * c->M, out, c->M,
@@ -936,6 +978,13 @@ int pm_nu_copy_density(pm_nu_ctx* ctx, int box, float* out) {
                                     c->stream)
           : launch_fixed_to_float(c->rho + box * c->M, out, c->M, c->stream);
   if (e != hipSuccess) return set_error(PM_NU_EHIP, "copy_density: %s", hipGetErrorString(e));
+  return PM_NU_OK;
+}
+
+int pm_nu_set_keep_density(pm_nu_ctx* ctx, int on) {
+  GET_CTX(ctx);
+  drop_graph(*c);   // a captured step keeps its kernel arguments
+  c->keep_density = on != 0;
   return PM_NU_OK;
 }
 

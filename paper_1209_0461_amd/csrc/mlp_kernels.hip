@@ -1,19 +1,26 @@
 // Surrogate network for the neutrino history integral (gfx950): an MLP
-// 11 -> 128 -> 128 -> 128 -> 1 with GELU hidden activations. Weights and every layer's
-// input are rounded to bfloat16 (round to nearest even) and multiplied with FP32
-// accumulation; biases, pre-activations, GELU, the loss and all gradients are FP32.
+// 16 -> 128 -> 128 -> 128 -> 1 with GELU hidden activations. Weights are rounded to
+// bfloat16 (round to nearest even); every layer's input is carried as two bfloat16 parts,
+// hi = bf16(v) and lo = bf16(v - hi) (a 16-bit significand), and multiplied by the weights as
+// two bf16 products with FP32 accumulation; biases, pre-activations, GELU, the loss and all
+// gradients are FP32. (A layer input rounded to one bfloat16 alone limits the network to
+// about 2e-3 in ln R; the second part removes that floor.)
 //
 // Training runs on the matrix cores: mlp_train_kernel takes 32 samples per workgroup
-// through the forward pass (16x16x16 bf16 MFMA tiles, activations kept in LDS) and the
-// backward pass (weight gradients H^T dZ and input gradients dZ W^T, also on MFMA, with
-// dZ rounded to bfloat16 as MFMA operand), and adds its share of the gradient to an FP32
-// buffer with global atomics. adam_kernel applies one Adam step to the FP32 masters.
+// through the forward pass (bf16 MFMA tiles, 16x16x32 where K is a multiple of 32 and
+// 16x16x16 for the 16 inputs, activations kept in LDS) and the backward pass (weight
+// gradients H^T dZ and input gradients dZ W^T, also on MFMA, with dZ rounded to bfloat16
+// as MFMA operand), and adds its share of the gradient to an FP32 buffer with global
+// atomics. adam_kernel applies one Adam step to the FP32 masters.
 //
-// Inside the step the network sees one row per k-bin: surrogate_response_kernel, one
-// workgroup per (bin, box), forms P_cdm, takes the bin's row through the same MFMA forward
-// pass with the weights staged at once from a bfloat16 image packed once per weight
-// change, and falls back to the exact integral (response_device.hpp) in the same
-// workgroup when the inputs are outside the training range (or when checking).
+// Inside the step one bin is one row, so a matrix-core tile would be 1/16 full:
+// surrogate_response_kernel, one workgroup per (bin, box) like the exact response, forms
+// P_cdm and the bin's inputs and takes the row through the network as FP32 dot products
+// with the bfloat16 weights (packed once per weight change) held in registers, fetched at
+// the start so that their latency hides behind the P_cdm reduction; it runs the exact
+// integral (response_device.hpp) for a bin whose inputs fall outside the training range
+// (or for every bin when checking). Its activations are FP32 where training carries them
+// as hi + lo bfloat16 pairs (16-bit significand): the two agree to about 1e-5 in ln R.
 #include "response_device.hpp"
 #include "surrogate_layout.hpp"
 
@@ -34,6 +41,11 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(static_cast<unsigned>(h) << 16); }
 __device__ __forceinline__ float bfr(float f) { return bf2f(f2bf(f)); }
+// v as hi + lo, both bfloat16
+__device__ __forceinline__ void split_bf(float v, unsigned short& hi, unsigned short& lo) {
+  hi = f2bf(v);
+  lo = f2bf(v - bf2f(hi));
+}
 
 __device__ __forceinline__ float gelu(float x) {
   return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
@@ -42,14 +54,34 @@ __device__ __forceinline__ float gelu_grad(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
 }
 
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
 // acc += A(16 x K) * B(K x 16) for one 16x16 tile, K a multiple of 16, operands bf16 in
 // LDS with element (m, k) of A at A[m*sam + k*sak] and (k, n) of B at B[k*sbk + n*sbn].
-// Lane l supplies row l%16 of A / column l%16 of B for k = 4*(l/16) .. +3 of every
-// 16-wide K step and receives rows 4*(l/16) .. +3 of column l%16 of the result.
+// With K a multiple of 32 it takes gfx950's 16x16x32 steps (lane l supplies row l%16 of A /
+// column l%16 of B for k = 8*(l/16) .. +7 of every 32-wide step), otherwise 16x16x16 steps
+// (k = 4*(l/16) .. +3 of every 16-wide step); either way lane l receives rows
+// 4*(l/16) .. +3 of column l%16 of the result.
 __device__ __forceinline__ f32x4 mma16(const unsigned short* A, int sam, int sak,
                                        const unsigned short* B, int sbk, int sbn, int K,
                                        f32x4 acc) {
-  const int l = threadIdx.x & 63, r = l & 15, kb = (l >> 4) << 2;
+  const int l = threadIdx.x & 63, r = l & 15;
+  if (K % 32 == 0) {
+    const int kb = (l >> 4) << 3;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      s16x8 a, b;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        a[q] = static_cast<short>(A[r * sam + (k0 + kb + q) * sak]);
+        b[q] = static_cast<short>(B[(k0 + kb + q) * sbk + r * sbn]);
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                     __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+    }
+    return acc;
+  }
+  const int kb = (l >> 4) << 2;
   for (int k0 = 0; k0 < K; k0 += 16) {
     bf16x4 a, b;
 #pragma unroll
@@ -63,8 +95,8 @@ __device__ __forceinline__ f32x4 mma16(const unsigned short* A, int sam, int sak
 }
 
 struct Smem {
-  unsigned short x[TB * 16];          // standardised inputs, K padded to 16 (bf16)
-  unsigned short h[3][TB * 128];      // inputs of layers 2, 3, 4: H1, H2, H3 (bf16)
+  unsigned short x[2][TB * 16];       // standardised inputs, K padded to 16 (bf16 hi, lo)
+  unsigned short h[3][2][TB * 128];   // inputs of layers 2, 3, 4: H1, H2, H3 (bf16 hi, lo)
   float z[3][TB * 128];               // pre-activations Z1..Z3, later dZ (FP32)
   alignas(16) unsigned short w[128 * 128];   // one staged weight matrix as [out][in] (bf16)
   unsigned short d[TB * 128];         // dZ of the current layer (bf16)
@@ -92,21 +124,25 @@ __device__ __forceinline__ void stage_weights(Smem& S, const float* W, int nin, 
   }
 }
 
-// Z = H W + b for the 32 x 128 tile; writes Z (FP32) and GELU(Z) (bf16)
-__device__ __forceinline__ void dense_gelu(Smem& S, const unsigned short* Hin, int kin,
-                                           const float* bias, float* Z, unsigned short* Hout) {
+// Z = H W + b for the 32 x 128 tile (H as its hi and lo parts); writes Z (FP32) and
+// GELU(Z) as hi and lo parts
+__device__ __forceinline__ void dense_gelu(Smem& S, const unsigned short* Hhi,
+                                           const unsigned short* Hlo, int kin,
+                                           const float* bias, float* Z, unsigned short* Ohi,
+                                           unsigned short* Olo) {
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
   for (int t = wv; t < 16; t += NT / 64) {
     const int mt = t >> 3, nt = t & 7;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    acc = mma16(Hin + mt * 16 * kin, kin, 1, S.w + nt * 16 * kin, 1, kin, kin, acc);
+    acc = mma16(Hhi + mt * 16 * kin, kin, 1, S.w + nt * 16 * kin, 1, kin, kin, acc);
+    acc = mma16(Hlo + mt * 16 * kin, kin, 1, S.w + nt * 16 * kin, 1, kin, kin, acc);
     const int col = nt * 16 + (l & 15);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int row = mt * 16 + ((l >> 4) << 2) + q;
       const float z = acc[q] + bias[col];
       Z[row * 128 + col] = z;
-      Hout[row * 128 + col] = f2bf(gelu(z));
+      split_bf(gelu(z), Ohi[row * 128 + col], Olo[row * 128 + col]);
     }
   }
 }
@@ -119,7 +155,7 @@ __device__ __forceinline__ void output_layer(Smem& S, const float* P) {
     float acc = 0.f;
 #pragma unroll
     for (int j = part * 16; j < part * 16 + 16; ++j)
-      acc += bf2f(S.h[2][s * 128 + j]) * bfr(P[kOffW4 + j]);
+      acc += (bf2f(S.h[2][0][s * 128 + j]) + bf2f(S.h[2][1][s * 128 + j])) * bfr(P[kOffW4 + j]);
     acc += __shfl_xor(acc, 1, 64);
     acc += __shfl_xor(acc, 2, 64);
     acc += __shfl_xor(acc, 4, 64);
@@ -140,15 +176,15 @@ constexpr int kPackSize = kPackW3 + 128 * 128;
 __device__ __forceinline__ void hidden_layers(Smem& S, const float* P) {
   stage_weights(S, P + kOffW1, kSurIn, 16);
   __syncthreads();
-  dense_gelu(S, S.x, 16, P + kOffB1, S.z[0], S.h[0]);
+  dense_gelu(S, S.x[0], S.x[1], 16, P + kOffB1, S.z[0], S.h[0][0], S.h[0][1]);
   __syncthreads();
   stage_weights(S, P + kOffW2, 128, 128);
   __syncthreads();
-  dense_gelu(S, S.h[0], 128, P + kOffB2, S.z[1], S.h[1]);
+  dense_gelu(S, S.h[0][0], S.h[0][1], 128, P + kOffB2, S.z[1], S.h[1][0], S.h[1][1]);
   __syncthreads();
   stage_weights(S, P + kOffW3, 128, 128);
   __syncthreads();
-  dense_gelu(S, S.h[1], 128, P + kOffB3, S.z[2], S.h[2]);
+  dense_gelu(S, S.h[1][0], S.h[1][1], 128, P + kOffB3, S.z[2], S.h[2][0], S.h[2][1]);
   __syncthreads();
   output_layer(S, P);
 }
@@ -165,20 +201,23 @@ __device__ __forceinline__ void forward_tile(Smem& S, const float* P, const floa
       const int64_t r = perm ? perm[row0 + s] : row0 + s;
       v = (x[r * kSurIn + i] - P[kOffMu + i]) / P[kOffSigma + i];
     }
-    S.x[t] = f2bf(v);
+    split_bf(v, S.x[0][t], S.x[1][t]);
   }
   hidden_layers(S, P);
 }
 
-// dW (kin x 128) += Hin^T dZ for the 32-row tile (rows i < nin), with atomics
-__device__ __forceinline__ void weight_grad(Smem& S, const unsigned short* Hin, int kin, int nin,
+// dW (kin x 128) += Hin^T dZ for the 32-row tile (rows i < nin), Hin as hi and lo parts,
+// with atomics
+__device__ __forceinline__ void weight_grad(Smem& S, const unsigned short* Hhi,
+                                            const unsigned short* Hlo, int kin, int nin,
                                             float* gW) {
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int ntiles = (kin / 16) * 8;
   for (int t = wv; t < ntiles; t += NT / 64) {
     const int mt = t >> 3, nt = t & 7;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    acc = mma16(Hin + mt * 16, 1, kin, S.d + nt * 16, 128, 1, TB, acc);
+    acc = mma16(Hhi + mt * 16, 1, kin, S.d + nt * 16, 128, 1, TB, acc);
+    acc = mma16(Hlo + mt * 16, 1, kin, S.d + nt * 16, 128, 1, TB, acc);
     const int col = nt * 16 + (l & 15);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -260,7 +299,8 @@ __global__ __launch_bounds__(NT) void mlp_train_kernel(const float* __restrict__
   // output layer
   if (tid < 128) {
     float g = 0.f;
-    for (int s = 0; s < TB; ++s) g += bf2f(S.h[2][s * 128 + tid]) * S.dy[s];
+    for (int s = 0; s < TB; ++s)
+      g += (bf2f(S.h[2][0][s * 128 + tid]) + bf2f(S.h[2][1][s * 128 + tid])) * S.dy[s];
     atomicAdd(grad + kOffW4 + tid, g);
   } else if (tid == 128) {
     float g = 0.f;
@@ -276,19 +316,19 @@ __global__ __launch_bounds__(NT) void mlp_train_kernel(const float* __restrict__
   __syncthreads();
   // layer 3: W3 (H2 -> Z3)
   bias_grad(S.z[2], grad + kOffB3);
-  weight_grad(S, S.h[1], 128, 128, grad + kOffW3);
+  weight_grad(S, S.h[1][0], S.h[1][1], 128, 128, grad + kOffW3);
   stage_weights(S, P + kOffW3, 128, 128);
   __syncthreads();
   backprop_hidden(S, S.z[1]);
   // layer 2: W2 (H1 -> Z2)
   bias_grad(S.z[1], grad + kOffB2);
-  weight_grad(S, S.h[0], 128, 128, grad + kOffW2);
+  weight_grad(S, S.h[0][0], S.h[0][1], 128, 128, grad + kOffW2);
   stage_weights(S, P + kOffW2, 128, 128);
   __syncthreads();
   backprop_hidden(S, S.z[0]);
   // layer 1: W1 (X -> Z1)
   bias_grad(S.z[0], grad + kOffB1);
-  weight_grad(S, S.x, 16, kSurIn, grad + kOffW1);
+  weight_grad(S, S.x[0], S.x[1], 16, kSurIn, grad + kOffW1);
 }
 
 __global__ __launch_bounds__(NT) void mlp_predict_kernel(const float* __restrict__ P,
@@ -315,17 +355,74 @@ __global__ void adam_kernel(float* __restrict__ P, const float* __restrict__ g,
 }
 
 // ---------------------------------------------------------------- in the step ----
-// Features of (box, bin): ln k, ln a, M_nu, stored P_M^{1/2}(a_{n-m}) / P_cdm^{1/2}, m=1..8.
-__device__ __forceinline__ bool make_features(const RespBox& bx, double k, double pcdm_half,
-                                              const double* hpm, int nbins, int b, float* f) {
-  if (!bx.sur_ok || bx.n_cur < kSurHistory + 1 || !(pcdm_half > 0.0) || !(bx.kfs > 0.0))
-    return false;
-  f[0] = static_cast<float>(log(k));
-  f[1] = static_cast<float>(log(bx.a_now));
-  f[2] = static_cast<float>(bx.m_total);
-  for (int mm = 1; mm <= kSurHistory; ++mm)
-    f[2 + mm] = static_cast<float>(hpm[static_cast<size_t>(bx.n_cur - mm) * nbins + b] / pcdm_half);
+// Inputs of (box, bin) as surrogate_layout.hpp defines them, from the stored history
+// (hpm, hpn: this box's rows), the lag brackets the host put in the box's constants and
+// box constants the host precomputed. Every value read from memory is one entry of a
+// staging array, so that a workgroup can fetch them with one load per lane, all in flight
+// together, before the P_cdm reduction (gather_value), and the inputs are formed once
+// P_cdm^{1/2} is known (finish_features).
+enum : int {
+  kGLo = 0,                    // A at node sur_j[m]
+  kGHi = kSurLags,             // A at node sur_j[m] + 1 (node sur_j[m] itself when sur_t = 0)
+  kGT = 2 * kSurLags,          // sur_t[m]
+  kGPn = 3 * kSurLags,         // P_nu^{1/2} at the last stored node
+  kGLnA, kGM, kGGap, kGLnA0, kGLnX0,
+  kGCount
+};
+
+__device__ __forceinline__ bool features_defined(const RespBox& bx) {
+  return bx.sur_ok && bx.sur_hist && bx.kfs > 0.0;
+}
+
+__device__ __forceinline__ double gather_value(const RespBox* __restrict__ bxp,
+                                               const double* hpm, const double* hpn, int nbins,
+                                               int b, int i) {
+  if (i < kGHi) return hpm[static_cast<size_t>(bxp->sur_j[i]) * nbins + b];
+  if (i < kGT) {
+    const int m = i - kGHi;
+    return hpm[static_cast<size_t>(bxp->sur_j[m] + (bxp->sur_t[m] > 0.0 ? 1 : 0)) * nbins + b];
+  }
+  if (i < kGPn) return bxp->sur_t[i - kGT];
+  switch (i) {
+    case kGPn: return hpn[static_cast<size_t>(bxp->n_cur - 1) * nbins + b];
+    case kGLnA: return bxp->sur_lna;
+    case kGM: return bxp->m_total;
+    case kGGap: return bxp->sur_gap;
+    case kGLnA0: return bxp->sur_lna0;
+    default: return bxp->sur_lnx0;
+  }
+}
+
+__device__ __forceinline__ bool finish_features(double k, double pcdm_half, const double* g,
+                                                float* f) {
+  if (!(pcdm_half > 0.0)) return false;
+  const double lnk = log(k);
+  const double lnx = lnk + g[kGLnX0];
+  if (!(lnx <= kSurXLastMax)) return false;
+  f[0] = static_cast<float>(lnk);
+  f[1] = static_cast<float>(g[kGLnA]);
+  f[2] = static_cast<float>(g[kGM]);
+  f[3] = static_cast<float>(g[kGGap]);
+  f[4] = static_cast<float>(g[kGPn] / pcdm_half);
+  f[5] = static_cast<float>(g[kGLnA0]);
+  f[6] = static_cast<float>(lnx);
+#pragma unroll
+  for (int m = 0; m < kSurLags; ++m) {
+    const double t = g[kGT + m];
+    f[7 + m] = static_cast<float>(((1.0 - t) * g[kGLo + m] + t * g[kGHi + m]) / pcdm_half);
+  }
   return true;
+}
+
+// The inputs of one (box, bin) in one thread (training rows)
+__device__ __forceinline__ bool make_features(const RespBox* __restrict__ bxp, double k,
+                                              double pcdm_half, const double* hpm,
+                                              const double* hpn, int nbins, int b, float* f) {
+  if (!features_defined(*bxp)) return false;
+  double g[kGCount];
+#pragma unroll
+  for (int i = 0; i < kGCount; ++i) g[i] = gather_value(bxp, hpm, hpn, nbins, b, i);
+  return finish_features(k, pcdm_half, g, f);
 }
 
 __device__ __forceinline__ double approx_factor(double k, double kfs) {
@@ -333,12 +430,14 @@ __device__ __forceinline__ double approx_factor(double k, double kfs) {
   return 1.0 / (t * t);
 }
 
-__device__ __forceinline__ bool in_range(const float* P, const float* f) {
+// lo, hi: the training set's minimum and maximum of each input
+__device__ __forceinline__ bool in_range(const float* lo, const float* hi, const float* f) {
+  bool in = true;
   for (int i = 0; i < kSurIn; ++i) {
-    const float lo = P[kOffMin + i], hi = P[kOffMax + i], mg = 0.05f * (hi - lo);
-    if (!(f[i] >= lo - mg && f[i] <= hi + mg)) return false;
+    const float mg = 0.05f * (hi[i] - lo[i]);
+    in = in && f[i] >= lo[i] - mg && f[i] <= hi[i] + mg;
   }
-  return true;
+  return in;
 }
 
 __global__ void pack_weights_kernel(const float* __restrict__ P, unsigned short* __restrict__ Q) {
@@ -355,58 +454,127 @@ __global__ void pack_weights_kernel(const float* __restrict__ P, unsigned short*
   }
 }
 
-// Inference-only shared memory for one bin: all three packed weight matrices at once, the
-// biases and the tail of the blob, activations of one 16-row tile ping-ponged.
-struct SmemInfer {
-  unsigned short x[16 * 16];
-  unsigned short h[2][16 * 128];
-  alignas(16) unsigned short w[kPackSize];   // W1 | W2 | W3 as packed ([out][in])
-  float b[3][128];                           // b1, b2, b3
-  float tail[kSurBlob - kOffW4];             // the FP32 blob from W4 on (W4, b4, scalers)
-  float y;
+// ---- one row through the network inside a workgroup of RT = 256 threads ----
+// The weights come from the packed bfloat16 image Q ([out][in] rows) in 16-byte chunks of 8
+// inputs. Layer 1 (128 x 16, 256 chunks): thread t holds chunk t, output t / 2, inputs
+// 8 (t % 2) .. +7. Layers 2 and 3 (128 x 128, 2048 chunks): thread t holds chunks
+// t + 256 u, u = 0..7, i.e. inputs 8 (t % 16) .. +7 of outputs t / 16 + 16 u; each load
+// instruction of a wave covers 1 KB of contiguous weights. Activations stay FP32.
+// The biases a thread adds are those of the output it finishes: t / 2 in layer 1 and
+// hidden_out(t) in layers 2 and 3; thread t holds W4[t % 128] (threads t < 128 use it).
+// Every load here is unconditional and its value first used after the P_cdm reduction, so
+// that no wait for them stands between the loads and the reduction.
+__device__ __forceinline__ int hidden_out(int t) {
+  return (t >> 4) + 16 * (4 * ((t >> 3) & 1) + 2 * ((t >> 2) & 1) + ((t >> 1) & 1));
+}
+
+struct NetRegs {
+  uint4 w1;
+  uint4 w2[8], w3[8];
+  float b1, b2, b3, w4;
+  float b4, ymu, ysg;   // output bias, target mean and scale
 };
 
-// acc += A(16 x K) * B(K x 16) with A = act[row][k] and B(k, n) = W[n][k], both bf16 rows of
-// length K in LDS: each lane's four consecutive k of a row are one 8-byte read. Same
-// operands, in the same order, as mma16 with (sam, sak) = (K, 1) and (sbk, sbn) = (1, K).
-template <int K>
-__device__ __forceinline__ f32x4 mma16_rows(const unsigned short* A, const unsigned short* W,
-                                            f32x4 acc) {
-  const int l = threadIdx.x & 63, r = l & 15, kb = (l >> 4) << 2;
+__device__ __forceinline__ void load_net_weights(const float* __restrict__ P,
+                                                 const unsigned short* __restrict__ Q, int t,
+                                                 NetRegs& r) {
+  const uint4* q = reinterpret_cast<const uint4*>(Q);
+  r.w1 = q[kPackW1 / 8 + t];
 #pragma unroll
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const bf16x4 a = *reinterpret_cast<const bf16x4*>(A + r * K + k0 + kb);
-    const bf16x4 b = *reinterpret_cast<const bf16x4*>(W + r * K + k0 + kb);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-  }
-  return acc;
+  for (int u = 0; u < 8; ++u) r.w2[u] = q[kPackW2 / 8 + t + 256 * u];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) r.w3[u] = q[kPackW3 / 8 + t + 256 * u];
+  const int o = hidden_out(t);
+  r.b1 = P[kOffB1 + (t >> 1)];
+  r.b2 = P[kOffB2 + o];
+  r.b3 = P[kOffB3 + o];
+  r.w4 = P[kOffW4 + (t & 127)];   // used (bf16-rounded) by threads t < 128
+  r.b4 = P[kOffB4];
+  r.ymu = P[kOffYMu];
+  r.ysg = P[kOffYSigma];
 }
 
-// GELU(H W + b) (bf16) for one 16 x 128 tile of rows, as dense_gelu without keeping Z
-template <int K>
-__device__ __forceinline__ void dense_gelu_rows(const unsigned short* Hin,
-                                                const unsigned short* W, const float* bias,
-                                                unsigned short* Hout) {
-  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int nt = wv; nt < 8; nt += RT / 64) {
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    acc = mma16_rows<K>(Hin, W + nt * 16 * K, acc);
-    const int col = nt * 16 + (l & 15);
+// sum_j a[j] w[j] over one chunk (w: 8 bfloat16 in a uint4)
+__device__ __forceinline__ float chunk_dot(const float* a, const uint4& w) {
+  const unsigned v[4] = {w.x, w.y, w.z, w.w};
+  float s = 0.f;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int row = ((l >> 4) << 2) + q;
-      Hout[row * 128 + col] = f2bf(gelu(acc[q] + bias[col]));
-    }
+  for (int i = 0; i < 4; ++i) {
+    s += a[2 * i] * __uint_as_float(v[i] << 16);
+    s += a[2 * i + 1] * __uint_as_float(v[i] & 0xffff0000u);
   }
+  return s;
 }
 
-// The surrogate's response, one workgroup per (bin, box): P_cdm from the deposit's partial
-// sums, the network's R for the bin (features from P_cdm and the stored history, forward
-// pass on the matrix cores; the arithmetic of the training kernels' forward pass), and the
-// exact integral (response_device.hpp) when the network cannot answer (inputs outside the
-// training range) or when checking (mode 2, which keeps the exact result and records
-// both). The whole packed weight image is staged first (one unrolled copy: the compiler
-// issues the loads ahead of the LDS stores).
+// One 128 x 128 layer: h_out = GELU(W h_in + b). Each thread has the partial sums of 8
+// outputs over its 8 inputs; the 16 threads sharing those outputs (16 consecutive lanes)
+// add them in a butterfly that halves the outputs each lane carries at every step, after
+// which lane pair (2v, 2v+1) of the group holds output (t / 16) + 16 u with
+// u = 4 b3 + 2 b2 + b1 from the lane's bits.
+__device__ __forceinline__ void hidden_128(const float* __restrict__ hin, const uint4* w,
+                                           float bias, float* hout) {
+  const int t = threadIdx.x, c = t & 15;
+  float a[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a[j] = hin[8 * c + j];
+  float v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) v[u] = chunk_dot(a, w[u]);
+  const bool b3 = (t >> 3) & 1, b2 = (t >> 2) & 1, b1 = (t >> 1) & 1;
+  float x4[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float keep = b3 ? v[4 + i] : v[i], send = b3 ? v[i] : v[4 + i];
+    x4[i] = keep + __shfl_xor(send, 8, 64);
+  }
+  float x2[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float keep = b2 ? x4[2 + i] : x4[i], send = b2 ? x4[i] : x4[2 + i];
+    x2[i] = keep + __shfl_xor(send, 4, 64);
+  }
+  const float keep = b1 ? x2[1] : x2[0], send = b1 ? x2[0] : x2[1];
+  float z = keep + __shfl_xor(send, 2, 64);
+  z += __shfl_xor(z, 1, 64);
+  if (!(t & 1)) hout[hidden_out(t)] = gelu(z + bias);
+}
+
+// The row's output y (standardised target) without the output bias, in every thread.
+// x: the 16 standardised inputs in LDS; h0, h1: two 128-float LDS rows; red: RT / 64 floats.
+__device__ __forceinline__ float net_forward(const NetRegs& r, const float* x, float* h0,
+                                             float* h1, float* red) {
+  const int t = threadIdx.x;
+  {
+    float a[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[j] = x[8 * (t & 1) + j];
+    float z = chunk_dot(a, r.w1);
+    z += __shfl_xor(z, 1, 64);
+    if (!(t & 1)) h0[t >> 1] = gelu(z + r.b1);
+  }
+  __syncthreads();
+  hidden_128(h0, r.w2, r.b2, h1);
+  __syncthreads();
+  hidden_128(h1, r.w3, r.b3, h0);
+  __syncthreads();
+  float s = t < 128 ? h0[t] * bfr(r.w4) : 0.f;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+  if ((t & 63) == 0) red[t >> 6] = s;
+  __syncthreads();
+  float y = 0.f;
+#pragma unroll
+  for (int w = 0; w < RT / 64; ++w) y += red[w];
+  return y;
+}
+
+// The surrogate's response, one workgroup per (bin b, box), as response_kernel but with the
+// network in place of the history integral where it can answer: P_cdm from the deposit's
+// partial sums, the bin's inputs (their memory reads are issued before the partial sums,
+// the network's weights right after them, so that the latencies overlap), the
+// network's R, and the exact integral (response_device.hpp) for a bin whose inputs are not
+// defined or fall outside the training range. Mode 1 keeps the network's R; mode 2 (check)
+// keeps the exact result and records the network's beside it.
 __global__ __launch_bounds__(RT) void surrogate_response_kernel(
     const float* __restrict__ P, const unsigned short* __restrict__ Q, int mode,
     const RespBox* __restrict__ boxes, const double* __restrict__ partial, int n_partial,
@@ -416,123 +584,97 @@ __global__ __launch_bounds__(RT) void surrogate_response_kernel(
     const double* __restrict__ tg_ds, const double* __restrict__ tg_w, int nbins, int jcap,
     int qcap, int q_sub, int iterations, double norm, double* __restrict__ pcdm_out,
     double* __restrict__ pnu_out, double* __restrict__ ratio_out, double* __restrict__ sur_r,
-    int* __restrict__ sur_use, double* __restrict__ chk_exact, double* __restrict__ chk_sur) {
-  __shared__ SmemInfer S;
+    double* __restrict__ chk_exact, double* __restrict__ chk_sur) {
   __shared__ double red[2 * RT / 64];
+  __shared__ float xs[kSurIn];
+  __shared__ float h0[128], h1[128];
+  __shared__ float redf[RT / 64];
+  __shared__ float scal[4 * kSurIn];   // the inputs' mean, scale, minimum, maximum
+  __shared__ double gsh[kGCount];      // the staged values of the inputs
   __shared__ int s_ok;
   const int tid = threadIdx.x;
   const int b = blockIdx.x, box = blockIdx.y;
   const size_t ob = static_cast<size_t>(box) * nbins + b;
-  constexpr int WV = kPackSize / 8, WIT = (WV + RT - 1) / RT;   // 16-byte pieces
-  constexpr int TV = kSurBlob - kOffW4;
-  static_assert(3 * 128 + TV <= 3 * RT, "three values per thread");
-  {
-    static_assert(WV % RT == 0, "whole rounds");
-    const uint4* src = reinterpret_cast<const uint4*>(Q);
-    uint4* dst = reinterpret_cast<uint4*>(S.w);
-#pragma unroll
-    for (int i = 0; i < WIT; ++i) dst[tid + i * RT] = src[tid + i * RT];
-    // slot t of 3 * 128 + TV: the biases, then the tail of the blob
-    auto src_of = [&](int t) {
-      return t < 128 ? kOffB1 + t : t < 256 ? kOffB2 + t - 128
-                                            : t < 384 ? kOffB3 + t - 256 : kOffW4 + t - 384;
-    };
-    float pr[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const int t = tid + i * RT;
-      if (t < 384 + TV) pr[i] = P[src_of(t)];
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const int t = tid + i * RT;
-      if (t < 384) S.b[t / 128][t % 128] = pr[i];
-      else if (t < 384 + TV) S.tail[t - 384] = pr[i];
-    }
-  }
-  const float* Ps = S.tail - kOffW4;         // blob offsets from W4 on, in LDS
-  const RespBox bx = boxes[box];
+  const RespBox* bxp = boxes + box;
+  const RespBox bx = *bxp;
   double* hpm = hist_pm + static_cast<size_t>(box) * jcap * nbins;
   double* hpn = hist_pnu + static_cast<size_t>(box) * jcap * nbins;
   const size_t row = static_cast<size_t>(bx.n_cur) * nbins + b;
   const double cb = counts[b];
+  const bool defined = cb > 0.0 && features_defined(bx);   // uniform over the workgroup
+  const double kb = kmean[b];
+  // fetched before the reduction: one staged value per lane and the scalers
+  double gv = 0.0;
+  float sc = 0.f;
+  if (defined) {
+    if (tid < kGCount) gv = gather_value(bxp, hpm, hpn, nbins, b, tid);
+    if (tid < 4 * kSurIn) sc = P[kOffMu + tid];   // kOffMu .. kOffMax + kSurIn are contiguous
+  }
   const double msum = bin_mode_sum(partial, n_partial, nbins, box, b, red);   // has barriers
+  // the weights after it (consuming the reduction's loads waits for every older load):
+  // their latency hides behind the inputs formed below
+  NetRegs w;
+  if (defined) load_net_weights(P, Q, tid, w);
   const double pcdm = cb > 0.0 ? norm * msum / cb : 0.0;
-  if (!(cb > 0.0)) {
-    if (tid == 0) {
-      pcdm_out[ob] = 0.0;
+  const double ph = sqrt(pcdm);
+  if (defined) {
+    if (tid < 4 * kSurIn) scal[tid] = sc;
+    if (tid < kGCount) gsh[tid] = gv;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    float f[kSurIn];
+    const bool ok = defined && finish_features(kb, ph, gsh, f) &&
+                    in_range(scal + 2 * kSurIn, scal + 3 * kSurIn, f);
+    s_ok = ok ? 1 : 0;
+    if (ok) {
+      for (int i = 0; i < kSurIn; ++i) xs[i] = (f[i] - scal[i]) / scal[kSurIn + i];
+    }
+    pcdm_out[ob] = pcdm;
+    if (!(cb > 0.0)) {
       sur_r[ob] = __builtin_nan("");
-      sur_use[ob] = 0;
       pnu_out[ob] = ratio_out[ob] = 0.0;
       hpm[row] = hpn[row] = 0.0;
       if (chk_exact) chk_exact[ob] = chk_sur[ob] = 0.0;
+    } else if (!ok) {
+      sur_r[ob] = __builtin_nan("");
     }
-    return;
-  }
-  const double ph = sqrt(pcdm);
-  if (tid == 0) {
-    float f[kSurIn];
-    const bool ok = make_features(bx, kmean[b], ph, hpm, nbins, b, f) && in_range(Ps, f);
-    s_ok = ok ? 1 : 0;
-    for (int i = 0; i < 16; ++i)
-      S.x[i] = f2bf(ok && i < kSurIn ? (f[i] - Ps[kOffMu + i]) / Ps[kOffSigma + i] : 0.f);
-  } else if (tid >= 16 && tid < 16 * 16) {
-    S.x[tid] = 0;                            // rows 1..15 of the tile (row 0: thread 0)
   }
   __syncthreads();
   const bool ok = s_ok != 0;
-  double r_net = __builtin_nan("");
   if (ok) {
-    dense_gelu_rows<16>(S.x, S.w + kPackW1, S.b[0], S.h[0]);
-    __syncthreads();
-    dense_gelu_rows<128>(S.h[0], S.w + kPackW2, S.b[1], S.h[1]);
-    __syncthreads();
-    dense_gelu_rows<128>(S.h[1], S.w + kPackW3, S.b[2], S.h[0]);
-    __syncthreads();
-    if (tid < 8) {
-      // output layer: 8 lanes, 16 products each, FP32 (as output_layer)
-      float acc = 0.f;
-#pragma unroll
-      for (int j = tid * 16; j < tid * 16 + 16; ++j)
-        acc += bf2f(S.h[0][j]) * bfr(Ps[kOffW4 + j]);
-      acc += __shfl_xor(acc, 1, 64);
-      acc += __shfl_xor(acc, 2, 64);
-      acc += __shfl_xor(acc, 4, 64);
-      if (tid == 0) S.y = acc + Ps[kOffB4];
-    }
-    __syncthreads();
-    r_net = exp(static_cast<double>(S.y * Ps[kOffYSigma] + Ps[kOffYMu])) *
-            approx_factor(kmean[b], bx.kfs);
-  }
-  if (tid == 0) {
-    pcdm_out[ob] = pcdm;
-    sur_r[ob] = r_net;
-    sur_use[ob] = ok ? 1 : 0;
-  }
-  if (ok && mode == 1) {                     // answered by the network
+    const float y = net_forward(w, xs, h0, h1, redf) + w.b4;
     if (tid == 0) {
-      const double pnu = r_net * ph;
+      const double r_net = exp(static_cast<double>(y * w.ysg + w.ymu)) *
+                           approx_factor(kb, bx.kfs);
+      sur_r[ob] = r_net;
+      if (mode == 1) {
+        const double pnu = r_net * ph;
+        pnu_out[ob] = pnu;
+        ratio_out[ob] = r_net;
+        hpm[row] = (1.0 - bx.f_nu) * ph + bx.f_nu * pnu;
+        hpn[row] = pnu;
+      } else if (chk_sur) {
+        chk_sur[ob] = r_net;
+      }
+    }
+  }
+  if (cb > 0.0 && (!ok || mode == 2)) {
+    const double pnu = exact_pnu(bx, kb, ph, (bx.n_cur > 0 ? hpn[row - nbins] : 0.0),
+                                 ic_pnu + static_cast<size_t>(box) * kMaxSpecies * nbins,
+                                 ic_theta[ob], hpm, nbins, b,
+                                 tg_ds + static_cast<size_t>(box) * qcap,
+                                 tg_w + static_cast<size_t>(box) * qcap, q_sub, iterations, red);
+    if (tid == 0) {
+      const double r = ph > 0.0 ? pnu / ph : 0.0;   // no CDM power in the bin: R = 0
       pnu_out[ob] = pnu;
-      ratio_out[ob] = r_net;
+      ratio_out[ob] = r;
       hpm[row] = (1.0 - bx.f_nu) * ph + bx.f_nu * pnu;
       hpn[row] = pnu;
-    }
-    return;
-  }
-  const double pnu = exact_pnu(bx, kmean[b], ph, (bx.n_cur > 0 ? hpn[row - nbins] : 0.0),
-                               ic_pnu + static_cast<size_t>(box) * kMaxSpecies * nbins,
-                               ic_theta[ob], hpm, nbins, b,
-                               tg_ds + static_cast<size_t>(box) * qcap,
-                               tg_w + static_cast<size_t>(box) * qcap, q_sub, iterations, red);
-  if (tid == 0) {
-    const double r = ph > 0.0 ? pnu / ph : 0.0;   // no CDM power in the bin: R = 0
-    pnu_out[ob] = pnu;
-    ratio_out[ob] = r;
-    hpm[row] = (1.0 - bx.f_nu) * ph + bx.f_nu * pnu;
-    hpn[row] = pnu;
-    if (chk_exact) {
-      chk_exact[ob] = r;
-      chk_sur[ob] = ok ? r_net : r;
+      if (chk_exact) {
+        chk_exact[ob] = r;
+        if (!ok) chk_sur[ob] = r;             // the network did not answer for this bin
+      }
     }
   }
 }
@@ -540,7 +682,8 @@ __global__ __launch_bounds__(RT) void surrogate_response_kernel(
 // Training rows from the step's state after an exact response: one thread per (box, bin).
 __global__ void dataset_kernel(const RespBox* __restrict__ boxes, const double* __restrict__ pcdm,
                                const double* __restrict__ ratio, const double* __restrict__ kmean,
-                               const double* __restrict__ hist_pm, int nbins, int jcap,
+                               const double* __restrict__ hist_pm,
+                               const double* __restrict__ hist_pnu, int nbins, int jcap,
                                int nbox, float* __restrict__ x, float* __restrict__ y) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nbox * nbins) return;
@@ -549,8 +692,10 @@ __global__ void dataset_kernel(const RespBox* __restrict__ boxes, const double* 
   const double ph = sqrt(pcdm[i]);
   const double r = ratio[i];
   float f[kSurIn];
-  bool ok = make_features(bx, kmean[b], ph, hist_pm + static_cast<size_t>(box) * jcap * nbins,
-                          nbins, b, f) && r > 0.0;
+  const size_t hoff = static_cast<size_t>(box) * jcap * nbins;
+  bool ok = make_features(boxes + box, kmean[b], ph, hist_pm + hoff, hist_pnu + hoff, nbins, b,
+                          f) &&
+            r > 0.0;
   for (int c = 0; c < kSurIn; ++c) x[static_cast<size_t>(i) * kSurIn + c] = ok ? f[c] : 0.f;
   y[i] = ok ? static_cast<float>(log(r / approx_factor(kmean[b], bx.kfs)))
             : __builtin_nanf("");
@@ -595,21 +740,21 @@ hipError_t launch_surrogate_response(const float* P, const unsigned short* Q, in
                                      const double* tg_w, int nbins, int jcap, int qcap,
                                      int q_sub, int iterations, double norm, int nbox,
                                      double* pcdm, double* pnu, double* ratio, double* sur_r,
-                                     int* sur_use, double* chk_exact, double* chk_sur,
-                                     hipStream_t s) {
+                                     double* chk_exact, double* chk_sur, hipStream_t s) {
   hipLaunchKernelGGL(surrogate_response_kernel, dim3(nbins, nbox), dim3(RT), 0, s, P, Q, mode,
                      boxes, partial, n_partial, counts, kmean, hist_pm, hist_pnu, ic_pnu,
                      ic_theta, tg_ds, tg_w, nbins, jcap, qcap, q_sub, iterations, norm, pcdm,
-                     pnu, ratio, sur_r, sur_use, chk_exact, chk_sur);
+                     pnu, ratio, sur_r, chk_exact, chk_sur);
   return hipGetLastError();
 }
 
 hipError_t launch_surrogate_dataset(const RespBox* boxes, const double* pcdm, const double* ratio,
-                                    const double* kmean, const double* hist_pm, int nbins,
-                                    int jcap, int nbox, float* x, float* y, hipStream_t s) {
+                                    const double* kmean, const double* hist_pm,
+                                    const double* hist_pnu, int nbins, int jcap, int nbox,
+                                    float* x, float* y, hipStream_t s) {
   const int n = nbox * nbins;
   hipLaunchKernelGGL(dataset_kernel, dim3((n + 255) / 256), dim3(256), 0, s, boxes, pcdm, ratio,
-                     kmean, hist_pm, nbins, jcap, nbox, x, y);
+                     kmean, hist_pm, hist_pnu, nbins, jcap, nbox, x, y);
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@
 
 #include "../../include/pm_nu.h"
 #include "host_consts.hpp"
+#include "surrogate_layout.hpp"
 
 namespace pmnu {
 
@@ -29,6 +30,17 @@ struct RespBox {
   int nq;            // sub-nodes of the quadrature (current step included)
   int n_cur;         // history row of the current step
   int series;        // 1: exact series for I(x), 0: the fit eq. (fit)
+  // the surrogate's history samples (surrogate_layout.hpp): lag m reads the stored nodes
+  // sur_j[m] and sur_j[m] + 1 with weights 1 - sur_t[m] and sur_t[m] (sur_t = 0: node
+  // sur_j alone); sur_hist = 0 when the history does not reach back far enough
+  int sur_hist;
+  int sur_j[kSurLags];
+  double sur_t[kSurLags];
+  double sur_gap;    // ln a_now - ln a_{n-1}
+  double sur_ds_last;  // s(a_now) - s(a_{n-1})
+  double sur_lna;      // ln a_now
+  double sur_lna0;     // ln(a_now / a_0)
+  double sur_lnx0;     // ln((s(a_now) - s(a_{n-1})) T_nu0 / m): input 6 is ln k + sur_lnx0
 };
 
 // A coordinate moved back into [0, L) (exact: fmodf; x + L may round up to L, which wraps to 0).
@@ -73,7 +85,7 @@ struct Timer {
 enum Stage {
   ST_ZERO = 0, ST_DEPOSIT, ST_FFT_Z, ST_FFT_Y, ST_FFT_X_BIN, ST_RESPONSE, ST_RTABLE,
   ST_INV_X_GREEN, ST_INV_Y, ST_INV_Z, ST_INTERP, ST_SURROGATE, ST_PATCH_REDUCE, ST_KICK_DRIFT,
-  ST_COUNT
+  ST_PATCH_FWD_Z, ST_COUNT
 };
 extern const char* const kStageNames[ST_COUNT];
 
@@ -153,7 +165,9 @@ struct Ctx {
   RespBox* h_resp = nullptr;       // [nbox]
   double* h_kd = nullptr;          // [nbox][2]
   hipEvent_t ev_tg = nullptr, ev_kd = nullptr;
-  bool density_is_delta = false;   // the last deposit wrote delta (modes 6, 7), not rho
+  bool density_is_delta = false;   // the last deposit wrote delta (modes 6..9), not rho
+  bool keep_density = false;       // modes 8, 9: also store delta (pm_nu_set_keep_density)
+  bool density_kept = false;       // the last deposit left a readable density
 
   // host state
   std::vector<std::vector<double>> hist_a;   // committed node scale factors per box
@@ -234,8 +248,16 @@ hipError_t launch_interp(const float* pos, const float* force, float* acc, int64
 hipError_t launch_fwd_z(int N, const unsigned long long* rho, const float* delta, int* reset,
                         int* clear, int n_clear, float2* out, const float2* tw, double scale,
                         int nbox, hipStream_t s, int v = 0);
+// reset, clear, n_clear: the patch registry's end-of-step work after launch_patch_fwd_z
 hipError_t launch_fwd_y(int N, const float2* in, float2* out, const float2* tw, int nbox,
-                        hipStream_t s, int v = 0);
+                        hipStream_t s, int v = 0, int* reset = nullptr, int* clear = nullptr,
+                        int n_clear = 0);
+// the patch sums and the first (z) forward pass in one kernel (N >= 32); delta_out, when
+// given, also receives delta
+hipError_t launch_patch_fwd_z(int n, const unsigned long long* patches, const int* reg_count,
+                              const int4* reg_list, unsigned long long* rho_fb, const int* n_fb,
+                              float2* out, const float2* tw, double scale, int nbox,
+                              hipStream_t s, float* delta_out);
 // partial != NULL: FFT along x and the mode sums per bin, data left unchanged (the step);
 // partial == NULL: FFT along x stored in place, no sums (reading the modes out)
 hipError_t launch_fwd_x_bin(int N, float2* data, const float2* tw, const uint16_t* bin_of_n2,
@@ -262,7 +284,9 @@ hipError_t launch_response(const RespBox* boxes, const double* partial, int n_pa
                            const double* ic_theta, const double* tg_ds, const double* tg_w,
                            int B, int Jcap, int qcap, int Q, int iterations, double norm,
                            int nbox, double* pcdm, double* pnu, double* ratio,
-                           hipStream_t s);
+                           hipStream_t s, int threads);
+// threads per workgroup of the exact response for this many (bin, box) pairs: 64 or 256
+int response_threads(int nbins, int nbox);
 // mlp_kernels.hip
 hipError_t launch_mlp_train(const float* P, const float* x, const float* y, const int* perm,
                             int64_t row0, int64_t count, float inv_batch, float* grad,
@@ -280,11 +304,11 @@ hipError_t launch_surrogate_response(const float* P, const unsigned short* Q, in
                                      const double* tg_w, int nbins, int jcap, int qcap,
                                      int q_sub, int iterations, double norm, int nbox,
                                      double* pcdm, double* pnu, double* ratio, double* sur_r,
-                                     int* sur_use, double* chk_exact, double* chk_sur,
-                                     hipStream_t s);
+                                     double* chk_exact, double* chk_sur, hipStream_t s);
 hipError_t launch_surrogate_dataset(const RespBox* boxes, const double* pcdm, const double* ratio,
-                                    const double* kmean, const double* hist_pm, int nbins,
-                                    int jcap, int nbox, float* x, float* y, hipStream_t s);
+                                    const double* kmean, const double* hist_pm,
+                                    const double* hist_pnu, int nbins, int jcap, int nbox,
+                                    float* x, float* y, hipStream_t s);
 int patch_cb_log2(int n);
 int64_t patch_coarse_cells(int n);
 int64_t patch_chunks(int64_t np);

@@ -1,5 +1,6 @@
 // Device pieces of the neutrino response shared by the exact and the surrogate kernels
-// (FP64, one workgroup of RT threads per (k-bin, box)).
+// (FP64, one workgroup of NT threads per (k-bin, box): RT = 256 when there are few
+// (bin, box) pairs to spread over the chip, one wave when there are many).
 #pragma once
 #include "pm_nu_internal.hpp"
 
@@ -74,23 +75,27 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-// Sum over the workgroup (RT threads); every thread gets the result.
+// Sum over the workgroup (NT threads); every thread gets the result.
+template <int NT = RT>
 __device__ __forceinline__ double block_sum_d(double v, double* red) {
   v = wave_sum_d(v);
+  if constexpr (NT == 64) return v;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) red[wave] = v;
   __syncthreads();
   double s = 0.0;
 #pragma unroll
-  for (int w = 0; w < RT / 64; ++w) s += red[w];
+  for (int w = 0; w < NT / 64; ++w) s += red[w];
   return s;
 }
 
 // Two sums over the workgroup at once; every thread gets both.
+template <int NT = RT>
 __device__ __forceinline__ double2 block_sum_d2(double2 v, double* red) {
   v.x = wave_sum_d(v.x);
   v.y = wave_sum_d(v.y);
+  if constexpr (NT == 64) return v;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) {
@@ -100,7 +105,7 @@ __device__ __forceinline__ double2 block_sum_d2(double2 v, double* red) {
   __syncthreads();
   double2 s = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int w = 0; w < RT / 64; ++w) {
+  for (int w = 0; w < NT / 64; ++w) {
     s.x += red[2 * w];
     s.y += red[2 * w + 1];
   }
@@ -109,22 +114,29 @@ __device__ __forceinline__ double2 block_sum_d2(double2 v, double* red) {
 
 // sum over the per-workgroup partial mode sums of bin b ([box][bin][workgroup]):
 // sum w |delta_k|^2
+template <int NT = RT>
 __device__ __forceinline__ double bin_mode_sum(const double* partial, int n_partial, int nbins,
                                                int box, int b, double* red) {
-  constexpr int U = 8;                       // loads in flight per thread
-  double s = 0.0;
+  // Each thread reads per = ceil(n_partial / NT) values at i = tid + NT u (coalesced for
+  // every u), in as few rounds of at most U loads in flight as cover them, split evenly, so
+  // that no round is a nearly empty one that would cost a memory latency of its own.
+  constexpr int U = 16;
   const double* pp = partial + (static_cast<size_t>(box) * nbins + b) * n_partial;
-  for (int i0 = 0; i0 < n_partial; i0 += U * RT) {
+  const int per = (n_partial + NT - 1) / NT;
+  const int rounds = (per + U - 1) / U;
+  const int chunk = rounds > 0 ? (per + rounds - 1) / rounds : 0;
+  double s = 0.0;
+  for (int u0 = 0; u0 < per; u0 += chunk) {
     double v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int i = i0 + threadIdx.x + u * RT;
-      v[u] = i < n_partial ? pp[i] : 0.0;
+      const int i = threadIdx.x + (u0 + u) * NT;
+      v[u] = (u < chunk && i < n_partial) ? pp[i] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) s += v[u];
   }
-  return block_sum_d(s, red);
+  return block_sum_d<NT>(s, red);
 }
 
 // eq. (P-final) for one bin: the initial-condition term plus the trapezoid sum over the
@@ -137,31 +149,41 @@ __device__ __forceinline__ double bin_mode_sum(const double* partial, int n_part
 // The sum is linear in the unknown current node A_n = (1 - f_nu) P_cdm^{1/2} + f_nu P_nu^{1/2}
 // (it enters only the last stored interval), so one pass gathers the part from the stored
 // nodes and the coefficient of A_n; each iteration of Appendix B is then a scalar update
-// and the kernel is evaluated once whatever the number of iterations.
-// red: 2 * RT / 64 doubles.
-template <int NSP, bool SERIES>   // species: 1 (equal masses) or kMaxSpecies; exact kernel
+// and the kernel is evaluated once whatever the number of iterations. The initial-condition
+// term is evaluated by the first wave only and enters the sum through thread 0. Each
+// thread takes ceil(nq / NT) sub-nodes q = tid + NT u, in as few rounds of at most U
+// whose loads go out together as cover them.
+// red: 2 * NT / 64 doubles.
+template <int NSP, bool SERIES, int NT>   // species: 1 (equal masses) or kMaxSpecies
 __device__ __forceinline__ double exact_pnu_n(const RespBox& bx, double k, double pcdm_half,
                                               double pnu_prev, const double* ic_pnu,
                                               double ic_theta, const double* hpm, int nbins,
                                               int b, const double* ds, const double* w,
                                               int q_sub, int iterations, double* red) {
   const double inv_q = 1.0 / q_sub;
-  double ic = 0.0;
-#pragma unroll
-  for (int sp = 0; sp < NSP; ++sp)           // constant bound: the arrays stay in registers
-    if (sp < bx.n_sp)
-      ic += bx.w_sp[sp] * i_kernel<SERIES>(k * bx.tm_sp[sp] * bx.ds_ic) * ic_pnu[sp * nbins + b];
-  ic *= 1.0 - bx.ds_ic * bx.a_i * ic_theta;
   double known = 0.0, coef = 0.0;
-  constexpr int U = 4;                       // sub-nodes per thread whose loads go out together
-  for (int q0 = 0; q0 < bx.nq; q0 += U * RT) {
+  if (threadIdx.x < 64) {                    // wave-uniform
+    double ic = 0.0;
+#pragma unroll
+    for (int sp = 0; sp < NSP; ++sp)         // constant bound: the arrays stay in registers
+      if (sp < bx.n_sp)
+        ic += bx.w_sp[sp] * i_kernel<SERIES>(k * bx.tm_sp[sp] * bx.ds_ic) *
+              ic_pnu[sp * nbins + b];
+    ic *= 1.0 - bx.ds_ic * bx.a_i * ic_theta;
+    if (threadIdx.x == 0) known = ic;
+  }
+  constexpr int U = NT == 64 ? 4 : 8;        // one wave: keep registers for occupancy
+  const int per = (bx.nq + NT - 1) / NT;
+  const int rounds = (per + U - 1) / U;
+  const int chunk = rounds > 0 ? (per + rounds - 1) / rounds : 0;
+  for (int u0 = 0; u0 < per; u0 += chunk) {
     double d[U], wq[U], a0[U], a1[U];
     bool c0[U], c1[U];                       // the bracketing node is the current one
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int q = q0 + threadIdx.x + u * RT;
+      const int q = threadIdx.x + (u0 + u) * NT;
       const int j = q / q_sub;
-      const bool in = q < bx.nq;
+      const bool in = u < chunk && q < bx.nq;
       d[u] = in ? ds[q] : 0.0;
       wq[u] = in ? w[q] : 0.0;
       c0[u] = !(j < bx.n_cur);
@@ -171,8 +193,8 @@ __device__ __forceinline__ double exact_pnu_n(const RespBox& bx, double k, doubl
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int q = q0 + threadIdx.x + u * RT;
-      if (q >= bx.nq) continue;
+      const int q = threadIdx.x + (u0 + u) * NT;
+      if (u >= chunk || q >= bx.nq) continue;
       const int j = q / q_sub, r = q - j * q_sub;
       const double t = r * inv_q;
       // amplitude = (1 - t) A_j + t A_{j+1}, with A_n split off
@@ -188,16 +210,17 @@ __device__ __forceinline__ double exact_pnu_n(const RespBox& bx, double k, doubl
       coef += g * cur;
     }
   }
-  const double2 sums = block_sum_d2(make_double2(known, coef), red);
+  const double2 sums = block_sum_d2<NT>(make_double2(known, coef), red);
   double pnu_guess = pnu_prev, pnu = 0.0;
   for (int it = 0; it < iterations; ++it) {
     const double a_cur = (1.0 - bx.f_nu) * pcdm_half + bx.f_nu * pnu_guess;
-    pnu = ic + sums.x + sums.y * a_cur;
+    pnu = sums.x + sums.y * a_cur;
     pnu_guess = pnu;
   }
   return pnu;
 }
 
+template <int NT = RT>
 __device__ __forceinline__ double exact_pnu(const RespBox& bx, double k, double pcdm_half,
                                             double pnu_prev, const double* ic_pnu,
                                             double ic_theta, const double* hpm, int nbins,
@@ -205,7 +228,7 @@ __device__ __forceinline__ double exact_pnu(const RespBox& bx, double k, double 
                                             int q_sub, int iterations, double* red) {
   if (bx.n_sp <= 0) return 0.0;          // no massive neutrinos: the term drops out
 #define PMNU_EXACT_PNU(NSP, SERIES)                                                        \
-  exact_pnu_n<NSP, SERIES>(bx, k, pcdm_half, pnu_prev, ic_pnu, ic_theta, hpm, nbins, b, ds, \
+  exact_pnu_n<NSP, SERIES, NT>(bx, k, pcdm_half, pnu_prev, ic_pnu, ic_theta, hpm, nbins, b, ds, \
                            w, q_sub, iterations, red)
   if (bx.series) {
     if (bx.n_sp == 1) return PMNU_EXACT_PNU(1, true);

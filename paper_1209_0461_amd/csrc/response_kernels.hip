@@ -27,7 +27,8 @@
 namespace pmnu {
 namespace {
 
-__global__ __launch_bounds__(RT) void response_kernel(
+template <int NT>
+__global__ __launch_bounds__(NT) void response_kernel(
     const RespBox* __restrict__ boxes, const double* __restrict__ partial, int n_partial,
     const double* __restrict__ counts, const double* __restrict__ kmean,
     double* __restrict__ hist_pm, double* __restrict__ hist_pnu,
@@ -35,7 +36,7 @@ __global__ __launch_bounds__(RT) void response_kernel(
     const double* __restrict__ tg_ds, const double* __restrict__ tg_w, int nbins, int jcap,
     int qcap, int q_sub, int iterations, double norm, double* __restrict__ pcdm_out,
     double* __restrict__ pnu_out, double* __restrict__ ratio_out) {
-  __shared__ double red[2 * RT / 64];
+  __shared__ double red[2 * NT / 64];
   const int b = blockIdx.x, box = blockIdx.y;
   const RespBox bx = boxes[box];
   const size_t ob = static_cast<size_t>(box) * nbins + b;
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(RT) void response_kernel(
   double* hpn = hist_pnu + static_cast<size_t>(box) * jcap * nbins;
 
   // 1. binned CDM power
-  const double s = bin_mode_sum(partial, n_partial, nbins, box, b, red);
+  const double s = bin_mode_sum<NT>(partial, n_partial, nbins, box, b, red);
   const double cb = counts[b];
   if (!(cb > 0.0)) {
     if (threadIdx.x == 0) {
@@ -59,7 +60,7 @@ __global__ __launch_bounds__(RT) void response_kernel(
   const double pcdm_half = sqrt(pcdm);
 
   // 2. history integral
-  const double pnu = exact_pnu(bx, kmean[b], pcdm_half,
+  const double pnu = exact_pnu<NT>(bx, kmean[b], pcdm_half,
                                (bx.n_cur > 0 ? hpn[static_cast<size_t>(bx.n_cur - 1) * nbins + b] : 0.0),
                                ic_pnu + static_cast<size_t>(box) * kMaxSpecies * nbins,
                                ic_theta[ob], hpm, nbins, b, tg_ds + static_cast<size_t>(box) * qcap,
@@ -156,12 +157,22 @@ hipError_t launch_response(const RespBox* boxes, const double* partial, int n_pa
                            const double* ic_theta, const double* tg_ds, const double* tg_w,
                            int nbins, int jcap, int qcap, int q_sub, int iterations,
                            double norm, int nbox, double* pcdm, double* pnu, double* ratio,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(response_kernel, dim3(nbins, nbox), dim3(RT), 0, s, boxes, partial,
-                     n_partial, counts, kmean, const_cast<double*>(hist_pm),
-                     const_cast<double*>(hist_pnu), ic_pnu, ic_theta, tg_ds, tg_w, nbins, jcap,
-                     qcap, q_sub, iterations, norm, pcdm, pnu, ratio);
+                           hipStream_t s, int threads) {
+#define PMNU_LAUNCH_RESPONSE(NT)                                                             \
+  hipLaunchKernelGGL(response_kernel<NT>, dim3(nbins, nbox), dim3(NT), 0, s, boxes, partial, \
+                     n_partial, counts, kmean, const_cast<double*>(hist_pm),                 \
+                     const_cast<double*>(hist_pnu), ic_pnu, ic_theta, tg_ds, tg_w, nbins,    \
+                     jcap, qcap, q_sub, iterations, norm, pcdm, pnu, ratio)
+  if (threads == 64) PMNU_LAUNCH_RESPONSE(64);
+  else PMNU_LAUNCH_RESPONSE(RT);
+#undef PMNU_LAUNCH_RESPONSE
   return hipGetLastError();
+}
+
+int response_threads(int nbins, int nbox) {
+  // one wave per (bin, box) once the pairs alone fill the chip's SIMDs several times over
+  // (the batched boxes); a full workgroup per pair otherwise, to spread its sub-nodes
+  return static_cast<int64_t>(nbins) * nbox >= 1024 ? 64 : RT;
 }
 
 hipError_t launch_bin_power(const double* partial, int n_partial, const double* counts,

@@ -27,7 +27,6 @@ struct Surrogate {
   double* chk_sur = nullptr;   // [nbox][B]
   unsigned short* packed = nullptr;  // bf16 image of W1..W3 for inference
   double* sur_r = nullptr;     // [nbox][B] the network's R of the last response
-  int* sur_use = nullptr;      // [nbox][B] 1 where the network answered
   bool packed_valid = false;   // cleared whenever the FP32 masters change
   bool loaded = false;
   int64_t step = 0;
@@ -37,7 +36,7 @@ void surrogate_free(Ctx& c) {
   Surrogate* s = c.sur;
   if (!s) return;
   void* bufs[] = {s->P, s->g, s->m, s->v, s->loss, s->perm, s->chk_exact, s->chk_sur,
-                  s->packed, s->sur_r, s->sur_use};
+                  s->packed, s->sur_r};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   delete s;
@@ -60,7 +59,6 @@ int ensure(Ctx& c) {
   if (!e) e = hipMalloc(&s->chk_sur, nb * sizeof(double));
   if (!e) e = hipMalloc(&s->packed, packed_weight_count() * sizeof(unsigned short));
   if (!e) e = hipMalloc(&s->sur_r, nb * sizeof(double));
-  if (!e) e = hipMalloc(&s->sur_use, nb * sizeof(int));
   if (!e) e = hipMemset(s->P, 0, kSurBlob * sizeof(float));
   if (!e) e = hipMemset(s->chk_exact, 0, nb * sizeof(double));
   if (!e) e = hipMemset(s->chk_sur, 0, nb * sizeof(double));
@@ -109,8 +107,8 @@ int surrogate_launch(Ctx& c, int mode, double norm) {
   hipError_t e = launch_surrogate_response(
       s->P, s->packed, mode, c.d_resp, c.bin_partial, c.n_partial, c.d_counts, c.d_kmean,
       c.hist_pm, c.hist_pnu, c.ic_pnu, c.ic_theta, c.tg_ds, c.tg_w, c.B, c.Jcap, c.qcap, c.Q,
-      c.cfg.iterations, norm, c.nbox, c.pcdm, c.pnu, c.ratio, s->sur_r, s->sur_use,
-      s->chk_exact, s->chk_sur, c.stream);
+      c.cfg.iterations, norm, c.nbox, c.pcdm, c.pnu, c.ratio, s->sur_r, s->chk_exact,
+      s->chk_sur, c.stream);
   timer_end(c);
   if (e != hipSuccess) return set_error(PM_NU_EHIP, "surrogate response: %s", hipGetErrorString(e));
   return PM_NU_OK;
@@ -213,13 +211,15 @@ int pm_nu_surrogate_init(pm_nu_ctx* ctx, const float* x, const float* y, int64_t
   return PM_NU_OK;
 }
 
-int pm_nu_surrogate_train(pm_nu_ctx* ctx, const float* x, const float* y, int64_t n,
-                          int epochs, int batch, float lr, uint64_t seed, float* loss_out) {
+int pm_nu_surrogate_train_part(pm_nu_ctx* ctx, const float* x, const float* y, int64_t n,
+                               int first_epoch, int epochs, int total_epochs, int batch,
+                               float lr, uint64_t seed, float* loss_out) {
   Ctx* c = reinterpret_cast<Ctx*>(ctx);
   int rc = need_loaded(c);
   if (rc) return rc;
   drop_graph(*c);   // new weights
-  if (!x || !y || n < 1 || epochs < 1 || batch < 32 || batch % 32 || !(lr > 0.f))
+  if (!x || !y || n < 1 || epochs < 1 || batch < 32 || batch % 32 || !(lr > 0.f) ||
+      first_epoch < 0 || total_epochs < first_epoch + epochs)
     return set_error(PM_NU_EINVAL, "bad training arguments");
   if (n > (1ll << 31) - 1) return set_error(PM_NU_EINVAL, "too many rows");
   Surrogate* s = c->sur;
@@ -232,10 +232,10 @@ int pm_nu_surrogate_train(pm_nu_ctx* ctx, const float* x, const float* y, int64_
   }
   std::vector<int> perm(n);
   const int64_t nb = (n + batch - 1) / batch;
-  const int64_t total = nb * epochs;
-  int64_t t = 0;
+  const int64_t total = nb * total_epochs;
+  int64_t t = nb * first_epoch;
   float last = 0.f;
-  for (int ep = 0; ep < epochs; ++ep) {
+  for (int ep = first_epoch; ep < first_epoch + epochs; ++ep) {
     for (int64_t i = 0; i < n; ++i) perm[i] = static_cast<int>(i);
     std::mt19937_64 rng(seed + 0x9E3779B97F4A7C15ull * (ep + 1));
     for (int64_t i = n - 1; i > 0; --i) {
@@ -267,6 +267,11 @@ int pm_nu_surrogate_train(pm_nu_ctx* ctx, const float* x, const float* y, int64_
   }
   if (loss_out) *loss_out = last;
   return PM_NU_OK;
+}
+
+int pm_nu_surrogate_train(pm_nu_ctx* ctx, const float* x, const float* y, int64_t n,
+                          int epochs, int batch, float lr, uint64_t seed, float* loss_out) {
+  return pm_nu_surrogate_train_part(ctx, x, y, n, 0, epochs, epochs, batch, lr, seed, loss_out);
 }
 
 int pm_nu_surrogate_predict(pm_nu_ctx* ctx, const float* x, float* y, int64_t n) {
@@ -302,8 +307,8 @@ int pm_nu_surrogate_dataset(pm_nu_ctx* ctx, double a_now, float* x, float* y) {
   if (!c || !x || !y) return set_error(PM_NU_EINVAL, "bad arguments");
   int rc = do_response_mode(*c, a_now, 0);
   if (rc) return rc;
-  SUR_LAUNCH(launch_surrogate_dataset(c->d_resp, c->pcdm, c->ratio, c->d_kmean, c->hist_pm, c->B,
-                                      c->Jcap, c->nbox, x, y, c->stream));
+  SUR_LAUNCH(launch_surrogate_dataset(c->d_resp, c->pcdm, c->ratio, c->d_kmean, c->hist_pm,
+                                      c->hist_pnu, c->B, c->Jcap, c->nbox, x, y, c->stream));
   return PM_NU_OK;
 }
 

@@ -1,16 +1,23 @@
 """Random stored histories for the surrogate network's training set.
 
 Each case is one box at the current node a_j of a fixed log-spaced node grid: a total
-neutrino mass, a linear power-law amplitude with a random tilt, and a non-linear
-enhancement of the CDM amplitude that grows with time,
+neutrino mass, a linear power-law amplitude with a random tilt, a non-linear change of
+the CDM amplitude that grows with time, and a smooth departure from linear growth of its
+own in every k-bin,
 
-    A_cdm(k, a_i) = D(a_i)/D(a_j) * k^(-1 + tilt) * (1 + eps(k) (D(a_i)/D(a_j))^p),
-    eps(k) = e0 (k/k0)^s / (1 + (k/k0)^s),
+    A_cdm(k, a_i) = g_i k^(-1 + tilt) (1 + eps(k) g_i^p) exp(delta_k (1 - g_i^q)),
+    g_i = D(a_i)/D(a_j),  eps(k) = e0 (k/k0)^s / (1 + (k/k0)^s),
 
-with e0 in [0, 2], k0 log-uniform in [0.05, 1] h/Mpc, s in [1, 3], p in [1, 4]. The
-neutrino amplitude follows the linear CDM one times 1/(1 + k/k_fs)^2 and the stored
-total is (1 - f_nu) CDM + f_nu neutrino, as in synth.history. None of this is the
-method's integral; it only spans the inputs the network will see.
+with e0 uniform in [-0.4, 0] (suppression, as below the mesh scale) for one case in five
+and log-uniform in [0.02, 8] (enhancement, up to the several-fold growth of the
+amplitude beyond the mesh Nyquist frequency late in a run) otherwise, k0 log-uniform in
+[0.05, 1] h/Mpc, s in [1, 3], p in [0.5, 4], q in [0.5, 3] and delta_k
+normal with a scale drawn from [0, 0.05] per case, independent between bins (a particle
+run's measured amplitudes depart from D(a) by a few per cent at low k, differently in
+each bin, from mode coupling and its start-up transients). The neutrino amplitude
+follows the linear CDM one times 1/(1 + k/k_fs)^2 and the stored total is
+(1 - f_nu) CDM + f_nu neutrino, as in synth.history. None of this is the method's
+integral; it only spans the inputs the network will see.
 """
 import numpy as np
 
@@ -18,7 +25,7 @@ from .history import _H0, _e, free_streaming_k, growth
 
 
 def surrogate_batch(k_mean, a_nodes, j, n_boxes, rng, omega_m=0.3, hubble=0.7,
-                    m_range=(0.05, 0.6), n_species=3, growth_nodes=None):
+                    m_range=(0.03, 0.7), n_species=3, growth_nodes=None):
     """n_boxes random cases sharing the current node a_nodes[j].
 
     growth_nodes: optional (D, f) at every node (computed here when not given).
@@ -38,13 +45,17 @@ def surrogate_batch(k_mean, a_nodes, j, n_boxes, rng, omega_m=0.3, hubble=0.7,
     hists, powers = [], []
     for m in masses:
         tilt = rng.uniform(-0.5, 0.5)
-        e0 = rng.uniform(0.0, 2.0)
+        e0 = rng.uniform(-0.4, 0.0) if rng.random() < 0.2 else \
+            float(np.exp(rng.uniform(np.log(0.02), np.log(8.0))))
         k0 = np.exp(rng.uniform(np.log(0.05), np.log(1.0)))
         s = rng.uniform(1.0, 3.0)
-        p = rng.uniform(1.0, 4.0)
+        p = rng.uniform(0.5, 4.0)
+        q = rng.uniform(0.5, 3.0)
+        delta = rng.normal(size=k.shape) * rng.uniform(0.0, 0.05)
         eps = e0 * (kk / k0) ** s / (1.0 + (kk / k0) ** s)
         lin = g[:, None] * kk[None, :] ** (-1.0 + tilt)
-        cdm = lin * (1.0 + eps[None, :] * g[:, None] ** p)
+        cdm = lin * (1.0 + eps[None, :] * g[:, None] ** p) \
+            * np.exp(delta[None, :] * (1.0 - g[:, None] ** q))
         f_nu = m / (93.14 * omega_m * hubble * hubble)
         kfs = free_streaming_k(a, m / n_species, omega_m)[:, None]
         nu = lin / (1.0 + kk[None, :] / kfs) ** 2

@@ -63,7 +63,7 @@ def test_null_context_is_an_error(lib):
 
 
 def test_blob_size(lib):
-    assert binding.pm_nu_surrogate_blob_floats() == 34689 + 4 * 11 + 2
+    assert binding.pm_nu_surrogate_blob_floats() == 35329 + 4 * 16 + 2
 
 
 def test_missing_library_fails_loudly(tmp_path):

@@ -245,7 +245,8 @@ def test_every_launch_mode_matches_oracle(order):
     p = torch.from_numpy(pos).cuda()
     acc = torch.zeros_like(p)
     for dm, im, ib in ((0, 0, 256), (1, 1, 256), (2, 2, 256), (3, 3, 256), (1, 0, 512),
-                       (0, 2, 256), (4, 0, 1024), (5, 1, 256), (6, 1, 256), (6, 0, 256), (7, 1, 256)):
+                       (0, 2, 256), (4, 0, 1024), (5, 1, 256), (6, 1, 256), (6, 0, 256), (7, 1, 256),
+                       (8, 1, 256), (9, 1, 256)):
         binding.pm_nu_set_launch(ctx.h, dm, 256, im, ib)
         ctx.step(p, acc, 0.7)
         torch.cuda.synchronize()
@@ -274,8 +275,9 @@ def test_spectrum_after_deposit_alone_matches_oracle():
     ctx.close()
 
 
-def test_patch_deposit_side_grid_on_crowded_cells():
-    """Deposit mode 6 with 40 chunks of particles packed into a few cells: the coarse cell's
+@pytest.mark.parametrize("deposit_mode", [6, 8])
+def test_patch_deposit_side_grid_on_crowded_cells(deposit_mode):
+    """Deposit mode 6 (and 8, its fused form) with 40 chunks of particles packed into a few cells: the coarse cell's
     patch list overflows, those chunks go through the side grid, and the result still
     matches the oracle; a following deposit of an ordinary lattice finds the side grid
     cleared. In the last input half of the chunks straddle two coarse cells of which only
@@ -292,7 +294,8 @@ def test_patch_deposit_side_grid_on_crowded_cells():
     straddle = crowd.copy()                                 # x nodes 15-17: cells 0 and 1
     straddle[: 20 * 4096, 0] += 20.0
     ctx = PMNu(nm, len(crowd), box, nb, J + 2, [0.3])
-    binding.pm_nu_set_launch(ctx.h, 6, 256, 1, 256)
+    binding.pm_nu_set_launch(ctx.h, deposit_mode, 256, 1, 256)
+    binding.pm_nu_set_keep_density(ctx.h, 1)
     assert binding.pm_nu_side_grid_uses(ctx.h) == 0
     # (five overlapping copies of a lattice also fill the coarse cells' lists: no claim there)
     for pos, side in ((crowd, True), (lattice, None), (straddle, True)):
@@ -567,4 +570,59 @@ def test_advance_matches_oracle(masses, relativistic, deposit_mode):
     # the history is full after (capacity - stored) more steps
     with pytest.raises(binding.PMNuError, match="history"):
         binding.pm_nu_advance(ctx.h, p, v, acc, np.geomspace(0.2, 0.5, 10))
+    ctx.close()
+
+
+@pytest.mark.parametrize("n_mesh,n_side,box", [(32, 32, 128.0), (64, 64, 256.0), (128, 64, 400.0)])
+def test_fused_patch_pass_equals_separate_passes(n_mesh, n_side, box):
+    """Deposit modes 8 and 9 (the coarse-cell sums and the z pass in one kernel) give the
+    modes and forces of modes 6 and 7 (reduce kernel, then the z pass) bit for bit: the
+    sums are exact integers and every later operation is the same. Also with chunks that
+    go through the side grid (random particles appended), with several boxes, and with
+    delta kept for reading back (the same density as mode 6; without asking for it the
+    read-back is refused)."""
+    import torch
+    from paper_1209_0461_amd import PMNu, PMNuError, binding
+    from synth import log_spaced_nodes, synthetic_history
+    nbox, nb, J = 2, 16, 10
+    pos = np.stack([make_inputs(n_side, box, 0.3, 90 + b, extra_random=3000) for b in range(nbox)])
+    ctx = PMNu(n_mesh, pos.shape[1], box, nb, J + 2, [0.3, 0.1])
+    nodes = log_spaced_nodes(0.02, 0.7, J)
+    _, counts, kmean = ctx.bins()
+    for b in range(nbox):
+        ctx.set_history(b, synthetic_history(kmean, np.where(counts > 0, 1.0, 0.0), nodes, 0.3))
+    p = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
+    nmode = n_mesh * n_mesh * (n_mesh // 2 + 1) * 2
+
+    def run(mode, keep):
+        binding.pm_nu_set_launch(ctx.h, mode, 256, 1, 256)
+        binding.pm_nu_set_keep_density(ctx.h, keep)
+        acc = torch.zeros_like(p)
+        ctx.step(p, acc, 0.7)
+        ctx.deposit(p)                              # the modes are read after a deposit
+        modes = [torch.empty(nmode, device="cuda") for _ in range(nbox)]
+        for b in range(nbox):
+            binding.pm_nu_copy_modes(ctx.h, b, modes[b])
+        rho = torch.empty(n_mesh ** 3, device="cuda")
+        if keep or mode < 8:
+            binding.pm_nu_copy_density(ctx.h, 1, rho)
+        else:
+            with pytest.raises(PMNuError) as e:
+                binding.pm_nu_copy_density(ctx.h, 1, rho)
+            assert e.value.code == -4
+            rho = None
+        torch.cuda.synchronize()
+        uses = binding.pm_nu_side_grid_uses(ctx.h)
+        return acc.cpu().numpy(), [m.cpu().numpy() for m in modes], rho, uses
+
+    for sep, fus in ((6, 8), (7, 9)):
+        a0, m0, r0, u0 = run(sep, 0)
+        a1, m1, r1, u1 = run(fus, 1)
+        a2, m2, r2, u2 = run(fus, 0)
+        assert u0 > 0 and u0 == u1 == u2            # the side grid took part, the same way
+        for mm in (m1, m2):
+            assert all(np.array_equal(x, y) for x, y in zip(m0, mm)), (sep, fus)
+        assert np.array_equal(a0, a1) and np.array_equal(a0, a2), (sep, fus)
+        assert torch.equal(r0, r1)
+        assert r2 is None
     ctx.close()

@@ -16,25 +16,29 @@ def _ctx(nbox=1):
     return PMNu(16, 8, 64.0, 8, 16, np.full(nbox, 0.3))
 
 
+NIN, NPARAM = 16, 35329
+
+
 def _unpack(blob):
     """Blob -> oracle params [(W (in, out), b)], feature mean/scale, target mean/scale."""
     o, params = 0, []
-    for fi, fo in ((11, 128), (128, 128), (128, 128), (128, 1)):
+    for fi, fo in ((NIN, 128), (128, 128), (128, 128), (128, 1)):
         w = blob[o:o + fi * fo].astype(np.float64).reshape(fi, fo)
         o += fi * fo
         b = blob[o:o + fo].astype(np.float64)
         o += fo
         params.append((w, b))
-    assert o == 34689
-    mu, sg = blob[o:o + 11].astype(np.float64), blob[o + 11:o + 22].astype(np.float64)
-    ymu, ysg = float(blob[o + 44]), float(blob[o + 45])
+    assert o == NPARAM
+    mu, sg = blob[o:o + NIN].astype(np.float64), blob[o + NIN:o + 2 * NIN].astype(np.float64)
+    ymu, ysg = float(blob[o + 4 * NIN]), float(blob[o + 4 * NIN + 1])
     return params, mu, sg, ymu, ysg
 
 
 def _data(n, seed):
     rng = np.random.default_rng(seed)
-    x = rng.normal(size=(n, 11)) * np.linspace(0.5, 2.0, 11) + np.linspace(-1, 1, 11)
-    y = np.sin(x[:, 0]) + 0.3 * x[:, 1] * x[:, 2] - 0.1 * x[:, 5] ** 2 + 0.05 * x[:, 10]
+    x = rng.normal(size=(n, NIN)) * np.linspace(0.5, 2.0, NIN) + np.linspace(-1, 1, NIN)
+    y = (np.sin(x[:, 0]) + 0.3 * x[:, 1] * x[:, 2] - 0.1 * x[:, 5] ** 2 + 0.05 * x[:, 10]
+         + 0.2 * np.tanh(x[:, 15]))
     return x.astype(np.float32), y.astype(np.float32)
 
 
@@ -53,7 +57,7 @@ def test_gradient_matches_oracle():
     binding.pm_nu_surrogate_init(ctx.h, xd, yd, 123)
     blob = binding.pm_nu_surrogate_save(ctx.h)
     params, mu, sg, ymu, ysg = _unpack(blob)
-    g = torch.zeros(34689, device="cuda")
+    g = torch.zeros(NPARAM, device="cuda")
     loss = binding.pm_nu_surrogate_grad(ctx.h, xd, yd, g)
     xs = _std_inputs(x, mu, sg)
     ts = (y.astype(np.float64) - ymu) / ysg
@@ -82,7 +86,7 @@ def test_gradient_after_training_steps_matches_oracle():
     binding.pm_nu_surrogate_train(ctx.h, xd, yd, 3, 512, 3e-3, 9)
     params, mu, sg, ymu, ysg = _unpack(binding.pm_nu_surrogate_save(ctx.h))
     xs, ys = xd[:160], yd[:160]
-    g = torch.zeros(34689, device="cuda")
+    g = torch.zeros(NPARAM, device="cuda")
     binding.pm_nu_surrogate_grad(ctx.h, xs, ys, g)
     _, ref = mlp.mse_loss_and_grads(params, _std_inputs(x[:160], mu, sg),
                                     (y[:160].astype(np.float64) - ymu) / ysg, bf16=True)
@@ -117,7 +121,7 @@ def test_training_reduces_loss():
     x, y = _data(16384, 4)
     xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
     binding.pm_nu_surrogate_init(ctx.h, xd, yd, 3)
-    g = torch.zeros(34689, device="cuda")
+    g = torch.zeros(NPARAM, device="cuda")
     l0 = binding.pm_nu_surrogate_grad(ctx.h, xd, yd, g)
     l1 = binding.pm_nu_surrogate_train(ctx.h, xd, yd, 30, 1024, 2e-3, 11)
     assert l1 < 0.05 * l0, (l0, l1)
@@ -138,7 +142,7 @@ def test_blob_roundtrip_and_bad_blob():
     binding.pm_nu_surrogate_load(ctx2.h, blob)
     assert np.array_equal(binding.pm_nu_surrogate_save(ctx2.h), blob)
     bad = blob.copy()
-    bad[34689 + 11] = 0.0     # zero feature scale
+    bad[NPARAM + NIN] = 0.0     # zero feature scale
     with pytest.raises(PMNuError):
         binding.pm_nu_surrogate_load(ctx2.h, bad)
     ctx.close()

@@ -14,12 +14,12 @@ BLOB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
 TOL_SUR = 1e-3
 
 
-def _step_state(mass, seed, mode, blob, n_hist=200):
+def _step_state(mass, seed, mode, blob, n_hist=200, a_lo=0.01):
     import torch
     from paper_1209_0461_amd import PMNu, binding
     from synth import log_spaced_nodes, synthetic_history, zeldovich_lattice
     pos = zeldovich_lattice(256, 512.0, 0.3, seed)
-    nodes = log_spaced_nodes(0.01, 1.0, n_hist)
+    nodes = log_spaced_nodes(a_lo, 1.0, n_hist)
     ctx = PMNu(256, pos.shape[0], 512.0, 64, n_hist + 2, [mass], response_mode=mode)
     binding.pm_nu_surrogate_load(ctx.h, blob)
     p = torch.from_numpy(pos).cuda()
@@ -77,10 +77,11 @@ def test_surrogate_mode_forces_close_to_exact(blob):
 
 
 def test_short_history_falls_back_to_exact(blob):
-    """Fewer than 9 stored nodes: the inputs do not exist, the exact integral is used."""
+    """A history reaching less than 2.1 in ln a below its last node: the inputs do not
+    exist, the exact integral is used for every bin."""
     import torch
     from paper_1209_0461_amd import binding
-    ctx, p, acc, counts, _ = _step_state(0.3, 257, 2, blob, n_hist=6)
+    ctx, p, acc, counts, _ = _step_state(0.3, 257, 2, blob, n_hist=12, a_lo=0.2)
     ctx.step(p, acc, 1.0)
     torch.cuda.synchronize()
     exact, sur = binding.pm_nu_get_surrogate_check(ctx.h, 0, 64)

@@ -67,6 +67,46 @@ def test_adam_first_step_moves_by_lr_times_sign():
     assert p[0][1][0] == pytest.approx(0.5 + 0.01, rel=1e-6)
 
 
-def test_layer_sizes_give_34689_parameters():
+def test_layer_sizes_give_35329_parameters():
     n = sum(a * b + b for a, b in zip(mlp.LAYERS[:-1], mlp.LAYERS[1:]))
-    assert n == 34689
+    assert n == 35329
+
+
+def test_features_sample_the_history_at_lags_in_ln_a():
+    """A history linear in ln a is sampled exactly at every lag whatever the node spacing
+    (irregular nodes here); lag 0 is the last stored node itself; the gap input is
+    ln a_now - ln a_{n-1}; a history shorter than the longest lag has no inputs."""
+    rng = np.random.default_rng(3)
+    lna = np.sort(np.concatenate([[np.log(0.01)], rng.uniform(np.log(0.01), np.log(0.9), 60),
+                                  [np.log(0.9)]]))
+    a_nodes = np.exp(lna)
+    k = np.array([0.02, 0.2, 2.0])
+    slope, icpt = np.array([0.8, 1.3, 2.0]), np.array([5.0, 3.0, 1.0])
+    hist = icpt[None, :] + slope[None, :] * lna[:, None]          # linear in ln a
+    pcdm_half = np.array([4.0, 2.0, 0.5])
+    pnu = 0.5 * hist
+    f = mlp.features(k, 1.0, 0.3, a_nodes, hist, pnu, pcdm_half)
+    assert f.shape == (3, 16)
+    assert np.allclose(f[:, 0], np.log(k)) and np.all(f[:, 1] == 0.0) and np.all(f[:, 2] == 0.3)
+    assert np.allclose(f[:, 3], -np.log(0.9), rtol=0, atol=1e-15)
+    assert np.array_equal(f[:, 4], pnu[-1] / pcdm_half)
+    assert np.allclose(f[:, 5], -np.log(0.01), rtol=1e-15)
+    # the kernel argument across the last interval, with s from its closed-form integral
+    from oracle import background as bg
+    from scipy import integrate
+    ds = integrate.quad(lambda a: 1.0 / (a ** 3 * bg.hubble_rate(a, 0.3)), 0.9, 1.0,
+                        epsrel=1e-13)[0]
+    assert np.allclose(f[:, 6], np.log(k * ds * bg.T_NU0 / 0.1), rtol=1e-9)
+    for m, lag in enumerate(mlp.LAGS):
+        want = (icpt + slope * (np.log(0.9) - lag)) / pcdm_half
+        assert np.allclose(f[:, 7 + m], want, rtol=1e-13, atol=0)
+    assert np.array_equal(f[:, 7], hist[-1] / pcdm_half)
+    # the same linear history on a regular grid gives the same inputs
+    reg = np.linspace(np.log(0.01), np.log(0.9), 25)
+    lin = icpt + slope * reg[:, None]
+    f2 = mlp.features(k, 1.0, 0.3, np.exp(reg), lin, 0.5 * lin, pcdm_half)
+    assert np.allclose(f2, f, rtol=1e-12, atol=1e-14)
+    # not enough history: 2.0 in ln a below the last node
+    short = np.linspace(np.log(0.9) - 2.0, np.log(0.9), 30)
+    assert mlp.features(k, 1.0, 0.3, np.exp(short), np.ones((30, 3)), np.ones((30, 3)),
+                        pcdm_half) is None
