@@ -151,12 +151,17 @@ __global__ __launch_bounds__(NT) void fwd_z_kernel(const void* __restrict__ in,
 // 8 and 9): the per-patch fixed-point sums are added up for a slab of the mesh and
 // transformed along z before delta ever reaches HBM. One workgroup per (x-plane, group of
 // CB = 16 y-rows, box): its slab is one x-plane of a column of N / CB coarse cells.
-//   1. Per coarse cell, the registered patch with the largest overlap of the slab (its
-//      "home") is found; every thread then loads the CB z-nodes of its (row, cell) runs from
-//      the home patch into registers.
-//   2. The other overlaps, cut into boxes (up to two periodic pieces per axis), are added
-//      into an LDS copy of the slab with 64-bit LDS atomics, GC cells at a time (the piece
-//      list of GC cells fits in LDS whatever the registry holds).
+//   1. Every cell's registry count and list row are loaded together (a half-wave per cell,
+//      all cells in one round); per cell the patch with the largest overlap of the slab
+//      (its "home") is chosen, and every other overlap is counted in boxes (up to two
+//      periodic pieces per axis) and nodes, kept per list entry in LDS.
+//   2. Each thread loads the CB z-nodes of its (row, cell) runs from their home patches into
+//      registers; meanwhile one workgroup-wide scan turns the entries' piece and node
+//      counts into offsets, the entries write their pieces into one flat list, and every
+//      thread walks that list's nodes (a bisection finds a node's piece), all of its loads
+//      issued before any add, into an LDS copy of the slab with 64-bit LDS atomics. The
+//      list holds kPieces; a slab with more (crowded registries) takes several windows of
+//      whole entries.
 //   3. Registers + LDS (+ the side grid when anything went there, which is then cleared) give
 //      the exact integer sum of each node, rounded once to delta = rho / rho_bar - 1 in FP32;
 //      the slab's 16 rows become 8 complex lines (rows 2p and 2p + 1 as real and imaginary
@@ -167,29 +172,37 @@ __global__ __launch_bounds__(NT) void fwd_z_kernel(const void* __restrict__ in,
 // The registry counts and the side-grid count are reset by the next pass (fwd_y): the other
 // x-planes of a cell read them until this kernel ends. Workgroups of one cell column (the
 // 16 x-planes that read the same patches) run on one XCD, so its L2 serves their halos.
+constexpr int kPatchFwdNT = 512;   // threads per workgroup of patch_fwd_z_kernel
 template <int N>
-__global__ __launch_bounds__(NT) void patch_fwd_z_kernel(
+__global__ __launch_bounds__(kPatchFwdNT) void patch_fwd_z_kernel(
     const unsigned long long* __restrict__ patches, int pcap, const int* __restrict__ reg_count,
     const int4* __restrict__ reg_list, unsigned long long* __restrict__ rho_fb,
     const int* __restrict__ n_fb, float2* __restrict__ out, const float2* __restrict__ twg,
     double scale, float* __restrict__ delta_out) {
+  constexpr int NT = kPatchFwdNT;                  // this kernel's workgroup size
   constexpr int CB = 16, NC = N / CB, TY = CB, NL = TY / 2, ES = NL + 1, NK = Shape<N>::NK;
   constexpr int RUNS = TY * NC;                    // (row, cell) runs of CB z-nodes
-  constexpr int RPT = (RUNS + NT - 1) / NT;        // runs per thread
-  constexpr int GC = N >= 512 ? 1 : 2;             // cells per piece list
-  constexpr int kPieces = GC * kPatchList * 8, kBatch = 8;
-  static_assert(NC >= 2 && RUNS % NT == 0 || RUNS < NT, "runs cover the threads evenly");
+  constexpr int RG = NT / CB;                      // runs a workgroup covers at once
+  constexpr int JPT = RUNS / RG;                   // nodes per thread: z = tid % CB of runs
+                                                   // r = tid / CB + RG j, j < JPT
+  constexpr int NE = NC * kPatchList;              // list entries of the column's cells
+  constexpr int EPT = (NE + NT - 1) / NT;          // entries per thread in the scan
+  constexpr int kPieces = 256, kBatch = 8;         // piece list capacity (power of two)
+  static_assert(NC >= 2 && RUNS % RG == 0, "runs cover the threads evenly");
+  static_assert(NE % NT == 0 || NE < NT, "entries cover the threads evenly");
   static_assert(N * ES * sizeof(float2) <= TY * N * sizeof(unsigned long long),
                 "the complex lines fit over the sums");
   __shared__ unsigned long long s_acc[TY * N];     // [y][z]; later the complex lines
   __shared__ float2 tw[N];
   __shared__ int4 s_home[NC];                      // chunk < 0: no patch
+  __shared__ int4 s_ent[NE];                       // list entries (chunk < 0: none)
+  __shared__ int s_np[NE + 1], s_ni[NE + 1];       // their pieces and nodes -> offsets
   __shared__ int p_off[kPieces + 1];
   __shared__ int p_dim[kPieces];
   __shared__ long long p_src[kPieces];
-  __shared__ int p_str[kPieces];
   __shared__ int p_dst[kPieces];
-  __shared__ int s_total;
+  __shared__ int s_wsum[2][NT / 64];
+  __shared__ int s_win[2];                         // current window: first, end entry
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // block -> (box, cell column, x within the column, y group): consecutive dispatch ids go
   // to the 8 XCDs in turn, so each XCD takes a contiguous run of virtual ids instead
@@ -203,90 +216,39 @@ __global__ __launch_bounds__(NT) void patch_fwd_z_kernel(
   const int x = cx * CB + xi, y0 = cy * CB;
   const int64_t cells = static_cast<int64_t>(NC) * NC * NC;
   const int64_t cell0 = box * cells + (static_cast<int64_t>(cx) * NC + cy) * NC;  // cz = 0
+  // overlap of a registry entry with the slab's part of cell c
+  auto pieces_of = [&](const int4& en, int c, Pieces& px, Pieces& py, Pieces& pz) {
+    px = overlap(en.y & 1023, en.z & 1023, x, 1, N);
+    py = overlap((en.y >> 10) & 1023, (en.z >> 10) & 1023, y0, CB, N);
+    pz = overlap(en.y >> 20, en.z >> 20, c * CB, CB, N);
+  };
   load_twiddles<N, NT>(tw, twg);
   for (int i = tid; i < TY * N; i += NT) s_acc[i] = 0ull;
-  // 1. homes: a half-wave per cell, its lanes over the cell's list
-  for (int c0 = 2 * wave; c0 < NC; c0 += 2 * (NT / 64)) {
-    const int c = c0 + (lane >> 5), e = lane & 31;
-    int key = -1;
-    int4 listed = make_int4(-1, 0, 0, 0);
-    if (c < NC) {
-      const int cnt = min(reg_count[cell0 + c], kPatchList);
-      if (e < cnt) {
-        listed = reg_list[(cell0 + c) * kPatchList + e];
-        const Pieces px = overlap(listed.y & 1023, listed.z & 1023, x, 1, N);
-        const Pieces py = overlap((listed.y >> 10) & 1023, (listed.z >> 10) & 1023, y0, CB, N);
-        const Pieces pz = overlap(listed.y >> 20, listed.z >> 20, c * CB, CB, N);
-        int lx = 0, ly = 0, lz = 0;
+  // 1. every cell's count and list row in one round: half-wave h of wave w takes the cells
+  //    c = 2 w + h + 2 (NT / 64) i
+  {
+    constexpr int CPR = 2 * (NT / 64);             // cells per round
+    constexpr int ROUNDS = (NC + CPR - 1) / CPR;
+    int cnt[ROUNDS];
+    int4 listed[ROUNDS];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          lx += q < px.cnt ? px.len[q] : 0;
-          ly += q < py.cnt ? py.len[q] : 0;
-          lz += q < pz.cnt ? pz.len[q] : 0;
-        }
-        const int vol = lx * ly * lz;
-        key = vol > 0 ? (vol << 6) | (63 - lane) : -1;
+    for (int i = 0; i < ROUNDS; ++i) {
+      const int c = 2 * wave + (lane >> 5) + CPR * i;
+      cnt[i] = 0;
+      listed[i] = make_int4(-1, 0, 0, 0);
+      if (c < NC) {
+        cnt[i] = reg_count[cell0 + c];
+        listed[i] = reg_list[(cell0 + c) * kPatchList + (lane & 31)];
       }
     }
 #pragma unroll
-    for (int off = 16; off > 0; off >>= 1) key = max(key, __shfl_xor(key, off, 64));
-    if (c < NC) {
-      if (e == 0) s_home[c] = make_int4(-1, 0, 0, 0);
-      if (key >= 0 && lane == 63 - (key & 63)) s_home[c] = listed;
-    }
-  }
-  __syncthreads();
-  // the home runs' loads go out first: run r = cell * TY + row (rows of a cell on
-  // neighbouring lanes read neighbouring patch rows)
-  unsigned long long hv[RPT][CB];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int r = tid + q * NT, c = r / TY, row = r % TY;
-#pragma unroll
-    for (int z = 0; z < CB; ++z) hv[q][z] = 0ull;
-    const int4 hl = r < RUNS ? s_home[c] : make_int4(-1, 0, 0, 0);
-    if (hl.x < 0) continue;
-    const int ex = hl.z & 1023, ey = (hl.z >> 10) & 1023, ez = hl.z >> 20;
-    const Pieces px = overlap(hl.y & 1023, ex, x, 1, N);
-    const Pieces py = overlap((hl.y >> 10) & 1023, ey, y0, CB, N);
-    const Pieces pz = overlap(hl.y >> 20, ez, c * CB, CB, N);
-    int lx = -1, ly = -1;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      if (k < px.cnt && px.cl[k] == 0) lx = px.pl[k];
-      if (k < py.cnt && row >= py.cl[k] && row < py.cl[k] + py.len[k])
-        ly = py.pl[k] + row - py.cl[k];
-    }
-    if (lx < 0 || ly < 0) continue;
-    const unsigned long long* src =
-        patches + static_cast<int64_t>(hl.x) * pcap + (static_cast<int64_t>(lx) * ey + ly) * ez;
-#pragma unroll
-    for (int z = 0; z < CB; ++z) {
-      int lz = -1;
-#pragma unroll
-      for (int k = 0; k < 2; ++k)
-        if (k < pz.cnt && z >= pz.cl[k] && z < pz.cl[k] + pz.len[k]) lz = pz.pl[k] + z - pz.cl[k];
-      if (lz >= 0) hv[q][z] = src[lz];
-    }
-  }
-  // 2. the other overlaps, GC cells at a time
-  for (int g0 = 0; g0 < NC; g0 += GC) {
-    if (wave == 0) {
-      // lanes 32 h .. 32 h + 31: the list of cell g0 + h (h < GC)
-      const int h = lane >> 5, e = lane & 31, c = g0 + h;
-      const bool cell_on = h < GC && c < NC;
-      const int cnt = cell_on ? min(reg_count[cell0 + c], kPatchList) : 0;
-      const int4 listed = e < cnt ? reg_list[(cell0 + c) * kPatchList + e] : make_int4(-1, 0, 0, 0);
-      const int4 home = cell_on ? s_home[c] : make_int4(-1, 0, 0, 0);
-      const bool other = e < cnt && !(listed.x == home.x && listed.y == home.y);
-      Pieces px, py, pz;
-      px.cnt = py.cnt = pz.cnt = 0;
-      int vol = 0;
-      const int ex = listed.z & 1023, ey = (listed.z >> 10) & 1023, ez = listed.z >> 20;
-      if (other) {
-        px = overlap(listed.y & 1023, ex, x, 1, N);
-        py = overlap((listed.y >> 10) & 1023, ey, y0, CB, N);
-        pz = overlap(listed.y >> 20, ez, c * CB, CB, N);
+    for (int i = 0; i < ROUNDS; ++i) {
+      const int c = 2 * wave + (lane >> 5) + CPR * i, e = lane & 31;
+      const bool mine = c < NC && e < min(cnt[i], kPatchList);
+      int vol = 0, np = 0;
+      if (mine) {
+        Pieces px, py, pz;
+        pieces_of(listed[i], c, px, py, pz);
         int lx = 0, ly = 0, lz = 0;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -295,45 +257,153 @@ __global__ __launch_bounds__(NT) void patch_fwd_z_kernel(
           lz += q < pz.cnt ? pz.len[q] : 0;
         }
         vol = lx * ly * lz;
+        np = px.cnt * py.cnt * pz.cnt;
       }
-      const bool has = vol > 0;
-      const int np_mine = has ? px.cnt * py.cnt * pz.cnt : 0;
-      int inc_p = np_mine, inc_v = has ? vol : 0;
+      // home: the largest volume, ties to the lowest lane
+      int key = vol > 0 ? (vol << 6) | (63 - lane) : -1;
 #pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const int tp = __shfl_up(inc_p, off, 64), tv = __shfl_up(inc_v, off, 64);
-        if (lane >= off) {
-          inc_p += tp;
-          inc_v += tv;
-        }
+      for (int off = 16; off > 0; off >>= 1) key = max(key, __shfl_xor(key, off, 64));
+      const bool home = key >= 0 && lane == 63 - (key & 63);
+      if (c < NC) {
+        if (e == 0 && key < 0) s_home[c] = make_int4(-1, 0, 0, 0);
+        if (home) s_home[c] = listed[i];
+        const int slot = c * kPatchList + e;
+        const bool other = mine && vol > 0 && !home;
+        s_ent[slot] = other ? listed[i] : make_int4(-1, 0, 0, 0);
+        s_np[slot] = other ? np : 0;
+        s_ni[slot] = other ? vol : 0;
       }
-      const int n_pieces = __shfl(inc_p, 63, 64);
-      if (lane == 63) s_total = inc_v;
-      int slot = inc_p - np_mine, item = inc_v - (has ? vol : 0);
-      if (has) {
-        const long long src0 = static_cast<long long>(listed.x) * pcap;
+    }
+  }
+  __syncthreads();
+  // 2a. the home patches' loads go out first: run r = cell * TY + row; lanes of a wave
+  //     take consecutive z of four runs (rows of one cell: neighbouring patch rows)
+  const int zt = tid % CB;
+  unsigned long long hv[JPT];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+  for (int j = 0; j < JPT; ++j) {
+    const int r = tid / CB + RG * j, c = r / TY, row = r % TY;
+    hv[j] = 0ull;
+    const int4 hl = s_home[c];
+    if (hl.x < 0) continue;
+    const int ey = (hl.z >> 10) & 1023, ez = hl.z >> 20;
+    Pieces px, py, pz;
+    pieces_of(hl, c, px, py, pz);
+    int lx = -1, ly = -1, lz = -1;
 #pragma unroll
-          for (int b = 0; b < 2; ++b)
+    for (int k = 0; k < 2; ++k) {
+      if (k < px.cnt && px.cl[k] == 0) lx = px.pl[k];
+      if (k < py.cnt && row >= py.cl[k] && row < py.cl[k] + py.len[k])
+        ly = py.pl[k] + row - py.cl[k];
+      if (k < pz.cnt && zt >= pz.cl[k] && zt < pz.cl[k] + pz.len[k]) lz = pz.pl[k] + zt - pz.cl[k];
+    }
+    if (lx >= 0 && ly >= 0 && lz >= 0)
+      hv[j] = patches[static_cast<int64_t>(hl.x) * pcap +
+                      (static_cast<int64_t>(lx) * ey + ly) * ez + lz];
+  }
+  // 2b. exclusive scan of the entries' piece and node counts (thread t: EPT consecutive
+  //     entries), s_np / s_ni become offsets, [NE] the totals
+  {
+    int lp[EPT], li[EPT], sp = 0, si = 0;
 #pragma unroll
-            for (int cc = 0; cc < 2; ++cc) {
-              if (a >= px.cnt || b >= py.cnt || cc >= pz.cnt) continue;
-              const int Lx = px.len[a], Ly = py.len[b], Lz = pz.len[cc];
-              p_off[slot] = item;
-              p_dim[slot] = Lz | (Ly << 8);
-              p_src[slot] = src0 + (static_cast<long long>(px.pl[a]) * ey + py.pl[b]) * ez + pz.pl[cc];
-              p_str[slot] = ez | ((ey * ez) << 10);
-              // LDS node (y, z) of the piece's first node; x is the slab's plane (Lx = 1)
-              p_dst[slot] = py.cl[b] * N + c * CB + pz.cl[cc];
-              item += Lx * Ly * Lz;
-              ++slot;
-            }
+    for (int k = 0; k < EPT; ++k) {
+      const int en = tid * EPT + k;
+      lp[k] = en < NE ? s_np[en] : 0;
+      li[k] = en < NE ? s_ni[en] : 0;
+      sp += lp[k];
+      si += li[k];
+    }
+    int ip = sp, ii = si;                          // inclusive scan over the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int tp = __shfl_up(ip, off, 64), ti = __shfl_up(ii, off, 64);
+      if (lane >= off) {
+        ip += tp;
+        ii += ti;
       }
-      for (int i = n_pieces + lane; i <= kPieces; i += 64) p_off[i] = 0x7fffffff;
+    }
+    if (lane == 63) {
+      s_wsum[0][wave] = ip;
+      s_wsum[1][wave] = ii;
     }
     __syncthreads();
-    const int total = s_total;
+    int bp = 0, bi = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+      if (w < wave) {
+        bp += s_wsum[0][w];
+        bi += s_wsum[1][w];
+      }
+    }
+    int op = bp + ip - sp, oi = bi + ii - si;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int en = tid * EPT + k;
+      if (en < NE) {
+        s_np[en] = op;
+        s_ni[en] = oi;
+      }
+      op += lp[k];
+      oi += li[k];
+    }
+    if (tid == NT - 1) {
+      s_np[NE] = op;
+      s_ni[NE] = oi;
+    }
+    if (tid == 0) s_win[1] = 0;
+  }
+  __syncthreads();
+  // 2c. windows of whole entries whose pieces fit the list (one window unless crowded)
+  while (true) {
+    if (tid == 0) {
+      // the last entry boundary e1 with pieces [e0, e1) <= kPieces (offsets are monotone)
+      const int e0 = s_win[1], lim = s_np[e0] + kPieces;
+      int e1 = NE;
+      if (s_np[NE] > lim) {
+        int lo = e0, hi = NE;                    // s_np[lo] <= lim < s_np[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_np[mid] <= lim) lo = mid;
+          else hi = mid;
+        }
+        e1 = lo;
+      }
+      s_win[0] = e0;
+      s_win[1] = e1;
+    }
+    __syncthreads();
+    const int e0 = s_win[0], e1 = s_win[1];
+    if (e0 >= NE) break;
+    const int pbase = s_np[e0], ibase = s_ni[e0];
+    const int n_pieces = s_np[e1] - pbase, total = s_ni[e1] - ibase;
+    for (int en = e0 + tid; en < e1; en += NT) {
+      const int4 en4 = s_ent[en];
+      if (en4.x < 0) continue;
+      const int c = en / kPatchList;
+      Pieces px, py, pz;
+      pieces_of(en4, c, px, py, pz);
+      const int ey = (en4.z >> 10) & 1023, ez = en4.z >> 20;
+      const long long src0 = static_cast<long long>(en4.x) * pcap;
+      int slot = s_np[en] - pbase, item = s_ni[en] - ibase;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int cc = 0; cc < 2; ++cc) {
+            if (a >= px.cnt || b >= py.cnt || cc >= pz.cnt) continue;
+            const int Ly = py.len[b], Lz = pz.len[cc];   // Lx = 1: the slab is one plane
+            p_off[slot] = item;
+            p_dim[slot] = Lz | (ez << 8);
+            p_src[slot] = src0 + (static_cast<long long>(px.pl[a]) * ey + py.pl[b]) * ez + pz.pl[cc];
+            // LDS node (y, z) of the piece's first node
+            p_dst[slot] = py.cl[b] * N + c * CB + pz.cl[cc];
+            item += Ly * Lz;
+            ++slot;
+          }
+    }
+    for (int i = n_pieces + tid; i <= kPieces; i += NT) p_off[i] = 0x7fffffff;
+    __syncthreads();
     for (int base = 0; base < total; base += kBatch * NT) {
       unsigned long long v[kBatch];
       int li[kBatch];
@@ -343,61 +413,48 @@ __global__ __launch_bounds__(NT) void patch_fwd_z_kernel(
         li[r] = -1;
         v[r] = 0ull;
         if (i < total) {
-          int e = 0;                              // the piece: last offset <= i
+          int pe = 0;                             // the piece: last offset <= i
 #pragma unroll
           for (int step = kPieces / 2; step > 0; step >>= 1)
-            if (p_off[e + step] <= i) e += step;
-          const int rem = i - p_off[e];
-          const int dim = p_dim[e], str = p_str[e];
-          const int Lz = dim & 255;
+            if (p_off[pe + step] <= i) pe += step;
+          const int rem = i - p_off[pe];
+          const int dim = p_dim[pe], Lz = dim & 255, ez = dim >> 8;
           // exact: rem < 256 and Lz <= 16 (x is one plane, so rem = y Lz + z)
           const int y = static_cast<int>((rem + 0.5f) * (1.0f / Lz));
           const int z = rem - y * Lz;
-          v[r] = patches[p_src[e] + y * (str & 1023) + z];
-          li[r] = p_dst[e] + y * N + z;
+          v[r] = patches[p_src[pe] + y * ez + z];
+          li[r] = p_dst[pe] + y * N + z;
         }
       }
 #pragma unroll
       for (int r = 0; r < kBatch; ++r)
         if (li[r] >= 0) atomicAdd(&s_acc[li[r]], v[r]);
     }
-    __syncthreads();
+    __syncthreads();                               // before the next window's list
   }
   // 3. exact sums -> delta, then the z transform over the same LDS
   const bool fold = *n_fb > 0;
   const int64_t m = static_cast<int64_t>(N) * N * N;
-  float dv[RPT][CB];
+  float dv[JPT];
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int r = tid + q * NT, c = r / TY, row = r % TY;
-    if (r >= RUNS) continue;
-#pragma unroll
-    for (int z = 0; z < CB; ++z) {
-      unsigned long long val = hv[q][z] + s_acc[row * N + c * CB + z];
-      if (fold) {
-        const int64_t node = box * m + (static_cast<int64_t>(x) * N + y0 + row) * N + c * CB + z;
-        val += rho_fb[node];
-        rho_fb[node] = 0ull;
-      }
-      dv[q][z] = static_cast<float>(static_cast<double>(val) * scale - 1.0);
+  for (int j = 0; j < JPT; ++j) {
+    const int r = tid / CB + RG * j, c = r / TY, row = r % TY;
+    unsigned long long val = hv[j] + s_acc[row * N + c * CB + zt];
+    const int64_t node = box * m + (static_cast<int64_t>(x) * N + y0 + row) * N + c * CB + zt;
+    if (fold) {
+      val += rho_fb[node];
+      rho_fb[node] = 0ull;
     }
-    if (delta_out) {                               // kept for reading the density back
-      float4* dst = reinterpret_cast<float4*>(
-          delta_out + box * m + (static_cast<int64_t>(x) * N + y0 + row) * N + c * CB);
-#pragma unroll
-      for (int z = 0; z < CB; z += 4)
-        dst[z / 4] = make_float4(dv[q][z], dv[q][z + 1], dv[q][z + 2], dv[q][z + 3]);
-    }
+    dv[j] = static_cast<float>(static_cast<double>(val) * scale - 1.0);
+    if (delta_out) delta_out[node] = dv[j];        // kept for reading the density back
   }
   __syncthreads();
   float2* lds = reinterpret_cast<float2*>(s_acc);
   float* ldsf = reinterpret_cast<float*>(s_acc);
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int r = tid + q * NT, c = r / TY, row = r % TY;
-    if (r >= RUNS) continue;
-#pragma unroll
-    for (int z = 0; z < CB; ++z) ldsf[((c * CB + z) * ES + (row >> 1)) * 2 + (row & 1)] = dv[q][z];
+  for (int j = 0; j < JPT; ++j) {
+    const int r = tid / CB + RG * j, c = r / TY, row = r % TY;
+    ldsf[((c * CB + zt) * ES + (row >> 1)) * 2 + (row & 1)] = dv[j];
   }
   __syncthreads();
   fft_lines<N, NL, NT, -1>(lds, tw);
@@ -416,8 +473,6 @@ __global__ __launch_bounds__(NT) void patch_fwd_z_kernel(
   }
 }
 
-// in: rows of [box][x][kz] (flattened, NL consecutive rows per workgroup);
-// out: the same rows at [box][kz][x].
 // After the fused patch pass (patch_fwd_z_kernel) it also does the patch registry's
 // end-of-step work that fwd_z does otherwise: reset (n_fb: this step's side-grid count
 // into the running total) and clear (the registry counts), when given.
@@ -975,8 +1030,8 @@ template <int N> struct PatchFwdZ {
       return hipErrorInvalidValue;                 // the fused pass needs N / 16 >= 2 cells
     } else {
       const dim3 grid(static_cast<unsigned>(N / 16 * N), nbox);
-      hipLaunchKernelGGL(patch_fwd_z_kernel<N>, grid, dim3(NT), 0, s, patches, pcap, reg_count,
-                         reg_list, rho_fb, n_fb, out, tw, scale, delta_out);
+      hipLaunchKernelGGL(patch_fwd_z_kernel<N>, grid, dim3(kPatchFwdNT), 0, s, patches, pcap,
+                         reg_count, reg_list, rho_fb, n_fb, out, tw, scale, delta_out);
       return hipGetLastError();
     }
   }
