@@ -28,7 +28,7 @@ STAGE_OF = {
     "inv_x_kernel": "inv_x_green", "inv_y_kernel": "fft_inv_y", "inv_z_kernel": "fft_inv_z",
     "interp_kernel": "cic_interp", "interp_tiled_kernel": "cic_interp",
     "deposit_patch_kernel": "cic_deposit", "patch_reduce_kernel": "patch_reduce",
-    "kick_drift_kernel": "kick_drift",
+    "kick_drift_kernel": "kick_drift", "patch_fwd_z_kernel": "patch_fwd_z",
 }
 
 

@@ -177,6 +177,7 @@ int prepare_time_grid(Ctx& c, double a_now) {
   PMNU_HIP(hipEventSynchronize(c.ev_tg));     // the staging's previous upload has run
   double* ds_all = c.h_tg;
   double* w_all = c.h_tg + c.nbox * qcap;
+  double* l2_all = c.h_tg + 2 * c.nbox * qcap;
   std::vector<double> a_last(Q), seg_last(Q), hinv_last(Q);
   for (int b = 0; b < c.nbox; ++b) {
     const std::vector<double>& nd = all_nodes[b];
@@ -210,6 +211,10 @@ int prepare_time_grid(Ctx& c, double a_now) {
     double* wb = w_all + b * qcap;
     assemble_time_grid(bg, nd.data(), n, Q, pref, cc.seg.data(), cc.hinv.data(),
                        seg_last.data(), hinv_last.data(), dsb, wb);
+    // log2 of each s difference, for the fit's fractional power (0 where ds = 0: the
+    // fit's x^4.1811 term is then 0 whatever this value)
+    double* l2b = l2_all + b * qcap;
+    for (int q = 0; q < nq; ++q) l2b[q] = dsb[q] > 0.0 ? std::log2(dsb[q]) : 0.0;
     RespBox& rb = c.h_resp[b];
     rb = RespBox();
     rb.f_nu = c.f_nu[b];
@@ -262,6 +267,7 @@ int prepare_time_grid(Ctx& c, double a_now) {
   const size_t bytes = c.nbox * qcap * sizeof(double);
   PMNU_HIP(hipMemcpyAsync(c.tg_ds, ds_all, bytes, hipMemcpyHostToDevice, c.stream));
   PMNU_HIP(hipMemcpyAsync(c.tg_w, w_all, bytes, hipMemcpyHostToDevice, c.stream));
+  PMNU_HIP(hipMemcpyAsync(c.tg_l2, l2_all, bytes, hipMemcpyHostToDevice, c.stream));
   PMNU_HIP(hipMemcpyAsync(c.d_resp, c.h_resp, c.nbox * sizeof(RespBox), hipMemcpyHostToDevice,
                           c.stream));
   PMNU_HIP(hipEventRecord(c.ev_tg, c.stream));
@@ -351,7 +357,7 @@ int do_response_mode(Ctx& c, double a_now, int mode) {
   if (mode == 0) {
     TIMED(c, ST_RESPONSE,
           launch_response(c.d_resp, c.bin_partial, c.n_partial, c.d_counts, c.d_kmean,
-                          c.hist_pm, c.hist_pnu, c.ic_pnu, c.ic_theta, c.tg_ds, c.tg_w, c.B,
+                          c.hist_pm, c.hist_pnu, c.ic_pnu, c.ic_theta, c.tg_ds, c.tg_l2, c.tg_w, c.B,
                           c.Jcap, c.qcap, c.Q, c.cfg.iterations, norm, c.nbox, c.pcdm, c.pnu,
                           c.ratio, c.stream, response_threads(c.B, c.nbox)));
   } else {
@@ -411,7 +417,7 @@ void free_ctx(Ctx* c) {
                   c->bin_partial,
                   c->bin_of_n2, c->d_counts, c->d_kmean, c->d_lnk, c->d_nonempty, c->pcdm, c->pnu,
                   c->ratio, c->hist_pm, c->hist_pnu, c->ic_pnu, c->ic_theta, c->tg_ds,
-                  c->tg_w, c->d_resp, c->rtable, c->tw, c->inv_w2, c->d_flags, c->patches,
+                  c->tg_l2, c->tg_w, c->d_resp, c->rtable, c->tw, c->inv_w2, c->d_flags, c->patches,
                   c->reg_count, c->reg_list, c->rho_fb, c->n_fb,
                   c->delta, c->d_kd};
   for (void* p : bufs)
@@ -535,6 +541,7 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   ALLOC(c->ic_pnu, nb * kMaxSpecies * B);
   ALLOC(c->ic_theta, nb * B);
   ALLOC(c->tg_ds, nb * c->qcap);
+  ALLOC(c->tg_l2, nb * c->qcap);
   ALLOC(c->tg_w, nb * c->qcap);
   ALLOC(c->d_resp, nb);
   ALLOC(c->rtable, nb * (static_cast<size_t>(c->n2max) + 1));
@@ -553,7 +560,7 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   }
   ALLOC(c->d_kd, 2 * nb);
 #undef ALLOC
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_tg), 2 * nb * c->qcap * sizeof(double)) !=
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_tg), 3 * nb * c->qcap * sizeof(double)) !=
           hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->h_resp), nb * sizeof(RespBox)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->h_kd), 2 * nb * sizeof(double)) != hipSuccess ||
@@ -562,7 +569,7 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
     free_ctx(c);
     return set_error(PM_NU_ENOMEM, "pinned staging or events could not be created");
   }
-  std::memset(c->h_tg, 0, 2 * nb * c->qcap * sizeof(double));
+  std::memset(c->h_tg, 0, 3 * nb * c->qcap * sizeof(double));
   c->tgc.resize(c->nbox);
   build_bins(*c);
   if (c->nonempty.empty()) {

@@ -393,25 +393,42 @@ __device__ __forceinline__ double gather_value(const RespBox* __restrict__ bxp,
   }
 }
 
+// Input i (FP64, before the rounding to FP32), one input per call so that the lanes of a
+// wave can form the inputs of a row together
+__device__ __forceinline__ double feature_value(int i, double k, double pcdm_half,
+                                                const double* g) {
+  switch (i) {
+    case 0: return log(k);
+    case 1: return g[kGLnA];
+    case 2: return g[kGM];
+    case 3: return g[kGGap];
+    case 4: return g[kGPn] / pcdm_half;
+    case 5: return g[kGLnA0];
+    case 6: return log(k) + g[kGLnX0];
+    default: {
+      const int m = i - 7;
+      const double t = g[kGT + m];
+      return ((1.0 - t) * g[kGLo + m] + t * g[kGHi + m]) / pcdm_half;
+    }
+  }
+}
+
+// whether input i's value keeps the row in the network's domain (input 6, the
+// free-streaming argument across the last interval, at most kSurXLastMax)
+__device__ __forceinline__ bool feature_in_domain(int i, double v) {
+  return i != 6 || v <= kSurXLastMax;
+}
+
 __device__ __forceinline__ bool finish_features(double k, double pcdm_half, const double* g,
                                                 float* f) {
   if (!(pcdm_half > 0.0)) return false;
-  const double lnk = log(k);
-  const double lnx = lnk + g[kGLnX0];
-  if (!(lnx <= kSurXLastMax)) return false;
-  f[0] = static_cast<float>(lnk);
-  f[1] = static_cast<float>(g[kGLnA]);
-  f[2] = static_cast<float>(g[kGM]);
-  f[3] = static_cast<float>(g[kGGap]);
-  f[4] = static_cast<float>(g[kGPn] / pcdm_half);
-  f[5] = static_cast<float>(g[kGLnA0]);
-  f[6] = static_cast<float>(lnx);
-#pragma unroll
-  for (int m = 0; m < kSurLags; ++m) {
-    const double t = g[kGT + m];
-    f[7 + m] = static_cast<float>(((1.0 - t) * g[kGLo + m] + t * g[kGHi + m]) / pcdm_half);
+  bool in = true;
+  for (int i = 0; i < kSurIn; ++i) {
+    const double v = feature_value(i, k, pcdm_half, g);
+    in = in && feature_in_domain(i, v);
+    f[i] = static_cast<float>(v);
   }
-  return true;
+  return in;
 }
 
 // The inputs of one (box, bin) in one thread (training rows)
@@ -428,16 +445,6 @@ __device__ __forceinline__ bool make_features(const RespBox* __restrict__ bxp, d
 __device__ __forceinline__ double approx_factor(double k, double kfs) {
   const double t = 1.0 + k / kfs;
   return 1.0 / (t * t);
-}
-
-// lo, hi: the training set's minimum and maximum of each input
-__device__ __forceinline__ bool in_range(const float* lo, const float* hi, const float* f) {
-  bool in = true;
-  for (int i = 0; i < kSurIn; ++i) {
-    const float mg = 0.05f * (hi[i] - lo[i]);
-    in = in && f[i] >= lo[i] - mg && f[i] <= hi[i] + mg;
-  }
-  return in;
 }
 
 __global__ void pack_weights_kernel(const float* __restrict__ P, unsigned short* __restrict__ Q) {
@@ -581,10 +588,11 @@ __global__ __launch_bounds__(RT) void surrogate_response_kernel(
     const double* __restrict__ counts, const double* __restrict__ kmean,
     double* __restrict__ hist_pm, double* __restrict__ hist_pnu,
     const double* __restrict__ ic_pnu, const double* __restrict__ ic_theta,
-    const double* __restrict__ tg_ds, const double* __restrict__ tg_w, int nbins, int jcap,
-    int qcap, int q_sub, int iterations, double norm, double* __restrict__ pcdm_out,
-    double* __restrict__ pnu_out, double* __restrict__ ratio_out, double* __restrict__ sur_r,
-    double* __restrict__ chk_exact, double* __restrict__ chk_sur) {
+    const double* __restrict__ tg_ds, const double* __restrict__ tg_l2,
+    const double* __restrict__ tg_w, int nbins, int jcap, int qcap, int q_sub, int iterations,
+    double norm, double* __restrict__ pcdm_out, double* __restrict__ pnu_out,
+    double* __restrict__ ratio_out, double* __restrict__ sur_r, double* __restrict__ chk_exact,
+    double* __restrict__ chk_sur) {
   __shared__ double red[2 * RT / 64];
   __shared__ float xs[kSurIn];
   __shared__ float h0[128], h1[128];
@@ -622,14 +630,24 @@ __global__ __launch_bounds__(RT) void surrogate_response_kernel(
     if (tid < kGCount) gsh[tid] = gv;
     __syncthreads();
   }
-  if (tid == 0) {
-    float f[kSurIn];
-    const bool ok = defined && finish_features(kb, ph, gsh, f) &&
-                    in_range(scal + 2 * kSurIn, scal + 3 * kSurIn, f);
-    s_ok = ok ? 1 : 0;
-    if (ok) {
-      for (int i = 0; i < kSurIn; ++i) xs[i] = (f[i] - scal[i]) / scal[kSurIn + i];
+  if (tid < 64) {
+    // lane i < kSurIn forms input i; the row is used when every input is in the network's
+    // domain and within the training range (5% margin)
+    bool in = true;
+    float fv = 0.f;
+    if (defined && ph > 0.0 && tid < kSurIn) {
+      const double v = feature_value(tid, kb, ph, gsh);
+      fv = static_cast<float>(v);
+      const float lo = scal[2 * kSurIn + tid], hi = scal[3 * kSurIn + tid];
+      const float mg = 0.05f * (hi - lo);
+      in = feature_in_domain(tid, v) && fv >= lo - mg && fv <= hi + mg;
     }
+    const bool ok = defined && ph > 0.0 && __all(in);
+    if (ok && tid < kSurIn) xs[tid] = (fv - scal[tid]) / scal[kSurIn + tid];
+    if (tid == 0) s_ok = ok ? 1 : 0;
+  }
+  if (tid == 0) {
+    const bool ok = s_ok != 0;
     pcdm_out[ob] = pcdm;
     if (!(cb > 0.0)) {
       sur_r[ob] = __builtin_nan("");
@@ -664,6 +682,7 @@ __global__ __launch_bounds__(RT) void surrogate_response_kernel(
                                  ic_pnu + static_cast<size_t>(box) * kMaxSpecies * nbins,
                                  ic_theta[ob], hpm, nbins, b,
                                  tg_ds + static_cast<size_t>(box) * qcap,
+                                 tg_l2 + static_cast<size_t>(box) * qcap,
                                  tg_w + static_cast<size_t>(box) * qcap, q_sub, iterations, red);
     if (tid == 0) {
       const double r = ph > 0.0 ? pnu / ph : 0.0;   // no CDM power in the bin: R = 0
@@ -737,13 +756,13 @@ hipError_t launch_surrogate_response(const float* P, const unsigned short* Q, in
                                      const double* counts, const double* kmean, double* hist_pm,
                                      double* hist_pnu, const double* ic_pnu,
                                      const double* ic_theta, const double* tg_ds,
-                                     const double* tg_w, int nbins, int jcap, int qcap,
-                                     int q_sub, int iterations, double norm, int nbox,
+                                     const double* tg_l2, const double* tg_w, int nbins, int jcap,
+                                     int qcap, int q_sub, int iterations, double norm, int nbox,
                                      double* pcdm, double* pnu, double* ratio, double* sur_r,
                                      double* chk_exact, double* chk_sur, hipStream_t s) {
   hipLaunchKernelGGL(surrogate_response_kernel, dim3(nbins, nbox), dim3(RT), 0, s, P, Q, mode,
                      boxes, partial, n_partial, counts, kmean, hist_pm, hist_pnu, ic_pnu,
-                     ic_theta, tg_ds, tg_w, nbins, jcap, qcap, q_sub, iterations, norm, pcdm,
+                     ic_theta, tg_ds, tg_l2, tg_w, nbins, jcap, qcap, q_sub, iterations, norm, pcdm,
                      pnu, ratio, sur_r, chk_exact, chk_sur);
   return hipGetLastError();
 }

@@ -144,6 +144,7 @@ struct Ctx {
   double* ic_pnu = nullptr;        // [nbox][kMaxSpecies][B] per massive species
   double* ic_theta = nullptr;      // [nbox][B]
   double* tg_ds = nullptr;         // [nbox][qcap]
+  double* tg_l2 = nullptr;         // [nbox][qcap] log2 of tg_ds (the fit's x^0.1811)
   double* tg_w = nullptr;          // [nbox][qcap]
   RespBox* d_resp = nullptr;       // [nbox]
   float* rtable = nullptr;         // [nbox][n2max+1]
@@ -161,7 +162,7 @@ struct Ctx {
   float* delta = nullptr;          // [nbox][M] delta in FP32 (modes 6, 7)
   double* d_kd = nullptr;          // [nbox][2] kick and drift factors of the leapfrog
   // pinned staging of the host-built arrays (copied in stream order) and the last copies
-  double* h_tg = nullptr;          // ds [nbox][qcap], then w [nbox][qcap]
+  double* h_tg = nullptr;          // ds [nbox][qcap], then w, then log2 ds
   RespBox* h_resp = nullptr;       // [nbox]
   double* h_kd = nullptr;          // [nbox][2]
   hipEvent_t ev_tg = nullptr, ev_kd = nullptr;
@@ -281,8 +282,9 @@ hipError_t launch_copy_modes(int N, const float2* ck, float2* out, int box, hipS
 hipError_t launch_response(const RespBox* boxes, const double* partial, int n_partial,
                            const double* counts, const double* kmean, const double* hist_pm,
                            const double* hist_pnu, const double* ic_pnu,
-                           const double* ic_theta, const double* tg_ds, const double* tg_w,
-                           int B, int Jcap, int qcap, int Q, int iterations, double norm,
+                           const double* ic_theta, const double* tg_ds, const double* tg_l2,
+                           const double* tg_w, int B, int Jcap, int qcap, int Q, int iterations,
+                           double norm,
                            int nbox, double* pcdm, double* pnu, double* ratio,
                            hipStream_t s, int threads);
 // threads per workgroup of the exact response for this many (bin, box) pairs: 64 or 256
@@ -301,8 +303,8 @@ hipError_t launch_surrogate_response(const float* P, const unsigned short* Q, in
                                      const double* counts, const double* kmean, double* hist_pm,
                                      double* hist_pnu, const double* ic_pnu,
                                      const double* ic_theta, const double* tg_ds,
-                                     const double* tg_w, int nbins, int jcap, int qcap,
-                                     int q_sub, int iterations, double norm, int nbox,
+                                     const double* tg_l2, const double* tg_w, int nbins, int jcap,
+                                     int qcap, int q_sub, int iterations, double norm, int nbox,
                                      double* pcdm, double* pnu, double* ratio, double* sur_r,
                                      double* chk_exact, double* chk_sur, hipStream_t s);
 hipError_t launch_surrogate_dataset(const RespBox* boxes, const double* pcdm, const double* ratio,

@@ -11,12 +11,15 @@ constexpr int RT = 256;
 // Rational fit of the free-streaming kernel I(x), the paper's Appendix C eq. (fit).
 // x^4.1811 is taken as x^4 2^(0.1811 log2 x): FP64 to a few ulp, and cheaper than pow,
 // whose extra-precision logarithm the small fractional exponent does not need.
-__device__ __forceinline__ double i_fit(double x) {
+__device__ __forceinline__ double i_fit_l2(double x, double l2x) {   // l2x = log2 x
   const double x2 = x * x, x4 = x2 * x2;
   const double num = 1.0 + 0.0168 * x2 + 0.0407 * x4;
-  const double xp = x > 0.0 ? x4 * exp2(0.1811 * log2(x)) : 0.0;
+  const double xp = x > 0.0 ? x4 * exp2(0.1811 * l2x) : 0.0;
   const double den = 1.0 + 2.1734 * x2 + 1.6787 * xp + 0.1467 * x4 * x4;
   return num / den;
+}
+__device__ __forceinline__ double i_fit(double x) {
+  return i_fit_l2(x, x > 0.0 ? log2(x) : 0.0);
 }
 
 // The exact kernel of Appendix C, I(x) = 4/(3 zeta(3)) sum_{n>=1} (-1)^{n+1} n/(n^2+x^2)^2,
@@ -67,6 +70,12 @@ template <bool SERIES>
 __device__ __forceinline__ double i_kernel(double x) {
   if constexpr (SERIES) return i_series(x);
   else return i_fit(x);
+}
+// the same with log2 x known (the fit then needs no logarithm; the series ignores it)
+template <bool SERIES>
+__device__ __forceinline__ double i_kernel_l2(double x, double l2x) {
+  if constexpr (SERIES) return i_series(x);
+  else return i_fit_l2(x, l2x);
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -158,9 +167,17 @@ template <int NSP, bool SERIES, int NT>   // species: 1 (equal masses) or kMaxSp
 __device__ __forceinline__ double exact_pnu_n(const RespBox& bx, double k, double pcdm_half,
                                               double pnu_prev, const double* ic_pnu,
                                               double ic_theta, const double* hpm, int nbins,
-                                              int b, const double* ds, const double* w,
-                                              int q_sub, int iterations, double* red) {
+                                              int b, const double* ds, const double* l2ds,
+                                              const double* w, int q_sub, int iterations,
+                                              double* red) {
   const double inv_q = 1.0 / q_sub;
+  // log2(k T/m_s) of each species: with log2(ds) per sub-node (host FP64) it gives the
+  // fit's log2 x without a logarithm per sub-node
+  double l2k[NSP];
+#pragma unroll
+  for (int sp = 0; sp < NSP; ++sp)
+    l2k[sp] = (SERIES || !(sp < bx.n_sp) || !(k * bx.tm_sp[sp] > 0.0)) ? 0.0
+                                                                       : log2(k * bx.tm_sp[sp]);
   double known = 0.0, coef = 0.0;
   if (threadIdx.x < 64) {                    // wave-uniform
     double ic = 0.0;
@@ -177,7 +194,7 @@ __device__ __forceinline__ double exact_pnu_n(const RespBox& bx, double k, doubl
   const int rounds = (per + U - 1) / U;
   const int chunk = rounds > 0 ? (per + rounds - 1) / rounds : 0;
   for (int u0 = 0; u0 < per; u0 += chunk) {
-    double d[U], wq[U], a0[U], a1[U];
+    double d[U], l2d[U], wq[U], a0[U], a1[U];
     bool c0[U], c1[U];                       // the bracketing node is the current one
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -185,6 +202,7 @@ __device__ __forceinline__ double exact_pnu_n(const RespBox& bx, double k, doubl
       const int j = q / q_sub;
       const bool in = u < chunk && q < bx.nq;
       d[u] = in ? ds[q] : 0.0;
+      l2d[u] = (in && !SERIES) ? l2ds[q] : 0.0;
       wq[u] = in ? w[q] : 0.0;
       c0[u] = !(j < bx.n_cur);
       c1[u] = !(j + 1 < bx.n_cur);
@@ -204,7 +222,8 @@ __device__ __forceinline__ double exact_pnu_n(const RespBox& bx, double k, doubl
       double kern = 0.0;
 #pragma unroll
       for (int sp = 0; sp < NSP; ++sp)
-        if (sp < bx.n_sp) kern += bx.w_sp[sp] * i_kernel<SERIES>(k * bx.tm_sp[sp] * d[u]);
+        if (sp < bx.n_sp)
+          kern += bx.w_sp[sp] * i_kernel_l2<SERIES>(k * bx.tm_sp[sp] * d[u], l2k[sp] + l2d[u]);
       const double g = wq[u] * kern * d[u];
       known += g * amp;
       coef += g * cur;
@@ -224,12 +243,13 @@ template <int NT = RT>
 __device__ __forceinline__ double exact_pnu(const RespBox& bx, double k, double pcdm_half,
                                             double pnu_prev, const double* ic_pnu,
                                             double ic_theta, const double* hpm, int nbins,
-                                            int b, const double* ds, const double* w,
-                                            int q_sub, int iterations, double* red) {
+                                            int b, const double* ds, const double* l2ds,
+                                            const double* w, int q_sub, int iterations,
+                                            double* red) {
   if (bx.n_sp <= 0) return 0.0;          // no massive neutrinos: the term drops out
 #define PMNU_EXACT_PNU(NSP, SERIES)                                                        \
   exact_pnu_n<NSP, SERIES, NT>(bx, k, pcdm_half, pnu_prev, ic_pnu, ic_theta, hpm, nbins, b, ds, \
-                           w, q_sub, iterations, red)
+                               l2ds, w, q_sub, iterations, red)
   if (bx.series) {
     if (bx.n_sp == 1) return PMNU_EXACT_PNU(1, true);
     return PMNU_EXACT_PNU(kMaxSpecies, true);

@@ -33,7 +33,8 @@ __global__ __launch_bounds__(NT) void response_kernel(
     const double* __restrict__ counts, const double* __restrict__ kmean,
     double* __restrict__ hist_pm, double* __restrict__ hist_pnu,
     const double* __restrict__ ic_pnu, const double* __restrict__ ic_theta,
-    const double* __restrict__ tg_ds, const double* __restrict__ tg_w, int nbins, int jcap,
+    const double* __restrict__ tg_ds, const double* __restrict__ tg_l2,
+    const double* __restrict__ tg_w, int nbins, int jcap,
     int qcap, int q_sub, int iterations, double norm, double* __restrict__ pcdm_out,
     double* __restrict__ pnu_out, double* __restrict__ ratio_out) {
   __shared__ double red[2 * NT / 64];
@@ -64,6 +65,7 @@ __global__ __launch_bounds__(NT) void response_kernel(
                                (bx.n_cur > 0 ? hpn[static_cast<size_t>(bx.n_cur - 1) * nbins + b] : 0.0),
                                ic_pnu + static_cast<size_t>(box) * kMaxSpecies * nbins,
                                ic_theta[ob], hpm, nbins, b, tg_ds + static_cast<size_t>(box) * qcap,
+                               tg_l2 + static_cast<size_t>(box) * qcap,
                                tg_w + static_cast<size_t>(box) * qcap, q_sub, iterations, red);
   if (threadIdx.x == 0) {
     pcdm_out[ob] = pcdm;
@@ -154,14 +156,16 @@ hipError_t launch_kernel_values(const double* x, int64_t n, int series, double* 
 hipError_t launch_response(const RespBox* boxes, const double* partial, int n_partial,
                            const double* counts, const double* kmean, const double* hist_pm,
                            const double* hist_pnu, const double* ic_pnu,
-                           const double* ic_theta, const double* tg_ds, const double* tg_w,
+                           const double* ic_theta, const double* tg_ds, const double* tg_l2,
+                           const double* tg_w,
                            int nbins, int jcap, int qcap, int q_sub, int iterations,
                            double norm, int nbox, double* pcdm, double* pnu, double* ratio,
                            hipStream_t s, int threads) {
 #define PMNU_LAUNCH_RESPONSE(NT)                                                             \
   hipLaunchKernelGGL(response_kernel<NT>, dim3(nbins, nbox), dim3(NT), 0, s, boxes, partial, \
                      n_partial, counts, kmean, const_cast<double*>(hist_pm),                 \
-                     const_cast<double*>(hist_pnu), ic_pnu, ic_theta, tg_ds, tg_w, nbins,    \
+                     const_cast<double*>(hist_pnu), ic_pnu, ic_theta, tg_ds, tg_l2, tg_w,    \
+                     nbins,                                                                  \
                      jcap, qcap, q_sub, iterations, norm, pcdm, pnu, ratio)
   if (threads == 64) PMNU_LAUNCH_RESPONSE(64);
   else PMNU_LAUNCH_RESPONSE(RT);

@@ -106,7 +106,8 @@ int surrogate_launch(Ctx& c, int mode, double norm) {
   timer_begin(c, ST_SURROGATE);
   hipError_t e = launch_surrogate_response(
       s->P, s->packed, mode, c.d_resp, c.bin_partial, c.n_partial, c.d_counts, c.d_kmean,
-      c.hist_pm, c.hist_pnu, c.ic_pnu, c.ic_theta, c.tg_ds, c.tg_w, c.B, c.Jcap, c.qcap, c.Q,
+      c.hist_pm, c.hist_pnu, c.ic_pnu, c.ic_theta, c.tg_ds, c.tg_l2, c.tg_w, c.B, c.Jcap, c.qcap,
+      c.Q,
       c.cfg.iterations, norm, c.nbox, c.pcdm, c.pnu, c.ratio, s->sur_r, s->chk_exact,
       s->chk_sur, c.stream);
   timer_end(c);
