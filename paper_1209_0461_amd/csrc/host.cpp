@@ -359,7 +359,9 @@ int do_response_mode(Ctx& c, double a_now, int mode) {
           launch_response(c.d_resp, c.bin_partial, c.n_partial, c.d_counts, c.d_kmean,
                           c.hist_pm, c.hist_pnu, c.ic_pnu, c.ic_theta, c.tg_ds, c.tg_l2, c.tg_w, c.B,
                           c.Jcap, c.qcap, c.Q, c.cfg.iterations, norm, c.nbox, c.pcdm, c.pnu,
-                          c.ratio, c.stream, response_threads(c.B, c.nbox)));
+                          c.ratio, c.stream, response_threads(c.B, c.nbox), c.series,
+                          std::any_of(c.h_resp, c.h_resp + c.nbox,
+                                      [](const RespBox& r) { return r.n_sp > 1; })));
   } else {
     int rc = surrogate_launch(c, mode, norm);
     if (rc) return rc;

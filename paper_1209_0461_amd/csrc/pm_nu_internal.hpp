@@ -286,7 +286,7 @@ hipError_t launch_response(const RespBox* boxes, const double* partial, int n_pa
                            const double* tg_w, int B, int Jcap, int qcap, int Q, int iterations,
                            double norm,
                            int nbox, double* pcdm, double* pnu, double* ratio,
-                           hipStream_t s, int threads);
+                           hipStream_t s, int threads, bool series, bool hierarchy);
 // threads per workgroup of the exact response for this many (bin, box) pairs: 64 or 256
 int response_threads(int nbins, int nbox);
 // mlp_kernels.hip

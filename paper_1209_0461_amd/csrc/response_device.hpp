@@ -189,7 +189,7 @@ __device__ __forceinline__ double exact_pnu_n(const RespBox& bx, double k, doubl
     ic *= 1.0 - bx.ds_ic * bx.a_i * ic_theta;
     if (threadIdx.x == 0) known = ic;
   }
-  constexpr int U = NT == 64 ? 4 : 8;        // one wave: keep registers for occupancy
+  constexpr int U = NT == 64 ? 5 : 8;        // one wave: keep registers for occupancy
   const int per = (bx.nq + NT - 1) / NT;
   const int rounds = (per + U - 1) / U;
   const int chunk = rounds > 0 ? (per + rounds - 1) / rounds : 0;
@@ -237,6 +237,20 @@ __device__ __forceinline__ double exact_pnu_n(const RespBox& bx, double k, doubl
     pnu_guess = pnu;
   }
   return pnu;
+}
+
+// One kernel form (I(x) series or fit, one or several species): a kernel that takes only
+// this form needs the registers of this form alone.
+template <int NT, bool SERIES, int NSP>
+__device__ __forceinline__ double exact_pnu_form(const RespBox& bx, double k, double pcdm_half,
+                                                 double pnu_prev, const double* ic_pnu,
+                                                 double ic_theta, const double* hpm, int nbins,
+                                                 int b, const double* ds, const double* l2ds,
+                                                 const double* w, int q_sub, int iterations,
+                                                 double* red) {
+  if (bx.n_sp <= 0) return 0.0;          // no massive neutrinos: the term drops out
+  return exact_pnu_n<NSP, SERIES, NT>(bx, k, pcdm_half, pnu_prev, ic_pnu, ic_theta, hpm, nbins,
+                                      b, ds, l2ds, w, q_sub, iterations, red);
 }
 
 template <int NT = RT>

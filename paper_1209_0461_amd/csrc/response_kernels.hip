@@ -27,7 +27,9 @@
 namespace pmnu {
 namespace {
 
-template <int NT>
+// FORM: 0 fit with one species per box, 1 fit with a mass hierarchy, 2 and 3 the same with
+// the exact series (the host takes the form the boxes need)
+template <int NT, int FORM>
 __global__ __launch_bounds__(NT) void response_kernel(
     const RespBox* __restrict__ boxes, const double* __restrict__ partial, int n_partial,
     const double* __restrict__ counts, const double* __restrict__ kmean,
@@ -61,7 +63,9 @@ __global__ __launch_bounds__(NT) void response_kernel(
   const double pcdm_half = sqrt(pcdm);
 
   // 2. history integral
-  const double pnu = exact_pnu<NT>(bx, kmean[b], pcdm_half,
+  constexpr bool SERIES = FORM >= 2;
+  constexpr int NSP = (FORM & 1) ? kMaxSpecies : 1;
+  const double pnu = exact_pnu_form<NT, SERIES, NSP>(bx, kmean[b], pcdm_half,
                                (bx.n_cur > 0 ? hpn[static_cast<size_t>(bx.n_cur - 1) * nbins + b] : 0.0),
                                ic_pnu + static_cast<size_t>(box) * kMaxSpecies * nbins,
                                ic_theta[ob], hpm, nbins, b, tg_ds + static_cast<size_t>(box) * qcap,
@@ -160,15 +164,30 @@ hipError_t launch_response(const RespBox* boxes, const double* partial, int n_pa
                            const double* tg_w,
                            int nbins, int jcap, int qcap, int q_sub, int iterations,
                            double norm, int nbox, double* pcdm, double* pnu, double* ratio,
-                           hipStream_t s, int threads) {
-#define PMNU_LAUNCH_RESPONSE(NT)                                                             \
-  hipLaunchKernelGGL(response_kernel<NT>, dim3(nbins, nbox), dim3(NT), 0, s, boxes, partial, \
+                           hipStream_t s, int threads, bool series, bool hierarchy) {
+#define PMNU_LAUNCH_RESPONSE(NT, FORM)                                                       \
+  hipLaunchKernelGGL((response_kernel<NT, FORM>), dim3(nbins, nbox), dim3(NT), 0, s, boxes,  \
+                     partial,                                                                \
                      n_partial, counts, kmean, const_cast<double*>(hist_pm),                 \
                      const_cast<double*>(hist_pnu), ic_pnu, ic_theta, tg_ds, tg_l2, tg_w,    \
                      nbins,                                                                  \
                      jcap, qcap, q_sub, iterations, norm, pcdm, pnu, ratio)
-  if (threads == 64) PMNU_LAUNCH_RESPONSE(64);
-  else PMNU_LAUNCH_RESPONSE(RT);
+  const int form = (series ? 2 : 0) + (hierarchy ? 1 : 0);
+  if (threads == 64) {
+    switch (form) {
+      case 0: PMNU_LAUNCH_RESPONSE(64, 0); break;
+      case 1: PMNU_LAUNCH_RESPONSE(64, 1); break;
+      case 2: PMNU_LAUNCH_RESPONSE(64, 2); break;
+      default: PMNU_LAUNCH_RESPONSE(64, 3); break;
+    }
+  } else {
+    switch (form) {
+      case 0: PMNU_LAUNCH_RESPONSE(RT, 0); break;
+      case 1: PMNU_LAUNCH_RESPONSE(RT, 1); break;
+      case 2: PMNU_LAUNCH_RESPONSE(RT, 2); break;
+      default: PMNU_LAUNCH_RESPONSE(RT, 3); break;
+    }
+  }
 #undef PMNU_LAUNCH_RESPONSE
   return hipGetLastError();
 }
