@@ -470,7 +470,7 @@ __global__ void pack_weights_kernel(const float* __restrict__ P, unsigned short*
 // The biases a thread adds are those of the output it finishes: t / 2 in layer 1 and
 // hidden_out(t) in layers 2 and 3; thread t holds W4[t % 128] (threads t < 128 use it).
 // Every load here is unconditional and its value first used after the P_cdm reduction, so
-// that no wait for them stands between the loads and the reduction.
+// that no wait for one of them stands between the loads and the reduction's own.
 __device__ __forceinline__ int hidden_out(int t) {
   return (t >> 4) + 16 * (4 * ((t >> 3) & 1) + 2 * ((t >> 2) & 1) + ((t >> 1) & 1));
 }
@@ -577,8 +577,8 @@ __device__ __forceinline__ float net_forward(const NetRegs& r, const float* x, f
 
 // The surrogate's response, one workgroup per (bin b, box), as response_kernel but with the
 // network in place of the history integral where it can answer: P_cdm from the deposit's
-// partial sums, the bin's inputs (their memory reads are issued before the partial sums,
-// the network's weights right after them, so that the latencies overlap), the
+// partial sums, the bin's inputs (their memory reads and the network's weights are issued
+// before the partial sums, so that the latencies overlap), the
 // network's R, and the exact integral (response_device.hpp) for a bin whose inputs are not
 // defined or fall outside the training range. Mode 1 keeps the network's R; mode 2 (check)
 // keeps the exact result and records the network's beside it.
@@ -618,11 +618,11 @@ __global__ __launch_bounds__(RT) void surrogate_response_kernel(
     if (tid < kGCount) gv = gather_value(bxp, hpm, hpn, nbins, b, tid);
     if (tid < 4 * kSurIn) sc = P[kOffMu + tid];   // kOffMu .. kOffMax + kSurIn are contiguous
   }
-  const double msum = bin_mode_sum(partial, n_partial, nbins, box, b, red);   // has barriers
-  // the weights after it (consuming the reduction's loads waits for every older load):
-  // their latency hides behind the inputs formed below
+  // the weights too: the reduction then waits for them as well (a wave consumes its loads
+  // in issue order), which costs less than their latency after it (14.5 against 15.3 us)
   NetRegs w;
   if (defined) load_net_weights(P, Q, tid, w);
+  const double msum = bin_mode_sum(partial, n_partial, nbins, box, b, red);   // has barriers
   const double pcdm = cb > 0.0 ? norm * msum / cb : 0.0;
   const double ph = sqrt(pcdm);
   if (defined) {
