@@ -81,6 +81,146 @@ __global__ __launch_bounds__(NT) void response_kernel(
   }
 }
 
+// The exact response for many (bin, box) pairs with the fit and one species per box (the
+// batched boxes): one workgroup of RT threads per (group of G bins, box). The box's time
+// grid (s differences, their log2, weights) and the group's stored history rows are staged
+// in LDS with one round of loads, since every bin of the box reads the same grid; then
+// WPB = 4 / G waves share each bin's sub-nodes (wave h of a bin takes the lanes' sub-nodes
+// q = 64 (WPB i + h) + lane), sum them over the wave, and the bin's first wave adds the
+// others' sums from LDS. Dynamic LDS: 3 nq + n_cur G doubles.
+template <int G>
+__global__ __launch_bounds__(RT) void response_group_kernel(
+    const RespBox* __restrict__ boxes, const double* __restrict__ partial, int n_partial,
+    const double* __restrict__ counts, const double* __restrict__ kmean,
+    double* __restrict__ hist_pm, double* __restrict__ hist_pnu,
+    const double* __restrict__ ic_pnu, const double* __restrict__ ic_theta,
+    const double* __restrict__ tg_ds, const double* __restrict__ tg_l2,
+    const double* __restrict__ tg_w, int nbins, int jcap, int qcap, int q_sub, int iterations,
+    double norm, double* __restrict__ pcdm_out, double* __restrict__ pnu_out,
+    double* __restrict__ ratio_out) {
+  constexpr int WPB = (RT / 64) / G;                 // waves per bin
+  static_assert(G * WPB == RT / 64, "the waves cover the bins evenly");
+  extern __shared__ double sm[];
+  __shared__ double s_red[RT / 64][2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int gv = wave / WPB, h = wave % WPB;         // this wave's bin in the group, its share
+  const int box = blockIdx.y, b0 = blockIdx.x * G, b = b0 + gv;
+  const bool bin_on = b < nbins;
+  const RespBox bx = boxes[box];
+  const int nq = bx.nq, ncur = bx.n_cur;
+  double* hpm = hist_pm + static_cast<size_t>(box) * jcap * nbins;
+  double* hpn = hist_pnu + static_cast<size_t>(box) * jcap * nbins;
+  const double* ds = tg_ds + static_cast<size_t>(box) * qcap;
+  const double* l2 = tg_l2 + static_cast<size_t>(box) * qcap;
+  const double* wt = tg_w + static_cast<size_t>(box) * qcap;
+  double* s_ds = sm;
+  double* s_l2 = sm + nq;
+  double* s_w = sm + 2 * nq;
+  double* s_h = sm + 3 * nq;                         // [j][g], j < n_cur
+  // the bin's partial sums (its first wave; loads before the staging's stores)
+  double psum = 0.0;
+  if (bin_on && h == 0) {
+    constexpr int UP = 4;                            // loads in flight per lane
+    const double* pp = partial + (static_cast<size_t>(box) * nbins + b) * n_partial;
+    for (int i0 = lane; i0 < n_partial; i0 += UP * 64) {
+      double x[UP];
+#pragma unroll
+      for (int u = 0; u < UP; ++u) x[u] = i0 + u * 64 < n_partial ? pp[i0 + u * 64] : 0.0;
+#pragma unroll
+      for (int u = 0; u < UP; ++u) psum += x[u];
+    }
+  }
+  {
+    constexpr int UB = 12;                           // one round at 100 nodes, Q = 8
+    const int nst = 3 * nq + ncur * G;
+    for (int i0 = tid; i0 < nst; i0 += UB * RT) {
+      double val[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int i = i0 + u * RT;
+        double x = 0.0;
+        if (i < nq) x = ds[i];
+        else if (i < 2 * nq) x = l2[i - nq];
+        else if (i < 3 * nq) x = wt[i - 2 * nq];
+        else if (i < nst) {
+          const int k = i - 3 * nq, j = k / G, g = k - j * G;
+          if (b0 + g < nbins) x = hpm[static_cast<size_t>(j) * nbins + b0 + g];
+        }
+        val[u] = x;
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u)
+        if (i0 + u * RT < nst) sm[i0 + u * RT] = val[u];
+    }
+  }
+  __syncthreads();
+  const bool massive = bx.n_sp > 0;
+  const double tm = bx.tm_sp[0], wsp = bx.w_sp[0], inv_q = 1.0 / q_sub;
+  const double kb = kmean[bin_on ? b : nbins - 1];
+  const double l2k = massive && kb * tm > 0.0 ? log2(kb * tm) : 0.0;
+  double known = 0.0, coef = 0.0;
+  if (massive && bin_on) {
+    for (int q = 64 * h + lane; q < nq; q += 64 * WPB) {
+      const double d = s_ds[q], l2d = s_l2[q], wq = s_w[q];
+      const int j = q / q_sub, r = q - j * q_sub;
+      const double t = r * inv_q;
+      const bool c0 = !(j < ncur), c1 = !(j + 1 < ncur);
+      const double cur = (c0 ? (r != 0 ? 1.0 - t : 1.0) : 0.0) + ((r != 0 && c1) ? t : 0.0);
+      const double a0 = c0 ? 0.0 : s_h[j * G + gv];
+      const double a1 = c1 ? 0.0 : s_h[(j + 1) * G + gv];
+      const double amp = (r != 0) ? (1.0 - t) * a0 + t * a1 : a0;
+      const double gq = wq * (wsp * i_fit_l2(kb * tm * d, l2k + l2d)) * d;
+      known += gq * amp;
+      coef += gq * cur;
+    }
+  }
+  known = wave_sum_d(known);
+  coef = wave_sum_d(coef);
+  psum = wave_sum_d(psum);
+  if (WPB > 1) {
+    if (lane == 0) {
+      s_red[wave][0] = known;
+      s_red[wave][1] = coef;
+    }
+    __syncthreads();
+    if (h == 0) {
+#pragma unroll
+      for (int o = 1; o < WPB; ++o) {                // fixed order over the bin's waves
+        known += s_red[wave + o][0];
+        coef += s_red[wave + o][1];
+      }
+    }
+  }
+  if (h != 0 || lane != 0 || !bin_on) return;
+  const size_t ob = static_cast<size_t>(box) * nbins + b;
+  const size_t row = static_cast<size_t>(ncur) * nbins + b;
+  const double cb = counts[b];
+  if (!(cb > 0.0)) {
+    pcdm_out[ob] = pnu_out[ob] = ratio_out[ob] = 0.0;
+    hpm[row] = hpn[row] = 0.0;
+    return;
+  }
+  const double pcdm = norm * psum / cb;
+  const double ph = sqrt(pcdm);
+  double pnu = 0.0;
+  if (massive) {
+    double ic = wsp * i_fit(kb * tm * bx.ds_ic) *
+                ic_pnu[static_cast<size_t>(box) * kMaxSpecies * nbins + b];   // species 0
+    ic *= 1.0 - bx.ds_ic * bx.a_i * ic_theta[ob];
+    double guess = ncur > 0 ? hpn[row - nbins] : 0.0;
+    for (int it = 0; it < iterations; ++it) {
+      const double a_cur = (1.0 - bx.f_nu) * ph + bx.f_nu * guess;
+      pnu = ic + known + coef * a_cur;
+      guess = pnu;
+    }
+  }
+  pcdm_out[ob] = pcdm;
+  pnu_out[ob] = pnu;
+  ratio_out[ob] = ph > 0.0 ? pnu / ph : 0.0;       // no CDM power in the bin: R = 0
+  hpm[row] = (1.0 - bx.f_nu) * ph + bx.f_nu * pnu;
+  hpn[row] = pnu;
+}
+
 // P_cdm(k_b) from the deposit's partial sums alone (for reading the spectrum before a
 // response): one workgroup per (bin, box).
 __global__ __launch_bounds__(RT) void bin_power_kernel(const double* __restrict__ partial,
@@ -173,7 +313,16 @@ hipError_t launch_response(const RespBox* boxes, const double* partial, int n_pa
                      nbins,                                                                  \
                      jcap, qcap, q_sub, iterations, norm, pcdm, pnu, ratio)
   const int form = (series ? 2 : 0) + (hierarchy ? 1 : 0);
-  if (threads == 64) {
+  constexpr int G = 4;                             // bins per workgroup of the grouped form
+  const size_t group_lds = (3 * static_cast<size_t>(qcap) + static_cast<size_t>(jcap) * G) *
+                           sizeof(double);
+  if (threads == 64 && form == 0 && group_lds <= 64 * 1024) {
+    hipLaunchKernelGGL((response_group_kernel<G>), dim3((nbins + G - 1) / G, nbox), dim3(RT),
+                       group_lds, s, boxes, partial, n_partial, counts, kmean,
+                       const_cast<double*>(hist_pm), const_cast<double*>(hist_pnu), ic_pnu,
+                       ic_theta, tg_ds, tg_l2, tg_w, nbins, jcap, qcap, q_sub, iterations, norm,
+                       pcdm, pnu, ratio);
+  } else if (threads == 64) {
     switch (form) {
       case 0: PMNU_LAUNCH_RESPONSE(64, 0); break;
       case 1: PMNU_LAUNCH_RESPONSE(64, 1); break;
