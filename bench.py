@@ -35,6 +35,7 @@ KERNEL_SOURCES = {
     "zero_mesh": "grid_kernels.hip", "fft_fwd_z": "fft_kernels.hip",
     "fft_fwd_y": "fft_kernels.hip", "fft_fwd_x_bin": "fft_kernels.hip",
     "inv_x_green": "fft_kernels.hip", "fft_inv_y": "fft_kernels.hip",
+    "inv_xy_green": "fft_kernels.hip",
     "fft_inv_z": "fft_kernels.hip", "nu_response": "response_kernels.hip",
     "rtable": "response_kernels.hip", "patch_reduce": "grid_kernels.hip",
     "kick_drift": "advance_kernels.hip", "patch_fwd_z": "fft_kernels.hip",
@@ -63,6 +64,7 @@ def stage_bytes(n_mesh, n_part, nbox, nbins, n_hist, n_partial, deposit_mode=0):
         "rtable": 4 * nbox * (3 * n_mesh * n_mesh // 4 + 1),
         "inv_x_green": 8 * mh + 16 * mh,
         "fft_inv_y": 16 * mh + 24 * mh,
+        "inv_xy_green": 8 * mh + 24 * mh,
         "fft_inv_z": 24 * mh + 12 * m,
         "cic_interp": 12 * npt + 12 * m + 12 * npt,
     }
@@ -105,6 +107,8 @@ def kernel_name(stage, tuning, n_mesh):
     tiles = tuning.get("fft_tiles", {})
     fft = {"fft_fwd_y": ("fwd_y_kernel", "fwd_y"), "inv_x_green": ("inv_x_kernel", "inv_x"),
            "fft_inv_y": ("inv_y_kernel", "inv_y"), "fft_inv_z": ("inv_z_kernel", "inv_z")}
+    if stage == "inv_xy_green":
+        return "inv_xy_kernel<%d>" % n_mesh
     if stage == "patch_fwd_z":
         return "patch_fwd_z_kernel<%d>" % n_mesh
     if stage == "fft_fwd_z":

@@ -167,6 +167,10 @@ int pm_nu_side_grid_uses(pm_nu_ctx* ctx, int64_t* uses);
  * Deposit modes 8 and 9 never write the density to HBM unless asked to by
  * pm_nu_set_keep_density before the deposit; otherwise PM_NU_ESTATE. */
 int pm_nu_copy_density(pm_nu_ctx* ctx, int box, float* out);
+/* For N <= 64 the first two inverse FFT passes (Green's function, x and y) run as one
+ * kernel per k_z slab, whose modes fit the LDS (fused != 0, the default); 0 runs them as the
+ * two passes that larger meshes use. Both give the same forces bit for bit. */
+int pm_nu_set_inverse_xy(pm_nu_ctx* ctx, int fused);
 /* With deposit modes 8 and 9, also store delta at every deposit (67 MB more writes per
  * 256^3 box) so that pm_nu_copy_density can read it (on != 0); the default is off. The
  * other deposit modes always keep it. */

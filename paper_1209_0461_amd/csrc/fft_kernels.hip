@@ -707,6 +707,132 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
   }
 }
 
+// For N <= 64 the first two inverse passes in one kernel, one workgroup per (k_z, box): the
+// whole k_z slab (N x N modes, [x][k_y]) fits the LDS, so F1 = phi and F2 = -i k_x phi never
+// go to HBM. As inv_x_kernel with all k_y at once: forward transform along x, the Green's
+// function with the neutrino factor T(n^2) and the deconvolution, -i k_x, inverse along x;
+// then the slab is transposed through registers (each thread holds 2 N^2 / NT values) to
+// lines along k_y, and as inv_y_kernel G1 = F1 and G3 = F2 are transformed along y and
+// written to [box][x][k_z][y], then G2 = -i k_y F1 from the registers. The same arithmetic
+// as the two passes in the same order, so the same result bit for bit.
+template <int N>
+__global__ __launch_bounds__(NT) void inv_xy_kernel(const float2* __restrict__ dk,
+                                                    float2* __restrict__ g1,
+                                                    float2* __restrict__ g2,
+                                                    float2* __restrict__ g3,
+                                                    const float2* __restrict__ twg,
+                                                    const float* __restrict__ rtable, int n2max,
+                                                    const float* __restrict__ inv_w2, float c,
+                                                    float kf) {
+  constexpr int NK = Shape<N>::NK, NL = 2 * N, ES = NL + 1;
+  constexpr int PER = (2 * N * N + NT - 1) / NT;    // F1, F2 values each thread holds
+  constexpr int GI = (N * N + NT - 1) / NT;         // Green's-function modes per thread
+  static_assert(N <= 64, "the slab must fit the LDS");
+  __shared__ float2 lds[N * ES];
+  __shared__ float2 tw[N];
+  __shared__ float s_iw[N];
+  const int tid = threadIdx.x;
+  const int kz = static_cast<int>(blockIdx.x) % NK, box = static_cast<int>(blockIdx.x) / NK;
+  load_twiddles<N, NT>(tw, twg);
+  for (int m = tid; m < N; m += NT) s_iw[m] = inv_w2[m];
+  const size_t off = (static_cast<size_t>(box) * NK + kz) * N * N;   // the slab, [x][k_y]
+  const float* rt = rtable + static_cast<size_t>(box) * (n2max + 1);
+  const float wz = inv_w2[kz];
+  // T(n^2) of this thread's modes first (gathers whose latency hides behind the transform)
+  float tv[GI];
+#pragma unroll
+  for (int i = 0; i < GI; ++i) {
+    const int t = tid + i * NT;
+    const int y = t % N, x = t / N;
+    const int nx = signed_index(x, N), ny = signed_index(y, N);
+    const int n2 = nx * nx + ny * ny + kz * kz;
+    tv[i] = (t < N * N && n2 > 0) ? rt[n2] : 0.f;
+  }
+  // the slab: element x of line k_y at lds[x ES + k_y]
+  {
+    constexpr int IT = (N * N / 2 + NT - 1) / NT;
+    float4 v[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int t = tid + i * NT;
+      if (t < N * N / 2) v[i] = *reinterpret_cast<const float4*>(dk + off + 2 * t);
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int t = tid + i * NT;
+      if (t >= N * N / 2) break;
+      const int x = (2 * t) / N, y = (2 * t) % N;
+      lds[x * ES + y] = make_float2(v[i].x, v[i].y);
+      lds[x * ES + y + 1] = make_float2(v[i].z, v[i].w);
+    }
+  }
+  __syncthreads();
+  fft_lines<N, N, NT, -1, ES>(lds, tw);
+  // delta_M -> phi (lines 0..N-1) and -i k_x phi (lines N..2N-1)
+#pragma unroll
+  for (int i = 0; i < GI; ++i) {
+    const int t = tid + i * NT;
+    if (t >= N * N) break;
+    const int y = t % N, x = t / N;
+    const int nx = signed_index(x, N), ny = signed_index(y, N);
+    const int n2 = nx * nx + ny * ny + kz * kz;
+    float2 phi = make_float2(0.f, 0.f);
+    if (n2 > 0) {
+      const float g = -c * tv[i] * s_iw[x] * s_iw[y] * wz / (kf * kf * static_cast<float>(n2));
+      phi = cscale(lds[x * ES + y], g);
+    }
+    const float kx = (x == N / 2) ? 0.f : kf * static_cast<float>(nx);
+    lds[x * ES + y] = phi;
+    lds[x * ES + N + y] = make_float2(kx * phi.y, -kx * phi.x);
+  }
+  __syncthreads();
+  fft_lines<N, NL, NT, +1, ES>(lds, tw);
+  // transpose through registers: value idx = (x, l), l < N: F1(x, k_y = l), else F2
+  float2 f[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int idx = tid + i * NT;
+    f[i] = idx < 2 * N * N ? lds[(idx / NL) * ES + idx % NL] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  // G1 (lines x) and G3 (lines N + x), element k_y
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int idx = tid + i * NT;
+    if (idx >= 2 * N * N) break;
+    const int x = idx / NL, l = idx % NL;
+    if (l < N) lds[l * ES + x] = f[i];
+    else lds[(l - N) * ES + N + x] = f[i];
+  }
+  __syncthreads();
+  fft_lines<N, NL, NT, +1, ES>(lds, tw);
+  auto store = [&](float2* g, int line0) {
+    for (int t = tid; t < N * N / 2; t += NT) {
+      const int x = (2 * t) / N, e = (2 * t) % N;
+      const size_t o = ((static_cast<size_t>(box) * N + x) * NK + kz) * N + e;
+      const float2 a = lds[e * ES + line0 + x], b = lds[(e + 1) * ES + line0 + x];
+      *reinterpret_cast<float4*>(g + o) = make_float4(a.x, a.y, b.x, b.y);
+    }
+  };
+  store(g1, 0);
+  store(g3, N);
+  __syncthreads();
+  // G2 = -i k_y F1
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int idx = tid + i * NT;
+    if (idx >= 2 * N * N) break;
+    const int x = idx / NL, l = idx % NL;
+    if (l < N) {
+      const float ky = (l == N / 2) ? 0.f : kf * static_cast<float>(signed_index(l, N));
+      lds[l * ES + x] = make_float2(ky * f[i].y, -ky * f[i].x);
+    }
+  }
+  __syncthreads();
+  fft_lines<N, N, NT, +1, ES>(lds, tw);
+  store(g2, 0);
+}
+
 // in: rows of [box][kz][x] (flattened); out: G1, G2, G3 rows at [box][x][kz].
 template <int N, int NLR>
 __global__ __launch_bounds__(NT) void inv_y_kernel(const float2* __restrict__ f1,
@@ -967,6 +1093,19 @@ template <int N> struct InvY {
     return with_tile<PMNU_TILES(IY)>(go, v);
   }
 };
+template <int N> struct InvXY {
+  static hipError_t run(const float2* dk, float2* g1, float2* g2, float2* g3, const float2* tw,
+                        const float* rt, int n2max, const float* iw, float cfac, float kf,
+                        int nbox, hipStream_t s) {
+    if constexpr (N > 64) {
+      return hipErrorInvalidValue;                 // the k_z slab does not fit the LDS
+    } else {
+      hipLaunchKernelGGL(inv_xy_kernel<N>, dim3(static_cast<unsigned>(Shape<N>::NK * nbox)),
+                         dim3(NT), 0, s, dk, g1, g2, g3, tw, rt, n2max, iw, cfac, kf);
+      return hipGetLastError();
+    }
+  }
+};
 template <int N> struct InvZ {
   static hipError_t run(const float2* g1, const float2* g2, const float2* g3, float* out,
                         const float2* tw, float kf, int nbox, hipStream_t s, int v) {
@@ -1065,6 +1204,11 @@ hipError_t launch_inv_x(int n, const float2* dk, float2* f1, float2* f2, const f
 hipError_t launch_inv_y(int n, const float2* f1, const float2* f2, float2* g1, float2* g2,
                         float2* g3, const float2* tw, float kf, int nbox, hipStream_t s, int v) {
   return dispatch_n<InvY>(n, f1, f2, g1, g2, g3, tw, kf, nbox, s, v);
+}
+hipError_t launch_inv_xy(int n, const float2* dk, float2* g1, float2* g2, float2* g3,
+                         const float2* tw, const float* rt, int n2max, const float* iw,
+                         float cgreen, float kf, int nbox, hipStream_t s) {
+  return dispatch_n<InvXY>(n, dk, g1, g2, g3, tw, rt, n2max, iw, cgreen, kf, nbox, s);
 }
 hipError_t launch_inv_z(int n, const float2* g1, const float2* g2, const float2* g3, float* out,
                         const float2* tw, float kf, int nbox, hipStream_t s, int v) {

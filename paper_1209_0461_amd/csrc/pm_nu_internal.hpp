@@ -71,6 +71,8 @@ struct Tuning {
   // tile candidate (0 default, 1, 2) of each FFT pass: fwd_z, fwd_y, fwd_x, inv_x, inv_y,
   // inv_z (fft_tile gives the tile); the same result for every candidate
   int fft[6] = {0, 0, 0, 0, 0, 0};
+  // N <= 64: the first two inverse passes as one kernel (inv_xy); 0: as two
+  int inv_xy = 1;
 };
 
 struct Timer {
@@ -85,7 +87,7 @@ struct Timer {
 enum Stage {
   ST_ZERO = 0, ST_DEPOSIT, ST_FFT_Z, ST_FFT_Y, ST_FFT_X_BIN, ST_RESPONSE, ST_RTABLE,
   ST_INV_X_GREEN, ST_INV_Y, ST_INV_Z, ST_INTERP, ST_SURROGATE, ST_PATCH_REDUCE, ST_KICK_DRIFT,
-  ST_PATCH_FWD_Z, ST_COUNT
+  ST_PATCH_FWD_Z, ST_INV_XY, ST_COUNT
 };
 extern const char* const kStageNames[ST_COUNT];
 
@@ -274,6 +276,10 @@ hipError_t launch_inv_x(int N, const float2* dk, float2* f1, float2* f2, const f
 hipError_t launch_inv_y(int N, const float2* f1, const float2* f2, float2* g1, float2* g2,
                         float2* g3, const float2* tw, float kf, int nbox, hipStream_t s,
                         int v = 0);
+// N <= 64: inv_x and inv_y in one kernel (g1 must not be dk: the layouts differ)
+hipError_t launch_inv_xy(int N, const float2* dk, float2* g1, float2* g2, float2* g3,
+                         const float2* tw, const float* rtable, int n2max, const float* inv_w2,
+                         float cgreen, float kf, int nbox, hipStream_t s);
 hipError_t launch_inv_z(int N, const float2* g1, const float2* g2, const float2* g3,
                         float* out, const float2* tw, float kf, int nbox, hipStream_t s,
                         int v = 0);

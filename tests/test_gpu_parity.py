@@ -216,14 +216,20 @@ def test_timing_records_every_stage():
     p = torch.from_numpy(pos).cuda()
     acc = torch.zeros_like(p)
     binding.pm_nu_set_timing(ctx.h, True)
-    for _ in range(2):
-        ctx.step(p, acc, 0.5)
-    t = binding.pm_nu_read_timing(ctx.h)
-    for stage in ("cic_deposit", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x_bin", "nu_response",
-                  "rtable", "inv_x_green", "fft_inv_y", "fft_inv_z", "cic_interp"):
-        ms, n = t[stage]
-        assert n == 2 and ms > 0, stage
-    assert binding.pm_nu_read_timing(ctx.h)["cic_deposit"][1] == 0
+    common = ("cic_deposit", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x_bin", "nu_response", "rtable",
+              "fft_inv_z", "cic_interp")
+    # N = 32: the first two inverse passes run as one kernel by default, as two on request
+    for fused, stages in ((1, ("inv_xy_green",)), (0, ("inv_x_green", "fft_inv_y"))):
+        binding.pm_nu_set_inverse_xy(ctx.h, fused)
+        for _ in range(2):
+            ctx.step(p, acc, 0.5)
+        t = binding.pm_nu_read_timing(ctx.h)
+        for stage in common + stages:
+            ms, n = t[stage]
+            assert n == 2 and ms > 0, (fused, stage)
+        other = ("inv_x_green", "fft_inv_y") if fused else ("inv_xy_green",)
+        assert all(t[s][1] == 0 for s in other), fused
+        assert binding.pm_nu_read_timing(ctx.h)["cic_deposit"][1] == 0
     ctx.close()
 
 
@@ -626,3 +632,32 @@ def test_fused_patch_pass_equals_separate_passes(n_mesh, n_side, box):
         assert torch.equal(r0, r1)
         assert r2 is None
     ctx.close()
+
+
+@pytest.mark.parametrize("n_mesh,n_side,box", [(16, 16, 64.0), (32, 32, 128.0), (64, 64, 256.0)])
+def test_fused_inverse_xy_equals_separate_passes(n_mesh, n_side, box):
+    """For N <= 64 the Green's function and the x and y inverse passes run as one kernel per
+    k_z slab; the forces equal those of the two separate passes bit for bit (two boxes with
+    different masses), and both match the oracle."""
+    import torch
+    from paper_1209_0461_amd import PMNu, binding
+    from synth import log_spaced_nodes, synthetic_history
+    nbox, nb, J = 2, 16, 10
+    pos = np.stack([make_inputs(n_side, box, 0.3, 40 + b) for b in range(nbox)])
+    ctx = PMNu(n_mesh, pos.shape[1], box, nb, J + 2, [0.3, 0.6])
+    nodes = log_spaced_nodes(0.02, 0.7, J)
+    _, counts, kmean = ctx.bins()
+    for b in range(nbox):
+        ctx.set_history(b, synthetic_history(kmean, np.where(counts > 0, 1.0, 0.0), nodes,
+                                             [0.3, 0.6][b]))
+    p = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
+    out = []
+    for fused in (1, 0, 1):
+        binding.pm_nu_set_inverse_xy(ctx.h, fused)
+        acc = torch.zeros_like(p)
+        ctx.step(p, acc, 0.7)
+        torch.cuda.synchronize()
+        out.append(acc.cpu().numpy())
+    ctx.close()
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    assert np.all(np.isfinite(out[0])) and np.abs(out[0]).max() > 0
