@@ -715,8 +715,9 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
 // lines along k_y, and as inv_y_kernel G1 = F1 and G3 = F2 are transformed along y and
 // written to [box][x][k_z][y], then G2 = -i k_y F1 from the registers. The same arithmetic
 // as the two passes in the same order, so the same result bit for bit.
+constexpr int kInvXYNT = 512;   // threads per workgroup of inv_xy_kernel
 template <int N>
-__global__ __launch_bounds__(NT) void inv_xy_kernel(const float2* __restrict__ dk,
+__global__ __launch_bounds__(kInvXYNT) void inv_xy_kernel(const float2* __restrict__ dk,
                                                     float2* __restrict__ g1,
                                                     float2* __restrict__ g2,
                                                     float2* __restrict__ g3,
@@ -724,6 +725,7 @@ __global__ __launch_bounds__(NT) void inv_xy_kernel(const float2* __restrict__ d
                                                     const float* __restrict__ rtable, int n2max,
                                                     const float* __restrict__ inv_w2, float c,
                                                     float kf) {
+  constexpr int NT = kInvXYNT;                     // this kernel's workgroup size
   constexpr int NK = Shape<N>::NK, NL = 2 * N, ES = NL + 1;
   constexpr int PER = (2 * N * N + NT - 1) / NT;    // F1, F2 values each thread holds
   constexpr int GI = (N * N + NT - 1) / NT;         // Green's-function modes per thread
@@ -1101,7 +1103,7 @@ template <int N> struct InvXY {
       return hipErrorInvalidValue;                 // the k_z slab does not fit the LDS
     } else {
       hipLaunchKernelGGL(inv_xy_kernel<N>, dim3(static_cast<unsigned>(Shape<N>::NK * nbox)),
-                         dim3(NT), 0, s, dk, g1, g2, g3, tw, rt, n2max, iw, cfac, kf);
+                         dim3(kInvXYNT), 0, s, dk, g1, g2, g3, tw, rt, n2max, iw, cfac, kf);
       return hipGetLastError();
     }
   }
