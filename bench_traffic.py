@@ -24,7 +24,7 @@ STAGE_OF = {
     "fill_zero_kernel": "zero_mesh", "deposit_kernel": "cic_deposit",
     "deposit_tiled_kernel": "cic_deposit", "fwd_z_kernel": "fft_fwd_z",
     "fwd_y_kernel": "fft_fwd_y", "fwd_x_bin_kernel": "fft_fwd_x_bin",
-    "response_kernel": "nu_response", "rtable_kernel": "rtable",
+    "response_kernel": "nu_response",
     "inv_x_kernel": "inv_x_green", "inv_y_kernel": "fft_inv_y", "inv_z_kernel": "fft_inv_z",
     "interp_kernel": "cic_interp", "interp_tiled_kernel": "cic_interp",
     "deposit_patch_kernel": "cic_deposit", "patch_reduce_kernel": "patch_reduce",

@@ -212,8 +212,9 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
             return launch_fwd_x_bin(c->N, c->ck[0], c->tw, c->bin_of_n2, c->bin_partial, c->B,
                                     c->nbox, c->stream, v);
           case 3:
-            return launch_inv_x(c->N, c->ck[0], c->ck[1], c->ck[2], c->tw, c->rtable, c->n2max,
-                                c->inv_w2, cgreen, kf, c->nbox, c->stream, v);
+            return launch_inv_x(c->N, c->ck[0], c->ck[1], c->ck[2], c->tw, c->ridx, c->d_next,
+                                c->ratio, c->d_resp, c->B, c->inv_w2, cgreen, kf, c->nbox,
+                                c->stream, v);
           case 4:
             return launch_inv_y(c->N, c->ck[1], c->ck[2], c->ck[0], c->ck[3], c->ck[4], c->tw, kf,
                                 c->nbox, c->stream, v);

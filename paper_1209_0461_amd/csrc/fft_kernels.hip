@@ -617,12 +617,31 @@ __global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data
 }
 
 // ------------------------------------------------------------------------ inverse ----
+// The neutrino factor of eq. (phases), T(n^2) = (1 - f_nu) + f_nu R(|k|), with R linear in
+// ln k between the bracketing non-empty bins: e packs the lower bin and the weight t of the
+// upper one (fixed by the geometry); s_ad holds per bin the step's (1 - f_nu) + f_nu R[b]
+// and f_nu (R[next(b)] - R[b]).
+__device__ __forceinline__ void stage_ratio(double2* s_ad, const double* ratio, const int* next,
+                                            double f, int nbins, int tid, int nt) {
+  for (int b = tid; b < nbins; b += nt) {
+    const double r = ratio[b];
+    s_ad[b] = make_double2((1.0 - f) + f * r, f * (ratio[next[b]] - r));
+  }
+}
+__device__ __forceinline__ float neutrino_factor(uint32_t e, const double2* s_ad) {
+  const double2 ad = s_ad[e & ((1u << kRatioBinBits) - 1)];
+  return static_cast<float>(ad.x + static_cast<double>(e >> kRatioBinBits) * kRatioUnit * ad.y);
+}
+
 template <int N, int TX>
 __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk,
                                                    float2* __restrict__ f1,
                                                    float2* __restrict__ f2,
                                                    const float2* __restrict__ twg,
-                                                   const float* __restrict__ rtable, int n2max,
+                                                   const uint32_t* __restrict__ ridx,
+                                                   const int* __restrict__ next,
+                                                   const double* __restrict__ ratio,
+                                                   const RespBox* __restrict__ boxes, int nbins,
                                                    const float* __restrict__ inv_w2,
                                                    float c, float kf, int nbox) {
   constexpr int NL = 2 * TX, ES = NL + 1, NK = Shape<N>::NK;
@@ -630,6 +649,7 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
   __shared__ float s_iw[N];
+  extern __shared__ double2 s_ad[];                // [nbins] (dynamic)
   // Workgroups go to the 8 XCDs in turn; the remap gives each XCD a contiguous run of
   // (k_y block, k_z) tiles, so the two workgroups writing the halves of a 128-byte line
   // (TX = 8 complex values = 64 bytes per row) share one L2 instead of each fetching it.
@@ -640,20 +660,21 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
   const int y0 = (logical % NYB) * TX, kz = (logical / NYB) % NK, box = logical / (NYB * NK);
   load_twiddles<N, NT>(tw, twg);
   for (int m = threadIdx.x; m < N; m += NT) s_iw[m] = inv_w2[m];
+  stage_ratio(s_ad, ratio + static_cast<size_t>(box) * nbins, next, boxes[box].f_nu, nbins,
+              threadIdx.x, NT);
   const size_t off = ((static_cast<size_t>(box) * NK + kz) * N) * N + y0;
-  const float* rt = rtable + static_cast<size_t>(box) * (n2max + 1);
   const float wz = inv_w2[kz];
-  // T(n^2) of this thread's Green's-function modes, fetched before the transform so that
-  // the gathers' latency hides behind it (0: the k = 0 mode)
+  // where n^2 of this thread's Green's-function modes falls among the bins, fetched before
+  // the tile so that the gathers' latency hides behind its loads
   constexpr int GI = (N * TX + NT - 1) / NT;
-  float tv[GI];
+  uint32_t ri[GI];
 #pragma unroll
   for (int i = 0; i < GI; ++i) {
     const int t = threadIdx.x + i * NT;
     const int y = t % TX, x = t / TX;
     const int nx = signed_index(x, N), ny = signed_index(y0 + y, N);
     const int n2 = nx * nx + ny * ny + kz * kz;
-    tv[i] = (t < N * TX && n2 > 0) ? rt[n2] : 0.f;
+    ri[i] = ridx[t < N * TX ? n2 : 0];
   }
   // the tile holds x (real space) by k_y: forward transform along x first (lines 0..TX-1)
   constexpr int P = TX / 2, IT = (N * P + NT - 1) / NT;
@@ -674,6 +695,9 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
     }
   }
   __syncthreads();
+  float tv[GI];                                    // T(n^2) (unused at the k = 0 mode)
+#pragma unroll
+  for (int i = 0; i < GI; ++i) tv[i] = neutrino_factor(ri[i], s_ad);
   fft_lines<N, TX, NT, -1, ES>(lds, tw);
   // delta_M -> phi and -i k_x phi, in place on the (k_x, k_y) tile
 #pragma unroll
@@ -722,7 +746,10 @@ __global__ __launch_bounds__(kInvXYNT) void inv_xy_kernel(const float2* __restri
                                                     float2* __restrict__ g2,
                                                     float2* __restrict__ g3,
                                                     const float2* __restrict__ twg,
-                                                    const float* __restrict__ rtable, int n2max,
+                                                    const uint32_t* __restrict__ ridx,
+                                                    const int* __restrict__ next,
+                                                    const double* __restrict__ ratio,
+                                                    const RespBox* __restrict__ boxes, int nbins,
                                                     const float* __restrict__ inv_w2, float c,
                                                     float kf) {
   constexpr int NT = kInvXYNT;                     // this kernel's workgroup size
@@ -733,22 +760,25 @@ __global__ __launch_bounds__(kInvXYNT) void inv_xy_kernel(const float2* __restri
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
   __shared__ float s_iw[N];
+  extern __shared__ double2 s_ad[];                // [nbins] (dynamic)
   const int tid = threadIdx.x;
   const int kz = static_cast<int>(blockIdx.x) % NK, box = static_cast<int>(blockIdx.x) / NK;
   load_twiddles<N, NT>(tw, twg);
   for (int m = tid; m < N; m += NT) s_iw[m] = inv_w2[m];
+  stage_ratio(s_ad, ratio + static_cast<size_t>(box) * nbins, next, boxes[box].f_nu, nbins, tid,
+              NT);
   const size_t off = (static_cast<size_t>(box) * NK + kz) * N * N;   // the slab, [x][k_y]
-  const float* rt = rtable + static_cast<size_t>(box) * (n2max + 1);
   const float wz = inv_w2[kz];
-  // T(n^2) of this thread's modes first (gathers whose latency hides behind the transform)
-  float tv[GI];
+  // where n^2 of this thread's modes falls among the bins, fetched before the slab so that
+  // the gathers' latency hides behind its loads
+  uint32_t ri[GI];
 #pragma unroll
   for (int i = 0; i < GI; ++i) {
     const int t = tid + i * NT;
     const int y = t % N, x = t / N;
     const int nx = signed_index(x, N), ny = signed_index(y, N);
     const int n2 = nx * nx + ny * ny + kz * kz;
-    tv[i] = (t < N * N && n2 > 0) ? rt[n2] : 0.f;
+    ri[i] = ridx[t < N * N ? n2 : 0];
   }
   // the slab: element x of line k_y at lds[x ES + k_y]
   {
@@ -769,6 +799,9 @@ __global__ __launch_bounds__(kInvXYNT) void inv_xy_kernel(const float2* __restri
     }
   }
   __syncthreads();
+  float tv[GI];                                    // T(n^2) (unused at the k = 0 mode)
+#pragma unroll
+  for (int i = 0; i < GI; ++i) tv[i] = neutrino_factor(ri[i], s_ad);
   fft_lines<N, N, NT, -1, ES>(lds, tw);
   // delta_M -> phi (lines 0..N-1) and -i k_x phi (lines N..2N-1)
 #pragma unroll
@@ -1073,14 +1106,16 @@ template <int N> struct FwdX {
 };
 template <int N> struct InvX {
   static hipError_t run(const float2* dk, float2* f1, float2* f2, const float2* tw,
-                        const float* rt, int n2max, const float* iw, float cfac,
-                        float kf, int nbox, hipStream_t s, int v) {
+                        const uint32_t* ridx, const int* next, const double* ratio,
+                        const RespBox* boxes, int nbins, const float* iw, float cfac, float kf,
+                        int nbox,
+                        hipStream_t s, int v) {
     auto go = [&](auto txv) -> hipError_t {
       constexpr int TX = decltype(txv)::value;
       const int total = N / TX * Shape<N>::NK * nbox;
       dim3 grid((total + 7) / 8 * 8);   // whole rounds over the 8 XCDs; extra blocks exit
-      hipLaunchKernelGGL((inv_x_kernel<N, TX>), grid, dim3(NT), 0, s, dk, f1, f2, tw, rt, n2max,
-                         iw, cfac, kf, nbox);
+      hipLaunchKernelGGL((inv_x_kernel<N, TX>), grid, dim3(NT), nbins * sizeof(double2), s, dk,
+                         f1, f2, tw, ridx, next, ratio, boxes, nbins, iw, cfac, kf, nbox);
       return hipGetLastError();
     };
     return with_tile<PMNU_TILES(IX)>(go, v);
@@ -1101,13 +1136,16 @@ template <int N> struct InvY {
 };
 template <int N> struct InvXY {
   static hipError_t run(const float2* dk, float2* g1, float2* g2, float2* g3, const float2* tw,
-                        const float* rt, int n2max, const float* iw, float cfac, float kf,
-                        int nbox, hipStream_t s) {
+                        const uint32_t* ridx, const int* next, const double* ratio,
+                        const RespBox* boxes, int nbins, const float* iw, float cfac, float kf,
+                        int nbox,
+                        hipStream_t s) {
     if constexpr (N > 64) {
       return hipErrorInvalidValue;                 // the k_z slab does not fit the LDS
     } else {
       hipLaunchKernelGGL(inv_xy_kernel<N>, dim3(static_cast<unsigned>(Shape<N>::NK * nbox)),
-                         dim3(kInvXYNT), 0, s, dk, g1, g2, g3, tw, rt, n2max, iw, cfac, kf);
+                         dim3(kInvXYNT), nbins * sizeof(double2), s, dk, g1, g2, g3, tw, ridx,
+                         next, ratio, boxes, nbins, iw, cfac, kf);
       return hipGetLastError();
     }
   }
@@ -1203,18 +1241,22 @@ int fft_tile(int n, int pass, int v) {
   return out;
 }
 hipError_t launch_inv_x(int n, const float2* dk, float2* f1, float2* f2, const float2* tw,
-                        const float* rtable, int n2max, const float* inv_w2,
-                        float cfac, float kf, int nbox, hipStream_t s, int v) {
-  return dispatch_n<InvX>(n, dk, f1, f2, tw, rtable, n2max, inv_w2, cfac, kf, nbox, s, v);
+                        const uint32_t* ridx, const int* next, const double* ratio,
+                        const RespBox* boxes, int nbins, const float* inv_w2, float cfac,
+                        float kf, int nbox, hipStream_t s, int v) {
+  return dispatch_n<InvX>(n, dk, f1, f2, tw, ridx, next, ratio, boxes, nbins, inv_w2, cfac, kf,
+                          nbox, s, v);
 }
 hipError_t launch_inv_y(int n, const float2* f1, const float2* f2, float2* g1, float2* g2,
                         float2* g3, const float2* tw, float kf, int nbox, hipStream_t s, int v) {
   return dispatch_n<InvY>(n, f1, f2, g1, g2, g3, tw, kf, nbox, s, v);
 }
 hipError_t launch_inv_xy(int n, const float2* dk, float2* g1, float2* g2, float2* g3,
-                         const float2* tw, const float* rt, int n2max, const float* iw,
+                         const float2* tw, const uint32_t* ridx, const int* next,
+                         const double* ratio, const RespBox* boxes, int nbins, const float* iw,
                          float cgreen, float kf, int nbox, hipStream_t s) {
-  return dispatch_n<InvXY>(n, dk, g1, g2, g3, tw, rt, n2max, iw, cgreen, kf, nbox, s);
+  return dispatch_n<InvXY>(n, dk, g1, g2, g3, tw, ridx, next, ratio, boxes, nbins, iw, cgreen,
+                           kf, nbox, s);
 }
 hipError_t launch_inv_z(int n, const float2* g1, const float2* g2, const float2* g3, float* out,
                         const float2* tw, float kf, int nbox, hipStream_t s, int v) {

@@ -22,7 +22,7 @@ namespace pmnu {
 
 const char* const kStageNames[ST_COUNT] = {
     "zero_mesh", "cic_deposit", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x_bin", "nu_response",
-    "rtable", "inv_x_green", "fft_inv_y", "fft_inv_z", "cic_interp", "surrogate",
+    "inv_x_green", "fft_inv_y", "fft_inv_z", "cic_interp", "surrogate",
     "patch_reduce", "kick_drift", "patch_fwd_z", "inv_xy_green"};
 
 namespace {
@@ -366,10 +366,6 @@ int do_response_mode(Ctx& c, double a_now, int mode) {
     int rc = surrogate_launch(c, mode, norm);
     if (rc) return rc;
   }
-  TIMED(c, ST_RTABLE,
-        launch_rtable(c.ratio, c.d_lnk, c.d_nonempty, static_cast<int>(c.nonempty.size()),
-                      c.d_resp, c.B, c.n2max, 2.0 * kPi / c.cfg.box_size, c.nbox, c.rtable,
-                      c.stream));
   // commit the node on the host side (the kernel wrote row n_cur)
   for (int b = 0; b < c.nbox; ++b) {
     std::vector<double>& ha = c.hist_a[b];
@@ -402,12 +398,14 @@ int do_force(Ctx& c, const float* pos, float* acc, double a_now, const Leap* lp 
   float2* g1 = inv_xy ? c.ck[1] : c.ck[0];
   if (inv_xy) {
     TIMED(c, ST_INV_XY,
-          launch_inv_xy(c.N, c.ck[0], g1, c.ck[3], c.ck[4], c.tw, c.rtable, c.n2max, c.inv_w2,
-                        static_cast<float>(cgreen), kf, c.nbox, c.stream));
+          launch_inv_xy(c.N, c.ck[0], g1, c.ck[3], c.ck[4], c.tw, c.ridx, c.d_next, c.ratio,
+                        c.d_resp, c.B, c.inv_w2, static_cast<float>(cgreen), kf, c.nbox,
+                        c.stream));
   } else {
     TIMED(c, ST_INV_X_GREEN,
-          launch_inv_x(c.N, c.ck[0], c.ck[1], c.ck[2], c.tw, c.rtable, c.n2max, c.inv_w2,
-                       static_cast<float>(cgreen), kf, c.nbox, c.stream, c.tune.fft[3]));
+          launch_inv_x(c.N, c.ck[0], c.ck[1], c.ck[2], c.tw, c.ridx, c.d_next, c.ratio,
+                       c.d_resp, c.B, c.inv_w2, static_cast<float>(cgreen), kf, c.nbox, c.stream,
+                       c.tune.fft[3]));
     TIMED(c, ST_INV_Y, launch_inv_y(c.N, c.ck[1], c.ck[2], g1, c.ck[3], c.ck[4], c.tw, kf,
                                     c.nbox, c.stream, c.tune.fft[4]));
   }
@@ -429,7 +427,7 @@ void free_ctx(Ctx* c) {
                   c->bin_partial,
                   c->bin_of_n2, c->d_counts, c->d_kmean, c->d_lnk, c->d_nonempty, c->pcdm, c->pnu,
                   c->ratio, c->hist_pm, c->hist_pnu, c->ic_pnu, c->ic_theta, c->tg_ds,
-                  c->tg_l2, c->tg_w, c->d_resp, c->rtable, c->tw, c->inv_w2, c->d_flags, c->patches,
+                  c->tg_l2, c->tg_w, c->d_resp, c->ridx, c->d_next, c->tw, c->inv_w2, c->d_flags, c->patches,
                   c->reg_count, c->reg_list, c->rho_fb, c->n_fb,
                   c->delta, c->d_kd};
   for (void* p : bufs)
@@ -556,7 +554,8 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   ALLOC(c->tg_l2, nb * c->qcap);
   ALLOC(c->tg_w, nb * c->qcap);
   ALLOC(c->d_resp, nb);
-  ALLOC(c->rtable, nb * (static_cast<size_t>(c->n2max) + 1));
+  ALLOC(c->ridx, static_cast<size_t>(c->n2max) + 1);
+  ALLOC(c->d_next, B);
   ALLOC(c->tw, static_cast<size_t>(c->N));
   ALLOC(c->inv_w2, static_cast<size_t>(c->N));
   ALLOC(c->d_flags, 1);
@@ -600,6 +599,9 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   }
   std::vector<int> ne(c->nonempty);
   ne.resize(B, 0);
+  std::vector<int> next(B);                       // next non-empty bin (the last: itself)
+  for (size_t b = 0; b < B; ++b) next[b] = static_cast<int>(b);
+  for (size_t i = 0; i + 1 < c->nonempty.size(); ++i) next[c->nonempty[i]] = c->nonempty[i + 1];
   hipError_t e = hipSuccess;
   e = e ? e : hipMemcpy(c->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice);
   e = e ? e : hipMemcpy(c->inv_w2, iw.data(), iw.size() * sizeof(float), hipMemcpyHostToDevice);
@@ -609,6 +611,9 @@ int pm_nu_init(const pm_nu_config* cfg, const double* m_nu_total, pm_nu_ctx** ou
   for (size_t b = 0; b < B; ++b) lnk[b] = c->kmean[b] > 0 ? std::log(c->kmean[b]) : 0.0;
   e = e ? e : hipMemcpy(c->d_lnk, lnk.data(), B * sizeof(double), hipMemcpyHostToDevice);
   e = e ? e : hipMemcpy(c->d_nonempty, ne.data(), B * sizeof(int), hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(c->d_next, next.data(), B * sizeof(int), hipMemcpyHostToDevice);
+  e = e ? e : launch_ratio_index(c->d_lnk, c->d_nonempty, static_cast<int>(c->nonempty.size()),
+                                 c->n2max, 2.0 * kPi / cfg->box_size, c->ridx, nullptr);
   e = e ? e : hipMemset(c->d_flags, 0, sizeof(int));
   e = e ? e : hipMemset(c->hist_pm, 0, nb * c->Jcap * B * sizeof(double));
   e = e ? e : hipMemset(c->hist_pnu, 0, nb * c->Jcap * B * sizeof(double));

@@ -85,13 +85,20 @@ struct Timer {
 };
 
 enum Stage {
-  ST_ZERO = 0, ST_DEPOSIT, ST_FFT_Z, ST_FFT_Y, ST_FFT_X_BIN, ST_RESPONSE, ST_RTABLE,
-  ST_INV_X_GREEN, ST_INV_Y, ST_INV_Z, ST_INTERP, ST_SURROGATE, ST_PATCH_REDUCE, ST_KICK_DRIFT,
+  ST_ZERO = 0, ST_DEPOSIT, ST_FFT_Z, ST_FFT_Y, ST_FFT_X_BIN, ST_RESPONSE, ST_INV_X_GREEN, ST_INV_Y, ST_INV_Z, ST_INTERP, ST_SURROGATE, ST_PATCH_REDUCE, ST_KICK_DRIFT,
   ST_PATCH_FWD_Z, ST_INV_XY, ST_COUNT
 };
 extern const char* const kStageNames[ST_COUNT];
 
 struct Surrogate;  // defined in surrogate.cpp
+
+// Where |n|^2 falls among the non-empty bins, packed in 32 bits: bits 0..9 the bin lo of
+// the lower bracketing mean, bits 10..31 the weight t of the next non-empty bin in units of
+// 2^-22, so that R(|k|) = R[lo] + t (R[next(lo)] - R[lo]) (t = 0 below the first and above
+// the last bin mean, and at n^2 = 0). Fixed by the geometry; the first inverse pass forms
+// the step's T(n^2) from it.
+constexpr int kRatioBinBits = 10;                 // kMaxBins = 2^10
+constexpr double kRatioUnit = 1.0 / 4194304.0;    // 2^-22
 
 // Per box: the quadrature sub-nodes of the intervals between stored history nodes (they do
 // not change as the history grows, only the interval to the current step does).
@@ -149,7 +156,8 @@ struct Ctx {
   double* tg_l2 = nullptr;         // [nbox][qcap] log2 of tg_ds (the fit's x^0.1811)
   double* tg_w = nullptr;          // [nbox][qcap]
   RespBox* d_resp = nullptr;       // [nbox]
-  float* rtable = nullptr;         // [nbox][n2max+1]
+  uint32_t* ridx = nullptr;        // [n2max+1] packed bin and weight of |n|^2
+  int* d_next = nullptr;           // [B] next non-empty bin after each non-empty bin (or itself)
   float2* tw = nullptr;            // [N] exp(-2 pi i m/N)
   float* inv_w2 = nullptr;         // [N] 1/sinc^4(pi n/N) per axis index (or 1)
   int* d_flags = nullptr;          // [1] bit 0: non-finite position seen
@@ -221,6 +229,7 @@ void surrogate_free(Ctx& c);
 // grid_kernels.hip
 constexpr double kFixScale = 1099511627776.0;   // 2^40: fixed-point unit of the deposit
 constexpr int kMaxBins = 1024;                   // largest n_kbins
+static_assert(kMaxBins <= (1 << kRatioBinBits), "bin index of the packed ratio index");
 // patch deposit (deposit mode 6): chunk of particles, LDS tile / patch capacity in nodes,
 // threads per workgroup
 // patch deposit: chunks of kPatchCH particles on kPatchNT threads; the LDS tile holds
@@ -270,16 +279,20 @@ int fwd_x_partials(int N, int v = 0);
 // tile of FFT pass `pass` (0 fwd_z rows, 1 fwd_y lines, 2 fwd_x columns, 3 inv_x columns,
 // 4 inv_y lines, 5 inv_z rows) for candidate v (0 default, 1, 2); 0 for a bad N or pass
 int fft_tile(int N, int pass, int v);
+// T(n^2) = (1 - f_nu) + f_nu R from ridx and next, the per-bin R ([nbox][nbins]) and the
+// boxes' f_nu
 hipError_t launch_inv_x(int N, const float2* dk, float2* f1, float2* f2, const float2* tw,
-                        const float* rtable, int n2max, const float* inv_w2,
-                        float cfac, float kf, int nbox, hipStream_t s, int v = 0);
+                        const uint32_t* ridx, const int* next, const double* ratio,
+                        const RespBox* boxes, int nbins, const float* inv_w2, float cfac,
+                        float kf, int nbox, hipStream_t s, int v = 0);
 hipError_t launch_inv_y(int N, const float2* f1, const float2* f2, float2* g1, float2* g2,
                         float2* g3, const float2* tw, float kf, int nbox, hipStream_t s,
                         int v = 0);
 // N <= 64: inv_x and inv_y in one kernel (g1 must not be dk: the layouts differ)
 hipError_t launch_inv_xy(int N, const float2* dk, float2* g1, float2* g2, float2* g3,
-                         const float2* tw, const float* rtable, int n2max, const float* inv_w2,
-                         float cgreen, float kf, int nbox, hipStream_t s);
+                         const float2* tw, const uint32_t* ridx, const int* next,
+                         const double* ratio, const RespBox* boxes, int nbins,
+                         const float* inv_w2, float cgreen, float kf, int nbox, hipStream_t s);
 hipError_t launch_inv_z(int N, const float2* g1, const float2* g2, const float2* g3,
                         float* out, const float2* tw, float kf, int nbox, hipStream_t s,
                         int v = 0);
@@ -339,8 +352,7 @@ hipError_t launch_kernel_values(const double* x, int64_t n, int series, double* 
                                 hipStream_t s);
 hipError_t launch_bin_power(const double* partial, int n_partial, const double* counts,
                             int nbins, double norm, int nbox, double* pcdm, hipStream_t s);
-hipError_t launch_rtable(const double* ratio, const double* lnk, const int* nonempty,
-                         int n_nonempty, const RespBox* boxes, int B, int n2max, double kf,
-                         int nbox, float* rtable, hipStream_t s);
+hipError_t launch_ratio_index(const double* lnk, const int* nonempty, int n_nonempty,
+                              int n2max, double kf, uint32_t* out, hipStream_t s);
 
 }  // namespace pmnu

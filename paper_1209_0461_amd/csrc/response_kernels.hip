@@ -20,8 +20,11 @@
 // I(x) is the rational fit of the paper's Appendix C, eq. (fit), or (per box) the exact
 // alternating series of the same appendix, accelerated.
 //
-// rtable_kernel: T(n^2) = (1 - f_nu) + f_nu R(|k|) for every integer n^2 in [0, 3N^2/4]
-// with R linear in ln k between the means of the non-empty bins, held at the end values.
+// ratio_index_kernel (once per geometry): for every integer n^2 in [0, 3N^2/4] the lower of
+// the two non-empty bins whose means bracket ln(k_f |n|) and the weight of the upper one,
+// packed in 32 bits, so that R(|k|) is linear in ln k between the means of the non-empty
+// bins and held at the end values outside them; the first inverse pass turns it and the
+// step's R into T(n^2) = (1 - f_nu) + f_nu R(|k|) (eq. (phases)).
 #include "response_device.hpp"
 
 namespace pmnu {
@@ -235,46 +238,43 @@ __global__ __launch_bounds__(RT) void bin_power_kernel(const double* __restrict_
     pcdm_out[static_cast<size_t>(box) * nbins + b] = counts[b] > 0.0 ? norm * s / counts[b] : 0.0;
 }
 
-__global__ __launch_bounds__(256) void rtable_kernel(const double* __restrict__ ratio,
-                                                     const double* __restrict__ lnk,
-                                                     const int* __restrict__ nonempty,
-                                                     int n_nonempty,
-                                                     const RespBox* __restrict__ boxes,
-                                                     int nbins, int n2max, double kf,
-                                                     float* __restrict__ rtable) {
-  // ln k and R of the non-empty bins, staged once per workgroup (the search runs in LDS)
-  __shared__ double s_lk[kMaxBins], s_r[kMaxBins];
-  const int box = blockIdx.y;
-  const double* rb = ratio + static_cast<size_t>(box) * nbins;
+__global__ __launch_bounds__(256) void ratio_index_kernel(const double* __restrict__ lnk,
+                                                          const int* __restrict__ nonempty,
+                                                          int n_nonempty, int n2max, double kf,
+                                                          uint32_t* __restrict__ out) {
+  // ln k of the non-empty bins, staged once per workgroup (the search runs in LDS)
+  __shared__ double s_lk[kMaxBins];
+  __shared__ int s_bin[kMaxBins];
   for (int i = threadIdx.x; i < n_nonempty; i += blockDim.x) {
-    const int b = nonempty[i];
-    s_lk[i] = lnk[b];
-    s_r[i] = rb[b];
+    s_bin[i] = nonempty[i];
+    s_lk[i] = lnk[nonempty[i]];
   }
   __syncthreads();
   const int n2 = blockIdx.x * blockDim.x + threadIdx.x;
   if (n2 > n2max) return;
-  const double f = boxes[box].f_nu;
-  double r;
-  if (n2 == 0) {
-    r = s_r[0];
-  } else {
+  int a = 0, z = 0;
+  double t = 0.0;
+  if (n2 > 0) {
     const double lk = log(kf * sqrt(static_cast<double>(n2)));
-    if (lk <= s_lk[0]) {
-      r = s_r[0];
-    } else if (lk >= s_lk[n_nonempty - 1]) {
-      r = s_r[n_nonempty - 1];
-    } else {
-      int a = 0, z = n_nonempty - 1;   // s_lk[a] <= lk < s_lk[z]
+    if (lk >= s_lk[n_nonempty - 1]) {
+      a = z = n_nonempty - 1;
+    } else if (lk > s_lk[0]) {
+      z = n_nonempty - 1;                 // s_lk[a] <= lk < s_lk[z]
       while (z - a > 1) {
         const int mid = (a + z) >> 1;
         if (s_lk[mid] <= lk) a = mid; else z = mid;
       }
-      const double t = (lk - s_lk[a]) / (s_lk[z] - s_lk[a]);
-      r = s_r[a] + t * (s_r[z] - s_r[a]);
+      t = (lk - s_lk[a]) / (s_lk[z] - s_lk[a]);
     }
   }
-  rtable[static_cast<size_t>(box) * (n2max + 1) + n2] = static_cast<float>((1.0 - f) + f * r);
+  // t in units of 2^-22 (error <= 2^-23, far below the FP32 rounding of T); a weight that
+  // rounds to 1 is the upper bin itself
+  uint32_t q = static_cast<uint32_t>(rint(t * 4194304.0));
+  if (q >= (1u << 22)) {
+    a = z;
+    q = 0;
+  }
+  out[n2] = static_cast<uint32_t>(s_bin[a]) | (q << kRatioBinBits);
 }
 
 // I(x) at n points, the fit or the exact series (a diagnostic of the device kernels).
@@ -354,12 +354,11 @@ hipError_t launch_bin_power(const double* partial, int n_partial, const double* 
   return hipGetLastError();
 }
 
-hipError_t launch_rtable(const double* ratio, const double* lnk, const int* nonempty,
-                         int n_nonempty, const RespBox* boxes, int nbins, int n2max, double kf,
-                         int nbox, float* rtable, hipStream_t s) {
-  dim3 grid((n2max + 1 + 255) / 256, nbox);
-  hipLaunchKernelGGL(rtable_kernel, grid, dim3(256), 0, s, ratio, lnk, nonempty, n_nonempty,
-                     boxes, nbins, n2max, kf, rtable);
+hipError_t launch_ratio_index(const double* lnk, const int* nonempty, int n_nonempty,
+                              int n2max, double kf, uint32_t* out, hipStream_t s) {
+  if (n_nonempty < 1 || n_nonempty > kMaxBins) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(ratio_index_kernel, dim3((n2max + 1 + 255) / 256), dim3(256), 0, s, lnk,
+                     nonempty, n_nonempty, n2max, kf, out);
   return hipGetLastError();
 }
 

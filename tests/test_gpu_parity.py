@@ -216,7 +216,7 @@ def test_timing_records_every_stage():
     p = torch.from_numpy(pos).cuda()
     acc = torch.zeros_like(p)
     binding.pm_nu_set_timing(ctx.h, True)
-    common = ("cic_deposit", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x_bin", "nu_response", "rtable",
+    common = ("cic_deposit", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x_bin", "nu_response",
               "fft_inv_z", "cic_interp")
     # N = 32: the first two inverse passes run as one kernel by default, as two on request
     for fused, stages in ((1, ("inv_xy_green",)), (0, ("inv_x_green", "fft_inv_y"))):
