@@ -37,7 +37,7 @@ KERNEL_SOURCES = {
     "inv_x_green": "fft_kernels.hip", "fft_inv_y": "fft_kernels.hip",
     "inv_xy_green": "fft_kernels.hip",
     "fft_inv_z": "fft_kernels.hip", "nu_response": "response_kernels.hip",
-    "rtable": "response_kernels.hip", "patch_reduce": "grid_kernels.hip",
+    "patch_reduce": "grid_kernels.hip",
     "kick_drift": "advance_kernels.hip", "patch_fwd_z": "fft_kernels.hip",
 }
 
@@ -61,7 +61,6 @@ def stage_bytes(n_mesh, n_part, nbox, nbins, n_hist, n_partial, deposit_mode=0):
         "fft_fwd_y": 16 * mh,
         "fft_fwd_x_bin": 16 * mh + 8 * n_partial * nbins * nbox,
         "nu_response": 8 * nbox * nbins * (2 * n_hist + n_partial + 8),
-        "rtable": 4 * nbox * (3 * n_mesh * n_mesh // 4 + 1),
         "inv_x_green": 8 * mh + 16 * mh,
         "fft_inv_y": 16 * mh + 24 * mh,
         "inv_xy_green": 8 * mh + 24 * mh,
@@ -101,7 +100,7 @@ def kernel_name(stage, tuning, n_mesh):
             return "interp_tiled_kernel" + itp[m]
         return "interp_kernel<%d, false>" % max(1, min(4, tuning["interp_block"] // 256))
     fixed = {"zero_mesh": "fill_zero_kernel", "nu_response": "response_kernel",
-             "rtable": "rtable_kernel", "patch_reduce": "patch_reduce_kernel<8>"}
+             "patch_reduce": "patch_reduce_kernel<8>"}
     if stage in fixed:
         return fixed[stage]
     tiles = tuning.get("fft_tiles", {})
@@ -152,7 +151,9 @@ SURROGATE_BLOB = os.path.join(ROOT, "paper_1209_0461_amd", "data", "surrogate_pm
 
 def measure_surrogate(ctx, binding, pos, acc, a_now, steps, stream, timing_exact, names):
     """Same step with the surrogate response: accuracy of R against the exact integral
-    (check mode, every box and non-empty bin) and the timed step."""
+    (check mode, every box and non-empty bin), the step's rate with the network beside its
+    rate with the integral (the same eager loop, no event pairs) and the network's kernel
+    time (event pairs around it alone)."""
     binding.pm_nu_surrogate_load(ctx.h, np.load(SURROGATE_BLOB))
     binding.pm_nu_set_response_mode(ctx.h, 2)
     ctx.step(pos, acc, a_now)
@@ -163,23 +164,35 @@ def measure_surrogate(ctx, binding, pos, acc, a_now, steps, stream, timing_exact
         ex, su = binding.pm_nu_get_surrogate_check(ctx.h, b, ctx.cfg.n_kbins)
         errs.append(np.abs(su[ok] / ex[ok] - 1.0))
     errs = np.concatenate(errs)
-    binding.pm_nu_set_response_mode(ctx.h, 1)
-    for _ in range(3):
-        ctx.step(pos, acc, a_now)
-    stream.synchronize()
+    def rate(mode):
+        # the same eager step in both response modes, no event pairs, at least 100 steps
+        binding.pm_nu_set_response_mode(ctx.h, mode)
+        for _ in range(3):
+            ctx.step(pos, acc, a_now)
+        stream.synchronize()
+        n = max(steps, 100)
+        t0 = time.perf_counter()
+        for _ in range(n):
+            ctx.step(pos, acc, a_now)
+        stream.synchronize()
+        return n / (time.perf_counter() - t0)
+
+    exact_rate = rate(0)
+    sur_rate = rate(1)
+    # the network's kernel time: event pairs around it alone, in a loop of their own
     binding.pm_nu_read_timing(ctx.h)
+    binding.pm_nu_set_timing(ctx.h, True)
     binding.pm_nu_set_timing_mask(ctx.h, 1 << names.index("surrogate"))
-    t0 = time.perf_counter()
     for _ in range(steps):
         ctx.step(pos, acc, a_now)
     stream.synchronize()
-    dt = time.perf_counter() - t0
     t = binding.pm_nu_read_timing(ctx.h)
     binding.pm_nu_set_timing(ctx.h, False)
     binding.pm_nu_set_response_mode(ctx.h, 0)
     sur_ms = t["surrogate"][0] / max(1, t["surrogate"][1])
     ex_ms = timing_exact["nu_response"][0] / max(1, timing_exact["nu_response"][1])
-    return {"steps_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps,
+    return {"steps_per_s": sur_rate, "ms_per_step": 1e3 / sur_rate,
+            "steps_per_s_exact_same_loop": exact_rate,
             "response_ms_exact": ex_ms, "response_ms_surrogate": sur_ms,
             "R_max_rel_err": float(errs.max()), "R_rms_rel_err": float(np.sqrt(np.mean(errs ** 2))),
             "bar": 1e-3}
