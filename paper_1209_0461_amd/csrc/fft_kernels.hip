@@ -618,19 +618,24 @@ __global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data
 
 // ------------------------------------------------------------------------ inverse ----
 // The neutrino factor of eq. (phases), T(n^2) = (1 - f_nu) + f_nu R(|k|), with R linear in
-// ln k between the bracketing non-empty bins: e packs the lower bin and the weight t of the
-// upper one (fixed by the geometry); s_ad holds per bin the step's (1 - f_nu) + f_nu R[b]
-// and f_nu (R[next(b)] - R[b]).
-__device__ __forceinline__ void stage_ratio(double2* s_ad, const double* ratio, const int* next,
-                                            double f, int nbins, int tid, int nt) {
+// ln k between the bracketing non-empty bins: e packs the lower bin lo and the weight t of
+// the upper one, next(lo) (both fixed by the geometry); the step's per-bin R and next are
+// staged in LDS (dynamic: nbins doubles, then nbins ints), with independent loads.
+__device__ __forceinline__ void stage_ratio(double* s_r, const double* ratio, const int* next,
+                                            int nbins, int tid, int nt) {
+  int* s_next = reinterpret_cast<int*>(s_r + nbins);
   for (int b = tid; b < nbins; b += nt) {
-    const double r = ratio[b];
-    s_ad[b] = make_double2((1.0 - f) + f * r, f * (ratio[next[b]] - r));
+    s_r[b] = ratio[b];
+    s_next[b] = next[b];
   }
 }
-__device__ __forceinline__ float neutrino_factor(uint32_t e, const double2* s_ad) {
-  const double2 ad = s_ad[e & ((1u << kRatioBinBits) - 1)];
-  return static_cast<float>(ad.x + static_cast<double>(e >> kRatioBinBits) * kRatioUnit * ad.y);
+__device__ __forceinline__ float neutrino_factor(uint32_t e, const double* s_r, int nbins,
+                                                 double f) {
+  const int lo = static_cast<int>(e & ((1u << kRatioBinBits) - 1));
+  const int hi = reinterpret_cast<const int*>(s_r + nbins)[lo];
+  const double t = static_cast<double>(e >> kRatioBinBits) * kRatioUnit;
+  const double r = s_r[lo] + t * (s_r[hi] - s_r[lo]);
+  return static_cast<float>((1.0 - f) + f * r);
 }
 
 template <int N, int TX>
@@ -649,7 +654,7 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
   __shared__ float s_iw[N];
-  extern __shared__ double2 s_ad[];                // [nbins] (dynamic)
+  extern __shared__ double s_r[];                  // R and next of this box (dynamic)
   // Workgroups go to the 8 XCDs in turn; the remap gives each XCD a contiguous run of
   // (k_y block, k_z) tiles, so the two workgroups writing the halves of a 128-byte line
   // (TX = 8 complex values = 64 bytes per row) share one L2 instead of each fetching it.
@@ -660,10 +665,10 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
   const int y0 = (logical % NYB) * TX, kz = (logical / NYB) % NK, box = logical / (NYB * NK);
   load_twiddles<N, NT>(tw, twg);
   for (int m = threadIdx.x; m < N; m += NT) s_iw[m] = inv_w2[m];
-  stage_ratio(s_ad, ratio + static_cast<size_t>(box) * nbins, next, boxes[box].f_nu, nbins,
-              threadIdx.x, NT);
+  stage_ratio(s_r, ratio + static_cast<size_t>(box) * nbins, next, nbins, threadIdx.x, NT);
   const size_t off = ((static_cast<size_t>(box) * NK + kz) * N) * N + y0;
   const float wz = inv_w2[kz];
+  const double fnu = boxes[box].f_nu;
   // where n^2 of this thread's Green's-function modes falls among the bins, fetched before
   // the tile so that the gathers' latency hides behind its loads
   constexpr int GI = (N * TX + NT - 1) / NT;
@@ -697,7 +702,7 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
   __syncthreads();
   float tv[GI];                                    // T(n^2) (unused at the k = 0 mode)
 #pragma unroll
-  for (int i = 0; i < GI; ++i) tv[i] = neutrino_factor(ri[i], s_ad);
+  for (int i = 0; i < GI; ++i) tv[i] = neutrino_factor(ri[i], s_r, nbins, fnu);
   fft_lines<N, TX, NT, -1, ES>(lds, tw);
   // delta_M -> phi and -i k_x phi, in place on the (k_x, k_y) tile
 #pragma unroll
@@ -760,15 +765,15 @@ __global__ __launch_bounds__(kInvXYNT) void inv_xy_kernel(const float2* __restri
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
   __shared__ float s_iw[N];
-  extern __shared__ double2 s_ad[];                // [nbins] (dynamic)
+  extern __shared__ double s_r[];                  // R and next of this box (dynamic)
   const int tid = threadIdx.x;
   const int kz = static_cast<int>(blockIdx.x) % NK, box = static_cast<int>(blockIdx.x) / NK;
   load_twiddles<N, NT>(tw, twg);
   for (int m = tid; m < N; m += NT) s_iw[m] = inv_w2[m];
-  stage_ratio(s_ad, ratio + static_cast<size_t>(box) * nbins, next, boxes[box].f_nu, nbins, tid,
-              NT);
+  stage_ratio(s_r, ratio + static_cast<size_t>(box) * nbins, next, nbins, tid, NT);
   const size_t off = (static_cast<size_t>(box) * NK + kz) * N * N;   // the slab, [x][k_y]
   const float wz = inv_w2[kz];
+  const double fnu = boxes[box].f_nu;
   // where n^2 of this thread's modes falls among the bins, fetched before the slab so that
   // the gathers' latency hides behind its loads
   uint32_t ri[GI];
@@ -801,7 +806,7 @@ __global__ __launch_bounds__(kInvXYNT) void inv_xy_kernel(const float2* __restri
   __syncthreads();
   float tv[GI];                                    // T(n^2) (unused at the k = 0 mode)
 #pragma unroll
-  for (int i = 0; i < GI; ++i) tv[i] = neutrino_factor(ri[i], s_ad);
+  for (int i = 0; i < GI; ++i) tv[i] = neutrino_factor(ri[i], s_r, nbins, fnu);
   fft_lines<N, N, NT, -1, ES>(lds, tw);
   // delta_M -> phi (lines 0..N-1) and -i k_x phi (lines N..2N-1)
 #pragma unroll
@@ -1114,8 +1119,9 @@ template <int N> struct InvX {
       constexpr int TX = decltype(txv)::value;
       const int total = N / TX * Shape<N>::NK * nbox;
       dim3 grid((total + 7) / 8 * 8);   // whole rounds over the 8 XCDs; extra blocks exit
-      hipLaunchKernelGGL((inv_x_kernel<N, TX>), grid, dim3(NT), nbins * sizeof(double2), s, dk,
-                         f1, f2, tw, ridx, next, ratio, boxes, nbins, iw, cfac, kf, nbox);
+      const size_t lds_ratio = nbins * (sizeof(double) + sizeof(int));   // R and next
+      hipLaunchKernelGGL((inv_x_kernel<N, TX>), grid, dim3(NT), lds_ratio, s, dk, f1, f2, tw,
+                         ridx, next, ratio, boxes, nbins, iw, cfac, kf, nbox);
       return hipGetLastError();
     };
     return with_tile<PMNU_TILES(IX)>(go, v);
@@ -1144,8 +1150,8 @@ template <int N> struct InvXY {
       return hipErrorInvalidValue;                 // the k_z slab does not fit the LDS
     } else {
       hipLaunchKernelGGL(inv_xy_kernel<N>, dim3(static_cast<unsigned>(Shape<N>::NK * nbox)),
-                         dim3(kInvXYNT), nbins * sizeof(double2), s, dk, g1, g2, g3, tw, ridx,
-                         next, ratio, boxes, nbins, iw, cfac, kf);
+                         dim3(kInvXYNT), nbins * (sizeof(double) + sizeof(int)), s, dk, g1, g2,
+                         g3, tw, ridx, next, ratio, boxes, nbins, iw, cfac, kf);
       return hipGetLastError();
     }
   }
