@@ -43,9 +43,11 @@ def test_default_config(lib):
     assert cfg.deconvolve == 1 and cfg.n_species == 3 and cfg.omega_m == 0.3
 
 
-@pytest.mark.parametrize("field,value", [("n_mesh", 100), ("n_mesh", 1024), ("n_kbins", 0),
-                                         ("substeps", 0), ("box_size", -1.0),
-                                         ("max_history", 1), ("response_mode", 5)])
+@pytest.mark.parametrize("field,value", [("n_mesh", 100), ("n_mesh", 1024), ("n_mesh", 4),
+                                         ("n_kbins", 0), ("n_kbins", 1025), ("substeps", 0),
+                                         ("box_size", -1.0), ("max_history", 1),
+                                         ("response_mode", 5), ("n_particles", 0),
+                                         ("iterations", 0)])
 def test_bad_config_is_rejected_before_touching_a_device(lib, field, value):
     cfg = binding.pm_nu_default_config()
     setattr(cfg, field, value)

@@ -92,6 +92,28 @@ def test_batched_boxes_with_different_masses():
         _check_box(out["boxes"][i], refs[i], J - 1, f"box {i}")
 
 
+def test_single_particle_box_matches_oracle():
+    """The degenerate box of one particle (the smallest input the call accepts): bins, the
+    density, the spectrum and P_nu^{1/2} as in every case; the acceleration grids at the RMS
+    bar; the particle's own (CIC self-) force against the grids' scale, since it is not
+    bounded away from zero."""
+    nm, box, nb, J, a_now, m_nu = 16, 64.0, 12, 8, 0.5, 0.3
+    pos = np.array([[17.3, 40.11, 5.7]], dtype=np.float32)
+    print(f"case single particle N={nm}", flush=True)
+    hist, ref = oracle_case(pos, nm, box, nb, J, 0.02, a_now, m_nu)
+    out = gpu_case(pos[None], nm, box, nb, J, a_now, [m_nu], [hist])
+    edges_, counts, _ = out["bins"]
+    assert np.array_equal(edges_, ref["edges"]) and np.array_equal(counts, ref["counts"])
+    g = out["boxes"][0]
+    ok = ref["counts"] > 0
+    assert np.abs(g["rho"] - ref["rho"]).max() <= 1e-7 * ref["rho"].max()
+    assert np.abs(g["p_cdm"][ok] / ref["p_cdm"][ok] - 1.0).max() <= 2e-6
+    assert np.abs(g["pnu_half"][ok] / ref["pnu_half"][ok] - 1.0).max() <= TOL_NU
+    assert rms_rel(g["grids"], ref["grids"]) <= TOL_FORCE_RMS
+    scale = np.abs(np.asarray(ref["grids"])).max()
+    assert np.abs(np.asarray(g["acc"], np.float64) - ref["acc"]).max() <= 1e-5 * scale
+
+
 def test_zero_mass_is_plain_pm():
     nm, box = 32, 128.0
     pos = make_inputs(32, box, 0.2, 21)
