@@ -39,6 +39,7 @@ KERNEL_SOURCES = {
     "fft_inv_z": "fft_kernels.hip", "nu_response": "response_kernels.hip",
     "patch_reduce": "grid_kernels.hip",
     "kick_drift": "advance_kernels.hip", "patch_fwd_z": "fft_kernels.hip",
+    "fft_fwd_zy": "fft_kernels.hip",
 }
 
 
@@ -47,7 +48,8 @@ def stage_bytes(n_mesh, n_part, nbox, nbins, n_hist, n_partial, deposit_mode=0):
     written once (FP32 grids, complex64 modes, FP32 positions/accelerations). The patch
     deposit (modes 6..9) splits the deposit into reading the positions (cic_deposit) and
     writing the density contrast (patch_reduce), which the fused modes (8, 9) never write:
-    their patch_fwd_z goes from the deposit to the z-transformed modes."""
+    their patch_fwd_z goes from the deposit to the z-transformed modes. For N <= 128
+    fft_fwd_zy is the z and y passes in one kernel (delta in, the y-transformed modes out)."""
     m = n_mesh ** 3 * nbox
     mh = n_mesh * n_mesh * (n_mesh // 2 + 1) * nbox
     npt = n_part * nbox
@@ -57,6 +59,7 @@ def stage_bytes(n_mesh, n_part, nbox, nbins, n_hist, n_partial, deposit_mode=0):
         "cic_deposit": 12 * npt + (0 if patch else 4 * m),
         "patch_reduce": 4 * m,
         "fft_fwd_z": 4 * m + 8 * mh,
+        "fft_fwd_zy": 4 * m + 8 * mh,
         "patch_fwd_z": 8 * mh,
         "fft_fwd_y": 16 * mh,
         "fft_fwd_x_bin": 16 * mh + 8 * n_partial * nbins * nbox,
@@ -110,6 +113,9 @@ def kernel_name(stage, tuning, n_mesh):
         return "inv_xy_kernel<%d>" % n_mesh
     if stage == "patch_fwd_z":
         return "patch_fwd_z_kernel<%d>" % n_mesh
+    if stage == "fft_fwd_zy":
+        return "fwd_zy_kernel<%d, %s>" % (n_mesh, "true" if tuning["deposit_mode"] >= 6
+                                          else "false")
     if stage == "fft_fwd_z":
         return "fwd_z_kernel<%d, %s, %d>" % (n_mesh, "true" if tuning["deposit_mode"] >= 6
                                              else "false", tiles.get("fwd_z", 0))

@@ -171,6 +171,11 @@ int pm_nu_copy_density(pm_nu_ctx* ctx, int box, float* out);
  * kernel per k_z slab, whose modes fit the LDS (fused != 0, the default); 0 runs them as the
  * two passes that larger meshes use. Both give the same forces bit for bit. */
 int pm_nu_set_inverse_xy(pm_nu_ctx* ctx, int fused);
+/* For N <= 128 the first two forward FFT passes (z, then y) run as one kernel per x-plane,
+ * which fits the LDS (fused != 0, the default; not with deposit modes 8 and 9, whose patch
+ * pass already does the z pass); 0 runs them as the two passes that larger meshes use. Both
+ * give the same modes bit for bit. */
+int pm_nu_set_forward_zy(pm_nu_ctx* ctx, int fused);
 /* With deposit modes 8 and 9, also store delta at every deposit (67 MB more writes per
  * 256^3 box) so that pm_nu_copy_density can read it (on != 0); the default is off. The
  * other deposit modes always keep it. */

@@ -526,6 +526,107 @@ __global__ __launch_bounds__(NT) void fwd_y_kernel(const float2* __restrict__ in
   }
 }
 
+// For N <= 128 the first two forward passes in one kernel, one workgroup per (x-plane, box):
+// the plane (N rows of y by N z) fits the LDS. Its rows are transformed along z as in
+// fwd_z_kernel (rows 2p and 2p + 1 as one complex line, then split into the two real rows'
+// half spectra), the half spectra go through registers to lines along y (one per k_z), are
+// transformed as in fwd_y_kernel and written to [box][k_z][x][k_y]. The same arithmetic in the
+// same order as the two passes, so the same modes bit for bit; the z-transformed plane never
+// reaches HBM. With DELTA it also does fwd_z_kernel's registry work (reset, clear).
+constexpr int kFwdZYNT = 256;   // threads per workgroup of fwd_zy_kernel
+template <int N, bool DELTA>
+__global__ __launch_bounds__(kFwdZYNT) void fwd_zy_kernel(const void* __restrict__ in,
+                                                          float2* __restrict__ out,
+                                                          const float2* __restrict__ twg,
+                                                          double scale, int* __restrict__ reset,
+                                                          int* __restrict__ clear, int n_clear) {
+  constexpr int NT = kFwdZYNT;                     // this kernel's workgroup size
+  constexpr int NL = N / 2, ES = NL + 1, NK = Shape<N>::NK, ES2 = NK + 1;
+  constexpr int LDS_N = N * (ES > ES2 ? ES : ES2);
+  constexpr int PER = (NK * N + NT - 1) / NT;      // half-spectrum values per thread
+  static_assert(N <= 128, "the plane must fit the LDS");
+  __shared__ float2 lds[LDS_N];
+  __shared__ float2 tw[N];
+  const int x = blockIdx.x, box = blockIdx.y, tid = threadIdx.x;
+  load_twiddles<N, NT>(tw, twg);
+  const size_t off = (static_cast<size_t>(box) * N + x) * N * N;   // the plane, [y][z]
+  float* ldsf = reinterpret_cast<float*>(lds);
+  if constexpr (DELTA) {
+    if (reset && tid == 0 && blockIdx.x == 0 && blockIdx.y == 0) {
+      reset[1] += reset[0];
+      reset[0] = 0;
+    }
+    // the patch registry's counts, read for the last time by the reduce before this kernel
+    const int64_t gid = (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x) * NT + tid;
+    if (clear && gid < n_clear) clear[gid] = 0;
+    const float4* src = reinterpret_cast<const float4*>(static_cast<const float*>(in) + off);
+    constexpr int IT = (N * N / 4 + NT - 1) / NT;
+    float4 v[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int t = tid + i * NT;
+      if (t < N * N / 4) v[i] = src[t];
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int t = tid + i * NT;
+      if (t >= N * N / 4) break;
+      const int row = (4 * t) / N, e = (4 * t) % N, sl = row & 1, p = row >> 1;
+      ldsf[(e * ES + p) * 2 + sl] = v[i].x;
+      ldsf[((e + 1) * ES + p) * 2 + sl] = v[i].y;
+      ldsf[((e + 2) * ES + p) * 2 + sl] = v[i].z;
+      ldsf[((e + 3) * ES + p) * 2 + sl] = v[i].w;
+    }
+  } else {
+    const ulonglong2* src =
+        reinterpret_cast<const ulonglong2*>(static_cast<const unsigned long long*>(in) + off);
+    for (int t = tid; t < N * N / 2; t += NT) {
+      const int row = (2 * t) / N, e = (2 * t) % N;
+      const ulonglong2 v = src[t];
+      // delta = rho / rho_bar - 1 from the exact fixed-point sum, rounded once to FP32
+      ldsf[(e * ES + (row >> 1)) * 2 + (row & 1)] =
+          static_cast<float>(static_cast<double>(v.x) * scale - 1.0);
+      ldsf[((e + 1) * ES + (row >> 1)) * 2 + (row & 1)] =
+          static_cast<float>(static_cast<double>(v.y) * scale - 1.0);
+    }
+  }
+  __syncthreads();
+  fft_lines<N, NL, NT, -1>(lds, tw);
+  // the two rows' half spectra, value t = (k_z, y) held in registers
+  float2 h[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int t = tid + i * NT;
+    h[i] = make_float2(0.f, 0.f);
+    if (t < NK * N) {
+      const int row = t % N, k = t / N, p = row >> 1;
+      const float2 zk = lds[k * ES + p];
+      const float2 zn = cconj(lds[((N - k) & (N - 1)) * ES + p]);
+      if ((row & 1) == 0) {
+        h[i] = cscale(cadd(zk, zn), 0.5f);               // A = (Z_k + conj Z_{N-k})/2
+      } else {
+        const float2 d = csub(zk, zn);                   // B = (Z_k - conj Z_{N-k})/(2i)
+        h[i] = make_float2(0.5f * d.y, -0.5f * d.x);
+      }
+    }
+  }
+  __syncthreads();
+  // line k_z, element y
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int t = tid + i * NT;
+    if (t < NK * N) lds[(t % N) * ES2 + t / N] = h[i];
+  }
+  __syncthreads();
+  fft_lines<N, NK, NT, -1, ES2>(lds, tw);
+  for (int t = tid; t < NK * N / 2; t += NT) {
+    const int kz = t / (N / 2), e = 2 * (t % (N / 2));
+    const float2 a = lds[e * ES2 + kz], b = lds[(e + 1) * ES2 + kz];
+    *reinterpret_cast<float4*>(out + ((static_cast<size_t>(box) * NK + kz) * N + x) * N + e) =
+        make_float4(a.x, a.y, b.x, b.y);
+  }
+}
+
 // STORE: write the transformed tile back (only for reading the modes out); BIN: the mode
 // sums per k-bin (the step bins without storing; the inverse pass redoes the x transform).
 template <int N, bool STORE, bool BIN, int TX>
@@ -1091,6 +1192,26 @@ template <int N> struct FwdY {
     return with_tile<PMNU_TILES(FY)>(go, v);
   }
 };
+template <int N> struct FwdZY {
+  static hipError_t run(const unsigned long long* rho, const float* delta, int* reset,
+                        int* clear, int n_clear, float2* out, const float2* tw, double scale,
+                        int nbox, hipStream_t s) {
+    if constexpr (N > 128) {
+      return hipErrorInvalidValue;                 // the plane does not fit the LDS
+    } else {
+      dim3 grid(N, nbox);
+      if (static_cast<int64_t>(grid.x) * grid.y * kFwdZYNT < n_clear)
+        return hipErrorInvalidValue;               // every count needs a thread to clear it
+      if (delta)
+        hipLaunchKernelGGL((fwd_zy_kernel<N, true>), grid, dim3(kFwdZYNT), 0, s, delta, out, tw,
+                           scale, reset, clear, n_clear);
+      else
+        hipLaunchKernelGGL((fwd_zy_kernel<N, false>), grid, dim3(kFwdZYNT), 0, s, rho, out, tw,
+                           scale, reset, clear, n_clear);
+      return hipGetLastError();
+    }
+  }
+};
 template <int N> struct FwdX {
   // partial != NULL: bin without storing (the step); NULL: store the modes, no binning
   static hipError_t run(float2* data, const float2* tw, const uint16_t* bins, double* partial,
@@ -1209,6 +1330,11 @@ hipError_t launch_fwd_z(int n, const unsigned long long* rho, const float* delta
 hipError_t launch_fwd_y(int n, const float2* in, float2* out, const float2* tw, int nbox,
                         hipStream_t s, int v, int* reset, int* clear, int n_clear) {
   return dispatch_n<FwdY>(n, in, out, tw, nbox, s, v, reset, clear, n_clear);
+}
+hipError_t launch_fwd_zy(int n, const unsigned long long* rho, const float* delta, int* reset,
+                         int* clear, int n_clear, float2* out, const float2* tw, double scale,
+                         int nbox, hipStream_t s) {
+  return dispatch_n<FwdZY>(n, rho, delta, reset, clear, n_clear, out, tw, scale, nbox, s);
 }
 template <int N> struct PatchFwdZ {
   static hipError_t run(const unsigned long long* patches, int pcap, const int* reg_count,

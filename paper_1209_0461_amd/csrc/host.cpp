@@ -23,7 +23,7 @@ namespace pmnu {
 const char* const kStageNames[ST_COUNT] = {
     "zero_mesh", "cic_deposit", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x_bin", "nu_response",
     "inv_x_green", "fft_inv_y", "fft_inv_z", "cic_interp", "surrogate",
-    "patch_reduce", "kick_drift", "patch_fwd_z", "inv_xy_green"};
+    "patch_reduce", "kick_drift", "patch_fwd_z", "inv_xy_green", "fft_fwd_zy"};
 
 namespace {
 thread_local std::string g_err = "no error";
@@ -298,6 +298,9 @@ int do_deposit(Ctx& c, const float* pos) {
   const double scale = static_cast<double>(c.M) / static_cast<double>(c.Np) / kFixScale;
   const bool fused = c.tune.deposit_mode >= 8;
   const int n_cells = static_cast<int>(c.nbox * patch_coarse_cells(c.N));
+  // N <= 128: the x-plane fits the LDS and the z and y passes are one kernel, writing the
+  // y-transformed modes straight to ck[0]
+  const bool zy = c.N <= 128 && c.tune.fwd_zy && !fused;
   if (c.tune.deposit_mode >= 6) {
     const bool big = c.tune.deposit_mode == 7 || c.tune.deposit_mode == 9;
     TIMED(c, ST_DEPOSIT,
@@ -313,8 +316,12 @@ int do_deposit(Ctx& c, const float* pos) {
       TIMED(c, ST_PATCH_REDUCE,
             launch_patch_reduce(c.patches, c.reg_count, c.reg_list, c.rho_fb, c.n_fb, c.delta,
                                 c.nbox, c.N, scale, c.stream));
-      TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, nullptr, c.delta, c.n_fb, c.reg_count, n_cells,
-                                      c.ck[1], c.tw, scale, c.nbox, c.stream, c.tune.fft[0]));
+      if (zy)
+        TIMED(c, ST_FWD_ZY, launch_fwd_zy(c.N, nullptr, c.delta, c.n_fb, c.reg_count, n_cells,
+                                          c.ck[0], c.tw, scale, c.nbox, c.stream));
+      else
+        TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, nullptr, c.delta, c.n_fb, c.reg_count, n_cells,
+                                        c.ck[1], c.tw, scale, c.nbox, c.stream, c.tune.fft[0]));
     }
     c.density_is_delta = true;
     c.density_kept = !fused || c.keep_density;
@@ -322,14 +329,19 @@ int do_deposit(Ctx& c, const float* pos) {
     TIMED(c, ST_ZERO, launch_fill_zero(c.rho, cells * 8, c.stream));
     TIMED(c, ST_DEPOSIT, launch_deposit(pos, c.rho, c.Np, c.nbox, c.N, inv_cell, c.d_flags,
                                         c.tune.deposit_mode, c.tune.deposit_block, c.stream));
-    TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, c.rho, nullptr, nullptr, nullptr, 0, c.ck[1], c.tw,
-                                    scale, c.nbox, c.stream, c.tune.fft[0]));
+    if (zy)
+      TIMED(c, ST_FWD_ZY, launch_fwd_zy(c.N, c.rho, nullptr, nullptr, nullptr, 0, c.ck[0], c.tw,
+                                        scale, c.nbox, c.stream));
+    else
+      TIMED(c, ST_FFT_Z, launch_fwd_z(c.N, c.rho, nullptr, nullptr, nullptr, 0, c.ck[1], c.tw,
+                                      scale, c.nbox, c.stream, c.tune.fft[0]));
     c.density_is_delta = false;
     c.density_kept = true;
   }
-  TIMED(c, ST_FFT_Y, launch_fwd_y(c.N, c.ck[1], c.ck[0], c.tw, c.nbox, c.stream,
-                                  c.tune.fft[1], fused ? c.n_fb : nullptr,
-                                  fused ? c.reg_count : nullptr, fused ? n_cells : 0));
+  if (!zy)
+    TIMED(c, ST_FFT_Y, launch_fwd_y(c.N, c.ck[1], c.ck[0], c.tw, c.nbox, c.stream,
+                                    c.tune.fft[1], fused ? c.n_fb : nullptr,
+                                    fused ? c.reg_count : nullptr, fused ? n_cells : 0));
   // the number of partial bin sums follows the tile of this pass
   c.n_partial = fwd_x_partials(c.N, c.tune.fft[2]);
   TIMED(c, ST_FFT_X_BIN, launch_fwd_x_bin(c.N, c.ck[0], c.tw, c.bin_of_n2, c.bin_partial,
@@ -1009,6 +1021,13 @@ int pm_nu_set_inverse_xy(pm_nu_ctx* ctx, int fused) {
   GET_CTX(ctx);
   drop_graph(*c);   // a captured step keeps its kernels
   c->tune.inv_xy = fused != 0 ? 1 : 0;
+  return PM_NU_OK;
+}
+
+int pm_nu_set_forward_zy(pm_nu_ctx* ctx, int fused) {
+  GET_CTX(ctx);
+  drop_graph(*c);   // a captured step keeps its kernels
+  c->tune.fwd_zy = fused != 0 ? 1 : 0;
   return PM_NU_OK;
 }
 

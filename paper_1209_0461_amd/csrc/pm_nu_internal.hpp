@@ -73,6 +73,8 @@ struct Tuning {
   int fft[6] = {0, 0, 0, 0, 0, 0};
   // N <= 64: the first two inverse passes as one kernel (inv_xy); 0: as two
   int inv_xy = 1;
+  // N <= 128: the first two forward passes as one kernel (fwd_zy); 0: as two
+  int fwd_zy = 1;
 };
 
 struct Timer {
@@ -86,7 +88,7 @@ struct Timer {
 
 enum Stage {
   ST_ZERO = 0, ST_DEPOSIT, ST_FFT_Z, ST_FFT_Y, ST_FFT_X_BIN, ST_RESPONSE, ST_INV_X_GREEN, ST_INV_Y, ST_INV_Z, ST_INTERP, ST_SURROGATE, ST_PATCH_REDUCE, ST_KICK_DRIFT,
-  ST_PATCH_FWD_Z, ST_INV_XY, ST_COUNT
+  ST_PATCH_FWD_Z, ST_INV_XY, ST_FWD_ZY, ST_COUNT
 };
 extern const char* const kStageNames[ST_COUNT];
 
@@ -264,6 +266,11 @@ hipError_t launch_fwd_z(int N, const unsigned long long* rho, const float* delta
 hipError_t launch_fwd_y(int N, const float2* in, float2* out, const float2* tw, int nbox,
                         hipStream_t s, int v = 0, int* reset = nullptr, int* clear = nullptr,
                         int n_clear = 0);
+// N <= 128: fwd_z and fwd_y in one kernel (rho or delta in as for launch_fwd_z; out: the
+// y-transformed modes fwd_y would write)
+hipError_t launch_fwd_zy(int N, const unsigned long long* rho, const float* delta, int* reset,
+                         int* clear, int n_clear, float2* out, const float2* tw, double scale,
+                         int nbox, hipStream_t s);
 // the patch sums and the first (z) forward pass in one kernel (N >= 32); delta_out, when
 // given, also receives delta
 hipError_t launch_patch_fwd_z(int n, const unsigned long long* patches, const int* reg_count,

@@ -238,19 +238,21 @@ def test_timing_records_every_stage():
     p = torch.from_numpy(pos).cuda()
     acc = torch.zeros_like(p)
     binding.pm_nu_set_timing(ctx.h, True)
-    common = ("cic_deposit", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x_bin", "nu_response",
-              "fft_inv_z", "cic_interp")
-    # N = 32: the first two inverse passes run as one kernel by default, as two on request
-    for fused, stages in ((1, ("inv_xy_green",)), (0, ("inv_x_green", "fft_inv_y"))):
+    common = ("cic_deposit", "fft_fwd_x_bin", "nu_response", "fft_inv_z", "cic_interp")
+    # N = 32: the first two forward and the first two inverse passes run as one kernel each
+    # by default, as two on request
+    for fused in (1, 0):
         binding.pm_nu_set_inverse_xy(ctx.h, fused)
+        binding.pm_nu_set_forward_zy(ctx.h, fused)
         for _ in range(2):
             ctx.step(p, acc, 0.5)
         t = binding.pm_nu_read_timing(ctx.h)
-        for stage in common + stages:
+        one = ("inv_xy_green", "fft_fwd_zy")
+        two = ("inv_x_green", "fft_inv_y", "fft_fwd_z", "fft_fwd_y")
+        for stage in common + (one if fused else two):
             ms, n = t[stage]
             assert n == 2 and ms > 0, (fused, stage)
-        other = ("inv_x_green", "fft_inv_y") if fused else ("inv_xy_green",)
-        assert all(t[s][1] == 0 for s in other), fused
+        assert all(t[s][1] == 0 for s in (two if fused else one)), fused
         assert binding.pm_nu_read_timing(ctx.h)["cic_deposit"][1] == 0
     ctx.close()
 
@@ -683,3 +685,48 @@ def test_fused_inverse_xy_equals_separate_passes(n_mesh, n_side, box):
     ctx.close()
     assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
     assert np.all(np.isfinite(out[0])) and np.abs(out[0]).max() > 0
+
+
+@pytest.mark.parametrize("n_mesh,n_side,box", [(8, 8, 32.0), (16, 16, 64.0), (32, 32, 128.0),
+                                               (64, 64, 256.0), (128, 64, 400.0)])
+def test_fused_forward_zy_equals_separate_passes(n_mesh, n_side, box):
+    """For N <= 128 the z and y forward passes run as one kernel per x-plane; the modes and
+    forces equal those of the two separate passes bit for bit, from the fixed-point density
+    (deposit modes 0 and 4) and from the patch deposit's delta (mode 6, whose registry the
+    fused kernel clears as the z pass does: the second step would otherwise differ)."""
+    import torch
+    from paper_1209_0461_amd import PMNu, binding
+    from synth import log_spaced_nodes, synthetic_history
+    nbox, nb, J = 2, 16, 10
+    pos = np.stack([make_inputs(n_side, box, 0.3, 70 + b, extra_random=500) for b in range(nbox)])
+    ctx = PMNu(n_mesh, pos.shape[1], box, nb, J + 8, [0.3, 0.6])
+    nodes = log_spaced_nodes(0.02, 0.7, J)
+    _, counts, kmean = ctx.bins()
+    for b in range(nbox):
+        ctx.set_history(b, synthetic_history(kmean, np.where(counts > 0, 1.0, 0.0), nodes,
+                                             [0.3, 0.6][b]))
+    p = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
+    nmode = n_mesh * n_mesh * (n_mesh // 2 + 1) * 2
+
+    def run(mode, fused):
+        binding.pm_nu_set_launch(ctx.h, mode, 256, 1, 256)
+        binding.pm_nu_set_forward_zy(ctx.h, fused)
+        accs = []
+        for _ in range(2):                          # a second step reuses the registry
+            acc = torch.zeros_like(p)
+            ctx.step(p, acc, 0.7)
+            accs.append(acc)
+        ctx.deposit(p)                              # the modes are read after a deposit
+        modes = [torch.empty(nmode, device="cuda") for _ in range(nbox)]
+        for b in range(nbox):
+            binding.pm_nu_copy_modes(ctx.h, b, modes[b])
+        torch.cuda.synchronize()
+        return [a.cpu().numpy() for a in accs], [m.cpu().numpy() for m in modes]
+
+    for mode in (0, 4, 6):
+        a0, m0 = run(mode, 0)
+        a1, m1 = run(mode, 1)
+        assert all(np.array_equal(x, y) for x, y in zip(m0, m1)), mode
+        assert all(np.array_equal(x, y) for x, y in zip(a0, a1)), mode
+        assert np.all(np.isfinite(a1[0])) and np.abs(a1[0]).max() > 0
+    ctx.close()
