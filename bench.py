@@ -39,7 +39,7 @@ KERNEL_SOURCES = {
     "fft_inv_z": "fft_kernels.hip", "nu_response": "response_kernels.hip",
     "patch_reduce": "grid_kernels.hip",
     "kick_drift": "advance_kernels.hip", "patch_fwd_z": "fft_kernels.hip",
-    "fft_fwd_zy": "fft_kernels.hip",
+    "fft_fwd_zy": "fft_kernels.hip", "inv_yz": "fft_kernels.hip",
 }
 
 
@@ -49,7 +49,9 @@ def stage_bytes(n_mesh, n_part, nbox, nbins, n_hist, n_partial, deposit_mode=0):
     deposit (modes 6..9) splits the deposit into reading the positions (cic_deposit) and
     writing the density contrast (patch_reduce), which the fused modes (8, 9) never write:
     their patch_fwd_z goes from the deposit to the z-transformed modes. For N <= 128
-    fft_fwd_zy is the z and y passes in one kernel (delta in, the y-transformed modes out)."""
+    fft_fwd_zy is the z and y passes in one kernel (delta in, the y-transformed modes out);
+    for N <= 64 inv_yz is the y and z inverse passes in one kernel (F1, F2 in, the
+    acceleration grid out)."""
     m = n_mesh ** 3 * nbox
     mh = n_mesh * n_mesh * (n_mesh // 2 + 1) * nbox
     npt = n_part * nbox
@@ -68,6 +70,7 @@ def stage_bytes(n_mesh, n_part, nbox, nbins, n_hist, n_partial, deposit_mode=0):
         "fft_inv_y": 16 * mh + 24 * mh,
         "inv_xy_green": 8 * mh + 24 * mh,
         "fft_inv_z": 24 * mh + 12 * m,
+        "inv_yz": 16 * mh + 12 * m,
         "cic_interp": 12 * npt + 12 * m + 12 * npt,
     }
 
@@ -111,6 +114,8 @@ def kernel_name(stage, tuning, n_mesh):
            "fft_inv_y": ("inv_y_kernel", "inv_y"), "fft_inv_z": ("inv_z_kernel", "inv_z")}
     if stage == "inv_xy_green":
         return "inv_xy_kernel<%d>" % n_mesh
+    if stage == "inv_yz":
+        return "inv_yz_kernel<%d>" % n_mesh
     if stage == "patch_fwd_z":
         return "patch_fwd_z_kernel<%d>" % n_mesh
     if stage == "fft_fwd_zy":

@@ -30,6 +30,7 @@ STAGE_OF = {
     "deposit_patch_kernel": "cic_deposit", "patch_reduce_kernel": "patch_reduce",
     "kick_drift_kernel": "kick_drift", "patch_fwd_z_kernel": "patch_fwd_z",
     "inv_xy_kernel": "inv_xy_green", "fwd_zy_kernel": "fft_fwd_zy",
+    "inv_yz_kernel": "inv_yz",
 }
 
 

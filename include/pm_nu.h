@@ -167,10 +167,15 @@ int pm_nu_side_grid_uses(pm_nu_ctx* ctx, int64_t* uses);
  * Deposit modes 8 and 9 never write the density to HBM unless asked to by
  * pm_nu_set_keep_density before the deposit; otherwise PM_NU_ESTATE. */
 int pm_nu_copy_density(pm_nu_ctx* ctx, int box, float* out);
-/* For N <= 64 the first two inverse FFT passes (Green's function, x and y) run as one
- * kernel per k_z slab, whose modes fit the LDS (fused != 0, the default); 0 runs them as the
- * two passes that larger meshes use. Both give the same forces bit for bit. */
+/* For N <= 64 the first two inverse FFT passes (Green's function, x and y) can run as one
+ * kernel per k_z slab, whose modes fit the LDS (fused != 0, the default), when the last two
+ * are not fused (pm_nu_set_inverse_yz, which takes precedence); 0 runs them as the two passes
+ * that larger meshes use. Every choice gives the same forces bit for bit. */
 int pm_nu_set_inverse_xy(pm_nu_ctx* ctx, int fused);
+/* For N <= 64 the last two inverse FFT passes (y, then z into the acceleration grid) run as
+ * one kernel per x-plane, whose modes fit the LDS, after the x pass (fused != 0, the
+ * default); 0 leaves the choice to pm_nu_set_inverse_xy. The same forces bit for bit. */
+int pm_nu_set_inverse_yz(pm_nu_ctx* ctx, int fused);
 /* For N <= 128 the first two forward FFT passes (z, then y) run as one kernel per x-plane,
  * which fits the LDS (fused != 0, the default; not with deposit modes 8 and 9, whose patch
  * pass already does the z pass); 0 runs them as the two passes that larger meshes use. Both

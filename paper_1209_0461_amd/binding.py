@@ -58,6 +58,7 @@ SIGNATURES = {
     "pm_nu_set_keep_density": (_INT, [_P, _INT]),
     "pm_nu_set_inverse_xy": (_INT, [_P, _INT]),
     "pm_nu_set_forward_zy": (_INT, [_P, _INT]),
+    "pm_nu_set_inverse_yz": (_INT, [_P, _INT]),
     "pm_nu_side_grid_uses": (_INT, [_P, _I64]),
     "pm_nu_binned_power_noalloc": (_INT, [_P, ctypes.c_int64, _INT, ctypes.c_double, _INT, _P,
                                           _P]),
@@ -260,6 +261,10 @@ def pm_nu_set_keep_density(h, on):
 
 def pm_nu_set_inverse_xy(h, fused):
     _check(load_library().pm_nu_set_inverse_xy(h, int(bool(fused))))
+
+
+def pm_nu_set_inverse_yz(h, fused):
+    _check(load_library().pm_nu_set_inverse_yz(h, int(bool(fused))))
 
 
 def pm_nu_set_forward_zy(h, fused):

@@ -1117,6 +1117,120 @@ __global__ __launch_bounds__(kInvZNT) void inv_z_kernel(const float2* __restrict
   }
 }
 
+// For N <= 64 the last two inverse passes in one kernel, one workgroup per (x-plane, box):
+// F1 and F2 of the plane (all k_z, all k_y: 2 N (N/2 + 1) modes) fit the LDS. As
+// inv_y_kernel, G1 = F1, G2 = -i k_y F1 and G3 = F2 are transformed along y (one line per
+// k_z each); the G values go through registers to the layout of inv_z_kernel (rows comp N + y,
+// two rows per complex line as A + iB, -i k_z on G1) and are transformed along z into the
+// plane's interleaved accelerations. The same arithmetic in the same order as the two passes,
+// so the same forces bit for bit; G1..G3 never reach HBM.
+constexpr int kInvYZNT = 512;   // threads per workgroup of inv_yz_kernel
+template <int N>
+__global__ __launch_bounds__(kInvYZNT) void inv_yz_kernel(const float2* __restrict__ f1,
+                                                          const float2* __restrict__ f2,
+                                                          float* __restrict__ out,
+                                                          const float2* __restrict__ twg,
+                                                          float kf) {
+  constexpr int NT = kInvYZNT;                     // this kernel's workgroup size
+  constexpr int NK = Shape<N>::NK;
+  constexpr int NL1 = 3 * NK, ES1 = NL1 + 1;       // y lines: F1, -i k_y F1, F2 per k_z
+  constexpr int NL2 = 3 * N / 2, ES2 = NL2 + 1;    // z lines: row pairs of rows comp N + y
+  constexpr int LDS_N = N * (ES1 > ES2 ? ES1 : ES2);
+  constexpr int NG = 3 * NK * N;                   // G values of the plane
+  constexpr int PER = (NG + NT - 1) / NT;
+  static_assert(N <= 64, "the plane's modes must fit the LDS");
+  __shared__ float2 lds[LDS_N];
+  __shared__ float2 tw[N];
+  const int x = blockIdx.x, box = blockIdx.y, tid = threadIdx.x;
+  load_twiddles<N, NT>(tw, twg);
+  // 1. F1, F2 of the plane: the k_z rows of [box][k_z][x][k_y], two values per float4
+  {
+    constexpr int IT = (NK * N / 2 + NT - 1) / NT;
+    float4 va[IT], vb[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int t = tid + i * NT;
+      if (t < NK * N / 2) {
+        const int kz = t / (N / 2), e0 = 2 * (t % (N / 2));
+        const size_t o = ((static_cast<size_t>(box) * NK + kz) * N + x) * N + e0;
+        va[i] = *reinterpret_cast<const float4*>(f1 + o);
+        vb[i] = *reinterpret_cast<const float4*>(f2 + o);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int t = tid + i * NT;
+      if (t >= NK * N / 2) continue;
+      const int kz = t / (N / 2), e0 = 2 * (t % (N / 2));
+      const float4 a4 = va[i], b4 = vb[i];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int e = e0 + h;
+        const float2 a = h ? make_float2(a4.z, a4.w) : make_float2(a4.x, a4.y);
+        lds[e * ES1 + kz] = a;
+        const float ky = (e == N / 2) ? 0.f : kf * static_cast<float>(signed_index(e, N));
+        lds[e * ES1 + NK + kz] = make_float2(ky * a.y, -ky * a.x);     // -i k_y F1
+        lds[e * ES1 + 2 * NK + kz] = h ? make_float2(b4.z, b4.w) : make_float2(b4.x, b4.y);
+      }
+    }
+  }
+  __syncthreads();
+  fft_lines<N, NL1, NT, +1, ES1>(lds, tw);
+  // 2. value t = (field f, k_z, y): G1 (f = 0) is g_z, G2 g_y, G3 g_x
+  float2 g[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int t = tid + i * NT;
+    g[i] = make_float2(0.f, 0.f);
+    if (t < NG) {
+      const int y = t % N, r = t / N, kz = r % NK, f = r / NK;
+      g[i] = lds[y * ES1 + f * NK + kz];
+    }
+  }
+  __syncthreads();
+  // 3. half spectra of row pair p: A[k] at slot k and B[k] at slot N-k for 0 < k < N/2; the
+  //    real parts of A and B at k = 0 and k = N/2 share slots 0 and N/2
+  float* ldsf = reinterpret_cast<float*>(lds);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int t = tid + i * NT;
+    if (t >= NG) break;
+    const int y = t % N, r = t / N, k = r % NK, f = r / NK;
+    const int comp = 2 - f;
+    float2 a = g[i];
+    if (comp == 2) {                                 // -i k_z G1
+      const float kz = (k == N / 2) ? 0.f : kf * static_cast<float>(k);
+      a = make_float2(kz * a.y, -kz * a.x);
+    }
+    const int row = comp * N + y, p = row >> 1;
+    if (k == 0 || k == N / 2)
+      ldsf[(k * ES2 + p) * 2 + (row & 1)] = a.x;
+    else if ((row & 1) == 0)
+      lds[k * ES2 + p] = a;
+    else
+      lds[(N - k) * ES2 + p] = a;
+  }
+  __syncthreads();
+  for (int t = tid; t < (N / 2 - 1) * NL2; t += NT) {
+    const int p = t % NL2, k = 1 + t / NL2;
+    const float2 a = lds[k * ES2 + p], b = lds[(N - k) * ES2 + p];
+    lds[k * ES2 + p] = make_float2(a.x - b.y, a.y + b.x);                // A + iB
+    lds[(N - k) * ES2 + p] = make_float2(a.x + b.y, b.x - a.y);          // conj A + i conj B
+  }
+  __syncthreads();
+  fft_lines<N, NL2, NT, +1, ES2>(lds, tw);
+  // interleaved output of the plane, one lane per node as in inv_z_kernel
+  float* dst = out + (static_cast<size_t>(box) * N + x) * N * N * 3;
+  for (int n = tid; n < N * N; n += NT) {
+    const int y = n / N, z = n % N;
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+      const int row = comp * N + y;
+      dst[3 * n + comp] = ldsf[(z * ES2 + (row >> 1)) * 2 + (row & 1)];
+    }
+  }
+}
+
 template <int N>
 __global__ void copy_modes_kernel(const float2* __restrict__ ck, float2* __restrict__ out,
                                   int box) {
@@ -1277,6 +1391,18 @@ template <int N> struct InvXY {
     }
   }
 };
+template <int N> struct InvYZ {
+  static hipError_t run(const float2* f1, const float2* f2, float* out, const float2* tw, float kf,
+                        int nbox, hipStream_t s) {
+    if constexpr (N > 64) {
+      return hipErrorInvalidValue;                 // the plane's modes do not fit the LDS
+    } else {
+      hipLaunchKernelGGL(inv_yz_kernel<N>, dim3(N, nbox), dim3(kInvYZNT), 0, s, f1, f2, out, tw,
+                         kf);
+      return hipGetLastError();
+    }
+  }
+};
 template <int N> struct InvZ {
   static hipError_t run(const float2* g1, const float2* g2, const float2* g3, float* out,
                         const float2* tw, float kf, int nbox, hipStream_t s, int v) {
@@ -1389,6 +1515,10 @@ hipError_t launch_inv_xy(int n, const float2* dk, float2* g1, float2* g2, float2
                          float cgreen, float kf, int nbox, hipStream_t s) {
   return dispatch_n<InvXY>(n, dk, g1, g2, g3, tw, ridx, next, ratio, boxes, nbins, iw, cgreen,
                            kf, nbox, s);
+}
+hipError_t launch_inv_yz(int n, const float2* f1, const float2* f2, float* out, const float2* tw,
+                         float kf, int nbox, hipStream_t s) {
+  return dispatch_n<InvYZ>(n, f1, f2, out, tw, kf, nbox, s);
 }
 hipError_t launch_inv_z(int n, const float2* g1, const float2* g2, const float2* g3, float* out,
                         const float2* tw, float kf, int nbox, hipStream_t s, int v) {

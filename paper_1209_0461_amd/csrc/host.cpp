@@ -23,7 +23,7 @@ namespace pmnu {
 const char* const kStageNames[ST_COUNT] = {
     "zero_mesh", "cic_deposit", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x_bin", "nu_response",
     "inv_x_green", "fft_inv_y", "fft_inv_z", "cic_interp", "surrogate",
-    "patch_reduce", "kick_drift", "patch_fwd_z", "inv_xy_green", "fft_fwd_zy"};
+    "patch_reduce", "kick_drift", "patch_fwd_z", "inv_xy_green", "fft_fwd_zy", "inv_yz"};
 
 namespace {
 thread_local std::string g_err = "no error";
@@ -404,11 +404,20 @@ int do_force(Ctx& c, const float* pos, float* acc, double a_now, const Leap* lp 
   if (!pos || !acc) return set_error(PM_NU_EINVAL, "pos/acc is NULL");
   const float kf = static_cast<float>(2.0 * kPi / c.cfg.box_size);
   const double cgreen = 1.5 * c.cfg.omega_m * kH0 * kH0 / a_now / static_cast<double>(c.M);
-  // N <= 64: the k_z slab fits the LDS and the first two inverse passes are one kernel,
-  // whose G1 goes to ck[1] (ck[0] still holds the modes it reads)
-  const bool inv_xy = c.N <= 64 && c.tune.inv_xy;
+  // N <= 64: an x-plane's F1 and F2 fit the LDS and the last two inverse passes are one
+  // kernel; else the k_z slab fits the LDS and the first two are one kernel, whose G1 goes to
+  // ck[1] (ck[0] still holds the modes it reads)
+  const bool inv_yz = c.N <= 64 && c.tune.inv_yz;
+  const bool inv_xy = c.N <= 64 && c.tune.inv_xy && !inv_yz;
   float2* g1 = inv_xy ? c.ck[1] : c.ck[0];
-  if (inv_xy) {
+  if (inv_yz) {
+    TIMED(c, ST_INV_X_GREEN,
+          launch_inv_x(c.N, c.ck[0], c.ck[1], c.ck[2], c.tw, c.ridx, c.d_next, c.ratio,
+                       c.d_resp, c.B, c.inv_w2, static_cast<float>(cgreen), kf, c.nbox, c.stream,
+                       c.tune.fft[3]));
+    TIMED(c, ST_INV_YZ, launch_inv_yz(c.N, c.ck[1], c.ck[2], c.force, c.tw, kf, c.nbox,
+                                      c.stream));
+  } else if (inv_xy) {
     TIMED(c, ST_INV_XY,
           launch_inv_xy(c.N, c.ck[0], g1, c.ck[3], c.ck[4], c.tw, c.ridx, c.d_next, c.ratio,
                         c.d_resp, c.B, c.inv_w2, static_cast<float>(cgreen), kf, c.nbox,
@@ -421,8 +430,9 @@ int do_force(Ctx& c, const float* pos, float* acc, double a_now, const Leap* lp 
     TIMED(c, ST_INV_Y, launch_inv_y(c.N, c.ck[1], c.ck[2], g1, c.ck[3], c.ck[4], c.tw, kf,
                                     c.nbox, c.stream, c.tune.fft[4]));
   }
-  TIMED(c, ST_INV_Z, launch_inv_z(c.N, g1, c.ck[3], c.ck[4], c.force, c.tw, kf, c.nbox,
-                                  c.stream, c.tune.fft[5]));
+  if (!inv_yz)
+    TIMED(c, ST_INV_Z, launch_inv_z(c.N, g1, c.ck[3], c.ck[4], c.force, c.tw, kf, c.nbox,
+                                    c.stream, c.tune.fft[5]));
   TIMED(c, ST_INTERP, launch_interp(pos, c.force, acc, c.Np, c.nbox, c.N,
                                     c.N / c.cfg.box_size, c.tune.interp_mode,
                                     c.tune.interp_block, c.stream, lp));
@@ -1021,6 +1031,13 @@ int pm_nu_set_inverse_xy(pm_nu_ctx* ctx, int fused) {
   GET_CTX(ctx);
   drop_graph(*c);   // a captured step keeps its kernels
   c->tune.inv_xy = fused != 0 ? 1 : 0;
+  return PM_NU_OK;
+}
+
+int pm_nu_set_inverse_yz(pm_nu_ctx* ctx, int fused) {
+  GET_CTX(ctx);
+  drop_graph(*c);   // a captured step keeps its kernels
+  c->tune.inv_yz = fused != 0 ? 1 : 0;
   return PM_NU_OK;
 }
 

@@ -71,7 +71,9 @@ struct Tuning {
   // tile candidate (0 default, 1, 2) of each FFT pass: fwd_z, fwd_y, fwd_x, inv_x, inv_y,
   // inv_z (fft_tile gives the tile); the same result for every candidate
   int fft[6] = {0, 0, 0, 0, 0, 0};
-  // N <= 64: the first two inverse passes as one kernel (inv_xy); 0: as two
+  // N <= 64: the last two inverse passes as one kernel (inv_yz, after inv_x), else the first
+  // two (inv_xy, before inv_z) when inv_xy is set; 0 and 0: three passes
+  int inv_yz = 1;
   int inv_xy = 1;
   // N <= 128: the first two forward passes as one kernel (fwd_zy); 0: as two
   int fwd_zy = 1;
@@ -88,7 +90,7 @@ struct Timer {
 
 enum Stage {
   ST_ZERO = 0, ST_DEPOSIT, ST_FFT_Z, ST_FFT_Y, ST_FFT_X_BIN, ST_RESPONSE, ST_INV_X_GREEN, ST_INV_Y, ST_INV_Z, ST_INTERP, ST_SURROGATE, ST_PATCH_REDUCE, ST_KICK_DRIFT,
-  ST_PATCH_FWD_Z, ST_INV_XY, ST_FWD_ZY, ST_COUNT
+  ST_PATCH_FWD_Z, ST_INV_XY, ST_FWD_ZY, ST_INV_YZ, ST_COUNT
 };
 extern const char* const kStageNames[ST_COUNT];
 
@@ -300,6 +302,9 @@ hipError_t launch_inv_xy(int N, const float2* dk, float2* g1, float2* g2, float2
                          const float2* tw, const uint32_t* ridx, const int* next,
                          const double* ratio, const RespBox* boxes, int nbins,
                          const float* inv_w2, float cgreen, float kf, int nbox, hipStream_t s);
+// N <= 64: inv_y and inv_z in one kernel (f1, f2 as inv_x writes them)
+hipError_t launch_inv_yz(int N, const float2* f1, const float2* f2, float* out, const float2* tw,
+                         float kf, int nbox, hipStream_t s);
 hipError_t launch_inv_z(int N, const float2* g1, const float2* g2, const float2* g3,
                         float* out, const float2* tw, float kf, int nbox, hipStream_t s,
                         int v = 0);

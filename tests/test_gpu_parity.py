@@ -238,21 +238,25 @@ def test_timing_records_every_stage():
     p = torch.from_numpy(pos).cuda()
     acc = torch.zeros_like(p)
     binding.pm_nu_set_timing(ctx.h, True)
-    common = ("cic_deposit", "fft_fwd_x_bin", "nu_response", "fft_inv_z", "cic_interp")
+    common = ("cic_deposit", "fft_fwd_x_bin", "nu_response", "cic_interp")
     # N = 32: the first two forward and the first two inverse passes run as one kernel each
     # by default, as two on request
-    for fused in (1, 0):
-        binding.pm_nu_set_inverse_xy(ctx.h, fused)
-        binding.pm_nu_set_forward_zy(ctx.h, fused)
+    # (fused forward, fused inverse x+y, fused inverse y+z) -> the stages that run
+    passes = {(1, 0, 1): ("fft_fwd_zy", "inv_x_green", "inv_yz"),
+              (1, 1, 0): ("fft_fwd_zy", "inv_xy_green", "fft_inv_z"),
+              (0, 0, 0): ("fft_fwd_z", "fft_fwd_y", "inv_x_green", "fft_inv_y", "fft_inv_z")}
+    every = set(sum(passes.values(), ()))
+    for (zy, xy, yz), stages in passes.items():
+        binding.pm_nu_set_forward_zy(ctx.h, zy)
+        binding.pm_nu_set_inverse_xy(ctx.h, xy)
+        binding.pm_nu_set_inverse_yz(ctx.h, yz)
         for _ in range(2):
             ctx.step(p, acc, 0.5)
         t = binding.pm_nu_read_timing(ctx.h)
-        one = ("inv_xy_green", "fft_fwd_zy")
-        two = ("inv_x_green", "fft_inv_y", "fft_fwd_z", "fft_fwd_y")
-        for stage in common + (one if fused else two):
+        for stage in common + stages:
             ms, n = t[stage]
-            assert n == 2 and ms > 0, (fused, stage)
-        assert all(t[s][1] == 0 for s in (two if fused else one)), fused
+            assert n == 2 and ms > 0, (zy, xy, yz, stage)
+        assert all(t[s][1] == 0 for s in every - set(stages)), (zy, xy, yz)
         assert binding.pm_nu_read_timing(ctx.h)["cic_deposit"][1] == 0
     ctx.close()
 
@@ -661,8 +665,8 @@ def test_fused_patch_pass_equals_separate_passes(n_mesh, n_side, box):
 @pytest.mark.parametrize("n_mesh,n_side,box", [(16, 16, 64.0), (32, 32, 128.0), (64, 64, 256.0)])
 def test_fused_inverse_xy_equals_separate_passes(n_mesh, n_side, box):
     """For N <= 64 the Green's function and the x and y inverse passes run as one kernel per
-    k_z slab; the forces equal those of the two separate passes bit for bit (two boxes with
-    different masses), and both match the oracle."""
+    k_z slab, or the y and z passes as one kernel per x-plane; the forces equal those of the
+    three separate passes bit for bit (two boxes with different masses)."""
     import torch
     from paper_1209_0461_amd import PMNu, binding
     from synth import log_spaced_nodes, synthetic_history
@@ -676,14 +680,16 @@ def test_fused_inverse_xy_equals_separate_passes(n_mesh, n_side, box):
                                              [0.3, 0.6][b]))
     p = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
     out = []
-    for fused in (1, 0, 1):
-        binding.pm_nu_set_inverse_xy(ctx.h, fused)
+    # (inverse x+y, inverse y+z): x+y fused, three passes, x+y fused again, y+z fused
+    for xy, yz in ((1, 0), (0, 0), (1, 0), (0, 1), (1, 1)):
+        binding.pm_nu_set_inverse_xy(ctx.h, xy)
+        binding.pm_nu_set_inverse_yz(ctx.h, yz)
         acc = torch.zeros_like(p)
         ctx.step(p, acc, 0.7)
         torch.cuda.synchronize()
         out.append(acc.cpu().numpy())
     ctx.close()
-    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    assert all(np.array_equal(out[0], o) for o in out[1:])
     assert np.all(np.isfinite(out[0])) and np.abs(out[0]).max() > 0
 
 
