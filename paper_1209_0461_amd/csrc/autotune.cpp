@@ -67,8 +67,9 @@ int json_int(const std::string& line, const char* field, int fallback) {
 }
 
 // Cache file: one JSON object per line,
-// {"key": "...", "deposit_mode": M, "deposit_block": D, "interp_block": I}
-bool read_cache(const char* path, const std::string& key, Tuning& t) {
+// {"key": "...", "deposit_mode": M, "deposit_block": D, "interp_block": I}; a line is taken
+// only if every field is a shape that pm_nu_set_launch would accept for a mesh of n
+bool read_cache(const char* path, const std::string& key, int n, Tuning& t) {
   std::ifstream f(path);
   if (!f) return false;
   std::string line;
@@ -79,8 +80,8 @@ bool read_cache(const char* path, const std::string& key, Tuning& t) {
     const int im = json_int(line, "interp_mode", -1);
     const int i = json_int(line, "interp_block", -1);
     int fft[6];
-    if (m >= 0 && m <= 7 && d >= 64 && d <= 1024 && im >= 0 && im <= 3 && i >= 64 && i <= 1024 &&
-        json_fft(line, fft)) {
+    if (m >= 0 && m <= 9 && (m < 8 || n >= 32) && d >= 64 && d <= 1024 && im >= 0 && im <= 3 &&
+        i >= 64 && i <= 1024 && json_fft(line, fft)) {
       t.deposit_mode = m;
       t.deposit_block = d;
       t.interp_mode = im;
@@ -121,7 +122,7 @@ int pm_nu_autotune(pm_nu_ctx* ctx, const float* pos, float* acc, double a_now,
   if (!pos || !acc) return set_error(PM_NU_EINVAL, "pos/acc is NULL");
   drop_graph(*c);   // the launch shapes may change
   const std::string key = cache_key(*c);
-  if (cache_path && read_cache(cache_path, key, c->tune)) return PM_NU_OK;
+  if (cache_path && read_cache(cache_path, key, c->N, c->tune)) return PM_NU_OK;
   const bool was_timing = c->timer.enabled;
   c->timer.enabled = false;
   struct DepCand { int mode, block; };

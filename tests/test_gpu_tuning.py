@@ -96,3 +96,17 @@ def test_autotune_reports_fft_choice_and_reloads_it_from_the_cache(tmp_path):
     torch.cuda.synchronize()
     assert rms_rel(acc.cpu().numpy(), ref["acc"]) <= TOL_FORCE_RMS
     ctx.close()
+    # every launch shape the library accepts is taken from the cache, the fused patch
+    # deposit (mode 9) and other tiles included
+    lines[0].update(deposit_mode=9, fft=[2, 1, 2, 1, 2, 1])
+    with open(cache, "w") as f:
+        f.write(json.dumps(lines[0]) + "\n")
+    ctx = PMNu(nm, pos.shape[0], box, nb, J + 4, [m])
+    ctx.set_history(0, hist)
+    binding.pm_nu_autotune(ctx.h, p, acc, a_now, cache)
+    third = json.loads(binding.pm_nu_tuning(ctx.h))
+    assert third["deposit_mode"] == 9 and third["fft"] == [2, 1, 2, 1, 2, 1], third
+    ctx.step(p, acc, a_now)
+    torch.cuda.synchronize()
+    assert rms_rel(acc.cpu().numpy(), ref["acc"]) <= TOL_FORCE_RMS
+    ctx.close()
