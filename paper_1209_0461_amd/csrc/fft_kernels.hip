@@ -30,6 +30,9 @@
 //                   components (g_x, g_y, g_z) interleaved per node
 // Since the derivative along an axis commutes with the transforms along the other axes,
 // this needs 2 + 3 intermediate fields instead of 3 + 3 + 3.
+// Where a plane or slab fits the LDS, two passes run as one kernel with the same arithmetic:
+// fwd_zy (N <= 128, per x-plane), inv_xy (N <= 64, per kz-slab) and inv_yz (N <= 64, per
+// x-plane, after inv_x); patch_fwd_z does the patch deposit's sums and fwd_z in one kernel.
 #include <type_traits>
 
 #include "fft_lds.hpp"
