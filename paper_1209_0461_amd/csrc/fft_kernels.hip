@@ -742,8 +742,12 @@ __device__ __forceinline__ float neutrino_factor(uint32_t e, const double* s_r, 
   return static_cast<float>((1.0 - f) + f * r);
 }
 
+// Threads per workgroup of inv_x_kernel: at N = 512 its LDS tile (N x 2 TX values, 75 KB)
+// leaves two workgroups per CU, and 512 threads keep twice the waves in flight (587 -> 510 us
+// at 512^3; no gain at 256^3, where four workgroups fit).
+template <int N> constexpr int kInvXNT = N >= 512 ? 512 : 256;
 template <int N, int TX>
-__global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk,
+__global__ __launch_bounds__(kInvXNT<N>) void inv_x_kernel(const float2* __restrict__ dk,
                                                    float2* __restrict__ f1,
                                                    float2* __restrict__ f2,
                                                    const float2* __restrict__ twg,
@@ -753,6 +757,7 @@ __global__ __launch_bounds__(NT) void inv_x_kernel(const float2* __restrict__ dk
                                                    const RespBox* __restrict__ boxes, int nbins,
                                                    const float* __restrict__ inv_w2,
                                                    float c, float kf, int nbox) {
+  constexpr int NT = kInvXNT<N>;                   // this kernel's workgroup size
   constexpr int NL = 2 * TX, ES = NL + 1, NK = Shape<N>::NK;
   constexpr int NYB = N / TX;
   __shared__ float2 lds[N * ES];
@@ -1358,8 +1363,8 @@ template <int N> struct InvX {
       const int total = N / TX * Shape<N>::NK * nbox;
       dim3 grid((total + 7) / 8 * 8);   // whole rounds over the 8 XCDs; extra blocks exit
       const size_t lds_ratio = nbins * (sizeof(double) + sizeof(int));   // R and next
-      hipLaunchKernelGGL((inv_x_kernel<N, TX>), grid, dim3(NT), lds_ratio, s, dk, f1, f2, tw,
-                         ridx, next, ratio, boxes, nbins, iw, cfac, kf, nbox);
+      hipLaunchKernelGGL((inv_x_kernel<N, TX>), grid, dim3(kInvXNT<N>), lds_ratio, s, dk, f1,
+                         f2, tw, ridx, next, ratio, boxes, nbins, iw, cfac, kf, nbox);
       return hipGetLastError();
     };
     return with_tile<PMNU_TILES(IX)>(go, v);
