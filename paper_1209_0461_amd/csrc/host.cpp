@@ -449,8 +449,8 @@ void free_ctx(Ctx* c) {
                   c->bin_partial,
                   c->bin_of_n2, c->d_counts, c->d_kmean, c->d_lnk, c->d_nonempty, c->pcdm, c->pnu,
                   c->ratio, c->hist_pm, c->hist_pnu, c->ic_pnu, c->ic_theta, c->tg_ds,
-                  c->tg_l2, c->tg_w, c->d_resp, c->ridx, c->d_next, c->tw, c->inv_w2, c->d_flags, c->patches,
-                  c->reg_count, c->reg_list, c->rho_fb, c->n_fb,
+                  c->tg_l2, c->tg_w, c->d_resp, c->ridx, c->d_next, c->tw, c->inv_w2,
+                  c->d_flags, c->patches, c->reg_count, c->reg_list, c->rho_fb, c->n_fb,
                   c->delta, c->d_kd};
   for (void* p : bufs)
     if (p) hipFree(p);
