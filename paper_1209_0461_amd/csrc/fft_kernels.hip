@@ -641,7 +641,14 @@ __global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data
   __shared__ float2 lds[N * ES];
   __shared__ float2 tw[N];
   extern __shared__ double bins[];
-  const int y0 = blockIdx.x * TX, kz = blockIdx.y, box = blockIdx.z;
+  // workgroups go to the 8 XCDs in turn; the remap gives each XCD a contiguous run of
+  // (k_y block, k_z) tiles of a box, so that the workgroups reading the two halves of a
+  // 128-byte line (TX = 8) share one L2
+  constexpr int NYB = N / TX;
+  const int per = static_cast<int>(gridDim.x) / 8, lid = static_cast<int>(blockIdx.x);
+  const int tile = (lid % 8) * per + lid / 8;
+  if (tile >= NYB * NK) return;
+  const int y0 = (tile % NYB) * TX, kz = tile / NYB, box = blockIdx.y;
   load_twiddles<N, NT>(tw, twg);
   if constexpr (BIN)
     for (int b = threadIdx.x; b < nbins; b += NT) bins[b] = 0.0;
@@ -714,8 +721,8 @@ __global__ __launch_bounds__(NT) void fwd_x_bin_kernel(float2* __restrict__ data
   }
   __syncthreads();
   // partial sums stored bin-major, [box][bin][workgroup], for contiguous reads per bin
-  const int wg = blockIdx.y * gridDim.x + blockIdx.x;
-  const size_t n_wg = static_cast<size_t>(gridDim.x) * gridDim.y;
+  const int wg = tile;
+  const size_t n_wg = static_cast<size_t>(NYB) * NK;
   double* dst = partial + static_cast<size_t>(box) * nbins * n_wg + wg;
   for (int b = threadIdx.x; b < nbins; b += NT) dst[b * n_wg] = bins[b];
 }
@@ -1340,7 +1347,8 @@ template <int N> struct FwdX {
                         int nbins, int nbox, hipStream_t s, int v) {
     auto go = [&](auto tx) -> hipError_t {
       constexpr int TX = decltype(tx)::value;
-      dim3 grid(N / TX, Shape<N>::NK, nbox);
+      const int tiles = N / TX * Shape<N>::NK;
+      dim3 grid((tiles + 7) / 8 * 8, nbox);          // whole rounds over the 8 XCDs
       if (partial)
         hipLaunchKernelGGL((fwd_x_bin_kernel<N, false, true, TX>), grid, dim3(NT),
                            nbins * sizeof(double), s, data, tw, bins, partial, nbins);
