@@ -61,6 +61,10 @@ def test_null_context_is_an_error(lib):
     assert lib.pm_nu_deposit(None, None) == -1
     assert lib.pm_nu_response(None, 1.0) == -1
     assert b"NULL" in lib.pm_nu_last_error()
+    # the switches between fused and separate FFT passes, like every other setter
+    for setter in (lib.pm_nu_set_forward_zy, lib.pm_nu_set_inverse_xy, lib.pm_nu_set_inverse_yz,
+                   lib.pm_nu_set_keep_density):
+        assert setter(None, 1) == -1
     lib.pm_nu_destroy(None)   # ignored
 
 
